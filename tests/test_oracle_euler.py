@@ -1,0 +1,356 @@
+"""Pins of the oracle's DG operator, RK stage, budgets, indicator, transfers and
+adjoint (sections 2.1, 2.2, 3.3 of the paper).
+
+Invariants the discretisation must satisfy exactly or to round-off:
+  * a hydrostatic rest state (q' = 0) has R = 0 bitwise, on AMR meshes, through
+    RK stages and transfers;
+  * a constant free stream is preserved (periodic, g = 0, hanging faces);
+  * discrete conservation of rho' and Theta' with walls, periodic wraps and mortars;
+  * the mass equation reproduces -div U exactly for any continuous polynomial U
+    of degree <= N, across hanging faces;
+  * design order of accuracy on an exact travelling entropy wave;
+  * Rusanov consistency and antisymmetry; wall mass flux exactly zero;
+  * quadrature of polynomials in the budgets; prolong-then-restrict = identity;
+  * adjoint against central finite differences.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import euler as eu
+from oracle import forest as fo
+from oracle.refelem import refelem
+from paper_2404_16648_amd.synth import random_state
+
+F64 = torch.float64
+
+
+def amr_mesh(N, periodic=(0, 0, 0), seed=0, n=(2, 2, 2), L=2, hi=(1000.0, 1000.0, 1000.0), rounds=2):
+    desc = fo.ForestDesc(N, *n, L, (0.0, 0.0, 0.0), hi, periodic)
+    m = fo.build(desc, None)
+    rng = np.random.default_rng(seed)
+    for _ in range(rounds):
+        fl = (rng.random(m.K) < 0.35).astype(np.int8)
+        m = fo.build(desc, m, fl, fo.PASS_REFINE)
+    assert len(m.hang) > 0
+    return m
+
+
+def rand_q(op, seed):
+    return torch.as_tensor(random_state(op.K, op.N, seed), dtype=F64).reshape(
+        5, op.K, op.N + 1, op.N + 1, op.N + 1)
+
+
+def test_hydrostatic_rest_is_exact():
+    m = amr_mesh(4, seed=1)
+    op = eu.Operator(m, eu.Phys())
+    z = torch.zeros(5, m.K, 5, 5, 5, dtype=F64)
+    R = op.rhs(z)
+    assert torch.count_nonzero(R) == 0
+    q1 = eu.ssp_rk3_step(op, 0.05, z)
+    assert torch.count_nonzero(q1) == 0
+    # and through a refine and a coarsen transfer
+    fl = np.ones(m.K, dtype=np.int8)
+    m2 = fo.build(m.desc, m, -fl, fo.PASS_COARSEN)
+    assert torch.count_nonzero(eu.coarsen_project(m2, z)) == 0
+
+
+def test_free_stream_preserved_with_mortars():
+    m = amr_mesh(3, periodic=(1, 1, 1), seed=2)
+    ph = eu.Phys(g=0.0, background=eu.BG_CONSTANT, rho0=1.2, Theta0=360.0)
+    op = eu.Operator(m, ph)
+    q = torch.zeros(5, m.K, 4, 4, 4, dtype=F64)
+    q[1], q[2], q[3] = 12.0, -7.0, 3.0
+    R = op.rhs(q)
+    # flux scale ~ P / h = 1e5 Pa / 250 m
+    assert float(R.abs().max()) < 1e-13 * 1e5 / 250.0 * 10
+
+
+@pytest.mark.parametrize("periodic", [(0, 0, 0), (1, 1, 1), (1, 0, 1)])
+def test_discrete_conservation(periodic):
+    m = amr_mesh(3, periodic=periodic, seed=3)
+    ph = eu.Phys()
+    op = eu.Operator(m, ph)
+    q = rand_q(op, 5)
+    R = op.rhs(q)
+    JW = eu.quad_weights(op)
+    # scale: typical |R| integrated
+    for v in (0, 4):
+        scale = float((JW * R[v].abs()).sum())
+        tot = math.fsum((JW * R[v]).reshape(-1).tolist())
+        assert abs(tot) < 1e-13 * scale, (v, tot, scale)
+    # with periodic wraps in every direction and g = 0 momentum is conserved too
+    if periodic == (1, 1, 1):
+        op0 = eu.Operator(m, eu.Phys(g=0.0, background=eu.BG_CONSTANT))
+        R0 = op0.rhs(q)
+        for v in (1, 2, 3):
+            scale = float((JW * R0[v].abs()).sum())
+            assert abs(math.fsum((JW * R0[v]).reshape(-1).tolist())) < 1e-13 * scale
+
+
+def test_wall_mass_and_theta_flux_zero():
+    """A single element with walls all round and U tangential only in the interior:
+    the mass flux through a wall is exactly zero, so the integral of R_rho is 0."""
+    m = fo.build(fo.ForestDesc(3, 1, 1, 1, 0, hi=(100.0, 100.0, 100.0)), None)
+    op = eu.Operator(m, eu.Phys())
+    q = rand_q(op, 9)
+    fs = eu.Operator.surface(op, q)
+    JW = eu.quad_weights(op)
+    # surface part alone: its rho and Theta' integrals vanish because every
+    # wall flux of rho and Theta is exactly zero (mirror state)
+    for v in (0, 4):
+        vol = op.volume(q)
+        tot = math.fsum((JW * (fs[v] + vol[v])).reshape(-1).tolist())
+        assert abs(tot) < 1e-12 * float((JW * vol[v].abs()).sum())
+
+
+@pytest.mark.parametrize("N", [2, 3, 4])
+def test_polynomial_divergence_through_mortars(N):
+    m = amr_mesh(N, periodic=(0, 0, 0), seed=4, hi=(2.0, 2.0, 2.0))
+    ph = eu.Phys(g=0.0, background=eu.BG_CONSTANT, rho0=1.0, Theta0=300.0)
+    op = eu.Operator(m, ph)
+    X, Y, Z = eu.node_xyz(m)
+    rng = np.random.default_rng(N)
+    # continuous polynomials of degree <= N in each variable whose normal
+    # component vanishes on the walls of [0,2]^3 (so the wall mirror state
+    # leaves the mass flux equal to U.n = 0)
+    c = rng.standard_normal(7)
+    bx, by, bz = X * (2 - X), Y * (2 - Y), Z * (2 - Z)
+    p1 = c[0] + c[1] * Y ** N + c[2] * Z
+    p2 = c[3] + c[4] * X ** N
+    p3 = c[5] + c[6] * X * Y ** (N - 1)
+    U, V, W = bx * p1, by * p2, bz * p3
+    divU = ((2 - 2 * X) * p1 + (2 - 2 * Y) * p2 + (2 - 2 * Z) * p3)
+    q = torch.stack([torch.zeros_like(U), U, V, W, torch.zeros_like(U)])
+    R = op.rhs(q)
+    err = float((R[0] + divU).abs().max())
+    assert err < 1e-11 * float(divU.abs().max() + 1), err
+
+
+def _entropy_wave_error(n, N, T=0.05, cfl_dt=0.002):
+    L = 1.0
+    desc = fo.ForestDesc(N, n, n, n, 0, (0.0, 0.0, 0.0), (L, L, L), (1, 1, 1))
+    m = fo.build(desc, None)
+    ph = eu.Phys(cp=3.5, cv=2.5, P0=1.0, g=0.0, background=eu.BG_CONSTANT, rho0=1.0, Theta0=1.0)
+    op = eu.Operator(m, ph)
+    X, Y, Z = eu.node_xyz(m)
+    u0 = 1.0
+
+    def exact(t):
+        rho = 1.0 + 0.1 * torch.sin(2 * math.pi * (X + Y + Z - 3 * u0 * t) / L)
+        return torch.stack([rho - 1.0, rho * u0, rho * u0, rho * u0, torch.zeros_like(rho)])
+
+    steps = int(round(T / cfl_dt))
+    dt = T / steps
+    q = exact(0.0)
+    for _ in range(steps):
+        q = eu.ssp_rk3_step(op, dt, q)
+    return float((q[0] - exact(T)[0]).abs().max())
+
+
+def test_design_order_entropy_wave():
+    """Error of a travelling exact Euler solution (constant P, periodic).
+
+    Solution error converges faster than h^N (the RHS truncation order) and
+    approaches the design order h^(N+1) on 2^3, 4^3, 8^3 elements."""
+    for N, rate_min in ((3, 3.0), (4, 4.0)):
+        e = [_entropy_wave_error(n, N, T=0.05, cfl_dt=0.0025) for n in (2, 4, 8)]
+        rates = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+        assert rates[-1] > rate_min, (N, e, rates)
+
+
+def test_rhs_truncation_order():
+    """RHS truncation error of the entropy wave decays like h^N."""
+    N = 4
+    errs = []
+    for n in (2, 4, 8):
+        desc = fo.ForestDesc(N, n, n, n, 0, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (1, 1, 1))
+        m = fo.build(desc, None)
+        ph = eu.Phys(cp=3.5, cv=2.5, P0=1.0, g=0.0, background=eu.BG_CONSTANT, rho0=1.0, Theta0=1.0)
+        op = eu.Operator(m, ph)
+        X, Y, Z = eu.node_xyz(m)
+        arg = 2 * math.pi * (X + Y + Z)
+        rho = 1.0 + 0.1 * torch.sin(arg)
+        q = torch.stack([rho - 1, rho, rho, rho, torch.zeros_like(rho)])
+        R = op.rhs(q)
+        exact = -3 * 0.1 * 2 * math.pi * torch.cos(arg)      # -div U
+        errs.append(float((R[0] - exact).abs().max()))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(rates) > N - 0.5, (errs, rates)
+
+
+def test_rk3_time_order():
+    """SSP-RK3 stages: halving dt divides the time error by ~8."""
+    N = 3
+    desc = fo.ForestDesc(N, 2, 2, 2, 0, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (1, 1, 1))
+    m = fo.build(desc, None)
+    ph = eu.Phys(cp=3.5, cv=2.5, P0=1.0, g=0.0, background=eu.BG_CONSTANT, rho0=1.0, Theta0=1.0)
+    op = eu.Operator(m, ph)
+    X, Y, Z = eu.node_xyz(m)
+    rho = 1.0 + 0.1 * torch.sin(2 * math.pi * (X + Y + Z))
+    q0 = torch.stack([rho - 1, rho, rho, rho, torch.zeros_like(rho)])
+    T = 0.08
+
+    def run(steps):
+        q = q0
+        for _ in range(steps):
+            q = eu.ssp_rk3_step(op, T / steps, q)
+        return q
+
+    ref = run(64)
+    e = [float((run(s) - ref).abs().max()) for s in (4, 8)]
+    assert 2.7 < math.log2(e[0] / e[1]) < 3.3, e
+
+
+def test_rusanov_consistency_and_antisymmetry():
+    m = fo.build(fo.ForestDesc(3, 1, 1, 1, 0), None)
+    op = eu.Operator(m, eu.Phys())
+    q = rand_q(op, 11)
+    qL, bL = op._trace(q, 1, torch.tensor([0]))
+    qR, bR = op._trace(q, 0, torch.tensor([0]))
+    for d in range(3):
+        Fs = eu.rusanov(qL, bL, qL, bL, op.phys, d, 1.0)
+        assert torch.allclose(Fs, eu.flux_dir(qL, bL, op.phys, d), rtol=1e-15, atol=0)
+        a = eu.rusanov(qL, bL, qR, bR, op.phys, d, 1.0)
+        b = eu.rusanov(qR, bR, qL, bL, op.phys, d, -1.0)
+        assert torch.equal(a, -b)
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_budget_quadrature_of_polynomials(N):
+    m = amr_mesh(N, seed=6, hi=(2.0, 3.0, 5.0))
+    op = eu.Operator(m, eu.Phys())
+    X, Y, Z = eu.node_xyz(m)
+    JW = eu.quad_weights(op)
+    # total degree 2N-1 in x: exact; integral over the box [0,2]x[0,3]x[0,5]
+    k = 2 * N - 1
+    f = X ** k * Y * Z ** 2
+    exact = (2.0 ** (k + 1) / (k + 1)) * (3.0 ** 2 / 2) * (5.0 ** 3 / 3)
+    got = math.fsum((JW * f).reshape(-1).tolist())
+    assert abs(got - exact) < 1e-12 * exact
+
+
+@pytest.mark.parametrize("N", [2, 4])
+def test_prolong_then_restrict_identity(N):
+    desc = fo.ForestDesc(N, 2, 1, 1, 2, hi=(2.0, 1.0, 1.0))
+    m0 = fo.build(desc, None)
+    op0 = eu.Operator(m0, eu.Phys())
+    q = rand_q(op0, 12)
+    m1 = fo.build(desc, m0, np.array([1, 0], dtype=np.int8), fo.PASS_REFINE)
+    q1 = eu.refine_project(m1, q)
+    m2 = fo.build(desc, m1, -np.ones(m1.K, dtype=np.int8), fo.PASS_COARSEN)
+    assert m2.leaves == m0.leaves
+    q2 = eu.coarsen_project(m2, q1)
+    assert float((q2 - q).abs().max()) < 1e-14 * float(q.abs().max()) * 10
+    # the integral of every variable is preserved by the refinement
+    op1 = eu.Operator(m1, eu.Phys())
+    for v in range(5):
+        a = math.fsum((eu.quad_weights(op0) * q[v]).reshape(-1).tolist())
+        b = math.fsum((eu.quad_weights(op1) * q1[v]).reshape(-1).tolist())
+        assert abs(a - b) < 1e-14 * float(q[v].abs().max()) * 8
+
+
+def test_coarsen_preserves_integrals_of_discontinuous_children():
+    N = 3
+    desc = fo.ForestDesc(N, 1, 1, 1, 1, hi=(1.0, 2.0, 1.0))
+    m0 = fo.build(desc, None)
+    m1 = fo.build(desc, m0, np.array([1], dtype=np.int8), fo.PASS_REFINE)
+    op1 = eu.Operator(m1, eu.Phys())
+    q1 = rand_q(op1, 13)                    # arbitrary, discontinuous between children
+    m2 = fo.build(desc, m1, -np.ones(8, dtype=np.int8), fo.PASS_COARSEN)
+    q2 = eu.coarsen_project(m2, q1)
+    op2 = eu.Operator(m2, eu.Phys())
+    for v in range(5):
+        a = math.fsum((eu.quad_weights(op1) * q1[v]).reshape(-1).tolist())
+        b = math.fsum((eu.quad_weights(op2) * q2[v]).reshape(-1).tolist())
+        assert abs(a - b) < 1e-14 * float(q1[v].abs().max()) * 8
+
+
+def test_indicator_and_flags():
+    m = fo.build(fo.ForestDesc(4, 4, 4, 4, 2, hi=(1000.0, 1000.0, 1000.0)), None)
+    op = eu.Operator(m, eu.Phys())
+    q = eu.bubble_state(op)
+    eta = eu.indicator(op, q, eu.IND_THETA).numpy()
+    # the bubble peak is 2 K at (500, 500, 350): no node sits exactly there, so
+    # eta < 2 everywhere, and the elements touching the centre see ~2 K
+    assert eta.max() <= 2.0 + 1e-12 and eta.max() > 1.5
+    X, Y, Z = eu.node_xyz(m)
+    r = torch.sqrt((X - 500) ** 2 + (Y - 500) ** 2 + (Z - 350) ** 2)
+    far = (r.reshape(m.K, -1).min(dim=1).values > 250.0).numpy()
+    assert np.all(eta[far] < 1e-10)
+    fl = eu.flags_from_indicator(m, eta, 0.1)
+    assert np.all(fl[far] == 0) and np.all(fl[~far & (eta > 0.1)] == 1)
+    # gradient indicator of a linear theta field: |grad theta| = slope everywhere
+    ph = eu.Phys(g=0.0, background=eu.BG_CONSTANT, rho0=1.0, Theta0=300.0)
+    op2 = eu.Operator(m, ph)
+    qq = torch.zeros(5, m.K, 5, 5, 5, dtype=F64)
+    qq[4] = 0.003 * X + 0.004 * Z          # theta = 300 + 0.003 x + 0.004 z, rho = 1
+    eta2 = eu.indicator(op2, qq, eu.IND_GRAD_THETA).numpy()
+    assert np.allclose(eta2, 0.005, rtol=1e-10)
+
+
+def test_bubble_initial_state_is_balanced_in_pressure():
+    m = fo.build(fo.ForestDesc(4, 2, 2, 2, 2, hi=(1000.0, 1000.0, 1000.0)), None)
+    op = eu.Operator(m, eu.Phys())
+    q = eu.bubble_state(op)
+    assert torch.count_nonzero(q[4]) == 0 and torch.count_nonzero(q[1:4]) == 0
+    rho_b, Th_b, P_b = op.bg
+    theta = (Th_b + q[4]) / (rho_b + q[0])
+    X, Y, Z = eu.node_xyz(m)
+    r = torch.sqrt((X - 500) ** 2 + (Y - 500) ** 2 + (Z - 350) ** 2)
+    want = 300.0 + torch.where(r <= 250, 1.0 + torch.cos(math.pi * r / 250), torch.zeros_like(r))
+    assert float((theta - want).abs().max()) < 1e-10
+    # background hydrostatic: dPbar/dz = -g rhobar to the order of the LGL derivative
+    dPz = torch.einsum('km,emji->ekji', op.D, P_b) * (2.0 / op.h[:, 2])[:, None, None, None]
+    assert float((dPz + op.phys.g * rho_b).abs().max() / (op.phys.g * rho_b.max())) < 1e-6
+
+
+def _rhs_flat(op, x):
+    return op.rhs(x).reshape(-1)
+
+
+def test_adjoint_matches_central_differences():
+    m = amr_mesh(2, seed=7, rounds=1)
+    op = eu.Operator(m, eu.Phys())
+    q = rand_q(op, 21)
+    lam = rand_q(op, 22)
+    qbar = eu.rhs_adjoint(op, q, lam)
+    for k in range(3):
+        v = rand_q(op, 30 + k)
+        eps = 1e-6
+        fd = (float((lam * op.rhs(q + eps * v)).sum()) - float((lam * op.rhs(q - eps * v)).sum())) / (2 * eps)
+        ad = float((qbar * v).sum())
+        assert abs(fd - ad) <= 1e-6 * max(abs(fd), abs(ad)), (fd, ad)
+    # dot-product test with the forward-mode (dual number) derivative
+    v = rand_q(op, 40)
+    jv = eu.rhs_jvp(op, q, v)
+    a, b = float((lam * jv).sum()), float((qbar * v).sum())
+    assert abs(a - b) <= 1e-12 * max(abs(a), abs(b))
+
+
+def test_rk3_adjoint_matches_central_differences():
+    m = amr_mesh(2, seed=8, rounds=1)
+    op = eu.Operator(m, eu.Phys())
+    q0 = eu.bubble_state(op) + 0.1 * rand_q(op, 23)
+    dt = 0.02
+    box = ((300.0, 700.0), (300.0, 700.0), (200.0, 600.0))
+
+    def J(q):
+        for _ in range(2):
+            q = eu.ssp_rk3_step(op, dt, q)
+        return eu.target_functional(op, q, box)
+
+    q1 = eu.ssp_rk3_step(op, dt, q0)
+    q2 = eu.ssp_rk3_step(op, dt, q1)
+    qT = q2.detach().clone().requires_grad_(True)
+    (lam,) = torch.autograd.grad(eu.target_functional(op, qT, box), qT)
+    lam = eu.rk3_step_adjoint(op, dt, q1, lam)
+    g = eu.rk3_step_adjoint(op, dt, q0, lam)
+    for k in range(2):
+        d = rand_q(op, 50 + k)
+        eps = 1e-6
+        fd = (float(J(q0 + eps * d)) - float(J(q0 - eps * d))) / (2 * eps)
+        ad = float((g * d).sum())
+        assert abs(fd - ad) <= 1e-6 * max(abs(fd), abs(ad)), (fd, ad)
