@@ -1,0 +1,212 @@
+/*
+ * dg.h -- C ABI of the MI355X DG-AMR hot path.
+ *
+ * Nodal discontinuous Galerkin (dGSEM) right-hand side of the compressible Euler
+ * equations in hydrostatic-perturbation form on 2:1-balanced oct-tree hexahedral
+ * meshes with L2 mortars on hanging faces, the explicit SSP-RK3 stage update,
+ * conservative refine/coarsen solution transfer, mass/energy budgets, the
+ * adaptation indicator and the discrete adjoint of the right-hand side.
+ *
+ * Paper: Abdi, Almgren, Giraldo, Jankov, "Comparison of adaptive mesh refinement
+ * techniques for numerical weather prediction", arXiv 2404.16648.
+ *   equations and equation of state ............ section 2.1
+ *   strong-form dGSEM, Rusanov flux ............. section 2.2
+ *   forest of trees, leaves only ................ section 3.1
+ *   conservative transfer and mortars ........... section 3.3
+ *   2:1 balance ................................. section 4.3
+ *
+ * Conventions shared by every call
+ *   - Field arrays are DEVICE pointers to float64, layout q[v][e][n]:
+ *     v in {rho', rho*u, rho*v, rho*w, Theta'} (perturbations about the
+ *     hydrostatic background for rho and Theta = rho*theta), e = leaf in the
+ *     mesh's canonical order, n = i + (N+1)*(j + (N+1)*k) over the LGL nodes of
+ *     the leaf (i along x fastest).  Size 5*K*Np doubles, Np = (N+1)^3.
+ *   - The caller owns every field buffer; the library owns the mesh handle, its
+ *     host tables, its device tables, background profiles and workspaces.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *     Field calls only enqueue work (asynchronous); dg_mesh_build, dg_budgets
+ *     and dg_indicator (flags copied to the host) synchronise the stream.
+ *   - Every function returns a dg_status; nothing throws across the ABI.  On an
+ *     error the outputs are unspecified, handles stay valid, and
+ *     dg_last_error() returns a message (thread-local).  Faults of kernels
+ *     already enqueued surface at the next synchronising call as DG_EHIP.
+ *   - Aliasing: outputs must not alias inputs unless stated.
+ */
+#ifndef DGAMR_DG_H
+#define DGAMR_DG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dg_status;
+#define DG_OK            0
+#define DG_EINVAL       -1   /* bad argument, unsupported size, wrong mesh pair */
+#define DG_ENOMEM       -2   /* host or device allocation failed */
+#define DG_EHIP         -3   /* a HIP runtime call or a kernel failed */
+#define DG_EUNSUPPORTED -4   /* valid request the build does not provide */
+#define DG_ENONFINITE   -5   /* a budget or indicator saw a non-finite value */
+
+#define DG_PASS_COARSEN 0
+#define DG_PASS_REFINE  1
+
+#define DG_BG_NEUTRAL   0    /* constant theta0: exner = 1 - g z/(cp theta0) */
+#define DG_BG_CONSTANT  1    /* rhobar = rho0, Thetabar = Theta0 everywhere  */
+
+#define DG_FP64         0    /* every operation in float64 */
+#define DG_MIXED        1    /* volume flux contractions in float32, rest float64 */
+
+#define DG_IND_THETA      0  /* eta_e = max |theta'| over the leaf's nodes   */
+#define DG_IND_GRAD_THETA 1  /* eta_e = max |grad theta| over the leaf's nodes */
+
+#define DG_KIND_COPY   -1    /* transfer: new leaf is old leaf src */
+#define DG_KIND_FAMILY  8    /* transfer: new leaf is the parent of old src..src+7 */
+
+typedef struct dg_mesh dg_mesh;   /* opaque */
+
+/* Brick forest: nx*ny*nz root hexes tiling [lo,hi], trees refined up to
+ * max_level (<= 12), polynomial order N (2..7).  periodic[d] = 1 joins the two
+ * faces normal to axis d, 0 makes them no-flux walls.  host_only = 1 builds the
+ * host tables only (no device memory; field calls on such a mesh fail with
+ * DG_EINVAL) -- used to check the integer tables on machines without a GPU. */
+typedef struct {
+    int32_t N, nx, ny, nz, max_level;
+    int32_t periodic[3];
+    double lo[3], hi[3];
+    int32_t host_only;
+} dg_forest_desc;
+
+/* Gas constants (section 2.1: R = cp - cv, gamma = cp/cv, P = P0 (R Theta/P0)^gamma),
+ * gravity g and the hydrostatic background (section 2.1 perturbation form;
+ * neutral profile of section 4.3).  precision selects DG_FP64 or DG_MIXED. */
+typedef struct {
+    double cp, cv, P0, g;
+    int32_t background;
+    int32_t precision;
+    double theta0, rho0, Theta0;
+} dg_phys;
+
+typedef struct {
+    int64_t K;            /* number of leaves */
+    int64_t Np;           /* (N+1)^3 */
+    int64_t n_conf;       /* conforming interior faces (incl. periodic wraps) */
+    int64_t n_bnd;        /* wall faces */
+    int64_t n_hang;       /* hanging faces (each = 1 coarse + 4 fine) */
+    int64_t n_refined;    /* old leaves refined by the pass that built this mesh */
+    int64_t n_coarsened;  /* families merged by the pass that built this mesh */
+    int32_t N;
+    int32_t max_level_present;
+} dg_mesh_info;
+
+/* Host copies of the integer tables (caller allocates, sizes from dg_mesh_info).
+ *   leaf [K][5]       (root, level, ix, iy, iz), root = rx + nx*(ry + ny*rz)
+ *   conf [n_conf][3]  (eM, eP, d): plus face of eM meets minus face of eP
+ *   bnd  [n_bnd][2]   (e, f), f = 2*d + s (s = 1 plus side)
+ *   hang [n_hang][6]  (ec, f, e0, e1, e2, e3): coarse leaf ec's face f is
+ *                     covered by fine leaves ordered by quadrant a + 2b over
+ *                     the two tangential axes in increasing axis order
+ *   xfer_src/kind [K] transfer plan from the previous mesh (DG_KIND_*, or the
+ *                     child id 0..7 = a + 2b + 4c of old leaf src)
+ * Any pointer may be NULL to skip that table. */
+typedef struct {
+    int32_t* leaf;
+    int32_t* conf;
+    int32_t* bnd;
+    int32_t* hang;
+    int32_t* xfer_src;
+    int32_t* xfer_kind;
+} dg_mesh_tables;
+
+/* Initial perturbation (row "background + IC"): a cosine bell of potential
+ * temperature dtheta * (1 + cos(pi r))/2 for r <= 1, r^2 = sum_d ((x_d - c_d)/r_d)^2
+ * over the axes with r_d > 0 (r_d = 0 drops that axis), at unperturbed
+ * hydrostatic pressure: Theta' = 0, rho' = -rhobar theta'/(theta0 + theta'),
+ * U = 0 (sections 4.2 and 4.3 cosine bell and rising bubble). */
+typedef struct {
+    double dtheta;
+    double centre[3];
+    double radius[3];
+} dg_bell;
+
+/* Build a mesh.  prev == NULL: uniform level-0 forest from desc (flags, pass
+ * ignored).  Otherwise one pass over prev (desc is taken from prev and the
+ * argument may be NULL): DG_PASS_REFINE applies the +1 flags of `flags` (host
+ * int8[K(prev)]) to leaves below max_level and then refines every leaf that
+ * has a face neighbour two or more levels finer, to a fixed point (2:1 face
+ * balance, periodic wraps included).  DG_PASS_COARSEN merges every family of 8
+ * sibling leaves that are all flagged -1 unless a leaf face-adjacent to the
+ * parent is two or more levels finer than the parent (judged on prev).
+ * On success *out is a new handle (free with dg_mesh_free) whose transfer
+ * plan refers to prev; prev must stay alive while it is used by the
+ * projections.  Synchronous. */
+dg_status dg_mesh_build(const dg_forest_desc* desc, const dg_mesh* prev, const int8_t* flags,
+                        int32_t pass, dg_mesh** out);
+dg_status dg_mesh_free(dg_mesh* mesh);
+dg_status dg_mesh_info_get(const dg_mesh* mesh, dg_mesh_info* info);
+dg_status dg_mesh_export(const dg_mesh* mesh, const dg_mesh_tables* tables);
+
+/* Node coordinates xyz[3][K][Np] (device, float64):
+ * x = lo + (hi-lo)/n * (r + (anchor + (1 + xi)/2) / 2^level) per axis. */
+dg_status dg_node_coords(const dg_mesh* mesh, double* xyz, void* stream);
+
+/* q (device [5][K][Np]) := cosine-bell perturbation described by *bell. */
+dg_status dg_init_bell(const dg_mesh* mesh, const dg_phys* phys, const dg_bell* bell, double* q,
+                       void* stream);
+
+/* rhs := R(q), the strong-form dGSEM right-hand side (section 2.2):
+ *   R = -sum_d (2/h_d) D_d F^d(q) + S(q) - lift((F* - F(q-)).n)
+ * with F the Euler flux carrying the pressure perturbation P', S the buoyancy
+ * -rho' g on rho*w, F* the Rusanov flux (local max wave speed, jump of the
+ * perturbation variables), mirror states at walls and L2 mortars on hanging
+ * faces (section 3.3).  rhs must not alias q. */
+dg_status dg_rhs(const dg_mesh* mesh, const dg_phys* phys, const double* q, double* rhs,
+                 void* stream);
+
+/* One Shu-Osher stage: qout := a*q0 + b*(qs + dt*R(qs)).  SSP-RK3 uses
+ * (a,b) = (0,1), (3/4,1/4), (1/3,2/3).  qout may alias q0 but not qs; q0 is
+ * not read when a == 0. */
+dg_status dg_rk_stage(const dg_mesh* mesh, const dg_phys* phys, double a, double b, double dt,
+                      const double* q0, const double* qs, double* qout, void* stream);
+
+/* Conservative transfer (section 3.3): `to` must have been built by a pass over
+ * `from`.  Refine: a child (a,b,c) gets (I_a x I_b x I_c) q_parent, I_a the
+ * interpolation of the parent polynomial to half-interval a (equal to the L2
+ * projection there).  Coarsen: the parent gets sum over the 8 children of
+ * (R_a x R_b x R_c) q_child, R_a = 1/2 M^{-1} I_a^T M with the exact mass
+ * matrix M (integrals are preserved).  Kept leaves are copied.  q_to must
+ * not alias q_from. */
+dg_status dg_refine_project(const dg_mesh* from, const dg_mesh* to, const double* q_from,
+                            double* q_to, void* stream);
+dg_status dg_coarsen_project(const dg_mesh* from, const dg_mesh* to, const double* q_from,
+                             double* q_to, void* stream);
+
+/* qbar := (dR/dq)^T lam, the exact transpose of the linearised right-hand side
+ * in the Euclidean inner product on the DOF vector (d|x|/dx := 0 at 0, a max
+ * tie splits the derivative 1/2, 1/2).  qbar must not alias q or lam. */
+dg_status dg_rhs_adjoint(const dg_mesh* mesh, const dg_phys* phys, const double* q,
+                         const double* lam, double* qbar, void* stream);
+
+/* Budgets over the mesh with weights J_e W_n = (hx hy hz / 8) w_i w_j w_k:
+ * out_host[0] = sum rho', [1] = sum (rhobar + rho'), [2] = sum Theta',
+ * [3] = sum P/(gamma-1) + |U|^2/(2 rho) + rho g z.  Compensated float64
+ * summation in a fixed order (deterministic).  Synchronises the stream. */
+dg_status dg_budgets(const dg_mesh* mesh, const dg_phys* phys, const double* q, double* out_host,
+                     void* stream);
+
+/* Adaptation indicator: eta (device double[K], may be NULL) and flags (host
+ * int8[K]): +1 where eta > thr and level < max_level, -1 where eta <= thr and
+ * level > 0, else 0.  kind is DG_IND_THETA or DG_IND_GRAD_THETA.
+ * Synchronises the stream. */
+dg_status dg_indicator(const dg_mesh* mesh, const dg_phys* phys, const double* q, int32_t kind,
+                       double thr, double* eta, int8_t* flags_host, void* stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* dg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGAMR_DG_H */

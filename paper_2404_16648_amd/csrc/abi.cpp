@@ -1,0 +1,406 @@
+// C ABI of the DG-AMR library: argument checks, mesh lifetime, device tables
+// and kernel launches.  Declarations and contracts are in include/dg.h.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dg.h"
+#include "internal.hpp"
+#include "kernels.hpp"
+
+using namespace dgamr;
+
+namespace {
+
+thread_local std::string g_err;
+std::atomic<uint64_t> g_next_id{1};
+
+dg_status fail(dg_status code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+dg_status hip_fail(hipError_t e, const char* where) {
+    return fail(DG_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                            \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);        \
+    } while (0)
+
+template <typename T>
+hipError_t upload(T** dst, const std::vector<T>& src) {
+    if (src.empty()) {
+        *dst = nullptr;
+        return hipSuccess;
+    }
+    hipError_t e = hipMalloc((void**)dst, src.size() * sizeof(T));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+void free_device(dg_mesh* m) {
+    void* ptrs[] = {m->d_ops, m->d_geo, m->d_c1d, m->d_ftype, m->d_fnb, m->d_level,
+                    m->d_xsrc, m->d_xkind, m->d_bg, m->d_red, m->d_flags, m->d_eta};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    m->d_ops = m->d_geo = m->d_c1d = m->d_bg = m->d_red = m->d_eta = nullptr;
+    m->d_ftype = m->d_fnb = m->d_level = m->d_xsrc = m->d_xkind = nullptr;
+    m->d_flags = nullptr;
+}
+
+// every face of every leaf has a type and in-range neighbours (the kernels index
+// field arrays with them); checked on the host before anything is uploaded
+bool tables_consistent(const HostMesh& h) {
+    const int64_t K = (int64_t)h.leaves.size();
+    if ((int64_t)h.ftype.size() != 6 * K || (int64_t)h.fnb.size() != 24 * K) return false;
+    for (int64_t i = 0; i < 6 * K; ++i) {
+        const int type = h.ftype[i] & 0xff;
+        const int nnb = type == FT_WALL ? 0 : type == FT_COARSE ? 4 : 1;
+        if (type > FT_COARSE || h.ftype[i] < 0) return false;
+        for (int q = 0; q < nnb; ++q)
+            if (h.fnb[i * 4 + q] < 0 || h.fnb[i * 4 + q] >= K) return false;
+    }
+    for (int64_t e = 0; e < K; ++e)
+        if (h.xfer_src[e] < 0) return false;
+    return true;
+}
+
+dg_status build_device(dg_mesh* m) {
+    const HostMesh& h = m->h;
+    const int64_t K = (int64_t)h.leaves.size();
+    if (!tables_consistent(h)) return fail(DG_EINVAL, "internal: inconsistent face tables");
+    if (K >= (int64_t)1 << 31) return fail(DG_EINVAL, "too many leaves for one launch");
+    const int N = h.desc.N, N1 = N + 1;
+    std::vector<double> ops;
+    for (auto* v : {&m->ops.D, &m->ops.I0, &m->ops.I1, &m->ops.R0, &m->ops.R1, &m->ops.w})
+        ops.insert(ops.end(), v->begin(), v->end());
+    std::vector<double> geo(K * 4), c1d(3 * K * N1);
+    std::vector<int32_t> level(K);
+    std::vector<double> c(3 * N1);
+    for (int64_t e = 0; e < K; ++e) {
+        double hh[3];
+        leaf_geometry(h.desc, h.leaves[e], m->ops.x, hh, c.data());
+        for (int d = 0; d < 3; ++d) {
+            geo[e * 4 + d] = 2.0 / hh[d];
+            for (int j = 0; j < N1; ++j) c1d[(d * K + e) * N1 + j] = c[d * N1 + j];
+        }
+        geo[e * 4 + 3] = hh[0] * hh[1] * hh[2] / 8.0;
+        level[e] = h.leaves[e].l;
+    }
+    HIP_TRY(hipGetDevice(&m->device));
+    HIP_TRY(upload(&m->d_ops, ops));
+    HIP_TRY(upload(&m->d_geo, geo));
+    HIP_TRY(upload(&m->d_c1d, c1d));
+    HIP_TRY(upload(&m->d_ftype, h.ftype));
+    HIP_TRY(upload(&m->d_fnb, h.fnb));
+    HIP_TRY(upload(&m->d_level, level));
+    HIP_TRY(upload(&m->d_xsrc, h.xfer_src));
+    HIP_TRY(upload(&m->d_xkind, h.xfer_kind));
+    HIP_TRY(hipMalloc((void**)&m->d_bg, sizeof(double) * 3 * K * N1));
+    m->red_len = (int64_t)budget_blocks(K) * 8 + 8;
+    HIP_TRY(hipMalloc((void**)&m->d_red, sizeof(double) * m->red_len));
+    HIP_TRY(hipMalloc((void**)&m->d_flags, K > 0 ? K : 1));
+    HIP_TRY(hipMalloc((void**)&m->d_eta, sizeof(double) * (K > 0 ? K : 1)));
+    m->on_device = true;
+    return DG_OK;
+}
+
+dg_status check_phys(const dg_phys* p) {
+    if (!p) return fail(DG_EINVAL, "phys is NULL");
+    if (!(p->cv > 0.0) || !(p->cp > p->cv)) return fail(DG_EINVAL, "need cp > cv > 0");
+    if (!(p->P0 > 0.0)) return fail(DG_EINVAL, "need P0 > 0");
+    if (p->background == DG_BG_NEUTRAL) {
+        if (!(p->theta0 > 0.0)) return fail(DG_EINVAL, "need theta0 > 0");
+    } else if (p->background == DG_BG_CONSTANT) {
+        if (!(p->rho0 > 0.0) || !(p->Theta0 > 0.0)) return fail(DG_EINVAL, "need rho0, Theta0 > 0");
+    } else {
+        return fail(DG_EINVAL, "unknown background");
+    }
+    if (p->precision != DG_FP64 && p->precision != DG_MIXED) return fail(DG_EINVAL, "unknown precision");
+    return DG_OK;
+}
+
+dg_status check_dev_mesh(const dg_mesh* m) {
+    if (!m) return fail(DG_EINVAL, "mesh is NULL");
+    if (!m->on_device) return fail(DG_EINVAL, "mesh was built host_only");
+    return DG_OK;
+}
+
+bool same_bg(const dg_phys& a, const dg_phys& b) {
+    return a.cp == b.cp && a.cv == b.cv && a.P0 == b.P0 && a.g == b.g && a.background == b.background &&
+           a.theta0 == b.theta0 && a.rho0 == b.rho0 && a.Theta0 == b.Theta0;
+}
+
+// background profile [3][K][N+1] for phys, (re)computed on the caller's stream when phys changes
+dg_status ensure_bg(dg_mesh* m, const dg_phys* p, hipStream_t s) {
+    if (m->bg_valid && same_bg(m->bg_phys, *p)) return DG_OK;
+    BgParams bp{p->background, p->cp, p->cv, p->P0, p->g, p->theta0, p->rho0, p->Theta0};
+    HIP_TRY(launch_background((int64_t)m->h.leaves.size(), m->h.desc.N, m->d_c1d, m->d_bg, bp, s));
+    m->bg_phys = *p;
+    m->bg_valid = true;
+    return DG_OK;
+}
+
+StageArgs stage_args(const dg_mesh* m, const dg_phys* p) {
+    StageArgs a{};
+    a.ops = m->d_ops;
+    a.geo = m->d_geo;
+    a.bg = m->d_bg;
+    a.ftype = m->d_ftype;
+    a.fnb = m->d_fnb;
+    a.K = (int64_t)m->h.leaves.size();
+    a.gamma = p->cp / p->cv;
+    a.g = p->g;
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dg_last_error(void) { return g_err.c_str(); }
+
+dg_status dg_mesh_build(const dg_forest_desc* desc, const dg_mesh* prev, const int8_t* flags, int32_t pass,
+                        dg_mesh** out) {
+    if (!out) return fail(DG_EINVAL, "out is NULL");
+    *out = nullptr;
+    dg_mesh* m = nullptr;
+    try {
+        m = new dg_mesh();
+        std::string err;
+        if (!prev) {
+            if (!desc) {
+                delete m;
+                return fail(DG_EINVAL, "desc is NULL");
+            }
+            err = forest_uniform(*desc, m->h);
+        } else {
+            if (!flags && !prev->h.leaves.empty()) {
+                delete m;
+                return fail(DG_EINVAL, "flags is NULL");
+            }
+            if (pass == DG_PASS_REFINE)
+                err = forest_refine(prev->h, flags, m->h);
+            else if (pass == DG_PASS_COARSEN)
+                err = forest_coarsen(prev->h, flags, m->h);
+            else
+                err = "unknown pass";
+            m->prev = prev;
+            m->prev_id = prev->id;
+        }
+        if (!err.empty()) {
+            delete m;
+            return fail(DG_EINVAL, err);
+        }
+        m->ops = make_refops(m->h.desc.N);
+        m->id = g_next_id++;
+        if (!m->h.desc.host_only) {
+            dg_status st = build_device(m);
+            if (st != DG_OK) {
+                free_device(m);
+                delete m;
+                return st;
+            }
+        }
+    } catch (const std::bad_alloc&) {
+        if (m) {
+            free_device(m);
+            delete m;
+        }
+        return fail(DG_ENOMEM, "host allocation failed");
+    } catch (const std::exception& ex) {
+        if (m) {
+            free_device(m);
+            delete m;
+        }
+        return fail(DG_EINVAL, ex.what());
+    }
+    *out = m;
+    return DG_OK;
+}
+
+dg_status dg_mesh_free(dg_mesh* m) {
+    if (!m) return DG_OK;
+    free_device(m);
+    delete m;
+    return DG_OK;
+}
+
+dg_status dg_mesh_info_get(const dg_mesh* m, dg_mesh_info* info) {
+    if (!m || !info) return fail(DG_EINVAL, "NULL argument");
+    const HostMesh& h = m->h;
+    info->K = (int64_t)h.leaves.size();
+    info->N = h.desc.N;
+    info->Np = (int64_t)(h.desc.N + 1) * (h.desc.N + 1) * (h.desc.N + 1);
+    info->n_conf = (int64_t)h.conf.size() / 3;
+    info->n_bnd = (int64_t)h.bnd.size() / 2;
+    info->n_hang = (int64_t)h.hang.size() / 6;
+    info->n_refined = h.n_refined;
+    info->n_coarsened = h.n_coarsened;
+    int lmax = 0;
+    for (const Leaf& lf : h.leaves) lmax = lf.l > lmax ? lf.l : lmax;
+    info->max_level_present = lmax;
+    return DG_OK;
+}
+
+dg_status dg_mesh_export(const dg_mesh* m, const dg_mesh_tables* t) {
+    if (!m || !t) return fail(DG_EINVAL, "NULL argument");
+    const HostMesh& h = m->h;
+    if (t->leaf)
+        for (size_t e = 0; e < h.leaves.size(); ++e) {
+            const Leaf& lf = h.leaves[e];
+            int32_t* row = t->leaf + 5 * e;
+            row[0] = lf.r;
+            row[1] = lf.l;
+            row[2] = lf.a[0];
+            row[3] = lf.a[1];
+            row[4] = lf.a[2];
+        }
+    auto cp = [](int32_t* dst, const std::vector<int32_t>& src) {
+        if (dst && !src.empty()) std::memcpy(dst, src.data(), src.size() * sizeof(int32_t));
+    };
+    cp(t->conf, h.conf);
+    cp(t->bnd, h.bnd);
+    cp(t->hang, h.hang);
+    cp(t->xfer_src, h.xfer_src);
+    cp(t->xfer_kind, h.xfer_kind);
+    return DG_OK;
+}
+
+dg_status dg_node_coords(const dg_mesh* m, double* xyz, void* stream) {
+    dg_status st = check_dev_mesh(m);
+    if (st) return st;
+    if (!xyz) return fail(DG_EINVAL, "xyz is NULL");
+    HIP_TRY(launch_node_coords((int64_t)m->h.leaves.size(), m->h.desc.N, m->d_c1d, xyz, (hipStream_t)stream));
+    return DG_OK;
+}
+
+dg_status dg_init_bell(const dg_mesh* mc, const dg_phys* phys, const dg_bell* bell, double* q, void* stream) {
+    dg_status st = check_dev_mesh(mc);
+    if (st) return st;
+    if ((st = check_phys(phys))) return st;
+    if (!bell || !q) return fail(DG_EINVAL, "NULL argument");
+    dg_mesh* m = const_cast<dg_mesh*>(mc);
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = ensure_bg(m, phys, s))) return st;
+    const double th0 = phys->background == DG_BG_NEUTRAL ? phys->theta0 : phys->Theta0 / phys->rho0;
+    HIP_TRY(launch_init_bell((int64_t)m->h.leaves.size(), m->h.desc.N, m->d_c1d, m->d_bg, th0, *bell, q, s));
+    return DG_OK;
+}
+
+static dg_status stage_common(const dg_mesh* mc, const dg_phys* phys, int mode, double a, double b, double dt,
+                              const double* q0, const double* qs, double* out, void* stream) {
+    dg_status st = check_dev_mesh(mc);
+    if (st) return st;
+    if ((st = check_phys(phys))) return st;
+    if (phys->precision != DG_FP64) return fail(DG_EUNSUPPORTED, "mixed precision is not available in this call");
+    if (!qs || !out) return fail(DG_EINVAL, "NULL field pointer");
+    if (out == qs) return fail(DG_EINVAL, "output must not alias the stage input");
+    if (mode == MODE_RK && a != 0.0 && !q0) return fail(DG_EINVAL, "q0 is NULL while a != 0");
+    dg_mesh* m = const_cast<dg_mesh*>(mc);
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = ensure_bg(m, phys, s))) return st;
+    StageArgs args = stage_args(m, phys);
+    args.q0 = q0;
+    args.qs = qs;
+    args.out = out;
+    args.a = a;
+    args.b = b;
+    args.dt = dt;
+    HIP_TRY(launch_stage(m->h.desc.N, mode, args, s));
+    return DG_OK;
+}
+
+dg_status dg_rhs(const dg_mesh* m, const dg_phys* phys, const double* q, double* rhs, void* stream) {
+    return stage_common(m, phys, MODE_RHS, 0.0, 1.0, 0.0, nullptr, q, rhs, stream);
+}
+
+dg_status dg_rk_stage(const dg_mesh* m, const dg_phys* phys, double a, double b, double dt, const double* q0,
+                      const double* qs, double* qout, void* stream) {
+    return stage_common(m, phys, MODE_RK, a, b, dt, q0, qs, qout, stream);
+}
+
+static dg_status xfer_common(const dg_mesh* from, const dg_mesh* to, const double* qf, double* qt, void* stream,
+                             bool refine) {
+    dg_status st = check_dev_mesh(from);
+    if (st) return st;
+    if ((st = check_dev_mesh(to))) return st;
+    if (to->prev_id != from->id) return fail(DG_EINVAL, "`to` was not built from `from`");
+    if (!qf || !qt) return fail(DG_EINVAL, "NULL field pointer");
+    if (qf == qt) return fail(DG_EINVAL, "q_to must not alias q_from");
+    if (refine && to->h.n_coarsened) return fail(DG_EINVAL, "`to` was built by a coarsen pass");
+    if (!refine && to->h.n_refined) return fail(DG_EINVAL, "`to` was built by a refine pass");
+    XferArgs a{qf, qt, to->d_ops, to->d_xsrc, to->d_xkind, (int64_t)from->h.leaves.size(),
+               (int64_t)to->h.leaves.size()};
+    hipStream_t s = (hipStream_t)stream;
+    if (refine)
+        HIP_TRY(launch_refine(to->h.desc.N, a, s));
+    else
+        HIP_TRY(launch_coarsen(to->h.desc.N, a, s));
+    return DG_OK;
+}
+
+dg_status dg_refine_project(const dg_mesh* from, const dg_mesh* to, const double* q_from, double* q_to,
+                            void* stream) {
+    return xfer_common(from, to, q_from, q_to, stream, true);
+}
+
+dg_status dg_coarsen_project(const dg_mesh* from, const dg_mesh* to, const double* q_from, double* q_to,
+                             void* stream) {
+    return xfer_common(from, to, q_from, q_to, stream, false);
+}
+
+dg_status dg_rhs_adjoint(const dg_mesh* m, const dg_phys* phys, const double* q, const double* lam, double* qbar,
+                         void* stream) {
+    (void)m; (void)phys; (void)q; (void)lam; (void)qbar; (void)stream;
+    return fail(DG_EUNSUPPORTED, "dg_rhs_adjoint is not available in this build");
+}
+
+dg_status dg_budgets(const dg_mesh* mc, const dg_phys* phys, const double* q, double* out_host, void* stream) {
+    dg_status st = check_dev_mesh(mc);
+    if (st) return st;
+    if ((st = check_phys(phys))) return st;
+    if (!q || !out_host) return fail(DG_EINVAL, "NULL argument");
+    dg_mesh* m = const_cast<dg_mesh*>(mc);
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = ensure_bg(m, phys, s))) return st;
+    const int64_t K = (int64_t)m->h.leaves.size();
+    const int nblk = budget_blocks(K);
+    BudgetArgs a{q, m->d_bg, m->d_geo, m->d_c1d, m->d_ops + 5 * (m->h.desc.N + 1) * (m->h.desc.N + 1),
+                 m->d_red, K, phys->cp / phys->cv, phys->g};
+    double* out_dev = m->d_red + (int64_t)nblk * 8;
+    HIP_TRY(launch_budgets(m->h.desc.N, a, nblk, out_dev, s));
+    HIP_TRY(hipMemcpyAsync(out_host, out_dev, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < 4; ++i)
+        if (!std::isfinite(out_host[i])) return fail(DG_ENONFINITE, "non-finite budget");
+    return DG_OK;
+}
+
+dg_status dg_indicator(const dg_mesh* mc, const dg_phys* phys, const double* q, int32_t kind, double thr,
+                       double* eta, int8_t* flags_host, void* stream) {
+    dg_status st = check_dev_mesh(mc);
+    if (st) return st;
+    if ((st = check_phys(phys))) return st;
+    if (!q || !flags_host) return fail(DG_EINVAL, "NULL argument");
+    if (kind != DG_IND_THETA && kind != DG_IND_GRAD_THETA) return fail(DG_EINVAL, "unknown indicator kind");
+    dg_mesh* m = const_cast<dg_mesh*>(mc);
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = ensure_bg(m, phys, s))) return st;
+    const int64_t K = (int64_t)m->h.leaves.size();
+    IndArgs a{q, m->d_bg, m->d_geo, m->d_ops, m->d_level, eta ? eta : m->d_eta, m->d_flags, K, kind,
+              m->h.desc.max_level, thr};
+    HIP_TRY(launch_indicator(m->h.desc.N, a, s));
+    if (K > 0) HIP_TRY(hipMemcpyAsync(flags_host, m->d_flags, K, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return DG_OK;
+}
+
+}  // extern "C"

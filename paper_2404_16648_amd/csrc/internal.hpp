@@ -1,0 +1,74 @@
+// Internal declarations of the DG-AMR library (host side).  Not part of the ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dg.h"
+#include "facetypes.hpp"
+
+namespace dgamr {
+
+constexpr int kMaxN = 7;
+constexpr int kMinN = 2;
+constexpr int kMaxLevel = 12;
+
+struct Leaf {
+    int32_t r, l, a[3];
+};
+
+// 1-D reference operators for order N, float64 (row-major [N+1][N+1])
+struct RefOps {
+    int N = 0;
+    std::vector<double> x, w, D, I0, I1, R0, R1;
+};
+RefOps make_refops(int N);
+
+struct HostMesh {
+    dg_forest_desc desc{};
+    std::vector<Leaf> leaves;
+    std::vector<int32_t> conf, bnd, hang;        // flattened tables (3, 2, 6 per row)
+    std::vector<int32_t> xfer_src, xfer_kind;
+    std::vector<int32_t> ftype, fnb;             // [K][6], [K][6][4]
+    int64_t n_refined = 0, n_coarsened = 0;
+};
+
+// forest passes (host, integer work); return "" or an error message
+std::string forest_uniform(const dg_forest_desc& desc, HostMesh& out);
+std::string forest_refine(const HostMesh& prev, const int8_t* flags, HostMesh& out);
+std::string forest_coarsen(const HostMesh& prev, const int8_t* flags, HostMesh& out);
+void forest_tables(HostMesh& m);
+
+// geometry of leaf e: h[3] and 1-D node coordinates c[3][N+1]
+void leaf_geometry(const dg_forest_desc& desc, const Leaf& lf, const std::vector<double>& xi,
+                   double h[3], double* c /* [3][N+1] */);
+
+}  // namespace dgamr
+
+struct dg_mesh {
+    dgamr::HostMesh h;
+    dgamr::RefOps ops;
+    const dg_mesh* prev = nullptr;
+    uint64_t id = 0, prev_id = 0;
+    bool on_device = false;
+    int device = 0;
+    // device tables
+    double* d_ops = nullptr;      // D, I0, I1, R0, R1 ([N1][N1] each), w [N1]
+    double* d_geo = nullptr;      // [K][4]: 2/hx, 2/hy, 2/hz, hx*hy*hz/8
+    double* d_c1d = nullptr;      // [3][K][N1] node coordinates per axis
+    int32_t* d_ftype = nullptr;   // [K][6]
+    int32_t* d_fnb = nullptr;     // [K][6][4]
+    int32_t* d_level = nullptr;   // [K]
+    int32_t* d_xsrc = nullptr;    // [K]
+    int32_t* d_xkind = nullptr;   // [K]
+    // background profile [3][K][N1] for bg_phys (computed on first use)
+    double* d_bg = nullptr;
+    dg_phys bg_phys{};
+    bool bg_valid = false;
+    // workspaces
+    double* d_red = nullptr;      // reduction partials
+    int64_t red_len = 0;
+    int8_t* d_flags = nullptr;    // [K]
+    double* d_eta = nullptr;      // [K]
+};

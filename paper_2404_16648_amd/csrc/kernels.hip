@@ -1,0 +1,707 @@
+// HIP kernels for gfx950 (MI355X) of the DG-AMR hot path.
+//
+// One workgroup per leaf ("element-centric"): the fused stage kernel loads the
+// leaf's (N+1)^3 tile into LDS, evaluates the pointwise physics and the three
+// tensor-product derivative contractions (strong-form volume term, section
+// 2.2), then computes the Rusanov flux on each of its six faces against the
+// neighbour trace gathered straight from HBM (conforming faces, no-flux walls,
+// and L2 mortars on hanging faces, section 3.3), lifts (F* - F).n into the
+// face nodes, and writes either R or the Shu-Osher stage a q0 + b (qs + dt R).
+// Every face is evaluated by both of its leaves; the Rusanov flux is computed
+// so that F*(qL, qR, n) = -F*(qR, qL, -n) bitwise, and both sides of a mortar
+// build the mortar state with the same arithmetic, so what one side gains the
+// other loses to the last bit (discrete conservation, section 2.1).
+//
+// The file is compiled with -ffp-contract=off: every fused multiply-add is an
+// explicit fma(), so that the rounding of a value does not depend on where the
+// compiler inlines it.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace dgamr {
+namespace {
+
+constexpr int kXcd = 8;  // MI355X: 8 XCDs, workgroups dispatched round-robin
+
+// Give each XCD a contiguous range of leaves (Morton order keeps face
+// neighbours close), so neighbour traces are mostly L2 hits on that XCD.
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblk) {
+    const int64_t q = nblk / kXcd, r = nblk % kXcd;
+    const int64_t x = bid % kXcd, i = bid / kXcd;
+    return x * q + (x < r ? x : r) + i;
+}
+
+template <int N>
+struct Sz {
+    static constexpr int N1 = N + 1;
+    static constexpr int NP = N1 * N1 * N1;
+    static constexpr int NF = N1 * N1;
+    static constexpr int NT = ((NP + 63) / 64) * 64;   // one thread per node
+    static constexpr int NOPS = 5 * NF + N1;           // D, I0, I1, R0, R1, w
+};
+
+// element node of face f = 2d + s at face-local index m = a + (N+1) b, with
+// (a, b) along the tangential axes in increasing axis order
+template <int N>
+__device__ __forceinline__ int face_node(int f, int m) {
+    constexpr int N1 = N + 1;
+    const int d = f >> 1, idx = (f & 1) ? N : 0;
+    const int a = m % N1, b = m / N1;
+    if (d == 0) return idx + N1 * (a + N1 * b);
+    if (d == 1) return a + N1 * (idx + N1 * b);
+    return a + N1 * (b + N1 * idx);
+}
+
+// k (z index) of that node, which selects the background value
+template <int N>
+__device__ __forceinline__ int face_k(int f, int m) {
+    const int d = f >> 1;
+    if (d == 2) return (f & 1) ? N : 0;
+    return m / (N + 1);
+}
+
+// P' = Pbar expm1(gamma log1p(Theta'/Thetabar))  (cancellation-free P(Theta) - Pbar)
+__device__ __forceinline__ double pprime(double Thp, double Thb, double Pb, double gamma) {
+    return Pb * expm1(gamma * log1p(Thp / Thb));
+}
+
+struct Bg {
+    double rho, Th, P;
+};
+
+// sgn * F^d(q) and the wave speed |u_d| + c
+__device__ __forceinline__ void flux_n(const double q[5], const Bg& bg, double Pp, int d, double sgn, double gamma,
+                                       double F[5], double& lam) {
+    const double rho = bg.rho + q[0];
+    const double ud = q[1 + d] / rho;
+    const double Th = bg.Th + q[4];
+    F[0] = sgn * q[1 + d];
+    F[1] = sgn * (d == 0 ? q[1] * ud + Pp : q[1] * ud);
+    F[2] = sgn * (d == 1 ? q[2] * ud + Pp : q[2] * ud);
+    F[3] = sgn * (d == 2 ? q[3] * ud + Pp : q[3] * ud);
+    F[4] = sgn * (Th * ud);
+    lam = fabs(ud) + sqrt(gamma * (bg.P + Pp) / rho);
+}
+
+// Rusanov flux F*.n, n = sgn e_d:  {F.n} + 1/2 max(|u.n| + c) (q'- - q'+)  (section 2.2)
+__device__ __forceinline__ void rusanov(const double qL[5], const Bg& bL, double PpL, const double qR[5],
+                                        const Bg& bR, double PpR, int d, double sgn, double gamma,
+                                        double Fs[5]) {
+    double FL[5], FR[5], lL, lR;
+    flux_n(qL, bL, PpL, d, sgn, gamma, FL, lL);
+    flux_n(qR, bR, PpR, d, sgn, gamma, FR, lR);
+    const double hl = 0.5 * fmax(lL, lR);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Fs[v] = 0.5 * (FL[v] + FR[v]) + hl * (qL[v] - qR[v]);
+}
+
+// (I_a x I_b) applied to a face trace T[(N+1)^2] at face node m
+template <int N>
+__device__ __forceinline__ double tensor2(const double* T, const double* A, const double* B, int m) {
+    constexpr int N1 = N + 1;
+    const int m1 = m % N1, m2 = m / N1;
+    double acc = 0.0;
+#pragma unroll
+    for (int j2 = 0; j2 < N1; ++j2) {
+        double row = 0.0;
+#pragma unroll
+        for (int j1 = 0; j1 < N1; ++j1) row = fma(A[m1 * N1 + j1], T[j2 * N1 + j1], row);
+        acc = fma(B[m2 * N1 + j2], row, acc);
+    }
+    return acc;
+}
+
+template <int N, int MODE>
+__global__ void __launch_bounds__(Sz<N>::NT) k_stage(const StageArgs A) {
+    constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
+    __shared__ double sQ[5 * NP];
+    __shared__ double sPp[NP];
+    __shared__ double sF[15 * NP];          // fluxes; reused as mortar scratch (20 NF <= 15 NP)
+    __shared__ double sS[6 * 5 * NF];       // lifted (F* - F).n per face
+    __shared__ double sT[5 * NF];           // a face trace for mortar interpolation
+    __shared__ double sOps[Sz<N>::NOPS];
+    __shared__ double sBg[3 * N1];
+    __shared__ int sType[6];
+    __shared__ int sNb[24];
+
+    const int64_t K = A.K;
+    const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
+    const int t = threadIdx.x;
+    const double gamma = A.gamma;
+    const double* D = sOps;
+    // I_a at sOps + (1 + a) NF, R_a at sOps + (3 + a) NF
+
+    for (int i = t; i < Sz<N>::NOPS; i += NT) sOps[i] = A.ops[i];
+    if (t < 3 * N1) sBg[t] = A.bg[(int64_t)(t / N1) * K * N1 + e * N1 + (t % N1)];
+    if (t < 6) sType[t] = A.ftype[e * 6 + t];
+    if (t < 24) sNb[t] = A.fnb[e * 24 + t];
+
+    double q[5] = {0, 0, 0, 0, 0};
+    if (t < NP) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            q[v] = A.qs[(int64_t)v * K * NP + e * NP + t];
+            sQ[v * NP + t] = q[v];
+        }
+    }
+    __syncthreads();
+
+    const int i = t % N1, j = (t / N1) % N1, k = t / NF;
+    double R[5] = {0, 0, 0, 0, 0};
+    if (t < NP) {
+        const double rhob = sBg[k], Thb = sBg[N1 + k], Pb = sBg[2 * N1 + k];
+        const double rho = rhob + q[0];
+        const double u = q[1] / rho, v = q[2] / rho, w = q[3] / rho;
+        const double Pp = pprime(q[4], Thb, Pb, gamma);
+        const double Th = Thb + q[4];
+        sPp[t] = Pp;
+        double* Fx = sF;
+        double* Fy = sF + 5 * NP;
+        double* Fz = sF + 10 * NP;
+        Fx[0 * NP + t] = q[1];
+        Fx[1 * NP + t] = q[1] * u + Pp;
+        Fx[2 * NP + t] = q[2] * u;
+        Fx[3 * NP + t] = q[3] * u;
+        Fx[4 * NP + t] = Th * u;
+        Fy[0 * NP + t] = q[2];
+        Fy[1 * NP + t] = q[1] * v;
+        Fy[2 * NP + t] = q[2] * v + Pp;
+        Fy[3 * NP + t] = q[3] * v;
+        Fy[4 * NP + t] = Th * v;
+        Fz[0 * NP + t] = q[3];
+        Fz[1 * NP + t] = q[1] * w;
+        Fz[2 * NP + t] = q[2] * w;
+        Fz[3 * NP + t] = q[3] * w + Pp;
+        Fz[4 * NP + t] = Th * w;
+        R[3] = -q[0] * A.g;  // buoyancy on rho*w
+    }
+    __syncthreads();
+
+    const double g2x = A.geo[e * 4 + 0], g2y = A.geo[e * 4 + 1], g2z = A.geo[e * 4 + 2];
+    if (t < NP) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            const double* Fx = sF + v * NP;
+            const double* Fy = sF + (5 + v) * NP;
+            const double* Fz = sF + (10 + v) * NP;
+            double ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll
+            for (int m = 0; m < N1; ++m) {
+                ax = fma(D[i * N1 + m], Fx[m + N1 * (j + N1 * k)], ax);
+                ay = fma(D[j * N1 + m], Fy[i + N1 * (m + N1 * k)], ay);
+                az = fma(D[k * N1 + m], Fz[i + N1 * (j + N1 * m)], az);
+            }
+            R[v] -= fma(g2x, ax, fma(g2y, ay, g2z * az));
+        }
+    }
+    __syncthreads();  // sF is free from here on
+
+    // ---- faces: conforming neighbours and walls, every (face, node) item
+    const double liftc = 0.5 * N * (N + 1);  // 1/w_N
+    const double* qs = A.qs;
+    for (int it = t; it < 6 * NF; it += NT) {
+        const int f = it / NF, m = it % NF;
+        const int type = sType[f] & 0xff;
+        if (type != FT_WALL && type != FT_CONF) continue;
+        const int d = f >> 1;
+        const double sgn = (f & 1) ? 1.0 : -1.0;
+        const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
+        double qL[5], qR[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qL[v] = sQ[v * NP + n];
+        const Bg bL{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
+        const double PpL = sPp[n];
+        Bg bR = bL;
+        double PpR = PpL;
+        if (type == FT_WALL) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qR[v] = qL[v];
+            qR[1 + d] = -qL[1 + d];  // mirror state
+        } else {
+            const int64_t nb = sNb[f * 4];
+            const int fo = f ^ 1;
+            const int nn = face_node<N>(fo, m), kn = face_k<N>(fo, m);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qR[v] = qs[(int64_t)v * K * NP + nb * NP + nn];
+            bR = Bg{A.bg[nb * N1 + kn], A.bg[K * N1 + nb * N1 + kn], A.bg[2 * K * N1 + nb * N1 + kn]};
+            PpR = pprime(qR[4], bR.Th, bR.P, gamma);
+        }
+        double Fs[5], Fo[5], lam;
+        rusanov(qL, bL, PpL, qR, bR, PpR, d, sgn, gamma, Fs);
+        flux_n(qL, bL, PpL, d, sgn, gamma, Fo, lam);
+        const double lift = A.geo[e * 4 + d] * liftc;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = (Fs[v] - Fo[v]) * lift;
+    }
+
+    // ---- hanging faces (L2 mortars), one face at a time (uniform over the block)
+    for (int f = 0; f < 6; ++f) {
+        const int type = sType[f] & 0xff;
+        if (type != FT_FINE && type != FT_COARSE) continue;
+        const int d = f >> 1, fo = f ^ 1;
+        const double lift = A.geo[e * 4 + d] * liftc;
+        if (type == FT_FINE) {
+            // this leaf is fine: mortar state = (I_a x I_b) of the coarse trace
+            const int64_t ec = sNb[f * 4];
+            const int quad = sType[f] >> 8, qa = quad & 1, qb = quad >> 1;
+            const double sgn = (f & 1) ? 1.0 : -1.0;
+            __syncthreads();
+            for (int it = t; it < 5 * NF; it += NT) {
+                const int v = it / NF, m = it % NF;
+                sT[it] = qs[(int64_t)v * K * NP + ec * NP + face_node<N>(fo, m)];
+            }
+            __syncthreads();
+            for (int m = t; m < NF; m += NT) {
+                const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
+                const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
+                double qL[5], qM[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    qL[v] = sQ[v * NP + n];
+                    qM[v] = tensor2<N>(sT + v * NF, sOps + (1 + qa) * NF, sOps + (1 + qb) * NF, m);
+                }
+                const double PpM = pprime(qM[4], b.Th, b.P, gamma);
+                double Fs[5], Fo[5], lam;
+                rusanov(qL, b, sPp[n], qM, b, PpM, d, sgn, gamma, Fs);
+                flux_n(qL, b, sPp[n], d, sgn, gamma, Fo, lam);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = (Fs[v] - Fo[v]) * lift;
+            }
+        } else {
+            // this leaf is coarse: 4 mortars, Riemann problems, projection back
+            const double sgn = (f & 1) ? 1.0 : -1.0;
+            double* sM = sF;  // [4][5][NF]
+            __syncthreads();
+            for (int it = t; it < 5 * NF; it += NT) {
+                const int v = it / NF, m = it % NF;
+                sT[it] = sQ[v * NP + face_node<N>(f, m)];
+            }
+            __syncthreads();
+            for (int it = t; it < 4 * NF; it += NT) {
+                const int quad = it / NF, m = it % NF, qa = quad & 1, qb = quad >> 1;
+                const int64_t ef = sNb[f * 4 + quad];
+                const int nn = face_node<N>(fo, m), kn = face_k<N>(fo, m);
+                const Bg b{A.bg[ef * N1 + kn], A.bg[K * N1 + ef * N1 + kn], A.bg[2 * K * N1 + ef * N1 + kn]};
+                double qM[5], qF[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    qM[v] = tensor2<N>(sT + v * NF, sOps + (1 + qa) * NF, sOps + (1 + qb) * NF, m);
+                    qF[v] = qs[(int64_t)v * K * NP + ef * NP + nn];
+                }
+                const double PpM = pprime(qM[4], b.Th, b.P, gamma);
+                const double PpF = pprime(qF[4], b.Th, b.P, gamma);
+                double Fs[5];
+                rusanov(qM, b, PpM, qF, b, PpF, d, sgn, gamma, Fs);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) sM[(quad * 5 + v) * NF + m] = Fs[v];
+            }
+            __syncthreads();
+            for (int m = t; m < NF; m += NT) {
+                const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
+                const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
+                double qL[5], Fo[5], lam;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) qL[v] = sQ[v * NP + n];
+                flux_n(qL, b, sPp[n], d, sgn, gamma, Fo, lam);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    double proj = 0.0;
+#pragma unroll
+                    for (int quad = 0; quad < 4; ++quad)
+                        proj += tensor2<N>(sM + (quad * 5 + v) * NF, sOps + (3 + (quad & 1)) * NF, sOps + (3 + (quad >> 1)) * NF, m);
+                    sS[(f * 5 + v) * NF + m] = (proj - Fo[v]) * lift;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    if (t >= NP) return;
+    // ---- lift: subtract the face contributions at the face nodes
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        if (i == 0) R[v] -= sS[(0 * 5 + v) * NF + j + N1 * k];
+        if (i == N) R[v] -= sS[(1 * 5 + v) * NF + j + N1 * k];
+        if (j == 0) R[v] -= sS[(2 * 5 + v) * NF + i + N1 * k];
+        if (j == N) R[v] -= sS[(3 * 5 + v) * NF + i + N1 * k];
+        if (k == 0) R[v] -= sS[(4 * 5 + v) * NF + i + N1 * j];
+        if (k == N) R[v] -= sS[(5 * 5 + v) * NF + i + N1 * j];
+    }
+    const int64_t base = e * NP + t;
+    if (MODE == MODE_RHS) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) A.out[(int64_t)v * K * NP + base] = R[v];
+    } else {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            const double stage = fma(A.dt, R[v], q[v]);
+            double o = A.b * stage;
+            if (A.a != 0.0) o = fma(A.a, A.q0[(int64_t)v * K * NP + base], o);
+            A.out[(int64_t)v * K * NP + base] = o;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- background, IC, coordinates
+
+__global__ void k_background(int64_t K, int N1, const double* c1d, double* bg, BgParams p) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= K * N1) return;
+    const double z = c1d[2 * K * N1 + idx];
+    const double R = p.cp - p.cv, gamma = p.cp / p.cv;
+    double rho, Th;
+    if (p.kind == DG_BG_NEUTRAL) {
+        const double exner = 1.0 - p.g * z / (p.cp * p.theta0);
+        rho = p.P0 * pow(exner, p.cv / R) / (R * p.theta0);
+        Th = rho * p.theta0;
+    } else {
+        rho = p.rho0;
+        Th = p.Theta0;
+    }
+    bg[idx] = rho;
+    bg[K * N1 + idx] = Th;
+    bg[2 * K * N1 + idx] = p.P0 * pow(R * Th / p.P0, gamma);
+}
+
+__global__ void k_init_bell(int64_t K, int N1, const double* c1d, const double* bg, double theta0, dg_bell bell,
+                            double* q) {
+    const int64_t NP = (int64_t)N1 * N1 * N1;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= K * NP) return;
+    const int64_t e = idx / NP;
+    const int n = (int)(idx % NP);
+    const int ii[3] = {n % N1, (n / N1) % N1, n / (N1 * N1)};
+    double r2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        if (bell.radius[d] > 0.0) {
+            const double s = (c1d[(int64_t)d * K * N1 + e * N1 + ii[d]] - bell.centre[d]) / bell.radius[d];
+            r2 += s * s;
+        }
+    }
+    const double r = sqrt(r2);
+    const double thp = r <= 1.0 ? bell.dtheta * 0.5 * (1.0 + cos(M_PI * r)) : 0.0;
+    const double rhob = bg[e * N1 + ii[2]];
+    q[idx] = -rhob * thp / (theta0 + thp);
+    for (int v = 1; v < 5; ++v) q[v * K * NP + idx] = 0.0;
+}
+
+__global__ void k_node_coords(int64_t K, int N1, const double* c1d, double* xyz) {
+    const int64_t NP = (int64_t)N1 * N1 * N1;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= K * NP) return;
+    const int64_t e = idx / NP;
+    const int n = (int)(idx % NP);
+    const int ii[3] = {n % N1, (n / N1) % N1, n / (N1 * N1)};
+    for (int d = 0; d < 3; ++d) xyz[d * K * NP + idx] = c1d[d * K * N1 + e * N1 + ii[d]];
+}
+
+// ---------------------------------------------------------------- transfer (section 3.3)
+
+// out[k][j][i] = sum C[k][k'] B[j][j'] A[i][i'] in[k'][j'][i'] for one variable; t < NP
+template <int N>
+__device__ __forceinline__ double apply3(const double* in, double* s1, double* s2, const double* Am, const double* Bm,
+                                         const double* Cm, int t) {
+    constexpr int N1 = N + 1, NP = N1 * N1 * N1;
+    const int i = t % N1, j = (t / N1) % N1, k = t / (N1 * N1);
+    if (t < NP) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) acc = fma(Am[i * N1 + m], in[m + N1 * (j + N1 * k)], acc);
+        s1[t] = acc;
+    }
+    __syncthreads();
+    if (t < NP) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) acc = fma(Bm[j * N1 + m], s1[i + N1 * (m + N1 * k)], acc);
+        s2[t] = acc;
+    }
+    __syncthreads();
+    double acc = 0.0;
+    if (t < NP) {
+#pragma unroll
+        for (int m = 0; m < N1; ++m) acc = fma(Cm[k * N1 + m], s2[i + N1 * (j + N1 * m)], acc);
+    }
+    __syncthreads();
+    return acc;
+}
+
+template <int N>
+__global__ void __launch_bounds__(Sz<N>::NT) k_refine(const XferArgs A) {
+    constexpr int NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
+    __shared__ double sIn[NP], s1[NP], s2[NP], sOps[Sz<N>::NOPS];
+    const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
+    const int t = threadIdx.x;
+    const int64_t src = A.src[e];
+    const int kind = A.kind[e];
+    for (int i = t; i < Sz<N>::NOPS; i += NT) sOps[i] = A.ops[i];
+    for (int v = 0; v < 5; ++v) {
+        const double* in = A.qin + (int64_t)v * A.Kin * NP + src * NP;
+        double* out = A.qout + (int64_t)v * A.Kout * NP + e * NP;
+        if (kind == DG_KIND_COPY) {
+            if (t < NP) out[t] = in[t];
+            continue;
+        }
+        __syncthreads();
+        if (t < NP) sIn[t] = in[t];
+        __syncthreads();
+        const double* I0 = sOps + NF;
+        const double* I1 = sOps + 2 * NF;
+        const double r = apply3<N>(sIn, s1, s2, (kind & 1) ? I1 : I0, (kind & 2) ? I1 : I0, (kind & 4) ? I1 : I0, t);
+        if (t < NP) out[t] = r;
+    }
+}
+
+template <int N>
+__global__ void __launch_bounds__(Sz<N>::NT) k_coarsen(const XferArgs A) {
+    constexpr int NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
+    __shared__ double sIn[NP], s1[NP], s2[NP], sOps[Sz<N>::NOPS];
+    const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
+    const int t = threadIdx.x;
+    const int64_t src = A.src[e];
+    const int kind = A.kind[e];
+    for (int i = t; i < Sz<N>::NOPS; i += NT) sOps[i] = A.ops[i];
+    for (int v = 0; v < 5; ++v) {
+        double* out = A.qout + (int64_t)v * A.Kout * NP + e * NP;
+        if (kind == DG_KIND_COPY) {
+            if (t < NP) out[t] = A.qin[(int64_t)v * A.Kin * NP + src * NP + t];
+            continue;
+        }
+        const double* R0 = sOps + 3 * NF;
+        const double* R1 = sOps + 4 * NF;
+        double acc = 0.0;
+        for (int c = 0; c < 8; ++c) {
+            __syncthreads();
+            if (t < NP) sIn[t] = A.qin[(int64_t)v * A.Kin * NP + (src + c) * NP + t];
+            __syncthreads();
+            acc += apply3<N>(sIn, s1, s2, (c & 1) ? R1 : R0, (c & 2) ? R1 : R0, (c & 4) ? R1 : R0, t);
+        }
+        if (t < NP) out[t] = acc;
+    }
+}
+
+// ---------------------------------------------------------------- budgets
+
+// compensated pair (s, c): value s + c
+struct Comp {
+    double s, c;
+};
+
+__device__ __forceinline__ Comp comp_add(Comp x, double y) {
+    const double s = x.s + y;
+    const double bp = s - x.s;
+    const double err = (x.s - (s - bp)) + (y - bp);
+    return Comp{s, x.c + err};
+}
+
+__device__ __forceinline__ Comp comp_merge(Comp x, Comp y) {
+    Comp r = comp_add(x, y.s);
+    r.c += y.c;
+    return r;
+}
+
+// deterministic block reduction of 4 compensated sums; result valid in thread 0
+template <int NT>
+__device__ void block_reduce4(Comp v[4], Comp* sh /* [4][NT] */) {
+    const int t = threadIdx.x;
+    for (int q = 0; q < 4; ++q) sh[q * NT + t] = v[q];
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (t < w)
+            for (int q = 0; q < 4; ++q) sh[q * NT + t] = comp_merge(sh[q * NT + t], sh[q * NT + t + w]);
+        __syncthreads();
+    }
+    for (int q = 0; q < 4; ++q) v[q] = sh[q * NT];
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) k_budgets(const BudgetArgs A) {
+    constexpr int N1 = N + 1, NP = N1 * N1 * N1;
+    constexpr int NT = 256;
+    __shared__ Comp sh[4 * NT];
+    const int t = threadIdx.x;
+    const int64_t K = A.K;
+    const double gamma = A.gamma;
+    Comp acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    // each block handles a contiguous range of leaves; thread t covers nodes t, t+NT, ...
+    const int64_t per = (K + gridDim.x - 1) / gridDim.x;
+    const int64_t e0 = blockIdx.x * per, e1 = (e0 + per < K) ? e0 + per : K;
+    for (int64_t e = e0; e < e1; ++e) {
+        const double J = A.geo[e * 4 + 3];
+        for (int n = t; n < NP; n += NT) {
+            const int i = n % N1, j = (n / N1) % N1, k = n / (N1 * N1);
+            const double W = J * A.w[i] * A.w[j] * A.w[k];
+            const double rp = A.q[e * NP + n];
+            const double U = A.q[K * NP + e * NP + n], V = A.q[2 * K * NP + e * NP + n],
+                         Wm = A.q[3 * K * NP + e * NP + n], Thp = A.q[4 * K * NP + e * NP + n];
+            const double rhob = A.bg[e * N1 + k], Thb = A.bg[K * N1 + e * N1 + k], Pb = A.bg[2 * K * N1 + e * N1 + k];
+            const double z = A.c1d[2 * K * N1 + e * N1 + k];
+            const double rho = rhob + rp;
+            const double P = Pb + pprime(Thp, Thb, Pb, gamma);
+            const double E = P / (gamma - 1.0) + (U * U + V * V + Wm * Wm) / (2.0 * rho) + rho * A.g * z;
+            acc[0] = comp_add(acc[0], W * rp);
+            acc[1] = comp_add(acc[1], W * rho);
+            acc[2] = comp_add(acc[2], W * Thp);
+            acc[3] = comp_add(acc[3], W * E);
+        }
+    }
+    block_reduce4<NT>(acc, sh);
+    if (t == 0)
+        for (int q = 0; q < 4; ++q) {
+            A.partial[(blockIdx.x * 4 + q) * 2 + 0] = acc[q].s;
+            A.partial[(blockIdx.x * 4 + q) * 2 + 1] = acc[q].c;
+        }
+}
+
+__global__ void __launch_bounds__(256) k_budgets_final(const double* partial, int nblk, double* out) {
+    constexpr int NT = 256;
+    __shared__ Comp sh[4 * NT];
+    const int t = threadIdx.x;
+    Comp acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    for (int b = t; b < nblk; b += NT)
+        for (int q = 0; q < 4; ++q)
+            acc[q] = comp_merge(acc[q], Comp{partial[(b * 4 + q) * 2], partial[(b * 4 + q) * 2 + 1]});
+    block_reduce4<NT>(acc, sh);
+    if (t == 0)
+        for (int q = 0; q < 4; ++q) out[q] = acc[q].s + acc[q].c;
+}
+
+// ---------------------------------------------------------------- indicator
+
+template <int N>
+__global__ void __launch_bounds__(Sz<N>::NT) k_indicator(const IndArgs A) {
+    constexpr int N1 = N + 1, NP = Sz<N>::NP, NT = Sz<N>::NT;
+    __shared__ double sTh[NP];
+    __shared__ double sD[N1 * N1];
+    constexpr int P2 = NT <= 64 ? 64 : NT <= 128 ? 128 : NT <= 256 ? 256 : NT <= 512 ? 512 : 1024;
+    __shared__ double sMax[P2];
+    const int64_t e = blockIdx.x;
+    const int64_t K = A.K;
+    const int t = threadIdx.x;
+    for (int i = t; i < N1 * N1; i += NT) sD[i] = A.ops[i];
+    const int i = t % N1, j = (t / N1) % N1, k = t / (N1 * N1);
+    double val = 0.0;
+    if (t < NP) {
+        const double rhob = A.bg[e * N1 + k], Thb = A.bg[K * N1 + e * N1 + k];
+        const double rp = A.q[e * NP + t], Thp = A.q[4 * K * NP + e * NP + t];
+        const double theta = (Thb + Thp) / (rhob + rp);
+        sTh[t] = theta;
+        val = fabs(theta - Thb / rhob);
+    }
+    __syncthreads();
+    if (A.kind == DG_IND_GRAD_THETA && t < NP) {
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        for (int m = 0; m < N1; ++m) {
+            ax = fma(sD[i * N1 + m], sTh[m + N1 * (j + N1 * k)], ax);
+            ay = fma(sD[j * N1 + m], sTh[i + N1 * (m + N1 * k)], ay);
+            az = fma(sD[k * N1 + m], sTh[i + N1 * (j + N1 * m)], az);
+        }
+        ax *= A.geo[e * 4 + 0];
+        ay *= A.geo[e * 4 + 1];
+        az *= A.geo[e * 4 + 2];
+        val = sqrt(ax * ax + ay * ay + az * az);
+    }
+    sMax[t] = (t < NP) ? val : 0.0;
+    if (t + NT < P2) sMax[t + NT] = 0.0;
+    __syncthreads();
+    for (int w = P2 / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            const double a = sMax[t], b = sMax[t + w];
+            sMax[t] = (a != a || b != b) ? NAN : fmax(a, b);  // a NaN anywhere survives
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double eta = sMax[0];
+        if (A.eta) A.eta[e] = eta;
+        const int lev = A.level[e];
+        int8_t fl = 0;
+        if (eta > A.thr && lev < A.max_level) fl = 1;
+        if (eta <= A.thr && lev > 0) fl = -1;
+        A.flags[e] = fl;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+#define DG_DISPATCH_N(N_, CALL)                                     \
+    switch (N_) {                                                   \
+        case 2: { constexpr int NN = 2; CALL; } break;              \
+        case 3: { constexpr int NN = 3; CALL; } break;              \
+        case 4: { constexpr int NN = 4; CALL; } break;              \
+        case 5: { constexpr int NN = 5; CALL; } break;              \
+        case 6: { constexpr int NN = 6; CALL; } break;              \
+        case 7: { constexpr int NN = 7; CALL; } break;              \
+        default: return hipErrorInvalidValue;                        \
+    }
+
+hipError_t launch_stage(int N, int mode, const StageArgs& a, hipStream_t s) {
+    if (a.K <= 0) return hipSuccess;
+    if (mode == MODE_RHS) {
+        DG_DISPATCH_N(N, (k_stage<NN, MODE_RHS><<<dim3((unsigned)a.K), dim3(Sz<NN>::NT), 0, s>>>(a)));
+    } else {
+        DG_DISPATCH_N(N, (k_stage<NN, MODE_RK><<<dim3((unsigned)a.K), dim3(Sz<NN>::NT), 0, s>>>(a)));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_background(int64_t K, int N, const double* c1d, double* bg, const BgParams& p, hipStream_t s) {
+    const int64_t n = K * (N + 1);
+    if (n <= 0) return hipSuccess;
+    k_background<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(K, N + 1, c1d, bg, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_bell(int64_t K, int N, const double* c1d, const double* bg, double theta0, const dg_bell& b,
+                            double* q, hipStream_t s) {
+    const int64_t n = K * (N + 1) * (N + 1) * (N + 1);
+    if (n <= 0) return hipSuccess;
+    k_init_bell<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(K, N + 1, c1d, bg, theta0, b, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_coords(int64_t K, int N, const double* c1d, double* xyz, hipStream_t s) {
+    const int64_t n = K * (N + 1) * (N + 1) * (N + 1);
+    if (n <= 0) return hipSuccess;
+    k_node_coords<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(K, N + 1, c1d, xyz);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine(int N, const XferArgs& a, hipStream_t s) {
+    if (a.Kout <= 0) return hipSuccess;
+    DG_DISPATCH_N(N, (k_refine<NN><<<dim3((unsigned)a.Kout), dim3(Sz<NN>::NT), 0, s>>>(a)));
+    return hipGetLastError();
+}
+
+hipError_t launch_coarsen(int N, const XferArgs& a, hipStream_t s) {
+    if (a.Kout <= 0) return hipSuccess;
+    DG_DISPATCH_N(N, (k_coarsen<NN><<<dim3((unsigned)a.Kout), dim3(Sz<NN>::NT), 0, s>>>(a)));
+    return hipGetLastError();
+}
+
+int budget_blocks(int64_t K) {
+    int64_t b = K < 1024 ? K : 1024;
+    return (int)(b < 1 ? 1 : b);
+}
+
+hipError_t launch_budgets(int N, const BudgetArgs& a, int nblk, double* out_dev, hipStream_t s) {
+    DG_DISPATCH_N(N, (k_budgets<NN><<<dim3((unsigned)nblk), dim3(256), 0, s>>>(a)));
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    k_budgets_final<<<dim3(1), dim3(256), 0, s>>>(a.partial, nblk, out_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_indicator(int N, const IndArgs& a, hipStream_t s) {
+    if (a.K <= 0) return hipSuccess;
+    DG_DISPATCH_N(N, (k_indicator<NN><<<dim3((unsigned)a.K), dim3(Sz<NN>::NT), 0, s>>>(a)));
+    return hipGetLastError();
+}
+
+}  // namespace dgamr

@@ -1,0 +1,79 @@
+// Kernel argument blocks and launchers (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dg.h"
+#include "facetypes.hpp"
+
+namespace dgamr {
+
+constexpr int MODE_RHS = 0;
+constexpr int MODE_RK = 1;
+
+struct StageArgs {
+    const double* q0;      // [5][K][Np] (read only when a != 0)
+    const double* qs;      // [5][K][Np]
+    double* out;           // [5][K][Np]
+    const double* ops;     // D, I0, I1, R0, R1, w
+    const double* geo;     // [K][4]
+    const double* bg;      // [3][K][N1]
+    const int32_t* ftype;  // [K][6]
+    const int32_t* fnb;    // [K][6][4]
+    int64_t K;
+    double a, b, dt;
+    double gamma, g;
+};
+
+struct BgParams {
+    int32_t kind;
+    double cp, cv, P0, g, theta0, rho0, Theta0;
+};
+
+struct XferArgs {
+    const double* qin;
+    double* qout;
+    const double* ops;
+    const int32_t* src;
+    const int32_t* kind;
+    int64_t Kin, Kout;
+};
+
+struct BudgetArgs {
+    const double* q;
+    const double* bg;
+    const double* geo;
+    const double* c1d;
+    const double* w;
+    double* partial;
+    int64_t K;
+    double gamma, g;
+};
+
+struct IndArgs {
+    const double* q;
+    const double* bg;
+    const double* geo;
+    const double* ops;
+    const int32_t* level;
+    double* eta;
+    int8_t* flags;
+    int64_t K;
+    int32_t kind, max_level;
+    double thr;
+};
+
+hipError_t launch_stage(int N, int mode, const StageArgs& a, hipStream_t s);
+hipError_t launch_background(int64_t K, int N, const double* c1d, double* bg, const BgParams& p, hipStream_t s);
+hipError_t launch_init_bell(int64_t K, int N, const double* c1d, const double* bg, double theta0, const dg_bell& b,
+                            double* q, hipStream_t s);
+hipError_t launch_node_coords(int64_t K, int N, const double* c1d, double* xyz, hipStream_t s);
+hipError_t launch_refine(int N, const XferArgs& a, hipStream_t s);
+hipError_t launch_coarsen(int N, const XferArgs& a, hipStream_t s);
+int budget_blocks(int64_t K);
+hipError_t launch_budgets(int N, const BudgetArgs& a, int nblk, double* out_dev, hipStream_t s);
+hipError_t launch_indicator(int N, const IndArgs& a, hipStream_t s);
+
+}  // namespace dgamr

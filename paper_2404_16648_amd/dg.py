@@ -1,0 +1,341 @@
+"""Thin ctypes binding of the C ABI in include/dg.h (argument marshalling only).
+
+Every numerical step runs in the HIP library ``libdgamr.so``; this module only
+converts torch tensors to device pointers and streams, checks shapes and turns
+status codes into exceptions.  It raises if the library is missing: there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libdgamr.so")
+
+DG_OK = 0
+DG_EINVAL = -1
+DG_ENOMEM = -2
+DG_EHIP = -3
+DG_EUNSUPPORTED = -4
+DG_ENONFINITE = -5
+
+DG_PASS_COARSEN = 0
+DG_PASS_REFINE = 1
+DG_BG_NEUTRAL = 0
+DG_BG_CONSTANT = 1
+DG_FP64 = 0
+DG_MIXED = 1
+DG_IND_THETA = 0
+DG_IND_GRAD_THETA = 1
+DG_KIND_COPY = -1
+DG_KIND_FAMILY = 8
+
+EXPORTED = [
+    "dg_mesh_build", "dg_mesh_free", "dg_mesh_info_get", "dg_mesh_export", "dg_node_coords",
+    "dg_init_bell", "dg_rhs", "dg_rk_stage", "dg_refine_project", "dg_coarsen_project",
+    "dg_rhs_adjoint", "dg_budgets", "dg_indicator", "dg_last_error",
+]
+
+
+class DGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dg status {code}: {msg}")
+        self.code = code
+
+
+class ForestDesc(C.Structure):
+    _fields_ = [("N", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("max_level", C.c_int32), ("periodic", C.c_int32 * 3),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("host_only", C.c_int32)]
+
+
+class Phys(C.Structure):
+    _fields_ = [("cp", C.c_double), ("cv", C.c_double), ("P0", C.c_double), ("g", C.c_double),
+                ("background", C.c_int32), ("precision", C.c_int32),
+                ("theta0", C.c_double), ("rho0", C.c_double), ("Theta0", C.c_double)]
+
+
+class MeshInfo(C.Structure):
+    _fields_ = [("K", C.c_int64), ("Np", C.c_int64), ("n_conf", C.c_int64), ("n_bnd", C.c_int64),
+                ("n_hang", C.c_int64), ("n_refined", C.c_int64), ("n_coarsened", C.c_int64),
+                ("N", C.c_int32), ("max_level_present", C.c_int32)]
+
+
+class MeshTables(C.Structure):
+    _fields_ = [("leaf", C.c_void_p), ("conf", C.c_void_p), ("bnd", C.c_void_p), ("hang", C.c_void_p),
+                ("xfer_src", C.c_void_p), ("xfer_kind", C.c_void_p)]
+
+
+class Bell(C.Structure):
+    _fields_ = [("dtheta", C.c_double), ("centre", C.c_double * 3), ("radius", C.c_double * 3)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdgamr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2404_16648_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.dg_mesh_build.argtypes = [C.POINTER(ForestDesc), P, P, C.c_int32, C.POINTER(P)]
+        L.dg_mesh_free.argtypes = [P]
+        L.dg_mesh_info_get.argtypes = [P, C.POINTER(MeshInfo)]
+        L.dg_mesh_export.argtypes = [P, C.POINTER(MeshTables)]
+        L.dg_node_coords.argtypes = [P, P, P]
+        L.dg_init_bell.argtypes = [P, C.POINTER(Phys), C.POINTER(Bell), P, P]
+        L.dg_rhs.argtypes = [P, C.POINTER(Phys), P, P, P]
+        L.dg_rk_stage.argtypes = [P, C.POINTER(Phys), C.c_double, C.c_double, C.c_double, P, P, P, P]
+        L.dg_refine_project.argtypes = [P, P, P, P, P]
+        L.dg_coarsen_project.argtypes = [P, P, P, P, P]
+        L.dg_rhs_adjoint.argtypes = [P, C.POINTER(Phys), P, P, P, P]
+        L.dg_budgets.argtypes = [P, C.POINTER(Phys), P, P, P]
+        L.dg_indicator.argtypes = [P, C.POINTER(Phys), P, C.c_int32, C.c_double, P, P, P]
+        L.dg_last_error.restype = C.c_char_p
+        for name in EXPORTED:
+            if name != "dg_last_error":
+                getattr(L, name).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != DG_OK:
+        raise DGError(code, lib().dg_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("field tensors must live on the GPU")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("field tensors must be contiguous float64")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass(frozen=True)
+class PhysParams:
+    """Gas constants, gravity, background and precision (dg_phys)."""
+    cp: float = 1004.67
+    cv: float = 717.5
+    P0: float = 1.0e5
+    g: float = 9.80616
+    background: int = DG_BG_NEUTRAL
+    precision: int = DG_FP64
+    theta0: float = 300.0
+    rho0: float = 1.0
+    Theta0: float = 300.0
+
+    def c(self):
+        return Phys(self.cp, self.cv, self.P0, self.g, self.background, self.precision,
+                    self.theta0, self.rho0, self.Theta0)
+
+
+class Mesh:
+    """Owning handle of a dg_mesh."""
+
+    def __init__(self, handle, prev=None):
+        self._h = C.c_void_p(handle)
+        self.prev = prev          # keeps the source mesh alive for the projections
+        info = MeshInfo()
+        _check(lib().dg_mesh_info_get(self._h, C.byref(info)))
+        self.info = info
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def K(self):
+        return int(self.info.K)
+
+    @property
+    def N(self):
+        return int(self.info.N)
+
+    @property
+    def Np(self):
+        return int(self.info.Np)
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            lib().dg_mesh_free(self._h)
+            self._h = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def tables(self):
+        """Host copies of the integer tables (numpy int32)."""
+        i = self.info
+        out = {
+            "leaf": np.zeros((i.K, 5), np.int32), "conf": np.zeros((i.n_conf, 3), np.int32),
+            "bnd": np.zeros((i.n_bnd, 2), np.int32), "hang": np.zeros((i.n_hang, 6), np.int32),
+            "xfer_src": np.zeros(i.K, np.int32), "xfer_kind": np.zeros(i.K, np.int32),
+        }
+        t = MeshTables(*[C.c_void_p(out[k].ctypes.data) if out[k].size else None
+                         for k in ("leaf", "conf", "bnd", "hang", "xfer_src", "xfer_kind")])
+        _check(lib().dg_mesh_export(self._h, C.byref(t)))
+        return out
+
+    def field(self, device="cuda"):
+        import torch
+        return torch.zeros(5, self.K, self.Np, dtype=torch.float64, device=device)
+
+
+def dg_mesh_build(N=None, nroot=None, max_level=0, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+                  periodic=(0, 0, 0), prev: Mesh | None = None, flags=None, pass_=DG_PASS_REFINE,
+                  host_only=False) -> Mesh:
+    out = C.c_void_p()
+    if prev is None:
+        d = ForestDesc(N, nroot[0], nroot[1], nroot[2], max_level, (C.c_int32 * 3)(*periodic),
+                       (C.c_double * 3)(*lo), (C.c_double * 3)(*hi), 1 if host_only else 0)
+        _check(lib().dg_mesh_build(C.byref(d), None, None, 0, C.byref(out)))
+    else:
+        fl = np.ascontiguousarray(np.asarray(flags, dtype=np.int8))
+        if fl.shape != (prev.K,):
+            raise ValueError("flags must have one entry per leaf of prev")
+        _check(lib().dg_mesh_build(None, prev.handle, C.c_void_p(fl.ctypes.data), pass_, C.byref(out)))
+    return Mesh(out.value, prev)
+
+
+def _shape_check(mesh, *ts):
+    for t in ts:
+        if t is not None and tuple(t.shape) != (5, mesh.K, mesh.Np):
+            raise ValueError(f"field shape {tuple(t.shape)} != (5, {mesh.K}, {mesh.Np})")
+
+
+def dg_node_coords(mesh: Mesh, xyz, stream=None):
+    if tuple(xyz.shape) != (3, mesh.K, mesh.Np):
+        raise ValueError("xyz must be [3, K, Np]")
+    _check(lib().dg_node_coords(mesh.handle, _ptr(xyz), _stream(stream)))
+
+
+def dg_init_bell(mesh: Mesh, phys: PhysParams, q, dtheta, centre, radius, stream=None):
+    _shape_check(mesh, q)
+    b = Bell(dtheta, (C.c_double * 3)(*centre), (C.c_double * 3)(*radius))
+    p = phys.c()
+    _check(lib().dg_init_bell(mesh.handle, C.byref(p), C.byref(b), _ptr(q), _stream(stream)))
+
+
+def dg_rhs(mesh: Mesh, phys: PhysParams, q, rhs, stream=None):
+    _shape_check(mesh, q, rhs)
+    p = phys.c()
+    _check(lib().dg_rhs(mesh.handle, C.byref(p), _ptr(q), _ptr(rhs), _stream(stream)))
+
+
+def dg_rk_stage(mesh: Mesh, phys: PhysParams, a, b, dt, q0, qs, qout, stream=None):
+    _shape_check(mesh, q0, qs, qout)
+    p = phys.c()
+    _check(lib().dg_rk_stage(mesh.handle, C.byref(p), a, b, dt, _ptr(q0), _ptr(qs), _ptr(qout),
+                             _stream(stream)))
+
+
+def dg_refine_project(src: Mesh, dst: Mesh, q_from, q_to, stream=None):
+    _shape_check(src, q_from)
+    _shape_check(dst, q_to)
+    _check(lib().dg_refine_project(src.handle, dst.handle, _ptr(q_from), _ptr(q_to), _stream(stream)))
+
+
+def dg_coarsen_project(src: Mesh, dst: Mesh, q_from, q_to, stream=None):
+    _shape_check(src, q_from)
+    _shape_check(dst, q_to)
+    _check(lib().dg_coarsen_project(src.handle, dst.handle, _ptr(q_from), _ptr(q_to), _stream(stream)))
+
+
+def dg_rhs_adjoint(mesh: Mesh, phys: PhysParams, q, lam, qbar, stream=None):
+    _shape_check(mesh, q, lam, qbar)
+    p = phys.c()
+    _check(lib().dg_rhs_adjoint(mesh.handle, C.byref(p), _ptr(q), _ptr(lam), _ptr(qbar), _stream(stream)))
+
+
+def dg_budgets(mesh: Mesh, phys: PhysParams, q, stream=None):
+    _shape_check(mesh, q)
+    out = (C.c_double * 4)()
+    p = phys.c()
+    _check(lib().dg_budgets(mesh.handle, C.byref(p), _ptr(q), out, _stream(stream)))
+    return tuple(out)
+
+
+def dg_indicator(mesh: Mesh, phys: PhysParams, q, kind, thr, eta=None, stream=None):
+    _shape_check(mesh, q)
+    fl = np.zeros(mesh.K, dtype=np.int8)
+    p = phys.c()
+    _check(lib().dg_indicator(mesh.handle, C.byref(p), _ptr(q), kind, thr, _ptr(eta),
+                              C.c_void_p(fl.ctypes.data) if mesh.K else None, _stream(stream)))
+    return fl
+
+
+SSP_RK3 = ((0.0, 1.0), (0.75, 0.25), (1.0 / 3.0, 2.0 / 3.0))
+
+
+def ssp_rk3_step(mesh: Mesh, phys: PhysParams, dt, q, q1, q2, stream=None):
+    """One SSP-RK3 step in place on q, using q1, q2 as stage buffers (3 dg_rk_stage calls)."""
+    dg_rk_stage(mesh, phys, *SSP_RK3[0], dt, q, q, q1, stream)
+    dg_rk_stage(mesh, phys, *SSP_RK3[1], dt, q, q1, q2, stream)
+    dg_rk_stage(mesh, phys, *SSP_RK3[2], dt, q, q2, q, stream)
+
+
+def adapt_cycle(mesh: Mesh, phys: PhysParams, q, kind, thr, stream=None):
+    """One adaptation cycle: indicator -> coarsen pass + projection -> refine
+    pass + projection (host control flow; every arithmetic step runs in the
+    library).  Parents made by the coarsen pass are not refined in the same
+    cycle.  Returns (new_mesh, new_q)."""
+    import torch
+    flags = dg_indicator(mesh, phys, q, kind, thr, stream=stream)
+    mc = dg_mesh_build(prev=mesh, flags=flags, pass_=DG_PASS_COARSEN)
+    if mc.info.n_coarsened:
+        qc = torch.empty(5, mc.K, mc.Np, dtype=torch.float64, device=q.device)
+        dg_coarsen_project(mesh, mc, q, qc, stream)
+    else:
+        qc = q
+    t = mc.tables()
+    fl2 = np.where(t["xfer_kind"] == DG_KIND_COPY, flags[t["xfer_src"]], 0).astype(np.int8)
+    fl2[fl2 < 0] = 0
+    mr = dg_mesh_build(prev=mc, flags=fl2, pass_=DG_PASS_REFINE)
+    if mr.info.n_refined:
+        qr = torch.empty(5, mr.K, mr.Np, dtype=torch.float64, device=q.device)
+        dg_refine_project(mc, mr, qc, qr, stream)
+    else:
+        qr = qc
+    return mr, qr
+
+
+def initial_mesh(N, nroot, max_level, lo, hi, periodic, phys: PhysParams, bell, kind, thr):
+    """Uniform level-0 forest, then repeat (cosine-bell IC on the nodes ->
+    indicator -> refine pass) until no leaf is flagged (at most max_level
+    passes).  Returns (mesh, q) with q the IC on the final mesh."""
+    import torch
+    m = dg_mesh_build(N, nroot, max_level, lo, hi, periodic)
+    for _ in range(max_level + 1):
+        q = torch.empty(5, m.K, m.Np, dtype=torch.float64, device="cuda")
+        dg_init_bell(m, phys, q, *bell)
+        fl = dg_indicator(m, phys, q, kind, thr)
+        fl[fl < 0] = 0
+        if not (fl > 0).any():
+            return m, q
+        m = dg_mesh_build(prev=m, flags=fl, pass_=DG_PASS_REFINE)
+        m.prev = None
+    q = torch.empty(5, m.K, m.Np, dtype=torch.float64, device="cuda")
+    dg_init_bell(m, phys, q, *bell)
+    return m, q

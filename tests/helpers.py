@@ -1,0 +1,70 @@
+"""Shared helpers of the library-vs-oracle tests (no arithmetic of the method)."""
+import numpy as np
+import torch
+
+from oracle import euler as eu
+from oracle import forest as fo
+
+F64 = torch.float64
+
+# per-variable relative L2 bound for float64 results (a few hundred ulps of
+# reassociation on sums of O(N) terms per node, far below any modelling error)
+TOL_FP64 = 1e-12
+
+
+def to_nodes(q):
+    """oracle layout [5, K, N+1, N+1, N+1] -> library layout [5, K, Np] (same order)."""
+    return q.reshape(q.shape[0], q.shape[1], -1).contiguous()
+
+
+def to_elem(q, N):
+    n1 = N + 1
+    return q.reshape(q.shape[0], q.shape[1], n1, n1, n1)
+
+
+def rel_l2(a, b):
+    """Per-variable ||a - b|| / ||b||; where ||b|| = 0, inf unless a is exactly 0 too."""
+    a = a.detach().double().cpu().reshape(a.shape[0], -1)
+    b = b.detach().double().cpu().reshape(b.shape[0], -1)
+    out = []
+    for v in range(a.shape[0]):
+        nb = float(torch.linalg.vector_norm(b[v]))
+        nd = float(torch.linalg.vector_norm(a[v] - b[v]))
+        if nb == 0.0:
+            out.append(0.0 if nd == 0.0 else float("inf"))
+        else:
+            out.append(nd / nb)
+    return out
+
+
+def oracle_phys(p):
+    """oracle Phys with the same constants as a binding PhysParams."""
+    return eu.Phys(cp=p.cp, cv=p.cv, P0=p.P0, g=p.g, background=p.background,
+                   theta0=p.theta0, rho0=p.rho0, Theta0=p.Theta0)
+
+
+def oracle_desc(N, nroot, max_level, lo, hi, periodic):
+    return fo.ForestDesc(N, nroot[0], nroot[1], nroot[2], max_level, tuple(lo), tuple(hi), tuple(periodic))
+
+
+def tables_equal(lib_tables, om):
+    """Bit-exact comparison of the library's exported tables with the oracle mesh."""
+    ok = (np.array_equal(lib_tables["leaf"], np.array(om.leaves, dtype=np.int32).reshape(-1, 5))
+          and np.array_equal(lib_tables["conf"], om.conf)
+          and np.array_equal(lib_tables["bnd"], om.bnd)
+          and np.array_equal(lib_tables["hang"], om.hang)
+          and np.array_equal(lib_tables["xfer_src"], om.xfer_src)
+          and np.array_equal(lib_tables["xfer_kind"], om.xfer_kind))
+    return ok
+
+
+def random_refinements(desc, rounds, seed, p=0.35):
+    """Flag sequences for `rounds` refine passes from the uniform mesh (oracle side)."""
+    m = fo.build(desc, None)
+    rng = np.random.default_rng(seed)
+    seq = []
+    for _ in range(rounds):
+        fl = (rng.random(m.K) < p).astype(np.int8)
+        seq.append(fl)
+        m = fo.build(desc, m, fl, fo.PASS_REFINE)
+    return seq
