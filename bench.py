@@ -3,7 +3,7 @@
 Workload (default): the AMR warm-bubble case -- box 1000 m cubed, 8x8x8 base
 hexes, N = 7, refined two levels where |theta'| > 0.1 K with 2:1 balance,
 cosine-bell bubble +2 K radius 250 m at (500, 500, 350) m, no-flux walls,
-SSP-RK3 with dt = 0.002 s and re-adaptation every 10 steps by conservative
+SSP-RK3 with dt = 0.001 s and re-adaptation every 10 steps by conservative
 projection.  One benchmark step = one SSP-RK3 step (3 fused stage launches);
 every 10th step also runs an adaptation cycle (indicator, coarsen pass and
 projection, refine pass and projection), inside the timed region.
@@ -53,7 +53,7 @@ def main():
     N, nroot, L = 7, (8, 8, 8), 2
     lo, hi = (0.0, 0.0, 0.0), (1000.0, 1000.0, 1000.0)
     bell = (2.0, (500.0, 500.0, 350.0), (250.0, 250.0, 250.0))
-    thr, dt = 0.1, 0.002
+    thr, dt = 0.1, 0.001
     mesh, q = dg.initial_mesh(N, nroot, L, lo, hi, (0, 0, 0), ph, bell, dg.DG_IND_THETA, thr)
     stream = torch.cuda.current_stream()
 
@@ -72,12 +72,12 @@ def main():
         nodes = m.K * m.Np
         stages = ((0.0, 1.0, qq, q1), (0.75, 0.25, q1, q2_), (1.0 / 3.0, 2.0 / 3.0, q2_, qq))
         for a, b, qs, out in stages:
-            if record:
+            if record is not None:
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
             dg.dg_rk_stage(m, ph, a, b, dt, qq, qs, out)
-            if record:
+            if record is not None:
                 e1.record(stream)
                 record.append((e0, e1, nodes * (BYTES_STAGE_FIRST if a == 0.0 else BYTES_STAGE)))
         state["step"] += 1
@@ -120,7 +120,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic (analytic warm-bubble initial state)",
         "config": {"workload": "AMR warm bubble: 1000 m box, 8x8x8 base, N=7, 2 levels where |theta'|>0.1 K, "
-                               "SSP-RK3 dt=0.002 s, adapt every 10 steps",
+                               "SSP-RK3 dt=0.001 s, adapt every 10 steps",
                    "leaves": m.K, "nodes": m.K * m.Np, "hanging_faces": int(m.info.n_hang),
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -159,7 +159,7 @@ def cpu_baseline():
     t = time.perf_counter()
     steps = 0
     while True:
-        q = eu.ssp_rk3_step(op, 0.002, q)
+        q = eu.ssp_rk3_step(op, 0.001, q)
         steps += 1
         if time.perf_counter() - t > 10.0:
             break

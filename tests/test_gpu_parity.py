@@ -232,7 +232,7 @@ def _adapt_initial_mesh(N, nroot, L, lo, hi, thr, bell):
 
 def test_config2_full_size_rhs_and_step():
     """Config 2 mesh (8^3 base, N = 7, 2 levels where |theta'| > 0.1 K): full-size
-    RHS and one SSP-RK3 step (dt = 0.002 s) against the oracle."""
+    RHS and one SSP-RK3 step (dt = 0.001 s) against the oracle."""
     lm, om = _adapt_initial_mesh(7, (8, 8, 8), 2, *BOX, 0.1, eu.bubble_state)
     print("C2 leaves", om.K, "hanging faces", len(om.hang), flush=True)
     assert len(om.hang) > 0
@@ -244,5 +244,5 @@ def test_config2_full_size_rhs_and_step():
     dg.dg_rhs(lm, ph, q, R)
     check(R, op.rhs(qo), what="C2 rhs")
     q1, q2 = lm.field(), lm.field()
-    dg.ssp_rk3_step(lm, ph, 0.002, q, q1, q2)
-    check(q, eu.ssp_rk3_step(op, 0.002, qo), what="C2 step")
+    dg.ssp_rk3_step(lm, ph, 0.001, q, q1, q2)
+    check(q, eu.ssp_rk3_step(op, 0.001, qo), what="C2 step")
