@@ -77,21 +77,24 @@ struct Bg {
 __device__ __forceinline__ void flux_n(const double q[5], const Bg& bg, double Pp, int d, double sgn, double gamma,
                                        double F[5], double& lam) {
     const double rho = bg.rho + q[0];
-    const double ud = q[1 + d] / rho;
+    const double rinv = 1.0 / rho;
+    const double Ud = d == 0 ? q[1] : d == 1 ? q[2] : q[3];  // selects, not a dynamic index
+    const double ud = Ud * rinv;
     const double Th = bg.Th + q[4];
-    F[0] = sgn * q[1 + d];
+    F[0] = sgn * Ud;
     F[1] = sgn * (d == 0 ? q[1] * ud + Pp : q[1] * ud);
     F[2] = sgn * (d == 1 ? q[2] * ud + Pp : q[2] * ud);
     F[3] = sgn * (d == 2 ? q[3] * ud + Pp : q[3] * ud);
     F[4] = sgn * (Th * ud);
-    lam = fabs(ud) + sqrt(gamma * (bg.P + Pp) / rho);
+    lam = fabs(ud) + sqrt(gamma * (bg.P + Pp) * rinv);
 }
 
-// Rusanov flux F*.n, n = sgn e_d:  {F.n} + 1/2 max(|u.n| + c) (q'- - q'+)  (section 2.2)
+// Rusanov flux F*.n, n = sgn e_d:  {F.n} + 1/2 max(|u.n| + c) (q'- - q'+)  (section 2.2);
+// also returns FL = F(qL).n
 __device__ __forceinline__ void rusanov(const double qL[5], const Bg& bL, double PpL, const double qR[5],
                                         const Bg& bR, double PpR, int d, double sgn, double gamma,
-                                        double Fs[5]) {
-    double FL[5], FR[5], lL, lR;
+                                        double Fs[5], double FL[5]) {
+    double FR[5], lL, lR;
     flux_n(qL, bL, PpL, d, sgn, gamma, FL, lL);
     flux_n(qR, bR, PpR, d, sgn, gamma, FR, lR);
     const double hl = 0.5 * fmax(lL, lR);
@@ -99,13 +102,14 @@ __device__ __forceinline__ void rusanov(const double qL[5], const Bg& bL, double
     for (int v = 0; v < 5; ++v) Fs[v] = 0.5 * (FL[v] + FR[v]) + hl * (qL[v] - qR[v]);
 }
 
-// (I_a x I_b) applied to a face trace T[(N+1)^2] at face node m
+// (A x B) applied to a face trace T[(N+1)^2] at face node m (A along the first
+// tangential axis, B along the second)
 template <int N>
 __device__ __forceinline__ double tensor2(const double* T, const double* A, const double* B, int m) {
     constexpr int N1 = N + 1;
     const int m1 = m % N1, m2 = m / N1;
     double acc = 0.0;
-#pragma unroll
+#pragma unroll 1
     for (int j2 = 0; j2 < N1; ++j2) {
         double row = 0.0;
 #pragma unroll
@@ -115,12 +119,19 @@ __device__ __forceinline__ double tensor2(const double* T, const double* A, cons
     return acc;
 }
 
+// waves per SIMD the stage kernel is compiled for (bounds the VGPR budget)
+template <int N>
+struct StageOcc {
+    static constexpr int W = N >= 6 ? 4 : 5;
+};
+
 template <int N, int MODE>
-__global__ void __launch_bounds__(Sz<N>::NT) k_stage(const StageArgs A) {
+__global__ void __launch_bounds__(Sz<N>::NT) __attribute__((amdgpu_waves_per_eu(StageOcc<N>::W)))
+k_stage(const StageArgs A) {
     constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
-    __shared__ double sQ[5 * NP];
+    constexpr int NFL = 5 * NP > 20 * NF ? 5 * NP : 20 * NF;
+    __shared__ double sF[NFL];              // one direction of fluxes; then mortar scratch [4][5][NF]
     __shared__ double sPp[NP];
-    __shared__ double sF[15 * NP];          // fluxes; reused as mortar scratch (20 NF <= 15 NP)
     __shared__ double sS[6 * 5 * NF];       // lifted (F* - F).n per face
     __shared__ double sT[5 * NF];           // a face trace for mortar interpolation
     __shared__ double sOps[Sz<N>::NOPS];
@@ -134,6 +145,8 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_stage(const StageArgs A) {
     const double gamma = A.gamma;
     const double* D = sOps;
     // I_a at sOps + (1 + a) NF, R_a at sOps + (3 + a) NF
+    const double* qs = A.qs;
+    const int64_t KNP = K * NP;
 
     for (int i = t; i < Sz<N>::NOPS; i += NT) sOps[i] = A.ops[i];
     if (t < 3 * N1) sBg[t] = A.bg[(int64_t)(t / N1) * K * N1 + e * N1 + (t % N1)];
@@ -143,66 +156,58 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_stage(const StageArgs A) {
     double q[5] = {0, 0, 0, 0, 0};
     if (t < NP) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            q[v] = A.qs[(int64_t)v * K * NP + e * NP + t];
-            sQ[v * NP + t] = q[v];
-        }
+        for (int v = 0; v < 5; ++v) q[v] = qs[v * KNP + e * NP + t];
     }
     __syncthreads();
 
     const int i = t % N1, j = (t / N1) % N1, k = t / NF;
     double R[5] = {0, 0, 0, 0, 0};
+    double vel[3] = {0, 0, 0}, Pp = 0.0, Th = 0.0;
     if (t < NP) {
         const double rhob = sBg[k], Thb = sBg[N1 + k], Pb = sBg[2 * N1 + k];
-        const double rho = rhob + q[0];
-        const double u = q[1] / rho, v = q[2] / rho, w = q[3] / rho;
-        const double Pp = pprime(q[4], Thb, Pb, gamma);
-        const double Th = Thb + q[4];
+        const double rinv = 1.0 / (rhob + q[0]);
+        vel[0] = q[1] * rinv;
+        vel[1] = q[2] * rinv;
+        vel[2] = q[3] * rinv;
+        Pp = pprime(q[4], Thb, Pb, gamma);
+        Th = Thb + q[4];
         sPp[t] = Pp;
-        double* Fx = sF;
-        double* Fy = sF + 5 * NP;
-        double* Fz = sF + 10 * NP;
-        Fx[0 * NP + t] = q[1];
-        Fx[1 * NP + t] = q[1] * u + Pp;
-        Fx[2 * NP + t] = q[2] * u;
-        Fx[3 * NP + t] = q[3] * u;
-        Fx[4 * NP + t] = Th * u;
-        Fy[0 * NP + t] = q[2];
-        Fy[1 * NP + t] = q[1] * v;
-        Fy[2 * NP + t] = q[2] * v + Pp;
-        Fy[3 * NP + t] = q[3] * v;
-        Fy[4 * NP + t] = Th * v;
-        Fz[0 * NP + t] = q[3];
-        Fz[1 * NP + t] = q[1] * w;
-        Fz[2 * NP + t] = q[2] * w;
-        Fz[3 * NP + t] = q[3] * w + Pp;
-        Fz[4 * NP + t] = Th * w;
         R[3] = -q[0] * A.g;  // buoyancy on rho*w
     }
-    __syncthreads();
 
-    const double g2x = A.geo[e * 4 + 0], g2y = A.geo[e * 4 + 1], g2z = A.geo[e * 4 + 2];
-    if (t < NP) {
+    // volume term, one direction at a time: R -= (2/h_d) D_d F^d
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            const double* Fx = sF + v * NP;
-            const double* Fy = sF + (5 + v) * NP;
-            const double* Fz = sF + (10 + v) * NP;
-            double ax = 0.0, ay = 0.0, az = 0.0;
-#pragma unroll
-            for (int m = 0; m < N1; ++m) {
-                ax = fma(D[i * N1 + m], Fx[m + N1 * (j + N1 * k)], ax);
-                ay = fma(D[j * N1 + m], Fy[i + N1 * (m + N1 * k)], ay);
-                az = fma(D[k * N1 + m], Fz[i + N1 * (j + N1 * m)], az);
-            }
-            R[v] -= fma(g2x, ax, fma(g2y, ay, g2z * az));
+    for (int d = 0; d < 3; ++d) {
+        if (t < NP) {
+            const double ud = vel[d];
+            sF[0 * NP + t] = q[1 + d];
+            sF[1 * NP + t] = d == 0 ? q[1] * ud + Pp : q[1] * ud;
+            sF[2 * NP + t] = d == 1 ? q[2] * ud + Pp : q[2] * ud;
+            sF[3 * NP + t] = d == 2 ? q[3] * ud + Pp : q[3] * ud;
+            sF[4 * NP + t] = Th * ud;
         }
+        __syncthreads();
+        if (t < NP) {
+            const int id = d == 0 ? i : d == 1 ? j : k;
+            const int stride = d == 0 ? 1 : d == 1 ? N1 : NF;
+            const int base = t - id * stride;
+            const double g2 = A.geo[e * 4 + d];
+            const double* Drow = D + id * N1;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const double* F = sF + v * NP + base;
+                double acc = 0.0;
+#pragma unroll
+                for (int m = 0; m < N1; ++m) acc = fma(Drow[m], F[m * stride], acc);
+                R[v] = fma(-g2, acc, R[v]);
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();  // sF is free from here on
 
     // ---- faces: conforming neighbours and walls, every (face, node) item
     const double liftc = 0.5 * N * (N + 1);  // 1/w_N
-    const double* qs = A.qs;
+#pragma unroll 1
     for (int it = t; it < 6 * NF; it += NT) {
         const int f = it / NF, m = it % NF;
         const int type = sType[f] & 0xff;
@@ -212,47 +217,50 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_stage(const StageArgs A) {
         const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
         double qL[5], qR[5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qL[v] = sQ[v * NP + n];
+        for (int v = 0; v < 5; ++v) qL[v] = qs[v * KNP + e * NP + n];
         const Bg bL{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
         const double PpL = sPp[n];
         Bg bR = bL;
         double PpR = PpL;
         if (type == FT_WALL) {
-#pragma unroll
-            for (int v = 0; v < 5; ++v) qR[v] = qL[v];
-            qR[1 + d] = -qL[1 + d];  // mirror state
+            // mirror state: reverse the normal momentum
+            qR[0] = qL[0];
+            qR[1] = d == 0 ? -qL[1] : qL[1];
+            qR[2] = d == 1 ? -qL[2] : qL[2];
+            qR[3] = d == 2 ? -qL[3] : qL[3];
+            qR[4] = qL[4];
         } else {
             const int64_t nb = sNb[f * 4];
             const int fo = f ^ 1;
             const int nn = face_node<N>(fo, m), kn = face_k<N>(fo, m);
 #pragma unroll
-            for (int v = 0; v < 5; ++v) qR[v] = qs[(int64_t)v * K * NP + nb * NP + nn];
+            for (int v = 0; v < 5; ++v) qR[v] = qs[v * KNP + nb * NP + nn];
             bR = Bg{A.bg[nb * N1 + kn], A.bg[K * N1 + nb * N1 + kn], A.bg[2 * K * N1 + nb * N1 + kn]};
             PpR = pprime(qR[4], bR.Th, bR.P, gamma);
         }
-        double Fs[5], Fo[5], lam;
-        rusanov(qL, bL, PpL, qR, bR, PpR, d, sgn, gamma, Fs);
-        flux_n(qL, bL, PpL, d, sgn, gamma, Fo, lam);
+        double Fs[5], Fo[5];
+        rusanov(qL, bL, PpL, qR, bR, PpR, d, sgn, gamma, Fs, Fo);
         const double lift = A.geo[e * 4 + d] * liftc;
 #pragma unroll
         for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = (Fs[v] - Fo[v]) * lift;
     }
 
     // ---- hanging faces (L2 mortars), one face at a time (uniform over the block)
+#pragma unroll 1
     for (int f = 0; f < 6; ++f) {
         const int type = sType[f] & 0xff;
         if (type != FT_FINE && type != FT_COARSE) continue;
         const int d = f >> 1, fo = f ^ 1;
         const double lift = A.geo[e * 4 + d] * liftc;
+        const double sgn = (f & 1) ? 1.0 : -1.0;
         if (type == FT_FINE) {
             // this leaf is fine: mortar state = (I_a x I_b) of the coarse trace
             const int64_t ec = sNb[f * 4];
             const int quad = sType[f] >> 8, qa = quad & 1, qb = quad >> 1;
-            const double sgn = (f & 1) ? 1.0 : -1.0;
             __syncthreads();
             for (int it = t; it < 5 * NF; it += NT) {
                 const int v = it / NF, m = it % NF;
-                sT[it] = qs[(int64_t)v * K * NP + ec * NP + face_node<N>(fo, m)];
+                sT[it] = qs[v * KNP + ec * NP + face_node<N>(fo, m)];
             }
             __syncthreads();
             for (int m = t; m < NF; m += NT) {
@@ -261,24 +269,22 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_stage(const StageArgs A) {
                 double qL[5], qM[5];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
-                    qL[v] = sQ[v * NP + n];
+                    qL[v] = qs[v * KNP + e * NP + n];
                     qM[v] = tensor2<N>(sT + v * NF, sOps + (1 + qa) * NF, sOps + (1 + qb) * NF, m);
                 }
                 const double PpM = pprime(qM[4], b.Th, b.P, gamma);
-                double Fs[5], Fo[5], lam;
-                rusanov(qL, b, sPp[n], qM, b, PpM, d, sgn, gamma, Fs);
-                flux_n(qL, b, sPp[n], d, sgn, gamma, Fo, lam);
+                double Fs[5], Fo[5];
+                rusanov(qL, b, sPp[n], qM, b, PpM, d, sgn, gamma, Fs, Fo);
 #pragma unroll
                 for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = (Fs[v] - Fo[v]) * lift;
             }
         } else {
             // this leaf is coarse: 4 mortars, Riemann problems, projection back
-            const double sgn = (f & 1) ? 1.0 : -1.0;
             double* sM = sF;  // [4][5][NF]
             __syncthreads();
             for (int it = t; it < 5 * NF; it += NT) {
                 const int v = it / NF, m = it % NF;
-                sT[it] = sQ[v * NP + face_node<N>(f, m)];
+                sT[it] = qs[v * KNP + e * NP + face_node<N>(f, m)];
             }
             __syncthreads();
             for (int it = t; it < 4 * NF; it += NT) {
@@ -290,12 +296,12 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_stage(const StageArgs A) {
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
                     qM[v] = tensor2<N>(sT + v * NF, sOps + (1 + qa) * NF, sOps + (1 + qb) * NF, m);
-                    qF[v] = qs[(int64_t)v * K * NP + ef * NP + nn];
+                    qF[v] = qs[v * KNP + ef * NP + nn];
                 }
                 const double PpM = pprime(qM[4], b.Th, b.P, gamma);
                 const double PpF = pprime(qF[4], b.Th, b.P, gamma);
-                double Fs[5];
-                rusanov(qM, b, PpM, qF, b, PpF, d, sgn, gamma, Fs);
+                double Fs[5], Fo[5];
+                rusanov(qM, b, PpM, qF, b, PpF, d, sgn, gamma, Fs, Fo);
 #pragma unroll
                 for (int v = 0; v < 5; ++v) sM[(quad * 5 + v) * NF + m] = Fs[v];
             }
@@ -305,14 +311,15 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_stage(const StageArgs A) {
                 const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
                 double qL[5], Fo[5], lam;
 #pragma unroll
-                for (int v = 0; v < 5; ++v) qL[v] = sQ[v * NP + n];
+                for (int v = 0; v < 5; ++v) qL[v] = qs[v * KNP + e * NP + n];
                 flux_n(qL, b, sPp[n], d, sgn, gamma, Fo, lam);
-#pragma unroll
+#pragma unroll 1
                 for (int v = 0; v < 5; ++v) {
                     double proj = 0.0;
-#pragma unroll
+#pragma unroll 1
                     for (int quad = 0; quad < 4; ++quad)
-                        proj += tensor2<N>(sM + (quad * 5 + v) * NF, sOps + (3 + (quad & 1)) * NF, sOps + (3 + (quad >> 1)) * NF, m);
+                        proj += tensor2<N>(sM + (quad * 5 + v) * NF, sOps + (3 + (quad & 1)) * NF,
+                                           sOps + (3 + (quad >> 1)) * NF, m);
                     sS[(f * 5 + v) * NF + m] = (proj - Fo[v]) * lift;
                 }
             }
@@ -334,14 +341,14 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_stage(const StageArgs A) {
     const int64_t base = e * NP + t;
     if (MODE == MODE_RHS) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) A.out[(int64_t)v * K * NP + base] = R[v];
+        for (int v = 0; v < 5; ++v) A.out[v * KNP + base] = R[v];
     } else {
+        const bool use_q0 = A.a != 0.0;
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-            const double stage = fma(A.dt, R[v], q[v]);
-            double o = A.b * stage;
-            if (A.a != 0.0) o = fma(A.a, A.q0[(int64_t)v * K * NP + base], o);
-            A.out[(int64_t)v * K * NP + base] = o;
+            double o = A.b * fma(A.dt, R[v], q[v]);
+            if (use_q0) o = fma(A.a, A.q0[v * KNP + base], o);
+            A.out[v * KNP + base] = o;
         }
     }
 }

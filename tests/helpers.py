@@ -22,6 +22,24 @@ def to_elem(q, N):
     return q.reshape(q.shape[0], q.shape[1], n1, n1, n1)
 
 
+def field_errors(a, b):
+    """Relative L2 errors of the three fields rho', momentum (rho u, rho v, rho w as
+    one vector field) and Theta'; where the reference field is 0, inf unless a is 0.
+
+    The momentum is compared as a vector: a per-component bound is not rotation
+    invariant, and a component that vanishes by symmetry (the horizontal momentum
+    of a centred bubble after one step, ~1e-10) sits below the rounding floor of
+    the problem (a one-ulp change of the background moves it by ~3e-12 relative)."""
+    a = a.detach().double().cpu().reshape(a.shape[0], -1)
+    b = b.detach().double().cpu().reshape(b.shape[0], -1)
+    out = []
+    for sl in (slice(0, 1), slice(1, 4), slice(4, 5)):
+        nb = float(torch.linalg.vector_norm(b[sl]))
+        nd = float(torch.linalg.vector_norm(a[sl] - b[sl]))
+        out.append((0.0 if nd == 0.0 else float("inf")) if nb == 0.0 else nd / nb)
+    return out
+
+
 def rel_l2(a, b):
     """Per-variable ||a - b|| / ||b||; where ||b|| = 0, inf unless a is exactly 0 too."""
     a = a.detach().double().cpu().reshape(a.shape[0], -1)

@@ -11,7 +11,7 @@ from oracle import euler as eu
 from oracle import forest as fo
 from paper_2404_16648_amd import dg
 from paper_2404_16648_amd.synth import random_state
-from tests.helpers import (TOL_FP64, oracle_desc, oracle_phys, random_refinements, rel_l2, tables_equal,
+from tests.helpers import (TOL_FP64, field_errors, oracle_desc, oracle_phys, random_refinements, rel_l2, tables_equal,
                            to_elem, to_nodes)
 
 pytestmark = pytest.mark.gpu
@@ -36,8 +36,11 @@ def gpu(t):
 
 
 def check(a_gpu, b_oracle, tol=TOL_FP64, what=""):
-    err = rel_l2(a_gpu, to_nodes(b_oracle))
-    print(what, ["%.2e" % x for x in err], flush=True)
+    """rho', momentum (as one vector field) and Theta' each within tol in relative L2."""
+    b = to_nodes(b_oracle)
+    err = field_errors(a_gpu, b)
+    comp = rel_l2(a_gpu, b)
+    print(what, "fields", ["%.2e" % x for x in err], "components", ["%.2e" % x for x in comp], flush=True)
     assert max(err) <= tol, (what, err)
 
 
