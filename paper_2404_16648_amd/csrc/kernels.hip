@@ -19,6 +19,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -73,33 +74,46 @@ struct Bg {
     double rho, Th, P;
 };
 
-// sgn * F^d(q) and the wave speed |u_d| + c
-__device__ __forceinline__ void flux_n(const double q[5], const Bg& bg, double Pp, int d, double sgn, double gamma,
+// sgn * F^D(q) and the wave speed |u_D| + c  (axis D known at compile time, so
+// no array is ever indexed by a run-time value)
+template <int D>
+__device__ __forceinline__ void flux_n(const double q[5], const Bg& bg, double Pp, double sgn, double gamma,
                                        double F[5], double& lam) {
     const double rho = bg.rho + q[0];
     const double rinv = 1.0 / rho;
-    const double Ud = d == 0 ? q[1] : d == 1 ? q[2] : q[3];  // selects, not a dynamic index
-    const double ud = Ud * rinv;
+    const double ud = q[1 + D] * rinv;
     const double Th = bg.Th + q[4];
-    F[0] = sgn * Ud;
-    F[1] = sgn * (d == 0 ? q[1] * ud + Pp : q[1] * ud);
-    F[2] = sgn * (d == 1 ? q[2] * ud + Pp : q[2] * ud);
-    F[3] = sgn * (d == 2 ? q[3] * ud + Pp : q[3] * ud);
+    F[0] = sgn * q[1 + D];
+    F[1] = sgn * (D == 0 ? q[1] * ud + Pp : q[1] * ud);
+    F[2] = sgn * (D == 1 ? q[2] * ud + Pp : q[2] * ud);
+    F[3] = sgn * (D == 2 ? q[3] * ud + Pp : q[3] * ud);
     F[4] = sgn * (Th * ud);
     lam = fabs(ud) + sqrt(gamma * (bg.P + Pp) * rinv);
 }
 
-// Rusanov flux F*.n, n = sgn e_d:  {F.n} + 1/2 max(|u.n| + c) (q'- - q'+)  (section 2.2);
+// Rusanov flux F*.n, n = sgn e_D:  {F.n} + 1/2 max(|u.n| + c) (q'- - q'+)  (section 2.2);
 // also returns FL = F(qL).n
+template <int D>
 __device__ __forceinline__ void rusanov(const double qL[5], const Bg& bL, double PpL, const double qR[5],
-                                        const Bg& bR, double PpR, int d, double sgn, double gamma,
-                                        double Fs[5], double FL[5]) {
+                                        const Bg& bR, double PpR, double sgn, double gamma, double Fs[5],
+                                        double FL[5]) {
     double FR[5], lL, lR;
-    flux_n(qL, bL, PpL, d, sgn, gamma, FL, lL);
-    flux_n(qR, bR, PpR, d, sgn, gamma, FR, lR);
+    flux_n<D>(qL, bL, PpL, sgn, gamma, FL, lL);
+    flux_n<D>(qR, bR, PpR, sgn, gamma, FR, lR);
     const double hl = 0.5 * fmax(lL, lR);
 #pragma unroll
     for (int v = 0; v < 5; ++v) Fs[v] = 0.5 * (FL[v] + FR[v]) + hl * (qL[v] - qR[v]);
+}
+
+// call body.template operator()<D>() with D the run-time axis d
+template <typename Body>
+__device__ __forceinline__ void with_axis(int d, Body&& body) {
+    if (d == 0)
+        body(std::integral_constant<int, 0>{});
+    else if (d == 1)
+        body(std::integral_constant<int, 1>{});
+    else
+        body(std::integral_constant<int, 2>{});
 }
 
 // (A x B) applied to a face trace T[(N+1)^2] at face node m (A along the first
@@ -125,19 +139,32 @@ struct StageOcc {
     static constexpr int W = N >= 6 ? 4 : 5;
 };
 
+// LDS plan of the stage kernel.  sS[6][5][NF] holds the lifted face terms for
+// the whole kernel; the work area holds first the face scratch (a trace
+// sT[5][NF] and the mortar fluxes sM[4][5][NF]) and then the flux planes of the
+// volume phase: all 15 at once when they fit, else x and y, then z.
+template <int N>
+struct StageLds {
+    static constexpr int NP = Sz<N>::NP, NF = Sz<N>::NF;
+    static constexpr bool ALL3 = (15 * NP + 30 * NF) * 8 <= 64 * 1024;
+    static constexpr int PLANES = ALL3 ? 15 : 10;
+    static constexpr int WORK = PLANES * NP > 25 * NF ? PLANES * NP : 25 * NF;
+};
+
 template <int N, int MODE>
 __global__ void __launch_bounds__(Sz<N>::NT) __attribute__((amdgpu_waves_per_eu(StageOcc<N>::W)))
 k_stage(const StageArgs A) {
     constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
-    constexpr int NFL = 5 * NP > 20 * NF ? 5 * NP : 20 * NF;
-    __shared__ double sF[NFL];              // one direction of fluxes; then mortar scratch [4][5][NF]
+    constexpr bool ALL3 = StageLds<N>::ALL3;
+    __shared__ double sS[30 * NF];
+    __shared__ double sW[StageLds<N>::WORK];
     __shared__ double sPp[NP];
-    __shared__ double sS[6 * 5 * NF];       // lifted (F* - F).n per face
-    __shared__ double sT[5 * NF];           // a face trace for mortar interpolation
     __shared__ double sOps[Sz<N>::NOPS];
     __shared__ double sBg[3 * N1];
     __shared__ int sType[6];
     __shared__ int sNb[24];
+    double* const sT = sW;               // [5][NF]     (face phase)
+    double* const sM = sW + 5 * NF;      // [4][5][NF]  (face phase)
 
     const int64_t K = A.K;
     const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
@@ -147,63 +174,15 @@ k_stage(const StageArgs A) {
     // I_a at sOps + (1 + a) NF, R_a at sOps + (3 + a) NF
     const double* qs = A.qs;
     const int64_t KNP = K * NP;
+    const int i = t % N1, j = (t / N1) % N1, k = t / NF;
 
-    for (int i = t; i < Sz<N>::NOPS; i += NT) sOps[i] = A.ops[i];
+    for (int ii = t; ii < Sz<N>::NOPS; ii += NT) sOps[ii] = A.ops[ii];
     if (t < 3 * N1) sBg[t] = A.bg[(int64_t)(t / N1) * K * N1 + e * N1 + (t % N1)];
     if (t < 6) sType[t] = A.ftype[e * 6 + t];
     if (t < 24) sNb[t] = A.fnb[e * 24 + t];
-
-    double q[5] = {0, 0, 0, 0, 0};
-    if (t < NP) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) q[v] = qs[v * KNP + e * NP + t];
-    }
+    if (t < NP) sPp[t] = pprime(qs[4 * KNP + e * NP + t], A.bg[K * N1 + e * N1 + k], A.bg[2 * K * N1 + e * N1 + k],
+                                gamma);
     __syncthreads();
-
-    const int i = t % N1, j = (t / N1) % N1, k = t / NF;
-    double R[5] = {0, 0, 0, 0, 0};
-    double vel[3] = {0, 0, 0}, Pp = 0.0, Th = 0.0;
-    if (t < NP) {
-        const double rhob = sBg[k], Thb = sBg[N1 + k], Pb = sBg[2 * N1 + k];
-        const double rinv = 1.0 / (rhob + q[0]);
-        vel[0] = q[1] * rinv;
-        vel[1] = q[2] * rinv;
-        vel[2] = q[3] * rinv;
-        Pp = pprime(q[4], Thb, Pb, gamma);
-        Th = Thb + q[4];
-        sPp[t] = Pp;
-        R[3] = -q[0] * A.g;  // buoyancy on rho*w
-    }
-
-    // volume term, one direction at a time: R -= (2/h_d) D_d F^d
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        if (t < NP) {
-            const double ud = vel[d];
-            sF[0 * NP + t] = q[1 + d];
-            sF[1 * NP + t] = d == 0 ? q[1] * ud + Pp : q[1] * ud;
-            sF[2 * NP + t] = d == 1 ? q[2] * ud + Pp : q[2] * ud;
-            sF[3 * NP + t] = d == 2 ? q[3] * ud + Pp : q[3] * ud;
-            sF[4 * NP + t] = Th * ud;
-        }
-        __syncthreads();
-        if (t < NP) {
-            const int id = d == 0 ? i : d == 1 ? j : k;
-            const int stride = d == 0 ? 1 : d == 1 ? N1 : NF;
-            const int base = t - id * stride;
-            const double g2 = A.geo[e * 4 + d];
-            const double* Drow = D + id * N1;
-#pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                const double* F = sF + v * NP + base;
-                double acc = 0.0;
-#pragma unroll
-                for (int m = 0; m < N1; ++m) acc = fma(Drow[m], F[m * stride], acc);
-                R[v] = fma(-g2, acc, R[v]);
-            }
-        }
-        __syncthreads();
-    }
 
     // ---- faces: conforming neighbours and walls, every (face, node) item
     const double liftc = 0.5 * N * (N + 1);  // 1/w_N
@@ -212,37 +191,36 @@ k_stage(const StageArgs A) {
         const int f = it / NF, m = it % NF;
         const int type = sType[f] & 0xff;
         if (type != FT_WALL && type != FT_CONF) continue;
-        const int d = f >> 1;
         const double sgn = (f & 1) ? 1.0 : -1.0;
         const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
-        double qL[5], qR[5];
+        const double lift = A.geo[e * 4 + (f >> 1)] * liftc;
+        with_axis(f >> 1, [&](auto dc) {
+            constexpr int d = decltype(dc)::value;
+            double qL[5], qR[5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qL[v] = qs[v * KNP + e * NP + n];
-        const Bg bL{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
-        const double PpL = sPp[n];
-        Bg bR = bL;
-        double PpR = PpL;
-        if (type == FT_WALL) {
-            // mirror state: reverse the normal momentum
-            qR[0] = qL[0];
-            qR[1] = d == 0 ? -qL[1] : qL[1];
-            qR[2] = d == 1 ? -qL[2] : qL[2];
-            qR[3] = d == 2 ? -qL[3] : qL[3];
-            qR[4] = qL[4];
-        } else {
-            const int64_t nb = sNb[f * 4];
-            const int fo = f ^ 1;
-            const int nn = face_node<N>(fo, m), kn = face_k<N>(fo, m);
+            for (int v = 0; v < 5; ++v) qL[v] = qs[v * KNP + e * NP + n];
+            const Bg bL{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
+            const double PpL = sPp[n];
+            Bg bR = bL;
+            double PpR = PpL;
+            if (type == FT_WALL) {
 #pragma unroll
-            for (int v = 0; v < 5; ++v) qR[v] = qs[v * KNP + nb * NP + nn];
-            bR = Bg{A.bg[nb * N1 + kn], A.bg[K * N1 + nb * N1 + kn], A.bg[2 * K * N1 + nb * N1 + kn]};
-            PpR = pprime(qR[4], bR.Th, bR.P, gamma);
-        }
-        double Fs[5], Fo[5];
-        rusanov(qL, bL, PpL, qR, bR, PpR, d, sgn, gamma, Fs, Fo);
-        const double lift = A.geo[e * 4 + d] * liftc;
+                for (int v = 0; v < 5; ++v) qR[v] = qL[v];
+                qR[1 + d] = -qL[1 + d];  // mirror state: reverse the normal momentum
+            } else {
+                const int64_t nb = sNb[f * 4];
+                const int fo = f ^ 1;
+                const int nn = face_node<N>(fo, m), kn = face_k<N>(fo, m);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = (Fs[v] - Fo[v]) * lift;
+                for (int v = 0; v < 5; ++v) qR[v] = qs[v * KNP + nb * NP + nn];
+                bR = Bg{A.bg[nb * N1 + kn], A.bg[K * N1 + nb * N1 + kn], A.bg[2 * K * N1 + nb * N1 + kn]};
+                PpR = pprime(qR[4], bR.Th, bR.P, gamma);
+            }
+            double Fs[5], Fo[5];
+            rusanov<d>(qL, bL, PpL, qR, bR, PpR, sgn, gamma, Fs, Fo);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = (Fs[v] - Fo[v]) * lift;
+        });
     }
 
     // ---- hanging faces (L2 mortars), one face at a time (uniform over the block)
@@ -250,8 +228,8 @@ k_stage(const StageArgs A) {
     for (int f = 0; f < 6; ++f) {
         const int type = sType[f] & 0xff;
         if (type != FT_FINE && type != FT_COARSE) continue;
-        const int d = f >> 1, fo = f ^ 1;
-        const double lift = A.geo[e * 4 + d] * liftc;
+        const int fo = f ^ 1;
+        const double lift = A.geo[e * 4 + (f >> 1)] * liftc;
         const double sgn = (f & 1) ? 1.0 : -1.0;
         if (type == FT_FINE) {
             // this leaf is fine: mortar state = (I_a x I_b) of the coarse trace
@@ -274,13 +252,14 @@ k_stage(const StageArgs A) {
                 }
                 const double PpM = pprime(qM[4], b.Th, b.P, gamma);
                 double Fs[5], Fo[5];
-                rusanov(qL, b, sPp[n], qM, b, PpM, d, sgn, gamma, Fs, Fo);
+                with_axis(f >> 1, [&](auto dc) {
+                    rusanov<decltype(dc)::value>(qL, b, sPp[n], qM, b, PpM, sgn, gamma, Fs, Fo);
+                });
 #pragma unroll
                 for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = (Fs[v] - Fo[v]) * lift;
             }
         } else {
             // this leaf is coarse: 4 mortars, Riemann problems, projection back
-            double* sM = sF;  // [4][5][NF]
             __syncthreads();
             for (int it = t; it < 5 * NF; it += NT) {
                 const int v = it / NF, m = it % NF;
@@ -301,7 +280,9 @@ k_stage(const StageArgs A) {
                 const double PpM = pprime(qM[4], b.Th, b.P, gamma);
                 const double PpF = pprime(qF[4], b.Th, b.P, gamma);
                 double Fs[5], Fo[5];
-                rusanov(qM, b, PpM, qF, b, PpF, d, sgn, gamma, Fs, Fo);
+                with_axis(f >> 1, [&](auto dc) {
+                    rusanov<decltype(dc)::value>(qM, b, PpM, qF, b, PpF, sgn, gamma, Fs, Fo);
+                });
 #pragma unroll
                 for (int v = 0; v < 5; ++v) sM[(quad * 5 + v) * NF + m] = Fs[v];
             }
@@ -312,8 +293,8 @@ k_stage(const StageArgs A) {
                 double qL[5], Fo[5], lam;
 #pragma unroll
                 for (int v = 0; v < 5; ++v) qL[v] = qs[v * KNP + e * NP + n];
-                flux_n(qL, b, sPp[n], d, sgn, gamma, Fo, lam);
-#pragma unroll 1
+                with_axis(f >> 1, [&](auto dc) { flux_n<decltype(dc)::value>(qL, b, sPp[n], sgn, gamma, Fo, lam); });
+#pragma unroll
                 for (int v = 0; v < 5; ++v) {
                     double proj = 0.0;
 #pragma unroll 1
@@ -326,6 +307,71 @@ k_stage(const StageArgs A) {
         }
     }
     __syncthreads();
+
+    // ---- volume term: R = S - sum_d (2/h_d) D_d F^d, fluxes staged in LDS
+    double q[5] = {0, 0, 0, 0, 0}, vel[3] = {0, 0, 0}, Pp = 0.0, Th = 0.0;
+    double R[5] = {0, 0, 0, 0, 0};
+    if (t < NP) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) q[v] = qs[v * KNP + e * NP + t];
+        const double rinv = 1.0 / (sBg[k] + q[0]);
+        vel[0] = q[1] * rinv;
+        vel[1] = q[2] * rinv;
+        vel[2] = q[3] * rinv;
+        Pp = sPp[t];
+        Th = sBg[N1 + k] + q[4];
+        R[3] = -q[0] * A.g;  // buoyancy on rho*w
+    }
+    auto put_flux = [&](int d, double* F) {
+        const double ud = vel[d];
+        F[0 * NP + t] = q[1 + d];
+        F[1 * NP + t] = d == 0 ? q[1] * ud + Pp : q[1] * ud;
+        F[2 * NP + t] = d == 1 ? q[2] * ud + Pp : q[2] * ud;
+        F[3 * NP + t] = d == 2 ? q[3] * ud + Pp : q[3] * ud;
+        F[4 * NP + t] = Th * ud;
+    };
+    auto contract = [&](int d, const double* Fp) {
+        const int id = d == 0 ? i : d == 1 ? j : k;
+        const int stride = d == 0 ? 1 : d == 1 ? N1 : NF;
+        const int base = t - id * stride;
+        const double g2 = A.geo[e * 4 + d];
+        const double* Drow = D + id * N1;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            const double* F = Fp + v * NP + base;
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m < N1; ++m) acc = fma(Drow[m], F[m * stride], acc);
+            R[v] = fma(-g2, acc, R[v]);
+        }
+    };
+    if (ALL3) {
+        if (t < NP) {
+            put_flux(0, sW);
+            put_flux(1, sW + 5 * NP);
+            put_flux(2, sW + 10 * NP);
+        }
+        __syncthreads();
+        if (t < NP) {
+            contract(0, sW);
+            contract(1, sW + 5 * NP);
+            contract(2, sW + 10 * NP);
+        }
+    } else {
+        if (t < NP) {
+            put_flux(0, sW);
+            put_flux(1, sW + 5 * NP);
+        }
+        __syncthreads();
+        if (t < NP) {
+            contract(0, sW);
+            contract(1, sW + 5 * NP);
+        }
+        __syncthreads();
+        if (t < NP) put_flux(2, sW);
+        __syncthreads();
+        if (t < NP) contract(2, sW);
+    }
 
     if (t >= NP) return;
     // ---- lift: subtract the face contributions at the face nodes
