@@ -76,7 +76,8 @@ dg_status build_device(dg_mesh* m) {
     const HostMesh& h = m->h;
     const int64_t K = (int64_t)h.leaves.size();
     if (!tables_consistent(h)) return fail(DG_EINVAL, "internal: inconsistent face tables");
-    if (K >= (int64_t)1 << 31) return fail(DG_EINVAL, "too many leaves for one launch");
+    if (5 * K * (int64_t)(h.desc.N + 1) * (h.desc.N + 1) * (h.desc.N + 1) >= ((int64_t)1 << 31))
+        return fail(DG_EINVAL, "mesh too large: 5 K Np must stay below 2^31");
     const int N = h.desc.N, N1 = N + 1;
     std::vector<double> ops;
     for (auto* v : {&m->ops.D, &m->ops.I0, &m->ops.I1, &m->ops.R0, &m->ops.R1, &m->ops.w})
@@ -148,6 +149,18 @@ dg_status ensure_bg(dg_mesh* m, const dg_phys* p, hipStream_t s) {
     return DG_OK;
 }
 
+// C(gamma, k), k = 1..10, for the binomial series of (1 + x)^gamma - 1
+BinomCoef binom_coef(const dg_phys* p) {
+    BinomCoef b{};
+    const long double g = (long double)p->cp / (long double)p->cv;
+    long double c = 1.0L;
+    for (int k = 1; k <= 10; ++k) {
+        c = c * (g - (k - 1)) / k;
+        b.c[k - 1] = (double)c;
+    }
+    return b;
+}
+
 StageArgs stage_args(const dg_mesh* m, const dg_phys* p) {
     StageArgs a{};
     a.ops = m->d_ops;
@@ -158,6 +171,7 @@ StageArgs stage_args(const dg_mesh* m, const dg_phys* p) {
     a.K = (int64_t)m->h.leaves.size();
     a.gamma = p->cp / p->cv;
     a.g = p->g;
+    a.binom = binom_coef(p);
     return a;
 }
 
@@ -374,7 +388,7 @@ dg_status dg_budgets(const dg_mesh* mc, const dg_phys* phys, const double* q, do
     const int64_t K = (int64_t)m->h.leaves.size();
     const int nblk = budget_blocks(K);
     BudgetArgs a{q, m->d_bg, m->d_geo, m->d_c1d, m->d_ops + 5 * (m->h.desc.N + 1) * (m->h.desc.N + 1),
-                 m->d_red, K, phys->cp / phys->cv, phys->g};
+                 m->d_red, K, phys->cp / phys->cv, phys->g, binom_coef(phys)};
     double* out_dev = m->d_red + (int64_t)nblk * 8;
     HIP_TRY(launch_budgets(m->h.desc.N, a, nblk, out_dev, s));
     HIP_TRY(hipMemcpyAsync(out_host, out_dev, 4 * sizeof(double), hipMemcpyDeviceToHost, s));

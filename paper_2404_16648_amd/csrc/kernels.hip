@@ -65,9 +65,23 @@ __device__ __forceinline__ int face_k(int f, int m) {
     return m / (N + 1);
 }
 
-// P' = Pbar expm1(gamma log1p(Theta'/Thetabar))  (cancellation-free P(Theta) - Pbar)
-__device__ __forceinline__ double pprime(double Thp, double Thb, double Pb, double gamma) {
-    return Pb * expm1(gamma * log1p(Thp / Thb));
+// P' = P(Thetabar + Theta') - Pbar = Pbar ((1 + x)^gamma - 1), x = Theta'/Thetabar, in
+// cancellation-free form: for |x| <= 2^-7 the binomial series sum_{k=1..10} C(gamma,k) x^k
+// (Horner; truncation below 1e-17 relative), else expm1(gamma log1p(x)).
+constexpr int kBinomTerms = 10;
+
+__device__ __forceinline__ double pprime(double Thp, double Thb, double Pb, double gamma, const BinomCoef& bc) {
+    const double x = Thp / Thb;
+    double r;
+    if (fabs(x) <= 0.0078125) {
+        double acc = bc.c[kBinomTerms - 1];
+#pragma unroll
+        for (int k = kBinomTerms - 2; k >= 0; --k) acc = fma(acc, x, bc.c[k]);
+        r = acc * x;
+    } else {
+        r = expm1(gamma * log1p(x));
+    }
+    return Pb * r;
 }
 
 struct Bg {
@@ -173,15 +187,16 @@ k_stage(const StageArgs A) {
     const double* D = sOps;
     // I_a at sOps + (1 + a) NF, R_a at sOps + (3 + a) NF
     const double* qs = A.qs;
-    const int64_t KNP = K * NP;
+    const int KNP = (int)(K * NP);  // 5 K Np < 2^31 is checked by the host
+    const double* const qe = qs + e * NP;  // this leaf's tile (uniform)
     const int i = t % N1, j = (t / N1) % N1, k = t / NF;
 
     for (int ii = t; ii < Sz<N>::NOPS; ii += NT) sOps[ii] = A.ops[ii];
     if (t < 3 * N1) sBg[t] = A.bg[(int64_t)(t / N1) * K * N1 + e * N1 + (t % N1)];
     if (t < 6) sType[t] = A.ftype[e * 6 + t];
     if (t < 24) sNb[t] = A.fnb[e * 24 + t];
-    if (t < NP) sPp[t] = pprime(qs[4 * KNP + e * NP + t], A.bg[K * N1 + e * N1 + k], A.bg[2 * K * N1 + e * N1 + k],
-                                gamma);
+    if (t < NP) sPp[t] = pprime(qe[4 * KNP + t], A.bg[K * N1 + e * N1 + k], A.bg[2 * K * N1 + e * N1 + k],
+                                gamma, A.binom);
     __syncthreads();
 
     // ---- faces: conforming neighbours and walls, every (face, node) item
@@ -198,7 +213,7 @@ k_stage(const StageArgs A) {
             constexpr int d = decltype(dc)::value;
             double qL[5], qR[5];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) qL[v] = qs[v * KNP + e * NP + n];
+            for (int v = 0; v < 5; ++v) qL[v] = qe[v * KNP + n];
             const Bg bL{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
             const double PpL = sPp[n];
             Bg bR = bL;
@@ -208,13 +223,13 @@ k_stage(const StageArgs A) {
                 for (int v = 0; v < 5; ++v) qR[v] = qL[v];
                 qR[1 + d] = -qL[1 + d];  // mirror state: reverse the normal momentum
             } else {
-                const int64_t nb = sNb[f * 4];
+                const int nb = sNb[f * 4];
                 const int fo = f ^ 1;
                 const int nn = face_node<N>(fo, m), kn = face_k<N>(fo, m);
 #pragma unroll
                 for (int v = 0; v < 5; ++v) qR[v] = qs[v * KNP + nb * NP + nn];
                 bR = Bg{A.bg[nb * N1 + kn], A.bg[K * N1 + nb * N1 + kn], A.bg[2 * K * N1 + nb * N1 + kn]};
-                PpR = pprime(qR[4], bR.Th, bR.P, gamma);
+                PpR = pprime(qR[4], bR.Th, bR.P, gamma, A.binom);
             }
             double Fs[5], Fo[5];
             rusanov<d>(qL, bL, PpL, qR, bR, PpR, sgn, gamma, Fs, Fo);
@@ -233,7 +248,7 @@ k_stage(const StageArgs A) {
         const double sgn = (f & 1) ? 1.0 : -1.0;
         if (type == FT_FINE) {
             // this leaf is fine: mortar state = (I_a x I_b) of the coarse trace
-            const int64_t ec = sNb[f * 4];
+            const int ec = sNb[f * 4];
             const int quad = sType[f] >> 8, qa = quad & 1, qb = quad >> 1;
             __syncthreads();
             for (int it = t; it < 5 * NF; it += NT) {
@@ -247,10 +262,10 @@ k_stage(const StageArgs A) {
                 double qL[5], qM[5];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
-                    qL[v] = qs[v * KNP + e * NP + n];
+                    qL[v] = qe[v * KNP + n];
                     qM[v] = tensor2<N>(sT + v * NF, sOps + (1 + qa) * NF, sOps + (1 + qb) * NF, m);
                 }
-                const double PpM = pprime(qM[4], b.Th, b.P, gamma);
+                const double PpM = pprime(qM[4], b.Th, b.P, gamma, A.binom);
                 double Fs[5], Fo[5];
                 with_axis(f >> 1, [&](auto dc) {
                     rusanov<decltype(dc)::value>(qL, b, sPp[n], qM, b, PpM, sgn, gamma, Fs, Fo);
@@ -263,12 +278,12 @@ k_stage(const StageArgs A) {
             __syncthreads();
             for (int it = t; it < 5 * NF; it += NT) {
                 const int v = it / NF, m = it % NF;
-                sT[it] = qs[v * KNP + e * NP + face_node<N>(f, m)];
+                sT[it] = qe[v * KNP + face_node<N>(f, m)];
             }
             __syncthreads();
             for (int it = t; it < 4 * NF; it += NT) {
                 const int quad = it / NF, m = it % NF, qa = quad & 1, qb = quad >> 1;
-                const int64_t ef = sNb[f * 4 + quad];
+                const int ef = sNb[f * 4 + quad];
                 const int nn = face_node<N>(fo, m), kn = face_k<N>(fo, m);
                 const Bg b{A.bg[ef * N1 + kn], A.bg[K * N1 + ef * N1 + kn], A.bg[2 * K * N1 + ef * N1 + kn]};
                 double qM[5], qF[5];
@@ -277,8 +292,8 @@ k_stage(const StageArgs A) {
                     qM[v] = tensor2<N>(sT + v * NF, sOps + (1 + qa) * NF, sOps + (1 + qb) * NF, m);
                     qF[v] = qs[v * KNP + ef * NP + nn];
                 }
-                const double PpM = pprime(qM[4], b.Th, b.P, gamma);
-                const double PpF = pprime(qF[4], b.Th, b.P, gamma);
+                const double PpM = pprime(qM[4], b.Th, b.P, gamma, A.binom);
+                const double PpF = pprime(qF[4], b.Th, b.P, gamma, A.binom);
                 double Fs[5], Fo[5];
                 with_axis(f >> 1, [&](auto dc) {
                     rusanov<decltype(dc)::value>(qM, b, PpM, qF, b, PpF, sgn, gamma, Fs, Fo);
@@ -292,7 +307,7 @@ k_stage(const StageArgs A) {
                 const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
                 double qL[5], Fo[5], lam;
 #pragma unroll
-                for (int v = 0; v < 5; ++v) qL[v] = qs[v * KNP + e * NP + n];
+                for (int v = 0; v < 5; ++v) qL[v] = qe[v * KNP + n];
                 with_axis(f >> 1, [&](auto dc) { flux_n<decltype(dc)::value>(qL, b, sPp[n], sgn, gamma, Fo, lam); });
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
@@ -313,7 +328,7 @@ k_stage(const StageArgs A) {
     double R[5] = {0, 0, 0, 0, 0};
     if (t < NP) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) q[v] = qs[v * KNP + e * NP + t];
+        for (int v = 0; v < 5; ++v) q[v] = qe[v * KNP + t];
         const double rinv = 1.0 / (sBg[k] + q[0]);
         vel[0] = q[1] * rinv;
         vel[1] = q[2] * rinv;
@@ -594,7 +609,7 @@ __global__ void __launch_bounds__(256) k_budgets(const BudgetArgs A) {
             const double rhob = A.bg[e * N1 + k], Thb = A.bg[K * N1 + e * N1 + k], Pb = A.bg[2 * K * N1 + e * N1 + k];
             const double z = A.c1d[2 * K * N1 + e * N1 + k];
             const double rho = rhob + rp;
-            const double P = Pb + pprime(Thp, Thb, Pb, gamma);
+            const double P = Pb + pprime(Thp, Thb, Pb, gamma, A.binom);
             const double E = P / (gamma - 1.0) + (U * U + V * V + Wm * Wm) / (2.0 * rho) + rho * A.g * z;
             acc[0] = comp_add(acc[0], W * rp);
             acc[1] = comp_add(acc[1], W * rho);

@@ -10,6 +10,11 @@
 
 namespace dgamr {
 
+// C(gamma, k), k = 1..10: binomial series of (1 + x)^gamma - 1 used for P'
+struct BinomCoef {
+    double c[10];
+};
+
 constexpr int MODE_RHS = 0;
 constexpr int MODE_RK = 1;
 
@@ -25,6 +30,7 @@ struct StageArgs {
     int64_t K;
     double a, b, dt;
     double gamma, g;
+    BinomCoef binom;
 };
 
 struct BgParams {
@@ -50,6 +56,7 @@ struct BudgetArgs {
     double* partial;
     int64_t K;
     double gamma, g;
+    BinomCoef binom;
 };
 
 struct IndArgs {
