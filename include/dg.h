@@ -188,6 +188,19 @@ dg_status dg_coarsen_project(const dg_mesh* from, const dg_mesh* to, const doubl
 dg_status dg_rhs_adjoint(const dg_mesh* mesh, const dg_phys* phys, const double* q,
                          const double* lam, double* qbar, void* stream);
 
+/* Transposed Shu-Osher stage, the building block of the reverse SSP-RK3 step:
+ *   out := a1*w1 + a2*w2 + b*(y + dt*(dR/dq)^T(q) y)
+ * with the same transpose as dg_rhs_adjoint evaluated at the stage input q.
+ * For the forward stages q1 = q0 + dt R(q0), q2 = 3/4 q0 + 1/4 (q1 + dt R(q1)),
+ * q3 = 1/3 q0 + 2/3 (q2 + dt R(q2)) and lam3 = dJ/dq3:
+ *   lam2 = (0, -, 0, -, 2/3, dt, q2, lam3),  lam1 = (0, -, 0, -, 1/4, dt, q1, lam2),
+ *   dJ/dq0 = (1/3, lam3, 3/4, lam2, 1, dt, q0, lam1).
+ * w1 / w2 are not read when a1 / a2 is 0 (may be NULL); out may alias w1 or w2
+ * but not q or y.  (Not in the paper: the discrete adjoint of the RK stepping.) */
+dg_status dg_rk_stage_adjoint(const dg_mesh* mesh, const dg_phys* phys, double a1, const double* w1, double a2,
+                              const double* w2, double b, double dt, const double* q, const double* y, double* out,
+                              void* stream);
+
 /* Budgets over the mesh with weights J_e W_n = (hx hy hz / 8) w_i w_j w_k:
  * out_host[0] = sum rho', [1] = sum (rhobar + rho'), [2] = sum Theta',
  * [3] = sum P/(gamma-1) + |U|^2/(2 rho) + rho g z.  Compensated float64

@@ -79,9 +79,13 @@ dg_status build_device(dg_mesh* m) {
     if (5 * K * (int64_t)(h.desc.N + 1) * (h.desc.N + 1) * (h.desc.N + 1) >= ((int64_t)1 << 31))
         return fail(DG_EINVAL, "mesh too large: 5 K Np must stay below 2^31");
     const int N = h.desc.N, N1 = N + 1;
+    // D, I0, I1, R0, R1 ([N1][N1] row-major), w [N1], then I0^T, I1^T, R0^T, R1^T (adjoint)
     std::vector<double> ops;
     for (auto* v : {&m->ops.D, &m->ops.I0, &m->ops.I1, &m->ops.R0, &m->ops.R1, &m->ops.w})
         ops.insert(ops.end(), v->begin(), v->end());
+    for (auto* v : {&m->ops.I0, &m->ops.I1, &m->ops.R0, &m->ops.R1})
+        for (int c = 0; c < N1; ++c)
+            for (int r = 0; r < N1; ++r) ops.push_back((*v)[r * N1 + c]);
     std::vector<double> geo(K * 4), c1d(3 * K * N1);
     std::vector<int32_t> level(K);
     std::vector<double> c(3 * N1);
@@ -371,10 +375,51 @@ dg_status dg_coarsen_project(const dg_mesh* from, const dg_mesh* to, const doubl
     return xfer_common(from, to, q_from, q_to, stream, false);
 }
 
+static dg_status adjoint_common(const dg_mesh* mc, const dg_phys* phys, int mode, double a1, const double* w1,
+                                double a2, const double* w2, double b, double dt, const double* q, const double* lam,
+                                double* out, void* stream) {
+    dg_status st = check_dev_mesh(mc);
+    if (st) return st;
+    if ((st = check_phys(phys))) return st;
+    if (phys->precision != DG_FP64) return fail(DG_EUNSUPPORTED, "the adjoint runs in float64 only");
+    if (!q || !lam || !out) return fail(DG_EINVAL, "NULL field pointer");
+    if (out == q || out == lam) return fail(DG_EINVAL, "output must not alias q or lam");
+    if ((a1 != 0.0 && !w1) || (a2 != 0.0 && !w2)) return fail(DG_EINVAL, "NULL w1/w2 with a non-zero weight");
+    dg_mesh* m = const_cast<dg_mesh*>(mc);
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = ensure_bg(m, phys, s))) return st;
+    AdjArgs a{};
+    a.q = q;
+    a.lam = lam;
+    a.w1 = w1;
+    a.w2 = w2;
+    a.out = out;
+    a.ops = m->d_ops;
+    a.geo = m->d_geo;
+    a.bg = m->d_bg;
+    a.ftype = m->d_ftype;
+    a.fnb = m->d_fnb;
+    a.K = (int64_t)m->h.leaves.size();
+    a.a1 = a1;
+    a.a2 = a2;
+    a.b = b;
+    a.dt = dt;
+    a.gamma = phys->cp / phys->cv;
+    a.g = phys->g;
+    a.binom = binom_coef(phys);
+    HIP_TRY(launch_adjoint(m->h.desc.N, mode, a, s));
+    return DG_OK;
+}
+
 dg_status dg_rhs_adjoint(const dg_mesh* m, const dg_phys* phys, const double* q, const double* lam, double* qbar,
                          void* stream) {
-    (void)m; (void)phys; (void)q; (void)lam; (void)qbar; (void)stream;
-    return fail(DG_EUNSUPPORTED, "dg_rhs_adjoint is not available in this build");
+    return adjoint_common(m, phys, MODE_RHS, 0.0, nullptr, 0.0, nullptr, 1.0, 1.0, q, lam, qbar, stream);
+}
+
+dg_status dg_rk_stage_adjoint(const dg_mesh* m, const dg_phys* phys, double a1, const double* w1, double a2,
+                              const double* w2, double b, double dt, const double* q, const double* y, double* out,
+                              void* stream) {
+    return adjoint_common(m, phys, MODE_RK, a1, w1, a2, w2, b, dt, q, y, out, stream);
 }
 
 dg_status dg_budgets(const dg_mesh* mc, const dg_phys* phys, const double* q, double* out_host, void* stream) {

@@ -414,6 +414,357 @@ k_stage(const StageArgs A) {
     }
 }
 
+// ---------------------------------------------------------------- adjoint (transpose of k_stage)
+
+// qbar += J^T a for the flux sgn F^D at a node (a = weights on the 5 flux
+// components); rinv = 1/rho, ud = q[1+D] rinv, Th = Thetabar + Theta',
+// dPdT = dP'/dTheta' = gamma P / Th
+template <int D>
+__device__ __forceinline__ void flux_vjp(const double q[5], double rinv, double ud, double Th, double dPdT,
+                                         const double a[5], double g[5]) {
+    const double ubar = a[1] * q[1] + a[2] * q[2] + a[3] * q[3] + a[4] * Th;
+    g[1 + D] += a[0] + ubar * rinv;
+    g[1] += a[1] * ud;
+    g[2] += a[2] * ud;
+    g[3] += a[3] * ud;
+    g[4] += a[4] * ud + a[1 + D] * dPdT;
+    g[0] -= ubar * ud * rinv;
+}
+
+struct NodeState {
+    double rinv, ud, Th, dPdT, lam;
+    double dlam0, dlamU, dlam4;  // d lam / d q0, d q[1+D], d q4
+};
+
+// pointwise state for axis D: u_D, wave speed lam = |u_D| + c and its gradient
+// (d|x|/dx = 0 at x = 0)
+template <int D>
+__device__ __forceinline__ NodeState node_state(const double q[5], const Bg& b, double Pp, double gamma) {
+    NodeState s;
+    const double rho = b.rho + q[0];
+    s.rinv = 1.0 / rho;
+    s.ud = q[1 + D] * s.rinv;
+    s.Th = b.Th + q[4];
+    const double P = b.P + Pp;
+    s.dPdT = gamma * P / s.Th;
+    const double c = sqrt(gamma * P * s.rinv);
+    const double au = fabs(s.ud);
+    const double su = s.ud > 0.0 ? 1.0 : (s.ud < 0.0 ? -1.0 : 0.0);
+    s.lam = au + c;
+    s.dlam0 = -(au + 0.5 * c) * s.rinv;
+    s.dlamU = su * s.rinv;
+    s.dlam4 = 0.5 * gamma * c / s.Th;
+    return s;
+}
+
+// gL (and gR if non-null) = derivative of w . F*(qL, qR, sgn e_D) w.r.t. qL (qR);
+// a max tie splits the derivative 1/2, 1/2
+template <int D>
+__device__ __forceinline__ void rusanov_vjp(const double qL[5], const Bg& bL, double PpL, const double qR[5],
+                                            const Bg& bR, double PpR, double sgn, double gamma, const double w[5],
+                                            double gL[5], double* gR) {
+    const NodeState L = node_state<D>(qL, bL, PpL, gamma);
+    const NodeState Rr = node_state<D>(qR, bR, PpR, gamma);
+    const double hl = 0.5 * fmax(L.lam, Rr.lam);
+    const double tL = L.lam > Rr.lam ? 1.0 : (L.lam < Rr.lam ? 0.0 : 0.5);
+    double wj = 0.0;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) wj += w[v] * (qL[v] - qR[v]);
+    double a[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) a[v] = 0.5 * sgn * w[v];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) gL[v] = hl * w[v];
+    flux_vjp<D>(qL, L.rinv, L.ud, L.Th, L.dPdT, a, gL);
+    const double cL = 0.5 * wj * tL;
+    gL[0] += cL * L.dlam0;
+    gL[1 + D] += cL * L.dlamU;
+    gL[4] += cL * L.dlam4;
+    if (gR) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) gR[v] = -hl * w[v];
+        flux_vjp<D>(qR, Rr.rinv, Rr.ud, Rr.Th, Rr.dPdT, a, gR);
+        const double cR = 0.5 * wj * (1.0 - tL);
+        gR[0] += cR * Rr.dlam0;
+        gR[1 + D] += cR * Rr.dlamU;
+        gR[4] += cR * Rr.dlam4;
+    }
+}
+
+// g += J^T (lift lam) for the own flux term -(-lift F(q).n) of the lift
+template <int D>
+__device__ __forceinline__ void own_flux_vjp(const double q[5], const Bg& b, double Pp, double sgn, double gamma,
+                                             double lift, const double lam[5], double g[5]) {
+    const NodeState S = node_state<D>(q, b, Pp, gamma);
+    double a[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) a[v] = lift * sgn * lam[v];
+    flux_vjp<D>(q, S.rinv, S.ud, S.Th, S.dPdT, a, g);
+}
+
+template <int N>
+struct AdjLds {
+    static constexpr int NF = Sz<N>::NF;
+    static constexpr int SCR = 30 * NF;  // sT, sT2 [5][NF] each + sM [4][5][NF]
+};
+
+// the adjoint keeps more state per node; bound it less tightly than the forward
+template <int N>
+struct AdjOcc {
+    static constexpr int W = N >= 6 ? 2 : 3;
+};
+
+template <int N, int MODE>
+__global__ void __launch_bounds__(Sz<N>::NT) __attribute__((amdgpu_waves_per_eu(AdjOcc<N>::W)))
+k_adjoint(const AdjArgs A) {
+    constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
+    constexpr int NOPS = Sz<N>::NOPS + 4 * NF;  // + I_0^T, I_1^T, R_0^T, R_1^T
+    __shared__ double sL[5 * NP];        // lambda tile
+    __shared__ double sPp[NP];
+    __shared__ double sS[30 * NF];       // face contributions to qbar
+    __shared__ double sX[AdjLds<N>::SCR];
+    __shared__ double sOps[NOPS];
+    __shared__ double sBg[3 * N1];
+    __shared__ int sType[6];
+    __shared__ int sNb[24];
+    double* const sT = sX;             // q trace
+    double* const sT2 = sX + 5 * NF;   // lambda trace
+    double* const sM = sX + 10 * NF;   // [4][5][NF]
+    // operator offsets in sOps: D 0, I_a (1+a), R_a (3+a), w 5, I_a^T after w, R_a^T
+    const double* D = sOps;
+    auto IT = [&](int a) { return sOps + 5 * NF + N1 + a * NF; };
+    auto RT = [&](int a) { return sOps + 7 * NF + N1 + a * NF; };
+
+    const int64_t K = A.K;
+    const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
+    const int t = threadIdx.x;
+    const double gamma = A.gamma;
+    const int KNP = (int)(K * NP);
+    const int KN1 = (int)(K * N1);
+    const double* const qs = A.q;
+    const double* const ls = A.lam;
+    const double* const qe = qs + e * NP;
+    const double* const le = ls + e * NP;
+    const int i = t % N1, j = (t / N1) % N1, k = t / NF;
+
+    for (int ii = t; ii < NOPS; ii += NT) sOps[ii] = A.ops[ii];
+    if (t < 3 * N1) sBg[t] = A.bg[(t / N1) * KN1 + e * N1 + (t % N1)];
+    if (t < 6) sType[t] = A.ftype[e * 6 + t];
+    if (t < 24) sNb[t] = A.fnb[e * 24 + t];
+    double q[5] = {0, 0, 0, 0, 0}, lam[5] = {0, 0, 0, 0, 0};
+    if (t < NP) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            q[v] = qe[v * KNP + t];
+            lam[v] = le[v * KNP + t];
+            sL[v * NP + t] = lam[v];
+        }
+        sPp[t] = pprime(q[4], A.bg[KN1 + e * N1 + k], A.bg[2 * KN1 + e * N1 + k], gamma, A.binom);
+    }
+    __syncthreads();
+
+    const double liftc = 0.5 * N * (N + 1);
+    // ---- conforming faces and walls
+#pragma unroll 1
+    for (int it = t; it < 6 * NF; it += NT) {
+        const int f = it / NF, m = it % NF;
+        const int type = sType[f] & 0xff;
+        if (type != FT_WALL && type != FT_CONF) continue;
+        const double sgn = (f & 1) ? 1.0 : -1.0;
+        const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
+        const double lift = A.geo[e * 4 + (f >> 1)] * liftc;
+        with_axis(f >> 1, [&](auto dc) {
+            constexpr int d = decltype(dc)::value;
+            double qL[5], lL[5], qR[5], w[5], g[5], gR[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                qL[v] = qe[v * KNP + n];
+                lL[v] = sL[v * NP + n];
+            }
+            const Bg bL{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
+            const double PpL = sPp[n];
+            if (type == FT_WALL) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    qR[v] = qL[v];
+                    w[v] = -lift * lL[v];
+                }
+                qR[1 + d] = -qL[1 + d];
+                rusanov_vjp<d>(qL, bL, PpL, qR, bL, PpL, sgn, gamma, w, g, gR);
+                gR[1 + d] = -gR[1 + d];  // transpose of the mirror map
+#pragma unroll
+                for (int v = 0; v < 5; ++v) g[v] += gR[v];
+            } else {
+                const int nb = sNb[f * 4];
+                const int nn = face_node<N>(f ^ 1, m), kn = face_k<N>(f ^ 1, m);
+                const double liftn = A.geo[nb * 4 + (f >> 1)] * liftc;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    qR[v] = qs[v * KNP + nb * NP + nn];
+                    w[v] = -lift * lL[v] + liftn * ls[v * KNP + nb * NP + nn];
+                }
+                const Bg bR{A.bg[nb * N1 + kn], A.bg[KN1 + nb * N1 + kn], A.bg[2 * KN1 + nb * N1 + kn]};
+                const double PpR = pprime(qR[4], bR.Th, bR.P, gamma, A.binom);
+                rusanov_vjp<d>(qL, bL, PpL, qR, bR, PpR, sgn, gamma, w, g, nullptr);
+            }
+            own_flux_vjp<d>(qL, bL, PpL, sgn, gamma, lift, lL, g);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = g[v];
+        });
+    }
+
+    // ---- hanging faces
+#pragma unroll 1
+    for (int f = 0; f < 6; ++f) {
+        const int type = sType[f] & 0xff;
+        if (type != FT_FINE && type != FT_COARSE) continue;
+        const int fo = f ^ 1;
+        const double lift = A.geo[e * 4 + (f >> 1)] * liftc;
+        const double sgn = (f & 1) ? 1.0 : -1.0;
+        if (type == FT_FINE) {
+            const int ec = sNb[f * 4];
+            const int quad = sType[f] >> 8, qa = quad & 1, qb = quad >> 1;
+            const double liftcoarse = A.geo[ec * 4 + (f >> 1)] * liftc;
+            __syncthreads();
+            for (int it = t; it < 5 * NF; it += NT) {
+                const int v = it / NF, m = it % NF;
+                const int off = v * KNP + ec * NP + face_node<N>(fo, m);
+                sT[it] = qs[off];
+                sT2[it] = ls[off];
+            }
+            __syncthreads();
+            for (int m = t; m < NF; m += NT) {
+                const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
+                const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
+                double qL[5], lL[5], qM[5], w[5], g[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    qL[v] = qe[v * KNP + n];
+                    lL[v] = sL[v * NP + n];
+                    qM[v] = tensor2<N>(sT + v * NF, sOps + (1 + qa) * NF, sOps + (1 + qb) * NF, m);
+                    w[v] = -lift * lL[v] + liftcoarse * tensor2<N>(sT2 + v * NF, RT(qa), RT(qb), m);
+                }
+                const double PpM = pprime(qM[4], b.Th, b.P, gamma, A.binom);
+                with_axis(f >> 1, [&](auto dc) {
+                    constexpr int d = decltype(dc)::value;
+                    rusanov_vjp<d>(qL, b, sPp[n], qM, b, PpM, sgn, gamma, w, g, nullptr);
+                    own_flux_vjp<d>(qL, b, sPp[n], sgn, gamma, lift, lL, g);
+                });
+#pragma unroll
+                for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = g[v];
+            }
+            __syncthreads();
+        } else {
+            __syncthreads();
+            for (int it = t; it < 5 * NF; it += NT) {
+                const int v = it / NF, m = it % NF;
+                const int n = face_node<N>(f, m);
+                sT[it] = qe[v * KNP + n];
+                sT2[it] = sL[v * NP + n];
+            }
+            __syncthreads();
+            for (int it = t; it < 4 * NF; it += NT) {
+                const int quad = it / NF, m = it % NF, qa = quad & 1, qb = quad >> 1;
+                const int ef = sNb[f * 4 + quad];
+                const int nn = face_node<N>(fo, m), kn = face_k<N>(fo, m);
+                const double liftf = A.geo[ef * 4 + (f >> 1)] * liftc;
+                const Bg b{A.bg[ef * N1 + kn], A.bg[KN1 + ef * N1 + kn], A.bg[2 * KN1 + ef * N1 + kn]};
+                double qM[5], qF[5], w[5], g[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    qM[v] = tensor2<N>(sT + v * NF, sOps + (1 + qa) * NF, sOps + (1 + qb) * NF, m);
+                    qF[v] = qs[v * KNP + ef * NP + nn];
+                    w[v] = -lift * tensor2<N>(sT2 + v * NF, RT(qa), RT(qb), m) + liftf * ls[v * KNP + ef * NP + nn];
+                }
+                const double PpM = pprime(qM[4], b.Th, b.P, gamma, A.binom);
+                const double PpF = pprime(qF[4], b.Th, b.P, gamma, A.binom);
+                with_axis(f >> 1, [&](auto dc) {
+                    rusanov_vjp<decltype(dc)::value>(qM, b, PpM, qF, b, PpF, sgn, gamma, w, g, nullptr);
+                });
+#pragma unroll
+                for (int v = 0; v < 5; ++v) sM[(quad * 5 + v) * NF + m] = g[v];
+            }
+            __syncthreads();
+            for (int m = t; m < NF; m += NT) {
+                const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
+                const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
+                double qL[5], lL[5], g[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    qL[v] = qe[v * KNP + n];
+                    lL[v] = sL[v * NP + n];
+                    double acc = 0.0;
+#pragma unroll 1
+                    for (int quad = 0; quad < 4; ++quad)
+                        acc += tensor2<N>(sM + (quad * 5 + v) * NF, IT(quad & 1), IT(quad >> 1), m);
+                    g[v] = acc;
+                }
+                with_axis(f >> 1, [&](auto dc) {
+                    own_flux_vjp<decltype(dc)::value>(qL, b, sPp[n], sgn, gamma, lift, lL, g);
+                });
+#pragma unroll
+                for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = g[v];
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+
+    if (t >= NP) return;
+    // ---- volume: a^d = -(2/h_d) D_d^T lam, then the pointwise chain rule
+    double g[5] = {0, 0, 0, 0, 0};
+    {
+        const double rhob = sBg[k], Thb = sBg[N1 + k], Pb = sBg[2 * N1 + k];
+        const double rinv = 1.0 / (rhob + q[0]);
+        const double Th = Thb + q[4];
+        const double dPdT = gamma * (Pb + sPp[t]) / Th;
+        const double vel[3] = {q[1] * rinv, q[2] * rinv, q[3] * rinv};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int id = d == 0 ? i : d == 1 ? j : k;
+            const int stride = d == 0 ? 1 : d == 1 ? N1 : NF;
+            const int base = t - id * stride;
+            const double g2 = A.geo[e * 4 + d];
+            double a[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const double* Lp = sL + v * NP + base;
+                double acc = 0.0;
+#pragma unroll
+                for (int m = 0; m < N1; ++m) acc = fma(D[m * N1 + id], Lp[m * stride], acc);
+                a[v] = -g2 * acc;
+            }
+            if (d == 0) flux_vjp<0>(q, rinv, vel[0], Th, dPdT, a, g);
+            if (d == 1) flux_vjp<1>(q, rinv, vel[1], Th, dPdT, a, g);
+            if (d == 2) flux_vjp<2>(q, rinv, vel[2], Th, dPdT, a, g);
+        }
+        g[0] -= A.g * lam[3];  // buoyancy -rho' g on rho*w
+    }
+    // ---- faces that touch this node
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        if (i == 0) g[v] += sS[(0 * 5 + v) * NF + j + N1 * k];
+        if (i == N) g[v] += sS[(1 * 5 + v) * NF + j + N1 * k];
+        if (j == 0) g[v] += sS[(2 * 5 + v) * NF + i + N1 * k];
+        if (j == N) g[v] += sS[(3 * 5 + v) * NF + i + N1 * k];
+        if (k == 0) g[v] += sS[(4 * 5 + v) * NF + i + N1 * j];
+        if (k == N) g[v] += sS[(5 * 5 + v) * NF + i + N1 * j];
+    }
+    const int64_t base = e * NP + t;
+    if (MODE == MODE_RHS) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) A.out[v * KNP + base] = g[v];
+    } else {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            double o = A.b * fma(A.dt, g[v], lam[v]);
+            if (A.a1 != 0.0) o = fma(A.a1, A.w1[v * KNP + base], o);
+            if (A.a2 != 0.0) o = fma(A.a2, A.w2[v * KNP + base], o);
+            A.out[v * KNP + base] = o;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- background, IC, coordinates
 
 __global__ void k_background(int64_t K, int N1, const double* c1d, double* bg, BgParams p) {
@@ -715,6 +1066,16 @@ hipError_t launch_stage(int N, int mode, const StageArgs& a, hipStream_t s) {
         DG_DISPATCH_N(N, (k_stage<NN, MODE_RHS><<<dim3((unsigned)a.K), dim3(Sz<NN>::NT), 0, s>>>(a)));
     } else {
         DG_DISPATCH_N(N, (k_stage<NN, MODE_RK><<<dim3((unsigned)a.K), dim3(Sz<NN>::NT), 0, s>>>(a)));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint(int N, int mode, const AdjArgs& a, hipStream_t s) {
+    if (a.K <= 0) return hipSuccess;
+    if (mode == MODE_RHS) {
+        DG_DISPATCH_N(N, (k_adjoint<NN, MODE_RHS><<<dim3((unsigned)a.K), dim3(Sz<NN>::NT), 0, s>>>(a)));
+    } else {
+        DG_DISPATCH_N(N, (k_adjoint<NN, MODE_RK><<<dim3((unsigned)a.K), dim3(Sz<NN>::NT), 0, s>>>(a)));
     }
     return hipGetLastError();
 }

@@ -33,6 +33,25 @@ struct StageArgs {
     BinomCoef binom;
 };
 
+// adjoint: out = q^T-derivative qbar = (dR/dq)^T(q) lam (MODE_RHS) or
+// out = a1 w1 + a2 w2 + b (lam + dt qbar) (MODE_RK)
+struct AdjArgs {
+    const double* q;
+    const double* lam;
+    const double* w1;
+    const double* w2;
+    double* out;
+    const double* ops;     // D, I0, I1, R0, R1, w, I0^T, I1^T, R0^T, R1^T
+    const double* geo;
+    const double* bg;
+    const int32_t* ftype;
+    const int32_t* fnb;
+    int64_t K;
+    double a1, a2, b, dt;
+    double gamma, g;
+    BinomCoef binom;
+};
+
 struct BgParams {
     int32_t kind;
     double cp, cv, P0, g, theta0, rho0, Theta0;
@@ -73,6 +92,7 @@ struct IndArgs {
 };
 
 hipError_t launch_stage(int N, int mode, const StageArgs& a, hipStream_t s);
+hipError_t launch_adjoint(int N, int mode, const AdjArgs& a, hipStream_t s);
 hipError_t launch_background(int64_t K, int N, const double* c1d, double* bg, const BgParams& p, hipStream_t s);
 hipError_t launch_init_bell(int64_t K, int N, const double* c1d, const double* bg, double theta0, const dg_bell& b,
                             double* q, hipStream_t s);

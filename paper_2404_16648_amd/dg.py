@@ -37,7 +37,7 @@ DG_KIND_FAMILY = 8
 EXPORTED = [
     "dg_mesh_build", "dg_mesh_free", "dg_mesh_info_get", "dg_mesh_export", "dg_node_coords",
     "dg_init_bell", "dg_rhs", "dg_rk_stage", "dg_refine_project", "dg_coarsen_project",
-    "dg_rhs_adjoint", "dg_budgets", "dg_indicator", "dg_last_error",
+    "dg_rhs_adjoint", "dg_rk_stage_adjoint", "dg_budgets", "dg_indicator", "dg_last_error",
 ]
 
 
@@ -96,6 +96,8 @@ def lib():
         L.dg_refine_project.argtypes = [P, P, P, P, P]
         L.dg_coarsen_project.argtypes = [P, P, P, P, P]
         L.dg_rhs_adjoint.argtypes = [P, C.POINTER(Phys), P, P, P, P]
+        L.dg_rk_stage_adjoint.argtypes = [P, C.POINTER(Phys), C.c_double, P, C.c_double, P, C.c_double,
+                                          C.c_double, P, P, P, P]
         L.dg_budgets.argtypes = [P, C.POINTER(Phys), P, P, P]
         L.dg_indicator.argtypes = [P, C.POINTER(Phys), P, C.c_int32, C.c_double, P, P, P]
         L.dg_last_error.restype = C.c_char_p
@@ -267,6 +269,13 @@ def dg_rhs_adjoint(mesh: Mesh, phys: PhysParams, q, lam, qbar, stream=None):
     _shape_check(mesh, q, lam, qbar)
     p = phys.c()
     _check(lib().dg_rhs_adjoint(mesh.handle, C.byref(p), _ptr(q), _ptr(lam), _ptr(qbar), _stream(stream)))
+
+
+def dg_rk_stage_adjoint(mesh: Mesh, phys: PhysParams, a1, w1, a2, w2, b, dt, q, y, out, stream=None):
+    _shape_check(mesh, w1, w2, q, y, out)
+    p = phys.c()
+    _check(lib().dg_rk_stage_adjoint(mesh.handle, C.byref(p), a1, _ptr(w1), a2, _ptr(w2), b, dt, _ptr(q),
+                                     _ptr(y), _ptr(out), _stream(stream)))
 
 
 def dg_budgets(mesh: Mesh, phys: PhysParams, q, stream=None):
