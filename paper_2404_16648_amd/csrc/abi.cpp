@@ -318,7 +318,6 @@ static dg_status stage_common(const dg_mesh* mc, const dg_phys* phys, int mode, 
     dg_status st = check_dev_mesh(mc);
     if (st) return st;
     if ((st = check_phys(phys))) return st;
-    if (phys->precision != DG_FP64) return fail(DG_EUNSUPPORTED, "mixed precision is not available in this call");
     if (!qs || !out) return fail(DG_EINVAL, "NULL field pointer");
     if (out == qs) return fail(DG_EINVAL, "output must not alias the stage input");
     if (mode == MODE_RK && a != 0.0 && !q0) return fail(DG_EINVAL, "q0 is NULL while a != 0");
@@ -332,7 +331,7 @@ static dg_status stage_common(const dg_mesh* mc, const dg_phys* phys, int mode, 
     args.a = a;
     args.b = b;
     args.dt = dt;
-    HIP_TRY(launch_stage(m->h.desc.N, mode, args, s));
+    HIP_TRY(launch_stage(m->h.desc.N, mode, phys->precision == DG_MIXED, args, s));
     return DG_OK;
 }
 

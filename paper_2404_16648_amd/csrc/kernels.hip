@@ -150,28 +150,35 @@ __device__ __forceinline__ double tensor2(const double* T, const double* A, cons
 // waves per SIMD the stage kernel is compiled for (bounds the VGPR budget)
 template <int N>
 struct StageOcc {
-    static constexpr int W = N >= 6 ? 4 : 5;
+    static constexpr int W = N >= 6 ? 4 : 3;
 };
 
-// LDS plan of the stage kernel.  sS[6][5][NF] holds the lifted face terms for
-// the whole kernel; the work area holds first the face scratch (a trace
-// sT[5][NF] and the mortar fluxes sM[4][5][NF]) and then the flux planes of the
-// volume phase: all 15 at once when they fit, else x and y, then z.
-template <int N>
+// LDS plan of the stage kernel: the work area holds first the face scratch (a
+// trace sT[5][NF] and the mortar fluxes sM[4][5][NF], doubles) and then the flux
+// planes of the volume phase: all 15 at once when they fit, else x and y, then z.
+// MIX stores the planes as float (flux minus an element-constant reference).
+template <int N, bool MIX>
 struct StageLds {
     static constexpr int NP = Sz<N>::NP, NF = Sz<N>::NF;
-    static constexpr bool ALL3 = (15 * NP + 30 * NF) * 8 <= 64 * 1024;
+    static constexpr int ESZ = MIX ? 4 : 8;
+    static constexpr bool ALL3 = (15 * NP * ESZ + 30 * NF * 8) <= 64 * 1024;
     static constexpr int PLANES = ALL3 ? 15 : 10;
-    static constexpr int WORK = PLANES * NP > 25 * NF ? PLANES * NP : 25 * NF;
+    static constexpr int PLANE_DBL = (PLANES * NP * ESZ + 7) / 8;
+    static constexpr int WORK = PLANE_DBL > 25 * NF ? PLANE_DBL : 25 * NF;
 };
 
-template <int N, int MODE>
+// MIX: the volume contractions in float32 on the flux minus the flux at the
+// leaf's first node (exact, since D annihilates constants), with D split into a
+// float32 high part and a float32 correction and float32 accumulation; the
+// pressure, the fluxes themselves, faces, mortars and the update stay float64.
+template <int N, int MODE, bool MIX>
 __global__ void __launch_bounds__(Sz<N>::NT) __attribute__((amdgpu_waves_per_eu(StageOcc<N>::W)))
 k_stage(const StageArgs A) {
     constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
-    constexpr bool ALL3 = StageLds<N>::ALL3;
+    constexpr bool ALL3 = StageLds<N, MIX>::ALL3;
     __shared__ double sS[30 * NF];
-    __shared__ double sW[StageLds<N>::WORK];
+    __shared__ double sW[StageLds<N, MIX>::WORK];
+    __shared__ float sD32[2 * N1 * N1];  // MIX: D high and low parts
     __shared__ double sPp[NP];
     __shared__ double sOps[Sz<N>::NOPS];
     __shared__ double sBg[3 * N1];
@@ -337,55 +344,105 @@ k_stage(const StageArgs A) {
         Th = sBg[N1 + k] + q[4];
         R[3] = -q[0] * A.g;  // buoyancy on rho*w
     }
-    auto put_flux = [&](int d, double* F) {
+    // MIX: element-constant reference flux (at the leaf's first node, same address
+    // for every thread), formed per direction in put_flux
+    double q0n[5] = {0, 0, 0, 0, 0}, rinv0 = 0.0, Pp0 = 0.0, Th0 = 0.0;
+    if (MIX) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) q0n[v] = qe[v * KNP];
+        rinv0 = 1.0 / (sBg[0] + q0n[0]);
+        Pp0 = sPp[0];
+        Th0 = sBg[N1] + q0n[4];
+        for (int ii = t; ii < N1 * N1; ii += NT) {
+            const double dv = A.ops[ii];
+            const float hi = (float)dv;
+            sD32[ii] = hi;
+            sD32[N1 * N1 + ii] = (float)(dv - (double)hi);
+        }
+    }
+    auto put_flux = [&](int d, int plane) {
         const double ud = vel[d];
-        F[0 * NP + t] = q[1 + d];
-        F[1 * NP + t] = d == 0 ? q[1] * ud + Pp : q[1] * ud;
-        F[2 * NP + t] = d == 1 ? q[2] * ud + Pp : q[2] * ud;
-        F[3 * NP + t] = d == 2 ? q[3] * ud + Pp : q[3] * ud;
-        F[4 * NP + t] = Th * ud;
+        double F[5];
+        F[0] = q[1 + d];
+        F[1] = d == 0 ? q[1] * ud + Pp : q[1] * ud;
+        F[2] = d == 1 ? q[2] * ud + Pp : q[2] * ud;
+        F[3] = d == 2 ? q[3] * ud + Pp : q[3] * ud;
+        F[4] = Th * ud;
+        if (MIX) {
+            const double u0 = q0n[1 + d] * rinv0;
+            double Fr[5];
+            Fr[0] = q0n[1 + d];
+            Fr[1] = d == 0 ? q0n[1] * u0 + Pp0 : q0n[1] * u0;
+            Fr[2] = d == 1 ? q0n[2] * u0 + Pp0 : q0n[2] * u0;
+            Fr[3] = d == 2 ? q0n[3] * u0 + Pp0 : q0n[3] * u0;
+            Fr[4] = Th0 * u0;
+            float* Ff = reinterpret_cast<float*>(sW) + plane * 5 * NP;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) Ff[v * NP + t] = (float)(F[v] - Fr[v]);
+        } else {
+            double* Fd = sW + plane * 5 * NP;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) Fd[v * NP + t] = F[v];
+        }
     };
-    auto contract = [&](int d, const double* Fp) {
+    auto contract = [&](int d, int plane) {
         const int id = d == 0 ? i : d == 1 ? j : k;
         const int stride = d == 0 ? 1 : d == 1 ? N1 : NF;
         const int base = t - id * stride;
         const double g2 = A.geo[e * 4 + d];
-        const double* Drow = D + id * N1;
+        if (MIX) {
+            const float* Dh = sD32 + id * N1;
+            const float* Dl = sD32 + N1 * N1 + id * N1;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            const double* F = Fp + v * NP + base;
-            double acc = 0.0;
+            for (int v = 0; v < 5; ++v) {
+                const float* F = reinterpret_cast<const float*>(sW) + (plane * 5 + v) * NP + base;
+                float ah = 0.0f, al = 0.0f;
 #pragma unroll
-            for (int m = 0; m < N1; ++m) acc = fma(Drow[m], F[m * stride], acc);
-            R[v] = fma(-g2, acc, R[v]);
+                for (int m = 0; m < N1; ++m) {
+                    const float fv = F[m * stride];
+                    ah = fmaf(Dh[m], fv, ah);
+                    al = fmaf(Dl[m], fv, al);
+                }
+                R[v] = fma(-g2, (double)ah + (double)al, R[v]);
+            }
+        } else {
+            const double* Drow = D + id * N1;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const double* F = sW + (plane * 5 + v) * NP + base;
+                double acc = 0.0;
+#pragma unroll
+                for (int m = 0; m < N1; ++m) acc = fma(Drow[m], F[m * stride], acc);
+                R[v] = fma(-g2, acc, R[v]);
+            }
         }
     };
     if (ALL3) {
         if (t < NP) {
-            put_flux(0, sW);
-            put_flux(1, sW + 5 * NP);
-            put_flux(2, sW + 10 * NP);
+            put_flux(0, 0);
+            put_flux(1, 1);
+            put_flux(2, 2);
         }
         __syncthreads();
         if (t < NP) {
-            contract(0, sW);
-            contract(1, sW + 5 * NP);
-            contract(2, sW + 10 * NP);
+            contract(0, 0);
+            contract(1, 1);
+            contract(2, 2);
         }
     } else {
         if (t < NP) {
-            put_flux(0, sW);
-            put_flux(1, sW + 5 * NP);
+            put_flux(0, 0);
+            put_flux(1, 1);
         }
         __syncthreads();
         if (t < NP) {
-            contract(0, sW);
-            contract(1, sW + 5 * NP);
+            contract(0, 0);
+            contract(1, 1);
         }
         __syncthreads();
-        if (t < NP) put_flux(2, sW);
+        if (t < NP) put_flux(2, 0);
         __syncthreads();
-        if (t < NP) contract(2, sW);
+        if (t < NP) contract(2, 0);
     }
 
     if (t >= NP) return;
@@ -1060,12 +1117,21 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_indicator(const IndArgs A) {
         default: return hipErrorInvalidValue;                        \
     }
 
-hipError_t launch_stage(int N, int mode, const StageArgs& a, hipStream_t s) {
+hipError_t launch_stage(int N, int mode, bool mixed, const StageArgs& a, hipStream_t s) {
     if (a.K <= 0) return hipSuccess;
-    if (mode == MODE_RHS) {
-        DG_DISPATCH_N(N, (k_stage<NN, MODE_RHS><<<dim3((unsigned)a.K), dim3(Sz<NN>::NT), 0, s>>>(a)));
+    const dim3 grid((unsigned)a.K);
+    if (mixed) {
+        if (mode == MODE_RHS) {
+            DG_DISPATCH_N(N, (k_stage<NN, MODE_RHS, true><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        } else {
+            DG_DISPATCH_N(N, (k_stage<NN, MODE_RK, true><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        }
     } else {
-        DG_DISPATCH_N(N, (k_stage<NN, MODE_RK><<<dim3((unsigned)a.K), dim3(Sz<NN>::NT), 0, s>>>(a)));
+        if (mode == MODE_RHS) {
+            DG_DISPATCH_N(N, (k_stage<NN, MODE_RHS, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        } else {
+            DG_DISPATCH_N(N, (k_stage<NN, MODE_RK, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        }
     }
     return hipGetLastError();
 }
