@@ -34,6 +34,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--adapt-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
     return ap.parse_args()
 
 
@@ -130,9 +131,88 @@ def main():
         "wall_s": wall,
         "mass_prime_final": budgets[0],
     }
+    if not args.no_extras:
+        result["extras"] = extras(dg, torch, state["mesh"], state["q"], ph, dt, 1e3 * stage_ms / len(events))
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)
+
+
+def _time_launches(torch, fn, reps):
+    """Average duration (us) of fn() over reps launches, HIP events on the current stream."""
+    stream = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return 1e3 * e0.elapsed_time(e1) / reps
+
+
+def _field_err(torch, a, b):
+    out = []
+    for sl in (slice(0, 1), slice(1, 4), slice(4, 5)):
+        nb = float(torch.linalg.vector_norm(b[sl]))
+        out.append(float(torch.linalg.vector_norm(a[sl] - b[sl])) / nb if nb > 0 else 0.0)
+    return out
+
+
+def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us):
+    """Mixed/float64 speedup with the mixed error, the adjoint/forward cost ratio,
+    and the largest AMR configuration (density current)."""
+    from paper_2404_16648_amd import adjoint as adj
+    out = {}
+    # ---- precision split on the same mesh and state
+    mixed = dg.PhysParams(precision=dg.DG_MIXED)
+    q1 = torch.empty_like(q)
+    mixed_us = _time_launches(torch, lambda: dg.dg_rk_stage(mesh, mixed, 0.75, 0.25, dt, q, q, q1), 20)
+    f64_us = _time_launches(torch, lambda: dg.dg_rk_stage(mesh, ph, 0.75, 0.25, dt, q, q, q1), 20)
+    Ra, Rb = torch.empty_like(q), torch.empty_like(q)
+    dg.dg_rhs(mesh, ph, q, Ra)
+    dg.dg_rhs(mesh, mixed, q, Rb)
+    out["mixed"] = {"stage_us_fp64": f64_us, "stage_us_mixed": mixed_us, "speedup": f64_us / mixed_us,
+                    "rhs_rel_l2_vs_fp64_fields(rho',momentum,Theta')": _field_err(torch, Rb, Ra)}
+    # ---- adjoint cost: one transposed RHS vs one RHS on the same state
+    lam = torch.randn(q.shape, dtype=torch.float64, device=q.device, generator=torch.Generator(q.device).manual_seed(7))
+    g = torch.empty_like(q)
+    rhs_us = _time_launches(torch, lambda: dg.dg_rhs(mesh, ph, q, Ra), 20)
+    adj_us = _time_launches(torch, lambda: dg.dg_rhs_adjoint(mesh, ph, q, lam, g), 20)
+    out["adjoint_rhs"] = {"rhs_us": rhs_us, "rhs_adjoint_us": adj_us, "ratio": adj_us / rhs_us}
+    # ---- adjoint configuration: 16^3 hexes, N = 4, 50 SSP-RK3 steps, checkpoints every 10
+    m4 = dg.dg_mesh_build(4, (16, 16, 16), 0, (0.0, 0.0, 0.0), (1000.0, 1000.0, 1000.0))
+    q4 = m4.field()
+    dg.dg_init_bell(m4, ph, q4, 2.0, (500.0, 500.0, 350.0), (250.0, 250.0, 250.0))
+    dt4, n4 = 0.005, 50
+    seed = torch.randn(q4.shape, dtype=torch.float64, device=q4.device,
+                       generator=torch.Generator(q4.device).manual_seed(3))
+    for rep in range(2):  # the first pass loads the kernels; the second is timed
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = q4.clone().requires_grad_(True)
+        qT = adj.integrate(x, m4, ph, dt4, n4, 10)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        (gx,) = torch.autograd.grad(qT, x, grad_outputs=seed)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+    out["adjoint_gradient"] = {"workload": "16^3 hexes, N=4, 50 SSP-RK3 steps (dt=0.005 s), checkpoints every 10",
+                               "forward_s": t1 - t0, "backward_s": t2 - t1, "ratio": (t2 - t1) / (t1 - t0)}
+    # ---- largest AMR configuration: density current, 64x4x16 base, N = 4, 2 levels on |grad theta|
+    m3, q3 = dg.initial_mesh(4, (64, 4, 16), 2, (0.0, 0.0, 0.0), (25600.0, 1600.0, 6400.0), (0, 0, 0), ph,
+                             (-15.0, (0.0, 800.0, 3000.0), (4000.0, 0.0, 2000.0)), dg.DG_IND_GRAD_THETA, 1e-3)
+    a3 = torch.empty_like(q3)
+    nodes3 = m3.K * m3.Np
+    for prec, key in ((ph, "fp64"), (mixed, "mixed")):
+        us = _time_launches(torch, lambda: dg.dg_rk_stage(m3, prec, 0.75, 0.25, 0.008, q3, q3, a3), 20)
+        ach = nodes3 * BYTES_STAGE / (us * 1e-6) / 1e9
+        out["density_current_" + key] = {
+            "leaves": m3.K, "nodes": nodes3, "hanging_faces": int(m3.info.n_hang), "stage_us": us,
+            "dof_updates_per_s": 5 * nodes3 / (us * 1e-6), "achieved_GBs": ach, "frac_hbm": ach / HBM_PEAK_GBS}
+    return out
 
 
 def cpu_baseline():
