@@ -147,6 +147,39 @@ __device__ __forceinline__ double tensor2(const double* T, const double* A, cons
     return acc;
 }
 
+// Block-level separable tensor products on face data laid out [plane][b][a]
+// ((N+1)^2 values per plane, a along the first tangential axis).  Every output
+// is an fma chain in a fixed order, so two blocks applying the same operator to
+// the same data get bitwise-identical results.
+// out[p][b][a'] = sum_a A(p)[a'][a] in[src(p)][b][a]   for planes p < np
+template <int N, typename OpA, typename Src>
+__device__ __forceinline__ void apply_t1(const double* in, double* out, int np, OpA opA, Src src, int t, int nt) {
+    constexpr int N1 = N + 1, NF = N1 * N1;
+    for (int it = t; it < np * NF; it += nt) {
+        const int p = it / NF, r = it % NF, b = r / N1, a2 = r % N1;
+        const double* A = opA(p) + a2 * N1;
+        const double* x = in + src(p) * NF + b * N1;
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < N1; ++a) acc = fma(A[a], x[a], acc);
+        out[it] = acc;
+    }
+}
+// out[p][b'][a] = sum_b B(p)[b'][b] in[src(p)][b][a]
+template <int N, typename OpB, typename Src>
+__device__ __forceinline__ void apply_t2(const double* in, double* out, int np, OpB opB, Src src, int t, int nt) {
+    constexpr int N1 = N + 1, NF = N1 * N1;
+    for (int it = t; it < np * NF; it += nt) {
+        const int p = it / NF, r = it % NF, b2 = r / N1, a = r % N1;
+        const double* B = opB(p) + b2 * N1;
+        const double* x = in + src(p) * NF + a;
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < N1; ++b) acc = fma(B[b], x[b * N1], acc);
+        out[it] = acc;
+    }
+}
+
 // waves per SIMD the stage kernel is compiled for (bounds the VGPR budget)
 template <int N>
 struct StageOcc {
@@ -164,7 +197,7 @@ struct StageLds {
     static constexpr bool ALL3 = (15 * NP * ESZ + 30 * NF * 8) <= 64 * 1024;
     static constexpr int PLANES = ALL3 ? 15 : 10;
     static constexpr int PLANE_DBL = (PLANES * NP * ESZ + 7) / 8;
-    static constexpr int WORK = PLANE_DBL > 25 * NF ? PLANE_DBL : 25 * NF;
+    static constexpr int WORK = PLANE_DBL > 45 * NF ? PLANE_DBL : 45 * NF;
 };
 
 // MIX: the volume contractions in float32 on the flux minus the flux at the
@@ -184,8 +217,7 @@ k_stage(const StageArgs A) {
     __shared__ double sBg[3 * N1];
     __shared__ int sType[6];
     __shared__ int sNb[24];
-    double* const sT = sW;               // [5][NF]     (face phase)
-    double* const sM = sW + 5 * NF;      // [4][5][NF]  (face phase)
+    double* const sT = sW;               // [5][NF]     (hanging faces)
 
     const int64_t K = A.K;
     const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
@@ -208,9 +240,14 @@ k_stage(const StageArgs A) {
 
     // ---- faces: conforming neighbours and walls, every (face, node) item
     const double liftc = 0.5 * N * (N + 1);  // 1/w_N
+    // items grouped by axis, each axis padded to whole waves, so a wave never
+    // mixes the three axis variants of the flux code
+    constexpr int PAD = ((2 * NF + 63) / 64) * 64;
 #pragma unroll 1
-    for (int it = t; it < 6 * NF; it += NT) {
-        const int f = it / NF, m = it % NF;
+    for (int it = t; it < 3 * PAD; it += NT) {
+        const int ax = it / PAD, r = it % PAD;
+        if (r >= 2 * NF) continue;
+        const int f = 2 * ax + r / NF, m = r % NF;
         const int type = sType[f] & 0xff;
         if (type != FT_WALL && type != FT_CONF) continue;
         const double sgn = (f & 1) ? 1.0 : -1.0;
@@ -245,7 +282,11 @@ k_stage(const StageArgs A) {
         });
     }
 
-    // ---- hanging faces (L2 mortars), one face at a time (uniform over the block)
+    // ---- hanging faces (L2 mortars), one face at a time (uniform over the block).
+    // Scratch in the work area: sT trace [5][NF], sU [10][NF], sM [20][NF], sG [10][NF].
+    double* const sU = sW + 5 * NF;
+    double* const sMq = sW + 15 * NF;
+    double* const sG = sW + 35 * NF;
 #pragma unroll 1
     for (int f = 0; f < 6; ++f) {
         const int type = sType[f] & 0xff;
@@ -263,6 +304,10 @@ k_stage(const StageArgs A) {
                 sT[it] = qs[v * KNP + ec * NP + face_node<N>(fo, m)];
             }
             __syncthreads();
+            apply_t1<N>(sT, sU, 5, [&](int) { return sOps + (1 + qa) * NF; }, [](int p) { return p; }, t, NT);
+            __syncthreads();
+            apply_t2<N>(sU, sMq, 5, [&](int) { return sOps + (1 + qb) * NF; }, [](int p) { return p; }, t, NT);
+            __syncthreads();
             for (int m = t; m < NF; m += NT) {
                 const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
                 const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
@@ -270,7 +315,7 @@ k_stage(const StageArgs A) {
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
                     qL[v] = qe[v * KNP + n];
-                    qM[v] = tensor2<N>(sT + v * NF, sOps + (1 + qa) * NF, sOps + (1 + qb) * NF, m);
+                    qM[v] = sMq[v * NF + m];
                 }
                 const double PpM = pprime(qM[4], b.Th, b.P, gamma, A.binom);
                 double Fs[5], Fo[5];
@@ -288,15 +333,22 @@ k_stage(const StageArgs A) {
                 sT[it] = qe[v * KNP + face_node<N>(f, m)];
             }
             __syncthreads();
+            // sU[a][v] = I_a along t1; sMq[quad][v] = I_b along t2 of sU[a]  (quad = a + 2b)
+            apply_t1<N>(sT, sU, 10, [&](int p) { return sOps + (1 + p / 5) * NF; }, [](int p) { return p % 5; }, t,
+                        NT);
+            __syncthreads();
+            apply_t2<N>(sU, sMq, 20, [&](int p) { return sOps + (1 + (p / 5) / 2) * NF; },
+                        [](int p) { return ((p / 5) & 1) * 5 + p % 5; }, t, NT);
+            __syncthreads();
             for (int it = t; it < 4 * NF; it += NT) {
-                const int quad = it / NF, m = it % NF, qa = quad & 1, qb = quad >> 1;
+                const int quad = it / NF, m = it % NF;
                 const int ef = sNb[f * 4 + quad];
                 const int nn = face_node<N>(fo, m), kn = face_k<N>(fo, m);
                 const Bg b{A.bg[ef * N1 + kn], A.bg[K * N1 + ef * N1 + kn], A.bg[2 * K * N1 + ef * N1 + kn]};
                 double qM[5], qF[5];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
-                    qM[v] = tensor2<N>(sT + v * NF, sOps + (1 + qa) * NF, sOps + (1 + qb) * NF, m);
+                    qM[v] = sMq[(quad * 5 + v) * NF + m];
                     qF[v] = qs[v * KNP + ef * NP + nn];
                 }
                 const double PpM = pprime(qM[4], b.Th, b.P, gamma, A.binom);
@@ -306,7 +358,35 @@ k_stage(const StageArgs A) {
                     rusanov<decltype(dc)::value>(qM, b, PpM, qF, b, PpF, sgn, gamma, Fs, Fo);
                 });
 #pragma unroll
-                for (int v = 0; v < 5; ++v) sM[(quad * 5 + v) * NF + m] = Fs[v];
+                for (int v = 0; v < 5; ++v) sMq[(quad * 5 + v) * NF + m] = Fs[v];  // in place
+            }
+            __syncthreads();
+            // projection back: sG[b][v] = sum_a R_a along t1 of F[a + 2b]; then sum_b R_b along t2
+            for (int it = t; it < 10 * NF; it += NT) {
+                const int p = it / NF, r = it % NF, bb = r / N1, a2 = r % N1;
+                const int qb = p / 5, v = p % 5;
+                double acc = 0.0;
+#pragma unroll
+                for (int qa = 0; qa < 2; ++qa) {
+                    const double* Rm = sOps + (3 + qa) * NF + a2 * N1;
+                    const double* x = sMq + ((qa + 2 * qb) * 5 + v) * NF + bb * N1;
+#pragma unroll
+                    for (int a = 0; a < N1; ++a) acc = fma(Rm[a], x[a], acc);
+                }
+                sG[it] = acc;
+            }
+            __syncthreads();
+            for (int it = t; it < 5 * NF; it += NT) {
+                const int v = it / NF, m = it % NF, b2 = m / N1, a = m % N1;
+                double proj = 0.0;
+#pragma unroll
+                for (int qb = 0; qb < 2; ++qb) {
+                    const double* Rm = sOps + (3 + qb) * NF + b2 * N1;
+                    const double* x = sG + (qb * 5 + v) * NF + a;
+#pragma unroll
+                    for (int bb = 0; bb < N1; ++bb) proj = fma(Rm[bb], x[bb * N1], proj);
+                }
+                sU[it] = proj;
             }
             __syncthreads();
             for (int m = t; m < NF; m += NT) {
@@ -317,14 +397,7 @@ k_stage(const StageArgs A) {
                 for (int v = 0; v < 5; ++v) qL[v] = qe[v * KNP + n];
                 with_axis(f >> 1, [&](auto dc) { flux_n<decltype(dc)::value>(qL, b, sPp[n], sgn, gamma, Fo, lam); });
 #pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    double proj = 0.0;
-#pragma unroll 1
-                    for (int quad = 0; quad < 4; ++quad)
-                        proj += tensor2<N>(sM + (quad * 5 + v) * NF, sOps + (3 + (quad & 1)) * NF,
-                                           sOps + (3 + (quad >> 1)) * NF, m);
-                    sS[(f * 5 + v) * NF + m] = (proj - Fo[v]) * lift;
-                }
+                for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = (sU[v * NF + m] - Fo[v]) * lift;
             }
         }
     }
