@@ -34,26 +34,28 @@ dg_status hip_fail(hipError_t e, const char* where) {
         if (e_ != hipSuccess) return hip_fail(e_, #call);        \
     } while (0)
 
-template <typename T>
-hipError_t upload(T** dst, const std::vector<T>& src) {
-    if (src.empty()) {
-        *dst = nullptr;
-        return hipSuccess;
-    }
-    hipError_t e = hipMalloc((void**)dst, src.size() * sizeof(T));
-    if (e != hipSuccess) return e;
-    return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
-}
-
 void free_device(dg_mesh* m) {
-    void* ptrs[] = {m->d_ops, m->d_geo, m->d_c1d, m->d_ftype, m->d_fnb, m->d_level,
-                    m->d_xsrc, m->d_xkind, m->d_bg, m->d_red, m->d_flags, m->d_eta};
-    for (void* p : ptrs)
-        if (p) (void)hipFree(p);
+    if (m->d_base) (void)hipFree(m->d_base);
+    m->d_base = nullptr;
     m->d_ops = m->d_geo = m->d_c1d = m->d_bg = m->d_red = m->d_eta = nullptr;
     m->d_ftype = m->d_fnb = m->d_level = m->d_xsrc = m->d_xkind = nullptr;
     m->d_flags = nullptr;
 }
+
+// packs host arrays into one staging buffer at 256-byte aligned offsets
+struct Packer {
+    std::vector<char> host;
+    size_t add(const void* src, size_t bytes) {
+        const size_t off = (host.size() + 255) & ~(size_t)255;
+        host.resize(off + bytes);
+        if (src && bytes) std::memcpy(host.data() + off, src, bytes);
+        return off;
+    }
+    template <typename T>
+    size_t add(const std::vector<T>& v) {
+        return add(v.data(), v.size() * sizeof(T));
+    }
+};
 
 // every face of every leaf has a type and in-range neighbours (the kernels index
 // field arrays with them); checked on the host before anything is uploaded
@@ -99,20 +101,36 @@ dg_status build_device(dg_mesh* m) {
         geo[e * 4 + 3] = hh[0] * hh[1] * hh[2] / 8.0;
         level[e] = h.leaves[e].l;
     }
-    HIP_TRY(hipGetDevice(&m->device));
-    HIP_TRY(upload(&m->d_ops, ops));
-    HIP_TRY(upload(&m->d_geo, geo));
-    HIP_TRY(upload(&m->d_c1d, c1d));
-    HIP_TRY(upload(&m->d_ftype, h.ftype));
-    HIP_TRY(upload(&m->d_fnb, h.fnb));
-    HIP_TRY(upload(&m->d_level, level));
-    HIP_TRY(upload(&m->d_xsrc, h.xfer_src));
-    HIP_TRY(upload(&m->d_xkind, h.xfer_kind));
-    HIP_TRY(hipMalloc((void**)&m->d_bg, sizeof(double) * 3 * K * N1));
+    // one device allocation and one copy for every table of the mesh; the
+    // background, reduction and flag buffers are carved from the same block
+    Packer pk;
+    const size_t o_ops = pk.add(ops), o_geo = pk.add(geo), o_c1d = pk.add(c1d);
+    const size_t o_ft = pk.add(h.ftype), o_nb = pk.add(h.fnb), o_lv = pk.add(level);
+    const size_t o_xs = pk.add(h.xfer_src), o_xk = pk.add(h.xfer_kind);
+    const size_t upload_bytes = pk.host.size();
     m->red_len = (int64_t)budget_blocks(K) * 8 + 8;
-    HIP_TRY(hipMalloc((void**)&m->d_red, sizeof(double) * m->red_len));
-    HIP_TRY(hipMalloc((void**)&m->d_flags, K > 0 ? K : 1));
-    HIP_TRY(hipMalloc((void**)&m->d_eta, sizeof(double) * (K > 0 ? K : 1)));
+    const size_t o_bg = pk.add(nullptr, sizeof(double) * 3 * K * N1);
+    const size_t o_red = pk.add(nullptr, sizeof(double) * m->red_len);
+    const size_t o_eta = pk.add(nullptr, sizeof(double) * (K > 0 ? K : 1));
+    const size_t o_fl = pk.add(nullptr, (size_t)(K > 0 ? K : 1));
+    const size_t total = pk.host.size();
+    HIP_TRY(hipGetDevice(&m->device));
+    char* base = nullptr;
+    HIP_TRY(hipMalloc((void**)&base, total));
+    m->d_base = base;
+    HIP_TRY(hipMemcpy(base, pk.host.data(), upload_bytes, hipMemcpyHostToDevice));
+    m->d_ops = (double*)(base + o_ops);
+    m->d_geo = (double*)(base + o_geo);
+    m->d_c1d = (double*)(base + o_c1d);
+    m->d_ftype = (int32_t*)(base + o_ft);
+    m->d_fnb = (int32_t*)(base + o_nb);
+    m->d_level = (int32_t*)(base + o_lv);
+    m->d_xsrc = (int32_t*)(base + o_xs);
+    m->d_xkind = (int32_t*)(base + o_xk);
+    m->d_bg = (double*)(base + o_bg);
+    m->d_red = (double*)(base + o_red);
+    m->d_eta = (double*)(base + o_eta);
+    m->d_flags = (int8_t*)(base + o_fl);
     m->on_device = true;
     return DG_OK;
 }

@@ -14,30 +14,31 @@
 //   * face tables enumerated by leaf, then face f = 2d + s; conforming faces
 //     from the minus leaf's plus face, hanging faces from the coarse side with
 //     fine leaves by quadrant a + 2b over the tangential axes.
+//
+// Lookups use the sorted leaf array itself: leaves are disjoint and sorted by
+// the key of their lower corner, so the leaf containing a cell (if any) is the
+// last leaf whose key does not exceed the cell's key -- a binary search.
+#include <omp.h>
+
 #include <algorithm>
 #include <cstring>
-#include <unordered_map>
-#include <unordered_set>
 
 #include "internal.hpp"
 
 namespace dgamr {
 namespace {
 
-// packed cell key: root (24 bits) | Morton key at max_level (36 bits) | level (4 bits)
-uint64_t morton(int L, int l, const int32_t a[3]) {
-    uint64_t X = (uint64_t)a[0] << (L - l), Y = (uint64_t)a[1] << (L - l), Z = (uint64_t)a[2] << (L - l);
+// position key of a cell's lower corner: root (24 bits) | Morton key at max_level (36 bits)
+uint64_t pos_key(int L, const Leaf& c) {
+    const uint64_t X = (uint64_t)c.a[0] << (L - c.l), Y = (uint64_t)c.a[1] << (L - c.l),
+                   Z = (uint64_t)c.a[2] << (L - c.l);
     uint64_t k = 0;
     for (int b = 0; b < L; ++b) {
         k |= ((X >> b) & 1ull) << (3 * b);
         k |= ((Y >> b) & 1ull) << (3 * b + 1);
         k |= ((Z >> b) & 1ull) << (3 * b + 2);
     }
-    return k;
-}
-
-uint64_t cell_key(int L, const Leaf& c) {
-    return ((uint64_t)c.r << 40) | (morton(L, c.l, c.a) << 4) | (uint64_t)c.l;
+    return ((uint64_t)c.r << 36) | k;
 }
 
 Leaf parent_of(const Leaf& c) {
@@ -56,21 +57,51 @@ Leaf child_of(const Leaf& c, int id) {
 
 int child_id_of(const Leaf& c) { return (c.a[0] & 1) | ((c.a[1] & 1) << 1) | ((c.a[2] & 1) << 2); }
 
-struct Forest {
+bool same_cell(const Leaf& x, const Leaf& y) {
+    return x.r == y.r && x.l == y.l && x.a[0] == y.a[0] && x.a[1] == y.a[1] && x.a[2] == y.a[2];
+}
+
+// true if leaf x (level <= c.l) is c or an ancestor of c
+bool contains(const Leaf& x, const Leaf& c) {
+    if (x.r != c.r || x.l > c.l) return false;
+    const int sh = c.l - x.l;
+    return (c.a[0] >> sh) == x.a[0] && (c.a[1] >> sh) == x.a[1] && (c.a[2] >> sh) == x.a[2];
+}
+
+// sorted leaf array with its keys
+struct Sorted {
     const dg_forest_desc& desc;
     int L;
-    std::unordered_set<uint64_t> set;
-    explicit Forest(const dg_forest_desc& d) : desc(d), L(d.max_level) {}
+    std::vector<Leaf> leaves;
+    std::vector<uint64_t> keys;
 
-    bool has(const Leaf& c) const { return set.count(cell_key(L, c)) != 0; }
-
-    // leaf equal to c or containing it; returns false if c is refined / absent
-    bool containing(Leaf c, Leaf& out) const {
-        for (;;) {
-            if (has(c)) { out = c; return true; }
-            if (c.l == 0) return false;
-            c = parent_of(c);
+    Sorted(const dg_forest_desc& d, std::vector<Leaf> v) : desc(d), L(d.max_level), leaves(std::move(v)) {
+        std::vector<std::pair<uint64_t, Leaf>> kv(leaves.size());
+        for (size_t i = 0; i < leaves.size(); ++i) kv[i] = {pos_key(L, leaves[i]), leaves[i]};
+        std::sort(kv.begin(), kv.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+        keys.resize(kv.size());
+        for (size_t i = 0; i < kv.size(); ++i) {
+            keys[i] = kv[i].first;
+            leaves[i] = kv[i].second;
         }
+    }
+
+    // index of the leaf equal to or containing cell c, or -1 if c is refined
+    int containing(const Leaf& c) const {
+        const uint64_t k = pos_key(L, c);
+        auto it = std::upper_bound(keys.begin(), keys.end(), k);
+        if (it == keys.begin()) return -1;
+        const int i = (int)(it - keys.begin()) - 1;
+        return contains(leaves[i], c) ? i : -1;
+    }
+
+    // index of the leaf equal to cell c, or -1
+    int find(const Leaf& c) const {
+        const uint64_t k = pos_key(L, c);
+        auto it = std::lower_bound(keys.begin(), keys.end(), k);
+        if (it == keys.end() || *it != k) return -1;
+        const int i = (int)(it - keys.begin());
+        return leaves[i].l == c.l ? i : -1;
     }
 
     // same-level cell across face f = 2d + s; false at a wall
@@ -92,22 +123,18 @@ struct Forest {
         nb.r = rc[0] + desc.nx * (rc[1] + desc.ny * rc[2]);
         return true;
     }
-
-    // the 4 children of c touching its face on `side` of axis d, by quadrant
-    void face_children(const Leaf& c, int d, int side, Leaf out[4]) const {
-        int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-        for (int q = 0; q < 4; ++q) {
-            int bits[3];
-            bits[d] = side;
-            bits[t1] = q & 1;
-            bits[t2] = q >> 1;
-            out[q] = child_of(c, bits[0] | (bits[1] << 1) | (bits[2] << 2));
-        }
-    }
 };
 
-void sort_leaves(int L, std::vector<Leaf>& v) {
-    std::sort(v.begin(), v.end(), [L](const Leaf& x, const Leaf& y) { return cell_key(L, x) < cell_key(L, y); });
+// the 4 children of c touching its face on `side` of axis d, by quadrant
+void face_children(const Leaf& c, int d, int side, Leaf out[4]) {
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    for (int q = 0; q < 4; ++q) {
+        int bits[3];
+        bits[d] = side;
+        bits[t1] = q & 1;
+        bits[t2] = q >> 1;
+        out[q] = child_of(c, bits[0] | (bits[1] << 1) | (bits[2] << 2));
+    }
 }
 
 std::string check_desc(const dg_forest_desc& d) {
@@ -120,30 +147,6 @@ std::string check_desc(const dg_forest_desc& d) {
         if (d.periodic[k] != 0 && d.periodic[k] != 1) return "periodic must be 0 or 1";
     }
     return "";
-}
-
-std::vector<Leaf> to_vector(const Forest& F) {
-    std::vector<Leaf> v;
-    v.reserve(F.set.size());
-    for (uint64_t k : F.set) {
-        Leaf c;
-        c.l = (int)(k & 15ull);
-        c.r = (int)(k >> 40);
-        uint64_t mk = (k >> 4) & ((1ull << 36) - 1);
-        int X = 0, Y = 0, Z = 0;
-        for (int b = 0; b < F.L; ++b) {
-            X |= (int)((mk >> (3 * b)) & 1ull) << b;
-            Y |= (int)((mk >> (3 * b + 1)) & 1ull) << b;
-            Z |= (int)((mk >> (3 * b + 2)) & 1ull) << b;
-        }
-        int sh = F.L - c.l;
-        c.a[0] = X >> sh;
-        c.a[1] = Y >> sh;
-        c.a[2] = Z >> sh;
-        v.push_back(c);
-    }
-    sort_leaves(F.L, v);
-    return v;
 }
 
 }  // namespace
@@ -166,200 +169,205 @@ std::string forest_uniform(const dg_forest_desc& desc, HostMesh& out) {
 std::string forest_refine(const HostMesh& prev, const int8_t* flags, HostMesh& out) {
     const dg_forest_desc& desc = prev.desc;
     const int L = desc.max_level;
-    Forest F(desc);
-    std::unordered_map<uint64_t, int32_t> old_index;
-    old_index.reserve(prev.leaves.size() * 2);
-    for (size_t e = 0; e < prev.leaves.size(); ++e) {
-        old_index[cell_key(L, prev.leaves[e])] = (int32_t)e;
-        F.set.insert(cell_key(L, prev.leaves[e]));
-    }
+    // old leaf index of every leaf of the result that is an old leaf or a child of one
+    std::vector<Leaf> cur;
+    cur.reserve(prev.leaves.size() * 2);
     for (size_t e = 0; e < prev.leaves.size(); ++e) {
         const Leaf& lf = prev.leaves[e];
-        if (flags[e] > 0 && lf.l < L) {
-            F.set.erase(cell_key(L, lf));
-            for (int c = 0; c < 8; ++c) F.set.insert(cell_key(L, child_of(lf, c)));
-        }
+        if (flags[e] > 0 && lf.l < L)
+            for (int c = 0; c < 8; ++c) cur.push_back(child_of(lf, c));
+        else
+            cur.push_back(lf);
     }
     // ripple: refine leaves that have a face neighbour two or more levels finer
     for (;;) {
-        std::vector<Leaf> cur = to_vector(F);
-        std::unordered_set<uint64_t> todo;
-        for (const Leaf& z : cur) {
+        Sorted S(desc, std::move(cur));
+        std::vector<char> todo(S.leaves.size(), 0);
+        int any = 0;
+        const int64_t nl = (int64_t)S.leaves.size();
+#pragma omp parallel for schedule(static) reduction(| : any)
+        for (int64_t zi = 0; zi < nl; ++zi) {
+            const Leaf& z = S.leaves[zi];
             if (z.l < 2) continue;
             for (int f = 0; f < 6; ++f) {
-                Leaf c, x;
-                if (!F.neighbor(z, f, c)) continue;
-                if (F.containing(c, x) && x.l <= z.l - 2) todo.insert(cell_key(L, x));
+                Leaf c;
+                if (!S.neighbor(z, f, c)) continue;
+                const int x = S.containing(c);
+                if (x >= 0 && S.leaves[x].l <= z.l - 2) {
+#pragma omp atomic write
+                    todo[x] = 1;
+                    any = 1;
+                }
             }
         }
-        if (todo.empty()) break;
-        for (const Leaf& z : cur) {
-            uint64_t k = cell_key(L, z);
-            if (!todo.count(k)) continue;
+        if (!any) {
+            cur = std::move(S.leaves);
+            break;
+        }
+        cur.clear();
+        for (size_t i = 0; i < S.leaves.size(); ++i) {
+            const Leaf& z = S.leaves[i];
+            if (!todo[i]) {
+                cur.push_back(z);
+                continue;
+            }
             if (z.l >= L) return "balance would exceed max_level";
-            F.set.erase(k);
-            for (int c = 0; c < 8; ++c) F.set.insert(cell_key(L, child_of(z, c)));
+            for (int c = 0; c < 8; ++c) cur.push_back(child_of(z, c));
         }
     }
     out = HostMesh();
     out.desc = desc;
-    out.leaves = to_vector(F);
+    out.leaves = std::move(cur);  // sorted by the last Sorted pass
     const size_t K = out.leaves.size();
     out.xfer_src.resize(K);
     out.xfer_kind.resize(K);
-    std::unordered_set<int32_t> refined;
-    for (size_t e = 0; e < K; ++e) {
+    Sorted P(desc, prev.leaves);  // prev is sorted already; keys recomputed
+    std::vector<char> refined(prev.leaves.size(), 0);
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int64_t e = 0; e < (int64_t)K; ++e) {
         const Leaf& lf = out.leaves[e];
-        auto it = old_index.find(cell_key(L, lf));
-        if (it != old_index.end()) {
-            out.xfer_src[e] = it->second;
+        const int old = P.find(lf);
+        if (old >= 0) {
+            out.xfer_src[e] = old;
             out.xfer_kind[e] = DG_KIND_COPY;
         } else {
-            auto ip = old_index.find(cell_key(L, parent_of(lf)));
-            if (ip == old_index.end()) return "internal: a leaf was refined twice in one pass";
-            out.xfer_src[e] = ip->second;
+            const int ip = P.find(parent_of(lf));
+            if (ip < 0) {
+                bad = 1;
+                continue;
+            }
+            out.xfer_src[e] = ip;
             out.xfer_kind[e] = child_id_of(lf);
-            refined.insert(ip->second);
+#pragma omp atomic write
+            refined[ip] = 1;
         }
     }
-    out.n_refined = (int64_t)refined.size();
+    if (bad) return "internal: a leaf was refined twice in one pass";
+    out.n_refined = std::count(refined.begin(), refined.end(), 1);
     forest_tables(out);
     return "";
 }
 
 std::string forest_coarsen(const HostMesh& prev, const int8_t* flags, HostMesh& out) {
     const dg_forest_desc& desc = prev.desc;
-    const int L = desc.max_level;
-    Forest F(desc);
-    std::unordered_map<uint64_t, int32_t> idx;
-    idx.reserve(prev.leaves.size() * 2);
-    for (size_t e = 0; e < prev.leaves.size(); ++e) {
-        idx[cell_key(L, prev.leaves[e])] = (int32_t)e;
-        F.set.insert(cell_key(L, prev.leaves[e]));
-    }
-    std::unordered_set<uint64_t> parents, tried;
-    for (size_t e = 0; e < prev.leaves.size(); ++e) {
-        const Leaf& lf = prev.leaves[e];
-        if (lf.l == 0 || flags[e] >= 0) continue;
-        Leaf p = parent_of(lf);
-        uint64_t pk = cell_key(L, p);
-        if (!tried.insert(pk).second) continue;
-        bool all = true;
-        for (int c = 0; c < 8 && all; ++c) {
-            auto it = idx.find(cell_key(L, child_of(p, c)));
-            all = it != idx.end() && flags[it->second] < 0;
+    Sorted P(desc, prev.leaves);
+    const size_t K0 = P.leaves.size();
+    // candidate families: 8 consecutive leaves (Morton order keeps a family
+    // contiguous) that are the 8 children of one parent, all flagged -1
+    std::vector<char> merge(K0, 0);  // 1 at the first child of a family that merges
+    int64_t nmerged = 0;
+    for (size_t e = 0; e + 8 <= K0;) {
+        const Leaf& lf = P.leaves[e];
+        if (lf.l == 0 || child_id_of(lf) != 0) {
+            ++e;
+            continue;
         }
-        if (!all) continue;
+        const Leaf p = parent_of(lf);
+        bool fam = true;
+        for (int c = 0; c < 8 && fam; ++c)
+            fam = same_cell(P.leaves[e + c], child_of(p, c)) && flags[e + c] < 0;
+        if (!fam) {
+            ++e;
+            continue;
+        }
         bool veto = false;
         for (int f = 0; f < 6 && !veto; ++f) {
-            Leaf c, x;
-            if (!F.neighbor(p, f, c)) continue;
-            if (F.containing(c, x)) continue;  // neighbour leaf no finer than the parent
+            Leaf c;
+            if (!P.neighbor(p, f, c)) continue;
+            if (P.containing(c) >= 0) continue;  // neighbour leaf no finer than the parent
             Leaf fc[4];
-            F.face_children(c, f >> 1, 1 - (f & 1), fc);
+            face_children(c, f >> 1, 1 - (f & 1), fc);
             for (int q = 0; q < 4; ++q)
-                if (!F.has(fc[q])) veto = true;
+                if (P.find(fc[q]) < 0) veto = true;
         }
-        if (!veto) parents.insert(pk);
-    }
-    // rebuild the set: remove children of merged parents, add the parents
-    std::vector<Leaf> newv;
-    newv.reserve(prev.leaves.size());
-    std::unordered_set<uint64_t> added;
-    for (size_t e = 0; e < prev.leaves.size(); ++e) {
-        const Leaf& lf = prev.leaves[e];
-        if (lf.l > 0) {
-            Leaf p = parent_of(lf);
-            uint64_t pk = cell_key(L, p);
-            if (parents.count(pk)) {
-                if (added.insert(pk).second) newv.push_back(p);
-                continue;
-            }
+        if (!veto) {
+            merge[e] = 1;
+            ++nmerged;
         }
-        newv.push_back(lf);
+        e += 8;
     }
-    sort_leaves(L, newv);
     out = HostMesh();
     out.desc = desc;
-    out.leaves = newv;
-    const size_t K = newv.size();
-    out.xfer_src.resize(K);
-    out.xfer_kind.resize(K);
-    for (size_t e = 0; e < K; ++e) {
-        const Leaf& lf = newv[e];
-        auto it = idx.find(cell_key(L, lf));
-        if (it != idx.end()) {
-            out.xfer_src[e] = it->second;
-            out.xfer_kind[e] = DG_KIND_COPY;
+    out.leaves.reserve(K0);
+    out.xfer_src.reserve(K0);
+    out.xfer_kind.reserve(K0);
+    for (size_t e = 0; e < K0;) {
+        if (merge[e]) {
+            out.leaves.push_back(parent_of(P.leaves[e]));
+            out.xfer_src.push_back((int32_t)e);
+            out.xfer_kind.push_back(DG_KIND_FAMILY);
+            e += 8;
         } else {
-            out.xfer_src[e] = idx.at(cell_key(L, child_of(lf, 0)));
-            out.xfer_kind[e] = DG_KIND_FAMILY;
+            out.leaves.push_back(P.leaves[e]);
+            out.xfer_src.push_back((int32_t)e);
+            out.xfer_kind.push_back(DG_KIND_COPY);
+            ++e;
         }
     }
-    out.n_coarsened = (int64_t)parents.size();
+    out.n_coarsened = nmerged;
     forest_tables(out);
     return "";
 }
 
 void forest_tables(HostMesh& m) {
     const dg_forest_desc& desc = m.desc;
-    const int L = desc.max_level;
-    Forest F(desc);
-    std::unordered_map<uint64_t, int32_t> idx;
-    idx.reserve(m.leaves.size() * 2);
-    for (size_t e = 0; e < m.leaves.size(); ++e) {
-        uint64_t k = cell_key(L, m.leaves[e]);
-        idx[k] = (int32_t)e;
-        F.set.insert(k);
-    }
-    const size_t K = m.leaves.size();
-    m.conf.clear();
-    m.bnd.clear();
-    m.hang.clear();
+    Sorted S(desc, m.leaves);
+    m.leaves = S.leaves;  // canonical order
+    const int64_t K = (int64_t)m.leaves.size();
     m.ftype.assign(K * 6, -1);
     m.fnb.assign(K * 24, -1);
-    for (size_t e = 0; e < K; ++e) {
+    // per leaf and face: type and neighbours (independent, in parallel)
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < K; ++e) {
         const Leaf& lf = m.leaves[e];
         for (int f = 0; f < 6; ++f) {
             const int d = f >> 1, s = f & 1;
-            Leaf c, x;
-            if (!F.neighbor(lf, f, c)) {
-                m.bnd.push_back((int32_t)e);
-                m.bnd.push_back(f);
+            Leaf c;
+            if (!S.neighbor(lf, f, c)) {
                 m.ftype[e * 6 + f] = FT_WALL;
                 continue;
             }
-            if (F.containing(c, x)) {
-                int32_t nb = idx.at(cell_key(L, x));
-                if (x.l == lf.l) {
-                    if (s == 1) {
-                        m.conf.push_back((int32_t)e);
-                        m.conf.push_back(nb);
-                        m.conf.push_back(d);
-                    }
+            const int x = S.containing(c);
+            if (x >= 0) {
+                if (S.leaves[x].l == lf.l) {
                     m.ftype[e * 6 + f] = FT_CONF;
-                    m.fnb[(e * 6 + f) * 4] = nb;
                 } else {
                     // this leaf is the fine side: quadrant from its tangential anchor bits
-                    int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-                    int q = (lf.a[t1] & 1) | ((lf.a[t2] & 1) << 1);
+                    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+                    const int q = (lf.a[t1] & 1) | ((lf.a[t2] & 1) << 1);
                     m.ftype[e * 6 + f] = FT_FINE | (q << 8);
-                    m.fnb[(e * 6 + f) * 4] = nb;
                 }
+                m.fnb[(e * 6 + f) * 4] = x;
             } else {
                 Leaf fc[4];
-                F.face_children(c, d, 1 - s, fc);
-                m.hang.push_back((int32_t)e);
-                m.hang.push_back(f);
+                face_children(c, d, 1 - s, fc);
                 m.ftype[e * 6 + f] = FT_COARSE;
-                for (int q = 0; q < 4; ++q) {
-                    int32_t ef = idx.at(cell_key(L, fc[q]));
-                    m.hang.push_back(ef);
-                    m.fnb[(e * 6 + f) * 4 + q] = ef;
-                }
+                for (int q = 0; q < 4; ++q) m.fnb[(e * 6 + f) * 4 + q] = S.find(fc[q]);  // leaves, by balance
             }
         }
     }
+    // the global lists in (leaf, face) order
+    m.conf.clear();
+    m.bnd.clear();
+    m.hang.clear();
+    for (int64_t e = 0; e < K; ++e)
+        for (int f = 0; f < 6; ++f) {
+            const int type = m.ftype[e * 6 + f] & 0xff;
+            const int32_t* nb = &m.fnb[(e * 6 + f) * 4];
+            if (type == FT_WALL) {
+                m.bnd.push_back((int32_t)e);
+                m.bnd.push_back(f);
+            } else if (type == FT_CONF && (f & 1)) {
+                m.conf.push_back((int32_t)e);
+                m.conf.push_back(nb[0]);
+                m.conf.push_back(f >> 1);
+            } else if (type == FT_COARSE) {
+                m.hang.push_back((int32_t)e);
+                m.hang.push_back(f);
+                for (int q = 0; q < 4; ++q) m.hang.push_back(nb[q]);
+            }
+        }
 }
 
 void leaf_geometry(const dg_forest_desc& desc, const Leaf& lf, const std::vector<double>& xi, double h[3],

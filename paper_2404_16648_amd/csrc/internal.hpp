@@ -53,6 +53,7 @@ struct dg_mesh {
     uint64_t id = 0, prev_id = 0;
     bool on_device = false;
     int device = 0;
+    char* d_base = nullptr;       // the one device allocation holding everything below
     // device tables
     double* d_ops = nullptr;      // D, I0, I1, R0, R1 ([N1][N1] each), w [N1]
     double* d_geo = nullptr;      // [K][4]: 2/hx, 2/hy, 2/hz, hx*hy*hz/8
