@@ -635,7 +635,8 @@ __device__ __forceinline__ void own_flux_vjp(const double q[5], const Bg& b, dou
 template <int N>
 struct AdjLds {
     static constexpr int NF = Sz<N>::NF;
-    static constexpr int SCR = 30 * NF;  // sT, sT2 [5][NF] each + sM [4][5][NF]
+    // sT, sT2 [5][NF] each, sU [20][NF], sMq [40][NF], sG [10][NF]
+    static constexpr int SCR = 80 * NF;
 };
 
 // the adjoint keeps more state per node; bound it less tightly than the forward
@@ -659,7 +660,6 @@ k_adjoint(const AdjArgs A) {
     __shared__ int sNb[24];
     double* const sT = sX;             // q trace
     double* const sT2 = sX + 5 * NF;   // lambda trace
-    double* const sM = sX + 10 * NF;   // [4][5][NF]
     // operator offsets in sOps: D 0, I_a (1+a), R_a (3+a), w 5, I_a^T after w, R_a^T
     const double* D = sOps;
     auto IT = [&](int a) { return sOps + 5 * NF + N1 + a * NF; };
@@ -743,7 +743,10 @@ k_adjoint(const AdjArgs A) {
         });
     }
 
-    // ---- hanging faces
+    // ---- hanging faces (separable two-pass tensor products, all threads busy)
+    double* const sU = sX + 10 * NF;   // [20][NF]
+    double* const sMq = sX + 30 * NF;  // [40][NF]
+    double* const sG = sX + 70 * NF;   // [10][NF]
 #pragma unroll 1
     for (int f = 0; f < 6; ++f) {
         const int type = sType[f] & 0xff;
@@ -763,6 +766,13 @@ k_adjoint(const AdjArgs A) {
                 sT2[it] = ls[off];
             }
             __syncthreads();
+            // planes 0..4: mortar state (I_a x I_b) q_c; 5..9: (R_a^T x R_b^T) lam_c
+            apply_t1<N>(sT, sU, 10, [&](int p) { return p < 5 ? sOps + (1 + qa) * NF : RT(qa); },
+                        [](int p) { return p; }, t, NT);
+            __syncthreads();
+            apply_t2<N>(sU, sMq, 10, [&](int p) { return p < 5 ? sOps + (1 + qb) * NF : RT(qb); },
+                        [](int p) { return p; }, t, NT);
+            __syncthreads();
             for (int m = t; m < NF; m += NT) {
                 const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
                 const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
@@ -771,8 +781,8 @@ k_adjoint(const AdjArgs A) {
                 for (int v = 0; v < 5; ++v) {
                     qL[v] = qe[v * KNP + n];
                     lL[v] = sL[v * NP + n];
-                    qM[v] = tensor2<N>(sT + v * NF, sOps + (1 + qa) * NF, sOps + (1 + qb) * NF, m);
-                    w[v] = -lift * lL[v] + liftcoarse * tensor2<N>(sT2 + v * NF, RT(qa), RT(qb), m);
+                    qM[v] = sMq[v * NF + m];
+                    w[v] = -lift * lL[v] + liftcoarse * sMq[(5 + v) * NF + m];
                 }
                 const double PpM = pprime(qM[4], b.Th, b.P, gamma, A.binom);
                 with_axis(f >> 1, [&](auto dc) {
@@ -783,7 +793,6 @@ k_adjoint(const AdjArgs A) {
 #pragma unroll
                 for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = g[v];
             }
-            __syncthreads();
         } else {
             __syncthreads();
             for (int it = t; it < 5 * NF; it += NT) {
@@ -793,8 +802,17 @@ k_adjoint(const AdjArgs A) {
                 sT2[it] = sL[v * NP + n];
             }
             __syncthreads();
+            // sU plane a*10 + c: along t1 with I_a (c < 5, state) or R_a^T (c >= 5, lambda)
+            apply_t1<N>(sT, sU, 20, [&](int p) { return (p % 10) < 5 ? sOps + (1 + p / 10) * NF : RT(p / 10); },
+                        [](int p) { return p % 10; }, t, NT);
+            __syncthreads();
+            // sMq plane quad*10 + c, quad = a + 2b: along t2 with I_b or R_b^T
+            apply_t2<N>(sU, sMq, 40,
+                        [&](int p) { return (p % 10) < 5 ? sOps + (1 + (p / 10) / 2) * NF : RT((p / 10) / 2); },
+                        [](int p) { return ((p / 10) & 1) * 10 + p % 10; }, t, NT);
+            __syncthreads();
             for (int it = t; it < 4 * NF; it += NT) {
-                const int quad = it / NF, m = it % NF, qa = quad & 1, qb = quad >> 1;
+                const int quad = it / NF, m = it % NF;
                 const int ef = sNb[f * 4 + quad];
                 const int nn = face_node<N>(fo, m), kn = face_k<N>(fo, m);
                 const double liftf = A.geo[ef * 4 + (f >> 1)] * liftc;
@@ -802,9 +820,9 @@ k_adjoint(const AdjArgs A) {
                 double qM[5], qF[5], w[5], g[5];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
-                    qM[v] = tensor2<N>(sT + v * NF, sOps + (1 + qa) * NF, sOps + (1 + qb) * NF, m);
+                    qM[v] = sMq[(quad * 10 + v) * NF + m];
                     qF[v] = qs[v * KNP + ef * NP + nn];
-                    w[v] = -lift * tensor2<N>(sT2 + v * NF, RT(qa), RT(qb), m) + liftf * ls[v * KNP + ef * NP + nn];
+                    w[v] = -lift * sMq[(quad * 10 + 5 + v) * NF + m] + liftf * ls[v * KNP + ef * NP + nn];
                 }
                 const double PpM = pprime(qM[4], b.Th, b.P, gamma, A.binom);
                 const double PpF = pprime(qF[4], b.Th, b.P, gamma, A.binom);
@@ -812,7 +830,35 @@ k_adjoint(const AdjArgs A) {
                     rusanov_vjp<decltype(dc)::value>(qM, b, PpM, qF, b, PpF, sgn, gamma, w, g, nullptr);
                 });
 #pragma unroll
-                for (int v = 0; v < 5; ++v) sM[(quad * 5 + v) * NF + m] = g[v];
+                for (int v = 0; v < 5; ++v) sMq[(quad * 10 + v) * NF + m] = g[v];  // in place
+            }
+            __syncthreads();
+            // back to the coarse face: sum_ab (I_a^T x I_b^T) gbar_ab, first along t1 then t2
+            for (int it = t; it < 10 * NF; it += NT) {
+                const int p = it / NF, r = it % NF, bb = r / N1, a2 = r % N1;
+                const int qb = p / 5, v = p % 5;
+                double acc = 0.0;
+#pragma unroll
+                for (int qa = 0; qa < 2; ++qa) {
+                    const double* Op = IT(qa) + a2 * N1;
+                    const double* x = sMq + ((qa + 2 * qb) * 10 + v) * NF + bb * N1;
+#pragma unroll
+                    for (int a = 0; a < N1; ++a) acc = fma(Op[a], x[a], acc);
+                }
+                sG[it] = acc;
+            }
+            __syncthreads();
+            for (int it = t; it < 5 * NF; it += NT) {
+                const int v = it / NF, m = it % NF, b2 = m / N1, a = m % N1;
+                double acc = 0.0;
+#pragma unroll
+                for (int qb = 0; qb < 2; ++qb) {
+                    const double* Op = IT(qb) + b2 * N1;
+                    const double* x = sG + (qb * 5 + v) * NF + a;
+#pragma unroll
+                    for (int bb = 0; bb < N1; ++bb) acc = fma(Op[bb], x[bb * N1], acc);
+                }
+                sU[it] = acc;
             }
             __syncthreads();
             for (int m = t; m < NF; m += NT) {
@@ -823,11 +869,7 @@ k_adjoint(const AdjArgs A) {
                 for (int v = 0; v < 5; ++v) {
                     qL[v] = qe[v * KNP + n];
                     lL[v] = sL[v * NP + n];
-                    double acc = 0.0;
-#pragma unroll 1
-                    for (int quad = 0; quad < 4; ++quad)
-                        acc += tensor2<N>(sM + (quad * 5 + v) * NF, IT(quad & 1), IT(quad >> 1), m);
-                    g[v] = acc;
+                    g[v] = sU[v * NF + m];
                 }
                 with_axis(f >> 1, [&](auto dc) {
                     own_flux_vjp<decltype(dc)::value>(qL, b, sPp[n], sgn, gamma, lift, lL, g);
@@ -835,7 +877,6 @@ k_adjoint(const AdjArgs A) {
 #pragma unroll
                 for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = g[v];
             }
-            __syncthreads();
         }
     }
     __syncthreads();
