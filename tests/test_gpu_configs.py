@@ -1,0 +1,154 @@
+"""Full-size GPU checks of the remaining workloads against the oracle:
+
+* density current (25.6 x 1.6 x 6.4 km, 64 x 4 x 16 base hexes, N = 4, two levels on
+  |grad theta| > 1e-3 K/m): mesh built from the same flags bit-exact, RHS and one
+  SSP-RK3 step in float64, RHS in the precision split, the library's own flags;
+* AMR warm bubble, forced adaptation cycle: coarsen every finest family, project,
+  refine them back, project -- meshes bit-exact, fields to 1e-12;
+* adjoint configuration (16^3 hexes, N = 4, 50 SSP-RK3 steps, checkpoints every 10):
+  gradient of J = integral of theta'^2 over a 200 m box against central differences
+  (eps = 1e-6) on 20 seeded directions.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import euler as eu
+from oracle import forest as fo
+from paper_2404_16648_amd import adjoint as adj
+from paper_2404_16648_amd import dg
+from paper_2404_16648_amd.synth import random_direction
+from tests.helpers import TOL_FP64, field_errors, oracle_phys, tables_equal, to_nodes
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def gpu(t):
+    return t.to(DEV).contiguous()
+
+
+def check(a, b, tol, what):
+    err = field_errors(a, to_nodes(b))
+    print(what, ["%.2e" % x for x in err], flush=True)
+    assert max(err) <= tol, (what, err)
+
+
+def adapt_both(N, nroot, L, lo, hi, state_fn, kind, thr):
+    """Uniform level 0, then (oracle IC -> oracle flags -> refine pass) on both sides."""
+    ph = dg.PhysParams()
+    od = fo.ForestDesc(N, *nroot, L, lo, hi, (0, 0, 0))
+    om = fo.build(od, None)
+    lm = dg.dg_mesh_build(N, nroot, L, lo, hi)
+    for _ in range(L):
+        op = eu.Operator(om, oracle_phys(ph))
+        fl = eu.flags_from_indicator(om, eu.indicator(op, state_fn(op), kind).numpy(), thr)
+        fl[fl < 0] = 0
+        if not (fl > 0).any():
+            break
+        om = fo.build(od, om, fl, fo.PASS_REFINE)
+        lm = dg.dg_mesh_build(prev=lm, flags=fl, pass_=dg.DG_PASS_REFINE)
+        lm.prev = None
+    assert tables_equal(lm.tables(), om)
+    return lm, om
+
+
+def test_density_current_full_size():
+    lo, hi = (0.0, 0.0, 0.0), (25600.0, 1600.0, 6400.0)
+    lm, om = adapt_both(4, (64, 4, 16), 2, lo, hi, eu.density_current_state, eu.IND_GRAD_THETA, 1e-3)
+    print("density current: leaves", om.K, "hanging faces", len(om.hang), flush=True)
+    assert om.K > 20000 and len(om.hang) > 0
+    ph = dg.PhysParams()
+    op = eu.Operator(om, oracle_phys(ph))
+    qo = eu.density_current_state(op)
+    # the library's own initial state and flags
+    ql = lm.field()
+    dg.dg_init_bell(lm, ph, ql, -15.0, (0.0, 800.0, 3000.0), (4000.0, 0.0, 2000.0))
+    check(ql, qo, TOL_FP64, "density current IC")
+    eta_o = eu.indicator(op, qo, eu.IND_GRAD_THETA).numpy()
+    fl = dg.dg_indicator(lm, ph, ql, dg.DG_IND_GRAD_THETA, 1e-3)
+    tie = np.abs(eta_o - 1e-3) <= 1e-9 * 1e-3
+    assert np.array_equal(fl[~tie], eu.flags_from_indicator(om, eta_o, 1e-3)[~tie])
+    q = gpu(to_nodes(qo))
+    R = lm.field()
+    dg.dg_rhs(lm, ph, q, R)
+    Ro = op.rhs(qo)
+    check(R, Ro, TOL_FP64, "density current rhs")
+    dg.dg_rhs(lm, dg.PhysParams(precision=dg.DG_MIXED), q, R)
+    check(R, Ro, 1e-5, "density current rhs (precision split)")
+    q1, q2 = lm.field(), lm.field()
+    dg.ssp_rk3_step(lm, ph, 0.01, q, q1, q2)
+    check(q, eu.ssp_rk3_step(op, 0.01, qo), TOL_FP64, "density current step")
+
+
+def test_bubble_forced_adaptation_cycle():
+    """Coarsen every family of finest leaves, then refine them back, with projections."""
+    lm, om = adapt_both(7, (8, 8, 8), 2, (0.0, 0.0, 0.0), (1000.0, 1000.0, 1000.0), eu.bubble_state,
+                        eu.IND_THETA, 0.1)
+    ph = dg.PhysParams()
+    op = eu.Operator(om, oracle_phys(ph))
+    qo = eu.bubble_state(op)
+    qo = eu.ssp_rk3_step(op, 0.001, qo)
+    lev = om.levels()
+    flc = np.where(lev == 2, -1, 0).astype(np.int8)
+    omc = fo.build(om.desc, om, flc, fo.PASS_COARSEN)
+    lmc = dg.dg_mesh_build(prev=lm, flags=flc, pass_=dg.DG_PASS_COARSEN)
+    assert tables_equal(lmc.tables(), omc) and lmc.info.n_coarsened > 0
+    qc = lmc.field()
+    dg.dg_coarsen_project(lm, lmc, gpu(to_nodes(qo)), qc)
+    qco = eu.coarsen_project(omc, qo)
+    check(qc, qco, TOL_FP64, "forced coarsen")
+    # refine back exactly the merged parents
+    flr = np.where(omc.xfer_kind == fo.KIND_FAMILY, 1, 0).astype(np.int8)
+    omr = fo.build(om.desc, omc, flr, fo.PASS_REFINE)
+    lmr = dg.dg_mesh_build(prev=lmc, flags=flr, pass_=dg.DG_PASS_REFINE)
+    assert tables_equal(lmr.tables(), omr)
+    assert omr.leaves == om.leaves
+    qr = lmr.field()
+    dg.dg_refine_project(lmc, lmr, qc, qr)
+    check(qr, eu.refine_project(omr, qco), TOL_FP64, "forced refine")
+    # integrals of every variable survive the round trip (budgets in the library)
+    b0 = dg.dg_budgets(lm, ph, gpu(to_nodes(qo)))
+    b1 = dg.dg_budgets(lmr, ph, qr)
+    assert abs(b1[0] - b0[0]) <= 1e-12 * abs(b0[0])
+    assert abs(b1[2] - b0[2]) <= 1e-12 * max(abs(b0[2]), 1e-300) + 1e-18
+
+
+def test_adjoint_config_gradient_20_directions():
+    ph = dg.PhysParams()
+    desc = fo.ForestDesc(4, 16, 16, 16, 0, (0.0, 0.0, 0.0), (1000.0, 1000.0, 1000.0), (0, 0, 0))
+    om = fo.build(desc, None)
+    lm = dg.dg_mesh_build(4, (16, 16, 16), 0, (0.0, 0.0, 0.0), (1000.0, 1000.0, 1000.0))
+    assert tables_equal(lm.tables(), om)
+    op = eu.Operator(om, oracle_phys(ph))
+    X, Y, Z = eu.node_xyz(om)
+    mask = ((X >= 400) & (X <= 600) & (Y >= 400) & (Y <= 600) & (Z >= 250) & (Z <= 450)).double()
+    wm = gpu(to_nodes((eu.quad_weights(op) * mask)[None])[0])
+    rb = gpu(to_nodes(op.bg[0][None])[0])
+    tb = gpu(to_nodes(op.bg[1][None])[0])
+
+    def J(q):
+        thp = (tb + q[4]) / (rb + q[0]) - tb / rb
+        return (wm * thp * thp).sum()
+
+    q0 = lm.field()
+    dg.dg_init_bell(lm, ph, q0, 2.0, (500.0, 500.0, 350.0), (250.0, 250.0, 250.0))
+    dt, nsteps = 0.005, 50
+    x = q0.clone().requires_grad_(True)
+    (g,) = torch.autograd.grad(J(adj.integrate(x, lm, ph, dt, nsteps, 10)), x)
+
+    def Jonly(y):
+        with torch.no_grad():
+            return float(J(adj.integrate(y, lm, ph, dt, nsteps, nsteps)))
+
+    eps = 1e-6
+    worst = 0.0
+    for k in range(1, 21):
+        d = gpu(torch.as_tensor(random_direction(om.K, 4, k)))
+        fd = (Jonly(q0 + eps * d) - Jonly(q0 - eps * d)) / (2 * eps)
+        ad = float((g * d).sum())
+        rel = abs(fd - ad) / max(abs(fd), abs(ad))
+        worst = max(worst, rel)
+        assert rel <= 1e-6, (k, fd, ad)
+    print("adjoint configuration: worst FD relative gap over 20 directions", worst, flush=True)
