@@ -25,6 +25,39 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_STAGE_FIRST = 80.0       # per node: read qs (40 B), write qout (40 B); a = 0
 BYTES_STAGE = 120.0            # per node: read q0 and qs, write qout
+STAGE_KERNEL = "k_stage<7, 1, false>"
+
+# Bytes beyond L2 per launch of the fused stage over the timed steps of the
+# default workload, from two counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch), each scaled by the ratio of the bytes a plain device copy of known
+# size moves to what the same counter reads for it.  Valid only for the kernel
+# sources they were taken on (SHA-256 of the files below); otherwise traffic is
+# reported as null.
+TRAFFIC = {
+    "sources_sha256": "2ab4fbb4374ce77f32935b16df20727622b2278cad0e88dec4514b8a08cbe701",
+    "fetch_kib_per_launch": 66473.7,    # mean over the 90 timed launches
+    "write_kib_per_launch": 67360.0,
+    "fetch_scale": 1048576.0 / 524302.5,  # 1 GiB copy: FETCH_SIZE reads 524302.5 KiB
+    "write_scale": 1048576.0 / 1048576.0,  # 1 GiB copy: WRITE_SIZE reads 1048576.0 KiB
+}
+KERNEL_SOURCES = ("paper_2404_16648_amd/csrc/kernels.hip", "paper_2404_16648_amd/csrc/kernels.hpp",
+                  "paper_2404_16648_amd/csrc/facetypes.hpp")
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_bytes_per_launch():
+    t = TRAFFIC
+    if t["sources_sha256"] is None or t["sources_sha256"] != kernel_sources_sha256():
+        return None
+    return 1024.0 * (t["fetch_kib_per_launch"] * t["fetch_scale"] + t["write_kib_per_launch"] * t["write_scale"])
 
 
 def parse():
@@ -35,6 +68,9 @@ def parse():
     ap.add_argument("--adapt-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, run 4 plain device copies of MIB MiB each "
+                         "(reference launches for the memory-traffic counters)")
     return ap.parse_args()
 
 
@@ -106,6 +142,18 @@ def main():
     dofs_per_s = state["dofs"] / (total_ms * 1e-3)
     m = state["mesh"]
     budgets = dg.dg_budgets(m, ph, state["q"])
+    calib = None
+    if args.copy_calibration > 0:
+        nb = args.copy_calibration << 20
+        src = torch.ones(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        calib = {"bytes_per_copy": nb, "copies": 4}
+        del src, dst
+    alg_bytes = stage_bytes / max(1, len(events))
+    traffic = traffic_bytes_per_launch()
 
     result = {
         "metric": "DG RHS DOF-updates/s (FP64)",
@@ -125,12 +173,16 @@ def main():
                    "leaves": m.K, "nodes": m.K * m.Np, "hanging_faces": int(m.info.n_hang),
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_stage (fused volume+faces+mortars+lift+RK stage)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "B/launch", "algorithmic_bytes_per_launch": alg_bytes,
+                     "traffic_over_algorithmic": None if traffic is None else traffic / alg_bytes,
+                     "kernel": STAGE_KERNEL + " (fused volume+faces+mortars+lift+RK stage)",
                      "avg_launch_us": 1e3 * stage_ms / max(1, len(events))},
         "wall_s": wall,
         "mass_prime_final": budgets[0],
     }
+    if calib is not None:
+        result["copy_calibration"] = calib
     if not args.no_extras:
         result["extras"] = extras(dg, torch, state["mesh"], state["q"], ph, dt, 1e3 * stage_ms / len(events))
     if not args.no_cpu_baseline:

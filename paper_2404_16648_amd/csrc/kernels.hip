@@ -70,6 +70,10 @@ __device__ __forceinline__ int face_k(int f, int m) {
 // (Horner; truncation below 1e-17 relative), else expm1(gamma log1p(x)).
 constexpr int kBinomTerms = 10;
 
+// |x| > 2^-7: kept out of line, so that the constants of expm1 and log1p are not
+// held in registers across the face loops of the kernels that inline pprime
+__device__ __attribute__((noinline)) double pow1p_m1(double x, double gamma) { return expm1(gamma * log1p(x)); }
+
 __device__ __forceinline__ double pprime(double Thp, double Thb, double Pb, double gamma, const BinomCoef& bc) {
     const double x = Thp / Thb;
     double r;
@@ -79,7 +83,7 @@ __device__ __forceinline__ double pprime(double Thp, double Thb, double Pb, doub
         for (int k = kBinomTerms - 2; k >= 0; --k) acc = fma(acc, x, bc.c[k]);
         r = acc * x;
     } else {
-        r = expm1(gamma * log1p(x));
+        r = pow1p_m1(x, gamma);
     }
     return Pb * r;
 }
@@ -180,24 +184,35 @@ __device__ __forceinline__ void apply_t2(const double* in, double* out, int np, 
     }
 }
 
-// waves per SIMD the stage kernel is compiled for (bounds the VGPR budget)
+// waves per SIMD the stage kernel is compiled for (bounds the VGPR budget to 128)
 template <int N>
 struct StageOcc {
-    static constexpr int W = N >= 6 ? 4 : 3;
+    static constexpr int W = 4;
 };
 
 // LDS plan of the stage kernel: the work area holds first the face scratch (a
 // trace sT[5][NF] and the mortar fluxes sM[4][5][NF], doubles) and then the flux
-// planes of the volume phase: all 15 at once when they fit, else x and y, then z.
-// MIX stores the planes as float (flux minus an element-constant reference).
+// planes of the volume phase: all 15 at once, or x and y, then z (one more
+// barrier).  All 15 only when that keeps as many workgroups per CU (160 KB of
+// LDS, W waves per SIMD) as the two-pass plan.  MIX stores the planes as float
+// (flux minus an element-constant reference).
 template <int N, bool MIX>
 struct StageLds {
-    static constexpr int NP = Sz<N>::NP, NF = Sz<N>::NF;
+    static constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF;
     static constexpr int ESZ = MIX ? 4 : 8;
-    static constexpr bool ALL3 = (15 * NP * ESZ + 30 * NF * 8) <= 64 * 1024;
+    static constexpr int work_dbl(int planes) {
+        return (planes * NP * ESZ + 7) / 8 > 45 * NF ? (planes * NP * ESZ + 7) / 8 : 45 * NF;
+    }
+    // bytes of the other LDS arrays of k_stage
+    static constexpr int FIXED = 8 * (30 * NF + NP + Sz<N>::NOPS + 3 * N1) + 4 * 2 * N1 * N1 + 4 * 30;
+    static constexpr int blocks(int planes) {
+        const int by_lds = 160 * 1024 / (FIXED + 8 * work_dbl(planes));
+        const int by_waves = 4 * StageOcc<N>::W / (Sz<N>::NT / 64);
+        return by_lds < by_waves ? by_lds : by_waves;
+    }
+    static constexpr bool ALL3 = FIXED + 8 * work_dbl(15) <= 64 * 1024 && blocks(15) >= blocks(10);
     static constexpr int PLANES = ALL3 ? 15 : 10;
-    static constexpr int PLANE_DBL = (PLANES * NP * ESZ + 7) / 8;
-    static constexpr int WORK = PLANE_DBL > 45 * NF ? PLANE_DBL : 45 * NF;
+    static constexpr int WORK = work_dbl(PLANES);
 };
 
 // MIX: the volume contractions in float32 on the flux minus the flux at the
