@@ -5,6 +5,8 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -34,6 +36,16 @@ dg_status hip_fail(hipError_t e, const char* where) {
         if (e_ != hipSuccess) return hip_fail(e_, #call);        \
     } while (0)
 
+// reference operators per N, computed once per process
+RefOps refops_cached(int N) {
+    static std::mutex mu;
+    static std::map<int, RefOps> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(N);
+    if (it == cache.end()) it = cache.emplace(N, make_refops(N)).first;
+    return it->second;
+}
+
 void free_device(dg_mesh* m) {
     if (m->d_base) (void)hipFree(m->d_base);
     m->d_base = nullptr;
@@ -42,20 +54,53 @@ void free_device(dg_mesh* m) {
     m->d_flags = nullptr;
 }
 
-// packs host arrays into one staging buffer at 256-byte aligned offsets
-struct Packer {
-    std::vector<char> host;
-    size_t add(const void* src, size_t bytes) {
-        const size_t off = (host.size() + 255) & ~(size_t)255;
-        host.resize(off + bytes);
-        if (src && bytes) std::memcpy(host.data() + off, src, bytes);
-        return off;
-    }
-    template <typename T>
-    size_t add(const std::vector<T>& v) {
-        return add(v.data(), v.size() * sizeof(T));
-    }
+// byte offsets of the arrays in a mesh's one device block, 256-byte aligned;
+// [0, upload) is copied from the host, the rest is device workspace
+struct DevLayout {
+    size_t ops, geo, c1d, ft, nb, lv, xs, xk, upload, bg, red, eta, fl, total;
 };
+
+DevLayout dev_layout(int64_t K, int N, int64_t red_len) {
+    const size_t N1 = (size_t)N + 1, k = (size_t)K;
+    size_t end = 0;
+    auto take = [&](size_t bytes) {
+        const size_t off = (end + 255) & ~(size_t)255;
+        end = off + bytes;
+        return off;
+    };
+    DevLayout L{};
+    L.ops = take(sizeof(double) * (9 * N1 * N1 + N1));
+    L.geo = take(sizeof(double) * 4 * k);
+    L.c1d = take(sizeof(double) * 3 * k * N1);
+    L.ft = take(sizeof(int32_t) * 6 * k);
+    L.nb = take(sizeof(int32_t) * 24 * k);
+    L.lv = take(sizeof(int32_t) * k);
+    L.xs = take(sizeof(int32_t) * k);
+    L.xk = take(sizeof(int32_t) * k);
+    L.upload = end;
+    L.bg = take(sizeof(double) * 3 * k * N1);
+    L.red = take(sizeof(double) * (size_t)red_len);
+    L.eta = take(sizeof(double) * (k > 0 ? k : 1));
+    L.fl = take(k > 0 ? k : 1);
+    L.total = end;
+    return L;
+}
+
+void set_device_pointers(dg_mesh* m, char* base, const DevLayout& L) {
+    m->d_base = base;
+    m->d_ops = (double*)(base + L.ops);
+    m->d_geo = (double*)(base + L.geo);
+    m->d_c1d = (double*)(base + L.c1d);
+    m->d_ftype = (int32_t*)(base + L.ft);
+    m->d_fnb = (int32_t*)(base + L.nb);
+    m->d_level = (int32_t*)(base + L.lv);
+    m->d_xsrc = (int32_t*)(base + L.xs);
+    m->d_xkind = (int32_t*)(base + L.xk);
+    m->d_bg = (double*)(base + L.bg);
+    m->d_red = (double*)(base + L.red);
+    m->d_eta = (double*)(base + L.eta);
+    m->d_flags = (int8_t*)(base + L.fl);
+}
 
 // every face of every leaf has a type and in-range neighbours (the kernels index
 // field arrays with them); checked on the host before anything is uploaded
@@ -74,26 +119,61 @@ bool tables_consistent(const HostMesh& h) {
     return true;
 }
 
+// A pass that changed no leaf leaves every table as it was: the device block is
+// cloned from the previous mesh's (and its background, when computed), and only
+// the identity transfer plan is uploaded.
+dg_status clone_device(dg_mesh* m, const dg_mesh* prev) {
+    const HostMesh& h = m->h;
+    const int64_t K = (int64_t)h.leaves.size();
+    m->red_len = prev->red_len;
+    const DevLayout L = dev_layout(K, h.desc.N, m->red_len);
+    HIP_TRY(hipSetDevice(prev->device));
+    m->device = prev->device;
+    char* base = nullptr;
+    HIP_TRY(hipMalloc((void**)&base, L.total));
+    set_device_pointers(m, base, L);
+    HIP_TRY(hipMemcpy(base, prev->d_base, L.xs, hipMemcpyDeviceToDevice));
+    std::vector<int32_t> xfer(2 * (size_t)K);
+    std::memcpy(xfer.data(), h.xfer_src.data(), sizeof(int32_t) * K);
+    std::memcpy(xfer.data() + K, h.xfer_kind.data(), sizeof(int32_t) * K);
+    HIP_TRY(hipMemcpy(base + L.xs, xfer.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(base + L.xk, xfer.data() + K, sizeof(int32_t) * K, hipMemcpyHostToDevice));
+    if (prev->bg_valid) {
+        HIP_TRY(hipMemcpy(m->d_bg, prev->d_bg, sizeof(double) * 3 * K * (h.desc.N + 1), hipMemcpyDeviceToDevice));
+        m->bg_phys = prev->bg_phys;
+        m->bg_valid = true;
+    }
+    m->on_device = true;
+    return DG_OK;
+}
+
 dg_status build_device(dg_mesh* m) {
     const HostMesh& h = m->h;
     const int64_t K = (int64_t)h.leaves.size();
     if (!tables_consistent(h)) return fail(DG_EINVAL, "internal: inconsistent face tables");
     if (5 * K * (int64_t)(h.desc.N + 1) * (h.desc.N + 1) * (h.desc.N + 1) >= ((int64_t)1 << 31))
         return fail(DG_EINVAL, "mesh too large: 5 K Np must stay below 2^31");
+    if (h.same_as_prev && m->prev && m->prev->on_device && m->prev->h.leaves.size() == h.leaves.size())
+        return clone_device(m, m->prev);
     const int N = h.desc.N, N1 = N + 1;
+    m->red_len = (int64_t)budget_blocks(K) * 8 + 8;
+    const DevLayout L = dev_layout(K, N, m->red_len);
+    // one staging buffer and one copy for every table of the mesh; the background,
+    // reduction and flag buffers are carved from the same block
+    std::vector<char> up(L.upload, 0);
     // D, I0, I1, R0, R1 ([N1][N1] row-major), w [N1], then I0^T, I1^T, R0^T, R1^T (adjoint)
-    std::vector<double> ops;
+    double* ops = (double*)(up.data() + L.ops);
     for (auto* v : {&m->ops.D, &m->ops.I0, &m->ops.I1, &m->ops.R0, &m->ops.R1, &m->ops.w})
-        ops.insert(ops.end(), v->begin(), v->end());
+        for (double x : *v) *ops++ = x;
     for (auto* v : {&m->ops.I0, &m->ops.I1, &m->ops.R0, &m->ops.R1})
         for (int c = 0; c < N1; ++c)
-            for (int r = 0; r < N1; ++r) ops.push_back((*v)[r * N1 + c]);
-    std::vector<double> geo(K * 4), c1d(3 * K * N1);
-    std::vector<int32_t> level(K);
-    std::vector<double> c(3 * N1);
+            for (int r = 0; r < N1; ++r) *ops++ = (*v)[r * N1 + c];
+    double* geo = (double*)(up.data() + L.geo);
+    double* c1d = (double*)(up.data() + L.c1d);
+    int32_t* level = (int32_t*)(up.data() + L.lv);
     for (int64_t e = 0; e < K; ++e) {
-        double hh[3];
-        leaf_geometry(h.desc, h.leaves[e], m->ops.x, hh, c.data());
+        double hh[3], c[3 * 8];  // N + 1 <= 8
+        leaf_geometry(h.desc, h.leaves[e], m->ops.x, hh, c);
         for (int d = 0; d < 3; ++d) {
             geo[e * 4 + d] = 2.0 / hh[d];
             for (int j = 0; j < N1; ++j) c1d[(d * K + e) * N1 + j] = c[d * N1 + j];
@@ -101,36 +181,15 @@ dg_status build_device(dg_mesh* m) {
         geo[e * 4 + 3] = hh[0] * hh[1] * hh[2] / 8.0;
         level[e] = h.leaves[e].l;
     }
-    // one device allocation and one copy for every table of the mesh; the
-    // background, reduction and flag buffers are carved from the same block
-    Packer pk;
-    const size_t o_ops = pk.add(ops), o_geo = pk.add(geo), o_c1d = pk.add(c1d);
-    const size_t o_ft = pk.add(h.ftype), o_nb = pk.add(h.fnb), o_lv = pk.add(level);
-    const size_t o_xs = pk.add(h.xfer_src), o_xk = pk.add(h.xfer_kind);
-    const size_t upload_bytes = pk.host.size();
-    m->red_len = (int64_t)budget_blocks(K) * 8 + 8;
-    const size_t o_bg = pk.add(nullptr, sizeof(double) * 3 * K * N1);
-    const size_t o_red = pk.add(nullptr, sizeof(double) * m->red_len);
-    const size_t o_eta = pk.add(nullptr, sizeof(double) * (K > 0 ? K : 1));
-    const size_t o_fl = pk.add(nullptr, (size_t)(K > 0 ? K : 1));
-    const size_t total = pk.host.size();
+    std::memcpy(up.data() + L.ft, h.ftype.data(), sizeof(int32_t) * 6 * K);
+    std::memcpy(up.data() + L.nb, h.fnb.data(), sizeof(int32_t) * 24 * K);
+    std::memcpy(up.data() + L.xs, h.xfer_src.data(), sizeof(int32_t) * K);
+    std::memcpy(up.data() + L.xk, h.xfer_kind.data(), sizeof(int32_t) * K);
     HIP_TRY(hipGetDevice(&m->device));
     char* base = nullptr;
-    HIP_TRY(hipMalloc((void**)&base, total));
-    m->d_base = base;
-    HIP_TRY(hipMemcpy(base, pk.host.data(), upload_bytes, hipMemcpyHostToDevice));
-    m->d_ops = (double*)(base + o_ops);
-    m->d_geo = (double*)(base + o_geo);
-    m->d_c1d = (double*)(base + o_c1d);
-    m->d_ftype = (int32_t*)(base + o_ft);
-    m->d_fnb = (int32_t*)(base + o_nb);
-    m->d_level = (int32_t*)(base + o_lv);
-    m->d_xsrc = (int32_t*)(base + o_xs);
-    m->d_xkind = (int32_t*)(base + o_xk);
-    m->d_bg = (double*)(base + o_bg);
-    m->d_red = (double*)(base + o_red);
-    m->d_eta = (double*)(base + o_eta);
-    m->d_flags = (int8_t*)(base + o_fl);
+    HIP_TRY(hipMalloc((void**)&base, L.total));
+    set_device_pointers(m, base, L);
+    HIP_TRY(hipMemcpy(base, up.data(), L.upload, hipMemcpyHostToDevice));
     m->on_device = true;
     return DG_OK;
 }
@@ -235,7 +294,7 @@ dg_status dg_mesh_build(const dg_forest_desc* desc, const dg_mesh* prev, const i
             delete m;
             return fail(DG_EINVAL, err);
         }
-        m->ops = make_refops(m->h.desc.N);
+        m->ops = refops_cached(m->h.desc.N);
         m->id = g_next_id++;
         if (!m->h.desc.host_only) {
             dg_status st = build_device(m);

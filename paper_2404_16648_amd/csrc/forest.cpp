@@ -76,6 +76,13 @@ struct Sorted {
     std::vector<uint64_t> keys;
 
     Sorted(const dg_forest_desc& d, std::vector<Leaf> v) : desc(d), L(d.max_level), leaves(std::move(v)) {
+        keys.resize(leaves.size());
+        bool sorted = true;
+        for (size_t i = 0; i < leaves.size(); ++i) {
+            keys[i] = pos_key(L, leaves[i]);
+            sorted = sorted && (i == 0 || keys[i - 1] < keys[i]);
+        }
+        if (sorted) return;  // a mesh's own leaves are stored in this order
         std::vector<std::pair<uint64_t, Leaf>> kv(leaves.size());
         for (size_t i = 0; i < leaves.size(); ++i) kv[i] = {pos_key(L, leaves[i]), leaves[i]};
         std::sort(kv.begin(), kv.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
@@ -166,9 +173,25 @@ std::string forest_uniform(const dg_forest_desc& desc, HostMesh& out) {
     return "";
 }
 
+// the result of a pass that changes no leaf: prev's leaves and tables, identity transfer
+static void unchanged(const HostMesh& prev, HostMesh& out) {
+    out = prev;
+    const int64_t K = (int64_t)prev.leaves.size();
+    out.xfer_kind.assign(K, DG_KIND_COPY);
+    for (int64_t e = 0; e < K; ++e) out.xfer_src[e] = (int32_t)e;
+    out.n_refined = out.n_coarsened = 0;
+    out.same_as_prev = true;
+}
+
 std::string forest_refine(const HostMesh& prev, const int8_t* flags, HostMesh& out) {
     const dg_forest_desc& desc = prev.desc;
     const int L = desc.max_level;
+    bool any_flag = false;
+    for (size_t e = 0; e < prev.leaves.size() && !any_flag; ++e) any_flag = flags[e] > 0 && prev.leaves[e].l < L;
+    if (!any_flag) {  // prev is balanced, so the ripple has nothing to do either
+        unchanged(prev, out);
+        return "";
+    }
     // old leaf index of every leaf of the result that is an old leaf or a child of one
     std::vector<Leaf> cur;
     cur.reserve(prev.leaves.size() * 2);
@@ -286,6 +309,10 @@ std::string forest_coarsen(const HostMesh& prev, const int8_t* flags, HostMesh& 
             ++nmerged;
         }
         e += 8;
+    }
+    if (nmerged == 0) {
+        unchanged(prev, out);
+        return "";
     }
     out = HostMesh();
     out.desc = desc;

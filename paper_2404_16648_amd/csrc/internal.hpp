@@ -32,6 +32,7 @@ struct HostMesh {
     std::vector<int32_t> xfer_src, xfer_kind;
     std::vector<int32_t> ftype, fnb;             // [K][6], [K][6][4]
     int64_t n_refined = 0, n_coarsened = 0;
+    bool same_as_prev = false;                   // the pass changed no leaf: tables copied
 };
 
 // forest passes (host, integer work); return "" or an error message

@@ -309,25 +309,26 @@ def adapt_cycle(mesh: Mesh, phys: PhysParams, q, kind, thr, stream=None):
     """One adaptation cycle: indicator -> coarsen pass + projection -> refine
     pass + projection (host control flow; every arithmetic step runs in the
     library).  Parents made by the coarsen pass are not refined in the same
-    cycle.  Returns (new_mesh, new_q)."""
+    cycle.  Returns (new_mesh, new_q); when neither pass changes a leaf, the
+    input mesh and field themselves."""
     import torch
     flags = dg_indicator(mesh, phys, q, kind, thr, stream=stream)
     mc = dg_mesh_build(prev=mesh, flags=flags, pass_=DG_PASS_COARSEN)
     if mc.info.n_coarsened:
         qc = torch.empty(5, mc.K, mc.Np, dtype=torch.float64, device=q.device)
         dg_coarsen_project(mesh, mc, q, qc, stream)
+        t = mc.tables()
+        fl2 = np.where(t["xfer_kind"] == DG_KIND_COPY, flags[t["xfer_src"]], 0).astype(np.int8)
     else:
-        qc = q
-    t = mc.tables()
-    fl2 = np.where(t["xfer_kind"] == DG_KIND_COPY, flags[t["xfer_src"]], 0).astype(np.int8)
+        mc, qc = mesh, q  # identity transfer plan: the flags index the same leaves
+        fl2 = flags.copy()
     fl2[fl2 < 0] = 0
     mr = dg_mesh_build(prev=mc, flags=fl2, pass_=DG_PASS_REFINE)
     if mr.info.n_refined:
         qr = torch.empty(5, mr.K, mr.Np, dtype=torch.float64, device=q.device)
         dg_refine_project(mc, mr, qc, qr, stream)
-    else:
-        qr = qc
-    return mr, qr
+        return mr, qr
+    return mc, qc
 
 
 def initial_mesh(N, nroot, max_level, lo, hi, periodic, phys: PhysParams, bell, kind, thr):
