@@ -91,3 +91,43 @@ def test_forest_tables_match_oracle(ci, seed):
 def test_uniform_config_counts():
     m = dg.dg_mesh_build(4, (16, 16, 16), 0, host_only=True)
     assert (m.K, m.info.n_conf, m.info.n_bnd, m.info.n_hang) == (4096, 11520, 1536, 0)
+
+
+def test_passes_that_change_no_leaf():
+    """A refine pass without an effective flag and a coarsen pass whose only family
+    is vetoed by 2:1 balance keep every leaf and table, with the identity transfer
+    plan, as the oracle's passes do (the library takes its copy path here)."""
+    lo, hi = (0.0, 0.0, 0.0), (1000.0, 1000.0, 1000.0)
+    od = oracle_desc(3, (2, 1, 1), 2, lo, hi, (0, 0, 0))
+    om = fo.build(od, None)
+    lm = dg.dg_mesh_build(3, (2, 1, 1), 2, lo, hi, host_only=True)
+    # refine both roots, then the children of root 1 that touch root 0 (x = 0 side)
+    fl = np.ones(om.K, np.int8)
+    om = fo.build(od, om, fl, fo.PASS_REFINE)
+    lm = dg.dg_mesh_build(prev=lm, flags=fl, pass_=dg.DG_PASS_REFINE)
+    fl = np.array([1 if (lf[0] == 1 and lf[2] == 0) else 0 for lf in om.leaves], np.int8)
+    om = fo.build(od, om, fl, fo.PASS_REFINE)
+    lm = dg.dg_mesh_build(prev=lm, flags=fl, pass_=dg.DG_PASS_REFINE)
+    assert tables_equal(lm.tables(), om) and om.levels().max() == 2
+    K = om.K
+    identity = np.arange(K, dtype=np.int32)
+    # (a) refine pass: nothing flagged, then only leaves already at max_level flagged
+    for fl in (np.zeros(K, np.int8), np.where(om.levels() == 2, 1, 0).astype(np.int8)):
+        om2 = fo.build(od, om, fl, fo.PASS_REFINE)
+        lm2 = dg.dg_mesh_build(prev=lm, flags=fl, pass_=dg.DG_PASS_REFINE)
+        assert tables_equal(lm2.tables(), om2) and om2.leaves == om.leaves
+        assert np.array_equal(om2.xfer_src, identity) and np.all(om2.xfer_kind == fo.KIND_COPY)
+        assert lm2.info.n_refined == 0
+    # (b) coarsen pass: root 0's children form a family, but its parent would face
+    # level-2 leaves of root 1, so the family is vetoed
+    fl = np.array([-1 if (lf[0] == 0 and lf[1] == 1) else 0 for lf in om.leaves], np.int8)
+    assert (fl < 0).sum() == 8
+    om2 = fo.build(od, om, fl, fo.PASS_COARSEN)
+    lm2 = dg.dg_mesh_build(prev=lm, flags=fl, pass_=dg.DG_PASS_COARSEN)
+    assert tables_equal(lm2.tables(), om2) and om2.leaves == om.leaves
+    assert np.array_equal(om2.xfer_src, identity) and lm2.info.n_coarsened == 0
+    # a coarsen pass that does merge (root 1's level-2 families) still matches
+    fl = np.where(om.levels() == 2, -1, 0).astype(np.int8)
+    om3 = fo.build(od, om, fl, fo.PASS_COARSEN)
+    lm3 = dg.dg_mesh_build(prev=lm, flags=fl, pass_=dg.DG_PASS_COARSEN)
+    assert tables_equal(lm3.tables(), om3) and lm3.info.n_coarsened > 0

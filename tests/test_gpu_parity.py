@@ -249,3 +249,37 @@ def test_config2_full_size_rhs_and_step():
     q1, q2 = lm.field(), lm.field()
     dg.ssp_rk3_step(lm, ph, 0.001, q, q1, q2)
     check(q, eu.ssp_rk3_step(op, 0.001, qo), what="C2 step")
+
+
+def test_unchanged_pass_clones_device_tables():
+    """A pass that changes no leaf clones the previous mesh's device block (and its
+    background when computed): the RHS on the clone equals the RHS on the source
+    bitwise, with the cached background and after the physics changes it; the
+    oracle agrees on both; a projection through such a pass copies the field."""
+    od = oracle_desc(3, (2, 2, 2), 2, *BOX, (0, 0, 0))
+    lm, om = both_meshes(3, (2, 2, 2), 2, flag_seq=random_refinements(od, 2, 51))
+    ph = dg.PhysParams()
+    qn = torch.as_tensor(random_state(om.K, 3, 52))
+    q = gpu(qn)
+    R0 = lm.field()
+    dg.dg_rhs(lm, ph, q, R0)  # computes and caches lm's background
+    zero = np.zeros(om.K, np.int8)
+    m2 = dg.dg_mesh_build(prev=lm, flags=zero, pass_=dg.DG_PASS_REFINE)
+    assert tables_equal(m2.tables(), fo.build(od, om, zero, fo.PASS_REFINE)) and m2.info.n_refined == 0
+    R2 = m2.field()
+    dg.dg_rhs(m2, ph, q, R2)
+    torch.cuda.synchronize()
+    assert torch.equal(R0, R2)
+    check(R2, eu.Operator(om, oracle_phys(ph)).rhs(to_elem(qn, 3)), what="rhs on the cloned mesh")
+    # a clone of the clone, then another background (theta0) on it
+    m3 = dg.dg_mesh_build(prev=m2, flags=zero, pass_=dg.DG_PASS_COARSEN)
+    assert m3.info.n_coarsened == 0 and m3.K == om.K
+    ph2 = dg.PhysParams(theta0=290.0)
+    R3 = m3.field()
+    dg.dg_rhs(m3, ph2, q, R3)
+    check(R3, eu.Operator(om, oracle_phys(ph2)).rhs(to_elem(qn, 3)), what="rhs, other background, on the clone")
+    # the projections through an unchanged pass copy the field
+    qc = m3.field()
+    dg.dg_coarsen_project(m2, m3, q, qc)
+    torch.cuda.synchronize()
+    assert torch.equal(qc, q)
