@@ -34,10 +34,10 @@ STAGE_KERNEL = "k_stage<7, 1, false>"
 # sources they were taken on (SHA-256 of the files below); otherwise traffic is
 # reported as null.
 TRAFFIC = {
-    "sources_sha256": "2ab4fbb4374ce77f32935b16df20727622b2278cad0e88dec4514b8a08cbe701",
-    "fetch_kib_per_launch": 66473.7,    # mean over the 90 timed launches
+    "sources_sha256": "f6ee9cf72e0d229c5247ecbfe00f3d76bb6c2bff9a76cbdb761d29b0edb56d7c",
+    "fetch_kib_per_launch": 66464.7,    # mean over the 90 timed launches
     "write_kib_per_launch": 67360.0,
-    "fetch_scale": 1048576.0 / 524302.5,  # 1 GiB copy: FETCH_SIZE reads 524302.5 KiB
+    "fetch_scale": 1048576.0 / 524301.8,  # 1 GiB copy: FETCH_SIZE reads 524301.8 KiB
     "write_scale": 1048576.0 / 1048576.0,  # 1 GiB copy: WRITE_SIZE reads 1048576.0 KiB
 }
 KERNEL_SOURCES = ("paper_2404_16648_amd/csrc/kernels.hip", "paper_2404_16648_amd/csrc/kernels.hpp",
@@ -166,6 +166,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
+        "node_updates_per_s": dofs_per_s / 5.0,
         "dtype": "f64",
         "data": "synthetic (analytic warm-bubble initial state)",
         "config": {"workload": "AMR warm bubble: 1000 m box, 8x8x8 base, N=7, 2 levels where |theta'|>0.1 K, "
@@ -190,19 +191,79 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def _time_launches(torch, fn, reps):
-    """Average duration (us) of fn() over reps launches, HIP events on the current stream."""
+def _time_launches(torch, fn, reps, warmup=5):
+    """Median duration (us) of fn() over reps launches after warmup ones, HIP
+    events around each launch on the current stream."""
     stream = torch.cuda.current_stream()
-    fn()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
+    for _ in range(warmup):
         fn()
-    e1.record(stream)
     torch.cuda.synchronize()
-    return 1e3 * e0.elapsed_time(e1) / reps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    d = sorted(1e3 * e0.elapsed_time(e1) for e0, e1 in ev)
+    return d[len(d) // 2]
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def forced_cycle(dg, torch, mesh, q, reps=5):
+    """AMR transfer on a forced cycle: coarsen every family of finest leaves, project,
+    refine those parents back, project.  Host pass time and projection kernels."""
+    import numpy as np
+    lev = mesh.tables()["leaf"][:, 1]
+    flc = np.where(lev == lev.max(), -1, 0).astype(np.int8)
+    host_c, host_r, kc, kr = [], [], [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mc = dg.dg_mesh_build(prev=mesh, flags=flc, pass_=dg.DG_PASS_COARSEN)
+        t1 = time.perf_counter()
+        qc = mc.field()
+        kc.append(_time_launches(torch, lambda: dg.dg_coarsen_project(mesh, mc, q, qc), 20))
+        flr = np.where(mc.tables()["xfer_kind"] == dg.DG_KIND_FAMILY, 1, 0).astype(np.int8)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        mr = dg.dg_mesh_build(prev=mc, flags=flr, pass_=dg.DG_PASS_REFINE)
+        t3 = time.perf_counter()
+        qr = mr.field()
+        kr.append(_time_launches(torch, lambda: dg.dg_refine_project(mc, mr, qc, qr), 20))
+        host_c.append(1e3 * (t1 - t0))
+        host_r.append(1e3 * (t3 - t2))
+    med = lambda v: sorted(v)[len(v) // 2]
+    np_ = mesh.Np
+    bytes_c = 40.0 * np_ * (mesh.K + mc.K)   # read every source leaf, write every target leaf
+    bytes_r = 40.0 * np_ * (mc.K + mr.K)
+    return {"leaves": [mesh.K, mc.K, mr.K], "families": int(mc.info.n_coarsened),
+            "coarsen_pass_host_ms": med(host_c), "refine_pass_host_ms": med(host_r),
+            "coarsen_project_us": med(kc), "refine_project_us": med(kr),
+            "coarsen_project_GBs": bytes_c / (med(kc) * 1e-6) / 1e9,
+            "refine_project_GBs": bytes_r / (med(kr) * 1e-6) / 1e9,
+            "same_leaves_after_cycle": bool(mr.K == mesh.K)}
+
+
+def budget_drift(dg, torch, mesh, q, ph, dt, steps=10):
+    """Change of the integral of rho' per SSP-RK3 step over `steps` steps (no
+    adaptation), relative to the integral of rho = rho_bar + rho'."""
+    a, b = torch.empty_like(q), torch.empty_like(q)
+    x = q.clone()
+    b0 = dg.dg_budgets(mesh, ph, x)
+    for _ in range(steps):
+        dg.ssp_rk3_step(mesh, ph, dt, x, a, b)
+    b1 = dg.dg_budgets(mesh, ph, x)
+    return abs(b1[0] - b0[0]) / steps / abs(b0[1])
 
 
 def _field_err(torch, a, b):
@@ -227,7 +288,11 @@ def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us):
     dg.dg_rhs(mesh, ph, q, Ra)
     dg.dg_rhs(mesh, mixed, q, Rb)
     out["mixed"] = {"stage_us_fp64": f64_us, "stage_us_mixed": mixed_us, "speedup": f64_us / mixed_us,
-                    "rhs_rel_l2_vs_fp64_fields(rho',momentum,Theta')": _field_err(torch, Rb, Ra)}
+                    "rhs_rel_l2_vs_fp64_fields(rho',momentum,Theta')": _field_err(torch, Rb, Ra),
+                    "mass_drift_per_step_rel_fp64": budget_drift(dg, torch, mesh, q, ph, dt),
+                    "mass_drift_per_step_rel_mixed": budget_drift(dg, torch, mesh, q, mixed, dt)}
+    # ---- forced adaptation cycle on the same mesh
+    out["forced_cycle"] = forced_cycle(dg, torch, mesh, q)
     # ---- adjoint cost: one transposed RHS vs one RHS on the same state
     lam = torch.randn(q.shape, dtype=torch.float64, device=q.device, generator=torch.Generator(q.device).manual_seed(7))
     g = torch.empty_like(q)
@@ -257,6 +322,9 @@ def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us):
     m3, q3 = dg.initial_mesh(4, (64, 4, 16), 2, (0.0, 0.0, 0.0), (25600.0, 1600.0, 6400.0), (0, 0, 0), ph,
                              (-15.0, (0.0, 800.0, 3000.0), (4000.0, 0.0, 2000.0)), dg.DG_IND_GRAD_THETA, 1e-3)
     a3 = torch.empty_like(q3)
+    b3 = torch.empty_like(q3)
+    for _ in range(10):  # every field non-zero before timing
+        dg.ssp_rk3_step(m3, ph, 0.008, q3, a3, b3)
     nodes3 = m3.K * m3.Np
     for prec, key in ((ph, "fp64"), (mixed, "mixed")):
         us = _time_launches(torch, lambda: dg.dg_rk_stage(m3, prec, 0.75, 0.25, 0.008, q3, q3, a3), 20)
@@ -264,6 +332,25 @@ def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us):
         out["density_current_" + key] = {
             "leaves": m3.K, "nodes": nodes3, "hanging_faces": int(m3.info.n_hang), "stage_us": us,
             "dof_updates_per_s": 5 * nodes3 / (us * 1e-6), "achieved_GBs": ach, "frac_hbm": ach / HBM_PEAK_GBS}
+    # ---- uniform bubble, 4^3 hexes, N = 4, dt = 0.05 s: launch-bound, reported only
+    m1 = dg.dg_mesh_build(4, (4, 4, 4), 0, (0.0, 0.0, 0.0), (1000.0, 1000.0, 1000.0))
+    q1c = m1.field()
+    dg.dg_init_bell(m1, ph, q1c, 2.0, (500.0, 500.0, 350.0), (250.0, 250.0, 250.0))
+    r1, s1, s2, s3 = m1.field(), m1.field(), m1.field(), m1.field()
+
+    def step1():  # the three stage launches of one step, out of place (same state every time)
+        dg.dg_rk_stage(m1, ph, 0.0, 1.0, 0.05, q1c, q1c, s1)
+        dg.dg_rk_stage(m1, ph, 0.75, 0.25, 0.05, q1c, s1, s2)
+        dg.dg_rk_stage(m1, ph, 1.0 / 3.0, 2.0 / 3.0, 0.05, q1c, s2, s3)
+
+    out["uniform_4x4x4_N4"] = {"rhs_us": _time_launches(torch, lambda: dg.dg_rhs(m1, ph, q1c, r1), 20),
+                               "step_us": _time_launches(torch, step1, 20), "nodes": m1.K * m1.Np}
+    # ---- measured copy bandwidth (1 GiB device-to-device) beside the 8 TB/s spec
+    src = torch.ones(1 << 30, dtype=torch.uint8, device=q.device)
+    dst = torch.empty_like(src)
+    cu = _time_launches(torch, lambda: dst.copy_(src), 10)
+    out["copy_1GiB_GBs"] = 2.0 * (1 << 30) / (cu * 1e-6) / 1e9
+    del src, dst
     return out
 
 
@@ -299,7 +386,7 @@ def cpu_baseline():
     nodes = m.K * (m.N + 1) ** 3
     return {"value": 3 * 5 * nodes * steps / el, "unit": "DOF-updates/s", "cores": torch.get_num_threads(),
             "kind": "oracle", "sample": f"{steps} SSP-RK3 step(s) of the same workload (K={m.K}, N=7) "
-                                        f"in {el:.1f} s"}
+                                        f"in {el:.1f} s on {_cpu_model()}"}
 
 
 if __name__ == "__main__":

@@ -1038,54 +1038,105 @@ __device__ __forceinline__ double apply3(const double* in, double* s1, double* s
 template <int N>
 __global__ void __launch_bounds__(Sz<N>::NT) k_refine(const XferArgs A) {
     constexpr int NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
-    __shared__ double sIn[NP], s1[NP], s2[NP], sOps[Sz<N>::NOPS];
+    __shared__ double sIn[NP], s1[NP], s2[NP], sI[2 * NF];
     const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
     const int t = threadIdx.x;
     const int64_t src = A.src[e];
     const int kind = A.kind[e];
-    for (int i = t; i < Sz<N>::NOPS; i += NT) sOps[i] = A.ops[i];
+    const int64_t KinNP = A.Kin * NP, KoutNP = A.Kout * NP;
+    if (kind == DG_KIND_COPY) {  // uniform over the block
+        if (t < NP)
+            for (int v = 0; v < 5; ++v) A.qout[v * KoutNP + e * NP + t] = A.qin[v * KinNP + src * NP + t];
+        return;
+    }
+    // the parent's five values at this node, all loads issued at once
+    double p[5] = {0, 0, 0, 0, 0};
+    if (t < NP)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) p[v] = A.qin[v * KinNP + src * NP + t];
+    for (int i = t; i < 2 * NF; i += NT) sI[i] = A.ops[NF + i];  // I_0, I_1
+    const double* I0 = sI;
+    const double* I1 = sI + NF;
+#pragma unroll 1
     for (int v = 0; v < 5; ++v) {
-        const double* in = A.qin + (int64_t)v * A.Kin * NP + src * NP;
-        double* out = A.qout + (int64_t)v * A.Kout * NP + e * NP;
-        if (kind == DG_KIND_COPY) {
-            if (t < NP) out[t] = in[t];
-            continue;
-        }
         __syncthreads();
-        if (t < NP) sIn[t] = in[t];
+        if (t < NP) sIn[t] = p[v];
         __syncthreads();
-        const double* I0 = sOps + NF;
-        const double* I1 = sOps + 2 * NF;
         const double r = apply3<N>(sIn, s1, s2, (kind & 1) ? I1 : I0, (kind & 2) ? I1 : I0, (kind & 4) ? I1 : I0, t);
-        if (t < NP) out[t] = r;
+        if (t < NP) A.qout[v * KoutNP + e * NP + t] = r;
     }
 }
 
+// Coarsening of a family: its eight children form one block of (2N+2)^3 nodes,
+// fine index I = a (N+1) + i along each axis (a = the child's bit on that axis),
+// and the parent is (R x R x R) applied to it with R = [R_0 | R_1], an
+// (N+1) x (2N+2) matrix: three separable passes per variable.  The next
+// variable's loads are in flight while the current one is contracted.
 template <int N>
 __global__ void __launch_bounds__(Sz<N>::NT) k_coarsen(const XferArgs A) {
-    constexpr int NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
-    __shared__ double sIn[NP], s1[NP], s2[NP], sOps[Sz<N>::NOPS];
+    constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
+    constexpr int M = 2 * N1;
+    __shared__ double sF[M * M * M];   // fine block; reused by the second pass's output
+    __shared__ double s1[N1 * M * M];
+    __shared__ double sR[N1 * M];      // sR[i M + m] = R_{m / (N+1)}[i][m % (N+1)]
+    double* const s2 = sF;             // [M][N1][N1]
     const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
     const int t = threadIdx.x;
     const int64_t src = A.src[e];
     const int kind = A.kind[e];
-    for (int i = t; i < Sz<N>::NOPS; i += NT) sOps[i] = A.ops[i];
+    const int64_t KinNP = A.Kin * NP, KoutNP = A.Kout * NP;
+    if (kind == DG_KIND_COPY) {  // uniform over the block
+        if (t < NP)
+            for (int v = 0; v < 5; ++v) A.qout[v * KoutNP + e * NP + t] = A.qin[v * KinNP + src * NP + t];
+        return;
+    }
+    for (int x = t; x < N1 * M; x += NT) {
+        const int i = x / M, m = x % M;
+        sR[x] = A.ops[(3 + m / N1) * NF + i * N1 + m % N1];
+    }
+    const int ic = t % N1, jc = (t / N1) % N1, kc = t / NF;
+    double pf[8];
+    if (t < NP)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) pf[c] = A.qin[(src + c) * NP + t];
+#pragma unroll 1
     for (int v = 0; v < 5; ++v) {
-        double* out = A.qout + (int64_t)v * A.Kout * NP + e * NP;
-        if (kind == DG_KIND_COPY) {
-            if (t < NP) out[t] = A.qin[(int64_t)v * A.Kin * NP + src * NP + t];
-            continue;
+        __syncthreads();
+        if (t < NP)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int I = (c & 1) * N1 + ic, J = ((c >> 1) & 1) * N1 + jc, Kf = (c >> 2) * N1 + kc;
+                sF[(Kf * M + J) * M + I] = pf[c];
+            }
+        __syncthreads();
+        if (v < 4 && t < NP)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) pf[c] = A.qin[(v + 1) * KinNP + (src + c) * NP + t];
+        // x: s1[K'][J'][i] = sum_m R[i][m] F[K'][J'][m]
+        for (int x = t; x < N1 * M * M; x += NT) {
+            const int i = x % N1, row = x / N1;
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) acc = fma(sR[i * M + m], sF[row * M + m], acc);
+            s1[x] = acc;
         }
-        const double* R0 = sOps + 3 * NF;
-        const double* R1 = sOps + 4 * NF;
-        double acc = 0.0;
-        for (int c = 0; c < 8; ++c) {
-            __syncthreads();
-            if (t < NP) sIn[t] = A.qin[(int64_t)v * A.Kin * NP + (src + c) * NP + t];
-            __syncthreads();
-            acc += apply3<N>(sIn, s1, s2, (c & 1) ? R1 : R0, (c & 2) ? R1 : R0, (c & 4) ? R1 : R0, t);
+        __syncthreads();
+        // y: s2[K'][j][i] = sum_m R[j][m] s1[K'][m][i]
+        for (int x = t; x < N1 * N1 * M; x += NT) {
+            const int i = x % N1, j = (x / N1) % N1, kk = x / NF;
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) acc = fma(sR[j * M + m], s1[(kk * M + m) * N1 + i], acc);
+            s2[x] = acc;
         }
-        if (t < NP) out[t] = acc;
+        __syncthreads();
+        // z: out[k][j][i] = sum_m R[k][m] s2[m][j][i]
+        if (t < NP) {
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) acc = fma(sR[kc * M + m], s2[m * NF + ic + N1 * jc], acc);
+            A.qout[v * KoutNP + e * NP + t] = acc;
+        }
     }
 }
 
