@@ -182,6 +182,20 @@ dg_status dg_refine_project(const dg_mesh* from, const dg_mesh* to, const double
 dg_status dg_coarsen_project(const dg_mesh* from, const dg_mesh* to, const double* q_from,
                              double* q_to, void* stream);
 
+/* Transposes of the transfers, for the adjoint through an adaptation: with P
+ * the linear map q_from -> q_to of dg_refine_project (resp.
+ * dg_coarsen_project) from `from` to `to`, qbar_from := P^T qbar_to in the
+ * Euclidean inner product on the DOF vectors.  Refine: a refined leaf gets
+ * sum over its 8 children of (I_a x I_b x I_c)^T qbar_child.  Coarsen: each
+ * child of a merged parent gets (R_a x R_b x R_c)^T qbar_parent.  Kept leaves
+ * are copied.  qbar_to is [5][K_to][Np], qbar_from [5][K_from][Np] (every
+ * entry written), device pointers on `to`'s device; they must not alias.
+ * Same checks and error codes as the forward transfers. */
+dg_status dg_refine_project_adjoint(const dg_mesh* from, const dg_mesh* to, const double* qbar_to,
+                                    double* qbar_from, void* stream);
+dg_status dg_coarsen_project_adjoint(const dg_mesh* from, const dg_mesh* to, const double* qbar_to,
+                                     double* qbar_from, void* stream);
+
 /* qbar := (dR/dq)^T lam, the exact transpose of the linearised right-hand side
  * in the Euclidean inner product on the DOF vector (d|x|/dx := 0 at 0, a max
  * tie splits the derivative 1/2, 1/2).  qbar must not alias q or lam. */

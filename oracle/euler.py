@@ -438,6 +438,25 @@ def coarsen_project(mesh_to: fo.Mesh, q_from):
     return torch.stack(out, dim=1)
 
 
+def _transfer_adjoint(forward, mesh_to: fo.Mesh, qbar_to, K_from):
+    N1 = mesh_to.N + 1
+    x = torch.zeros(5, K_from, N1, N1, N1, dtype=torch.float64, requires_grad=True)
+    (g,) = torch.autograd.grad(forward(mesh_to, x), x, grad_outputs=qbar_to)
+    return g
+
+
+def refine_project_adjoint(mesh_to: fo.Mesh, qbar_to, K_from):
+    """P^T qbar_to for the (linear) refine transfer P onto mesh_to from K_from
+    source leaves, in the Euclidean inner product on the DOF vectors, by
+    reverse-mode differentiation of ``refine_project``."""
+    return _transfer_adjoint(refine_project, mesh_to, qbar_to, K_from)
+
+
+def coarsen_project_adjoint(mesh_to: fo.Mesh, qbar_to, K_from):
+    """P^T qbar_to for the (linear) coarsen transfer onto mesh_to, as above."""
+    return _transfer_adjoint(coarsen_project, mesh_to, qbar_to, K_from)
+
+
 # ----------------------------------------------------------------------------- adjoint and JVP
 
 def rhs_adjoint(op: Operator, q, lam):

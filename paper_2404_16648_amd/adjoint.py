@@ -1,10 +1,12 @@
-"""Discrete adjoint of the SSP-RK3 integration behind a torch.autograd.Function.
+"""Discrete adjoint of the SSP-RK3 integration behind torch.autograd.Functions.
 
 Forward: n SSP-RK3 steps with dg_rk_stage, keeping the state every
 ``ckpt_every`` steps.  Backward: for each segment in reverse, recompute its
 steps once from the checkpoint (keeping the three stage inputs of every step)
-and run the transposed stages with dg_rk_stage_adjoint.  All arithmetic runs in
-the HIP library; this module only orders calls and holds buffers.
+and run the transposed stages with dg_rk_stage_adjoint.  Through an adaptation
+cycle the gradient flows back through the transposes of the conservative
+transfers (section 3.3) along the recorded mesh sequence.  All arithmetic runs
+in the HIP library; this module only orders calls and holds buffers.
 """
 from __future__ import annotations
 
@@ -74,3 +76,61 @@ class SSPRK3Integrate(torch.autograd.Function):
 def integrate(q0, mesh, phys, dt, nsteps, ckpt_every=10):
     """Differentiable n-step SSP-RK3 integration on a fixed mesh."""
     return SSPRK3Integrate.apply(q0, mesh, phys, dt, nsteps, ckpt_every)
+
+
+class Transfer(torch.autograd.Function):
+    """q_to = P q_from for the refine or coarsen transfer src -> dst (a linear
+    map); the backward applies P^T with the library's transposed transfer."""
+
+    @staticmethod
+    def forward(ctx, q, src, dst, refine):
+        out = torch.empty(5, dst.K, dst.Np, dtype=torch.float64, device=q.device)
+        (dg.dg_refine_project if refine else dg.dg_coarsen_project)(src, dst, q.detach().contiguous(), out)
+        ctx.src, ctx.dst, ctx.refine = src, dst, refine
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        src, dst = ctx.src, ctx.dst
+        out = torch.empty(5, src.K, src.Np, dtype=torch.float64, device=g.device)
+        adj = dg.dg_refine_project_adjoint if ctx.refine else dg.dg_coarsen_project_adjoint
+        adj(src, dst, g.detach().contiguous(), out)
+        return out, None, None, None
+
+
+class AdaptPlan:
+    """Mesh sequence of an adaptive run: (mesh_c, mesh_r) of every cycle, as
+    :func:`dg.adapt_meshes` returns them.  The flags are piecewise constant in
+    the state, so derivatives are taken along a fixed sequence: a plan recorded
+    by one run is replayed by the next (gradient, finite differences)."""
+
+    def __init__(self, cycles=None):
+        self.cycles = list(cycles or [])
+
+
+def integrate_adaptive(q0, mesh, phys, dt, nsteps, adapt_every, kind=None, thr=None, plan=None,
+                       ckpt_every=10):
+    """Differentiable SSP-RK3 integration with an adaptation cycle after every
+    ``adapt_every`` steps (none after the last step).  Without a plan, each cycle
+    comes from the indicator (kind, thr) of the current state and is recorded;
+    with a plan, its meshes are replayed.  Returns (q_T, mesh_T, plan)."""
+    record = plan is None
+    plan = AdaptPlan() if record else plan
+    q, m, n, cyc = q0, mesh, 0, 0
+    while n < nsteps:
+        seg = min(adapt_every, nsteps - n)
+        q = integrate(q, m, phys, dt, seg, min(ckpt_every, seg))
+        n += seg
+        if n >= nsteps:
+            break
+        if record:
+            mc, mr = dg.adapt_meshes(m, phys, q.detach(), kind, thr)
+            plan.cycles.append((mc, mr))
+        else:
+            mc, mr = plan.cycles[cyc]
+        if mc is not m:
+            q = Transfer.apply(q, m, mc, False)
+        if mr is not mc:
+            q = Transfer.apply(q, mc, mr, True)
+        m, cyc = mr, cyc + 1
+    return q, m, plan

@@ -114,8 +114,32 @@ bool tables_consistent(const HostMesh& h) {
         for (int q = 0; q < nnb; ++q)
             if (h.fnb[i * 4 + q] < 0 || h.fnb[i * 4 + q] >= K) return false;
     }
-    for (int64_t e = 0; e < K; ++e)
-        if (h.xfer_src[e] < 0) return false;
+    return true;
+}
+
+// the transfer plan indexes fields of K_from source leaves: a kept or refined
+// source in range; a refined leaf's eight children consecutive, ids 0..7, with
+// one source; a merged parent's eight source leaves in range (the transfer
+// kernels read and write whole families from these indices)
+bool plan_consistent(const HostMesh& h, int64_t K_from) {
+    const int64_t K = (int64_t)h.leaves.size();
+    if ((int64_t)h.xfer_src.size() != K || (int64_t)h.xfer_kind.size() != K) return false;
+    for (int64_t e = 0; e < K; ++e) {
+        const int64_t src = h.xfer_src[e];
+        const int kind = h.xfer_kind[e];
+        if (kind == DG_KIND_COPY) {
+            if (src < 0 || src >= K_from) return false;
+        } else if (kind == DG_KIND_FAMILY) {
+            if (src < 0 || src + 7 >= K_from) return false;
+        } else if (kind >= 0 && kind < 8) {
+            const int64_t e0 = e - kind;
+            if (src < 0 || src >= K_from || e0 < 0 || e0 + 7 >= K) return false;
+            for (int c = 0; c < 8; ++c)
+                if (h.xfer_kind[e0 + c] != c || h.xfer_src[e0 + c] != src) return false;
+        } else {
+            return false;
+        }
+    }
     return true;
 }
 
@@ -151,6 +175,8 @@ dg_status build_device(dg_mesh* m) {
     const HostMesh& h = m->h;
     const int64_t K = (int64_t)h.leaves.size();
     if (!tables_consistent(h)) return fail(DG_EINVAL, "internal: inconsistent face tables");
+    if (!plan_consistent(h, m->prev ? (int64_t)m->prev->h.leaves.size() : K))
+        return fail(DG_EINVAL, "internal: inconsistent transfer plan");
     if (5 * K * (int64_t)(h.desc.N + 1) * (h.desc.N + 1) * (h.desc.N + 1) >= ((int64_t)1 << 31))
         return fail(DG_EINVAL, "mesh too large: 5 K Np must stay below 2^31");
     if (h.same_as_prev && m->prev && m->prev->on_device && m->prev->h.leaves.size() == h.leaves.size())
@@ -421,34 +447,44 @@ dg_status dg_rk_stage(const dg_mesh* m, const dg_phys* phys, double a, double b,
     return stage_common(m, phys, MODE_RK, a, b, dt, q0, qs, qout, stream);
 }
 
-static dg_status xfer_common(const dg_mesh* from, const dg_mesh* to, const double* qf, double* qt, void* stream,
-                             bool refine) {
+static dg_status xfer_common(const dg_mesh* from, const dg_mesh* to, const double* qin, double* qout,
+                             void* stream, bool refine, bool adjoint) {
     dg_status st = check_dev_mesh(from);
     if (st) return st;
     if ((st = check_dev_mesh(to))) return st;
     if (to->prev_id != from->id) return fail(DG_EINVAL, "`to` was not built from `from`");
-    if (!qf || !qt) return fail(DG_EINVAL, "NULL field pointer");
-    if (qf == qt) return fail(DG_EINVAL, "q_to must not alias q_from");
+    if (!qin || !qout) return fail(DG_EINVAL, "NULL field pointer");
+    if (qin == qout) return fail(DG_EINVAL, "input and output fields must not alias");
     if (refine && to->h.n_coarsened) return fail(DG_EINVAL, "`to` was built by a coarsen pass");
     if (!refine && to->h.n_refined) return fail(DG_EINVAL, "`to` was built by a refine pass");
-    XferArgs a{qf, qt, to->d_ops, to->d_xsrc, to->d_xkind, (int64_t)from->h.leaves.size(),
-               (int64_t)to->h.leaves.size()};
+    const int64_t Kf = (int64_t)from->h.leaves.size(), Kt = (int64_t)to->h.leaves.size();
+    XferArgs a{qin, qout, to->d_ops, to->d_xsrc, to->d_xkind, adjoint ? Kt : Kf, adjoint ? Kf : Kt, Kt};
     hipStream_t s = (hipStream_t)stream;
     if (refine)
-        HIP_TRY(launch_refine(to->h.desc.N, a, s));
+        HIP_TRY(launch_refine(to->h.desc.N, adjoint, a, s));
     else
-        HIP_TRY(launch_coarsen(to->h.desc.N, a, s));
+        HIP_TRY(launch_coarsen(to->h.desc.N, adjoint, a, s));
     return DG_OK;
 }
 
 dg_status dg_refine_project(const dg_mesh* from, const dg_mesh* to, const double* q_from, double* q_to,
                             void* stream) {
-    return xfer_common(from, to, q_from, q_to, stream, true);
+    return xfer_common(from, to, q_from, q_to, stream, true, false);
 }
 
 dg_status dg_coarsen_project(const dg_mesh* from, const dg_mesh* to, const double* q_from, double* q_to,
                              void* stream) {
-    return xfer_common(from, to, q_from, q_to, stream, false);
+    return xfer_common(from, to, q_from, q_to, stream, false, false);
+}
+
+dg_status dg_refine_project_adjoint(const dg_mesh* from, const dg_mesh* to, const double* qbar_to, double* qbar_from,
+                                    void* stream) {
+    return xfer_common(from, to, qbar_to, qbar_from, stream, true, true);
+}
+
+dg_status dg_coarsen_project_adjoint(const dg_mesh* from, const dg_mesh* to, const double* qbar_to,
+                                     double* qbar_from, void* stream) {
+    return xfer_common(from, to, qbar_to, qbar_from, stream, false, true);
 }
 
 static dg_status adjoint_common(const dg_mesh* mc, const dg_phys* phys, int mode, double a1, const double* w1,

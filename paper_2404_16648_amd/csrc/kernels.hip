@@ -1006,99 +1006,58 @@ __global__ void k_node_coords(int64_t K, int N1, const double* c1d, double* xyz)
 
 // ---------------------------------------------------------------- transfer (section 3.3)
 
-// out[k][j][i] = sum C[k][k'] B[j][j'] A[i][i'] in[k'][j'][i'] for one variable; t < NP
-template <int N>
-__device__ __forceinline__ double apply3(const double* in, double* s1, double* s2, const double* Am, const double* Bm,
-                                         const double* Cm, int t) {
-    constexpr int N1 = N + 1, NP = N1 * N1 * N1;
-    const int i = t % N1, j = (t / N1) % N1, k = t / (N1 * N1);
-    if (t < NP) {
-        double acc = 0.0;
-#pragma unroll
-        for (int m = 0; m < N1; ++m) acc = fma(Am[i * N1 + m], in[m + N1 * (j + N1 * k)], acc);
-        s1[t] = acc;
-    }
-    __syncthreads();
-    if (t < NP) {
-        double acc = 0.0;
-#pragma unroll
-        for (int m = 0; m < N1; ++m) acc = fma(Bm[j * N1 + m], s1[i + N1 * (m + N1 * k)], acc);
-        s2[t] = acc;
-    }
-    __syncthreads();
-    double acc = 0.0;
-    if (t < NP) {
-#pragma unroll
-        for (int m = 0; m < N1; ++m) acc = fma(Cm[k * N1 + m], s2[i + N1 * (j + N1 * m)], acc);
-    }
-    __syncthreads();
-    return acc;
-}
+// A family is eight consecutive leaves, children 0..7 of one leaf (consecutive in
+// Morton order, checked on the host): the targets of a refined leaf, or the
+// sources of a merged parent.  Its nodes form one block of (2N+2)^3 points, fine
+// index I = a (N+1) + i along each axis, a = the child's bit on that axis.
+//
+// k_family_reduce: one leaf = (A x A x A) applied to a family block, A an
+//   (N+1) x (2N+2) matrix: coarsening, A = [R_0 | R_1]; transpose of refinement,
+//   A = [I_0^T | I_1^T].
+// k_family_expand: a family block = (B x B x B) applied to one leaf, B a
+//   (2N+2) x (N+1) matrix: refinement, B = [I_0 ; I_1]; transpose of
+//   coarsening, B = [R_0^T ; R_1^T].
+// Three separable passes per variable; kept leaves are copied.  The block of a
+// refined family is the one at child 0; the others return at once.
 
-template <int N>
-__global__ void __launch_bounds__(Sz<N>::NT) k_refine(const XferArgs A) {
-    constexpr int NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
-    __shared__ double sIn[NP], s1[NP], s2[NP], sI[2 * NF];
-    const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
-    const int t = threadIdx.x;
-    const int64_t src = A.src[e];
-    const int kind = A.kind[e];
-    const int64_t KinNP = A.Kin * NP, KoutNP = A.Kout * NP;
-    if (kind == DG_KIND_COPY) {  // uniform over the block
-        if (t < NP)
-            for (int v = 0; v < 5; ++v) A.qout[v * KoutNP + e * NP + t] = A.qin[v * KinNP + src * NP + t];
-        return;
-    }
-    // the parent's five values at this node, all loads issued at once
-    double p[5] = {0, 0, 0, 0, 0};
+// copy of a kept leaf: forward q_to[e] = q_from[src]; transpose qbar_from[src] = qbar_to[e]
+template <int N, bool ADJ>
+__device__ __forceinline__ void xfer_copy(const XferArgs& A, int64_t e, int64_t src, int t) {
+    constexpr int NP = Sz<N>::NP;
+    const int64_t li = ADJ ? e : src, lo = ADJ ? src : e;
     if (t < NP)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) p[v] = A.qin[v * KinNP + src * NP + t];
-    for (int i = t; i < 2 * NF; i += NT) sI[i] = A.ops[NF + i];  // I_0, I_1
-    const double* I0 = sI;
-    const double* I1 = sI + NF;
-#pragma unroll 1
-    for (int v = 0; v < 5; ++v) {
-        __syncthreads();
-        if (t < NP) sIn[t] = p[v];
-        __syncthreads();
-        const double r = apply3<N>(sIn, s1, s2, (kind & 1) ? I1 : I0, (kind & 2) ? I1 : I0, (kind & 4) ? I1 : I0, t);
-        if (t < NP) A.qout[v * KoutNP + e * NP + t] = r;
-    }
+        for (int v = 0; v < 5; ++v) A.qout[v * A.Kout * NP + lo * NP + t] = A.qin[v * A.Kin * NP + li * NP + t];
 }
 
-// Coarsening of a family: its eight children form one block of (2N+2)^3 nodes,
-// fine index I = a (N+1) + i along each axis (a = the child's bit on that axis),
-// and the parent is (R x R x R) applied to it with R = [R_0 | R_1], an
-// (N+1) x (2N+2) matrix: three separable passes per variable.  The next
-// variable's loads are in flight while the current one is contracted.
-template <int N>
-__global__ void __launch_bounds__(Sz<N>::NT) k_coarsen(const XferArgs A) {
+template <int N, bool ADJ>
+__global__ void __launch_bounds__(Sz<N>::NT) k_family_reduce(const XferArgs A) {
     constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
     constexpr int M = 2 * N1;
-    __shared__ double sF[M * M * M];   // fine block; reused by the second pass's output
+    __shared__ double sF[M * M * M];   // family block; reused by the second pass's output
     __shared__ double s1[N1 * M * M];
-    __shared__ double sR[N1 * M];      // sR[i M + m] = R_{m / (N+1)}[i][m % (N+1)]
+    __shared__ double sA[N1 * M];      // sA[i M + m]
     double* const s2 = sF;             // [M][N1][N1]
     const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
     const int t = threadIdx.x;
     const int64_t src = A.src[e];
     const int kind = A.kind[e];
-    const int64_t KinNP = A.Kin * NP, KoutNP = A.Kout * NP;
     if (kind == DG_KIND_COPY) {  // uniform over the block
-        if (t < NP)
-            for (int v = 0; v < 5; ++v) A.qout[v * KoutNP + e * NP + t] = A.qin[v * KinNP + src * NP + t];
+        xfer_copy<N, ADJ>(A, e, src, t);
         return;
     }
+    if (ADJ && kind != 0) return;  // refined family: handled by the block of child 0
+    const int64_t fine0 = ADJ ? e : src, lo = ADJ ? src : e;
+    const int64_t KinNP = A.Kin * NP, KoutNP = A.Kout * NP;
     for (int x = t; x < N1 * M; x += NT) {
-        const int i = x / M, m = x % M;
-        sR[x] = A.ops[(3 + m / N1) * NF + i * N1 + m % N1];
+        const int i = x / M, m = x % M, h = m / N1, r = m % N1;
+        sA[x] = ADJ ? A.ops[(1 + h) * NF + r * N1 + i]    // I_h^T[i][r]
+                    : A.ops[(3 + h) * NF + i * N1 + r];   // R_h[i][r]
     }
     const int ic = t % N1, jc = (t / N1) % N1, kc = t / NF;
     double pf[8];
     if (t < NP)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) pf[c] = A.qin[(src + c) * NP + t];
+        for (int c = 0; c < 8; ++c) pf[c] = A.qin[(fine0 + c) * NP + t];
 #pragma unroll 1
     for (int v = 0; v < 5; ++v) {
         __syncthreads();
@@ -1109,33 +1068,97 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_coarsen(const XferArgs A) {
                 sF[(Kf * M + J) * M + I] = pf[c];
             }
         __syncthreads();
-        if (v < 4 && t < NP)
+        if (v < 4 && t < NP)  // the next variable's loads, in flight during the passes
 #pragma unroll
-            for (int c = 0; c < 8; ++c) pf[c] = A.qin[(v + 1) * KinNP + (src + c) * NP + t];
-        // x: s1[K'][J'][i] = sum_m R[i][m] F[K'][J'][m]
+            for (int c = 0; c < 8; ++c) pf[c] = A.qin[(v + 1) * KinNP + (fine0 + c) * NP + t];
+        // x: s1[K'][J'][i] = sum_m A[i][m] F[K'][J'][m]
         for (int x = t; x < N1 * M * M; x += NT) {
             const int i = x % N1, row = x / N1;
             double acc = 0.0;
 #pragma unroll
-            for (int m = 0; m < M; ++m) acc = fma(sR[i * M + m], sF[row * M + m], acc);
+            for (int m = 0; m < M; ++m) acc = fma(sA[i * M + m], sF[row * M + m], acc);
             s1[x] = acc;
         }
         __syncthreads();
-        // y: s2[K'][j][i] = sum_m R[j][m] s1[K'][m][i]
+        // y: s2[K'][j][i] = sum_m A[j][m] s1[K'][m][i]
         for (int x = t; x < N1 * N1 * M; x += NT) {
             const int i = x % N1, j = (x / N1) % N1, kk = x / NF;
             double acc = 0.0;
 #pragma unroll
-            for (int m = 0; m < M; ++m) acc = fma(sR[j * M + m], s1[(kk * M + m) * N1 + i], acc);
+            for (int m = 0; m < M; ++m) acc = fma(sA[j * M + m], s1[(kk * M + m) * N1 + i], acc);
             s2[x] = acc;
         }
         __syncthreads();
-        // z: out[k][j][i] = sum_m R[k][m] s2[m][j][i]
+        // z: out[k][j][i] = sum_m A[k][m] s2[m][j][i]
         if (t < NP) {
             double acc = 0.0;
 #pragma unroll
-            for (int m = 0; m < M; ++m) acc = fma(sR[kc * M + m], s2[m * NF + ic + N1 * jc], acc);
-            A.qout[v * KoutNP + e * NP + t] = acc;
+            for (int m = 0; m < M; ++m) acc = fma(sA[kc * M + m], s2[m * NF + ic + N1 * jc], acc);
+            A.qout[v * KoutNP + lo * NP + t] = acc;
+        }
+    }
+}
+
+template <int N, bool ADJ>
+__global__ void __launch_bounds__(Sz<N>::NT) k_family_expand(const XferArgs A) {
+    constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
+    constexpr int M = 2 * N1;
+    __shared__ double sIn[NP];
+    __shared__ double s1[N1 * N1 * M];  // [k][j][I]
+    __shared__ double s2[N1 * M * M];   // [k][J][I]
+    __shared__ double sB[M * N1];       // sB[m (N+1) + i]
+    const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
+    const int t = threadIdx.x;
+    const int64_t src = A.src[e];
+    const int kind = A.kind[e];
+    if (kind == DG_KIND_COPY) {  // uniform over the block
+        xfer_copy<N, ADJ>(A, e, src, t);
+        return;
+    }
+    if (!ADJ && kind != 0) return;  // refined family: handled by the block of child 0
+    const int64_t li = ADJ ? e : src, fine0 = ADJ ? src : e;
+    const int64_t KinNP = A.Kin * NP, KoutNP = A.Kout * NP;
+    for (int x = t; x < M * N1; x += NT) {
+        const int m = x / N1, i = x % N1, h = m / N1, r = m % N1;
+        sB[x] = ADJ ? A.ops[(3 + h) * NF + i * N1 + r]    // R_h^T[r][i]
+                    : A.ops[(1 + h) * NF + r * N1 + i];   // I_h[r][i]
+    }
+    double p[5] = {0, 0, 0, 0, 0};  // the leaf's five values at this node, loaded at once
+    if (t < NP)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) p[v] = A.qin[v * KinNP + li * NP + t];
+#pragma unroll 1
+    for (int v = 0; v < 5; ++v) {
+        __syncthreads();
+        if (t < NP) sIn[t] = p[v];
+        __syncthreads();
+        // x: s1[k][j][I] = sum_i B[I][i] in[k][j][i]
+        for (int x = t; x < N1 * N1 * M; x += NT) {
+            const int I = x % M, row = x / M;
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < N1; ++i) acc = fma(sB[I * N1 + i], sIn[row * N1 + i], acc);
+            s1[x] = acc;
+        }
+        __syncthreads();
+        // y: s2[k][J][I] = sum_j B[J][j] s1[k][j][I]
+        for (int x = t; x < N1 * M * M; x += NT) {
+            const int I = x % M, J = (x / M) % M, kk = x / (M * M);
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < N1; ++j) acc = fma(sB[J * N1 + j], s1[(kk * N1 + j) * M + I], acc);
+            s2[x] = acc;
+        }
+        __syncthreads();
+        // z: child c, node n: out = sum_k B[K][k] s2[k][J][I]
+        for (int x = t; x < 8 * NP; x += NT) {
+            const int c = x / NP, n = x % NP;
+            const int I = (c & 1) * N1 + n % N1, J = ((c >> 1) & 1) * N1 + (n / N1) % N1,
+                      Kf = (c >> 2) * N1 + n / NF;
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < N1; ++k) acc = fma(sB[Kf * N1 + k], s2[(k * M + J) * M + I], acc);
+            A.qout[v * KoutNP + (fine0 + c) * NP + n] = acc;
         }
     }
 }
@@ -1348,15 +1371,25 @@ hipError_t launch_node_coords(int64_t K, int N, const double* c1d, double* xyz, 
     return hipGetLastError();
 }
 
-hipError_t launch_refine(int N, const XferArgs& a, hipStream_t s) {
-    if (a.Kout <= 0) return hipSuccess;
-    DG_DISPATCH_N(N, (k_refine<NN><<<dim3((unsigned)a.Kout), dim3(Sz<NN>::NT), 0, s>>>(a)));
+hipError_t launch_refine(int N, bool adjoint, const XferArgs& a, hipStream_t s) {
+    if (a.Kto <= 0) return hipSuccess;
+    const dim3 grid((unsigned)a.Kto);
+    if (adjoint) {
+        DG_DISPATCH_N(N, (k_family_reduce<NN, true><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+    } else {
+        DG_DISPATCH_N(N, (k_family_expand<NN, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_coarsen(int N, const XferArgs& a, hipStream_t s) {
-    if (a.Kout <= 0) return hipSuccess;
-    DG_DISPATCH_N(N, (k_coarsen<NN><<<dim3((unsigned)a.Kout), dim3(Sz<NN>::NT), 0, s>>>(a)));
+hipError_t launch_coarsen(int N, bool adjoint, const XferArgs& a, hipStream_t s) {
+    if (a.Kto <= 0) return hipSuccess;
+    const dim3 grid((unsigned)a.Kto);
+    if (adjoint) {
+        DG_DISPATCH_N(N, (k_family_expand<NN, true><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+    } else {
+        DG_DISPATCH_N(N, (k_family_reduce<NN, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+    }
     return hipGetLastError();
 }
 

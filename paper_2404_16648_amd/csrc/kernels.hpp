@@ -57,13 +57,16 @@ struct BgParams {
     double cp, cv, P0, g, theta0, rho0, Theta0;
 };
 
+// One launch per transfer: the grid runs over the Kto entries of the target
+// mesh's transfer plan (src, kind).  Forward: qin = q_from (Kin = K_from
+// leaves), qout = q_to.  Transpose: qin = qbar_to (Kin = K_to), qout = qbar_from.
 struct XferArgs {
     const double* qin;
     double* qout;
     const double* ops;
     const int32_t* src;
     const int32_t* kind;
-    int64_t Kin, Kout;
+    int64_t Kin, Kout, Kto;
 };
 
 struct BudgetArgs {
@@ -97,8 +100,9 @@ hipError_t launch_background(int64_t K, int N, const double* c1d, double* bg, co
 hipError_t launch_init_bell(int64_t K, int N, const double* c1d, const double* bg, double theta0, const dg_bell& b,
                             double* q, hipStream_t s);
 hipError_t launch_node_coords(int64_t K, int N, const double* c1d, double* xyz, hipStream_t s);
-hipError_t launch_refine(int N, const XferArgs& a, hipStream_t s);
-hipError_t launch_coarsen(int N, const XferArgs& a, hipStream_t s);
+// adjoint = false: the projection; true: its transpose
+hipError_t launch_refine(int N, bool adjoint, const XferArgs& a, hipStream_t s);
+hipError_t launch_coarsen(int N, bool adjoint, const XferArgs& a, hipStream_t s);
 int budget_blocks(int64_t K);
 hipError_t launch_budgets(int N, const BudgetArgs& a, int nblk, double* out_dev, hipStream_t s);
 hipError_t launch_indicator(int N, const IndArgs& a, hipStream_t s);

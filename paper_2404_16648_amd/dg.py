@@ -37,7 +37,7 @@ DG_KIND_FAMILY = 8
 EXPORTED = [
     "dg_mesh_build", "dg_mesh_free", "dg_mesh_info_get", "dg_mesh_export", "dg_node_coords",
     "dg_init_bell", "dg_rhs", "dg_rk_stage", "dg_refine_project", "dg_coarsen_project",
-    "dg_rhs_adjoint", "dg_rk_stage_adjoint", "dg_budgets", "dg_indicator", "dg_last_error",
+    "dg_refine_project_adjoint", "dg_coarsen_project_adjoint", "dg_rhs_adjoint", "dg_rk_stage_adjoint", "dg_budgets", "dg_indicator", "dg_last_error",
 ]
 
 
@@ -95,6 +95,8 @@ def lib():
         L.dg_rk_stage.argtypes = [P, C.POINTER(Phys), C.c_double, C.c_double, C.c_double, P, P, P, P]
         L.dg_refine_project.argtypes = [P, P, P, P, P]
         L.dg_coarsen_project.argtypes = [P, P, P, P, P]
+        L.dg_refine_project_adjoint.argtypes = [P, P, P, P, P]
+        L.dg_coarsen_project_adjoint.argtypes = [P, P, P, P, P]
         L.dg_rhs_adjoint.argtypes = [P, C.POINTER(Phys), P, P, P, P]
         L.dg_rk_stage_adjoint.argtypes = [P, C.POINTER(Phys), C.c_double, P, C.c_double, P, C.c_double,
                                           C.c_double, P, P, P, P]
@@ -265,6 +267,22 @@ def dg_coarsen_project(src: Mesh, dst: Mesh, q_from, q_to, stream=None):
     _check(lib().dg_coarsen_project(src.handle, dst.handle, _ptr(q_from), _ptr(q_to), _stream(stream)))
 
 
+def dg_refine_project_adjoint(src: Mesh, dst: Mesh, qbar_to, qbar_from, stream=None):
+    """qbar_from := P^T qbar_to, P the refine transfer src -> dst."""
+    _shape_check(dst, qbar_to)
+    _shape_check(src, qbar_from)
+    _check(lib().dg_refine_project_adjoint(src.handle, dst.handle, _ptr(qbar_to), _ptr(qbar_from),
+                                           _stream(stream)))
+
+
+def dg_coarsen_project_adjoint(src: Mesh, dst: Mesh, qbar_to, qbar_from, stream=None):
+    """qbar_from := P^T qbar_to, P the coarsen transfer src -> dst."""
+    _shape_check(dst, qbar_to)
+    _shape_check(src, qbar_from)
+    _check(lib().dg_coarsen_project_adjoint(src.handle, dst.handle, _ptr(qbar_to), _ptr(qbar_from),
+                                            _stream(stream)))
+
+
 def dg_rhs_adjoint(mesh: Mesh, phys: PhysParams, q, lam, qbar, stream=None):
     _shape_check(mesh, q, lam, qbar)
     p = phys.c()
@@ -305,30 +323,42 @@ def ssp_rk3_step(mesh: Mesh, phys: PhysParams, dt, q, q1, q2, stream=None):
     dg_rk_stage(mesh, phys, *SSP_RK3[2], dt, q, q2, q, stream)
 
 
-def adapt_cycle(mesh: Mesh, phys: PhysParams, q, kind, thr, stream=None):
-    """One adaptation cycle: indicator -> coarsen pass + projection -> refine
-    pass + projection (host control flow; every arithmetic step runs in the
-    library).  Parents made by the coarsen pass are not refined in the same
-    cycle.  Returns (new_mesh, new_q); when neither pass changes a leaf, the
-    input mesh and field themselves."""
-    import torch
+def adapt_meshes(mesh: Mesh, phys: PhysParams, q, kind, thr, stream=None):
+    """The two passes of one adaptation cycle from the state q: indicator -> flags
+    -> coarsen pass -> refine pass (parents made by the coarsen pass are not
+    refined in the same cycle).  Returns (mesh_c, mesh_r); a pass that changes no
+    leaf returns its input mesh itself."""
     flags = dg_indicator(mesh, phys, q, kind, thr, stream=stream)
     mc = dg_mesh_build(prev=mesh, flags=flags, pass_=DG_PASS_COARSEN)
     if mc.info.n_coarsened:
-        qc = torch.empty(5, mc.K, mc.Np, dtype=torch.float64, device=q.device)
-        dg_coarsen_project(mesh, mc, q, qc, stream)
         t = mc.tables()
         fl2 = np.where(t["xfer_kind"] == DG_KIND_COPY, flags[t["xfer_src"]], 0).astype(np.int8)
     else:
-        mc, qc = mesh, q  # identity transfer plan: the flags index the same leaves
+        mc = mesh  # identity transfer plan: the flags index the same leaves
         fl2 = flags.copy()
     fl2[fl2 < 0] = 0
     mr = dg_mesh_build(prev=mc, flags=fl2, pass_=DG_PASS_REFINE)
-    if mr.info.n_refined:
+    if not mr.info.n_refined:
+        mr = mc
+    return mc, mr
+
+
+def adapt_cycle(mesh: Mesh, phys: PhysParams, q, kind, thr, stream=None):
+    """One adaptation cycle: the passes of :func:`adapt_meshes`, each followed by
+    its conservative projection (host control flow; every arithmetic step runs in
+    the library).  Returns (new_mesh, new_q); when neither pass changes a leaf,
+    the input mesh and field themselves."""
+    import torch
+    mc, mr = adapt_meshes(mesh, phys, q, kind, thr, stream)
+    qc = q
+    if mc is not mesh:
+        qc = torch.empty(5, mc.K, mc.Np, dtype=torch.float64, device=q.device)
+        dg_coarsen_project(mesh, mc, q, qc, stream)
+    qr = qc
+    if mr is not mc:
         qr = torch.empty(5, mr.K, mr.Np, dtype=torch.float64, device=q.device)
         dg_refine_project(mc, mr, qc, qr, stream)
-        return mr, qr
-    return mc, qc
+    return mr, qr
 
 
 def initial_mesh(N, nroot, max_level, lo, hi, periodic, phys: PhysParams, bell, kind, thr):

@@ -1,7 +1,9 @@
 """GPU parity of the discrete adjoint: dg_rhs_adjoint and dg_rk_stage_adjoint
 against the oracle's reverse-mode derivative of its own RHS, the dot-product
-test against the oracle's forward-mode JVP, and the checkpointed
-autograd.Function gradient against central finite differences."""
+test against the oracle's forward-mode JVP, the checkpointed autograd.Function
+gradient against central finite differences, the transposed transfers against
+the oracle's, and the gradient through adaptation cycles (replayed mesh
+sequence) against the oracle and central differences."""
 import math
 
 import numpy as np
@@ -122,15 +124,21 @@ def test_rk3_step_adjoint_matches_oracle():
     check(got, want, what="rk3 step adjoint")
 
 
-def _functional_parts(om, ph, box):
-    """Test-side functional J(q) = sum J_e W_n 1_box theta'^2 (torch on the GPU)."""
-    op = eu.Operator(om, oracle_phys(ph))
-    X, Y, Z = eu.node_xyz(om)
+def _functional_weights(op, box):
+    """J_e W_n 1_box, rho_bar and Theta_bar at the nodes (node layout, on the GPU)."""
+    X, Y, Z = eu.node_xyz(op.mesh)
     (x0, x1), (y0, y1), (z0, z1) = box
     mask = ((X >= x0) & (X <= x1) & (Y >= y0) & (Y <= y1) & (Z >= z0) & (Z <= z1)).double()
     wm = gpu(to_nodes((eu.quad_weights(op) * mask)[None])[0])
     rb = gpu(to_nodes(op.bg[0][None])[0])
     tb = gpu(to_nodes(op.bg[1][None])[0])
+    return wm, rb, tb
+
+
+def _functional_parts(om, ph, box):
+    """Test-side functional J(q) = sum J_e W_n 1_box theta'^2 (torch on the GPU)."""
+    op = eu.Operator(om, oracle_phys(ph))
+    wm, rb, tb = _functional_weights(op, box)
 
     def J(q):
         thp = (tb + q[4]) / (rb + q[0]) - tb / rb
@@ -170,4 +178,106 @@ def test_integrate_gradient_fd_and_checkpoints():
         fd = (Jonly(q0 + eps * d) - Jonly(q0 - eps * d)) / (2 * eps)
         ad = float((g * d).sum())
         print("direction", k, "fd", fd, "adjoint", ad, flush=True)
+        assert abs(fd - ad) <= 1e-6 * max(abs(fd), abs(ad)), (k, fd, ad)
+
+
+@pytest.mark.parametrize("N,seed", [(2, 60), (4, 61), (7, 62)], ids=lambda x: str(x))
+def test_transfer_adjoints_random_amr(N, seed):
+    """dg_refine_project_adjoint / dg_coarsen_project_adjoint against the oracle's
+    transposes, and <P x, y> = <x, P^T y> with the library's own forward transfers."""
+    od = oracle_desc(N, (2, 2, 2), 2, *BOX, (0, 0, 0))
+    lm, om = both_meshes(N, (2, 2, 2), 2, flag_seq=random_refinements(od, 1, seed))
+    rng = np.random.default_rng(seed)
+    fl_r = (rng.random(om.K) < 0.4).astype(np.int8)
+    lr = dg.dg_mesh_build(prev=lm, flags=fl_r, pass_=dg.DG_PASS_REFINE)
+    orr = fo.build(od, om, fl_r, fo.PASS_REFINE)
+    fl_c = np.where(orr.levels() == 2, -1, np.where(orr.levels() == 1, -1, 0)).astype(np.int8)
+    lc = dg.dg_mesh_build(prev=lr, flags=fl_c, pass_=dg.DG_PASS_COARSEN)
+    oc = fo.build(od, orr, fl_c, fo.PASS_COARSEN)
+    assert tables_equal(lr.tables(), orr) and tables_equal(lc.tables(), oc)
+    assert lr.info.n_refined > 0 and lc.info.n_coarsened > 0
+    for name, fwd, tr_adj, src, dst, ot, oadj, Kf in (
+            ("refine", dg.dg_refine_project, dg.dg_refine_project_adjoint, lm, lr, orr, eu.refine_project_adjoint,
+             om.K),
+            ("coarsen", dg.dg_coarsen_project, dg.dg_coarsen_project_adjoint, lr, lc, oc, eu.coarsen_project_adjoint,
+             orr.K)):
+        y = torch.as_tensor(random_state(dst.K, N, seed + 1, (1.0,) * 5))
+        x = torch.as_tensor(random_state(src.K, N, seed + 2, (1.0,) * 5))
+        g = src.field()
+        tr_adj(src, dst, gpu(y), g)
+        check(g, oadj(ot, to_elem(y, N), Kf), what=f"{name} transpose N={N}")
+        px = dst.field()
+        fwd(src, dst, gpu(x), px)
+        torch.cuda.synchronize()
+        a = float((px.cpu() * y).sum())
+        b = float((x * g.cpu()).sum())
+        assert abs(a - b) <= 1e-13 * max(abs(a), abs(b)), (name, a, b)
+
+
+def _plan_meshes(N, seed):
+    """A fixed mesh sequence with real changes: an AMR start, then two cycles, each
+    coarsening every family of level-1 leaves and refining random leaves; library
+    meshes and the oracle's, tables equal."""
+    od = oracle_desc(N, (2, 2, 2), 2, *BOX, (0, 0, 0))
+    lm, om = both_meshes(N, (2, 2, 2), 2, flag_seq=random_refinements(od, 1, seed))
+    rng = np.random.default_rng(seed)
+    cycles, ocycles = [], []
+    m, o = lm, om
+    for _ in range(2):
+        flc = np.where(o.levels() == 1, -1, 0).astype(np.int8)
+        mc = dg.dg_mesh_build(prev=m, flags=flc, pass_=dg.DG_PASS_COARSEN)
+        oc = fo.build(od, o, flc, fo.PASS_COARSEN)
+        assert mc.info.n_coarsened > 0
+        flr = (rng.random(oc.K) < 0.3).astype(np.int8)
+        mr = dg.dg_mesh_build(prev=mc, flags=flr, pass_=dg.DG_PASS_REFINE)
+        orr = fo.build(od, oc, flr, fo.PASS_REFINE)
+        assert mr.info.n_refined > 0 and tables_equal(mc.tables(), oc) and tables_equal(mr.tables(), orr)
+        cycles.append((mc, mr))
+        ocycles.append((oc, orr))
+        m, o = mr, orr
+    return lm, om, adj.AdaptPlan(cycles), ocycles
+
+
+def test_integrate_adaptive_gradient_through_transfers():
+    """Gradient of J(q_T) through 6 SSP-RK3 steps with two adaptation cycles (a
+    replayed mesh sequence that coarsens and refines): against the oracle's
+    reverse-mode derivative of its own steps and transfers, and against central
+    differences on seeded directions along the same sequence."""
+    N, dt, nsteps, every = 3, 0.02, 6, 2
+    lm, om, plan, ocycles = _plan_meshes(N, 63)
+    ph = dg.PhysParams()
+    om_T = ocycles[-1][1]
+    box = ((300.0, 700.0), (300.0, 700.0), (200.0, 600.0))
+    J, opT = _functional_parts(om_T, ph, box)
+    op0 = eu.Operator(om, oracle_phys(ph))
+    q0o = eu.bubble_state(op0) + 0.1 * to_elem(torch.as_tensor(random_state(om.K, N, 64)), N)
+    q0 = gpu(to_nodes(q0o))
+    x = q0.clone().requires_grad_(True)
+    qT, mT, _ = adj.integrate_adaptive(x, lm, ph, dt, nsteps, every, plan=plan, ckpt_every=2)
+    assert mT is plan.cycles[-1][1]
+    (g,) = torch.autograd.grad(J(qT), x)
+    # the oracle: the same steps and transfers, differentiated in reverse mode
+    xo = q0o.clone().requires_grad_(True)
+    qo, o, cyc = xo, om, 0
+    for n in range(nsteps):
+        qo = eu.ssp_rk3_step(eu.Operator(o, oracle_phys(ph)), dt, qo)
+        if (n + 1) % every == 0 and n + 1 < nsteps:
+            oc, orr = ocycles[cyc]
+            qo = eu.refine_project(orr, eu.coarsen_project(oc, qo))
+            o, cyc = orr, cyc + 1
+    wm, rb, tb = (to_elem(t.cpu()[None], N)[0] for t in _functional_weights(opT, box))
+    thp = (tb + qo[4]) / (rb + qo[0]) - tb / rb
+    (go,) = torch.autograd.grad((wm * thp * thp).sum(), xo)
+    check(g, go, what="adaptive gradient vs oracle")
+
+    def Jonly(y):
+        with torch.no_grad():
+            return float(J(adj.integrate_adaptive(y, lm, ph, dt, nsteps, every, plan=plan)[0]))
+
+    eps = 1e-6
+    for k in range(1, 4):
+        d = gpu(torch.as_tensor(random_direction(om.K, N, k)))
+        fd = (Jonly(q0 + eps * d) - Jonly(q0 - eps * d)) / (2 * eps)
+        ad = float((g * d).sum())
+        print("adaptive direction", k, "fd", fd, "adjoint", ad, flush=True)
         assert abs(fd - ad) <= 1e-6 * max(abs(fd), abs(ad)), (k, fd, ad)

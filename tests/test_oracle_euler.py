@@ -11,6 +11,7 @@ Invariants the discretisation must satisfy exactly or to round-off:
   * design order of accuracy on an exact travelling entropy wave;
   * Rusanov consistency and antisymmetry; wall mass flux exactly zero;
   * quadrature of polynomials in the budgets; prolong-then-restrict = identity;
+  * the transposes of the transfers against the dense transpose, and P^T w = w;
   * adjoint against central finite differences.
 """
 import math
@@ -266,6 +267,45 @@ def test_coarsen_preserves_integrals_of_discontinuous_children():
         a = math.fsum((eu.quad_weights(op1) * q1[v]).reshape(-1).tolist())
         b = math.fsum((eu.quad_weights(op2) * q2[v]).reshape(-1).tolist())
         assert abs(a - b) < 1e-14 * float(q1[v].abs().max()) * 8
+
+
+def _dense(fwd, mesh_to, K_from, N1):
+    """Matrix of a linear transfer, column by column from unit vectors (brute force)."""
+    n_from = 5 * K_from * N1 ** 3
+    cols = []
+    for c in range(n_from):
+        x = torch.zeros(n_from, dtype=F64)
+        x[c] = 1.0
+        cols.append(fwd(mesh_to, x.reshape(5, K_from, N1, N1, N1)).reshape(-1))
+    return torch.stack(cols, dim=1)
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_transfer_adjoints_are_the_transposes(N):
+    """The transposes of the refine and coarsen transfers: against the explicit
+    transpose of the dense matrix of the forward map (unit vectors, tiny mesh),
+    and P^T(w_to) = w_from for the quadrature weights w = J W (integrals are
+    preserved by both transfers)."""
+    N1 = N + 1
+    desc = fo.ForestDesc(N, 2, 1, 1, 1, hi=(2.0, 1.0, 1.0))
+    m0 = fo.build(desc, None)
+    m1 = fo.build(desc, m0, np.array([0, 1], dtype=np.int8), fo.PASS_REFINE)  # root 1 refined, root 0 kept
+    fl = np.where(m1.levels() == 1, -1, 0).astype(np.int8)
+    m2 = fo.build(desc, m1, fl, fo.PASS_COARSEN)
+    assert m2.leaves == m0.leaves and (m2.xfer_kind == fo.KIND_FAMILY).sum() == 1
+    rng = np.random.default_rng(N)
+    for fwd, adj, mf, mt in ((eu.refine_project, eu.refine_project_adjoint, m0, m1),
+                             (eu.coarsen_project, eu.coarsen_project_adjoint, m1, m2)):
+        P = _dense(fwd, mt, mf.K, N1)
+        y = torch.as_tensor(rng.standard_normal((5, mt.K, N1, N1, N1)))
+        got = adj(mt, y, mf.K).reshape(-1)
+        want = P.T @ y.reshape(-1)
+        assert float((got - want).abs().max()) <= 1e-14 * float(want.abs().max())
+        wt = eu.quad_weights(eu.Operator(mt, eu.Phys()))
+        wf = eu.quad_weights(eu.Operator(mf, eu.Phys()))
+        g = adj(mt, wt[None].expand(5, -1, -1, -1, -1).contiguous(), mf.K)
+        for v in range(5):
+            assert float((g[v] - wf).abs().max()) <= 1e-14 * float(wf.abs().max())
 
 
 def test_indicator_and_flags():
