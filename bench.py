@@ -30,25 +30,35 @@ STAGE_KERNEL = "k_stage<7, 1, false>"
 # Bytes beyond L2 per launch of the fused stage over the timed steps of the
 # default workload, from two counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per
 # dispatch), each scaled by the ratio of the bytes a plain device copy of known
-# size moves to what the same counter reads for it.  Valid only for the kernel
-# sources they were taken on (SHA-256 of the files below); otherwise traffic is
-# reported as null.
+# size moves to what the same counter reads for it.  Valid only for the stage
+# kernel's sources they were taken on (SHA-256 below: kernels.hip up to the
+# adjoint section, the stage launcher, kernels.hpp and facetypes.hpp);
+# otherwise traffic is reported as null.
 TRAFFIC = {
-    "sources_sha256": "f6ee9cf72e0d229c5247ecbfe00f3d76bb6c2bff9a76cbdb761d29b0edb56d7c",
+    "sources_sha256": "82518a7ce691efc259c3f7dd3329014672aae566ed7a1dc597c4f3f976a5baaf",
     "fetch_kib_per_launch": 66464.7,    # mean over the 90 timed launches
     "write_kib_per_launch": 67360.0,
     "fetch_scale": 1048576.0 / 524301.8,  # 1 GiB copy: FETCH_SIZE reads 524301.8 KiB
     "write_scale": 1048576.0 / 1048576.0,  # 1 GiB copy: WRITE_SIZE reads 1048576.0 KiB
 }
-KERNEL_SOURCES = ("paper_2404_16648_amd/csrc/kernels.hip", "paper_2404_16648_amd/csrc/kernels.hpp",
-                  "paper_2404_16648_amd/csrc/facetypes.hpp")
+CSRC = os.path.join(ROOT, "paper_2404_16648_amd", "csrc")
 
 
 def kernel_sources_sha256():
+    """SHA-256 of the stage kernel's sources, or None if they cannot be delimited."""
     import hashlib
+    with open(os.path.join(CSRC, "kernels.hip")) as f:
+        src = f.read()
+    a = src.find("// ---------------------------------------------------------------- adjoint")
+    b = src.find("hipError_t launch_stage(")
+    c = src.find("\n}\n", b)
+    if a < 0 or b < 0 or c < 0:
+        return None
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
+    h.update(src[:a].encode())
+    h.update(src[b:c].encode())
+    for name in ("kernels.hpp", "facetypes.hpp"):
+        with open(os.path.join(CSRC, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 

@@ -1014,11 +1014,9 @@ __global__ void k_node_coords(int64_t K, int N1, const double* c1d, double* xyz)
 // k_family_reduce: one leaf = (A x A x A) applied to a family block, A an
 //   (N+1) x (2N+2) matrix: coarsening, A = [R_0 | R_1]; transpose of refinement,
 //   A = [I_0^T | I_1^T].
-// k_family_expand: a family block = (B x B x B) applied to one leaf, B a
-//   (2N+2) x (N+1) matrix: refinement, B = [I_0 ; I_1]; transpose of
-//   coarsening, B = [R_0^T ; R_1^T].
 // Three separable passes per variable; kept leaves are copied.  The block of a
-// refined family is the one at child 0; the others return at once.
+// refined family is the one at child 0; the others return at once.  The
+// opposite direction (one leaf to its children) is k_expand, one child per block.
 
 // copy of a kept leaf: forward q_to[e] = q_from[src]; transpose qbar_from[src] = qbar_to[e]
 template <int N, bool ADJ>
@@ -1099,30 +1097,43 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_family_reduce(const XferArgs A) {
     }
 }
 
+// One child of a family per workgroup: child c = (a, b, c') of leaf li gets
+// (B_a x B_b x B_c') applied to it, three separable passes per variable:
+// refinement, B_h = I_h (grid over the plan's child entries); transpose of
+// coarsening, B_h = R_h^T (grid over the plan's entries x 8 children).
 template <int N, bool ADJ>
-__global__ void __launch_bounds__(Sz<N>::NT) k_family_expand(const XferArgs A) {
+__global__ void __launch_bounds__(Sz<N>::NT) k_expand(const XferArgs A) {
     constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
-    constexpr int M = 2 * N1;
-    __shared__ double sIn[NP];
-    __shared__ double s1[N1 * N1 * M];  // [k][j][I]
-    __shared__ double s2[N1 * M * M];   // [k][J][I]
-    __shared__ double sB[M * N1];       // sB[m (N+1) + i]
+    __shared__ double sIn[NP], s1[NP], s2[NP];
+    __shared__ double sM[3 * NF];  // the 1-D operator along x, y, z: sM[d NF + r (N+1) + col]
     const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
     const int t = threadIdx.x;
     const int64_t src = A.src[e];
     const int kind = A.kind[e];
     if (kind == DG_KIND_COPY) {  // uniform over the block
-        xfer_copy<N, ADJ>(A, e, src, t);
+        if (blockIdx.y == 0) xfer_copy<N, ADJ>(A, e, src, t);
         return;
     }
-    if (!ADJ && kind != 0) return;  // refined family: handled by the block of child 0
-    const int64_t li = ADJ ? e : src, fine0 = ADJ ? src : e;
-    const int64_t KinNP = A.Kin * NP, KoutNP = A.Kout * NP;
-    for (int x = t; x < M * N1; x += NT) {
-        const int m = x / N1, i = x % N1, h = m / N1, r = m % N1;
-        sB[x] = ADJ ? A.ops[(3 + h) * NF + i * N1 + r]    // R_h^T[r][i]
-                    : A.ops[(1 + h) * NF + r * N1 + i];   // I_h[r][i]
+    int c;
+    int64_t li, lo;
+    if (!ADJ) {  // refined leaf src: this entry is its child `kind`
+        if (kind < 0 || kind > 7) return;
+        c = kind;
+        li = src;
+        lo = e;
+    } else {  // merged parent e: its child blockIdx.y is source leaf src + c
+        if (kind != DG_KIND_FAMILY) return;
+        c = (int)blockIdx.y;
+        li = e;
+        lo = src + c;
     }
+    for (int x = t; x < 3 * NF; x += NT) {
+        const int d = x / NF, r = (x % NF) / N1, col = x % N1, h = (c >> d) & 1;
+        sM[x] = ADJ ? A.ops[(3 + h) * NF + col * N1 + r]    // R_h^T[r][col]
+                    : A.ops[(1 + h) * NF + r * N1 + col];   // I_h[r][col]
+    }
+    const int64_t KinNP = A.Kin * NP, KoutNP = A.Kout * NP;
+    const int i = t % N1, j = (t / N1) % N1, k = t / NF;
     double p[5] = {0, 0, 0, 0, 0};  // the leaf's five values at this node, loaded at once
     if (t < NP)
 #pragma unroll
@@ -1132,33 +1143,25 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_family_expand(const XferArgs A) {
         __syncthreads();
         if (t < NP) sIn[t] = p[v];
         __syncthreads();
-        // x: s1[k][j][I] = sum_i B[I][i] in[k][j][i]
-        for (int x = t; x < N1 * N1 * M; x += NT) {
-            const int I = x % M, row = x / M;
+        if (t < NP) {
             double acc = 0.0;
 #pragma unroll
-            for (int i = 0; i < N1; ++i) acc = fma(sB[I * N1 + i], sIn[row * N1 + i], acc);
-            s1[x] = acc;
+            for (int m = 0; m < N1; ++m) acc = fma(sM[i * N1 + m], sIn[m + N1 * (j + N1 * k)], acc);
+            s1[t] = acc;
         }
         __syncthreads();
-        // y: s2[k][J][I] = sum_j B[J][j] s1[k][j][I]
-        for (int x = t; x < N1 * M * M; x += NT) {
-            const int I = x % M, J = (x / M) % M, kk = x / (M * M);
+        if (t < NP) {
             double acc = 0.0;
 #pragma unroll
-            for (int j = 0; j < N1; ++j) acc = fma(sB[J * N1 + j], s1[(kk * N1 + j) * M + I], acc);
-            s2[x] = acc;
+            for (int m = 0; m < N1; ++m) acc = fma(sM[NF + j * N1 + m], s1[i + N1 * (m + N1 * k)], acc);
+            s2[t] = acc;
         }
         __syncthreads();
-        // z: child c, node n: out = sum_k B[K][k] s2[k][J][I]
-        for (int x = t; x < 8 * NP; x += NT) {
-            const int c = x / NP, n = x % NP;
-            const int I = (c & 1) * N1 + n % N1, J = ((c >> 1) & 1) * N1 + (n / N1) % N1,
-                      Kf = (c >> 2) * N1 + n / NF;
+        if (t < NP) {
             double acc = 0.0;
 #pragma unroll
-            for (int k = 0; k < N1; ++k) acc = fma(sB[Kf * N1 + k], s2[(k * M + J) * M + I], acc);
-            A.qout[v * KoutNP + (fine0 + c) * NP + n] = acc;
+            for (int m = 0; m < N1; ++m) acc = fma(sM[2 * NF + k * N1 + m], s2[i + N1 * (j + N1 * m)], acc);
+            A.qout[v * KoutNP + lo * NP + t] = acc;
         }
     }
 }
@@ -1377,7 +1380,7 @@ hipError_t launch_refine(int N, bool adjoint, const XferArgs& a, hipStream_t s) 
     if (adjoint) {
         DG_DISPATCH_N(N, (k_family_reduce<NN, true><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
     } else {
-        DG_DISPATCH_N(N, (k_family_expand<NN, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        DG_DISPATCH_N(N, (k_expand<NN, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
     }
     return hipGetLastError();
 }
@@ -1386,7 +1389,7 @@ hipError_t launch_coarsen(int N, bool adjoint, const XferArgs& a, hipStream_t s)
     if (a.Kto <= 0) return hipSuccess;
     const dim3 grid((unsigned)a.Kto);
     if (adjoint) {
-        DG_DISPATCH_N(N, (k_family_expand<NN, true><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        DG_DISPATCH_N(N, (k_expand<NN, true><<<dim3((unsigned)a.Kto, 8), dim3(Sz<NN>::NT), 0, s>>>(a)));
     } else {
         DG_DISPATCH_N(N, (k_family_reduce<NN, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
     }
