@@ -308,7 +308,11 @@ def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us):
     g = torch.empty_like(q)
     rhs_us = _time_launches(torch, lambda: dg.dg_rhs(mesh, ph, q, Ra), 20)
     adj_us = _time_launches(torch, lambda: dg.dg_rhs_adjoint(mesh, ph, q, lam, g), 20)
-    out["adjoint_rhs"] = {"rhs_us": rhs_us, "rhs_adjoint_us": adj_us, "ratio": adj_us / rhs_us}
+    gm = torch.empty_like(q)
+    adjm_us = _time_launches(torch, lambda: dg.dg_rhs_adjoint(mesh, mixed, q, lam, gm), 20)
+    out["adjoint_rhs"] = {"rhs_us": rhs_us, "rhs_adjoint_us": adj_us, "ratio": adj_us / rhs_us,
+                          "rhs_adjoint_us_mixed": adjm_us,
+                          "mixed_rel_l2_vs_fp64_fields(rho',momentum,Theta')": _field_err(torch, gm, g)}
     # ---- adjoint configuration: 16^3 hexes, N = 4, 50 SSP-RK3 steps, checkpoints every 10
     m4 = dg.dg_mesh_build(4, (16, 16, 16), 0, (0.0, 0.0, 0.0), (1000.0, 1000.0, 1000.0))
     q4 = m4.field()

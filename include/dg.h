@@ -198,7 +198,11 @@ dg_status dg_coarsen_project_adjoint(const dg_mesh* from, const dg_mesh* to, con
 
 /* qbar := (dR/dq)^T lam, the exact transpose of the linearised right-hand side
  * in the Euclidean inner product on the DOF vector (d|x|/dx := 0 at 0, a max
- * tie splits the derivative 1/2, 1/2).  qbar must not alias q or lam. */
+ * tie splits the derivative 1/2, 1/2).  qbar must not alias q or lam.  With
+ * phys->precision == DG_MIXED the transposed volume contractions D^T lam run in
+ * float32 (lam rounded to float32, D split into float32 high and low parts,
+ * float32 accumulation); faces, mortars, the chain rule and the output stay
+ * float64 (relative error of the order 1e-7 against the float64 transpose). */
 dg_status dg_rhs_adjoint(const dg_mesh* mesh, const dg_phys* phys, const double* q,
                          const double* lam, double* qbar, void* stream);
 

@@ -493,7 +493,6 @@ static dg_status adjoint_common(const dg_mesh* mc, const dg_phys* phys, int mode
     dg_status st = check_dev_mesh(mc);
     if (st) return st;
     if ((st = check_phys(phys))) return st;
-    if (phys->precision != DG_FP64) return fail(DG_EUNSUPPORTED, "the adjoint runs in float64 only");
     if (!q || !lam || !out) return fail(DG_EINVAL, "NULL field pointer");
     if (out == q || out == lam) return fail(DG_EINVAL, "output must not alias q or lam");
     if ((a1 != 0.0 && !w1) || (a2 != 0.0 && !w2)) return fail(DG_EINVAL, "NULL w1/w2 with a non-zero weight");
@@ -519,7 +518,7 @@ static dg_status adjoint_common(const dg_mesh* mc, const dg_phys* phys, int mode
     a.gamma = phys->cp / phys->cv;
     a.g = phys->g;
     a.binom = binom_coef(phys);
-    HIP_TRY(launch_adjoint(m->h.desc.N, mode, a, s));
+    HIP_TRY(launch_adjoint(m->h.desc.N, mode, phys->precision == DG_MIXED, a, s));
     return DG_OK;
 }
 

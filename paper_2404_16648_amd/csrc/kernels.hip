@@ -655,17 +655,24 @@ struct AdjLds {
 };
 
 // the adjoint keeps more state per node; bound it less tightly than the forward
-template <int N>
+template <int N, bool MIX>
 struct AdjOcc {
-    static constexpr int W = N >= 6 ? 2 : 3;
+    // MIX at N = 7 fits two workgroups per CU in LDS; 4 waves per SIMD lets them
+    // both run (a few registers spill; measured faster than 2 waves per SIMD)
+    static constexpr int W = N >= 6 ? (MIX && N == 7 ? 4 : 2) : 3;
 };
 
-template <int N, int MODE>
-__global__ void __launch_bounds__(Sz<N>::NT) __attribute__((amdgpu_waves_per_eu(AdjOcc<N>::W)))
+// MIX: the transposed volume contractions D^T lam in float32 (lambda tile rounded
+// to float32, D split into float32 high and low parts, float32 accumulation); the
+// faces read lambda from memory in float64, and everything else stays float64.
+template <int N, int MODE, bool MIX>
+__global__ void __launch_bounds__(Sz<N>::NT) __attribute__((amdgpu_waves_per_eu(AdjOcc<N, MIX>::W)))
 k_adjoint(const AdjArgs A) {
     constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
     constexpr int NOPS = Sz<N>::NOPS + 4 * NF;  // + I_0^T, I_1^T, R_0^T, R_1^T
-    __shared__ double sL[5 * NP];        // lambda tile
+    __shared__ double sL[MIX ? (5 * NP + 1) / 2 : 5 * NP];  // lambda tile (MIX: float)
+    __shared__ float sD32[MIX ? 2 * N1 * N1 : 1];            // MIX: D high and low parts
+    float* const sLf = reinterpret_cast<float*>(sL);
     __shared__ double sPp[NP];
     __shared__ double sS[30 * NF];       // face contributions to qbar
     __shared__ double sX[AdjLds<N>::SCR];
@@ -693,6 +700,13 @@ k_adjoint(const AdjArgs A) {
     const int i = t % N1, j = (t / N1) % N1, k = t / NF;
 
     for (int ii = t; ii < NOPS; ii += NT) sOps[ii] = A.ops[ii];
+    if (MIX)
+        for (int ii = t; ii < N1 * N1; ii += NT) {
+            const double dv = A.ops[ii];
+            const float hi = (float)dv;
+            sD32[ii] = hi;
+            sD32[N1 * N1 + ii] = (float)(dv - (double)hi);
+        }
     if (t < 3 * N1) sBg[t] = A.bg[(t / N1) * KN1 + e * N1 + (t % N1)];
     if (t < 6) sType[t] = A.ftype[e * 6 + t];
     if (t < 24) sNb[t] = A.fnb[e * 24 + t];
@@ -702,7 +716,10 @@ k_adjoint(const AdjArgs A) {
         for (int v = 0; v < 5; ++v) {
             q[v] = qe[v * KNP + t];
             lam[v] = le[v * KNP + t];
-            sL[v * NP + t] = lam[v];
+            if (MIX)
+                sLf[v * NP + t] = (float)lam[v];
+            else
+                sL[v * NP + t] = lam[v];
         }
         sPp[t] = pprime(q[4], A.bg[KN1 + e * N1 + k], A.bg[2 * KN1 + e * N1 + k], gamma, A.binom);
     }
@@ -724,7 +741,7 @@ k_adjoint(const AdjArgs A) {
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 qL[v] = qe[v * KNP + n];
-                lL[v] = sL[v * NP + n];
+                lL[v] = MIX ? le[v * KNP + n] : sL[v * NP + n];
             }
             const Bg bL{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
             const double PpL = sPp[n];
@@ -795,7 +812,7 @@ k_adjoint(const AdjArgs A) {
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
                     qL[v] = qe[v * KNP + n];
-                    lL[v] = sL[v * NP + n];
+                    lL[v] = MIX ? le[v * KNP + n] : sL[v * NP + n];
                     qM[v] = sMq[v * NF + m];
                     w[v] = -lift * lL[v] + liftcoarse * sMq[(5 + v) * NF + m];
                 }
@@ -814,7 +831,7 @@ k_adjoint(const AdjArgs A) {
                 const int v = it / NF, m = it % NF;
                 const int n = face_node<N>(f, m);
                 sT[it] = qe[v * KNP + n];
-                sT2[it] = sL[v * NP + n];
+                sT2[it] = MIX ? le[v * KNP + n] : sL[v * NP + n];
             }
             __syncthreads();
             // sU plane a*10 + c: along t1 with I_a (c < 5, state) or R_a^T (c >= 5, lambda)
@@ -883,7 +900,7 @@ k_adjoint(const AdjArgs A) {
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
                     qL[v] = qe[v * KNP + n];
-                    lL[v] = sL[v * NP + n];
+                    lL[v] = MIX ? le[v * KNP + n] : sL[v * NP + n];
                     g[v] = sU[v * NF + m];
                 }
                 with_axis(f >> 1, [&](auto dc) {
@@ -914,11 +931,23 @@ k_adjoint(const AdjArgs A) {
             double a[5];
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
-                const double* Lp = sL + v * NP + base;
-                double acc = 0.0;
+                if (MIX) {
+                    const float* Lp = sLf + v * NP + base;
+                    float ah = 0.0f, al = 0.0f;
 #pragma unroll
-                for (int m = 0; m < N1; ++m) acc = fma(D[m * N1 + id], Lp[m * stride], acc);
-                a[v] = -g2 * acc;
+                    for (int m = 0; m < N1; ++m) {
+                        const float lv = Lp[m * stride];
+                        ah = fmaf(sD32[m * N1 + id], lv, ah);
+                        al = fmaf(sD32[N1 * N1 + m * N1 + id], lv, al);
+                    }
+                    a[v] = -g2 * ((double)ah + (double)al);
+                } else {
+                    const double* Lp = sL + v * NP + base;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int m = 0; m < N1; ++m) acc = fma(D[m * N1 + id], Lp[m * stride], acc);
+                    a[v] = -g2 * acc;
+                }
             }
             if (d == 0) flux_vjp<0>(q, rinv, vel[0], Th, dPdT, a, g);
             if (d == 1) flux_vjp<1>(q, rinv, vel[1], Th, dPdT, a, g);
@@ -1342,12 +1371,21 @@ hipError_t launch_stage(int N, int mode, bool mixed, const StageArgs& a, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint(int N, int mode, const AdjArgs& a, hipStream_t s) {
+hipError_t launch_adjoint(int N, int mode, bool mixed, const AdjArgs& a, hipStream_t s) {
     if (a.K <= 0) return hipSuccess;
-    if (mode == MODE_RHS) {
-        DG_DISPATCH_N(N, (k_adjoint<NN, MODE_RHS><<<dim3((unsigned)a.K), dim3(Sz<NN>::NT), 0, s>>>(a)));
+    const dim3 grid((unsigned)a.K);
+    if (mixed) {
+        if (mode == MODE_RHS) {
+            DG_DISPATCH_N(N, (k_adjoint<NN, MODE_RHS, true><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        } else {
+            DG_DISPATCH_N(N, (k_adjoint<NN, MODE_RK, true><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        }
     } else {
-        DG_DISPATCH_N(N, (k_adjoint<NN, MODE_RK><<<dim3((unsigned)a.K), dim3(Sz<NN>::NT), 0, s>>>(a)));
+        if (mode == MODE_RHS) {
+            DG_DISPATCH_N(N, (k_adjoint<NN, MODE_RHS, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        } else {
+            DG_DISPATCH_N(N, (k_adjoint<NN, MODE_RK, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        }
     }
     return hipGetLastError();
 }

@@ -95,7 +95,7 @@ struct IndArgs {
 };
 
 hipError_t launch_stage(int N, int mode, bool mixed, const StageArgs& a, hipStream_t s);
-hipError_t launch_adjoint(int N, int mode, const AdjArgs& a, hipStream_t s);
+hipError_t launch_adjoint(int N, int mode, bool mixed, const AdjArgs& a, hipStream_t s);
 hipError_t launch_background(int64_t K, int N, const double* c1d, double* bg, const BgParams& p, hipStream_t s);
 hipError_t launch_init_bell(int64_t K, int N, const double* c1d, const double* bg, double theta0, const dg_bell& b,
                             double* q, hipStream_t s);

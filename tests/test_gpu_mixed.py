@@ -95,3 +95,48 @@ def test_mixed_hydrostatic_rest_exact():
     dg.dg_rhs(lm, MIXED, z, R)
     torch.cuda.synchronize()
     assert torch.count_nonzero(R) == 0
+
+
+@pytest.mark.parametrize("N", [3, 7])
+def test_mixed_adjoint_random_amr(N):
+    """dg_rhs_adjoint and dg_rk_stage_adjoint with the precision split (transposed
+    volume contractions in float32) against the float64 oracle adjoint."""
+    od = oracle_desc(N, (2, 2, 2), 2, *BOX, (0, 0, 0))
+    lm, om = both_meshes(N, (2, 2, 2), 2, flag_seq=random_refinements(od, 2, 80 + N))
+    op = eu.Operator(om, oracle_phys(MIXED))
+    qn = torch.as_tensor(random_state(om.K, N, 81 + N))
+    ln = torch.as_tensor(random_state(om.K, N, 82 + N, (1.0,) * 5))
+    wn = torch.as_tensor(random_state(om.K, N, 83 + N, (1.0,) * 5))
+    want = eu.rhs_adjoint(op, to_elem(qn, N), to_elem(ln, N))
+    g = lm.field()
+    dg.dg_rhs_adjoint(lm, MIXED, gpu(qn), gpu(ln), g)
+    check(g, want, f"mixed adjoint N={N}")
+    dt = 0.01
+    dg.dg_rk_stage_adjoint(lm, MIXED, 0.5, gpu(wn), 0.0, None, 0.25, dt, gpu(qn), gpu(ln), g)
+    E = lambda t: to_elem(t, N)
+    check(g, 0.5 * E(wn) + 0.25 * (E(ln) + dt * want), f"mixed stage adjoint N={N}")
+
+
+def test_mixed_gradient_through_steps():
+    """Checkpointed gradient of a functional through 10 SSP-RK3 steps, forward and
+    adjoint with the precision split, against the float64 gradient (both from the
+    library; the float64 path is itself pinned to the oracle and to finite
+    differences)."""
+    from paper_2404_16648_amd import adjoint as adj
+    od = oracle_desc(4, (4, 4, 4), 1, *BOX, (0, 0, 0))
+    lm, om = both_meshes(4, (4, 4, 4), 1, flag_seq=random_refinements(od, 1, 84, p=0.2))
+    ph = dg.PhysParams()
+    op = eu.Operator(om, oracle_phys(ph))
+    q0 = gpu(to_nodes(eu.bubble_state(op)))
+    wm = gpu(to_nodes(eu.quad_weights(op)[None])[0])
+
+    def grad(phys):
+        x = q0.clone().requires_grad_(True)
+        qT = adj.integrate(x, lm, phys, 0.02, 10, 5)
+        (g,) = torch.autograd.grad((wm * qT[4] * qT[4]).sum() + (wm * qT[0] * qT[0]).sum(), x)
+        return g
+
+    g64, gmx = grad(ph), grad(MIXED)
+    err = field_errors(gmx, g64)
+    print("mixed gradient vs float64", ["%.2e" % x for x in err], flush=True)
+    assert max(err) <= TOL_MIXED
