@@ -35,8 +35,8 @@ STAGE_KERNEL = "k_stage<7, 1, false>"
 # adjoint section, the stage launcher, kernels.hpp and facetypes.hpp);
 # otherwise traffic is reported as null.
 TRAFFIC = {
-    "sources_sha256": "82518a7ce691efc259c3f7dd3329014672aae566ed7a1dc597c4f3f976a5baaf",
-    "fetch_kib_per_launch": 66464.7,    # mean over the 90 timed launches
+    "sources_sha256": "2b6a46592b275369bbe0bb65ae5f0c625761c1a35121eb95b7c41300669259af",
+    "fetch_kib_per_launch": 66707.8,    # mean over the 90 timed launches
     "write_kib_per_launch": 67360.0,
     "fetch_scale": 1048576.0 / 524301.8,  # 1 GiB copy: FETCH_SIZE reads 524301.8 KiB
     "write_scale": 1048576.0 / 1048576.0,  # 1 GiB copy: WRITE_SIZE reads 1048576.0 KiB

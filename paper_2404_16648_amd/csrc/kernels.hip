@@ -204,7 +204,7 @@ struct StageLds {
         return (planes * NP * ESZ + 7) / 8 > 45 * NF ? (planes * NP * ESZ + 7) / 8 : 45 * NF;
     }
     // bytes of the other LDS arrays of k_stage
-    static constexpr int FIXED = 8 * (30 * NF + NP + Sz<N>::NOPS + 3 * N1) + 4 * 2 * N1 * N1 + 4 * 30;
+    static constexpr int FIXED = 8 * (30 * NF + Sz<N>::NOPS + 3 * N1) + 4 * 2 * N1 * N1 + 4 * 30;
     static constexpr int blocks(int planes) {
         const int by_lds = 160 * 1024 / (FIXED + 8 * work_dbl(planes));
         const int by_waves = 4 * StageOcc<N>::W / (Sz<N>::NT / 64);
@@ -227,7 +227,6 @@ k_stage(const StageArgs A) {
     __shared__ double sS[30 * NF];
     __shared__ double sW[StageLds<N, MIX>::WORK];
     __shared__ float sD32[2 * N1 * N1];  // MIX: D high and low parts
-    __shared__ double sPp[NP];
     __shared__ double sOps[Sz<N>::NOPS];
     __shared__ double sBg[3 * N1];
     __shared__ int sType[6];
@@ -249,8 +248,6 @@ k_stage(const StageArgs A) {
     if (t < 3 * N1) sBg[t] = A.bg[(int64_t)(t / N1) * K * N1 + e * N1 + (t % N1)];
     if (t < 6) sType[t] = A.ftype[e * 6 + t];
     if (t < 24) sNb[t] = A.fnb[e * 24 + t];
-    if (t < NP) sPp[t] = pprime(qe[4 * KNP + t], A.bg[K * N1 + e * N1 + k], A.bg[2 * K * N1 + e * N1 + k],
-                                gamma, A.binom);
     __syncthreads();
 
     // ---- faces: conforming neighbours and walls, every (face, node) item
@@ -274,7 +271,7 @@ k_stage(const StageArgs A) {
 #pragma unroll
             for (int v = 0; v < 5; ++v) qL[v] = qe[v * KNP + n];
             const Bg bL{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
-            const double PpL = sPp[n];
+            const double PpL = pprime(qL[4], bL.Th, bL.P, gamma, A.binom);
             Bg bR = bL;
             double PpR = PpL;
             if (type == FT_WALL) {
@@ -335,7 +332,8 @@ k_stage(const StageArgs A) {
                 const double PpM = pprime(qM[4], b.Th, b.P, gamma, A.binom);
                 double Fs[5], Fo[5];
                 with_axis(f >> 1, [&](auto dc) {
-                    rusanov<decltype(dc)::value>(qL, b, sPp[n], qM, b, PpM, sgn, gamma, Fs, Fo);
+                    rusanov<decltype(dc)::value>(qL, b, pprime(qL[4], b.Th, b.P, gamma, A.binom), qM, b, PpM, sgn,
+                                                 gamma, Fs, Fo);
                 });
 #pragma unroll
                 for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = (Fs[v] - Fo[v]) * lift;
@@ -410,7 +408,8 @@ k_stage(const StageArgs A) {
                 double qL[5], Fo[5], lam;
 #pragma unroll
                 for (int v = 0; v < 5; ++v) qL[v] = qe[v * KNP + n];
-                with_axis(f >> 1, [&](auto dc) { flux_n<decltype(dc)::value>(qL, b, sPp[n], sgn, gamma, Fo, lam); });
+                const double PpL = pprime(qL[4], b.Th, b.P, gamma, A.binom);
+                with_axis(f >> 1, [&](auto dc) { flux_n<decltype(dc)::value>(qL, b, PpL, sgn, gamma, Fo, lam); });
 #pragma unroll
                 for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = (sU[v * NF + m] - Fo[v]) * lift;
             }
@@ -421,14 +420,20 @@ k_stage(const StageArgs A) {
     // ---- volume term: R = S - sum_d (2/h_d) D_d F^d, fluxes staged in LDS
     double q[5] = {0, 0, 0, 0, 0}, vel[3] = {0, 0, 0}, Pp = 0.0, Th = 0.0;
     double R[5] = {0, 0, 0, 0, 0};
+    // q0 of the update (stage form, a != 0) loaded with q: one memory round trip
+    double q0v[5] = {0, 0, 0, 0, 0};
+    const bool use_q0 = MODE == MODE_RK && A.a != 0.0;
     if (t < NP) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) q[v] = qe[v * KNP + t];
+        if (use_q0)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) q0v[v] = A.q0[v * KNP + e * NP + t];
         const double rinv = 1.0 / (sBg[k] + q[0]);
         vel[0] = q[1] * rinv;
         vel[1] = q[2] * rinv;
         vel[2] = q[3] * rinv;
-        Pp = sPp[t];
+        Pp = pprime(q[4], sBg[N1 + k], sBg[2 * N1 + k], gamma, A.binom);
         Th = sBg[N1 + k] + q[4];
         R[3] = -q[0] * A.g;  // buoyancy on rho*w
     }
@@ -439,7 +444,7 @@ k_stage(const StageArgs A) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) q0n[v] = qe[v * KNP];
         rinv0 = 1.0 / (sBg[0] + q0n[0]);
-        Pp0 = sPp[0];
+        Pp0 = pprime(q0n[4], sBg[N1], sBg[2 * N1], gamma, A.binom);
         Th0 = sBg[N1] + q0n[4];
         for (int ii = t; ii < N1 * N1; ii += NT) {
             const double dv = A.ops[ii];
@@ -549,11 +554,10 @@ k_stage(const StageArgs A) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) A.out[v * KNP + base] = R[v];
     } else {
-        const bool use_q0 = A.a != 0.0;
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
             double o = A.b * fma(A.dt, R[v], q[v]);
-            if (use_q0) o = fma(A.a, A.q0[v * KNP + base], o);
+            if (use_q0) o = fma(A.a, q0v[v], o);
             A.out[v * KNP + base] = o;
         }
     }
