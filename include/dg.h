@@ -160,7 +160,10 @@ dg_status dg_init_bell(const dg_mesh* mesh, const dg_phys* phys, const dg_bell* 
  * with F the Euler flux carrying the pressure perturbation P', S the buoyancy
  * -rho' g on rho*w, F* the Rusanov flux (local max wave speed, jump of the
  * perturbation variables), mirror states at walls and L2 mortars on hanging
- * faces (section 3.3).  rhs must not alias q. */
+ * faces (section 3.3).  rhs must not alias q.  The mortars are evaluated by a
+ * pre-pass into a workspace owned by the mesh, so calls of dg_rhs and
+ * dg_rk_stage on one mesh must be ordered (one stream, or synchronised);
+ * concurrent calls on different meshes are independent. */
 dg_status dg_rhs(const dg_mesh* mesh, const dg_phys* phys, const double* q, double* rhs,
                  void* stream);
 

@@ -2,6 +2,7 @@
 // and kernel launches.  Declarations and contracts are in include/dg.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -51,16 +52,18 @@ void free_device(dg_mesh* m) {
     m->d_base = nullptr;
     m->d_ops = m->d_geo = m->d_c1d = m->d_bg = m->d_red = m->d_eta = nullptr;
     m->d_ftype = m->d_fnb = m->d_level = m->d_xsrc = m->d_xkind = nullptr;
+    m->d_hslot = m->d_hang = nullptr;
+    m->d_mort = nullptr;
     m->d_flags = nullptr;
 }
 
 // byte offsets of the arrays in a mesh's one device block, 256-byte aligned;
 // [0, upload) is copied from the host, the rest is device workspace
 struct DevLayout {
-    size_t ops, geo, c1d, ft, nb, lv, xs, xk, upload, bg, red, eta, fl, total;
+    size_t ops, geo, c1d, ft, nb, hs, hg, lv, xs, xk, upload, bg, red, eta, fl, mort, total;
 };
 
-DevLayout dev_layout(int64_t K, int N, int64_t red_len) {
+DevLayout dev_layout(int64_t K, int N, int64_t red_len, int64_t n_hang) {
     const size_t N1 = (size_t)N + 1, k = (size_t)K;
     size_t end = 0;
     auto take = [&](size_t bytes) {
@@ -74,6 +77,8 @@ DevLayout dev_layout(int64_t K, int N, int64_t red_len) {
     L.c1d = take(sizeof(double) * 3 * k * N1);
     L.ft = take(sizeof(int32_t) * 6 * k);
     L.nb = take(sizeof(int32_t) * 24 * k);
+    L.hs = take(sizeof(int32_t) * 6 * k);
+    L.hg = take(sizeof(int32_t) * 6 * (size_t)n_hang);
     L.lv = take(sizeof(int32_t) * k);
     L.xs = take(sizeof(int32_t) * k);
     L.xk = take(sizeof(int32_t) * k);
@@ -82,6 +87,7 @@ DevLayout dev_layout(int64_t K, int N, int64_t red_len) {
     L.red = take(sizeof(double) * (size_t)red_len);
     L.eta = take(sizeof(double) * (k > 0 ? k : 1));
     L.fl = take(k > 0 ? k : 1);
+    L.mort = take(sizeof(double) * 25 * N1 * N1 * (size_t)n_hang);
     L.total = end;
     return L;
 }
@@ -93,6 +99,9 @@ void set_device_pointers(dg_mesh* m, char* base, const DevLayout& L) {
     m->d_c1d = (double*)(base + L.c1d);
     m->d_ftype = (int32_t*)(base + L.ft);
     m->d_fnb = (int32_t*)(base + L.nb);
+    m->d_hslot = (int32_t*)(base + L.hs);
+    m->d_hang = (int32_t*)(base + L.hg);
+    m->d_mort = (double*)(base + L.mort);
     m->d_level = (int32_t*)(base + L.lv);
     m->d_xsrc = (int32_t*)(base + L.xs);
     m->d_xkind = (int32_t*)(base + L.xk);
@@ -150,7 +159,8 @@ dg_status clone_device(dg_mesh* m, const dg_mesh* prev) {
     const HostMesh& h = m->h;
     const int64_t K = (int64_t)h.leaves.size();
     m->red_len = prev->red_len;
-    const DevLayout L = dev_layout(K, h.desc.N, m->red_len);
+    m->n_hang = prev->n_hang;
+    const DevLayout L = dev_layout(K, h.desc.N, m->red_len, m->n_hang);
     HIP_TRY(hipSetDevice(prev->device));
     m->device = prev->device;
     char* base = nullptr;
@@ -183,7 +193,8 @@ dg_status build_device(dg_mesh* m) {
         return clone_device(m, m->prev);
     const int N = h.desc.N, N1 = N + 1;
     m->red_len = (int64_t)budget_blocks(K) * 8 + 8;
-    const DevLayout L = dev_layout(K, N, m->red_len);
+    m->n_hang = (int64_t)h.hang.size() / 6;
+    const DevLayout L = dev_layout(K, N, m->red_len, m->n_hang);
     // one staging buffer and one copy for every table of the mesh; the background,
     // reduction and flag buffers are carved from the same block
     std::vector<char> up(L.upload, 0);
@@ -209,6 +220,15 @@ dg_status build_device(dg_mesh* m) {
     }
     std::memcpy(up.data() + L.ft, h.ftype.data(), sizeof(int32_t) * 6 * K);
     std::memcpy(up.data() + L.nb, h.fnb.data(), sizeof(int32_t) * 24 * K);
+    // hanging faces: each (leaf, face) on either side of a mortar knows its table row
+    int32_t* hs = (int32_t*)(up.data() + L.hs);
+    std::fill(hs, hs + 6 * K, -1);
+    for (int64_t r = 0; r < m->n_hang; ++r) {
+        const int32_t* row = &h.hang[6 * r];
+        hs[row[0] * 6 + row[1]] = (int32_t)r;
+        for (int q = 0; q < 4; ++q) hs[row[2 + q] * 6 + (row[1] ^ 1)] = (int32_t)r;
+    }
+    if (m->n_hang) std::memcpy(up.data() + L.hg, h.hang.data(), sizeof(int32_t) * 6 * m->n_hang);
     std::memcpy(up.data() + L.xs, h.xfer_src.data(), sizeof(int32_t) * K);
     std::memcpy(up.data() + L.xk, h.xfer_kind.data(), sizeof(int32_t) * K);
     HIP_TRY(hipGetDevice(&m->device));
@@ -275,6 +295,8 @@ StageArgs stage_args(const dg_mesh* m, const dg_phys* p) {
     a.bg = m->d_bg;
     a.ftype = m->d_ftype;
     a.fnb = m->d_fnb;
+    a.hslot = m->d_hslot;
+    a.mort = m->d_mort;
     a.K = (int64_t)m->h.leaves.size();
     a.gamma = p->cp / p->cv;
     a.g = p->g;
@@ -428,6 +450,10 @@ static dg_status stage_common(const dg_mesh* mc, const dg_phys* phys, int mode, 
     hipStream_t s = (hipStream_t)stream;
     if ((st = ensure_bg(m, phys, s))) return st;
     StageArgs args = stage_args(m, phys);
+    if (m->n_hang) {
+        MortArgs ma{qs, m->d_mort, m->d_ops, m->d_geo, m->d_bg, m->d_hang, m->n_hang, args.K, args.gamma, args.binom};
+        HIP_TRY(launch_mortar(m->h.desc.N, ma, s));
+    }
     args.q0 = q0;
     args.qs = qs;
     args.out = out;

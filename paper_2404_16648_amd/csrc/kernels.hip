@@ -184,36 +184,153 @@ __device__ __forceinline__ void apply_t2(const double* in, double* out, int np, 
     }
 }
 
-// waves per SIMD the stage kernel is compiled for (bounds the VGPR budget to 128)
+// waves per SIMD the stage kernel is compiled for (bounds its VGPR budget:
+// 6 -> 80, 5 -> 96 registers); with the mortars in their own pre-pass the stage
+// fits these, and at N = 7 three workgroups of 8 waves then share a CU
 template <int N>
 struct StageOcc {
-    static constexpr int W = 4;
+    static constexpr int W = N == 7 ? 6 : 5;
 };
 
-// LDS plan of the stage kernel: the work area holds first the face scratch (a
-// trace sT[5][NF] and the mortar fluxes sM[4][5][NF], doubles) and then the flux
-// planes of the volume phase: all 15 at once, or x and y, then z (one more
-// barrier).  All 15 only when that keeps as many workgroups per CU (160 KB of
-// LDS, W waves per SIMD) as the two-pass plan.  MIX stores the planes as float
-// (flux minus an element-constant reference).
+// LDS plan of the stage kernel: the work area holds the flux planes of the
+// volume phase: all 15 at once, or x and y, then z (one more barrier), or one
+// direction at a time (five planes; three more barriers).  The plan with the
+// most workgroups per CU (160 KB of LDS, W waves per SIMD) wins, the one with
+// fewer barriers on a tie.  MIX stores the planes as float (flux minus an
+// element-constant reference).
 template <int N, bool MIX>
 struct StageLds {
     static constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF;
     static constexpr int ESZ = MIX ? 4 : 8;
-    static constexpr int work_dbl(int planes) {
-        return (planes * NP * ESZ + 7) / 8 > 45 * NF ? (planes * NP * ESZ + 7) / 8 : 45 * NF;
-    }
+    static constexpr int work_dbl(int planes) { return (planes * NP * ESZ + 7) / 8; }
     // bytes of the other LDS arrays of k_stage
-    static constexpr int FIXED = 8 * (30 * NF + Sz<N>::NOPS + 3 * N1) + 4 * 2 * N1 * N1 + 4 * 30;
+    static constexpr int FIXED = 8 * (30 * NF + Sz<N>::NOPS + 3 * N1) + 4 * 2 * N1 * N1 + 4 * 36;
     static constexpr int blocks(int planes) {
         const int by_lds = 160 * 1024 / (FIXED + 8 * work_dbl(planes));
         const int by_waves = 4 * StageOcc<N>::W / (Sz<N>::NT / 64);
         return by_lds < by_waves ? by_lds : by_waves;
     }
-    static constexpr bool ALL3 = FIXED + 8 * work_dbl(15) <= 64 * 1024 && blocks(15) >= blocks(10);
-    static constexpr int PLANES = ALL3 ? 15 : 10;
+    static constexpr bool FITS15 = FIXED + 8 * work_dbl(15) <= 64 * 1024;
+    static constexpr int PLANES = FITS15 && blocks(15) >= blocks(10) && blocks(15) >= blocks(5) ? 15
+                                  : blocks(10) >= blocks(5)                                  ? 10
+                                                                                             : 5;
+    static constexpr bool ALL3 = PLANES == 15;
     static constexpr int WORK = work_dbl(PLANES);
 };
+
+// Mortar pre-pass (section 3.3, the three steps on the mortars of one hanging
+// face per workgroup): the coarse trace is interpolated to the four mortars
+// (I_a x I_b, two separable passes), the Riemann problem is solved on each
+// mortar point from the fine leaf's side, and the coarse side's flux is that
+// flux with the sign reversed (the Rusanov flux is antisymmetric bitwise), which
+// is projected back with R_a x R_b.  Output per hanging face h, lifted and
+// ready for the stage kernel: mort[h][0] the coarse face, mort[h][1 + quad] the
+// fine faces, each [5][NF].  The stage kernel copies these into its faces.
+template <int N>
+__global__ void __launch_bounds__(Sz<N>::NT) k_mortar(const MortArgs A) {
+    constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
+    static_assert(4 * NF <= NT, "one mortar point per thread");
+    __shared__ double sT[5 * NF], sU[10 * NF], sMq[20 * NF], sG[10 * NF];
+    __shared__ double sOps[Sz<N>::NOPS];
+    __shared__ double sBg[3 * N1];  // the coarse leaf's background
+    const int64_t h = xcd_remap(blockIdx.x, gridDim.x);
+    const int t = threadIdx.x;
+    const int32_t* const row = A.hang + h * 6;
+    const int64_t ec = row[0];
+    const int f = row[1], fo = f ^ 1;
+    const int KNP = (int)(A.K * NP), KN1 = (int)(A.K * N1);
+    const double gamma = A.gamma;
+    const double liftc = 0.5 * N * (N + 1);  // 1/w_N
+    const double sgn = (f & 1) ? 1.0 : -1.0;  // the coarse leaf's outward normal
+    const double* const qs = A.qs;
+    for (int ii = t; ii < Sz<N>::NOPS; ii += NT) sOps[ii] = A.ops[ii];
+    if (t < 3 * N1) sBg[t] = A.bg[(t / N1) * KN1 + ec * N1 + (t % N1)];
+    for (int it = t; it < 5 * NF; it += NT) {
+        const int v = it / NF, m = it % NF;
+        sT[it] = qs[v * KNP + ec * NP + face_node<N>(f, m)];
+    }
+    // this thread's fine-side point, loaded with the trace: quadrant t / NF
+    double qF[5];
+    Bg bF{};
+    int64_t ef = 0;
+    if (t < 4 * NF) {
+        const int quad = t / NF, m = t % NF;
+        ef = row[2 + quad];
+        const int nn = face_node<N>(fo, m), kn = face_k<N>(fo, m);
+        bF = Bg{A.bg[ef * N1 + kn], A.bg[KN1 + ef * N1 + kn], A.bg[2 * KN1 + ef * N1 + kn]};
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qF[v] = qs[v * KNP + ef * NP + nn];
+    }
+    __syncthreads();
+    // sU[a][v] = I_a along t1; sMq[quad][v] = I_b along t2 of sU[a]  (quad = a + 2b)
+    apply_t1<N>(sT, sU, 10, [&](int p) { return sOps + (1 + p / 5) * NF; }, [](int p) { return p % 5; }, t, NT);
+    __syncthreads();
+    apply_t2<N>(sU, sMq, 20, [&](int p) { return sOps + (1 + (p / 5) / 2) * NF; },
+                [](int p) { return ((p / 5) & 1) * 5 + p % 5; }, t, NT);
+    __syncthreads();
+    if (t < 4 * NF) {
+        const int quad = t / NF, m = t % NF;
+        double qM[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qM[v] = sMq[(quad * 5 + v) * NF + m];
+        const double PpF = pprime(qF[4], bF.Th, bF.P, gamma, A.binom);
+        const double PpM = pprime(qM[4], bF.Th, bF.P, gamma, A.binom);
+        double Fs[5], Fo[5];
+        with_axis(f >> 1, [&](auto dc) {
+            rusanov<decltype(dc)::value>(qF, bF, PpF, qM, bF, PpM, -sgn, gamma, Fs, Fo);
+        });
+        const double lift_f = A.geo[ef * 4 + (f >> 1)] * liftc;
+        double* const out = A.mort + ((h * 5 + 1 + quad) * 5) * NF + m;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            out[v * NF] = (Fs[v] - Fo[v]) * lift_f;
+            sMq[(quad * 5 + v) * NF + m] = -Fs[v];  // in place: the coarse side's flux
+        }
+    }
+    __syncthreads();
+    // projection back: sG[b][v] = sum_a R_a along t1 of F[a + 2b]; then sum_b R_b along t2
+    for (int it = t; it < 10 * NF; it += NT) {
+        const int p = it / NF, r = it % NF, bb = r / N1, a2 = r % N1;
+        const int qb = p / 5, v = p % 5;
+        double acc = 0.0;
+#pragma unroll
+        for (int qa = 0; qa < 2; ++qa) {
+            const double* Rm = sOps + (3 + qa) * NF + a2 * N1;
+            const double* x = sMq + ((qa + 2 * qb) * 5 + v) * NF + bb * N1;
+#pragma unroll
+            for (int a = 0; a < N1; ++a) acc = fma(Rm[a], x[a], acc);
+        }
+        sG[it] = acc;
+    }
+    __syncthreads();
+    for (int it = t; it < 5 * NF; it += NT) {
+        const int v = it / NF, m = it % NF, b2 = m / N1, a = m % N1;
+        double proj = 0.0;
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb) {
+            const double* Rm = sOps + (3 + qb) * NF + b2 * N1;
+            const double* x = sG + (qb * 5 + v) * NF + a;
+#pragma unroll
+            for (int bb = 0; bb < N1; ++bb) proj = fma(Rm[bb], x[bb * N1], proj);
+        }
+        sU[it] = proj;
+    }
+    __syncthreads();
+    if (t < NF) {
+        const int m = t;
+        const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
+        const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
+        double qL[5], Fo[5], lam;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qL[v] = qs[v * KNP + ec * NP + n];
+        const double PpL = pprime(qL[4], b.Th, b.P, gamma, A.binom);
+        with_axis(f >> 1, [&](auto dc) { flux_n<decltype(dc)::value>(qL, b, PpL, sgn, gamma, Fo, lam); });
+        const double lift_c = A.geo[ec * 4 + (f >> 1)] * liftc;
+        double* const out = A.mort + (h * 5 * 5) * NF + m;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) out[v * NF] = (sU[v * NF + m] - Fo[v]) * lift_c;
+    }
+}
 
 // MIX: the volume contractions in float32 on the flux minus the flux at the
 // leaf's first node (exact, since D annihilates constants), with D split into a
@@ -231,7 +348,7 @@ k_stage(const StageArgs A) {
     __shared__ double sBg[3 * N1];
     __shared__ int sType[6];
     __shared__ int sNb[24];
-    double* const sT = sW;               // [5][NF]     (hanging faces)
+    __shared__ int sHs[6];               // hanging face: row of the mortar pre-pass
 
     const int64_t K = A.K;
     const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
@@ -248,9 +365,11 @@ k_stage(const StageArgs A) {
     if (t < 3 * N1) sBg[t] = A.bg[(int64_t)(t / N1) * K * N1 + e * N1 + (t % N1)];
     if (t < 6) sType[t] = A.ftype[e * 6 + t];
     if (t < 24) sNb[t] = A.fnb[e * 24 + t];
+    if (t < 6) sHs[t] = A.hslot[e * 6 + t];
     __syncthreads();
 
-    // ---- faces: conforming neighbours and walls, every (face, node) item
+    // ---- faces, every (face, node) item: conforming neighbours and walls here;
+    // hanging faces (L2 mortars) copy what the mortar pre-pass computed
     const double liftc = 0.5 * N * (N + 1);  // 1/w_N
     // items grouped by axis, each axis padded to whole waves, so a wave never
     // mixes the three axis variants of the flux code
@@ -261,7 +380,12 @@ k_stage(const StageArgs A) {
         if (r >= 2 * NF) continue;
         const int f = 2 * ax + r / NF, m = r % NF;
         const int type = sType[f] & 0xff;
-        if (type != FT_WALL && type != FT_CONF) continue;
+        if (type == FT_FINE || type == FT_COARSE) {
+            const int64_t slot = (int64_t)sHs[f] * 5 + (type == FT_COARSE ? 0 : 1 + (sType[f] >> 8));
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = A.mort[(slot * 5 + v) * NF + m];
+            continue;
+        }
         const double sgn = (f & 1) ? 1.0 : -1.0;
         const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
         const double lift = A.geo[e * 4 + (f >> 1)] * liftc;
@@ -294,127 +418,6 @@ k_stage(const StageArgs A) {
         });
     }
 
-    // ---- hanging faces (L2 mortars), one face at a time (uniform over the block).
-    // Scratch in the work area: sT trace [5][NF], sU [10][NF], sM [20][NF], sG [10][NF].
-    double* const sU = sW + 5 * NF;
-    double* const sMq = sW + 15 * NF;
-    double* const sG = sW + 35 * NF;
-#pragma unroll 1
-    for (int f = 0; f < 6; ++f) {
-        const int type = sType[f] & 0xff;
-        if (type != FT_FINE && type != FT_COARSE) continue;
-        const int fo = f ^ 1;
-        const double lift = A.geo[e * 4 + (f >> 1)] * liftc;
-        const double sgn = (f & 1) ? 1.0 : -1.0;
-        if (type == FT_FINE) {
-            // this leaf is fine: mortar state = (I_a x I_b) of the coarse trace
-            const int ec = sNb[f * 4];
-            const int quad = sType[f] >> 8, qa = quad & 1, qb = quad >> 1;
-            __syncthreads();
-            for (int it = t; it < 5 * NF; it += NT) {
-                const int v = it / NF, m = it % NF;
-                sT[it] = qs[v * KNP + ec * NP + face_node<N>(fo, m)];
-            }
-            __syncthreads();
-            apply_t1<N>(sT, sU, 5, [&](int) { return sOps + (1 + qa) * NF; }, [](int p) { return p; }, t, NT);
-            __syncthreads();
-            apply_t2<N>(sU, sMq, 5, [&](int) { return sOps + (1 + qb) * NF; }, [](int p) { return p; }, t, NT);
-            __syncthreads();
-            for (int m = t; m < NF; m += NT) {
-                const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
-                const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
-                double qL[5], qM[5];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    qL[v] = qe[v * KNP + n];
-                    qM[v] = sMq[v * NF + m];
-                }
-                const double PpM = pprime(qM[4], b.Th, b.P, gamma, A.binom);
-                double Fs[5], Fo[5];
-                with_axis(f >> 1, [&](auto dc) {
-                    rusanov<decltype(dc)::value>(qL, b, pprime(qL[4], b.Th, b.P, gamma, A.binom), qM, b, PpM, sgn,
-                                                 gamma, Fs, Fo);
-                });
-#pragma unroll
-                for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = (Fs[v] - Fo[v]) * lift;
-            }
-        } else {
-            // this leaf is coarse: 4 mortars, Riemann problems, projection back
-            __syncthreads();
-            for (int it = t; it < 5 * NF; it += NT) {
-                const int v = it / NF, m = it % NF;
-                sT[it] = qe[v * KNP + face_node<N>(f, m)];
-            }
-            __syncthreads();
-            // sU[a][v] = I_a along t1; sMq[quad][v] = I_b along t2 of sU[a]  (quad = a + 2b)
-            apply_t1<N>(sT, sU, 10, [&](int p) { return sOps + (1 + p / 5) * NF; }, [](int p) { return p % 5; }, t,
-                        NT);
-            __syncthreads();
-            apply_t2<N>(sU, sMq, 20, [&](int p) { return sOps + (1 + (p / 5) / 2) * NF; },
-                        [](int p) { return ((p / 5) & 1) * 5 + p % 5; }, t, NT);
-            __syncthreads();
-            for (int it = t; it < 4 * NF; it += NT) {
-                const int quad = it / NF, m = it % NF;
-                const int ef = sNb[f * 4 + quad];
-                const int nn = face_node<N>(fo, m), kn = face_k<N>(fo, m);
-                const Bg b{A.bg[ef * N1 + kn], A.bg[K * N1 + ef * N1 + kn], A.bg[2 * K * N1 + ef * N1 + kn]};
-                double qM[5], qF[5];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    qM[v] = sMq[(quad * 5 + v) * NF + m];
-                    qF[v] = qs[v * KNP + ef * NP + nn];
-                }
-                const double PpM = pprime(qM[4], b.Th, b.P, gamma, A.binom);
-                const double PpF = pprime(qF[4], b.Th, b.P, gamma, A.binom);
-                double Fs[5], Fo[5];
-                with_axis(f >> 1, [&](auto dc) {
-                    rusanov<decltype(dc)::value>(qM, b, PpM, qF, b, PpF, sgn, gamma, Fs, Fo);
-                });
-#pragma unroll
-                for (int v = 0; v < 5; ++v) sMq[(quad * 5 + v) * NF + m] = Fs[v];  // in place
-            }
-            __syncthreads();
-            // projection back: sG[b][v] = sum_a R_a along t1 of F[a + 2b]; then sum_b R_b along t2
-            for (int it = t; it < 10 * NF; it += NT) {
-                const int p = it / NF, r = it % NF, bb = r / N1, a2 = r % N1;
-                const int qb = p / 5, v = p % 5;
-                double acc = 0.0;
-#pragma unroll
-                for (int qa = 0; qa < 2; ++qa) {
-                    const double* Rm = sOps + (3 + qa) * NF + a2 * N1;
-                    const double* x = sMq + ((qa + 2 * qb) * 5 + v) * NF + bb * N1;
-#pragma unroll
-                    for (int a = 0; a < N1; ++a) acc = fma(Rm[a], x[a], acc);
-                }
-                sG[it] = acc;
-            }
-            __syncthreads();
-            for (int it = t; it < 5 * NF; it += NT) {
-                const int v = it / NF, m = it % NF, b2 = m / N1, a = m % N1;
-                double proj = 0.0;
-#pragma unroll
-                for (int qb = 0; qb < 2; ++qb) {
-                    const double* Rm = sOps + (3 + qb) * NF + b2 * N1;
-                    const double* x = sG + (qb * 5 + v) * NF + a;
-#pragma unroll
-                    for (int bb = 0; bb < N1; ++bb) proj = fma(Rm[bb], x[bb * N1], proj);
-                }
-                sU[it] = proj;
-            }
-            __syncthreads();
-            for (int m = t; m < NF; m += NT) {
-                const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
-                const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
-                double qL[5], Fo[5], lam;
-#pragma unroll
-                for (int v = 0; v < 5; ++v) qL[v] = qe[v * KNP + n];
-                const double PpL = pprime(qL[4], b.Th, b.P, gamma, A.binom);
-                with_axis(f >> 1, [&](auto dc) { flux_n<decltype(dc)::value>(qL, b, PpL, sgn, gamma, Fo, lam); });
-#pragma unroll
-                for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = (sU[v * NF + m] - Fo[v]) * lift;
-            }
-        }
-    }
     __syncthreads();
 
     // ---- volume term: R = S - sum_d (2/h_d) D_d F^d, fluxes staged in LDS
@@ -522,7 +525,7 @@ k_stage(const StageArgs A) {
             contract(1, 1);
             contract(2, 2);
         }
-    } else {
+    } else if (StageLds<N, MIX>::PLANES == 10) {
         if (t < NP) {
             put_flux(0, 0);
             put_flux(1, 1);
@@ -536,6 +539,14 @@ k_stage(const StageArgs A) {
         if (t < NP) put_flux(2, 0);
         __syncthreads();
         if (t < NP) contract(2, 0);
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (d > 0) __syncthreads();
+            if (t < NP) put_flux(d, 0);
+            __syncthreads();
+            if (t < NP) contract(d, 0);
+        }
     }
 
     if (t >= NP) return;
@@ -1372,6 +1383,12 @@ hipError_t launch_stage(int N, int mode, bool mixed, const StageArgs& a, hipStre
             DG_DISPATCH_N(N, (k_stage<NN, MODE_RK, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
         }
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_mortar(int N, const MortArgs& a, hipStream_t s) {
+    if (a.n_hang <= 0) return hipSuccess;
+    DG_DISPATCH_N(N, (k_mortar<NN><<<dim3((unsigned)a.n_hang), dim3(Sz<NN>::NT), 0, s>>>(a)));
     return hipGetLastError();
 }
 

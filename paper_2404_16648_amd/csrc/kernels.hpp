@@ -27,6 +27,8 @@ struct StageArgs {
     const double* bg;      // [3][K][N1]
     const int32_t* ftype;  // [K][6]
     const int32_t* fnb;    // [K][6][4]
+    const int32_t* hslot;  // [K][6]: row of the hanging-face table, or -1
+    const double* mort;    // [n_hang][5][5][NF]: lifted mortar contributions (k_mortar)
     int64_t K;
     double a, b, dt;
     double gamma, g;
@@ -55,6 +57,19 @@ struct AdjArgs {
 struct BgParams {
     int32_t kind;
     double cp, cv, P0, g, theta0, rho0, Theta0;
+};
+
+// mortar pre-pass of a stage: one workgroup per row of the hanging-face table
+struct MortArgs {
+    const double* qs;      // [5][K][Np] stage input
+    double* mort;          // [n_hang][5][5][NF] output
+    const double* ops;
+    const double* geo;
+    const double* bg;
+    const int32_t* hang;   // [n_hang][6]: coarse leaf, its face, the 4 fine leaves by quadrant
+    int64_t n_hang, K;
+    double gamma;
+    BinomCoef binom;
 };
 
 // One launch per transfer: the grid runs over the Kto entries of the target
@@ -100,6 +115,7 @@ hipError_t launch_background(int64_t K, int N, const double* c1d, double* bg, co
 hipError_t launch_init_bell(int64_t K, int N, const double* c1d, const double* bg, double theta0, const dg_bell& b,
                             double* q, hipStream_t s);
 hipError_t launch_node_coords(int64_t K, int N, const double* c1d, double* xyz, hipStream_t s);
+hipError_t launch_mortar(int N, const MortArgs& a, hipStream_t s);
 // adjoint = false: the projection; true: its transpose
 hipError_t launch_refine(int N, bool adjoint, const XferArgs& a, hipStream_t s);
 hipError_t launch_coarsen(int N, bool adjoint, const XferArgs& a, hipStream_t s);
