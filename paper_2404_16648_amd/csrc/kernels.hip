@@ -204,7 +204,7 @@ struct StageLds {
     static constexpr int ESZ = MIX ? 4 : 8;
     static constexpr int work_dbl(int planes) { return (planes * NP * ESZ + 7) / 8; }
     // bytes of the other LDS arrays of k_stage
-    static constexpr int FIXED = 8 * (30 * NF + Sz<N>::NOPS + 3 * N1) + 4 * 2 * N1 * N1 + 4 * 36;
+    static constexpr int FIXED = 8 * (30 * NF + Sz<N>::NOPS + 3 * N1 + (MIX ? 15 : 1)) + 4 * 2 * N1 * N1 + 4 * 36;
     static constexpr int blocks(int planes) {
         const int by_lds = 160 * 1024 / (FIXED + 8 * work_dbl(planes));
         const int by_waves = 4 * StageOcc<N>::W / (Sz<N>::NT / 64);
@@ -349,6 +349,7 @@ k_stage(const StageArgs A) {
     __shared__ int sType[6];
     __shared__ int sNb[24];
     __shared__ int sHs[6];               // hanging face: row of the mortar pre-pass
+    __shared__ double sFr[MIX ? 15 : 1];  // MIX: reference flux [direction][variable]
 
     const int64_t K = A.K;
     const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
@@ -366,6 +367,32 @@ k_stage(const StageArgs A) {
     if (t < 6) sType[t] = A.ftype[e * 6 + t];
     if (t < 24) sNb[t] = A.fnb[e * 24 + t];
     if (t < 6) sHs[t] = A.hslot[e * 6 + t];
+    if (MIX) {
+        for (int ii = t; ii < N1 * N1; ii += NT) {
+            const double dv = A.ops[ii];
+            const float hi = (float)dv;
+            sD32[ii] = hi;
+            sD32[N1 * N1 + ii] = (float)(dv - (double)hi);
+        }
+        // element-constant reference flux: the flux at the leaf's first node, one
+        // direction per thread
+        if (t < 3) {
+            double q0n[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) q0n[v] = qe[v * KNP];
+            const double Thb = A.bg[K * N1 + e * N1], Pb = A.bg[2 * K * N1 + e * N1];
+            const double rinv0 = 1.0 / (A.bg[e * N1] + q0n[0]);
+            const double Pp0 = pprime(q0n[4], Thb, Pb, gamma, A.binom);
+            const double Th0 = Thb + q0n[4];
+            const double Ud = t == 0 ? q0n[1] : t == 1 ? q0n[2] : q0n[3];
+            const double u0 = Ud * rinv0;
+            sFr[t * 5 + 0] = Ud;
+            sFr[t * 5 + 1] = t == 0 ? q0n[1] * u0 + Pp0 : q0n[1] * u0;
+            sFr[t * 5 + 2] = t == 1 ? q0n[2] * u0 + Pp0 : q0n[2] * u0;
+            sFr[t * 5 + 3] = t == 2 ? q0n[3] * u0 + Pp0 : q0n[3] * u0;
+            sFr[t * 5 + 4] = Th0 * u0;
+        }
+    }
     __syncthreads();
 
     // ---- faces, every (face, node) item: conforming neighbours and walls here;
@@ -440,22 +467,6 @@ k_stage(const StageArgs A) {
         Th = sBg[N1 + k] + q[4];
         R[3] = -q[0] * A.g;  // buoyancy on rho*w
     }
-    // MIX: element-constant reference flux (at the leaf's first node, same address
-    // for every thread), formed per direction in put_flux
-    double q0n[5] = {0, 0, 0, 0, 0}, rinv0 = 0.0, Pp0 = 0.0, Th0 = 0.0;
-    if (MIX) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) q0n[v] = qe[v * KNP];
-        rinv0 = 1.0 / (sBg[0] + q0n[0]);
-        Pp0 = pprime(q0n[4], sBg[N1], sBg[2 * N1], gamma, A.binom);
-        Th0 = sBg[N1] + q0n[4];
-        for (int ii = t; ii < N1 * N1; ii += NT) {
-            const double dv = A.ops[ii];
-            const float hi = (float)dv;
-            sD32[ii] = hi;
-            sD32[N1 * N1 + ii] = (float)(dv - (double)hi);
-        }
-    }
     auto put_flux = [&](int d, int plane) {
         const double ud = vel[d];
         double F[5];
@@ -465,16 +476,9 @@ k_stage(const StageArgs A) {
         F[3] = d == 2 ? q[3] * ud + Pp : q[3] * ud;
         F[4] = Th * ud;
         if (MIX) {
-            const double u0 = q0n[1 + d] * rinv0;
-            double Fr[5];
-            Fr[0] = q0n[1 + d];
-            Fr[1] = d == 0 ? q0n[1] * u0 + Pp0 : q0n[1] * u0;
-            Fr[2] = d == 1 ? q0n[2] * u0 + Pp0 : q0n[2] * u0;
-            Fr[3] = d == 2 ? q0n[3] * u0 + Pp0 : q0n[3] * u0;
-            Fr[4] = Th0 * u0;
             float* Ff = reinterpret_cast<float*>(sW) + plane * 5 * NP;
 #pragma unroll
-            for (int v = 0; v < 5; ++v) Ff[v * NP + t] = (float)(F[v] - Fr[v]);
+            for (int v = 0; v < 5; ++v) Ff[v * NP + t] = (float)(F[v] - sFr[d * 5 + v]);
         } else {
             double* Fd = sW + plane * 5 * NP;
 #pragma unroll
