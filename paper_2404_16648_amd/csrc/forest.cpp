@@ -358,7 +358,10 @@ void forest_tables(HostMesh& m) {
             const int x = S.containing(c);
             if (x >= 0) {
                 if (S.leaves[x].l == lf.l) {
-                    m.ftype[e * 6 + f] = FT_CONF;
+                    const int rz = lf.r / (desc.nx * desc.ny);
+                    const bool wrap_z = d == 2 && (s ? rz == desc.nz - 1 && lf.a[2] == (1 << lf.l) - 1
+                                                     : rz == 0 && lf.a[2] == 0);
+                    m.ftype[e * 6 + f] = FT_CONF | (wrap_z ? FT_BG_NB : 0);
                 } else {
                     // this leaf is the fine side: quadrant from its tangential anchor bits
                     const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;

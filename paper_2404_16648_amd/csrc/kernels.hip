@@ -65,32 +65,71 @@ __device__ __forceinline__ int face_k(int f, int m) {
     return m / (N + 1);
 }
 
-// P' = P(Thetabar + Theta') - Pbar = Pbar ((1 + x)^gamma - 1), x = Theta'/Thetabar, in
-// cancellation-free form: for |x| <= 2^-7 the binomial series sum_{k=1..10} C(gamma,k) x^k
-// (Horner; truncation below 1e-17 relative), else expm1(gamma log1p(x)).
+// P' = P(Thetabar + Theta') - Pbar = Pbar F(x), F(x) = (1 + x)^gamma - 1, x = Theta'/Thetabar,
+// without cancellation: for |x| <= 2^-7 the binomial series sum_{k=1..10} C(gamma,k) x^k
+// (Horner; truncation below 1e-17 relative).  A larger |x| is first brought into that
+// range by halving log(1 + x): 1 + x = (1 + y)^2 with y = x / (1 + sqrt(1 + x)) (no
+// cancellation), repeated until |y| <= 2^-7, and F is rebuilt by F(x) = F(y) (F(y) + 2)
+// once per halving.  Only the series coefficients are needed (no special-function
+// constants, no call), so the rare wide-range path costs the kernels no registers.
 constexpr int kBinomTerms = 10;
 
-// |x| > 2^-7: kept out of line, so that the constants of expm1 and log1p are not
-// held in registers across the face loops of the kernels that inline pprime
-__device__ __attribute__((noinline)) double pow1p_m1(double x, double gamma) { return expm1(gamma * log1p(x)); }
-
-__device__ __forceinline__ double pprime(double Thp, double Thb, double Pb, double gamma, const BinomCoef& bc) {
-    const double x = Thp / Thb;
-    double r;
-    if (fabs(x) <= 0.0078125) {
-        double acc = bc.c[kBinomTerms - 1];
-#pragma unroll
-        for (int k = kBinomTerms - 2; k >= 0; --k) acc = fma(acc, x, bc.c[k]);
-        r = acc * x;
-    } else {
-        r = pow1p_m1(x, gamma);
+// x = Theta' (1/Thetabar): every kernel forms 1/Thetabar by the same IEEE division,
+// so a node's P' has the same bits wherever it is evaluated
+__device__ __forceinline__ double pprime(double Thp, double rThb, double Pb, double gamma, const BinomCoef& bc) {
+    double x = Thp * rThb;
+    int m = 0;
+    // every step halves |log(1 + x)|; NaN (and x <= -1) leave the loop at once
+    while (fabs(x) > 0.0078125 && m < 64) {
+        x = x / (1.0 + sqrt(1.0 + x));
+        ++m;
     }
+    double acc = bc.c[kBinomTerms - 1];
+#pragma unroll
+    for (int k = kBinomTerms - 2; k >= 0; --k) acc = fma(acc, x, bc.c[k]);
+    double r = acc * x;
+    for (; m > 0; --m) r = r * (r + 2.0);
     return Pb * r;
 }
 
+// 1/x for a positive normal x: the hardware reciprocal estimate refined by two
+// Newton steps (within about one ulp; the same bits for the same input), instead
+// of the scaled, correctly rounded division sequence
+__device__ __forceinline__ double rcp_pos(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// sqrt(a) for a positive normal a: reciprocal square-root estimate, one coupled
+// Newton step on (g, h) ~ (sqrt a, 1/(2 sqrt a)), two residual corrections (no
+// range scaling or special-value handling)
+__device__ __forceinline__ double sqrt_pos(double a) {
+    const double y = __builtin_amdgcn_rsq(a);
+    double g = a * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, a);
+    g = fma(d, h, g);
+    d = fma(-g, g, a);
+    return fma(d, h, g);
+}
+
+// background at a node: density, Theta, pressure and 1/Theta
 struct Bg {
-    double rho, Th, P;
+    double rho, Th, P, rTh;
 };
+
+__device__ __forceinline__ Bg bg_make(double rho, double Th, double P) { return Bg{rho, Th, P, 1.0 / Th}; }
+
+// a double at a 32-bit byte offset from a wave-uniform base: one global load with
+// a scalar base and a 32-bit vector offset, no 64-bit address arithmetic
+__device__ __forceinline__ double ld_off(const double* base, uint32_t byte_off) {
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off);
+}
 
 // sgn * F^D(q) and the wave speed |u_D| + c  (axis D known at compile time, so
 // no array is ever indexed by a run-time value)
@@ -98,7 +137,7 @@ template <int D>
 __device__ __forceinline__ void flux_n(const double q[5], const Bg& bg, double Pp, double sgn, double gamma,
                                        double F[5], double& lam) {
     const double rho = bg.rho + q[0];
-    const double rinv = 1.0 / rho;
+    const double rinv = rcp_pos(rho);
     const double ud = q[1 + D] * rinv;
     const double Th = bg.Th + q[4];
     F[0] = sgn * q[1 + D];
@@ -106,7 +145,7 @@ __device__ __forceinline__ void flux_n(const double q[5], const Bg& bg, double P
     F[2] = sgn * (D == 1 ? q[2] * ud + Pp : q[2] * ud);
     F[3] = sgn * (D == 2 ? q[3] * ud + Pp : q[3] * ud);
     F[4] = sgn * (Th * ud);
-    lam = fabs(ud) + sqrt(gamma * (bg.P + Pp) * rinv);
+    lam = fabs(ud) + sqrt_pos(gamma * (bg.P + Pp) * rinv);
 }
 
 // Rusanov flux F*.n, n = sgn e_D:  {F.n} + 1/2 max(|u.n| + c) (q'- - q'+)  (section 2.2);
@@ -189,22 +228,27 @@ __device__ __forceinline__ void apply_t2(const double* in, double* out, int np, 
 // fits these, and at N = 7 three workgroups of 8 waves then share a CU
 template <int N>
 struct StageOcc {
-    static constexpr int W = N == 7 ? 6 : 5;
+    static constexpr int W = N == 7 || N == 4 ? 6 : 5;
+    // one batched gather of the tile and the neighbour traces into LDS (pays at low
+    // order, where faces carry most of the work), or loads straight into registers
+    static constexpr bool GATHER = N <= 5;
 };
 
-// LDS plan of the stage kernel: the work area holds the flux planes of the
-// volume phase: all 15 at once, or x and y, then z (one more barrier), or one
-// direction at a time (five planes; three more barriers).  The plan with the
-// most workgroups per CU (160 KB of LDS, W waves per SIMD) wins, the one with
-// fewer barriers on a tie.  MIX stores the planes as float (flux minus an
-// element-constant reference).
+// LDS plan of the stage kernel: the work area first holds the leaf's float64 tile
+// [5][NP], then the flux planes of the volume phase: all 15 at once, or x and y,
+// then z (one more barrier), or one direction at a time (five planes; three more
+// barriers).  The plan with the most workgroups per CU (160 KB of LDS, W waves per
+// SIMD) wins, the one with fewer barriers on a tie.  MIX stores the planes as float
+// (flux minus an element-constant reference).
 template <int N, bool MIX>
 struct StageLds {
     static constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF;
     static constexpr int ESZ = MIX ? 4 : 8;
-    static constexpr int work_dbl(int planes) { return (planes * NP * ESZ + 7) / 8; }
+    static constexpr int work_dbl(int planes) {
+        return (planes * NP * ESZ + 7) / 8 > 5 * NP ? (planes * NP * ESZ + 7) / 8 : 5 * NP;
+    }
     // bytes of the other LDS arrays of k_stage
-    static constexpr int FIXED = 8 * (30 * NF + Sz<N>::NOPS + 3 * N1 + (MIX ? 15 : 1)) + 4 * 2 * N1 * N1 + 4 * 36;
+    static constexpr int FIXED = 8 * (30 * NF + N1 * N1 + 4 * N1 + 4 + (MIX ? 15 : 1)) + 4 * 2 * N1 * N1 + 4 * 36;
     static constexpr int blocks(int planes) {
         const int by_lds = 160 * 1024 / (FIXED + 8 * work_dbl(planes));
         const int by_waves = 4 * StageOcc<N>::W / (Sz<N>::NT / 64);
@@ -257,7 +301,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_mortar(const MortArgs A) {
         const int quad = t / NF, m = t % NF;
         ef = row[2 + quad];
         const int nn = face_node<N>(fo, m), kn = face_k<N>(fo, m);
-        bF = Bg{A.bg[ef * N1 + kn], A.bg[KN1 + ef * N1 + kn], A.bg[2 * KN1 + ef * N1 + kn]};
+        bF = bg_make(A.bg[ef * N1 + kn], A.bg[KN1 + ef * N1 + kn], A.bg[2 * KN1 + ef * N1 + kn]);
 #pragma unroll
         for (int v = 0; v < 5; ++v) qF[v] = qs[v * KNP + ef * NP + nn];
     }
@@ -273,8 +317,8 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_mortar(const MortArgs A) {
         double qM[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) qM[v] = sMq[(quad * 5 + v) * NF + m];
-        const double PpF = pprime(qF[4], bF.Th, bF.P, gamma, A.binom);
-        const double PpM = pprime(qM[4], bF.Th, bF.P, gamma, A.binom);
+        const double PpF = pprime(qF[4], bF.rTh, bF.P, gamma, A.binom);
+        const double PpM = pprime(qM[4], bF.rTh, bF.P, gamma, A.binom);
         double Fs[5], Fo[5];
         with_axis(f >> 1, [&](auto dc) {
             rusanov<decltype(dc)::value>(qF, bF, PpF, qM, bF, PpM, -sgn, gamma, Fs, Fo);
@@ -319,11 +363,11 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_mortar(const MortArgs A) {
     if (t < NF) {
         const int m = t;
         const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
-        const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
+        const Bg b = bg_make(sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]);
         double qL[5], Fo[5], lam;
 #pragma unroll
         for (int v = 0; v < 5; ++v) qL[v] = qs[v * KNP + ec * NP + n];
-        const double PpL = pprime(qL[4], b.Th, b.P, gamma, A.binom);
+        const double PpL = pprime(qL[4], b.rTh, b.P, gamma, A.binom);
         with_axis(f >> 1, [&](auto dc) { flux_n<decltype(dc)::value>(qL, b, PpL, sgn, gamma, Fo, lam); });
         const double lift_c = A.geo[ec * 4 + (f >> 1)] * liftc;
         double* const out = A.mort + (h * 5 * 5) * NF + m;
@@ -341,11 +385,16 @@ __global__ void __launch_bounds__(Sz<N>::NT) __attribute__((amdgpu_waves_per_eu(
 k_stage(const StageArgs A) {
     constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
     constexpr bool ALL3 = StageLds<N, MIX>::ALL3;
+    // sS: per face f and variable v the trace slot [f][v][NF]: first the neighbour's
+    // trace (conforming faces) or the lifted mortar contribution (hanging faces),
+    // then the lifted contribution itself
     __shared__ double sS[30 * NF];
+    // sW: first this leaf's tile [5][NP], then the flux planes of the volume phase
     __shared__ double sW[StageLds<N, MIX>::WORK];
     __shared__ float sD32[2 * N1 * N1];  // MIX: D high and low parts
-    __shared__ double sOps[Sz<N>::NOPS];
-    __shared__ double sBg[3 * N1];
+    __shared__ double sD[N1 * N1];
+    __shared__ double sBg[4 * N1];       // rho, Theta, P, 1/Theta of the background
+    __shared__ double sGeo[4];
     __shared__ int sType[6];
     __shared__ int sNb[24];
     __shared__ int sHs[6];               // hanging face: row of the mortar pre-pass
@@ -355,48 +404,108 @@ k_stage(const StageArgs A) {
     const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
     const int t = threadIdx.x;
     const double gamma = A.gamma;
-    const double* D = sOps;
-    // I_a at sOps + (1 + a) NF, R_a at sOps + (3 + a) NF
+    const double* const D = sD;
     const double* qs = A.qs;
     const int KNP = (int)(K * NP);  // 5 K Np < 2^31 is checked by the host
-    const double* const qe = qs + e * NP;  // this leaf's tile (uniform)
     const int i = t % N1, j = (t / N1) % N1, k = t / NF;
+    // per-variable planes of qs: wave-uniform bases, 32-bit byte offsets within a plane
+    // (K Np 8 < 2^32 follows from the 5 K Np < 2^31 the host checks)
+    const double* qv[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) qv[v] = qs + (int64_t)v * KNP;
+    const uint32_t eoff = (uint32_t)e * NP * 8u;
 
-    for (int ii = t; ii < Sz<N>::NOPS; ii += NT) sOps[ii] = A.ops[ii];
-    if (t < 3 * N1) sBg[t] = A.bg[(int64_t)(t / N1) * K * N1 + e * N1 + (t % N1)];
-    if (t < 6) sType[t] = A.ftype[e * 6 + t];
-    if (t < 24) sNb[t] = A.fnb[e * 24 + t];
-    if (t < 6) sHs[t] = A.hslot[e * 6 + t];
-    if (MIX) {
-        for (int ii = t; ii < N1 * N1; ii += NT) {
-            const double dv = A.ops[ii];
+    // ---- tables, D and the background profile
+    for (int ii = t; ii < N1 * N1; ii += NT) {
+        const double dv = A.ops[ii];
+        sD[ii] = dv;
+        if (MIX) {
             const float hi = (float)dv;
             sD32[ii] = hi;
             sD32[N1 * N1 + ii] = (float)(dv - (double)hi);
         }
+    }
+    if (t < 3 * N1) {
+        const double v = A.bg[(int64_t)(t / N1) * K * N1 + e * N1 + (t % N1)];
+        sBg[t] = v;
+        if (t >= N1 && t < 2 * N1) sBg[2 * N1 + t] = 1.0 / v;
+    }
+    if (t < 4) sGeo[t] = A.geo[e * 4 + t];
+    if (t < 6) sType[t] = A.ftype[e * 6 + t];
+    if (t < 24) sNb[t] = A.fnb[e * 24 + t];
+    if (t < 6) sHs[t] = A.hslot[e * 6 + t];
+    __syncthreads();
+
+    // ---- gather (GATHER): all loads of the leaf in one batch, the tile into sW, the
+    // neighbours' face traces and the mortar contributions into sS; otherwise the
+    // face items and the volume load straight into registers
+    constexpr bool GATHER = StageOcc<N>::GATHER;
+    if constexpr (GATHER) {
+        // every load is issued before any of them is written to LDS, so all of them are
+        // in flight together: one memory round trip for the leaf
+        static_assert(NP <= NT, "one thread per node");
+        constexpr int NR = (5 * NF + NT - 1) / NT;  // passes over the face slots
+        double tv[5] = {0, 0, 0, 0, 0};
+        if (t < NP)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) tv[v] = ld_off(qv[v], eoff + (uint32_t)t * 8u);
+        // face slots: thread t covers (v, m) of every face, one pass per face; each slot
+        // issues one load (a wall face reads its own leaf's entry and drops it)
+        int ftype[6], fsrc[6];  // per face: type; neighbour leaf or first mortar row
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const int tf = sType[f], type = tf & 0xff;
+            ftype[f] = type;
+            fsrc[f] = type == FT_CONF     ? sNb[f * 4]
+                      : type == FT_WALL   ? (int)e
+                      : type == FT_COARSE ? sHs[f] * 5
+                                          : sHs[f] * 5 + 1 + ((tf >> 8) & 0xff);
+        }
+        double fv[NR][6];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int vm = (5 * NF % NT == 0 || t + r * NT < 5 * NF) ? t + r * NT : 0;
+            const int v = vm / NF, m = vm - v * NF;
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                const double* src = ftype[f] == FT_CONF || ftype[f] == FT_WALL
+                                        ? qs + (v * KNP + fsrc[f] * NP + face_node<N>(f ^ 1, m))
+                                        : A.mort + (int64_t)fsrc[f] * 5 * NF + vm;
+                fv[r][f] = *src;
+            }
+        }
+        if (t < NP)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sW[v * NP + t] = tv[v];
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            if (5 * NF % NT == 0 || t + r * NT < 5 * NF)
+#pragma unroll
+                for (int f = 0; f < 6; ++f)
+                    if (ftype[f] != FT_WALL) sS[f * 5 * NF + t + r * NT] = fv[r][f];
+    }
+    if (MIX && t < 3) {
         // element-constant reference flux: the flux at the leaf's first node, one
         // direction per thread
-        if (t < 3) {
-            double q0n[5];
+        double q0n[5];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) q0n[v] = qe[v * KNP];
-            const double Thb = A.bg[K * N1 + e * N1], Pb = A.bg[2 * K * N1 + e * N1];
-            const double rinv0 = 1.0 / (A.bg[e * N1] + q0n[0]);
-            const double Pp0 = pprime(q0n[4], Thb, Pb, gamma, A.binom);
-            const double Th0 = Thb + q0n[4];
-            const double Ud = t == 0 ? q0n[1] : t == 1 ? q0n[2] : q0n[3];
-            const double u0 = Ud * rinv0;
-            sFr[t * 5 + 0] = Ud;
-            sFr[t * 5 + 1] = t == 0 ? q0n[1] * u0 + Pp0 : q0n[1] * u0;
-            sFr[t * 5 + 2] = t == 1 ? q0n[2] * u0 + Pp0 : q0n[2] * u0;
-            sFr[t * 5 + 3] = t == 2 ? q0n[3] * u0 + Pp0 : q0n[3] * u0;
-            sFr[t * 5 + 4] = Th0 * u0;
-        }
+        for (int v = 0; v < 5; ++v) q0n[v] = ld_off(qv[v], eoff);
+        const double rinv0 = rcp_pos(sBg[0] + q0n[0]);
+        const double Pp0 = pprime(q0n[4], sBg[3 * N1], sBg[2 * N1], gamma, A.binom);
+        const double Th0 = sBg[N1] + q0n[4];
+        const double Ud = t == 0 ? q0n[1] : t == 1 ? q0n[2] : q0n[3];
+        const double u0 = Ud * rinv0;
+        sFr[t * 5 + 0] = Ud;
+        sFr[t * 5 + 1] = t == 0 ? q0n[1] * u0 + Pp0 : q0n[1] * u0;
+        sFr[t * 5 + 2] = t == 1 ? q0n[2] * u0 + Pp0 : q0n[2] * u0;
+        sFr[t * 5 + 3] = t == 2 ? q0n[3] * u0 + Pp0 : q0n[3] * u0;
+        sFr[t * 5 + 4] = Th0 * u0;
     }
     __syncthreads();
 
-    // ---- faces, every (face, node) item: conforming neighbours and walls here;
-    // hanging faces (L2 mortars) copy what the mortar pre-pass computed
+    // ---- faces, every (face, node) item of a wall or conforming face: Rusanov flux
+    // from the own trace (tile) and the neighbour trace (sS), lifted in place;
+    // hanging faces already hold the pre-pass contributions
     const double liftc = 0.5 * N * (N + 1);  // 1/w_N
     // items grouped by axis, each axis padded to whole waves, so a wave never
     // mixes the three axis variants of the flux code
@@ -406,23 +515,43 @@ k_stage(const StageArgs A) {
         const int ax = it / PAD, r = it % PAD;
         if (r >= 2 * NF) continue;
         const int f = 2 * ax + r / NF, m = r % NF;
-        const int type = sType[f] & 0xff;
+        const int tf = sType[f];
+        const int type = tf & 0xff;
         if (type == FT_FINE || type == FT_COARSE) {
-            const int64_t slot = (int64_t)sHs[f] * 5 + (type == FT_COARSE ? 0 : 1 + (sType[f] >> 8));
+            if constexpr (!GATHER) {
+                const int64_t row = (int64_t)sHs[f] * 5 + (type == FT_COARSE ? 0 : 1 + ((tf >> 8) & 0xff));
 #pragma unroll
-            for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = A.mort[(slot * 5 + v) * NF + m];
+                for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = A.mort[(row * 5 + v) * NF + m];
+            }
             continue;
         }
         const double sgn = (f & 1) ? 1.0 : -1.0;
         const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
-        const double lift = A.geo[e * 4 + (f >> 1)] * liftc;
-        with_axis(f >> 1, [&](auto dc) {
+        const double lift = sGeo[ax] * liftc;
+        double* const slot = sS + f * 5 * NF + m;
+        with_axis(ax, [&](auto dc) {
             constexpr int d = decltype(dc)::value;
             double qL[5], qR[5];
+            if constexpr (GATHER) {
 #pragma unroll
-            for (int v = 0; v < 5; ++v) qL[v] = qe[v * KNP + n];
-            const Bg bL{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
-            const double PpL = pprime(qL[4], bL.Th, bL.P, gamma, A.binom);
+                for (int v = 0; v < 5; ++v) qL[v] = sW[v * NP + n];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) qR[v] = slot[v * NF];
+            } else {
+                // both traces requested before either is used (a wall face loads its
+                // own entry twice and mirrors it below)
+                const int nb = type == FT_CONF ? sNb[f * 4] : (int)e;
+                const uint32_t nn = (uint32_t)(type == FT_CONF ? face_node<N>(f ^ 1, m) : n);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) qL[v] = ld_off(qv[v], eoff + (uint32_t)n * 8u);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) qR[v] = ld_off(qv[v], ((uint32_t)nb * NP + nn) * 8u);
+            }
+            // the background is a function of z, and the two leaves of a conforming
+            // face see bitwise-identical z at its nodes, except across a periodic
+            // wrap along z (flagged by the host)
+            const Bg bL{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk], sBg[3 * N1 + kk]};
+            const double PpL = pprime(qL[4], bL.rTh, bL.P, gamma, A.binom);
             Bg bR = bL;
             double PpR = PpL;
             if (type == FT_WALL) {
@@ -430,45 +559,43 @@ k_stage(const StageArgs A) {
                 for (int v = 0; v < 5; ++v) qR[v] = qL[v];
                 qR[1 + d] = -qL[1 + d];  // mirror state: reverse the normal momentum
             } else {
-                const int nb = sNb[f * 4];
-                const int fo = f ^ 1;
-                const int nn = face_node<N>(fo, m), kn = face_k<N>(fo, m);
-#pragma unroll
-                for (int v = 0; v < 5; ++v) qR[v] = qs[v * KNP + nb * NP + nn];
-                bR = Bg{A.bg[nb * N1 + kn], A.bg[K * N1 + nb * N1 + kn], A.bg[2 * K * N1 + nb * N1 + kn]};
-                PpR = pprime(qR[4], bR.Th, bR.P, gamma, A.binom);
+                if (tf & FT_BG_NB) {
+                    const int nb = sNb[f * 4], kn = face_k<N>(f ^ 1, m);
+                    bR = bg_make(A.bg[nb * N1 + kn], A.bg[K * N1 + nb * N1 + kn], A.bg[2 * K * N1 + nb * N1 + kn]);
+                }
+                PpR = pprime(qR[4], bR.rTh, bR.P, gamma, A.binom);
             }
             double Fs[5], Fo[5];
             rusanov<d>(qL, bL, PpL, qR, bR, PpR, sgn, gamma, Fs, Fo);
 #pragma unroll
-            for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = (Fs[v] - Fo[v]) * lift;
+            for (int v = 0; v < 5; ++v) slot[v * NF] = (Fs[v] - Fo[v]) * lift;
         });
     }
 
-    __syncthreads();
-
-    // ---- volume term: R = S - sum_d (2/h_d) D_d F^d, fluxes staged in LDS
-    double q[5] = {0, 0, 0, 0, 0}, vel[3] = {0, 0, 0}, Pp = 0.0, Th = 0.0;
-    double R[5] = {0, 0, 0, 0, 0};
-    // q0 of the update (stage form, a != 0) loaded with q: one memory round trip
-    double q0v[5] = {0, 0, 0, 0, 0};
+    // ---- volume term: R = S - sum_d (2/h_d) D_d F^d, fluxes staged in LDS; q from
+    // the tile, q0 of the update (stage form, a != 0) loaded now, used at the end
+    double q[5] = {0, 0, 0, 0, 0}, q0v[5] = {0, 0, 0, 0, 0};
     const bool use_q0 = MODE == MODE_RK && A.a != 0.0;
+    if (use_q0 && t < NP)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) q0v[v] = ld_off(A.q0 + (int64_t)v * KNP, eoff + (uint32_t)t * 8u);
+    double rinv = 0.0, Pp = 0.0, Th = 0.0;
+    double R[5] = {0, 0, 0, 0, 0};
     if (t < NP) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) q[v] = qe[v * KNP + t];
-        if (use_q0)
-#pragma unroll
-            for (int v = 0; v < 5; ++v) q0v[v] = A.q0[v * KNP + e * NP + t];
-        const double rinv = 1.0 / (sBg[k] + q[0]);
-        vel[0] = q[1] * rinv;
-        vel[1] = q[2] * rinv;
-        vel[2] = q[3] * rinv;
-        Pp = pprime(q[4], sBg[N1 + k], sBg[2 * N1 + k], gamma, A.binom);
+        for (int v = 0; v < 5; ++v) q[v] = GATHER ? sW[v * NP + t] : ld_off(qv[v], eoff + (uint32_t)t * 8u);
+        rinv = rcp_pos(sBg[k] + q[0]);
+        Pp = pprime(q[4], sBg[3 * N1 + k], sBg[2 * N1 + k], gamma, A.binom);
         Th = sBg[N1 + k] + q[4];
         R[3] = -q[0] * A.g;  // buoyancy on rho*w
     }
+    // GATHER: the faces read other nodes' tile entries, and the flux planes overwrite
+    // the tile: every read must be done (otherwise nothing is shared yet: the face
+    // results in sS are read after the volume's barriers)
+    if constexpr (GATHER) __syncthreads();
+
     auto put_flux = [&](int d, int plane) {
-        const double ud = vel[d];
+        const double ud = q[1 + d] * rinv;
         double F[5];
         F[0] = q[1 + d];
         F[1] = d == 0 ? q[1] * ud + Pp : q[1] * ud;
@@ -489,7 +616,7 @@ k_stage(const StageArgs A) {
         const int id = d == 0 ? i : d == 1 ? j : k;
         const int stride = d == 0 ? 1 : d == 1 ? N1 : NF;
         const int base = t - id * stride;
-        const double g2 = A.geo[e * 4 + d];
+        const double g2 = A.geo[e * 4 + d];  // uniform: a scalar load
         if (MIX) {
             const float* Dh = sD32 + id * N1;
             const float* Dl = sD32 + N1 * N1 + id * N1;
@@ -606,12 +733,12 @@ template <int D>
 __device__ __forceinline__ NodeState node_state(const double q[5], const Bg& b, double Pp, double gamma) {
     NodeState s;
     const double rho = b.rho + q[0];
-    s.rinv = 1.0 / rho;
+    s.rinv = rcp_pos(rho);
     s.ud = q[1 + D] * s.rinv;
     s.Th = b.Th + q[4];
     const double P = b.P + Pp;
     s.dPdT = gamma * P / s.Th;
-    const double c = sqrt(gamma * P * s.rinv);
+    const double c = sqrt_pos(gamma * P * s.rinv);
     const double au = fabs(s.ud);
     const double su = s.ud > 0.0 ? 1.0 : (s.ud < 0.0 ? -1.0 : 0.0);
     s.lam = au + c;
@@ -696,7 +823,7 @@ k_adjoint(const AdjArgs A) {
     __shared__ double sS[30 * NF];       // face contributions to qbar
     __shared__ double sX[AdjLds<N>::SCR];
     __shared__ double sOps[NOPS];
-    __shared__ double sBg[3 * N1];
+    __shared__ double sBg[4 * N1];  // rho, Theta, P, 1/Theta of the background
     __shared__ int sType[6];
     __shared__ int sNb[24];
     double* const sT = sX;             // q trace
@@ -726,7 +853,11 @@ k_adjoint(const AdjArgs A) {
             sD32[ii] = hi;
             sD32[N1 * N1 + ii] = (float)(dv - (double)hi);
         }
-    if (t < 3 * N1) sBg[t] = A.bg[(t / N1) * KN1 + e * N1 + (t % N1)];
+    if (t < 3 * N1) {
+        const double v = A.bg[(t / N1) * KN1 + e * N1 + (t % N1)];
+        sBg[t] = v;
+        if (t >= N1 && t < 2 * N1) sBg[2 * N1 + t] = 1.0 / v;
+    }
     if (t < 6) sType[t] = A.ftype[e * 6 + t];
     if (t < 24) sNb[t] = A.fnb[e * 24 + t];
     double q[5] = {0, 0, 0, 0, 0}, lam[5] = {0, 0, 0, 0, 0};
@@ -740,7 +871,7 @@ k_adjoint(const AdjArgs A) {
             else
                 sL[v * NP + t] = lam[v];
         }
-        sPp[t] = pprime(q[4], A.bg[KN1 + e * N1 + k], A.bg[2 * KN1 + e * N1 + k], gamma, A.binom);
+        sPp[t] = pprime(q[4], 1.0 / A.bg[KN1 + e * N1 + k], A.bg[2 * KN1 + e * N1 + k], gamma, A.binom);
     }
     __syncthreads();
 
@@ -762,7 +893,7 @@ k_adjoint(const AdjArgs A) {
                 qL[v] = qe[v * KNP + n];
                 lL[v] = MIX ? le[v * KNP + n] : sL[v * NP + n];
             }
-            const Bg bL{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
+            const Bg bL{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk], sBg[3 * N1 + kk]};
             const double PpL = sPp[n];
             if (type == FT_WALL) {
 #pragma unroll
@@ -784,8 +915,11 @@ k_adjoint(const AdjArgs A) {
                     qR[v] = qs[v * KNP + nb * NP + nn];
                     w[v] = -lift * lL[v] + liftn * ls[v * KNP + nb * NP + nn];
                 }
-                const Bg bR{A.bg[nb * N1 + kn], A.bg[KN1 + nb * N1 + kn], A.bg[2 * KN1 + nb * N1 + kn]};
-                const double PpR = pprime(qR[4], bR.Th, bR.P, gamma, A.binom);
+                // same background as this side except across a periodic wrap along z
+                const Bg bR = (sType[f] & FT_BG_NB)
+                                  ? bg_make(A.bg[nb * N1 + kn], A.bg[KN1 + nb * N1 + kn], A.bg[2 * KN1 + nb * N1 + kn])
+                                  : bL;
+                const double PpR = pprime(qR[4], bR.rTh, bR.P, gamma, A.binom);
                 rusanov_vjp<d>(qL, bL, PpL, qR, bR, PpR, sgn, gamma, w, g, nullptr);
             }
             own_flux_vjp<d>(qL, bL, PpL, sgn, gamma, lift, lL, g);
@@ -807,7 +941,7 @@ k_adjoint(const AdjArgs A) {
         const double sgn = (f & 1) ? 1.0 : -1.0;
         if (type == FT_FINE) {
             const int ec = sNb[f * 4];
-            const int quad = sType[f] >> 8, qa = quad & 1, qb = quad >> 1;
+            const int quad = (sType[f] >> 8) & 0xff, qa = quad & 1, qb = quad >> 1;
             const double liftcoarse = A.geo[ec * 4 + (f >> 1)] * liftc;
             __syncthreads();
             for (int it = t; it < 5 * NF; it += NT) {
@@ -826,7 +960,7 @@ k_adjoint(const AdjArgs A) {
             __syncthreads();
             for (int m = t; m < NF; m += NT) {
                 const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
-                const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
+                const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk], sBg[3 * N1 + kk]};
                 double qL[5], lL[5], qM[5], w[5], g[5];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
@@ -835,7 +969,7 @@ k_adjoint(const AdjArgs A) {
                     qM[v] = sMq[v * NF + m];
                     w[v] = -lift * lL[v] + liftcoarse * sMq[(5 + v) * NF + m];
                 }
-                const double PpM = pprime(qM[4], b.Th, b.P, gamma, A.binom);
+                const double PpM = pprime(qM[4], b.rTh, b.P, gamma, A.binom);
                 with_axis(f >> 1, [&](auto dc) {
                     constexpr int d = decltype(dc)::value;
                     rusanov_vjp<d>(qL, b, sPp[n], qM, b, PpM, sgn, gamma, w, g, nullptr);
@@ -867,7 +1001,7 @@ k_adjoint(const AdjArgs A) {
                 const int ef = sNb[f * 4 + quad];
                 const int nn = face_node<N>(fo, m), kn = face_k<N>(fo, m);
                 const double liftf = A.geo[ef * 4 + (f >> 1)] * liftc;
-                const Bg b{A.bg[ef * N1 + kn], A.bg[KN1 + ef * N1 + kn], A.bg[2 * KN1 + ef * N1 + kn]};
+                const Bg b = bg_make(A.bg[ef * N1 + kn], A.bg[KN1 + ef * N1 + kn], A.bg[2 * KN1 + ef * N1 + kn]);
                 double qM[5], qF[5], w[5], g[5];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
@@ -875,8 +1009,8 @@ k_adjoint(const AdjArgs A) {
                     qF[v] = qs[v * KNP + ef * NP + nn];
                     w[v] = -lift * sMq[(quad * 10 + 5 + v) * NF + m] + liftf * ls[v * KNP + ef * NP + nn];
                 }
-                const double PpM = pprime(qM[4], b.Th, b.P, gamma, A.binom);
-                const double PpF = pprime(qF[4], b.Th, b.P, gamma, A.binom);
+                const double PpM = pprime(qM[4], b.rTh, b.P, gamma, A.binom);
+                const double PpF = pprime(qF[4], b.rTh, b.P, gamma, A.binom);
                 with_axis(f >> 1, [&](auto dc) {
                     rusanov_vjp<decltype(dc)::value>(qM, b, PpM, qF, b, PpF, sgn, gamma, w, g, nullptr);
                 });
@@ -914,7 +1048,7 @@ k_adjoint(const AdjArgs A) {
             __syncthreads();
             for (int m = t; m < NF; m += NT) {
                 const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
-                const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]};
+                const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk], sBg[3 * N1 + kk]};
                 double qL[5], lL[5], g[5];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
@@ -1271,7 +1405,7 @@ __global__ void __launch_bounds__(256) k_budgets(const BudgetArgs A) {
             const double rhob = A.bg[e * N1 + k], Thb = A.bg[K * N1 + e * N1 + k], Pb = A.bg[2 * K * N1 + e * N1 + k];
             const double z = A.c1d[2 * K * N1 + e * N1 + k];
             const double rho = rhob + rp;
-            const double P = Pb + pprime(Thp, Thb, Pb, gamma, A.binom);
+            const double P = Pb + pprime(Thp, 1.0 / Thb, Pb, gamma, A.binom);
             const double E = P / (gamma - 1.0) + (U * U + V * V + Wm * Wm) / (2.0 * rho) + rho * A.g * z;
             acc[0] = comp_add(acc[0], W * rp);
             acc[1] = comp_add(acc[1], W * rho);
