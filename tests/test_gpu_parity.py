@@ -95,6 +95,30 @@ def test_rhs_random_state_amr(case):
     check(R, op.rhs(q), what=f"rhs N={case['N']}")
 
 
+@pytest.mark.parametrize("N", [4, 7])
+def test_rhs_large_theta_perturbation(N):
+    """Theta' up to ~+-25% of Thetabar: P' leaves the short binomial series and takes
+    the kernels' wide-range path (log-halving), checked against the oracle's
+    expm1/log1p form, on faces, mortars and volume, with a periodic z wrap."""
+    od = oracle_desc(N, (2, 2, 2), 2, *BOX, (0, 0, 1))
+    seq = random_refinements(od, 2, 31 + N)
+    lm, om = both_meshes(N, (2, 2, 2), 2, (0, 0, 1), flag_seq=seq)
+    assert lm.info.n_hang > 0
+    ph = dg.PhysParams()
+    op = eu.Operator(om, oracle_phys(ph))
+    qn = torch.as_tensor(random_state(om.K, N, 40 + N, scales=(1e-3, 0.1, 0.1, 0.1, 30.0)))
+    x = qn[4] / to_nodes(op.bg[1][None])[0]
+    assert float(x.abs().max()) > 0.1  # far outside the series range 2^-7
+    R = lm.field()
+    dg.dg_rhs(lm, ph, gpu(qn), R)
+    out = lm.field()
+    dg.dg_rk_stage(lm, ph, 0.75, 0.25, 0.001, gpu(qn), gpu(qn), out)
+    torch.cuda.synchronize()
+    q = to_elem(qn, N)
+    check(R, op.rhs(q), what=f"rhs wide P' N={N}")
+    check(out, eu.rk_stage(op, 0.75, 0.25, 0.001, q, q), what=f"stage wide P' N={N}")
+
+
 def test_hydrostatic_rest_bitwise_zero_and_conservation():
     od = oracle_desc(4, (2, 2, 2), 2, *BOX, (0, 0, 0))
     seq = random_refinements(od, 2, 11)
