@@ -10,8 +10,10 @@ projection, refine pass and projection), inside the timed region.
 
 Prints one JSON line: DOF-updates/s (5 variables x nodes x 3 RHS evaluations
 per step) over the timed steps, the roofline of the dominant kernel (the fused
-stage) from HIP events around its launches, and the oracle timed on the host
-cores on a bounded sample of the same workload.
+stage) from HIP events around the stage launches of a second pass of as many
+steps (the timed steps carry no events between stages: each timing marker
+costs the GPU a few microseconds), and the oracle timed on the host cores on a
+bounded sample of the same workload.
 """
 import argparse
 import json
@@ -36,10 +38,10 @@ STAGE_KERNEL = "k_mortar<7> + k_stage<7, 1, false>"
 # kernels.hip up to the adjoint section, the stage and mortar launchers,
 # kernels.hpp and facetypes.hpp); otherwise traffic is reported as null.
 TRAFFIC = {
-    "sources_sha256": "afc31dee2ac3a51b89452e391c43bdbfec500dc40e4c769ef4f61e0f4a9b3e5d",
-    "fetch_kib_per_launch": 79022.6,    # mean over the 90 timed stages, both kernels
+    "sources_sha256": "ba1ec90a1857901c48802f9e81319680d68c7b45289645a9fad97bb9f998ab8b",
+    "fetch_kib_per_launch": 78423.6,    # mean over the 90 stages of the stage-timing pass, both kernels
     "write_kib_per_launch": 73210.0,
-    "fetch_scale": 1048576.0 / 524301.7,  # 1 GiB copy: FETCH_SIZE reads 524301.7 KiB
+    "fetch_scale": 1048576.0 / 524301.9,  # 1 GiB copy: FETCH_SIZE reads 524301.9 KiB
     "write_scale": 1048576.0 / 1048576.0,  # 1 GiB copy: WRITE_SIZE reads 1048576.0 KiB
 }
 CSRC = os.path.join(ROOT, "paper_2404_16648_amd", "csrc")
@@ -124,15 +126,15 @@ def main():
         q2_ = torch.empty_like(qq)
         nodes = m.K * m.Np
         stages = ((0.0, 1.0, qq, q1), (0.75, 0.25, q1, q2_), (1.0 / 3.0, 2.0 / 3.0, q2_, qq))
+        if record is not None:  # one event pair around the three stage launches of the step
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
         for a, b, qs, out in stages:
-            if record is not None:
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
             dg.dg_rk_stage(m, ph, a, b, dt, qq, qs, out)
-            if record is not None:
-                e1.record(stream)
-                record.append((e0, e1, nodes * (BYTES_STAGE_FIRST if a == 0.0 else BYTES_STAGE)))
+        if record is not None:
+            e1.record(stream)
+            record.append((e0, e1, nodes * (BYTES_STAGE_FIRST + 2 * BYTES_STAGE), 3))
         state["step"] += 1
         state["dofs"] += 3 * 5 * nodes
 
@@ -140,22 +142,32 @@ def main():
         one_step(None)
     torch.cuda.synchronize()
     state["dofs"] = 0
-    events = []
+    # throughput: the K timed steps carry no events of their own (a timing event
+    # between two stages costs the GPU ~5 us each)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t0.record(stream)
     for _ in range(args.steps):
-        one_step(events)
+        one_step(None)
     t1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = t0.elapsed_time(t1)
-    stage_ms = sum(e0.elapsed_time(e1) for e0, e1, _ in events)
-    stage_bytes = sum(b for _, _, b in events)
+    dofs_timed = state["dofs"]
+    # stage timing for the roofline: the next K steps of the same run, one HIP event
+    # pair on the launching stream around the three stage launches of every step
+    # (the adaptation cycles stay outside the pairs)
+    events = []
+    for _ in range(args.steps):
+        one_step(events)
+    torch.cuda.synchronize()
+    stage_ms = sum(e0.elapsed_time(e1) for e0, e1, _, _ in events)
+    stage_bytes = sum(b for _, _, b, _ in events)
+    n_launches = sum(n for _, _, _, n in events)
     achieved = stage_bytes / (stage_ms * 1e-3) / 1e9
-    dofs_per_s = state["dofs"] / (total_ms * 1e-3)
+    dofs_per_s = dofs_timed / (total_ms * 1e-3)
     m = state["mesh"]
     budgets = dg.dg_budgets(m, ph, state["q"])
     calib = None
@@ -168,7 +180,7 @@ def main():
         torch.cuda.synchronize()
         calib = {"bytes_per_copy": nb, "copies": 4}
         del src, dst
-    alg_bytes = stage_bytes / max(1, len(events))
+    alg_bytes = stage_bytes / max(1, n_launches)
     traffic = traffic_bytes_per_launch()
 
     result = {
@@ -194,33 +206,37 @@ def main():
                      "traffic_unit": "B/launch", "algorithmic_bytes_per_launch": alg_bytes,
                      "traffic_over_algorithmic": None if traffic is None else traffic / alg_bytes,
                      "kernel": STAGE_KERNEL + " (mortar pre-pass, then fused volume+faces+lift+RK stage)",
-                     "avg_launch_us": 1e3 * stage_ms / max(1, len(events))},
+                     "avg_launch_us": 1e3 * stage_ms / max(1, n_launches)},
         "wall_s": wall,
         "mass_prime_final": budgets[0],
     }
     if calib is not None:
         result["copy_calibration"] = calib
     if not args.no_extras:
-        result["extras"] = extras(dg, torch, state["mesh"], state["q"], ph, dt, 1e3 * stage_ms / len(events))
+        result["extras"] = extras(dg, torch, state["mesh"], state["q"], ph, dt, 1e3 * stage_ms / n_launches)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)
 
 
-def _time_launches(torch, fn, reps, warmup=5):
-    """Median duration (us) of fn() over reps launches after warmup ones, HIP
-    events around each launch on the current stream."""
+def _time_launches(torch, fn, reps, warmup=5, batches=5):
+    """Duration (us) of one fn(): HIP events on the current stream around batches
+    of reps back-to-back calls (no timing marker between two calls), the median
+    batch divided by reps."""
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-    for e0, e1 in ev:
+    d = []
+    for _ in range(batches):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        fn()
+        for _ in range(reps):
+            fn()
         e1.record(stream)
-    torch.cuda.synchronize()
-    d = sorted(1e3 * e0.elapsed_time(e1) for e0, e1 in ev)
+        torch.cuda.synchronize()
+        d.append(1e3 * e0.elapsed_time(e1) / reps)
+    d.sort()
     return d[len(d) // 2]
 
 

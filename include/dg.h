@@ -24,8 +24,11 @@
  *   - The caller owns every field buffer; the library owns the mesh handle, its
  *     host tables, its device tables, background profiles and workspaces.
  *   - `stream` is a hipStream_t passed as void*; NULL is the default stream.
- *     Field calls only enqueue work (asynchronous); dg_mesh_build, dg_budgets
- *     and dg_indicator (flags copied to the host) synchronise the stream.
+ *     Field calls only enqueue work (asynchronous); dg_budgets and
+ *     dg_indicator (flags copied to the host) synchronise the stream.  A mesh's
+ *     device tables are uploaded by the first call that uses the mesh on the
+ *     GPU (synchronous, on the device that was current at dg_mesh_build); a
+ *     mesh that is only inspected on the host costs no device memory.
  *   - Every function returns a dg_status; nothing throws across the ABI.  On an
  *     error the outputs are unspecified, handles stay valid, and
  *     dg_last_error() returns a message (thread-local).  Faults of kernels
@@ -140,7 +143,7 @@ typedef struct {
  * parent is two or more levels finer than the parent (judged on prev).
  * On success *out is a new handle (free with dg_mesh_free) whose transfer
  * plan refers to prev; prev must stay alive while it is used by the
- * projections.  Synchronous. */
+ * projections.  Host work only (the device copy is made at first GPU use). */
 dg_status dg_mesh_build(const dg_forest_desc* desc, const dg_mesh* prev, const int8_t* flags,
                         int32_t pass, dg_mesh** out);
 dg_status dg_mesh_free(dg_mesh* mesh);

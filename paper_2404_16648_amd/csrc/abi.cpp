@@ -155,42 +155,27 @@ bool plan_consistent(const HostMesh& h, int64_t K_from) {
 // A pass that changed no leaf leaves every table as it was: the device block is
 // cloned from the previous mesh's (and its background, when computed), and only
 // the identity transfer plan is uploaded.
-dg_status clone_device(dg_mesh* m, const dg_mesh* prev) {
+// host checks of a new mesh, before any device work: every face has a type and
+// in-range neighbours, the transfer plan is sound, the sizes fit the kernels' indexing
+dg_status validate_mesh(const dg_mesh* m) {
     const HostMesh& h = m->h;
     const int64_t K = (int64_t)h.leaves.size();
-    m->red_len = prev->red_len;
-    m->n_hang = prev->n_hang;
-    const DevLayout L = dev_layout(K, h.desc.N, m->red_len, m->n_hang);
-    HIP_TRY(hipSetDevice(prev->device));
-    m->device = prev->device;
-    char* base = nullptr;
-    HIP_TRY(hipMalloc((void**)&base, L.total));
-    set_device_pointers(m, base, L);
-    HIP_TRY(hipMemcpy(base, prev->d_base, L.xs, hipMemcpyDeviceToDevice));
-    std::vector<int32_t> xfer(2 * (size_t)K);
-    std::memcpy(xfer.data(), h.xfer_src.data(), sizeof(int32_t) * K);
-    std::memcpy(xfer.data() + K, h.xfer_kind.data(), sizeof(int32_t) * K);
-    HIP_TRY(hipMemcpy(base + L.xs, xfer.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(base + L.xk, xfer.data() + K, sizeof(int32_t) * K, hipMemcpyHostToDevice));
-    if (prev->bg_valid) {
-        HIP_TRY(hipMemcpy(m->d_bg, prev->d_bg, sizeof(double) * 3 * K * (h.desc.N + 1), hipMemcpyDeviceToDevice));
-        m->bg_phys = prev->bg_phys;
-        m->bg_valid = true;
-    }
-    m->on_device = true;
-    return DG_OK;
-}
-
-dg_status build_device(dg_mesh* m) {
-    const HostMesh& h = m->h;
-    const int64_t K = (int64_t)h.leaves.size();
+    // a pass that changed no leaf copied the checked tables of prev and holds the
+    // identity plan
+    if (h.same_as_prev && m->prev && m->prev->h.leaves.size() == h.leaves.size()) return DG_OK;
     if (!tables_consistent(h)) return fail(DG_EINVAL, "internal: inconsistent face tables");
     if (!plan_consistent(h, m->prev ? (int64_t)m->prev->h.leaves.size() : K))
         return fail(DG_EINVAL, "internal: inconsistent transfer plan");
     if (5 * K * (int64_t)(h.desc.N + 1) * (h.desc.N + 1) * (h.desc.N + 1) >= ((int64_t)1 << 31))
         return fail(DG_EINVAL, "mesh too large: 5 K Np must stay below 2^31");
-    if (h.same_as_prev && m->prev && m->prev->on_device && m->prev->h.leaves.size() == h.leaves.size())
-        return clone_device(m, m->prev);
+    return DG_OK;
+}
+
+// one device allocation per mesh, filled from the host tables by one copy (on the
+// device the mesh was built on)
+dg_status build_device(dg_mesh* m) {
+    const HostMesh& h = m->h;
+    const int64_t K = (int64_t)h.leaves.size();
     const int N = h.desc.N, N1 = N + 1;
     m->red_len = (int64_t)budget_blocks(K) * 8 + 8;
     m->n_hang = (int64_t)h.hang.size() / 6;
@@ -231,7 +216,6 @@ dg_status build_device(dg_mesh* m) {
     if (m->n_hang) std::memcpy(up.data() + L.hg, h.hang.data(), sizeof(int32_t) * 6 * m->n_hang);
     std::memcpy(up.data() + L.xs, h.xfer_src.data(), sizeof(int32_t) * K);
     std::memcpy(up.data() + L.xk, h.xfer_kind.data(), sizeof(int32_t) * K);
-    HIP_TRY(hipGetDevice(&m->device));
     char* base = nullptr;
     HIP_TRY(hipMalloc((void**)&base, L.total));
     set_device_pointers(m, base, L);
@@ -255,10 +239,24 @@ dg_status check_phys(const dg_phys* p) {
     return DG_OK;
 }
 
-dg_status check_dev_mesh(const dg_mesh* m) {
-    if (!m) return fail(DG_EINVAL, "mesh is NULL");
-    if (!m->on_device) return fail(DG_EINVAL, "mesh was built host_only");
-    return DG_OK;
+// the device tables are made when a call first uses the mesh on the GPU (a mesh that
+// is only inspected on the host, such as a pass that changed no leaf and is
+// dropped, never costs an allocation or a copy)
+dg_status check_dev_mesh(const dg_mesh* mc) {
+    if (!mc) return fail(DG_EINVAL, "mesh is NULL");
+    if (mc->h.desc.host_only) return fail(DG_EINVAL, "mesh was built host_only");
+    if (mc->on_device) return DG_OK;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
+    if (mc->on_device) return DG_OK;
+    dg_mesh* m = const_cast<dg_mesh*>(mc);
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != m->device) HIP_TRY(hipSetDevice(m->device));
+    const dg_status st = build_device(m);
+    if (st != DG_OK) free_device(m);
+    if (cur != m->device) (void)hipSetDevice(cur);
+    return st;
 }
 
 bool same_bg(const dg_phys& a, const dg_phys& b) {
@@ -344,13 +342,14 @@ dg_status dg_mesh_build(const dg_forest_desc* desc, const dg_mesh* prev, const i
         }
         m->ops = refops_cached(m->h.desc.N);
         m->id = g_next_id++;
-        if (!m->h.desc.host_only) {
-            dg_status st = build_device(m);
-            if (st != DG_OK) {
-                free_device(m);
-                delete m;
-                return st;
-            }
+        dg_status st = validate_mesh(m);
+        if (st == DG_OK && !m->h.desc.host_only) {
+            const hipError_t e = hipGetDevice(&m->device);
+            if (e != hipSuccess) st = hip_fail(e, "hipGetDevice");
+        }
+        if (st != DG_OK) {
+            delete m;
+            return st;
         }
     } catch (const std::bad_alloc&) {
         if (m) {

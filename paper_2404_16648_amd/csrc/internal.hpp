@@ -1,6 +1,7 @@
 // Internal declarations of the DG-AMR library (host side).  Not part of the ABI.
 #pragma once
 
+#include <atomic>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -52,7 +53,7 @@ struct dg_mesh {
     dgamr::RefOps ops;
     const dg_mesh* prev = nullptr;
     uint64_t id = 0, prev_id = 0;
-    bool on_device = false;
+    std::atomic<bool> on_device{false};  // device tables made (at first GPU use)
     int device = 0;
     char* d_base = nullptr;       // the one device allocation holding everything below
     // device tables
