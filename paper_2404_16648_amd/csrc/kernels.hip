@@ -395,6 +395,7 @@ k_stage(const StageArgs A) {
     __shared__ double sD[N1 * N1];
     __shared__ double sBg[4 * N1];       // rho, Theta, P, 1/Theta of the background
     __shared__ double sGeo[4];
+    __shared__ double sBgZ[8];           // far-side background of faces 4, 5 (rho, Theta, P, 1/Theta)
     __shared__ int sType[6];
     __shared__ int sNb[24];
     __shared__ int sHs[6];               // hanging face: row of the mortar pre-pass
@@ -468,21 +469,39 @@ k_stage(const StageArgs A) {
             const int v = vm / NF, m = vm - v * NF;
 #pragma unroll
             for (int f = 0; f < 6; ++f) {
+                // conforming: the neighbour's node across the face; wall: this leaf's own
+                // face node (the slot becomes the mirror state)
+                const int nn = face_node<N>(ftype[f] == FT_CONF ? f ^ 1 : f, m);
                 const double* src = ftype[f] == FT_CONF || ftype[f] == FT_WALL
-                                        ? qs + (v * KNP + fsrc[f] * NP + face_node<N>(f ^ 1, m))
+                                        ? qs + (v * KNP + fsrc[f] * NP + nn)
                                         : A.mort + (int64_t)fsrc[f] * 5 * NF + vm;
                 fv[r][f] = *src;
             }
         }
+        // far side of the z faces (f = 4, 5): this leaf's bottom / top level, or the
+        // neighbour's top / bottom level across a periodic wrap along z
+        double zb = 0.0;
+        const int zf = 4 + ((t - 32) >> 2), zc = (t - 32) & 3;
+        const bool zt = t >= 32 && t < 40;
+        const bool znb = zt && (sType[zf] & FT_BG_NB) != 0;
+        if (zt) {
+            const int kk = (zf == 4) == znb ? N : 0;
+            zb = znb ? A.bg[(int64_t)(zc == 3 ? 1 : zc) * K * N1 + (int64_t)sNb[zf * 4] * N1 + kk]
+                     : sBg[(zc == 3 ? 1 : zc) * N1 + kk];
+        }
         if (t < NP)
 #pragma unroll
             for (int v = 0; v < 5; ++v) sW[v * NP + t] = tv[v];
+        if (zt) sBgZ[t - 32] = zc == 3 ? 1.0 / zb : zb;
 #pragma unroll
         for (int r = 0; r < NR; ++r)
             if (5 * NF % NT == 0 || t + r * NT < 5 * NF)
 #pragma unroll
-                for (int f = 0; f < 6; ++f)
-                    if (ftype[f] != FT_WALL) sS[f * 5 * NF + t + r * NT] = fv[r][f];
+                for (int f = 0; f < 6; ++f) {
+                    // mirror state of a wall: the normal momentum reversed
+                    const bool flip = ftype[f] == FT_WALL && (t + r * NT) / NF == 1 + (f >> 1);
+                    sS[f * 5 * NF + t + r * NT] = flip ? -fv[r][f] : fv[r][f];
+                }
     }
     if (MIX && t < 3) {
         // element-constant reference flux: the flux at the leaf's first node, one
@@ -533,10 +552,23 @@ k_stage(const StageArgs A) {
             constexpr int d = decltype(dc)::value;
             double qL[5], qR[5];
             if constexpr (GATHER) {
+                // the slot holds the neighbour's trace or a wall's mirror state; the far
+                // side's background is this side's except on z faces (sBgZ)
 #pragma unroll
                 for (int v = 0; v < 5; ++v) qL[v] = sW[v * NP + n];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) qR[v] = slot[v * NF];
+                const Bg bL{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk], sBg[3 * N1 + kk]};
+                const Bg bR = d == 2 ? Bg{sBgZ[(f & 1) * 4], sBgZ[(f & 1) * 4 + 1], sBgZ[(f & 1) * 4 + 2],
+                                          sBgZ[(f & 1) * 4 + 3]}
+                                     : bL;
+                const double PpL = pprime(qL[4], bL.rTh, bL.P, gamma, A.binom);
+                const double PpR = pprime(qR[4], bR.rTh, bR.P, gamma, A.binom);
+                double Fs[5], Fo[5];
+                rusanov<d>(qL, bL, PpL, qR, bR, PpR, sgn, gamma, Fs, Fo);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) slot[v * NF] = (Fs[v] - Fo[v]) * lift;
+                return;
             } else {
                 // both traces requested before either is used (a wall face loads its
                 // own entry twice and mirrors it below)
