@@ -248,7 +248,7 @@ struct StageLds {
         return (planes * NP * ESZ + 7) / 8 > 5 * NP ? (planes * NP * ESZ + 7) / 8 : 5 * NP;
     }
     // bytes of the other LDS arrays of k_stage
-    static constexpr int FIXED = 8 * (30 * NF + N1 * N1 + 4 * N1 + 4 + (MIX ? 15 : 1)) + 4 * 2 * N1 * N1 + 4 * 36;
+    static constexpr int FIXED = 8 * (30 * NF + N1 * N1 + 4 * N1 + 4 + 8 + (MIX ? 15 : 1)) + 4 * (MIX ? 2 * N1 * N1 : 1) + 4 * 36;
     static constexpr int blocks(int planes) {
         const int by_lds = 160 * 1024 / (FIXED + 8 * work_dbl(planes));
         const int by_waves = 4 * StageOcc<N>::W / (Sz<N>::NT / 64);
@@ -391,7 +391,7 @@ k_stage(const StageArgs A) {
     __shared__ double sS[30 * NF];
     // sW: first this leaf's tile [5][NP], then the flux planes of the volume phase
     __shared__ double sW[StageLds<N, MIX>::WORK];
-    __shared__ float sD32[2 * N1 * N1];  // MIX: D high and low parts
+    __shared__ float sD32[MIX ? 2 * N1 * N1 : 1];  // MIX: D high and low parts
     __shared__ double sD[N1 * N1];
     __shared__ double sBg[4 * N1];       // rho, Theta, P, 1/Theta of the background
     __shared__ double sGeo[4];
@@ -713,15 +713,29 @@ k_stage(const StageArgs A) {
     }
 
     if (t >= NP) return;
-    // ---- lift: subtract the face contributions at the face nodes
+    // ---- lift: subtract the face contributions at the face nodes, x then y then z
+    // (a node lies on at most one face per axis; off the faces of an axis it reads a
+    // valid slot and subtracts 0, so no branches)
+    {
+        const double* px = sS + (i == N ? 5 : 0) * NF + j + N1 * k;
+        const double* py = sS + (j == N ? 15 : 10) * NF + i + N1 * k;
+        const double* pz = sS + (k == N ? 25 : 20) * NF + i + N1 * j;
+        const bool ox = i == 0 || i == N, oy = j == 0 || j == N, oz = k == 0 || k == N;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        if (i == 0) R[v] -= sS[(0 * 5 + v) * NF + j + N1 * k];
-        if (i == N) R[v] -= sS[(1 * 5 + v) * NF + j + N1 * k];
-        if (j == 0) R[v] -= sS[(2 * 5 + v) * NF + i + N1 * k];
-        if (j == N) R[v] -= sS[(3 * 5 + v) * NF + i + N1 * k];
-        if (k == 0) R[v] -= sS[(4 * 5 + v) * NF + i + N1 * j];
-        if (k == N) R[v] -= sS[(5 * 5 + v) * NF + i + N1 * j];
+        for (int v = 0; v < 5; ++v) {
+            const double a = px[v * NF];
+            R[v] -= ox ? a : 0.0;
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            const double a = py[v * NF];
+            R[v] -= oy ? a : 0.0;
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            const double a = pz[v * NF];
+            R[v] -= oz ? a : 0.0;
+        }
     }
     const int64_t base = e * NP + t;
     if (MODE == MODE_RHS) {
