@@ -76,19 +76,27 @@ constexpr int kBinomTerms = 10;
 
 // x = Theta' (1/Thetabar): every kernel forms 1/Thetabar by the same IEEE division,
 // so a node's P' has the same bits wherever it is evaluated
-__device__ __forceinline__ double pprime(double Thp, double rThb, double Pb, double gamma, const BinomCoef& bc) {
-    double x = Thp * rThb;
-    int m = 0;
-    // every step halves |log(1 + x)|; NaN (and x <= -1) leave the loop at once
-    while (fabs(x) > 0.0078125 && m < 64) {
-        x = x / (1.0 + sqrt(1.0 + x));
-        ++m;
-    }
+__device__ __forceinline__ double binom_series(double x, const BinomCoef& bc) {
     double acc = bc.c[kBinomTerms - 1];
 #pragma unroll
     for (int k = kBinomTerms - 2; k >= 0; --k) acc = fma(acc, x, bc.c[k]);
-    double r = acc * x;
-    for (; m > 0; --m) r = r * (r + 2.0);
+    return acc * x;
+}
+
+__device__ __forceinline__ double pprime(double Thp, double rThb, double Pb, double gamma, const BinomCoef& bc) {
+    const double x = Thp * rThb;
+    double r = binom_series(x, bc);
+    if (__builtin_expect(!(fabs(x) <= 0.0078125), 0)) {
+        // every step halves |log(1 + y)|; NaN (and y <= -1) leave the loop at once
+        double y = x;
+        int m = 0;
+        while (fabs(y) > 0.0078125 && m < 64) {
+            y = y / (1.0 + sqrt(1.0 + y));
+            ++m;
+        }
+        r = binom_series(y, bc);
+        for (; m > 0; --m) r = r * (r + 2.0);
+    }
     return Pb * r;
 }
 
@@ -531,6 +539,7 @@ k_stage(const StageArgs A) {
     constexpr int PAD = ((2 * NF + 63) / 64) * 64;
 #pragma unroll 1
     for (int it = t; it < 3 * PAD; it += NT) {
+        // PAD and NT are whole waves: the axis is the same across a wave
         const int ax = it / PAD, r = it % PAD;
         if (r >= 2 * NF) continue;
         const int f = 2 * ax + r / NF, m = r % NF;
