@@ -1163,15 +1163,28 @@ k_adjoint(const AdjArgs A) {
         }
         g[0] -= A.g * lam[3];  // buoyancy -rho' g on rho*w
     }
-    // ---- faces that touch this node
+    // ---- faces that touch this node, x then y then z (at most one face per axis;
+    // off the faces of an axis a valid slot is read and 0 added: no branches)
+    {
+        const double* px = sS + (i == N ? 5 : 0) * NF + j + N1 * k;
+        const double* py = sS + (j == N ? 15 : 10) * NF + i + N1 * k;
+        const double* pz = sS + (k == N ? 25 : 20) * NF + i + N1 * j;
+        const bool ox = i == 0 || i == N, oy = j == 0 || j == N, oz = k == 0 || k == N;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        if (i == 0) g[v] += sS[(0 * 5 + v) * NF + j + N1 * k];
-        if (i == N) g[v] += sS[(1 * 5 + v) * NF + j + N1 * k];
-        if (j == 0) g[v] += sS[(2 * 5 + v) * NF + i + N1 * k];
-        if (j == N) g[v] += sS[(3 * 5 + v) * NF + i + N1 * k];
-        if (k == 0) g[v] += sS[(4 * 5 + v) * NF + i + N1 * j];
-        if (k == N) g[v] += sS[(5 * 5 + v) * NF + i + N1 * j];
+        for (int v = 0; v < 5; ++v) {
+            const double a = px[v * NF];
+            g[v] += ox ? a : 0.0;
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            const double a = py[v * NF];
+            g[v] += oy ? a : 0.0;
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            const double a = pz[v * NF];
+            g[v] += oz ? a : 0.0;
+        }
     }
     const int64_t base = e * NP + t;
     if (MODE == MODE_RHS) {
