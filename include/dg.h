@@ -164,9 +164,10 @@ dg_status dg_init_bell(const dg_mesh* mesh, const dg_phys* phys, const dg_bell* 
  * -rho' g on rho*w, F* the Rusanov flux (local max wave speed, jump of the
  * perturbation variables), mirror states at walls and L2 mortars on hanging
  * faces (section 3.3).  rhs must not alias q.  The mortars are evaluated by a
- * pre-pass into a workspace owned by the mesh, so calls of dg_rhs and
- * dg_rk_stage on one mesh must be ordered (one stream, or synchronised);
- * concurrent calls on different meshes are independent. */
+ * pre-pass into a workspace owned by the mesh, so calls of dg_rhs,
+ * dg_rk_stage, dg_rhs_adjoint and dg_rk_stage_adjoint on one mesh must be
+ * ordered (one stream, or synchronised); concurrent calls on different meshes
+ * are independent. */
 dg_status dg_rhs(const dg_mesh* mesh, const dg_phys* phys, const double* q, double* rhs,
                  void* stream);
 
@@ -208,7 +209,9 @@ dg_status dg_coarsen_project_adjoint(const dg_mesh* from, const dg_mesh* to, con
  * phys->precision == DG_MIXED the transposed volume contractions D^T lam run in
  * float32 (lam rounded to float32, D split into float32 high and low parts,
  * float32 accumulation); faces, mortars, the chain rule and the output stay
- * float64 (relative error of the order 1e-7 against the float64 transpose). */
+ * float64 (relative error of the order 1e-7 against the float64 transpose).
+ * The transposed mortars run as a pre-pass into the mesh's mortar workspace
+ * (ordering as for dg_rhs). */
 dg_status dg_rhs_adjoint(const dg_mesh* mesh, const dg_phys* phys, const double* q,
                          const double* lam, double* qbar, void* stream);
 

@@ -535,6 +535,8 @@ static dg_status adjoint_common(const dg_mesh* mc, const dg_phys* phys, int mode
     a.bg = m->d_bg;
     a.ftype = m->d_ftype;
     a.fnb = m->d_fnb;
+    a.hslot = m->d_hslot;
+    a.mort = m->d_mort;
     a.K = (int64_t)m->h.leaves.size();
     a.a1 = a1;
     a.a2 = a2;
@@ -543,6 +545,10 @@ static dg_status adjoint_common(const dg_mesh* mc, const dg_phys* phys, int mode
     a.gamma = phys->cp / phys->cv;
     a.g = phys->g;
     a.binom = binom_coef(phys);
+    if (m->n_hang) {
+        MortAdjArgs ma{q, lam, m->d_mort, m->d_ops, m->d_geo, m->d_bg, m->d_hang, m->n_hang, a.K, a.gamma, a.binom};
+        HIP_TRY(launch_mortar_adjoint(m->h.desc.N, ma, s));
+    }
     HIP_TRY(launch_adjoint(m->h.desc.N, mode, phys->precision == DG_MIXED, a, s));
     return DG_OK;
 }

@@ -848,19 +848,153 @@ __device__ __forceinline__ void own_flux_vjp(const double q[5], const Bg& b, dou
     flux_vjp<D>(q, S.rinv, S.ud, S.Th, S.dPdT, a, g);
 }
 
+// Transposed mortar pre-pass (the transpose of k_mortar's three steps, one hanging
+// face per workgroup).  With w = -lift_f lam_f + lift_c (R_a^T x R_b^T) lam_c at a
+// mortar point, w . F*(q_f, q_m, n_f) is the part of <lam, R> that the point
+// carries; its gradient with respect to the fine state goes to the fine face
+// (with the fine side's own-flux term), its gradient with respect to the mortar
+// state q_m = (I_a x I_b) q_c goes back to the coarse face through I_a^T x I_b^T
+// (with the coarse side's own-flux term).  F*(q_m, q_f, n_c) = -F*(q_f, q_m, n_f)
+// and the coarse side's weight is -w, so one VJP serves both sides.  Output per
+// hanging face h: mort[h][0] the coarse face, mort[h][1 + quad] the fine faces,
+// each [5][NF], added to qbar by the adjoint kernel.
 template <int N>
-struct AdjLds {
-    static constexpr int NF = Sz<N>::NF;
-    // sT, sT2 [5][NF] each, sU [20][NF], sMq [40][NF], sG [10][NF]
-    static constexpr int SCR = 80 * NF;
-};
+__global__ void __launch_bounds__(Sz<N>::NT) k_mortar_adjoint(const MortAdjArgs A) {
+    constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
+    constexpr int NOPS = Sz<N>::NOPS + 4 * NF;
+    static_assert(4 * NF <= NT, "one mortar point per thread");
+    // sT [10][NF]: coarse q (0..4) and lam (5..9); sU [20][NF]; sMq [40][NF]: per
+    // quadrant q_m (0..4) and R^T lam (5..9), later the mortar-state gradient; sG [10][NF]
+    __shared__ double sT[10 * NF], sU[20 * NF], sMq[40 * NF], sG[10 * NF];
+    __shared__ double sOps[NOPS];
+    __shared__ double sBg[4 * N1];  // the coarse leaf's background, with 1/Theta
+    auto IT = [&](int a) { return sOps + 5 * NF + N1 + a * NF; };
+    auto RT = [&](int a) { return sOps + 7 * NF + N1 + a * NF; };
+    const int64_t h = xcd_remap(blockIdx.x, gridDim.x);
+    const int t = threadIdx.x;
+    const int32_t* const row = A.hang + h * 6;
+    const int64_t ec = row[0];
+    const int f = row[1], fo = f ^ 1;
+    const int KNP = (int)(A.K * NP), KN1 = (int)(A.K * N1);
+    const double gamma = A.gamma;
+    const double liftc = 0.5 * N * (N + 1);   // 1/w_N
+    const double sgn_c = (f & 1) ? 1.0 : -1.0;  // the coarse leaf's outward normal
+    for (int ii = t; ii < NOPS; ii += NT) sOps[ii] = A.ops[ii];
+    if (t < 3 * N1) {
+        const double v = A.bg[(t / N1) * KN1 + ec * N1 + (t % N1)];
+        sBg[t] = v;
+        if (t >= N1 && t < 2 * N1) sBg[2 * N1 + t] = 1.0 / v;
+    }
+    for (int it = t; it < 5 * NF; it += NT) {
+        const int v = it / NF, m = it % NF;
+        const int off = v * KNP + (int)ec * NP + face_node<N>(f, m);
+        sT[it] = A.q[off];
+        sT[5 * NF + it] = A.lam[off];
+    }
+    // this thread's fine-side point, loaded with the coarse trace: quadrant t / NF
+    double qF[5] = {0, 0, 0, 0, 0}, lF[5] = {0, 0, 0, 0, 0};
+    Bg bF{1.0, 1.0, 1.0, 1.0};
+    int64_t ef = 0;
+    if (t < 4 * NF) {
+        const int quad = t / NF, m = t % NF;
+        ef = row[2 + quad];
+        const int nn = face_node<N>(fo, m), kn = face_k<N>(fo, m);
+        bF = bg_make(A.bg[ef * N1 + kn], A.bg[KN1 + ef * N1 + kn], A.bg[2 * KN1 + ef * N1 + kn]);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            qF[v] = A.q[v * KNP + ef * NP + nn];
+            lF[v] = A.lam[v * KNP + ef * NP + nn];
+        }
+    }
+    __syncthreads();
+    // sU plane a*10 + c: along t1 with I_a (c < 5, state) or R_a^T (c >= 5, lambda)
+    apply_t1<N>(sT, sU, 20, [&](int p) { return (p % 10) < 5 ? sOps + (1 + p / 10) * NF : RT(p / 10); },
+                [](int p) { return p % 10; }, t, NT);
+    __syncthreads();
+    // sMq plane quad*10 + c, quad = a + 2b: along t2 with I_b or R_b^T
+    apply_t2<N>(sU, sMq, 40, [&](int p) { return (p % 10) < 5 ? sOps + (1 + (p / 10) / 2) * NF : RT((p / 10) / 2); },
+                [](int p) { return ((p / 10) & 1) * 10 + p % 10; }, t, NT);
+    __syncthreads();
+    if (t < 4 * NF) {
+        const int quad = t / NF, m = t % NF;
+        const double lift_f = A.geo[ef * 4 + (f >> 1)] * liftc;
+        const double lift_c = A.geo[ec * 4 + (f >> 1)] * liftc;
+        double qM[5], w[5], gF[5], gM[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            qM[v] = sMq[(quad * 10 + v) * NF + m];
+            w[v] = -lift_f * lF[v] + lift_c * sMq[(quad * 10 + 5 + v) * NF + m];
+        }
+        const double PpF = pprime(qF[4], bF.rTh, bF.P, gamma, A.binom);
+        const double PpM = pprime(qM[4], bF.rTh, bF.P, gamma, A.binom);
+        with_axis(f >> 1, [&](auto dc) {
+            constexpr int d = decltype(dc)::value;
+            rusanov_vjp<d>(qF, bF, PpF, qM, bF, PpM, -sgn_c, gamma, w, gF, gM);
+            own_flux_vjp<d>(qF, bF, PpF, -sgn_c, gamma, lift_f, lF, gF);
+        });
+        double* const out = A.mort + ((h * 5 + 1 + quad) * 5) * NF + m;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            out[v * NF] = gF[v];
+            sMq[(quad * 10 + v) * NF + m] = gM[v];  // in place: the mortar-state gradient
+        }
+    }
+    __syncthreads();
+    // back to the coarse face: sum_ab (I_a^T x I_b^T) gM_ab, first along t1 then t2
+    for (int it = t; it < 10 * NF; it += NT) {
+        const int p = it / NF, r = it % NF, bb = r / N1, a2 = r % N1;
+        const int qb = p / 5, v = p % 5;
+        double acc = 0.0;
+#pragma unroll
+        for (int qa = 0; qa < 2; ++qa) {
+            const double* Op = IT(qa) + a2 * N1;
+            const double* x = sMq + ((qa + 2 * qb) * 10 + v) * NF + bb * N1;
+#pragma unroll
+            for (int a = 0; a < N1; ++a) acc = fma(Op[a], x[a], acc);
+        }
+        sG[it] = acc;
+    }
+    __syncthreads();
+    for (int it = t; it < 5 * NF; it += NT) {
+        const int v = it / NF, m = it % NF, b2 = m / N1, a = m % N1;
+        double acc = 0.0;
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb) {
+            const double* Op = IT(qb) + b2 * N1;
+            const double* x = sG + (qb * 5 + v) * NF + a;
+#pragma unroll
+            for (int bb = 0; bb < N1; ++bb) acc = fma(Op[bb], x[bb * N1], acc);
+        }
+        sU[it] = acc;
+    }
+    __syncthreads();
+    if (t < NF) {
+        const int m = t, kk = face_k<N>(f, m);
+        const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk], sBg[3 * N1 + kk]};
+        const double lift_c = A.geo[ec * 4 + (f >> 1)] * liftc;
+        double qL[5], lL[5], g[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            qL[v] = sT[v * NF + m];
+            lL[v] = sT[(5 + v) * NF + m];
+            g[v] = sU[v * NF + m];
+        }
+        const double PpL = pprime(qL[4], b.rTh, b.P, gamma, A.binom);
+        with_axis(f >> 1, [&](auto dc) {
+            own_flux_vjp<decltype(dc)::value>(qL, b, PpL, sgn_c, gamma, lift_c, lL, g);
+        });
+        double* const out = A.mort + (h * 5 * 5) * NF + m;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) out[v * NF] = g[v];
+    }
+}
 
 // the adjoint keeps more state per node; bound it less tightly than the forward
+// (with the mortars in their own pre-pass, N = 7 fits 4 waves per SIMD: two
+// workgroups of 8 waves per CU)
 template <int N, bool MIX>
 struct AdjOcc {
-    // MIX at N = 7 fits two workgroups per CU in LDS; 4 waves per SIMD lets them
-    // both run (a few registers spill; measured faster than 2 waves per SIMD)
-    static constexpr int W = N >= 6 ? (MIX && N == 7 ? 4 : 2) : 3;
+    static constexpr int W = N >= 6 ? 4 : 3;
 };
 
 // MIX: the transposed volume contractions D^T lam in float32 (lambda tile rounded
@@ -870,23 +1004,18 @@ template <int N, int MODE, bool MIX>
 __global__ void __launch_bounds__(Sz<N>::NT) __attribute__((amdgpu_waves_per_eu(AdjOcc<N, MIX>::W)))
 k_adjoint(const AdjArgs A) {
     constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
-    constexpr int NOPS = Sz<N>::NOPS + 4 * NF;  // + I_0^T, I_1^T, R_0^T, R_1^T
+    constexpr int NOPS = N1 * N1;  // D
     __shared__ double sL[MIX ? (5 * NP + 1) / 2 : 5 * NP];  // lambda tile (MIX: float)
     __shared__ float sD32[MIX ? 2 * N1 * N1 : 1];            // MIX: D high and low parts
     float* const sLf = reinterpret_cast<float*>(sL);
     __shared__ double sPp[NP];
     __shared__ double sS[30 * NF];       // face contributions to qbar
-    __shared__ double sX[AdjLds<N>::SCR];
     __shared__ double sOps[NOPS];
     __shared__ double sBg[4 * N1];  // rho, Theta, P, 1/Theta of the background
     __shared__ int sType[6];
     __shared__ int sNb[24];
-    double* const sT = sX;             // q trace
-    double* const sT2 = sX + 5 * NF;   // lambda trace
-    // operator offsets in sOps: D 0, I_a (1+a), R_a (3+a), w 5, I_a^T after w, R_a^T
+    __shared__ int sHs[6];          // hanging face: row of the transposed mortar pre-pass
     const double* D = sOps;
-    auto IT = [&](int a) { return sOps + 5 * NF + N1 + a * NF; };
-    auto RT = [&](int a) { return sOps + 7 * NF + N1 + a * NF; };
 
     const int64_t K = A.K;
     const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
@@ -915,6 +1044,7 @@ k_adjoint(const AdjArgs A) {
     }
     if (t < 6) sType[t] = A.ftype[e * 6 + t];
     if (t < 24) sNb[t] = A.fnb[e * 24 + t];
+    if (t < 6) sHs[t] = A.hslot[e * 6 + t];
     double q[5] = {0, 0, 0, 0, 0}, lam[5] = {0, 0, 0, 0, 0};
     if (t < NP) {
 #pragma unroll
@@ -935,8 +1065,14 @@ k_adjoint(const AdjArgs A) {
 #pragma unroll 1
     for (int it = t; it < 6 * NF; it += NT) {
         const int f = it / NF, m = it % NF;
-        const int type = sType[f] & 0xff;
-        if (type != FT_WALL && type != FT_CONF) continue;
+        const int tf = sType[f], type = tf & 0xff;
+        if (type == FT_FINE || type == FT_COARSE) {
+            // hanging face: the transposed mortar pre-pass holds this side's contribution
+            const int64_t row = (int64_t)sHs[f] * 5 + (type == FT_COARSE ? 0 : 1 + ((tf >> 8) & 0xff));
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = A.mort[(row * 5 + v) * NF + m];
+            continue;
+        }
         const double sgn = (f & 1) ? 1.0 : -1.0;
         const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
         const double lift = A.geo[e * 4 + (f >> 1)] * liftc;
@@ -983,142 +1119,6 @@ k_adjoint(const AdjArgs A) {
         });
     }
 
-    // ---- hanging faces (separable two-pass tensor products, all threads busy)
-    double* const sU = sX + 10 * NF;   // [20][NF]
-    double* const sMq = sX + 30 * NF;  // [40][NF]
-    double* const sG = sX + 70 * NF;   // [10][NF]
-#pragma unroll 1
-    for (int f = 0; f < 6; ++f) {
-        const int type = sType[f] & 0xff;
-        if (type != FT_FINE && type != FT_COARSE) continue;
-        const int fo = f ^ 1;
-        const double lift = A.geo[e * 4 + (f >> 1)] * liftc;
-        const double sgn = (f & 1) ? 1.0 : -1.0;
-        if (type == FT_FINE) {
-            const int ec = sNb[f * 4];
-            const int quad = (sType[f] >> 8) & 0xff, qa = quad & 1, qb = quad >> 1;
-            const double liftcoarse = A.geo[ec * 4 + (f >> 1)] * liftc;
-            __syncthreads();
-            for (int it = t; it < 5 * NF; it += NT) {
-                const int v = it / NF, m = it % NF;
-                const int off = v * KNP + ec * NP + face_node<N>(fo, m);
-                sT[it] = qs[off];
-                sT2[it] = ls[off];
-            }
-            __syncthreads();
-            // planes 0..4: mortar state (I_a x I_b) q_c; 5..9: (R_a^T x R_b^T) lam_c
-            apply_t1<N>(sT, sU, 10, [&](int p) { return p < 5 ? sOps + (1 + qa) * NF : RT(qa); },
-                        [](int p) { return p; }, t, NT);
-            __syncthreads();
-            apply_t2<N>(sU, sMq, 10, [&](int p) { return p < 5 ? sOps + (1 + qb) * NF : RT(qb); },
-                        [](int p) { return p; }, t, NT);
-            __syncthreads();
-            for (int m = t; m < NF; m += NT) {
-                const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
-                const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk], sBg[3 * N1 + kk]};
-                double qL[5], lL[5], qM[5], w[5], g[5];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    qL[v] = qe[v * KNP + n];
-                    lL[v] = MIX ? le[v * KNP + n] : sL[v * NP + n];
-                    qM[v] = sMq[v * NF + m];
-                    w[v] = -lift * lL[v] + liftcoarse * sMq[(5 + v) * NF + m];
-                }
-                const double PpM = pprime(qM[4], b.rTh, b.P, gamma, A.binom);
-                with_axis(f >> 1, [&](auto dc) {
-                    constexpr int d = decltype(dc)::value;
-                    rusanov_vjp<d>(qL, b, sPp[n], qM, b, PpM, sgn, gamma, w, g, nullptr);
-                    own_flux_vjp<d>(qL, b, sPp[n], sgn, gamma, lift, lL, g);
-                });
-#pragma unroll
-                for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = g[v];
-            }
-        } else {
-            __syncthreads();
-            for (int it = t; it < 5 * NF; it += NT) {
-                const int v = it / NF, m = it % NF;
-                const int n = face_node<N>(f, m);
-                sT[it] = qe[v * KNP + n];
-                sT2[it] = MIX ? le[v * KNP + n] : sL[v * NP + n];
-            }
-            __syncthreads();
-            // sU plane a*10 + c: along t1 with I_a (c < 5, state) or R_a^T (c >= 5, lambda)
-            apply_t1<N>(sT, sU, 20, [&](int p) { return (p % 10) < 5 ? sOps + (1 + p / 10) * NF : RT(p / 10); },
-                        [](int p) { return p % 10; }, t, NT);
-            __syncthreads();
-            // sMq plane quad*10 + c, quad = a + 2b: along t2 with I_b or R_b^T
-            apply_t2<N>(sU, sMq, 40,
-                        [&](int p) { return (p % 10) < 5 ? sOps + (1 + (p / 10) / 2) * NF : RT((p / 10) / 2); },
-                        [](int p) { return ((p / 10) & 1) * 10 + p % 10; }, t, NT);
-            __syncthreads();
-            for (int it = t; it < 4 * NF; it += NT) {
-                const int quad = it / NF, m = it % NF;
-                const int ef = sNb[f * 4 + quad];
-                const int nn = face_node<N>(fo, m), kn = face_k<N>(fo, m);
-                const double liftf = A.geo[ef * 4 + (f >> 1)] * liftc;
-                const Bg b = bg_make(A.bg[ef * N1 + kn], A.bg[KN1 + ef * N1 + kn], A.bg[2 * KN1 + ef * N1 + kn]);
-                double qM[5], qF[5], w[5], g[5];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    qM[v] = sMq[(quad * 10 + v) * NF + m];
-                    qF[v] = qs[v * KNP + ef * NP + nn];
-                    w[v] = -lift * sMq[(quad * 10 + 5 + v) * NF + m] + liftf * ls[v * KNP + ef * NP + nn];
-                }
-                const double PpM = pprime(qM[4], b.rTh, b.P, gamma, A.binom);
-                const double PpF = pprime(qF[4], b.rTh, b.P, gamma, A.binom);
-                with_axis(f >> 1, [&](auto dc) {
-                    rusanov_vjp<decltype(dc)::value>(qM, b, PpM, qF, b, PpF, sgn, gamma, w, g, nullptr);
-                });
-#pragma unroll
-                for (int v = 0; v < 5; ++v) sMq[(quad * 10 + v) * NF + m] = g[v];  // in place
-            }
-            __syncthreads();
-            // back to the coarse face: sum_ab (I_a^T x I_b^T) gbar_ab, first along t1 then t2
-            for (int it = t; it < 10 * NF; it += NT) {
-                const int p = it / NF, r = it % NF, bb = r / N1, a2 = r % N1;
-                const int qb = p / 5, v = p % 5;
-                double acc = 0.0;
-#pragma unroll
-                for (int qa = 0; qa < 2; ++qa) {
-                    const double* Op = IT(qa) + a2 * N1;
-                    const double* x = sMq + ((qa + 2 * qb) * 10 + v) * NF + bb * N1;
-#pragma unroll
-                    for (int a = 0; a < N1; ++a) acc = fma(Op[a], x[a], acc);
-                }
-                sG[it] = acc;
-            }
-            __syncthreads();
-            for (int it = t; it < 5 * NF; it += NT) {
-                const int v = it / NF, m = it % NF, b2 = m / N1, a = m % N1;
-                double acc = 0.0;
-#pragma unroll
-                for (int qb = 0; qb < 2; ++qb) {
-                    const double* Op = IT(qb) + b2 * N1;
-                    const double* x = sG + (qb * 5 + v) * NF + a;
-#pragma unroll
-                    for (int bb = 0; bb < N1; ++bb) acc = fma(Op[bb], x[bb * N1], acc);
-                }
-                sU[it] = acc;
-            }
-            __syncthreads();
-            for (int m = t; m < NF; m += NT) {
-                const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
-                const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk], sBg[3 * N1 + kk]};
-                double qL[5], lL[5], g[5];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    qL[v] = qe[v * KNP + n];
-                    lL[v] = MIX ? le[v * KNP + n] : sL[v * NP + n];
-                    g[v] = sU[v * NF + m];
-                }
-                with_axis(f >> 1, [&](auto dc) {
-                    own_flux_vjp<decltype(dc)::value>(qL, b, sPp[n], sgn, gamma, lift, lL, g);
-                });
-#pragma unroll
-                for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = g[v];
-            }
-        }
-    }
     __syncthreads();
 
     if (t >= NP) return;
@@ -1589,6 +1589,12 @@ hipError_t launch_stage(int N, int mode, bool mixed, const StageArgs& a, hipStre
             DG_DISPATCH_N(N, (k_stage<NN, MODE_RK, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
         }
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_mortar_adjoint(int N, const MortAdjArgs& a, hipStream_t s) {
+    if (a.n_hang <= 0) return hipSuccess;
+    DG_DISPATCH_N(N, (k_mortar_adjoint<NN><<<dim3((unsigned)a.n_hang), dim3(Sz<NN>::NT), 0, s>>>(a)));
     return hipGetLastError();
 }
 

@@ -48,6 +48,8 @@ struct AdjArgs {
     const double* bg;
     const int32_t* ftype;
     const int32_t* fnb;
+    const int32_t* hslot;  // [K][6]: row of the hanging-face table, or -1
+    const double* mort;    // [n_hang][5][5][NF]: mortar contributions to qbar (k_mortar_adjoint)
     int64_t K;
     double a1, a2, b, dt;
     double gamma, g;
@@ -67,6 +69,21 @@ struct MortArgs {
     const double* geo;
     const double* bg;
     const int32_t* hang;   // [n_hang][6]: coarse leaf, its face, the 4 fine leaves by quadrant
+    int64_t n_hang, K;
+    double gamma;
+    BinomCoef binom;
+};
+
+// transposed mortar pre-pass: one workgroup per row of the hanging-face table;
+// q the state, lam the adjoint weights, mort [n_hang][5][5][NF] the output
+struct MortAdjArgs {
+    const double* q;
+    const double* lam;
+    double* mort;
+    const double* ops;     // with the transposes I_a^T, R_a^T
+    const double* geo;
+    const double* bg;
+    const int32_t* hang;
     int64_t n_hang, K;
     double gamma;
     BinomCoef binom;
@@ -116,6 +133,7 @@ hipError_t launch_init_bell(int64_t K, int N, const double* c1d, const double* b
                             double* q, hipStream_t s);
 hipError_t launch_node_coords(int64_t K, int N, const double* c1d, double* xyz, hipStream_t s);
 hipError_t launch_mortar(int N, const MortArgs& a, hipStream_t s);
+hipError_t launch_mortar_adjoint(int N, const MortAdjArgs& a, hipStream_t s);
 // adjoint = false: the projection; true: its transpose
 hipError_t launch_refine(int N, bool adjoint, const XferArgs& a, hipStream_t s);
 hipError_t launch_coarsen(int N, bool adjoint, const XferArgs& a, hipStream_t s);
