@@ -1061,10 +1061,14 @@ k_adjoint(const AdjArgs A) {
     __syncthreads();
 
     const double liftc = 0.5 * N * (N + 1);
-    // ---- conforming faces and walls
-#pragma unroll 1
-    for (int it = t; it < 6 * NF; it += NT) {
-        const int f = it / NF, m = it % NF;
+    // ---- conforming faces and walls; items grouped by axis, each axis padded to
+    // whole waves (a wave never mixes the three axis variants)
+    constexpr int PAD = ((2 * NF + 63) / 64) * 64;
+#pragma unroll
+    for (int it = t; it < 3 * PAD; it += NT) {
+        const int ax = it / PAD, r = it % PAD;
+        if (r >= 2 * NF) continue;
+        const int f = 2 * ax + r / NF, m = r % NF;
         const int tf = sType[f], type = tf & 0xff;
         if (type == FT_FINE || type == FT_COARSE) {
             // hanging face: the transposed mortar pre-pass holds this side's contribution
@@ -1075,8 +1079,8 @@ k_adjoint(const AdjArgs A) {
         }
         const double sgn = (f & 1) ? 1.0 : -1.0;
         const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
-        const double lift = A.geo[e * 4 + (f >> 1)] * liftc;
-        with_axis(f >> 1, [&](auto dc) {
+        const double lift = A.geo[e * 4 + ax] * liftc;
+        with_axis(ax, [&](auto dc) {
             constexpr int d = decltype(dc)::value;
             double qL[5], lL[5], qR[5], w[5], g[5], gR[5];
 #pragma unroll
