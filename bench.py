@@ -389,6 +389,11 @@ def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us):
     dst = torch.empty_like(src)
     cu = _time_launches(torch, lambda: dst.copy_(src), 10)
     out["copy_1GiB_GBs"] = 2.0 * (1 << 30) / (cu * 1e-6) / 1e9
+    # ---- measured float64 FMA rate (8 independent chains per thread) beside the 78.6 TF spec
+    sink = torch.empty(256 * 4096, dtype=torch.float64, device=q.device)
+    flops = dg.dg_fma_burst(4096, 4000, sink)
+    fu = _time_launches(torch, lambda: dg.dg_fma_burst(4096, 4000, sink), 5)
+    out["fma_f64_TFLOPs"] = flops / (fu * 1e-6) / 1e12
     del src, dst
     return out
 

@@ -243,6 +243,23 @@ dg_status dg_indicator(const dg_mesh* mesh, const dg_phys* phys, const double* q
                        double thr, double* eta, int8_t* flags_host, void* stream);
 
 /* Message of the last failed call on this thread ("" if none). */
+/* Buffer zone around refinement (section 3.2: at least B coarse cells between a
+ * feature and the coarse-fine interface, the same B in the tree-based code).
+ * Reading: B rounds of face-neighbour dilation of the +1 flags, in place on the
+ * host array flags (int8[K], as from dg_indicator): in each round every leaf
+ * that shares a face with a leaf flagged +1 (conforming, or either side of a
+ * hanging face) becomes +1, whatever its flag was; other flags are kept.  Host
+ * only (the mesh's host tables); B >= 0. */
+dg_status dg_flags_buffer(const dg_mesh* mesh, int8_t* flags, int32_t B);
+
+/* Calibration only, not part of the method: one launch of `blocks` workgroups of
+ * 256 threads, every thread running `iters` rounds of 8 independent float64
+ * fused multiply-adds, so that a caller timing it on `stream` can compare the
+ * chip's achievable float64 vector rate with its published peak.  sink is a
+ * device double[256*blocks] (one value per thread, keeps the work live);
+ * *flops_out (host) receives 2*8*iters*256*blocks.  blocks, iters > 0. */
+dg_status dg_fma_burst(int32_t blocks, int32_t iters, double* sink, double* flops_out, void* stream);
+
 const char* dg_last_error(void);
 
 #ifdef __cplusplus

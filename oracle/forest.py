@@ -360,3 +360,31 @@ def leaf_boxes(mesh: Mesh):
             out[e, 0, d] = (rc[d] << L) + anc[d] * size
             out[e, 1, d] = out[e, 0, d] + size
     return out
+
+
+def buffer_flags(mesh: Mesh, flags, B: int):
+    """Buffer zone around refinement (section 3.2: at least B coarse cells between a
+    feature and the coarse-fine interface; the tree-based code uses the same B).
+    Reading: B rounds of face-neighbour dilation of the +1 flags; in each round
+    every leaf that shares a face with a leaf flagged +1 is flagged +1 (0 and -1
+    alike).  Face adjacency from the mesh's own lists: CONF pairs and the coarse
+    leaf of each HANG row with each of its four fine leaves."""
+    K = mesh.K
+    adj = [set() for _ in range(K)]
+    for eM, eP, _d in mesh.conf:
+        adj[int(eM)].add(int(eP))
+        adj[int(eP)].add(int(eM))
+    for row in mesh.hang:
+        ec = int(row[0])
+        for x in row[2:]:
+            adj[ec].add(int(x))
+            adj[int(x)].add(ec)
+    out = [int(v) for v in flags]
+    for _ in range(B):
+        cur = list(out)
+        for e in range(K):
+            if cur[e] > 0:
+                for x in adj[e]:
+                    out[x] = 1
+    return np.array(out, dtype=np.int8)
+

@@ -564,6 +564,33 @@ dg_status dg_rk_stage_adjoint(const dg_mesh* m, const dg_phys* phys, double a1, 
     return adjoint_common(m, phys, MODE_RK, a1, w1, a2, w2, b, dt, q, y, out, stream);
 }
 
+dg_status dg_flags_buffer(const dg_mesh* m, int8_t* flags, int32_t B) {
+    if (!m || !flags) return fail(DG_EINVAL, "NULL argument");
+    if (B < 0) return fail(DG_EINVAL, "B must be >= 0");
+    const HostMesh& h = m->h;
+    const int64_t K = (int64_t)h.leaves.size();
+    std::vector<int8_t> cur((size_t)K);
+    for (int32_t round = 0; round < B; ++round) {
+        std::memcpy(cur.data(), flags, (size_t)K);
+        for (int64_t e = 0; e < K; ++e) {
+            if (cur[(size_t)e] <= 0) continue;
+            for (int f = 0; f < 6; ++f) {
+                const int type = h.ftype[e * 6 + f] & 0xff;
+                const int nnb = type == FT_WALL ? 0 : type == FT_COARSE ? 4 : 1;
+                for (int q = 0; q < nnb; ++q) flags[h.fnb[(e * 6 + f) * 4 + q]] = 1;
+            }
+        }
+    }
+    return DG_OK;
+}
+
+dg_status dg_fma_burst(int32_t blocks, int32_t iters, double* sink, double* flops_out, void* stream) {
+    if (blocks <= 0 || iters <= 0 || !sink || !flops_out) return fail(DG_EINVAL, "need blocks, iters > 0 and sink, flops_out");
+    HIP_TRY(launch_fma_burst(blocks, iters, sink, (hipStream_t)stream));
+    *flops_out = 2.0 * 8.0 * (double)iters * 256.0 * (double)blocks;
+    return DG_OK;
+}
+
 dg_status dg_budgets(const dg_mesh* mc, const dg_phys* phys, const double* q, double* out_host, void* stream) {
     dg_status st = check_dev_mesh(mc);
     if (st) return st;

@@ -1596,6 +1596,27 @@ hipError_t launch_stage(int N, int mode, bool mixed, const StageArgs& a, hipStre
     return hipGetLastError();
 }
 
+// float64 FMA rate calibration: 8 independent dependency chains per thread
+__global__ void __launch_bounds__(256) k_fma_burst(int iters, double* sink) {
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const double m = 0.9999999, c = 1e-7;
+    double x[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) x[r] = 1e-3 * (double)(threadIdx.x + r);
+    for (int i = 0; i < iters; ++i)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) x[r] = fma(x[r], m, c);
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) acc += x[r];
+    sink[gid] = acc;
+}
+
+hipError_t launch_fma_burst(int blocks, int iters, double* sink, hipStream_t s) {
+    k_fma_burst<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(iters, sink);
+    return hipGetLastError();
+}
+
 hipError_t launch_mortar_adjoint(int N, const MortAdjArgs& a, hipStream_t s) {
     if (a.n_hang <= 0) return hipSuccess;
     DG_DISPATCH_N(N, (k_mortar_adjoint<NN><<<dim3((unsigned)a.n_hang), dim3(Sz<NN>::NT), 0, s>>>(a)));

@@ -134,6 +134,7 @@ hipError_t launch_init_bell(int64_t K, int N, const double* c1d, const double* b
 hipError_t launch_node_coords(int64_t K, int N, const double* c1d, double* xyz, hipStream_t s);
 hipError_t launch_mortar(int N, const MortArgs& a, hipStream_t s);
 hipError_t launch_mortar_adjoint(int N, const MortAdjArgs& a, hipStream_t s);
+hipError_t launch_fma_burst(int blocks, int iters, double* sink, hipStream_t s);
 // adjoint = false: the projection; true: its transpose
 hipError_t launch_refine(int N, bool adjoint, const XferArgs& a, hipStream_t s);
 hipError_t launch_coarsen(int N, bool adjoint, const XferArgs& a, hipStream_t s);

@@ -37,7 +37,7 @@ DG_KIND_FAMILY = 8
 EXPORTED = [
     "dg_mesh_build", "dg_mesh_free", "dg_mesh_info_get", "dg_mesh_export", "dg_node_coords",
     "dg_init_bell", "dg_rhs", "dg_rk_stage", "dg_refine_project", "dg_coarsen_project",
-    "dg_refine_project_adjoint", "dg_coarsen_project_adjoint", "dg_rhs_adjoint", "dg_rk_stage_adjoint", "dg_budgets", "dg_indicator", "dg_last_error",
+    "dg_refine_project_adjoint", "dg_coarsen_project_adjoint", "dg_rhs_adjoint", "dg_rk_stage_adjoint", "dg_budgets", "dg_indicator", "dg_flags_buffer", "dg_fma_burst", "dg_last_error",
 ]
 
 
@@ -101,6 +101,8 @@ def lib():
         L.dg_rk_stage_adjoint.argtypes = [P, C.POINTER(Phys), C.c_double, P, C.c_double, P, C.c_double,
                                           C.c_double, P, P, P, P]
         L.dg_budgets.argtypes = [P, C.POINTER(Phys), P, P, P]
+        L.dg_fma_burst.argtypes = [C.c_int32, C.c_int32, P, P, P]
+        L.dg_flags_buffer.argtypes = [P, P, C.c_int32]
         L.dg_indicator.argtypes = [P, C.POINTER(Phys), P, C.c_int32, C.c_double, P, P, P]
         L.dg_last_error.restype = C.c_char_p
         for name in EXPORTED:
@@ -296,6 +298,24 @@ def dg_rk_stage_adjoint(mesh: Mesh, phys: PhysParams, a1, w1, a2, w2, b, dt, q, 
                                      _ptr(y), _ptr(out), _stream(stream)))
 
 
+def dg_flags_buffer(mesh: Mesh, flags, B):
+    """Buffer zone: B rounds of face-neighbour dilation of the +1 flags (returns a new array)."""
+    fl = np.ascontiguousarray(np.asarray(flags, dtype=np.int8)).copy()
+    if fl.shape != (mesh.K,):
+        raise ValueError("flags must have one entry per leaf")
+    _check(lib().dg_flags_buffer(mesh.handle, C.c_void_p(fl.ctypes.data), int(B)))
+    return fl
+
+
+def dg_fma_burst(blocks, iters, sink, stream=None):
+    """Calibration launch (float64 FMA rate); returns the flops it performs."""
+    if tuple(sink.shape) != (256 * blocks,):
+        raise ValueError("sink must be [256*blocks]")
+    out = C.c_double()
+    _check(lib().dg_fma_burst(blocks, iters, _ptr(sink), C.byref(out), _stream(stream)))
+    return out.value
+
+
 def dg_budgets(mesh: Mesh, phys: PhysParams, q, stream=None):
     _shape_check(mesh, q)
     out = (C.c_double * 4)()
@@ -323,12 +343,14 @@ def ssp_rk3_step(mesh: Mesh, phys: PhysParams, dt, q, q1, q2, stream=None):
     dg_rk_stage(mesh, phys, *SSP_RK3[2], dt, q, q2, q, stream)
 
 
-def adapt_meshes(mesh: Mesh, phys: PhysParams, q, kind, thr, stream=None):
+def adapt_meshes(mesh: Mesh, phys: PhysParams, q, kind, thr, stream=None, buffer=0):
     """The two passes of one adaptation cycle from the state q: indicator -> flags
-    -> coarsen pass -> refine pass (parents made by the coarsen pass are not
-    refined in the same cycle).  Returns (mesh_c, mesh_r); a pass that changes no
-    leaf returns its input mesh itself."""
+    (-> buffer zone of `buffer` leaves) -> coarsen pass -> refine pass (parents
+    made by the coarsen pass are not refined in the same cycle).  Returns
+    (mesh_c, mesh_r); a pass that changes no leaf returns its input mesh itself."""
     flags = dg_indicator(mesh, phys, q, kind, thr, stream=stream)
+    if buffer:
+        flags = dg_flags_buffer(mesh, flags, buffer)
     mc = dg_mesh_build(prev=mesh, flags=flags, pass_=DG_PASS_COARSEN)
     if mc.info.n_coarsened:
         t = mc.tables()
@@ -343,13 +365,13 @@ def adapt_meshes(mesh: Mesh, phys: PhysParams, q, kind, thr, stream=None):
     return mc, mr
 
 
-def adapt_cycle(mesh: Mesh, phys: PhysParams, q, kind, thr, stream=None):
+def adapt_cycle(mesh: Mesh, phys: PhysParams, q, kind, thr, stream=None, buffer=0):
     """One adaptation cycle: the passes of :func:`adapt_meshes`, each followed by
     its conservative projection (host control flow; every arithmetic step runs in
     the library).  Returns (new_mesh, new_q); when neither pass changes a leaf,
     the input mesh and field themselves."""
     import torch
-    mc, mr = adapt_meshes(mesh, phys, q, kind, thr, stream)
+    mc, mr = adapt_meshes(mesh, phys, q, kind, thr, stream, buffer)
     qc = q
     if mc is not mesh:
         qc = torch.empty(5, mc.K, mc.Np, dtype=torch.float64, device=q.device)

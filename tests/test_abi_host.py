@@ -131,3 +131,25 @@ def test_passes_that_change_no_leaf():
     om3 = fo.build(od, om, fl, fo.PASS_COARSEN)
     lm3 = dg.dg_mesh_build(prev=lm, flags=fl, pass_=dg.DG_PASS_COARSEN)
     assert tables_equal(lm3.tables(), om3) and lm3.info.n_coarsened > 0
+
+
+@pytest.mark.parametrize("ci,seed", [(c, s) for c in range(len(CASES)) for s in range(2)])
+def test_flags_buffer_matches_oracle(ci, seed):
+    """Buffer zone (B rounds of face-neighbour dilation of the +1 flags): the
+    library's host implementation against the oracle's, bit-exact, on AMR meshes
+    with hanging faces and periodic wraps."""
+    c = CASES[ci]
+    lo, hi = (0.0, 0.0, 0.0), (1000.0, 500.0, 700.0)
+    lm = dg.dg_mesh_build(c["N"], c["nroot"], c["L"], lo, hi, c["periodic"], host_only=True)
+    od = oracle_desc(c["N"], c["nroot"], c["L"], lo, hi, c["periodic"])
+    om = fo.build(od, None)
+    rng = np.random.default_rng(70 + seed)
+    for _ in range(2):
+        fl = (rng.random(om.K) < 0.3).astype(np.int8)
+        lm = dg.dg_mesh_build(prev=lm, flags=fl, pass_=dg.DG_PASS_REFINE)
+        om = fo.build(od, om, fl, fo.PASS_REFINE)
+    fl = rng.choice(np.array([-1, 0, 0, 0, 0, 0, 1], dtype=np.int8), size=om.K)
+    for B in range(4):
+        assert np.array_equal(dg.dg_flags_buffer(lm, fl, B), fo.buffer_flags(om, fl, B)), B
+    with pytest.raises(dg.DGError):
+        dg.dg_flags_buffer(lm, fl, -1)

@@ -234,3 +234,35 @@ def test_node_coordinates_shared_faces_bitwise():
         d, s = f // 2, f % 2
         for ef in row[2:]:
             assert c[d, ec, -1 if s else 0] == c[d, ef, 0 if s else -1]
+
+
+@pytest.mark.parametrize("di,seed", list(itertools.product(range(3), range(4))))
+def test_buffer_flags_is_face_hop_distance(di, seed):
+    """Buffer zone (section 3.2, B): a leaf ends +1 iff it was +1 or lies within B
+    face hops of a +1 leaf, with face contact taken from the integer boxes (not
+    from the oracle's tables); other flags are kept."""
+    desc = DESCS[di]
+    m = _random_balanced_mesh(desc, 500 + seed, rounds=2)
+    rng = np.random.default_rng(900 + seed)
+    fl = rng.choice(np.array([-1, 0, 0, 0, 1], dtype=np.int8), size=m.K)
+    nbrs = [set() for _ in range(m.K)]
+    for a, b, _, _ in _adjacent_pairs(m):
+        nbrs[a].add(b)
+        nbrs[b].add(a)
+    dist = [None] * m.K
+    front = [e for e in range(m.K) if fl[e] > 0]
+    for e in front:
+        dist[e] = 0
+    while front:
+        nxt = []
+        for e in front:
+            for x in nbrs[e]:
+                if dist[x] is None:
+                    dist[x] = dist[e] + 1
+                    nxt.append(x)
+        front = nxt
+    for B in range(4):
+        got = fo.buffer_flags(m, fl, B)
+        want = np.array([1 if dist[e] is not None and dist[e] <= B else int(fl[e]) for e in range(m.K)],
+                        dtype=np.int8)
+        assert np.array_equal(got, want), (B, np.nonzero(got != want))
