@@ -119,6 +119,25 @@ def test_rhs_large_theta_perturbation(N):
     check(out, eu.rk_stage(op, 0.75, 0.25, 0.001, q, q), what=f"stage wide P' N={N}")
 
 
+@pytest.mark.parametrize("case", AMR_CASES, ids=lambda c: f"N{c['N']}")
+def test_rk_stage_random_state_amr(case):
+    """A Shu-Osher stage with q0 distinct from the stage input (the update reads q0),
+    at every order: the low orders gather the tile and traces into LDS, N = 6, 7
+    load straight into registers."""
+    od = oracle_desc(case["N"], case["nroot"], case["L"], *BOX, case["periodic"])
+    seq = random_refinements(od, 2, case["seed"] + 100)
+    lm, om = both_meshes(case["N"], case["nroot"], case["L"], case["periodic"], flag_seq=seq)
+    ph = dg.PhysParams()
+    op = eu.Operator(om, oracle_phys(ph))
+    N = om.N
+    q0 = torch.as_tensor(random_state(om.K, N, case["seed"] + 200))
+    qs = torch.as_tensor(random_state(om.K, N, case["seed"] + 300))
+    out = lm.field()
+    dg.dg_rk_stage(lm, ph, 0.75, 0.25, 0.002, gpu(q0), gpu(qs), out)
+    torch.cuda.synchronize()
+    check(out, eu.rk_stage(op, 0.75, 0.25, 0.002, to_elem(q0, N), to_elem(qs, N)), what=f"stage N={N}")
+
+
 def test_hydrostatic_rest_bitwise_zero_and_conservation():
     od = oracle_desc(4, (2, 2, 2), 2, *BOX, (0, 0, 0))
     seq = random_refinements(od, 2, 11)
