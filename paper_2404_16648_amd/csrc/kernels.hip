@@ -424,36 +424,49 @@ k_stage(const StageArgs A) {
     for (int v = 0; v < 5; ++v) qv[v] = qs + (int64_t)v * KNP;
     const uint32_t eoff = (uint32_t)e * NP * 8u;
 
-    // ---- tables, D and the background profile
-    for (int ii = t; ii < N1 * N1; ii += NT) {
-        const double dv = A.ops[ii];
-        sD[ii] = dv;
-        if (MIX) {
-            const float hi = (float)dv;
-            sD32[ii] = hi;
-            sD32[N1 * N1 + ii] = (float)(dv - (double)hi);
-        }
-    }
-    if (t < 3 * N1) {
-        const double v = A.bg[(int64_t)(t / N1) * K * N1 + e * N1 + (t % N1)];
-        sBg[t] = v;
-        if (t >= N1 && t < 2 * N1) sBg[2 * N1 + t] = 1.0 / v;
-    }
-    if (t < 4) sGeo[t] = A.geo[e * 4 + t];
-    if (t < 6) sType[t] = A.ftype[e * 6 + t];
-    if (t < 24) sNb[t] = A.fnb[e * 24 + t];
-    if (t < 6) sHs[t] = A.hslot[e * 6 + t];
-    __syncthreads();
-
-    // ---- gather (GATHER): all loads of the leaf in one batch, the tile into sW, the
-    // neighbours' face traces and the mortar contributions into sS; otherwise the
-    // face items and the volume load straight into registers
     constexpr bool GATHER = StageOcc<N>::GATHER;
-    if constexpr (GATHER) {
-        // every load is issued before any of them is written to LDS, so all of them are
-        // in flight together: one memory round trip for the leaf
-        static_assert(NP <= NT, "one thread per node");
+    // the leaf's face tables: uniform, read before any store of the kernel (scalar
+    // loads), so the loads that depend on them wait for no LDS round trip
+    int tfs[6], nbs[6], hss[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        tfs[f] = A.ftype[e * 6 + f];
+        nbs[f] = A.fnb[e * 24 + f * 4];
+        hss[f] = A.hslot[e * 6 + f];
+    }
+    if (t < 6) {
+        sType[t] = A.ftype[e * 6 + t];
+        sNb[4 * t] = A.fnb[e * 24 + 4 * t];
+        sHs[t] = A.hslot[e * 6 + t];
+    }
+    if constexpr (!GATHER) {
+        // ---- D and the background profile
+        for (int ii = t; ii < N1 * N1; ii += NT) {
+            const double dv = A.ops[ii];
+            sD[ii] = dv;
+            if (MIX) {
+                const float hi = (float)dv;
+                sD32[ii] = hi;
+                sD32[N1 * N1 + ii] = (float)(dv - (double)hi);
+            }
+        }
+        if (t < 3 * N1) {
+            const double v = A.bg[(int64_t)(t / N1) * K * N1 + e * N1 + (t % N1)];
+            sBg[t] = v;
+            if (t >= N1 && t < 2 * N1) sBg[2 * N1 + t] = 1.0 / v;
+        }
+        if (t < 4) sGeo[t] = A.geo[e * 4 + t];
+        __syncthreads();
+    } else {
+        // ---- gather: every load of the leaf (D, background, geometry, tile, the
+        // neighbours' face traces, the mortar contributions) is issued before any of
+        // them is written to LDS, so all of them are in flight together: one memory
+        // round trip for the leaf, one barrier
+        static_assert(NP <= NT && N1 * N1 <= NT && 3 * N1 <= NT, "one thread per node");
         constexpr int NR = (5 * NF + NT - 1) / NT;  // passes over the face slots
+        const double dv = t < N1 * N1 ? A.ops[t] : 0.0;
+        const double bv = t < 3 * N1 ? A.bg[(int64_t)(t / N1) * K * N1 + e * N1 + (t % N1)] : 0.0;
+        const double gv = t < 4 ? A.geo[e * 4 + t] : 0.0;
         double tv[5] = {0, 0, 0, 0, 0};
         if (t < NP)
 #pragma unroll
@@ -463,12 +476,12 @@ k_stage(const StageArgs A) {
         int ftype[6], fsrc[6];  // per face: type; neighbour leaf or first mortar row
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
-            const int tf = sType[f], type = tf & 0xff;
+            const int tf = tfs[f], type = tf & 0xff;
             ftype[f] = type;
-            fsrc[f] = type == FT_CONF     ? sNb[f * 4]
+            fsrc[f] = type == FT_CONF     ? nbs[f]
                       : type == FT_WALL   ? (int)e
-                      : type == FT_COARSE ? sHs[f] * 5
-                                          : sHs[f] * 5 + 1 + ((tf >> 8) & 0xff);
+                      : type == FT_COARSE ? hss[f] * 5
+                                          : hss[f] * 5 + 1 + ((tf >> 8) & 0xff);
         }
         double fv[NR][6];
 #pragma unroll
@@ -489,14 +502,27 @@ k_stage(const StageArgs A) {
         // far side of the z faces (f = 4, 5): this leaf's bottom / top level, or the
         // neighbour's top / bottom level across a periodic wrap along z
         double zb = 0.0;
-        const int zf = 4 + ((t - 32) >> 2), zc = (t - 32) & 3;
-        const bool zt = t >= 32 && t < 40;
-        const bool znb = zt && (sType[zf] & FT_BG_NB) != 0;
+        const int zc = (t - 32) & 3;
+        const bool zt = t >= 32 && t < 40, zhi = t >= 36;
+        const bool znb = zt && ((zhi ? tfs[5] : tfs[4]) & FT_BG_NB) != 0;
         if (zt) {
-            const int kk = (zf == 4) == znb ? N : 0;
-            zb = znb ? A.bg[(int64_t)(zc == 3 ? 1 : zc) * K * N1 + (int64_t)sNb[zf * 4] * N1 + kk]
-                     : sBg[(zc == 3 ? 1 : zc) * N1 + kk];
+            const int kk = zhi != znb ? N : 0;
+            const int64_t src = znb ? (int64_t)(zhi ? nbs[5] : nbs[4]) : e;
+            zb = A.bg[(int64_t)(zc == 3 ? 1 : zc) * K * N1 + src * N1 + kk];
         }
+        if (t < N1 * N1) {
+            sD[t] = dv;
+            if (MIX) {
+                const float hi = (float)dv;
+                sD32[t] = hi;
+                sD32[N1 * N1 + t] = (float)(dv - (double)hi);
+            }
+        }
+        if (t < 3 * N1) {
+            sBg[t] = bv;
+            if (t >= N1 && t < 2 * N1) sBg[2 * N1 + t] = 1.0 / bv;
+        }
+        if (t < 4) sGeo[t] = gv;
         if (t < NP)
 #pragma unroll
             for (int v = 0; v < 5; ++v) sW[v * NP + t] = tv[v];
@@ -513,13 +539,14 @@ k_stage(const StageArgs A) {
     }
     if (MIX && t < 3) {
         // element-constant reference flux: the flux at the leaf's first node, one
-        // direction per thread
+        // direction per thread (background at the leaf's lowest level, read here)
         double q0n[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) q0n[v] = ld_off(qv[v], eoff);
-        const double rinv0 = rcp_pos(sBg[0] + q0n[0]);
-        const double Pp0 = pprime(q0n[4], sBg[3 * N1], sBg[2 * N1], gamma, A.binom);
-        const double Th0 = sBg[N1] + q0n[4];
+        const double rho0 = A.bg[e * N1], Th0b = A.bg[K * N1 + e * N1], P0b = A.bg[2 * K * N1 + e * N1];
+        const double rinv0 = rcp_pos(rho0 + q0n[0]);
+        const double Pp0 = pprime(q0n[4], 1.0 / Th0b, P0b, gamma, A.binom);
+        const double Th0 = Th0b + q0n[4];
         const double Ud = t == 0 ? q0n[1] : t == 1 ? q0n[2] : q0n[3];
         const double u0 = Ud * rinv0;
         sFr[t * 5 + 0] = Ud;
