@@ -274,12 +274,12 @@ dg_status ensure_bg(dg_mesh* m, const dg_phys* p, hipStream_t s) {
     return DG_OK;
 }
 
-// C(gamma, k), k = 1..10, for the binomial series of (1 + x)^gamma - 1
+// C(gamma, k), k = 1..kBinomTerms, for the binomial series of (1 + x)^gamma - 1
 BinomCoef binom_coef(const dg_phys* p) {
     BinomCoef b{};
     const long double g = (long double)p->cp / (long double)p->cv;
     long double c = 1.0L;
-    for (int k = 1; k <= 10; ++k) {
+    for (int k = 1; k <= kBinomTerms; ++k) {
         c = c * (g - (k - 1)) / k;
         b.c[k - 1] = (double)c;
     }
@@ -299,6 +299,14 @@ StageArgs stage_args(const dg_mesh* m, const dg_phys* p) {
     a.gamma = p->cp / p->cv;
     a.g = p->g;
     a.binom = binom_coef(p);
+    // the update's q0 and its output are touched once per stage: when the three fields
+    // of a stage (q0, stage input, output) exceed the 256 MiB last-level cache they are
+    // streamed past it, leaving the cache to the stage input, whose face traces are
+    // read again by the neighbours (measured: density current, 372 MB, 109 -> 101 us;
+    // AMR bubble, 207 MB, whose fields stay cached, 61 -> 67 us if streamed too)
+    const double n1 = m->h.desc.N + 1;
+    const double field_bytes = 5.0 * (double)a.K * n1 * n1 * n1 * 8.0;
+    a.stream_io = 3.0 * field_bytes > 256.0 * 1024 * 1024 ? 1 : 0;
     return a;
 }
 

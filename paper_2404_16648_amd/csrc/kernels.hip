@@ -66,13 +66,12 @@ __device__ __forceinline__ int face_k(int f, int m) {
 }
 
 // P' = P(Thetabar + Theta') - Pbar = Pbar F(x), F(x) = (1 + x)^gamma - 1, x = Theta'/Thetabar,
-// without cancellation: for |x| <= 2^-7 the binomial series sum_{k=1..10} C(gamma,k) x^k
-// (Horner; truncation below 1e-17 relative).  A larger |x| is first brought into that
+// without cancellation: for |x| <= 2^-7 the binomial series sum_{k=1..7} C(gamma,k) x^k
+// (Horner; truncation below 1e-17 relative for 1 < gamma < 2).  A larger |x| is first brought into that
 // range by halving log(1 + x): 1 + x = (1 + y)^2 with y = x / (1 + sqrt(1 + x)) (no
 // cancellation), repeated until |y| <= 2^-7, and F is rebuilt by F(x) = F(y) (F(y) + 2)
 // once per halving.  Only the series coefficients are needed (no special-function
 // constants, no call), so the rare wide-range path costs the kernels no registers.
-constexpr int kBinomTerms = 10;
 
 // x = Theta' (1/Thetabar): every kernel forms 1/Thetabar by the same IEEE division,
 // so a node's P' has the same bits wherever it is evaluated
@@ -168,6 +167,21 @@ __device__ __forceinline__ void rusanov(const double qL[5], const Bg& bL, double
     const double hl = 0.5 * fmax(lL, lR);
 #pragma unroll
     for (int v = 0; v < 5; ++v) Fs[v] = 0.5 * (FL[v] + FR[v]) + hl * (qL[v] - qR[v]);
+}
+
+// lift (F*.n - F(qL).n) for the Rusanov flux, written as
+// lift (sgn/2 (F^D(qR) - F^D(qL)) + 1/2 max(|u.n| + c) (q'L - q'R)): the lifted
+// surface term of the leaf on the L side, without forming F*.n itself
+template <int D>
+__device__ __forceinline__ void rusanov_lifted(const double qL[5], const Bg& bL, double PpL, const double qR[5],
+                                               const Bg& bR, double PpR, double sgn, double gamma, double lift,
+                                               double out[5]) {
+    double FL[5], FR[5], lL, lR;
+    flux_n<D>(qL, bL, PpL, 1.0, gamma, FL, lL);
+    flux_n<D>(qR, bR, PpR, 1.0, gamma, FR, lR);
+    const double c1 = 0.5 * sgn * lift, c2 = 0.5 * fmax(lL, lR) * lift;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) out[v] = fma(c1, FR[v] - FL[v], c2 * (qL[v] - qR[v]));
 }
 
 // call body.template operator()<D>() with D the run-time axis d
@@ -600,10 +614,10 @@ k_stage(const StageArgs A) {
                                      : bL;
                 const double PpL = pprime(qL[4], bL.rTh, bL.P, gamma, A.binom);
                 const double PpR = pprime(qR[4], bR.rTh, bR.P, gamma, A.binom);
-                double Fs[5], Fo[5];
-                rusanov<d>(qL, bL, PpL, qR, bR, PpR, sgn, gamma, Fs, Fo);
+                double o[5];
+                rusanov_lifted<d>(qL, bL, PpL, qR, bR, PpR, sgn, gamma, lift, o);
 #pragma unroll
-                for (int v = 0; v < 5; ++v) slot[v * NF] = (Fs[v] - Fo[v]) * lift;
+                for (int v = 0; v < 5; ++v) slot[v * NF] = o[v];
                 return;
             } else {
                 // both traces requested before either is used (a wall face loads its
@@ -633,20 +647,27 @@ k_stage(const StageArgs A) {
                 }
                 PpR = pprime(qR[4], bR.rTh, bR.P, gamma, A.binom);
             }
-            double Fs[5], Fo[5];
-            rusanov<d>(qL, bL, PpL, qR, bR, PpR, sgn, gamma, Fs, Fo);
+            double o[5];
+            rusanov_lifted<d>(qL, bL, PpL, qR, bR, PpR, sgn, gamma, lift, o);
 #pragma unroll
-            for (int v = 0; v < 5; ++v) slot[v * NF] = (Fs[v] - Fo[v]) * lift;
+            for (int v = 0; v < 5; ++v) slot[v * NF] = o[v];
         });
     }
 
     // ---- volume term: R = S - sum_d (2/h_d) D_d F^d, fluxes staged in LDS; q from
     // the tile, q0 of the update (stage form, a != 0) loaded now, used at the end
     double q[5] = {0, 0, 0, 0, 0}, q0v[5] = {0, 0, 0, 0, 0};
-    const bool use_q0 = MODE == MODE_RK && A.a != 0.0;
+    const bool use_q0 = MODE != MODE_RHS && A.a != 0.0;
     if (use_q0 && t < NP)
 #pragma unroll
-        for (int v = 0; v < 5; ++v) q0v[v] = ld_off(A.q0 + (int64_t)v * KNP, eoff + (uint32_t)t * 8u);
+        for (int v = 0; v < 5; ++v) {
+            const double* src = reinterpret_cast<const double*>(reinterpret_cast<const char*>(A.q0 + (int64_t)v * KNP) +
+                                                                (eoff + (uint32_t)t * 8u));
+            if constexpr (MODE == MODE_RK_STREAM)
+                q0v[v] = __builtin_nontemporal_load(src);
+            else
+                q0v[v] = *src;
+        }
     double rinv = 0.0, Pp = 0.0, Th = 0.0;
     double R[5] = {0, 0, 0, 0, 0};
     if (t < NP) {
@@ -782,7 +803,10 @@ k_stage(const StageArgs A) {
         for (int v = 0; v < 5; ++v) {
             double o = A.b * fma(A.dt, R[v], q[v]);
             if (use_q0) o = fma(A.a, q0v[v], o);
-            A.out[v * KNP + base] = o;
+            if constexpr (MODE == MODE_RK_STREAM)
+                __builtin_nontemporal_store(o, A.out + v * KNP + base);
+            else
+                A.out[v * KNP + base] = o;
         }
     }
 }
@@ -1607,15 +1631,20 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_indicator(const IndArgs A) {
 hipError_t launch_stage(int N, int mode, bool mixed, const StageArgs& a, hipStream_t s) {
     if (a.K <= 0) return hipSuccess;
     const dim3 grid((unsigned)a.K);
+    const bool stream = mode == MODE_RK && a.stream_io;
     if (mixed) {
         if (mode == MODE_RHS) {
             DG_DISPATCH_N(N, (k_stage<NN, MODE_RHS, true><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        } else if (stream) {
+            DG_DISPATCH_N(N, (k_stage<NN, MODE_RK_STREAM, true><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
         } else {
             DG_DISPATCH_N(N, (k_stage<NN, MODE_RK, true><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
         }
     } else {
         if (mode == MODE_RHS) {
             DG_DISPATCH_N(N, (k_stage<NN, MODE_RHS, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        } else if (stream) {
+            DG_DISPATCH_N(N, (k_stage<NN, MODE_RK_STREAM, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
         } else {
             DG_DISPATCH_N(N, (k_stage<NN, MODE_RK, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
         }

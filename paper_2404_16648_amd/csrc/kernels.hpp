@@ -10,13 +10,17 @@
 
 namespace dgamr {
 
-// C(gamma, k), k = 1..10: binomial series of (1 + x)^gamma - 1 used for P'
+// C(gamma, k), k = 1..kBinomTerms: binomial series of (1 + x)^gamma - 1 used for P'
+// (seven terms: for |x| <= 2^-7 and 1 < gamma < 2 the truncation is below 1e-17
+// relative)
+constexpr int kBinomTerms = 7;
 struct BinomCoef {
-    double c[10];
+    double c[kBinomTerms];
 };
 
 constexpr int MODE_RHS = 0;
 constexpr int MODE_RK = 1;
+constexpr int MODE_RK_STREAM = 2;  // MODE_RK with q0 and the output streamed (non-temporal)
 
 struct StageArgs {
     const double* q0;      // [5][K][Np] (read only when a != 0)
@@ -33,6 +37,7 @@ struct StageArgs {
     double a, b, dt;
     double gamma, g;
     BinomCoef binom;
+    int32_t stream_io;     // stage form: launch MODE_RK_STREAM
 };
 
 // adjoint: out = q^T-derivative qbar = (dR/dq)^T(q) lam (MODE_RHS) or
