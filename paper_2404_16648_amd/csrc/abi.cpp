@@ -60,7 +60,7 @@ void free_device(dg_mesh* m) {
 // byte offsets of the arrays in a mesh's one device block, 256-byte aligned;
 // [0, upload) is copied from the host, the rest is device workspace
 struct DevLayout {
-    size_t ops, geo, c1d, ft, nb, hs, hg, lv, xs, xk, upload, bg, red, eta, fl, mort, total;
+    size_t ops, geo, c1d, ft, nb, hs, hg, lv, xs, xk, sr, upload, bg, red, eta, fl, mort, total;
 };
 
 DevLayout dev_layout(int64_t K, int N, int64_t red_len, int64_t n_hang) {
@@ -82,6 +82,7 @@ DevLayout dev_layout(int64_t K, int N, int64_t red_len, int64_t n_hang) {
     L.lv = take(sizeof(int32_t) * k);
     L.xs = take(sizeof(int32_t) * k);
     L.xk = take(sizeof(int32_t) * k);
+    L.sr = take(sizeof(int32_t) * kStageRec * k);
     L.upload = end;
     L.bg = take(sizeof(double) * 3 * k * N1);
     L.red = take(sizeof(double) * (size_t)red_len);
@@ -105,6 +106,7 @@ void set_device_pointers(dg_mesh* m, char* base, const DevLayout& L) {
     m->d_level = (int32_t*)(base + L.lv);
     m->d_xsrc = (int32_t*)(base + L.xs);
     m->d_xkind = (int32_t*)(base + L.xk);
+    m->d_srec = (int32_t*)(base + L.sr);
     m->d_bg = (double*)(base + L.bg);
     m->d_red = (double*)(base + L.red);
     m->d_eta = (double*)(base + L.eta);
@@ -216,6 +218,18 @@ dg_status build_device(dg_mesh* m) {
     if (m->n_hang) std::memcpy(up.data() + L.hg, h.hang.data(), sizeof(int32_t) * 6 * m->n_hang);
     std::memcpy(up.data() + L.xs, h.xfer_src.data(), sizeof(int32_t) * K);
     std::memcpy(up.data() + L.xk, h.xfer_kind.data(), sizeof(int32_t) * K);
+    // the stage kernel's face tables, one contiguous record per leaf (read with scalar
+    // loads): per face type, first neighbour, hanging-face row or -1
+    int32_t* sr = (int32_t*)(up.data() + L.sr);
+    for (int64_t e = 0; e < K; ++e) {
+        int32_t* rec = sr + e * kStageRec;
+        for (int f = 0; f < 6; ++f) {
+            rec[f] = h.ftype[e * 6 + f];
+            rec[6 + f] = h.fnb[e * 24 + f * 4];
+            rec[12 + f] = hs[e * 6 + f];
+        }
+        rec[18] = rec[19] = 0;
+    }
     char* base = nullptr;
     HIP_TRY(hipMalloc((void**)&base, L.total));
     set_device_pointers(m, base, L);
@@ -295,6 +309,7 @@ StageArgs stage_args(const dg_mesh* m, const dg_phys* p) {
     a.fnb = m->d_fnb;
     a.hslot = m->d_hslot;
     a.mort = m->d_mort;
+    a.srec = m->d_srec;
     a.K = (int64_t)m->h.leaves.size();
     a.gamma = p->cp / p->cv;
     a.g = p->g;

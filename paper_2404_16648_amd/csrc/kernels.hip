@@ -425,6 +425,7 @@ k_stage(const StageArgs A) {
 
     const int64_t K = A.K;
     const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
+    const int32_t* const rec = A.srec + e * kStageRec;
     const int t = threadIdx.x;
     const double gamma = A.gamma;
     const double* const D = sD;
@@ -439,19 +440,19 @@ k_stage(const StageArgs A) {
     const uint32_t eoff = (uint32_t)e * NP * 8u;
 
     constexpr bool GATHER = StageOcc<N>::GATHER;
-    // the leaf's face tables: uniform, read before any store of the kernel (scalar
-    // loads), so the loads that depend on them wait for no LDS round trip
+    // the leaf's face tables: one uniform record, read before any store of the kernel
+    // (scalar loads), so the loads that depend on them wait for no LDS round trip
     int tfs[6], nbs[6], hss[6];
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
-        tfs[f] = A.ftype[e * 6 + f];
-        nbs[f] = A.fnb[e * 24 + f * 4];
-        hss[f] = A.hslot[e * 6 + f];
+        tfs[f] = rec[f];
+        nbs[f] = rec[6 + f];
+        hss[f] = rec[12 + f];
     }
     if (t < 6) {
-        sType[t] = A.ftype[e * 6 + t];
-        sNb[4 * t] = A.fnb[e * 24 + 4 * t];
-        sHs[t] = A.hslot[e * 6 + t];
+        sType[t] = rec[t];
+        sNb[4 * t] = rec[6 + t];
+        sHs[t] = rec[12 + t];
     }
     if constexpr (!GATHER) {
         // ---- D and the background profile

@@ -22,6 +22,10 @@ constexpr int MODE_RHS = 0;
 constexpr int MODE_RK = 1;
 constexpr int MODE_RK_STREAM = 2;  // MODE_RK with q0 and the output streamed (non-temporal)
 
+// per-leaf record of the stage kernel's face tables: per face f its type (f), first
+// neighbour (6 + f) and hanging-face row or -1 (12 + f); two ints of padding
+constexpr int kStageRec = 20;
+
 struct StageArgs {
     const double* q0;      // [5][K][Np] (read only when a != 0)
     const double* qs;      // [5][K][Np]
@@ -33,6 +37,7 @@ struct StageArgs {
     const int32_t* fnb;    // [K][6][4]
     const int32_t* hslot;  // [K][6]: row of the hanging-face table, or -1
     const double* mort;    // [n_hang][5][5][NF]: lifted mortar contributions (k_mortar)
+    const int32_t* srec;   // [K][kStageRec]: face tables, one record per leaf
     int64_t K;
     double a, b, dt;
     double gamma, g;
