@@ -315,17 +315,20 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_mortar(const MortArgs A) {
         const int v = it / NF, m = it % NF;
         sT[it] = qs[v * KNP + ec * NP + face_node<N>(f, m)];
     }
-    // this thread's fine-side point, loaded with the trace: quadrant t / NF
+    // this thread's fine-side point and the lift factors, loaded with the trace (every
+    // global read of the workgroup is in this one batch): quadrant t / NF
     double qF[5];
     Bg bF{};
-    int64_t ef = 0;
+    double lift_f = 0.0;
+    const double lift_c = A.geo[ec * 4 + (f >> 1)] * liftc;
     if (t < 4 * NF) {
         const int quad = t / NF, m = t % NF;
-        ef = row[2 + quad];
+        const int64_t ef = row[2 + quad];
         const int nn = face_node<N>(fo, m), kn = face_k<N>(fo, m);
         bF = bg_make(A.bg[ef * N1 + kn], A.bg[KN1 + ef * N1 + kn], A.bg[2 * KN1 + ef * N1 + kn]);
 #pragma unroll
         for (int v = 0; v < 5; ++v) qF[v] = qs[v * KNP + ef * NP + nn];
+        lift_f = A.geo[ef * 4 + (f >> 1)] * liftc;
     }
     __syncthreads();
     // sU[a][v] = I_a along t1; sMq[quad][v] = I_b along t2 of sU[a]  (quad = a + 2b)
@@ -345,7 +348,6 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_mortar(const MortArgs A) {
         with_axis(f >> 1, [&](auto dc) {
             rusanov<decltype(dc)::value>(qF, bF, PpF, qM, bF, PpM, -sgn, gamma, Fs, Fo);
         });
-        const double lift_f = A.geo[ef * 4 + (f >> 1)] * liftc;
         double* const out = A.mort + ((h * 5 + 1 + quad) * 5) * NF + m;
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
@@ -384,14 +386,13 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_mortar(const MortArgs A) {
     __syncthreads();
     if (t < NF) {
         const int m = t;
-        const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
+        const int kk = face_k<N>(f, m);
         const Bg b = bg_make(sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]);
         double qL[5], Fo[5], lam;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qL[v] = qs[v * KNP + ec * NP + n];
+        for (int v = 0; v < 5; ++v) qL[v] = sT[v * NF + m];  // the coarse trace at face node m
         const double PpL = pprime(qL[4], b.rTh, b.P, gamma, A.binom);
         with_axis(f >> 1, [&](auto dc) { flux_n<decltype(dc)::value>(qL, b, PpL, sgn, gamma, Fo, lam); });
-        const double lift_c = A.geo[ec * 4 + (f >> 1)] * liftc;
         double* const out = A.mort + (h * 5 * 5) * NF + m;
 #pragma unroll
         for (int v = 0; v < 5; ++v) out[v * NF] = (sU[v * NF + m] - Fo[v]) * lift_c;
@@ -943,13 +944,15 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_mortar_adjoint(const MortAdjArgs 
         sT[it] = A.q[off];
         sT[5 * NF + it] = A.lam[off];
     }
-    // this thread's fine-side point, loaded with the coarse trace: quadrant t / NF
+    // this thread's fine-side point and the lift factors, loaded with the coarse trace
+    // (every global read of the workgroup is in this one batch): quadrant t / NF
     double qF[5] = {0, 0, 0, 0, 0}, lF[5] = {0, 0, 0, 0, 0};
     Bg bF{1.0, 1.0, 1.0, 1.0};
-    int64_t ef = 0;
+    double lift_f = 0.0;
+    const double lift_c = A.geo[ec * 4 + (f >> 1)] * liftc;
     if (t < 4 * NF) {
         const int quad = t / NF, m = t % NF;
-        ef = row[2 + quad];
+        const int64_t ef = row[2 + quad];
         const int nn = face_node<N>(fo, m), kn = face_k<N>(fo, m);
         bF = bg_make(A.bg[ef * N1 + kn], A.bg[KN1 + ef * N1 + kn], A.bg[2 * KN1 + ef * N1 + kn]);
 #pragma unroll
@@ -957,6 +960,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_mortar_adjoint(const MortAdjArgs 
             qF[v] = A.q[v * KNP + ef * NP + nn];
             lF[v] = A.lam[v * KNP + ef * NP + nn];
         }
+        lift_f = A.geo[ef * 4 + (f >> 1)] * liftc;
     }
     __syncthreads();
     // sU plane a*10 + c: along t1 with I_a (c < 5, state) or R_a^T (c >= 5, lambda)
@@ -969,8 +973,6 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_mortar_adjoint(const MortAdjArgs 
     __syncthreads();
     if (t < 4 * NF) {
         const int quad = t / NF, m = t % NF;
-        const double lift_f = A.geo[ef * 4 + (f >> 1)] * liftc;
-        const double lift_c = A.geo[ec * 4 + (f >> 1)] * liftc;
         double qM[5], w[5], gF[5], gM[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
@@ -1023,7 +1025,6 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_mortar_adjoint(const MortAdjArgs 
     if (t < NF) {
         const int m = t, kk = face_k<N>(f, m);
         const Bg b{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk], sBg[3 * N1 + kk]};
-        const double lift_c = A.geo[ec * 4 + (f >> 1)] * liftc;
         double qL[5], lL[5], g[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
