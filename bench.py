@@ -38,11 +38,12 @@ STAGE_KERNEL = "k_mortar<7> + k_stage<7, 1, false>"
 # kernels.hip up to the adjoint section, the stage and mortar launchers,
 # kernels.hpp and facetypes.hpp); otherwise traffic is reported as null.
 TRAFFIC = {
-    "sources_sha256": "01b8915e02ae56b8c6c77513d2866bcad630509ecc72dda46c201227d4fe55df",
-    "fetch_kib_per_launch": 78362.2,    # mean over the 90 stages of the stage-timing pass, both kernels
-    "write_kib_per_launch": 73210.0,
+    "sources_sha256": "5c99894be873f0eb8a30c0081dd71f5522c9474c5e969a2c9679a8ada9c45724",
     "fetch_scale": 1048576.0 / 524302.0,  # 1 GiB copy: FETCH_SIZE reads 524302.0 KiB
     "write_scale": 1048576.0 / 1048576.0,  # 1 GiB copy: WRITE_SIZE reads 1048576.0 KiB
+    # KiB per stage (mortar pre-pass + stage kernel), mean over the timed stages
+    "amr_bubble": {"fetch_kib": 77936.4, "write_kib": 73210.0},  # the 90 stages of the stage-timing pass
+    "density_current": {"fetch_kib": 168236.8, "write_kib": 131796.3},  # the 100 timed float64 stages
 }
 CSRC = os.path.join(ROOT, "paper_2404_16648_amd", "csrc")
 
@@ -71,11 +72,12 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def traffic_bytes_per_launch():
+def traffic_bytes_per_launch(workload="amr_bubble"):
     t = TRAFFIC
-    if t["sources_sha256"] is None or t["sources_sha256"] != kernel_sources_sha256():
+    w = t[workload]
+    if t["sources_sha256"] is None or t["sources_sha256"] != kernel_sources_sha256() or w["fetch_kib"] is None:
         return None
-    return 1024.0 * (t["fetch_kib_per_launch"] * t["fetch_scale"] + t["write_kib_per_launch"] * t["write_scale"])
+    return 1024.0 * (w["fetch_kib"] * t["fetch_scale"] + w["write_kib"] * t["write_scale"])
 
 
 def parse():
@@ -371,6 +373,11 @@ def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us):
         out["density_current_" + key] = {
             "leaves": m3.K, "nodes": nodes3, "hanging_faces": int(m3.info.n_hang), "stage_us": us,
             "dof_updates_per_s": 5 * nodes3 / (us * 1e-6), "achieved_GBs": ach, "frac_hbm": ach / HBM_PEAK_GBS}
+        if key == "fp64":
+            tr = traffic_bytes_per_launch("density_current")
+            out["density_current_fp64"]["traffic_B_per_stage"] = tr
+            out["density_current_fp64"]["traffic_over_algorithmic"] = (
+                None if tr is None else tr / (nodes3 * BYTES_STAGE))
     # ---- uniform bubble, 4^3 hexes, N = 4, dt = 0.05 s: launch-bound, reported only
     m1 = dg.dg_mesh_build(4, (4, 4, 4), 0, (0.0, 0.0, 0.0), (1000.0, 1000.0, 1000.0))
     q1c = m1.field()
