@@ -6,7 +6,10 @@ cosine-bell bubble +2 K radius 250 m at (500, 500, 350) m, no-flux walls,
 SSP-RK3 with dt = 0.001 s and re-adaptation every 10 steps by conservative
 projection.  One benchmark step = one SSP-RK3 step (3 fused stage launches);
 every 10th step also runs an adaptation cycle (indicator, coarsen pass and
-projection, refine pass and projection), inside the timed region.
+projection, refine pass and projection), inside the timed region; the host part
+of a cycle (flag download, forest passes) overlaps a step computed at once on
+the current mesh, kept when the cycle changes no leaf and made again on the
+adapted mesh otherwise (the same result either way).
 
 Prints one JSON line: DOF-updates/s (5 variables x nodes x 3 RHS evaluations
 per step) over the timed steps, the roofline of the dominant kernel (the fused
@@ -114,30 +117,18 @@ def main():
     mesh, q = dg.initial_mesh(N, nroot, L, lo, hi, (0, 0, 0), ph, bell, dg.DG_IND_THETA, thr)
     stream = torch.cuda.current_stream()
 
-    state = {"mesh": mesh, "q": q, "step": 0, "dofs": 0, "stage_ms": 0.0, "stage_bytes": 0.0,
-             "stage_launches": 0}
+    # SSP-RK3 with an adaptation cycle every adapt_every steps; the host part of each
+    # cycle (flag download, forest passes) overlaps a speculative step on the GPU
+    stepper = dg.AdaptiveStepper(mesh, ph, q, dt, args.adapt_every, dg.DG_IND_THETA, thr)
+    state = {"dofs": 0}
 
     def one_step(record):
-        m, qq = state["mesh"], state["q"]
-        if state["step"] > 0 and state["step"] % args.adapt_every == 0:
-            m2, q2 = dg.adapt_cycle(m, ph, qq, dg.DG_IND_THETA, thr)
-            m2.prev = None
-            state["mesh"], state["q"] = m2, q2
-            m, qq = m2, q2
-        q1 = torch.empty_like(qq)
-        q2_ = torch.empty_like(qq)
-        nodes = m.K * m.Np
-        stages = ((0.0, 1.0, qq, q1), (0.75, 0.25, q1, q2_), (1.0 / 3.0, 2.0 / 3.0, q2_, qq))
+        ev = [] if record is not None else None
+        stepper.step(ev)
+        nodes = stepper.mesh.K * stepper.mesh.Np
         if record is not None:  # one event pair around the three stage launches of the step
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-        for a, b, qs, out in stages:
-            dg.dg_rk_stage(m, ph, a, b, dt, qq, qs, out)
-        if record is not None:
-            e1.record(stream)
+            e0, e1 = ev[0]
             record.append((e0, e1, nodes * (BYTES_STAGE_FIRST + 2 * BYTES_STAGE), 3))
-        state["step"] += 1
         state["dofs"] += 3 * 5 * nodes
 
     for _ in range(args.warmup):
@@ -170,8 +161,8 @@ def main():
     n_launches = sum(n for _, _, _, n in events)
     achieved = stage_bytes / (stage_ms * 1e-3) / 1e9
     dofs_per_s = dofs_timed / (total_ms * 1e-3)
-    m = state["mesh"]
-    budgets = dg.dg_budgets(m, ph, state["q"])
+    m = stepper.mesh
+    budgets = dg.dg_budgets(m, ph, stepper.q)
     calib = None
     if args.copy_calibration > 0:
         nb = args.copy_calibration << 20
@@ -211,11 +202,12 @@ def main():
                      "avg_launch_us": 1e3 * stage_ms / max(1, n_launches)},
         "wall_s": wall,
         "mass_prime_final": budgets[0],
+        "adaptation_cycles": {"run": stepper.cycles, "changed_mesh": stepper.changed},
     }
     if calib is not None:
         result["copy_calibration"] = calib
     if not args.no_extras:
-        result["extras"] = extras(dg, torch, state["mesh"], state["q"], ph, dt, 1e3 * stage_ms / n_launches)
+        result["extras"] = extras(dg, torch, stepper.mesh, stepper.q, ph, dt, 1e3 * stage_ms / n_launches)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)

@@ -146,6 +146,15 @@ typedef struct {
  * projections.  Host work only (the device copy is made at first GPU use). */
 dg_status dg_mesh_build(const dg_forest_desc* desc, const dg_mesh* prev, const int8_t* flags,
                         int32_t pass, dg_mesh** out);
+/* Whether dg_mesh_build(prev = mesh, flags, pass) would change a leaf of mesh
+ * (section 3.1: a refine pass splits leaves flagged +1 below max_level; a
+ * coarsen pass merges complete sibling families flagged -1 that pass the 2:1
+ * veto): *changes = 1 if so, else 0.  Host work only, nothing allocated for a
+ * result, so a caller can skip building a mesh equal to its input.  flags is
+ * host int8[K] as for dg_mesh_build.  DG_EINVAL on a NULL argument or an
+ * unknown pass. */
+dg_status dg_pass_changes(const dg_mesh* mesh, const int8_t* flags, int32_t pass, int32_t* changes);
+
 dg_status dg_mesh_free(dg_mesh* mesh);
 dg_status dg_mesh_info_get(const dg_mesh* mesh, dg_mesh_info* info);
 dg_status dg_mesh_export(const dg_mesh* mesh, const dg_mesh_tables* tables);
@@ -241,6 +250,15 @@ dg_status dg_budgets(const dg_mesh* mesh, const dg_phys* phys, const double* q, 
  * Synchronises the stream. */
 dg_status dg_indicator(const dg_mesh* mesh, const dg_phys* phys, const double* q, int32_t kind,
                        double thr, double* eta, int8_t* flags_host, void* stream);
+
+/* The same indicator, only enqueued: the flags go to flags_dev (DEVICE int8[K],
+ * caller-owned, not aliasing q or eta) and nothing synchronises, for a caller
+ * that overlaps the regrid decision (section 3.2: the host-side forest passes)
+ * with further GPU work on the stream (copy flags_dev to pinned host memory
+ * asynchronously and wait on an event before the passes).  Same errors as
+ * dg_indicator; a fault in the kernel surfaces at the next synchronising call. */
+dg_status dg_indicator_async(const dg_mesh* mesh, const dg_phys* phys, const double* q, int32_t kind,
+                             double thr, double* eta, int8_t* flags_dev, void* stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 /* Buffer zone around refinement (section 3.2: at least B coarse cells between a

@@ -391,6 +391,18 @@ dg_status dg_mesh_build(const dg_forest_desc* desc, const dg_mesh* prev, const i
     return DG_OK;
 }
 
+dg_status dg_pass_changes(const dg_mesh* m, const int8_t* flags, int32_t pass, int32_t* changes) {
+    if (!m || !changes) return fail(DG_EINVAL, "NULL argument");
+    if (!flags && !m->h.leaves.empty()) return fail(DG_EINVAL, "flags is NULL");
+    if (pass != DG_PASS_REFINE && pass != DG_PASS_COARSEN) return fail(DG_EINVAL, "unknown pass");
+    try {
+        *changes = pass_changes(m->h, flags, pass == DG_PASS_REFINE) ? 1 : 0;
+    } catch (const std::bad_alloc&) {
+        return fail(DG_ENOMEM, "host allocation failed");
+    }
+    return DG_OK;
+}
+
 dg_status dg_mesh_free(dg_mesh* m) {
     if (!m) return DG_OK;
     free_device(m);
@@ -651,6 +663,23 @@ dg_status dg_indicator(const dg_mesh* mc, const dg_phys* phys, const double* q, 
     HIP_TRY(launch_indicator(m->h.desc.N, a, s));
     if (K > 0) HIP_TRY(hipMemcpyAsync(flags_host, m->d_flags, K, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    return DG_OK;
+}
+
+dg_status dg_indicator_async(const dg_mesh* mc, const dg_phys* phys, const double* q, int32_t kind, double thr,
+                             double* eta, int8_t* flags_dev, void* stream) {
+    dg_status st = check_dev_mesh(mc);
+    if (st) return st;
+    if ((st = check_phys(phys))) return st;
+    if (!q || !flags_dev) return fail(DG_EINVAL, "NULL argument");
+    if (kind != DG_IND_THETA && kind != DG_IND_GRAD_THETA) return fail(DG_EINVAL, "unknown indicator kind");
+    dg_mesh* m = const_cast<dg_mesh*>(mc);
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = ensure_bg(m, phys, s))) return st;
+    const int64_t K = (int64_t)m->h.leaves.size();
+    IndArgs a{q, m->d_bg, m->d_geo, m->d_ops, m->d_level, eta ? eta : m->d_eta, flags_dev, K, kind,
+              m->h.desc.max_level, thr};
+    HIP_TRY(launch_indicator(m->h.desc.N, a, s));
     return DG_OK;
 }
 

@@ -272,13 +272,15 @@ std::string forest_refine(const HostMesh& prev, const int8_t* flags, HostMesh& o
     return "";
 }
 
-std::string forest_coarsen(const HostMesh& prev, const int8_t* flags, HostMesh& out) {
+// the families the coarsen pass merges: merge[e] = 1 at the first child of each;
+// returns their number
+static int64_t coarsen_families(const HostMesh& prev, const int8_t* flags, std::vector<char>& merge) {
     const dg_forest_desc& desc = prev.desc;
     Sorted P(desc, prev.leaves);
     const size_t K0 = P.leaves.size();
     // candidate families: 8 consecutive leaves (Morton order keeps a family
     // contiguous) that are the 8 children of one parent, all flagged -1
-    std::vector<char> merge(K0, 0);  // 1 at the first child of a family that merges
+    merge.assign(K0, 0);
     int64_t nmerged = 0;
     for (size_t e = 0; e + 8 <= K0;) {
         const Leaf& lf = P.leaves[e];
@@ -310,10 +312,31 @@ std::string forest_coarsen(const HostMesh& prev, const int8_t* flags, HostMesh& 
         }
         e += 8;
     }
+    return nmerged;
+}
+
+bool pass_changes(const HostMesh& prev, const int8_t* flags, bool refine) {
+    if (refine) {
+        const int L = prev.desc.max_level;
+        for (size_t e = 0; e < prev.leaves.size(); ++e)
+            if (flags[e] > 0 && prev.leaves[e].l < L) return true;
+        return false;
+    }
+    std::vector<char> merge;
+    return coarsen_families(prev, flags, merge) > 0;
+}
+
+std::string forest_coarsen(const HostMesh& prev, const int8_t* flags, HostMesh& out) {
+    const dg_forest_desc& desc = prev.desc;
+    std::vector<char> merge;  // 1 at the first child of a family that merges
+    const int64_t nmerged = coarsen_families(prev, flags, merge);
     if (nmerged == 0) {
         unchanged(prev, out);
         return "";
     }
+    // prev's leaves are in canonical (sorted) order, the order the families were found in
+    const std::vector<Leaf>& src = prev.leaves;
+    const size_t K0 = src.size();
     out = HostMesh();
     out.desc = desc;
     out.leaves.reserve(K0);
@@ -321,12 +344,12 @@ std::string forest_coarsen(const HostMesh& prev, const int8_t* flags, HostMesh& 
     out.xfer_kind.reserve(K0);
     for (size_t e = 0; e < K0;) {
         if (merge[e]) {
-            out.leaves.push_back(parent_of(P.leaves[e]));
+            out.leaves.push_back(parent_of(src[e]));
             out.xfer_src.push_back((int32_t)e);
             out.xfer_kind.push_back(DG_KIND_FAMILY);
             e += 8;
         } else {
-            out.leaves.push_back(P.leaves[e]);
+            out.leaves.push_back(src[e]);
             out.xfer_src.push_back((int32_t)e);
             out.xfer_kind.push_back(DG_KIND_COPY);
             ++e;

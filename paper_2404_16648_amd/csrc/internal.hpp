@@ -41,6 +41,8 @@ std::string forest_uniform(const dg_forest_desc& desc, HostMesh& out);
 std::string forest_refine(const HostMesh& prev, const int8_t* flags, HostMesh& out);
 std::string forest_coarsen(const HostMesh& prev, const int8_t* flags, HostMesh& out);
 void forest_tables(HostMesh& m);
+// whether forest_refine (refine) or forest_coarsen (!refine) would change a leaf
+bool pass_changes(const HostMesh& prev, const int8_t* flags, bool refine);
 
 // geometry of leaf e: h[3] and 1-D node coordinates c[3][N+1]
 void leaf_geometry(const dg_forest_desc& desc, const Leaf& lf, const std::vector<double>& xi,

@@ -37,7 +37,7 @@ DG_KIND_FAMILY = 8
 EXPORTED = [
     "dg_mesh_build", "dg_mesh_free", "dg_mesh_info_get", "dg_mesh_export", "dg_node_coords",
     "dg_init_bell", "dg_rhs", "dg_rk_stage", "dg_refine_project", "dg_coarsen_project",
-    "dg_refine_project_adjoint", "dg_coarsen_project_adjoint", "dg_rhs_adjoint", "dg_rk_stage_adjoint", "dg_budgets", "dg_indicator", "dg_flags_buffer", "dg_fma_burst", "dg_last_error",
+    "dg_refine_project_adjoint", "dg_coarsen_project_adjoint", "dg_rhs_adjoint", "dg_rk_stage_adjoint", "dg_budgets", "dg_indicator", "dg_indicator_async", "dg_pass_changes", "dg_flags_buffer", "dg_fma_burst", "dg_last_error",
 ]
 
 
@@ -104,6 +104,8 @@ def lib():
         L.dg_fma_burst.argtypes = [C.c_int32, C.c_int32, P, P, P]
         L.dg_flags_buffer.argtypes = [P, P, C.c_int32]
         L.dg_indicator.argtypes = [P, C.POINTER(Phys), P, C.c_int32, C.c_double, P, P, P]
+        L.dg_indicator_async.argtypes = [P, C.POINTER(Phys), P, C.c_int32, C.c_double, P, P, P]
+        L.dg_pass_changes.argtypes = [P, P, C.c_int32, C.POINTER(C.c_int32)]
         L.dg_last_error.restype = C.c_char_p
         for name in EXPORTED:
             if name != "dg_last_error":
@@ -225,6 +227,16 @@ def dg_mesh_build(N=None, nroot=None, max_level=0, lo=(0.0, 0.0, 0.0), hi=(1.0, 
     return Mesh(out.value, prev)
 
 
+def dg_pass_changes(mesh: Mesh, flags, pass_) -> bool:
+    """Whether dg_mesh_build(prev=mesh, flags=flags, pass_=pass_) would change a leaf."""
+    fl = np.ascontiguousarray(np.asarray(flags, dtype=np.int8))
+    if fl.shape != (mesh.K,):
+        raise ValueError("flags must have one entry per leaf")
+    ch = C.c_int32(0)
+    _check(lib().dg_pass_changes(mesh.handle, C.c_void_p(fl.ctypes.data), pass_, C.byref(ch)))
+    return bool(ch.value)
+
+
 def _shape_check(mesh, *ts):
     for t in ts:
         if t is not None and tuple(t.shape) != (5, mesh.K, mesh.Np):
@@ -333,6 +345,18 @@ def dg_indicator(mesh: Mesh, phys: PhysParams, q, kind, thr, eta=None, stream=No
     return fl
 
 
+def dg_indicator_async(mesh: Mesh, phys: PhysParams, q, kind, thr, flags_dev, eta=None, stream=None):
+    """Enqueue the indicator; flags_dev is a device int8 tensor of K entries."""
+    import torch
+    _shape_check(mesh, q)
+    if (not isinstance(flags_dev, torch.Tensor) or not flags_dev.is_cuda or flags_dev.dtype != torch.int8
+            or flags_dev.numel() < mesh.K or not flags_dev.is_contiguous()):
+        raise ValueError("flags_dev must be a contiguous int8 GPU tensor of at least K entries")
+    p = phys.c()
+    _check(lib().dg_indicator_async(mesh.handle, C.byref(p), _ptr(q), kind, thr, _ptr(eta),
+                                    C.c_void_p(flags_dev.data_ptr()), _stream(stream)))
+
+
 SSP_RK3 = ((0.0, 1.0), (0.75, 0.25), (1.0 / 3.0, 2.0 / 3.0))
 
 
@@ -348,20 +372,26 @@ def adapt_meshes(mesh: Mesh, phys: PhysParams, q, kind, thr, stream=None, buffer
     (-> buffer zone of `buffer` leaves) -> coarsen pass -> refine pass (parents
     made by the coarsen pass are not refined in the same cycle).  Returns
     (mesh_c, mesh_r); a pass that changes no leaf returns its input mesh itself."""
-    flags = dg_indicator(mesh, phys, q, kind, thr, stream=stream)
+    return adapt_meshes_from_flags(mesh, dg_indicator(mesh, phys, q, kind, thr, stream=stream), buffer)
+
+
+def adapt_meshes_from_flags(mesh: Mesh, flags, buffer=0):
+    """The two forest passes of one adaptation cycle from the indicator's flags
+    (host work only); see :func:`adapt_meshes`."""
     if buffer:
         flags = dg_flags_buffer(mesh, flags, buffer)
-    mc = dg_mesh_build(prev=mesh, flags=flags, pass_=DG_PASS_COARSEN)
-    if mc.info.n_coarsened:
+    # a pass that would change no leaf is not built (its result would equal its input)
+    mc = mesh
+    if dg_pass_changes(mesh, flags, DG_PASS_COARSEN):
+        mc = dg_mesh_build(prev=mesh, flags=flags, pass_=DG_PASS_COARSEN)
         t = mc.tables()
         fl2 = np.where(t["xfer_kind"] == DG_KIND_COPY, flags[t["xfer_src"]], 0).astype(np.int8)
     else:
-        mc = mesh  # identity transfer plan: the flags index the same leaves
-        fl2 = flags.copy()
+        fl2 = np.array(flags, dtype=np.int8)  # identity transfer plan: the flags index the same leaves
     fl2[fl2 < 0] = 0
-    mr = dg_mesh_build(prev=mc, flags=fl2, pass_=DG_PASS_REFINE)
-    if not mr.info.n_refined:
-        mr = mc
+    mr = mc
+    if dg_pass_changes(mc, fl2, DG_PASS_REFINE):
+        mr = dg_mesh_build(prev=mc, flags=fl2, pass_=DG_PASS_REFINE)
     return mc, mr
 
 
@@ -370,8 +400,13 @@ def adapt_cycle(mesh: Mesh, phys: PhysParams, q, kind, thr, stream=None, buffer=
     its conservative projection (host control flow; every arithmetic step runs in
     the library).  Returns (new_mesh, new_q); when neither pass changes a leaf,
     the input mesh and field themselves."""
+    return project_cycle(mesh, *adapt_meshes(mesh, phys, q, kind, thr, stream, buffer), q, stream)
+
+
+def project_cycle(mesh: Mesh, mc: Mesh, mr: Mesh, q, stream=None):
+    """The projections of one adaptation cycle (mesh -> mc coarsening, mc -> mr
+    refinement; a pass that changed nothing is skipped).  Returns (mr, q on mr)."""
     import torch
-    mc, mr = adapt_meshes(mesh, phys, q, kind, thr, stream, buffer)
     qc = q
     if mc is not mesh:
         qc = torch.empty(5, mc.K, mc.Np, dtype=torch.float64, device=q.device)
@@ -381,6 +416,90 @@ def adapt_cycle(mesh: Mesh, phys: PhysParams, q, kind, thr, stream=None, buffer=
         qr = torch.empty(5, mr.K, mr.Np, dtype=torch.float64, device=q.device)
         dg_refine_project(mc, mr, qc, qr, stream)
     return mr, qr
+
+
+class AdaptiveStepper:
+    """SSP-RK3 steps with an adaptation cycle before every `every`-th step
+    (section 3.2: regrid every T steps; indicator and projections on the GPU,
+    forest passes on the host), the host part of each cycle overlapped with GPU
+    work.  At a cycle the indicator is enqueued, its flags copied to pinned host
+    memory behind an event, and the next step is computed at once on the current
+    mesh, out of place, while the host waits for the flags and runs the passes.
+    If the cycle changes no leaf that step is the result (the same kernels on the
+    same inputs as adapting first: bitwise the same state); otherwise it is
+    dropped and the step is made again after the projections.  Host control flow
+    only: every arithmetic step runs in the library.
+
+    step(events=None) advances one step; with a list, an event pair around the
+    three stage launches of the step that is kept is appended to it."""
+
+    def __init__(self, mesh: Mesh, phys: PhysParams, q, dt, every, kind, thr, buffer=0, stream=None):
+        import torch
+        self.mesh, self.phys, self.q, self.dt = mesh, phys, q, dt
+        self.every, self.kind, self.thr, self.buffer = every, kind, thr, buffer
+        self.stream = stream
+        self.n = 0           # steps made
+        self.cycles = 0      # adaptation cycles run
+        self.changed = 0     # cycles that changed the mesh (speculative step dropped)
+        # flag buffers (device and pinned host), allocated ahead of the first cycle and
+        # grown with the mesh: an allocation inside a cycle would stall it
+        self._dev = torch.empty(0, dtype=torch.int8, device=q.device)
+        self._host = torch.empty(0, dtype=torch.int8).pin_memory()
+        self._reserve(mesh.K)
+
+    def _reserve(self, K):
+        import torch
+        if self._dev.numel() < K:
+            self._dev = torch.empty(2 * K, dtype=torch.int8, device=self.q.device)
+        if self._host.numel() < K:
+            self._host = torch.empty(2 * K, dtype=torch.int8).pin_memory()
+
+    def _stages(self, mesh, q, out, events):
+        import torch
+        q1, q2 = torch.empty_like(q), torch.empty_like(q)
+        if events is not None:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(torch.cuda.current_stream() if self.stream is None else self.stream)
+        dg_rk_stage(mesh, self.phys, *SSP_RK3[0], self.dt, q, q, q1, self.stream)
+        dg_rk_stage(mesh, self.phys, *SSP_RK3[1], self.dt, q, q1, q2, self.stream)
+        dg_rk_stage(mesh, self.phys, *SSP_RK3[2], self.dt, q, q2, out, self.stream)
+        if events is not None:
+            e1.record(torch.cuda.current_stream() if self.stream is None else self.stream)
+            return e0, e1
+        return None
+
+    def step(self, events=None):
+        import torch
+        due = self.n > 0 and self.every > 0 and self.n % self.every == 0
+        mesh, q = self.mesh, self.q
+        if not due:
+            ev = self._stages(mesh, q, q, events)
+        else:
+            self.cycles += 1
+            K = mesh.K
+            self._reserve(max(K, 1))
+            dg_indicator_async(mesh, self.phys, q, self.kind, self.thr, self._dev, stream=self.stream)
+            host = self._host[:K]
+            host.copy_(self._dev[:K], non_blocking=True)
+            ready = torch.cuda.Event()
+            ready.record(torch.cuda.current_stream() if self.stream is None else self.stream)
+            spec = torch.empty_like(q)
+            ev = self._stages(mesh, q, spec, events)  # speculative: q itself is kept
+            ready.synchronize()
+            flags = host.numpy().copy()
+            mc, mr = adapt_meshes_from_flags(mesh, flags, self.buffer)
+            if mr is mesh:
+                self.q = spec
+            else:
+                self.changed += 1
+                mr2, qn = project_cycle(mesh, mc, mr, q, self.stream)
+                mr2.prev = None
+                self.mesh, self.q = mr2, qn
+                self._reserve(mr2.K)
+                ev = self._stages(mr2, qn, qn, events)
+        if ev is not None:
+            events.append(ev)
+        self.n += 1
 
 
 def initial_mesh(N, nroot, max_level, lo, hi, periodic, phys: PhysParams, bell, kind, thr):

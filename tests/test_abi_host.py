@@ -153,3 +153,33 @@ def test_flags_buffer_matches_oracle(ci, seed):
         assert np.array_equal(dg.dg_flags_buffer(lm, fl, B), fo.buffer_flags(om, fl, B)), B
     with pytest.raises(dg.DGError):
         dg.dg_flags_buffer(lm, fl, -1)
+
+
+@pytest.mark.parametrize("ci", range(len(CASES)))
+def test_pass_changes_predicts_the_pass(ci):
+    """dg_pass_changes answers whether the pass changes a leaf without building a
+    mesh: it must agree with what dg_mesh_build then does (n_refined /
+    n_coarsened), on flag patterns that do and do not change the mesh: random
+    flags, all -1 (complete families, some vetoed), -1 only on level-0 leaves
+    (no family), +1 only at max_level (nothing to refine)."""
+    c = CASES[ci]
+    lo, hi = (0.0, 0.0, 0.0), (1000.0, 500.0, 700.0)
+    lm = dg.dg_mesh_build(c["N"], c["nroot"], c["L"], lo, hi, c["periodic"], host_only=True)
+    rng = np.random.default_rng(90 + ci)
+    for _ in range(2):
+        lm = dg.dg_mesh_build(prev=lm, flags=(rng.random(lm.K) < 0.3).astype(np.int8), pass_=dg.DG_PASS_REFINE)
+    lvl = lm.tables()["leaf"][:, 1]
+    patterns = [rng.choice(np.array([-1, 0, 1], dtype=np.int8), size=lm.K) for _ in range(4)]
+    patterns += [np.full(lm.K, -1, np.int8), np.where(lvl == 0, -1, 0).astype(np.int8),
+                 np.where(lvl == c["L"], 1, 0).astype(np.int8), np.zeros(lm.K, np.int8)]
+    seen = set()
+    for fl in patterns:
+        for pass_ in (dg.DG_PASS_COARSEN, dg.DG_PASS_REFINE):
+            pred = dg.dg_pass_changes(lm, fl, pass_)
+            m2 = dg.dg_mesh_build(prev=lm, flags=fl, pass_=pass_)
+            got = (m2.info.n_coarsened if pass_ == dg.DG_PASS_COARSEN else m2.info.n_refined) > 0
+            assert pred == got, (pass_, pred, got)
+            seen.add((pass_, pred))
+    assert len(seen) == 4  # both answers for both passes
+    with pytest.raises(dg.DGError):
+        dg.dg_pass_changes(lm, np.zeros(lm.K, np.int8), 7)
