@@ -16,6 +16,11 @@ Plain PyTorch CPU float64 code written from the paper's statements:
   half-interval mortars per tangential axis (the fine side projection is the
   identity), the Riemann problem is solved on the mortars and the flux is
   projected back with sum_i s_i M^{-1} S^T, s_i = 1/2 per axis.
+* Pointwise matching (section 3.3, the simpler alternative the paper compares
+  the mortars with; ``Operator(..., nonconforming="pointwise")``): each side
+  solves the Riemann problem at its own face nodes against the other side's
+  polynomial evaluated there, with no projection, so the two sides' fluxes do
+  not balance and the scheme loses discrete conservation.
 * Conservative coarsening by LGL integration and refinement by the same
   tensor-product projection matrices (section 3.3).
 
@@ -31,6 +36,11 @@ Readings where the paper is silent (each is listed in the design notes):
   taken on the perturbation variables, with the dissipative sign q'- - q'+.
 * No-flux walls use the mirror state (rho', U - 2 (U.n) n, Theta').
 * Background on a mortar is that of the fine face nodes.
+* Pointwise matching: the fine side is the mortar method's fine side (the
+  coarse polynomial at the fine nodes); at a coarse node the fine polynomial of
+  the quadrant containing it, the average of the two (four) quadrants on a
+  shared mid-line (mid-point), against the coarse trace with the coarse node's
+  background.
 * Lift: at a face node the boundary integral divided by the LGL volume weight
   gives R -= (2/h_d) / w_N * (F*.n - F(q-).n), w_N = 2/(N(N+1)).
 
@@ -207,8 +217,11 @@ def interp2(Ia, Ib, tr, N):
 class Operator:
     """Geometry and tables of one mesh, prepared once (plain tensors)."""
 
-    def __init__(self, mesh: fo.Mesh, phys: Phys):
+    def __init__(self, mesh: fo.Mesh, phys: Phys, nonconforming: str = "mortar"):
+        if nonconforming not in ("mortar", "pointwise"):
+            raise ValueError("nonconforming must be 'mortar' or 'pointwise'")
         self.mesh, self.phys = mesh, phys
+        self.nonconforming = nonconforming
         N = mesh.N
         self.N, self.K = N, mesh.K
         re = refelem(N)
@@ -216,6 +229,7 @@ class Operator:
         self.D = _t(re.D)
         self.I = [_t(re.I[0]), _t(re.I[1])]
         self.Rm = [_t(re.R[0]), _t(re.R[1])]
+        self.P = [_t(re.P[0]), _t(re.P[1])]
         self.wN = 2.0 / (N * (N + 1))
         _, h = fo.elem_lo_h(mesh)
         self.h = _t(h)                       # [K, 3]
@@ -293,16 +307,21 @@ class Operator:
             fo_ = 2 * d + (1 - s)                                    # fine side face
             ec = self.hang[sel, 0]
             qc, bc = self._trace(q, f, ec)
-            proj = torch.zeros_like(qc)
+            proj = torch.zeros_like(qc)   # mortar: projected flux; pointwise: fine state at coarse nodes
             for quad in range(4):
                 a, b = quad & 1, quad >> 1
                 ef = self.hang[sel, 2 + quad]
                 qf, bf = self._trace(q, fo_, ef)
                 qm = interp2(self.I[a], self.I[b], qc, N)             # coarse -> mortar
                 Fs = rusanov(qm, bf, qf, bf, ph, d, sgn)             # F*.n_c on mortar
-                proj = proj + interp2(self.Rm[a], self.Rm[b], Fs, N)  # mortar -> coarse
+                if self.nonconforming == "mortar":
+                    proj = proj + interp2(self.Rm[a], self.Rm[b], Fs, N)  # mortar -> coarse
+                else:
+                    proj = proj + interp2(self.P[a], self.P[b], qf, N)    # fine polynomial at coarse nodes
                 dF = -Fs + sgn * flux_dir(qf, bf, ph, d)             # fine side, n_f = -n_c
                 delta[fo_] = delta[fo_].index_add(1, ef, dF)
+            if self.nonconforming == "pointwise":
+                proj = rusanov(qc, bc, proj, bc, ph, d, sgn)         # F*.n_c at the coarse nodes
             delta[f] = delta[f].index_add(1, ec, proj - sgn * flux_dir(qc, bc, ph, d))
 
         R = torch.zeros(5, K, N + 1, N + 1, N + 1, dtype=F64)

@@ -102,6 +102,18 @@ def half_interp(xnodes, a: int):
     return lagrange_eval(x, (x + 2 * a - 1) / 2.0)
 
 
+def pointwise_from_half(xnodes, a: int):
+    """P_a[m, j] = c_a(m) l_j(2 x_m - (2a - 1)): the polynomial of half a (nodal
+    values on its own LGL nodes) evaluated at the parent's node m, for pointwise
+    matching at a non-conforming face (section 3.3, alternative (a)).  c_a(m) = 1
+    when x_m lies inside half a, 1/2 on the midpoint x_m = 0 shared by both halves
+    (the two values are averaged), 0 otherwise."""
+    x = np.asarray(xnodes, dtype=np.float64)
+    inside = (x <= 0.0) if a == 0 else (x >= 0.0)
+    c = np.where(inside, np.where(x == 0.0, 0.5, 1.0), 0.0)
+    return c[:, None] * lagrange_eval(x, 2.0 * x - (2 * a - 1))
+
+
 def exact_mass(xnodes):
     """M[j, k] = integral over [-1,1] of l_j l_k, exact (Gauss-Legendre, N+2 points)."""
     x = np.asarray(xnodes, dtype=np.float64)
@@ -127,6 +139,7 @@ class RefElem:
         self.I = [half_interp(self.x, 0), half_interp(self.x, 1)]
         self.M = exact_mass(self.x)
         self.R = [restriction(self.x, 0), restriction(self.x, 1)]
+        self.P = [pointwise_from_half(self.x, 0), pointwise_from_half(self.x, 1)]
 
 
 @functools.lru_cache(maxsize=None)

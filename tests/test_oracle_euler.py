@@ -394,3 +394,128 @@ def test_rk3_adjoint_matches_central_differences():
         fd = (float(J(q0 + eps * d)) - float(J(q0 - eps * d))) / (2 * eps)
         ad = float((g * d).sum())
         assert abs(fd - ad) <= 1e-6 * max(abs(fd), abs(ad)), (fd, ad)
+
+
+# ----------------------------------------------------------------------------- pointwise matching
+
+@pytest.mark.parametrize("N", [2, 3, 4, 7])
+def test_pointwise_operators_partition_identity(N):
+    """P_a evaluates the polynomial of half a at the parent's nodes: for any
+    parent polynomial v, I_a v are the nodal values of v on half a, and
+    sum_a P_a I_a v = v (each parent node lies in one half, the mid-point in
+    both with weight 1/2).  Also: P_a is exact on a node strictly inside half a
+    for a monomial sampled on that half's own nodes."""
+    re = refelem(N)
+    S = re.P[0] @ re.I[0] + re.P[1] @ re.I[1]
+    assert np.abs(S - np.eye(N + 1)).max() < 1e-12
+    x = re.x
+    for a in (0, 1):
+        for k in range(N + 1):
+            half = ((x + 2 * a - 1) / 2.0) ** k          # x^k sampled on half a's nodes
+            got = re.P[a] @ half
+            inside = (x < 0) if a == 0 else (x > 0)
+            assert np.abs(got[inside] - x[inside] ** k).max() < 1e-12
+            assert np.all(got[(x > 0) if a == 0 else (x < 0)] == 0.0)
+
+
+def test_pointwise_equals_mortar_without_hanging_faces():
+    desc = fo.ForestDesc(3, 2, 2, 2, 1, (0.0, 0.0, 0.0), (1000.0, 1000.0, 1000.0), (1, 0, 0))
+    m = fo.build(desc, None)
+    op_m, op_p = eu.Operator(m, eu.Phys()), eu.Operator(m, eu.Phys(), nonconforming="pointwise")
+    q = rand_q(op_m, 21)
+    assert torch.equal(op_m.rhs(q), op_p.rhs(q))
+
+
+def test_pointwise_free_stream_and_rest():
+    m = amr_mesh(3, periodic=(1, 1, 1), seed=2)
+    ph = eu.Phys(g=0.0, background=eu.BG_CONSTANT, rho0=1.2, Theta0=360.0)
+    op = eu.Operator(m, ph, nonconforming="pointwise")
+    q = torch.zeros(5, m.K, 4, 4, 4, dtype=F64)
+    assert torch.count_nonzero(op.rhs(q)) == 0
+    q[1], q[2], q[3] = 12.0, -7.0, 3.0
+    assert float(op.rhs(q).abs().max()) < 1e-13 * 1e5 / 250.0 * 10
+
+
+@pytest.mark.parametrize("N", [2, 3, 4])
+def test_pointwise_polynomial_divergence(N):
+    """With U a continuous polynomial of degree <= N, both sides see the same
+    state at every face point, so pointwise matching also reproduces -div U."""
+    m = amr_mesh(N, periodic=(0, 0, 0), seed=4, hi=(2.0, 2.0, 2.0))
+    ph = eu.Phys(g=0.0, background=eu.BG_CONSTANT, rho0=1.0, Theta0=300.0)
+    op = eu.Operator(m, ph, nonconforming="pointwise")
+    X, Y, Z = eu.node_xyz(m)
+    c = np.random.default_rng(N).standard_normal(7)
+    bx, by, bz = X * (2 - X), Y * (2 - Y), Z * (2 - Z)
+    p1, p2, p3 = c[0] + c[1] * Y ** N + c[2] * Z, c[3] + c[4] * X ** N, c[5] + c[6] * X * Y ** (N - 1)
+    divU = (2 - 2 * X) * p1 + (2 - 2 * Y) * p2 + (2 - 2 * Z) * p3
+    q = torch.stack([torch.zeros_like(X), bx * p1, by * p2, bz * p3, torch.zeros_like(X)])
+    R = op.rhs(q)
+    assert float((R[0] + divU).abs().max()) < 1e-11 * float(divU.abs().max() + 1)
+
+
+def test_pointwise_loses_conservation_mortar_keeps_it():
+    """The conservation gap the paper compares (section 3.3, tracer budgets of
+    section 4): with hanging faces the mortar scheme conserves rho' and Theta'
+    (= rho theta, a tracer with c = theta) to round-off, pointwise matching does
+    not; on the fine faces the two schemes agree exactly."""
+    m = amr_mesh(3, periodic=(1, 0, 1), seed=3)
+    op_m = eu.Operator(m, eu.Phys())
+    op_p = eu.Operator(m, eu.Phys(), nonconforming="pointwise")
+    q = rand_q(op_m, 5)
+    Rm, Rp = op_m.rhs(q), op_p.rhs(q)
+    JW = eu.quad_weights(op_m)
+    for v in (0, 4):
+        scale = float((JW * Rm[v].abs()).sum())
+        tot_m = math.fsum((JW * Rm[v]).reshape(-1).tolist())
+        tot_p = math.fsum((JW * Rp[v]).reshape(-1).tolist())
+        assert abs(tot_m) < 1e-13 * scale
+        assert abs(tot_p) > 1e-6 * scale, (v, tot_p, scale)
+    # leaves on no coarse side of a hanging face have identical right-hand sides
+    coarse = set(int(e) for e in np.asarray(m.hang)[:, 0])
+    other = torch.tensor([e for e in range(m.K) if e not in coarse])
+    assert torch.equal(Rm[:, other], Rp[:, other])
+
+
+def test_pointwise_coarse_side_by_geometry():
+    """Brute force on one hanging face: the fine state the pointwise coarse side
+    uses at each coarse face node is the fine leaf's own polynomial evaluated at
+    that node's physical position (found from the node coordinates, tensor
+    Lagrange evaluation on the fine leaf's face), averaged over the fine leaves
+    whose face contains the point."""
+    N = 3
+    m = amr_mesh(N, periodic=(0, 0, 0), seed=6)
+    op = eu.Operator(m, eu.Phys(), nonconforming="pointwise")
+    q = rand_q(op, 8)
+    X, Y, Z = eu.node_xyz(m)
+    xyz = torch.stack([X, Y, Z])
+    re = refelem(N)
+    from oracle.refelem import lagrange_eval
+    row = np.asarray(m.hang)[0]
+    ec, f = int(row[0]), int(row[1])
+    d = f // 2
+    fo_ = 2 * d + (1 - f % 2)
+    t1, t2 = [a for a in range(3) if a != d]
+    qc = eu.face_slice(q, f, N)[:, ec]                  # [5, nf]
+    pc = eu.face_slice(xyz, f, N)[:, ec]                # [3, nf] coarse face node positions
+    want = torch.zeros_like(qc)
+    for mm in range(qc.shape[1]):
+        vals, cnt = torch.zeros(5, dtype=F64), 0
+        for quad in range(4):
+            ef = int(row[2 + quad])
+            pf = eu.face_slice(xyz, fo_, N)[:, ef]      # fine face node positions
+            lo1, hi1 = float(pf[t1].min()), float(pf[t1].max())
+            lo2, hi2 = float(pf[t2].min()), float(pf[t2].max())
+            u, v = float(pc[t1, mm]), float(pc[t2, mm])
+            if not (lo1 <= u <= hi1 and lo2 <= v <= hi2):
+                continue
+            s1 = 2 * (u - lo1) / (hi1 - lo1) - 1
+            s2 = 2 * (v - lo2) / (hi2 - lo2) - 1
+            L1 = lagrange_eval(re.x, [s1])[0]
+            L2 = lagrange_eval(re.x, [s2])[0]
+            tr = eu.face_slice(q, fo_, N)[:, ef].reshape(5, N + 1, N + 1)   # [v, b(t2), a(t1)]
+            vals = vals + torch.einsum('vba,b,a->v', tr, torch.as_tensor(L2), torch.as_tensor(L1))
+            cnt += 1
+        want[:, mm] = vals / cnt
+    got = sum(eu.interp2(op.P[quad & 1], op.P[quad >> 1],
+                         eu.face_slice(q, fo_, N)[:, int(row[2 + quad])], N) for quad in range(4))
+    assert float((got - want).abs().max()) < 1e-10 * float(qc.abs().max())
