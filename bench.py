@@ -321,6 +321,22 @@ def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us):
                     "mass_drift_per_step_rel_mixed": budget_drift(dg, torch, mesh, q, mixed, dt)}
     # ---- forced adaptation cycle on the same mesh
     out["forced_cycle"] = forced_cycle(dg, torch, mesh, q)
+    # ---- conservation gap at the hanging faces: mortars against pointwise matching,
+    # 10 SSP-RK3 steps from the same state, change of the rho' and Theta' budgets
+    # relative to the total mass (Theta' = rho theta, a tracer with c = theta)
+    gap = {}
+    for scheme, key in ((dg.DG_NC_MORTAR, "mortar"), (dg.DG_NC_POINTWISE, "pointwise")):
+        php = dg.PhysParams(nonconforming=scheme)
+        qg, g1, g2 = q.clone(), torch.empty_like(q), torch.empty_like(q)
+        b0 = dg.dg_budgets(mesh, php, qg)
+        for _ in range(10):
+            dg.ssp_rk3_step(mesh, php, dt, qg, g1, g2)
+        b1 = dg.dg_budgets(mesh, php, qg)
+        stage_us = _time_launches(torch, lambda: dg.dg_rk_stage(mesh, php, 0.75, 0.25, dt, q, qs2, q1), 20)
+        gap[key] = {"rho_prime_drift_rel_mass": abs(b1[0] - b0[0]) / abs(b0[1]),
+                    "theta_prime_drift_rel_mass": abs(b1[2] - b0[2]) / abs(b0[1]), "stage_us": stage_us}
+    out["nonconforming_gap_10_steps"] = gap
+    del qg, g1, g2
     # ---- adjoint cost: one transposed RHS vs one RHS on the same state
     lam = torch.randn(q.shape, dtype=torch.float64, device=q.device, generator=torch.Generator(q.device).manual_seed(7))
     g = torch.empty_like(q)

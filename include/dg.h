@@ -61,6 +61,10 @@ typedef int32_t dg_status;
 #define DG_FP64         0    /* every operation in float64 */
 #define DG_MIXED        1    /* volume flux contractions in float32, rest float64 */
 
+#define DG_NC_MORTAR    0    /* hanging faces: L2 mortars (section 3.3; conservative) */
+#define DG_NC_POINTWISE 1    /* hanging faces: pointwise matching (section 3.3's simpler
+                                alternative; not conservative, forward calls only) */
+
 #define DG_IND_THETA      0  /* eta_e = max |theta'| over the leaf's nodes   */
 #define DG_IND_GRAD_THETA 1  /* eta_e = max |grad theta| over the leaf's nodes */
 
@@ -83,12 +87,18 @@ typedef struct {
 
 /* Gas constants (section 2.1: R = cp - cv, gamma = cp/cv, P = P0 (R Theta/P0)^gamma),
  * gravity g and the hydrostatic background (section 2.1 perturbation form;
- * neutral profile of section 4.3).  precision selects DG_FP64 or DG_MIXED. */
+ * neutral profile of section 4.3).  precision selects DG_FP64 or DG_MIXED;
+ * nonconforming selects the hanging-face scheme, DG_NC_MORTAR or
+ * DG_NC_POINTWISE (the fine side solves its Riemann problem against the coarse
+ * polynomial at its nodes, the coarse side against the fine polynomial at its
+ * nodes, averaged over the quadrants on a shared mid-line, with no projection;
+ * the adjoint calls return DG_EUNSUPPORTED for it). */
 typedef struct {
     double cp, cv, P0, g;
     int32_t background;
     int32_t precision;
     double theta0, rho0, Theta0;
+    int32_t nonconforming;
 } dg_phys;
 
 typedef struct {

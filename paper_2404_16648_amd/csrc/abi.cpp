@@ -72,7 +72,7 @@ DevLayout dev_layout(int64_t K, int N, int64_t red_len, int64_t n_hang) {
         return off;
     };
     DevLayout L{};
-    L.ops = take(sizeof(double) * (9 * N1 * N1 + N1));
+    L.ops = take(sizeof(double) * (11 * N1 * N1 + N1));
     L.geo = take(sizeof(double) * 4 * k);
     L.c1d = take(sizeof(double) * 3 * k * N1);
     L.ft = take(sizeof(int32_t) * 6 * k);
@@ -185,13 +185,16 @@ dg_status build_device(dg_mesh* m) {
     // one staging buffer and one copy for every table of the mesh; the background,
     // reduction and flag buffers are carved from the same block
     std::vector<char> up(L.upload, 0);
-    // D, I0, I1, R0, R1 ([N1][N1] row-major), w [N1], then I0^T, I1^T, R0^T, R1^T (adjoint)
+    // D, I0, I1, R0, R1 ([N1][N1] row-major), w [N1], then I0^T, I1^T, R0^T, R1^T (adjoint),
+    // then P0, P1 (pointwise matching)
     double* ops = (double*)(up.data() + L.ops);
     for (auto* v : {&m->ops.D, &m->ops.I0, &m->ops.I1, &m->ops.R0, &m->ops.R1, &m->ops.w})
         for (double x : *v) *ops++ = x;
     for (auto* v : {&m->ops.I0, &m->ops.I1, &m->ops.R0, &m->ops.R1})
         for (int c = 0; c < N1; ++c)
             for (int r = 0; r < N1; ++r) *ops++ = (*v)[r * N1 + c];
+    for (auto* v : {&m->ops.P0, &m->ops.P1})
+        for (double x : *v) *ops++ = x;
     double* geo = (double*)(up.data() + L.geo);
     double* c1d = (double*)(up.data() + L.c1d);
     int32_t* level = (int32_t*)(up.data() + L.lv);
@@ -250,6 +253,8 @@ dg_status check_phys(const dg_phys* p) {
         return fail(DG_EINVAL, "unknown background");
     }
     if (p->precision != DG_FP64 && p->precision != DG_MIXED) return fail(DG_EINVAL, "unknown precision");
+    if (p->nonconforming != DG_NC_MORTAR && p->nonconforming != DG_NC_POINTWISE)
+        return fail(DG_EINVAL, "unknown nonconforming-face scheme");
     return DG_OK;
 }
 
@@ -485,7 +490,8 @@ static dg_status stage_common(const dg_mesh* mc, const dg_phys* phys, int mode, 
     if ((st = ensure_bg(m, phys, s))) return st;
     StageArgs args = stage_args(m, phys);
     if (m->n_hang) {
-        MortArgs ma{qs, m->d_mort, m->d_ops, m->d_geo, m->d_bg, m->d_hang, m->n_hang, args.K, args.gamma, args.binom};
+        MortArgs ma{qs, m->d_mort, m->d_ops, m->d_geo, m->d_bg, m->d_hang, m->n_hang, args.K, args.gamma, args.binom,
+                    phys->nonconforming == DG_NC_POINTWISE ? 1 : 0};
         HIP_TRY(launch_mortar(m->h.desc.N, ma, s));
     }
     args.q0 = q0;
@@ -553,6 +559,8 @@ static dg_status adjoint_common(const dg_mesh* mc, const dg_phys* phys, int mode
     dg_status st = check_dev_mesh(mc);
     if (st) return st;
     if ((st = check_phys(phys))) return st;
+    if (phys->nonconforming != DG_NC_MORTAR)
+        return fail(DG_EUNSUPPORTED, "the adjoint is provided for the mortar scheme only");
     if (!q || !lam || !out) return fail(DG_EINVAL, "NULL field pointer");
     if (out == q || out == lam) return fail(DG_EINVAL, "output must not alias q or lam");
     if ((a1 != 0.0 && !w1) || (a2 != 0.0 && !w2)) return fail(DG_EINVAL, "NULL w1/w2 with a non-zero weight");

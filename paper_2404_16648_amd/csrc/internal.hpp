@@ -23,6 +23,7 @@ struct Leaf {
 struct RefOps {
     int N = 0;
     std::vector<double> x, w, D, I0, I1, R0, R1;
+    std::vector<double> P0, P1;  // pointwise matching: half a's polynomial at the parent's nodes
 };
 RefOps make_refops(int N);
 

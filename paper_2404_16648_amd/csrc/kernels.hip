@@ -292,12 +292,18 @@ struct StageLds {
 // is projected back with R_a x R_b.  Output per hanging face h, lifted and
 // ready for the stage kernel: mort[h][0] the coarse face, mort[h][1 + quad] the
 // fine faces, each [5][NF].  The stage kernel copies these into its faces.
-template <int N>
+// PW (pointwise matching, section 3.3's simpler alternative): the fine faces as
+// above; the coarse side instead solves the Riemann problem at each of its own
+// face nodes against the fine polynomial evaluated there (sum over quadrants of
+// P_a x P_b applied to the fine traces, the same separable passes as the
+// projection), so the two sides' fluxes no longer balance.
+template <int N, bool PW>
 __global__ void __launch_bounds__(Sz<N>::NT) k_mortar(const MortArgs A) {
     constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
     static_assert(4 * NF <= NT, "one mortar point per thread");
+    constexpr int PWOFF = Sz<N>::NOPS;       // P0, P1 after D, I0, I1, R0, R1, w (PW)
     __shared__ double sT[5 * NF], sU[10 * NF], sMq[20 * NF], sG[10 * NF];
-    __shared__ double sOps[Sz<N>::NOPS];
+    __shared__ double sOps[Sz<N>::NOPS + (PW ? 2 * NF : 0)];
     __shared__ double sBg[3 * N1];  // the coarse leaf's background
     const int64_t h = xcd_remap(blockIdx.x, gridDim.x);
     const int t = threadIdx.x;
@@ -310,6 +316,8 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_mortar(const MortArgs A) {
     const double sgn = (f & 1) ? 1.0 : -1.0;  // the coarse leaf's outward normal
     const double* const qs = A.qs;
     for (int ii = t; ii < Sz<N>::NOPS; ii += NT) sOps[ii] = A.ops[ii];
+    if (PW)  // the ops table holds 4 transposes (adjoint) before P0, P1
+        for (int ii = t; ii < 2 * NF; ii += NT) sOps[PWOFF + ii] = A.ops[Sz<N>::NOPS + 4 * NF + ii];
     if (t < 3 * N1) sBg[t] = A.bg[(t / N1) * KN1 + ec * N1 + (t % N1)];
     for (int it = t; it < 5 * NF; it += NT) {
         const int v = it / NF, m = it % NF;
@@ -352,18 +360,20 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_mortar(const MortArgs A) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
             out[v * NF] = (Fs[v] - Fo[v]) * lift_f;
-            sMq[(quad * 5 + v) * NF + m] = -Fs[v];  // in place: the coarse side's flux
+            // in place: the coarse side's flux (mortars) or the fine state (pointwise)
+            sMq[(quad * 5 + v) * NF + m] = PW ? qF[v] : -Fs[v];
         }
     }
     __syncthreads();
-    // projection back: sG[b][v] = sum_a R_a along t1 of F[a + 2b]; then sum_b R_b along t2
+    // back to the coarse nodes: sG[b][v] = sum_a B_a along t1 of X[a + 2b]; then sum_b
+    // B_b along t2, with B = R (mortars: X the flux) or B = P (pointwise: X the fine state)
     for (int it = t; it < 10 * NF; it += NT) {
         const int p = it / NF, r = it % NF, bb = r / N1, a2 = r % N1;
         const int qb = p / 5, v = p % 5;
         double acc = 0.0;
 #pragma unroll
         for (int qa = 0; qa < 2; ++qa) {
-            const double* Rm = sOps + (3 + qa) * NF + a2 * N1;
+            const double* Rm = sOps + (PW ? PWOFF + qa * NF : (3 + qa) * NF) + a2 * N1;
             const double* x = sMq + ((qa + 2 * qb) * 5 + v) * NF + bb * N1;
 #pragma unroll
             for (int a = 0; a < N1; ++a) acc = fma(Rm[a], x[a], acc);
@@ -376,7 +386,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_mortar(const MortArgs A) {
         double proj = 0.0;
 #pragma unroll
         for (int qb = 0; qb < 2; ++qb) {
-            const double* Rm = sOps + (3 + qb) * NF + b2 * N1;
+            const double* Rm = sOps + (PW ? PWOFF + qb * NF : (3 + qb) * NF) + b2 * N1;
             const double* x = sG + (qb * 5 + v) * NF + a;
 #pragma unroll
             for (int bb = 0; bb < N1; ++bb) proj = fma(Rm[bb], x[bb * N1], proj);
@@ -388,14 +398,27 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_mortar(const MortArgs A) {
         const int m = t;
         const int kk = face_k<N>(f, m);
         const Bg b = bg_make(sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk]);
-        double qL[5], Fo[5], lam;
+        double qL[5], Fo[5], Fc[5], lam;
 #pragma unroll
         for (int v = 0; v < 5; ++v) qL[v] = sT[v * NF + m];  // the coarse trace at face node m
         const double PpL = pprime(qL[4], b.rTh, b.P, gamma, A.binom);
-        with_axis(f >> 1, [&](auto dc) { flux_n<decltype(dc)::value>(qL, b, PpL, sgn, gamma, Fo, lam); });
+        if constexpr (PW) {
+            // Riemann problem at the coarse node against the fine state there
+            double qR[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qR[v] = sU[v * NF + m];
+            const double PpR = pprime(qR[4], b.rTh, b.P, gamma, A.binom);
+            with_axis(f >> 1, [&](auto dc) {
+                rusanov<decltype(dc)::value>(qL, b, PpL, qR, b, PpR, sgn, gamma, Fc, Fo);
+            });
+        } else {
+            with_axis(f >> 1, [&](auto dc) { flux_n<decltype(dc)::value>(qL, b, PpL, sgn, gamma, Fo, lam); });
+#pragma unroll
+            for (int v = 0; v < 5; ++v) Fc[v] = sU[v * NF + m];
+        }
         double* const out = A.mort + (h * 5 * 5) * NF + m;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) out[v * NF] = (sU[v * NF + m] - Fo[v]) * lift_c;
+        for (int v = 0; v < 5; ++v) out[v * NF] = (Fc[v] - Fo[v]) * lift_c;
     }
 }
 
@@ -1683,7 +1706,11 @@ hipError_t launch_mortar_adjoint(int N, const MortAdjArgs& a, hipStream_t s) {
 
 hipError_t launch_mortar(int N, const MortArgs& a, hipStream_t s) {
     if (a.n_hang <= 0) return hipSuccess;
-    DG_DISPATCH_N(N, (k_mortar<NN><<<dim3((unsigned)a.n_hang), dim3(Sz<NN>::NT), 0, s>>>(a)));
+    if (a.pointwise) {
+        DG_DISPATCH_N(N, (k_mortar<NN, true><<<dim3((unsigned)a.n_hang), dim3(Sz<NN>::NT), 0, s>>>(a)));
+    } else {
+        DG_DISPATCH_N(N, (k_mortar<NN, false><<<dim3((unsigned)a.n_hang), dim3(Sz<NN>::NT), 0, s>>>(a)));
+    }
     return hipGetLastError();
 }
 

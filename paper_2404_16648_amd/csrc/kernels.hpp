@@ -82,6 +82,7 @@ struct MortArgs {
     int64_t n_hang, K;
     double gamma;
     BinomCoef binom;
+    int32_t pointwise;     // coarse side by pointwise matching instead of the mortar projection
 };
 
 // transposed mortar pre-pass: one workgroup per row of the hanging-face table;

@@ -180,6 +180,22 @@ RefOps make_refops(int N) {
         R[a] = B;
     }
 
+    // P_a[m][j] = c_a(m) l_j(2 x_m - (2a - 1)) (pointwise matching, section 3.3):
+    // half a's polynomial at the parent's node m, c_a = 1 inside half a, 1/2 on the
+    // shared mid-point (even N), 0 in the other half
+    std::vector<ld> P[2];
+    for (int a = 0; a < 2; ++a) {
+        P[a].assign(n * n, 0.0L);
+        for (int m = 0; m < n; ++m) {
+            const bool mid = std::fabs(x[m]) < 1e-12L;
+            const bool inside = mid || (a == 0 ? x[m] < 0.0L : x[m] > 0.0L);
+            if (!inside) continue;
+            lagrange_row(x, lam, 2.0L * x[m] - (2 * a - 1), &P[a][m * n]);
+            if (mid)
+                for (int j = 0; j < n; ++j) P[a][m * n + j] *= 0.5L;
+        }
+    }
+
     RefOps o;
     o.N = N;
     auto cvt = [](const std::vector<ld>& v) { return std::vector<double>(v.begin(), v.end()); };
@@ -190,6 +206,8 @@ RefOps make_refops(int N) {
     o.I1 = cvt(I[1]);
     o.R0 = cvt(R[0]);
     o.R1 = cvt(R[1]);
+    o.P0 = cvt(P[0]);
+    o.P1 = cvt(P[1]);
     return o;
 }
 

@@ -29,6 +29,8 @@ DG_BG_NEUTRAL = 0
 DG_BG_CONSTANT = 1
 DG_FP64 = 0
 DG_MIXED = 1
+DG_NC_MORTAR = 0
+DG_NC_POINTWISE = 1
 DG_IND_THETA = 0
 DG_IND_GRAD_THETA = 1
 DG_KIND_COPY = -1
@@ -56,7 +58,8 @@ class ForestDesc(C.Structure):
 class Phys(C.Structure):
     _fields_ = [("cp", C.c_double), ("cv", C.c_double), ("P0", C.c_double), ("g", C.c_double),
                 ("background", C.c_int32), ("precision", C.c_int32),
-                ("theta0", C.c_double), ("rho0", C.c_double), ("Theta0", C.c_double)]
+                ("theta0", C.c_double), ("rho0", C.c_double), ("Theta0", C.c_double),
+                ("nonconforming", C.c_int32)]
 
 
 class MeshInfo(C.Structure):
@@ -150,10 +153,11 @@ class PhysParams:
     theta0: float = 300.0
     rho0: float = 1.0
     Theta0: float = 300.0
+    nonconforming: int = DG_NC_MORTAR
 
     def c(self):
         return Phys(self.cp, self.cv, self.P0, self.g, self.background, self.precision,
-                    self.theta0, self.rho0, self.Theta0)
+                    self.theta0, self.rho0, self.Theta0, self.nonconforming)
 
 
 class Mesh:

@@ -1,0 +1,74 @@
+"""Pointwise matching at hanging faces (section 3.3's simpler alternative to the
+mortars) on the GPU: parity with the oracle's pointwise operator on AMR meshes
+at every order, the stage, the conservation gap against the mortars measured
+with the library's own budgets, and the adjoint refusing the scheme."""
+import dataclasses
+
+import pytest
+import torch
+
+from oracle import euler as eu
+from paper_2404_16648_amd import dg
+from paper_2404_16648_amd.synth import random_state
+from tests.helpers import oracle_desc, oracle_phys, random_refinements, to_elem, to_nodes
+from tests.test_gpu_parity import AMR_CASES, BOX, both_meshes, check, gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _pw(ph):
+    return dataclasses.replace(ph, nonconforming=dg.DG_NC_POINTWISE)
+
+
+@pytest.mark.parametrize("case", AMR_CASES, ids=lambda c: f"N{c['N']}")
+def test_pointwise_rhs_and_stage_amr(case):
+    od = oracle_desc(case["N"], case["nroot"], case["L"], *BOX, case["periodic"])
+    seq = random_refinements(od, 2, case["seed"])
+    lm, om = both_meshes(case["N"], case["nroot"], case["L"], case["periodic"], flag_seq=seq)
+    assert lm.info.n_hang > 0
+    ph = _pw(dg.PhysParams())
+    op = eu.Operator(om, oracle_phys(ph), nonconforming="pointwise")
+    N = om.N
+    qn = torch.as_tensor(random_state(om.K, N, case["seed"]))
+    R = lm.field()
+    dg.dg_rhs(lm, ph, gpu(qn), R)
+    torch.cuda.synchronize()
+    check(R, op.rhs(to_elem(qn, N)), what=f"pointwise rhs N={N}")
+    q0 = torch.as_tensor(random_state(om.K, N, case["seed"] + 50))
+    out = lm.field()
+    dg.dg_rk_stage(lm, ph, 0.75, 0.25, 0.002, gpu(q0), gpu(qn), out)
+    torch.cuda.synchronize()
+    check(out, eu.rk_stage(op, 0.75, 0.25, 0.002, to_elem(q0, N), to_elem(qn, N)), what=f"pointwise stage N={N}")
+
+
+def test_conservation_gap_on_gpu():
+    """Budgets of rho' and Theta' (Theta' = rho theta: the tracer with c = theta)
+    over SSP-RK3 steps on an AMR mesh with walls: the mortars keep them to
+    round-off, pointwise matching drifts by orders of magnitude more."""
+    print("conservation gap N=4", flush=True)
+    od = oracle_desc(4, (2, 2, 2), 2, *BOX, (0, 0, 0))
+    lm, om = both_meshes(4, (2, 2, 2), 2, flag_seq=random_refinements(od, 2, 31))
+    qn = gpu(torch.as_tensor(random_state(om.K, 4, 32)) * 0.1)
+    drift = {}
+    for scheme in (dg.DG_NC_MORTAR, dg.DG_NC_POINTWISE):
+        ph = dg.PhysParams(nonconforming=scheme)
+        q = qn.clone()
+        b0 = dg.dg_budgets(lm, ph, q)
+        q1, q2 = lm.field(), lm.field()
+        for _ in range(5):
+            dg.ssp_rk3_step(lm, ph, 0.005, q, q1, q2)
+        b1 = dg.dg_budgets(lm, ph, q)
+        drift[scheme] = (abs(b1[0] - b0[0]) / abs(b0[1]), abs(b1[2] - b0[2]) / abs(b0[1]))
+    print("relative drift (rho', Theta') mortar", drift[dg.DG_NC_MORTAR], "pointwise", drift[dg.DG_NC_POINTWISE])
+    for v in range(2):
+        assert drift[dg.DG_NC_MORTAR][v] < 1e-14
+        assert drift[dg.DG_NC_POINTWISE][v] > 1e3 * max(drift[dg.DG_NC_MORTAR][v], 1e-16)
+
+
+def test_adjoint_refuses_pointwise():
+    lm, om = both_meshes(3, (2, 2, 2), 1, flag_seq=random_refinements(oracle_desc(3, (2, 2, 2), 1, *BOX, (0, 0, 0)), 1, 5))
+    ph = _pw(dg.PhysParams())
+    q = lm.field()
+    with pytest.raises(dg.DGError) as ei:
+        dg.dg_rhs_adjoint(lm, ph, q, lm.field(), lm.field())
+    assert ei.value.code == -4  # DG_EUNSUPPORTED
