@@ -183,3 +183,15 @@ def test_pass_changes_predicts_the_pass(ci):
     assert len(seen) == 4  # both answers for both passes
     with pytest.raises(dg.DGError):
         dg.dg_pass_changes(lm, np.zeros(lm.K, np.int8), 7)
+
+
+def test_size_limit_at_the_kernels_indexing_bound():
+    """5 K Np must stay below 2^31 (the kernels' 32-bit field offsets): N = 7 (Np =
+    512) allows K < 838,861, so a 94^3 forest (830,584 leaves) builds and a 95^3
+    one (857,375) is refused with DG_EINVAL before any device work."""
+    m = dg.dg_mesh_build(7, (94, 94, 94), 0, host_only=True)
+    assert m.K == 94 ** 3 and 5 * m.K * m.Np < 2 ** 31
+    del m
+    with pytest.raises(dg.DGError) as e:
+        dg.dg_mesh_build(7, (95, 95, 95), 0, host_only=True)
+    assert e.value.code == dg.DG_EINVAL and "too large" in str(e.value)
