@@ -17,8 +17,8 @@ from oracle import euler as eu
 from oracle import forest as fo
 from paper_2404_16648_amd import adjoint as adj
 from paper_2404_16648_amd import dg
-from paper_2404_16648_amd.synth import random_direction
-from tests.helpers import TOL_FP64, field_errors, oracle_phys, tables_equal, to_nodes
+from paper_2404_16648_amd.synth import random_direction, random_state
+from tests.helpers import TOL_FP64, field_errors, oracle_phys, tables_equal, to_elem, to_nodes
 
 pytestmark = pytest.mark.gpu
 
@@ -157,3 +157,21 @@ def test_adjoint_config_gradient_20_directions():
         worst = max(worst, rel)
         assert rel <= 1e-6, (k, fd, ad)
     print("adjoint configuration: worst FD relative gap over 20 directions", worst, flush=True)
+
+
+def test_density_current_streamed_stage_random_state():
+    """At full size the three fields of a stage exceed the last-level cache and the
+    stage runs with q0 and its output streamed (non-temporal): a Shu-Osher stage
+    with q0 and the stage input distinct random states, against the oracle."""
+    lo, hi = (0.0, 0.0, 0.0), (25600.0, 1600.0, 6400.0)
+    lm, om = adapt_both(4, (64, 4, 16), 2, lo, hi, eu.density_current_state, eu.IND_GRAD_THETA, 1e-3)
+    assert 3 * 5 * lm.K * lm.Np * 8 > 256 * 2 ** 20
+    print("streamed stage: leaves", om.K, flush=True)
+    ph = dg.PhysParams()
+    op = eu.Operator(om, oracle_phys(ph))
+    q0 = torch.as_tensor(random_state(om.K, 4, 71))
+    qs = torch.as_tensor(random_state(om.K, 4, 72))
+    out = lm.field()
+    dg.dg_rk_stage(lm, ph, 0.75, 0.25, 0.01, gpu(q0), gpu(qs), out)
+    want = eu.rk_stage(op, 0.75, 0.25, 0.01, to_elem(q0, 4), to_elem(qs, 4))
+    check(out, want, TOL_FP64, "density current streamed stage")
