@@ -397,8 +397,13 @@ def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us):
         dg.dg_rk_stage(m1, ph, 0.75, 0.25, 0.05, q1c, s1, s2)
         dg.dg_rk_stage(m1, ph, 1.0 / 3.0, 2.0 / 3.0, 0.05, q1c, s2, s3)
 
+    # the configuration's ten steps captured once as a HIP graph and replayed (the
+    # launch-bound case: 30 stage launches of ~1 us of work each)
+    gs = dg.GraphedSteps(m1, ph, 0.05, q1c.clone(), 10)
+    graph_us = _time_launches(torch, gs.replay, 5) / 10.0
     out["uniform_4x4x4_N4"] = {"rhs_us": _time_launches(torch, lambda: dg.dg_rhs(m1, ph, q1c, r1), 20),
-                               "step_us": _time_launches(torch, step1, 20), "nodes": m1.K * m1.Np}
+                               "step_us": _time_launches(torch, step1, 20),
+                               "step_us_hip_graph_of_10_steps": graph_us, "nodes": m1.K * m1.Np}
     # ---- measured copy bandwidth (1 GiB device-to-device) beside the 8 TB/s spec
     src = torch.ones(1 << 30, dtype=torch.uint8, device=q.device)
     dst = torch.empty_like(src)

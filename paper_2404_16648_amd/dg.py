@@ -422,6 +422,32 @@ def project_cycle(mesh: Mesh, mc: Mesh, mr: Mesh, q, stream=None):
     return mr, qr
 
 
+class GraphedSteps:
+    """`nsteps` SSP-RK3 steps on one mesh captured once as a HIP graph and then
+    replayed, for meshes small enough that launch overhead dominates.  The state
+    lives in `self.q` (advanced in place by every replay()); the stage buffers are
+    owned by the object.  The mesh's device tables, its background and the kernels
+    are made ready by a warm-up step on scratch buffers before the capture, so the
+    captured calls only launch kernels (no allocation, no memset, no copy)."""
+
+    def __init__(self, mesh: Mesh, phys: PhysParams, dt, q, nsteps):
+        import torch
+        self.mesh, self.phys, self.dt, self.nsteps = mesh, phys, dt, nsteps
+        self.q = q
+        self.q1, self.q2 = torch.empty_like(q), torch.empty_like(q)
+        w = q.clone()
+        ssp_rk3_step(mesh, phys, dt, w, self.q1, self.q2)
+        torch.cuda.synchronize()
+        del w
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            for _ in range(nsteps):
+                ssp_rk3_step(mesh, phys, dt, self.q, self.q1, self.q2)
+
+    def replay(self):
+        self.graph.replay()
+
+
 class AdaptiveStepper:
     """SSP-RK3 steps with an adaptation cycle before every `every`-th step
     (section 3.2: regrid every T steps; indicator and projections on the GPU,
