@@ -41,12 +41,12 @@ STAGE_KERNEL = "k_mortar<7> + k_stage<7, 1, false>"
 # kernels.hip up to the adjoint section, the stage and mortar launchers,
 # kernels.hpp and facetypes.hpp); otherwise traffic is reported as null.
 TRAFFIC = {
-    "sources_sha256": "5c99894be873f0eb8a30c0081dd71f5522c9474c5e969a2c9679a8ada9c45724",
+    "sources_sha256": "7954d3606bf3d1cc23aa7059f163602592b7687069bf7c4f38178b909c41bb2a",
     "fetch_scale": 1048576.0 / 524302.0,  # 1 GiB copy: FETCH_SIZE reads 524302.0 KiB
     "write_scale": 1048576.0 / 1048576.0,  # 1 GiB copy: WRITE_SIZE reads 1048576.0 KiB
     # KiB per stage (mortar pre-pass + stage kernel), mean over the timed stages
-    "amr_bubble": {"fetch_kib": 77936.4, "write_kib": 73210.0},  # the 90 stages of the stage-timing pass
-    "density_current": {"fetch_kib": 168236.8, "write_kib": 131796.3},  # the 100 timed float64 stages
+    "amr_bubble": {"fetch_kib": 77900.1, "write_kib": 73210.0},  # the 90 stages of the stage-timing pass
+    "density_current": {"fetch_kib": 168387.9, "write_kib": 131957.2},  # the 100 timed float64 stages
 }
 CSRC = os.path.join(ROOT, "paper_2404_16648_amd", "csrc")
 
