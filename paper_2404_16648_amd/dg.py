@@ -461,7 +461,8 @@ class AdaptiveStepper:
     only: every arithmetic step runs in the library.
 
     step(events=None) advances one step; with a list, an event pair around the
-    three stage launches of the step that is kept is appended to it."""
+    three stage launches of the step that is kept is appended to it.  The state is
+    `self.q`; the tensor passed in becomes one of the stepper's buffers."""
 
     def __init__(self, mesh: Mesh, phys: PhysParams, q, dt, every, kind, thr, buffer=0, stream=None):
         import torch
@@ -476,6 +477,13 @@ class AdaptiveStepper:
         self._dev = torch.empty(0, dtype=torch.int8, device=q.device)
         self._host = torch.empty(0, dtype=torch.int8).pin_memory()
         self._reserve(mesh.K)
+        # stage buffers and the speculative step's output, kept across steps (swapped
+        # with the state when the speculative step is kept)
+        self._bufs(q)
+
+    def _bufs(self, q):
+        import torch
+        self._q1, self._q2, self._spec = torch.empty_like(q), torch.empty_like(q), torch.empty_like(q)
 
     def _reserve(self, K):
         import torch
@@ -486,7 +494,7 @@ class AdaptiveStepper:
 
     def _stages(self, mesh, q, out, events):
         import torch
-        q1, q2 = torch.empty_like(q), torch.empty_like(q)
+        q1, q2 = self._q1, self._q2
         if events is not None:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(torch.cuda.current_stream() if self.stream is None else self.stream)
@@ -513,19 +521,20 @@ class AdaptiveStepper:
             host.copy_(self._dev[:K], non_blocking=True)
             ready = torch.cuda.Event()
             ready.record(torch.cuda.current_stream() if self.stream is None else self.stream)
-            spec = torch.empty_like(q)
+            spec = self._spec
             ev = self._stages(mesh, q, spec, events)  # speculative: q itself is kept
             ready.synchronize()
             flags = host.numpy().copy()
             mc, mr = adapt_meshes_from_flags(mesh, flags, self.buffer)
             if mr is mesh:
-                self.q = spec
+                self.q, self._spec = spec, q  # the old state's buffer takes the next speculation
             else:
                 self.changed += 1
                 mr2, qn = project_cycle(mesh, mc, mr, q, self.stream)
                 mr2.prev = None
                 self.mesh, self.q = mr2, qn
                 self._reserve(mr2.K)
+                self._bufs(qn)
                 ev = self._stages(mr2, qn, qn, events)
         if ev is not None:
             events.append(ev)
