@@ -91,6 +91,8 @@ def parse():
     ap.add_argument("--adapt-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--rtb-seconds", type=float, default=100.0,
+                    help="simulated time of the rising-thermal-bubble long run in the extras")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run 4 plain device copies of MIB MiB each "
                          "(reference launches for the memory-traffic counters)")
@@ -207,7 +209,8 @@ def main():
     if calib is not None:
         result["copy_calibration"] = calib
     if not args.no_extras:
-        result["extras"] = extras(dg, torch, stepper.mesh, stepper.q, ph, dt, 1e3 * stage_ms / n_launches)
+        result["extras"] = extras(dg, torch, stepper.mesh, stepper.q, ph, dt, 1e3 * stage_ms / n_launches,
+                                  args.rtb_seconds)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)
@@ -280,6 +283,45 @@ def forced_cycle(dg, torch, mesh, q, reps=5):
             "same_leaves_after_cycle": bool(mr.K == mesh.K)}
 
 
+def rtb_long_run(dg, torch, t_end=100.0, regrid=25.0, dt=0.0025, seg=100):
+    """Rising-thermal-bubble-style long run (section 4.3's setting, quasi-2-D: 1000 m x
+    1000 m in x, z, one 100 m root periodic along y; 10 x 1 x 10 roots, N = 4, two
+    levels where |theta'| > 0.05 K, warm bubble 0.5 K, radius 250 m at (500, 350) m,
+    walls in x and z; no artificial viscosity), SSP-RK3 with a regrid every `regrid`
+    seconds.  Steps between regrids run as replays of a HIP graph of `seg` steps.
+    Reports the relative change of the total mass and energy over the run."""
+    ph = dg.PhysParams()
+    thr = 0.05
+    mesh, q = dg.initial_mesh(4, (10, 1, 10), 2, (0.0, 0.0, 0.0), (1000.0, 100.0, 1000.0), (0, 1, 0), ph,
+                              (0.5, (500.0, 50.0, 350.0), (250.0, 0.0, 250.0)), dg.DG_IND_THETA, thr)
+    b0 = dg.dg_budgets(mesh, ph, q)
+    steps_per_regrid = int(round(regrid / dt))
+    nreg = int(round(t_end / regrid))
+    leaves, t0 = [mesh.K], time.perf_counter()
+    steps = 0
+    for c in range(nreg):
+        if c > 0:
+            m2, q = dg.adapt_cycle(mesh, ph, q, dg.DG_IND_THETA, thr)
+            m2.prev = None
+            mesh = m2
+            leaves.append(mesh.K)
+        g = dg.GraphedSteps(mesh, ph, dt, q, seg)
+        for _ in range(steps_per_regrid // seg):
+            g.replay()
+        q = g.q
+        steps += steps_per_regrid // seg * seg
+        del g
+        try:
+            b1 = dg.dg_budgets(mesh, ph, q)
+        except dg.DGError as err:  # a non-finite state ends the run
+            return {"t_end_s": t_end, "dt_s": dt, "steps": steps, "non_finite_by_s": steps * dt, "error": str(err)}
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return {"t_end_s": t_end, "regrid_s": regrid, "dt_s": dt, "steps": steps, "regrids": nreg - 1,
+            "leaves_min_max": [min(leaves), max(leaves)], "wall_s": wall,
+            "mass_rel_change": (b1[1] - b0[1]) / b0[1], "energy_rel_change": (b1[3] - b0[3]) / abs(b0[3])}
+
+
 def budget_drift(dg, torch, mesh, q, ph, dt, steps=10):
     """Change of the integral of rho' per SSP-RK3 step over `steps` steps (no
     adaptation), relative to the integral of rho = rho_bar + rho'."""
@@ -300,7 +342,7 @@ def _field_err(torch, a, b):
     return out
 
 
-def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us):
+def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us, rtb_seconds=100.0):
     """Mixed/float64 speedup with the mixed error, the adjoint/forward cost ratio,
     and the largest AMR configuration (density current)."""
     from paper_2404_16648_amd import adjoint as adj
@@ -404,6 +446,8 @@ def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us):
     out["uniform_4x4x4_N4"] = {"rhs_us": _time_launches(torch, lambda: dg.dg_rhs(m1, ph, q1c, r1), 20),
                                "step_us": _time_launches(torch, step1, 20),
                                "step_us_hip_graph_of_10_steps": graph_us, "nodes": m1.K * m1.Np}
+    # ---- long adaptive run in the rising-thermal-bubble setting: mass and energy budgets
+    out["rtb_long_run"] = rtb_long_run(dg, torch, t_end=rtb_seconds)
     # ---- measured copy bandwidth (1 GiB device-to-device) beside the 8 TB/s spec
     src = torch.ones(1 << 30, dtype=torch.uint8, device=q.device)
     dst = torch.empty_like(src)
