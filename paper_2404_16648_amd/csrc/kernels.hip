@@ -270,7 +270,7 @@ struct StageLds {
         return (planes * NP * ESZ + 7) / 8 > 5 * NP ? (planes * NP * ESZ + 7) / 8 : 5 * NP;
     }
     // bytes of the other LDS arrays of k_stage
-    static constexpr int FIXED = 8 * (30 * NF + N1 * N1 + 4 * N1 + 4 + 8 + (MIX ? 15 : 1)) + 4 * (MIX ? 2 * N1 * N1 : 1) + 4 * 36;
+    static constexpr int FIXED = 8 * (30 * NF + N1 * N1 + 4 * N1 + 4 + 8 + (MIX ? 15 : 1)) + 4 * (MIX ? 2 * N1 * N1 : 1) + 4 * 18;
     static constexpr int blocks(int planes) {
         const int by_lds = 160 * 1024 / (FIXED + 8 * work_dbl(planes));
         const int by_waves = 4 * StageOcc<N>::W / (Sz<N>::NT / 64);
@@ -443,7 +443,7 @@ k_stage(const StageArgs A) {
     __shared__ double sGeo[4];
     __shared__ double sBgZ[8];           // far-side background of faces 4, 5 (rho, Theta, P, 1/Theta)
     __shared__ int sType[6];
-    __shared__ int sNb[24];
+    __shared__ int sNb[6];               // first neighbour per face
     __shared__ int sHs[6];               // hanging face: row of the mortar pre-pass
     __shared__ double sFr[MIX ? 15 : 1];  // MIX: reference flux [direction][variable]
 
@@ -475,7 +475,7 @@ k_stage(const StageArgs A) {
     }
     if (t < 6) {
         sType[t] = rec[t];
-        sNb[4 * t] = rec[6 + t];
+        sNb[t] = rec[6 + t];
         sHs[t] = rec[12 + t];
     }
     if constexpr (!GATHER) {
@@ -647,7 +647,7 @@ k_stage(const StageArgs A) {
             } else {
                 // both traces requested before either is used (a wall face loads its
                 // own entry twice and mirrors it below)
-                const int nb = type == FT_CONF ? sNb[f * 4] : (int)e;
+                const int nb = type == FT_CONF ? sNb[f] : (int)e;
                 const uint32_t nn = (uint32_t)(type == FT_CONF ? face_node<N>(f ^ 1, m) : n);
 #pragma unroll
                 for (int v = 0; v < 5; ++v) qL[v] = ld_off(qv[v], eoff + (uint32_t)n * 8u);
@@ -667,7 +667,7 @@ k_stage(const StageArgs A) {
                 qR[1 + d] = -qL[1 + d];  // mirror state: reverse the normal momentum
             } else {
                 if (tf & FT_BG_NB) {
-                    const int nb = sNb[f * 4], kn = face_k<N>(f ^ 1, m);
+                    const int nb = sNb[f], kn = face_k<N>(f ^ 1, m);
                     bR = bg_make(A.bg[nb * N1 + kn], A.bg[K * N1 + nb * N1 + kn], A.bg[2 * K * N1 + nb * N1 + kn]);
                 }
                 PpR = pprime(qR[4], bR.rTh, bR.P, gamma, A.binom);
