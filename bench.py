@@ -41,12 +41,12 @@ STAGE_KERNEL = "k_mortar<7> + k_stage<7, 1, false>"
 # kernels.hip up to the adjoint section, the stage and mortar launchers,
 # kernels.hpp and facetypes.hpp); otherwise traffic is reported as null.
 TRAFFIC = {
-    "sources_sha256": "7954d3606bf3d1cc23aa7059f163602592b7687069bf7c4f38178b909c41bb2a",
+    "sources_sha256": "5a042cd026d0f0c865cb036dec607beb92a7261e7a7795db2df7f8bed8a4a0a9",
     "fetch_scale": 1048576.0 / 524302.0,  # 1 GiB copy: FETCH_SIZE reads 524302.0 KiB
     "write_scale": 1048576.0 / 1048576.0,  # 1 GiB copy: WRITE_SIZE reads 1048576.0 KiB
     # KiB per stage (mortar pre-pass + stage kernel), mean over the timed stages
-    "amr_bubble": {"fetch_kib": 77900.1, "write_kib": 73210.0},  # the 90 stages of the stage-timing pass
-    "density_current": {"fetch_kib": 168387.9, "write_kib": 131957.2},  # the 100 timed float64 stages
+    "amr_bubble": {"fetch_kib": 77927.0, "write_kib": 73210.0},  # the 90 stages of the stage-timing pass
+    "density_current": {"fetch_kib": 168310.6, "write_kib": 131938.3},  # the 100 timed float64 stages
 }
 CSRC = os.path.join(ROOT, "paper_2404_16648_amd", "csrc")
 
@@ -92,7 +92,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--rtb-seconds", type=float, default=100.0,
-                    help="simulated time of the rising-thermal-bubble long run in the extras")
+                    help="simulated time of the rising-thermal-bubble long run in the extras (0: skip it; "
+                         "the counter passes skip it: its graph replays hold thousands of queued dispatches)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run 4 plain device copies of MIB MiB each "
                          "(reference launches for the memory-traffic counters)")
@@ -133,6 +134,7 @@ def main():
             record.append((e0, e1, nodes * (BYTES_STAGE_FIRST + 2 * BYTES_STAGE), 3))
         state["dofs"] += 3 * 5 * nodes
 
+    _progress("warm-up steps")
     for _ in range(args.warmup):
         one_step(None)
     torch.cuda.synchronize()
@@ -290,6 +292,8 @@ def rtb_long_run(dg, torch, t_end=100.0, regrid=25.0, dt=0.0025, seg=100):
     walls in x and z; no artificial viscosity), SSP-RK3 with a regrid every `regrid`
     seconds.  Steps between regrids run as replays of a HIP graph of `seg` steps.
     Reports the relative change of the total mass and energy over the run."""
+    if t_end <= 0:
+        return {"skipped": True}
     ph = dg.PhysParams()
     thr = 0.05
     mesh, q = dg.initial_mesh(4, (10, 1, 10), 2, (0.0, 0.0, 0.0), (1000.0, 100.0, 1000.0), (0, 1, 0), ph,
@@ -342,9 +346,14 @@ def _field_err(torch, a, b):
     return out
 
 
+def _progress(what):
+    print(f"[bench] {what}", file=sys.stderr, flush=True)
+
+
 def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us, rtb_seconds=100.0):
     """Mixed/float64 speedup with the mixed error, the adjoint/forward cost ratio,
     and the largest AMR configuration (density current)."""
+    _progress("extras: precision split")
     from paper_2404_16648_amd import adjoint as adj
     out = {}
     # ---- precision split on the same mesh and state
@@ -362,6 +371,7 @@ def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us, rtb_seconds=100.0):
                     "mass_drift_per_step_rel_fp64": budget_drift(dg, torch, mesh, q, ph, dt),
                     "mass_drift_per_step_rel_mixed": budget_drift(dg, torch, mesh, q, mixed, dt)}
     # ---- forced adaptation cycle on the same mesh
+    _progress("extras: forced adaptation cycle")
     out["forced_cycle"] = forced_cycle(dg, torch, mesh, q)
     # ---- conservation gap at the hanging faces: mortars against pointwise matching,
     # 10 SSP-RK3 steps from the same state, change of the rho' and Theta' budgets
@@ -379,6 +389,7 @@ def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us, rtb_seconds=100.0):
                     "theta_prime_drift_rel_mass": abs(b1[2] - b0[2]) / abs(b0[1]), "stage_us": stage_us}
     out["nonconforming_gap_10_steps"] = gap
     del qg, g1, g2
+    _progress("extras: adjoint")
     # ---- adjoint cost: one transposed RHS vs one RHS on the same state
     lam = torch.randn(q.shape, dtype=torch.float64, device=q.device, generator=torch.Generator(q.device).manual_seed(7))
     g = torch.empty_like(q)
@@ -408,6 +419,7 @@ def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us, rtb_seconds=100.0):
         t2 = time.perf_counter()
     out["adjoint_gradient"] = {"workload": "16^3 hexes, N=4, 50 SSP-RK3 steps (dt=0.005 s), checkpoints every 10",
                                "forward_s": t1 - t0, "backward_s": t2 - t1, "ratio": (t2 - t1) / (t1 - t0)}
+    _progress("extras: density current")
     # ---- largest AMR configuration: density current, 64x4x16 base, N = 4, 2 levels on |grad theta|
     m3, q3 = dg.initial_mesh(4, (64, 4, 16), 2, (0.0, 0.0, 0.0), (25600.0, 1600.0, 6400.0), (0, 0, 0), ph,
                              (-15.0, (0.0, 800.0, 3000.0), (4000.0, 0.0, 2000.0)), dg.DG_IND_GRAD_THETA, 1e-3)
@@ -446,6 +458,7 @@ def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us, rtb_seconds=100.0):
     out["uniform_4x4x4_N4"] = {"rhs_us": _time_launches(torch, lambda: dg.dg_rhs(m1, ph, q1c, r1), 20),
                                "step_us": _time_launches(torch, step1, 20),
                                "step_us_hip_graph_of_10_steps": graph_us, "nodes": m1.K * m1.Np}
+    _progress("extras: long run")
     # ---- long adaptive run in the rising-thermal-bubble setting: mass and energy budgets
     out["rtb_long_run"] = rtb_long_run(dg, torch, t_end=rtb_seconds)
     # ---- measured copy bandwidth (1 GiB device-to-device) beside the 8 TB/s spec
