@@ -518,9 +518,11 @@ class AdaptiveStepper:
             self._reserve(max(K, 1))
             dg_indicator_async(mesh, self.phys, q, self.kind, self.thr, self._dev, stream=self.stream)
             host = self._host[:K]
-            host.copy_(self._dev[:K], non_blocking=True)
+            strm = torch.cuda.current_stream() if self.stream is None else self.stream
+            with torch.cuda.stream(strm):  # the copy and its event on the indicator's stream
+                host.copy_(self._dev[:K], non_blocking=True)
             ready = torch.cuda.Event()
-            ready.record(torch.cuda.current_stream() if self.stream is None else self.stream)
+            ready.record(strm)
             spec = self._spec
             ev = self._stages(mesh, q, spec, events)  # speculative: q itself is kept
             ready.synchronize()
