@@ -550,3 +550,26 @@ def density_current_state(op: Operator, dtheta=-15.0, xc=0.0, zc=3000.0, rx=4000
     X, _, Z = node_xyz(op.mesh)
     r = torch.sqrt(((X - xc) / rx) ** 2 + ((Z - zc) / rz) ** 2)
     return thermal_state(op, dtheta * cosine_bell(r))
+
+
+def isentropic_vortex(X, Y, t=0.0, beta=5.0, gamma=1.4, centre=(0.0, 0.0), speed=(1.0, 1.0)):
+    """Isentropic vortex of section 4.1 with R = P0 = 1 and theta = 1 far away:
+    (u, v) = (U_inf, V_inf) + beta/(2 pi) exp((1 - r^2)/2) (-(y - y_c), x - x_c),
+    a temperature deficit T = 1 - (gamma - 1) beta^2/(8 gamma pi^2) exp(1 - r^2),
+    rho = T^(1/(gamma - 1)), P = rho^gamma (isentropic, so theta = 1 everywhere and
+    Theta = rho), translated rigidly at (U_inf, V_inf): the exact solution at time
+    t (no periodic images; the perturbation is below 3e-7 at the edge of the
+    paper's [-6, 6]^2 domain).  Returns the perturbation state about the constant
+    background (rhobar, Thetabar) = (1, 1): (rho', rho u, rho v, 0, Theta').
+    Reading: the paper prints the perturbation with a plus sign and calls it the
+    potential temperature; with theta = 1 and P = rho^gamma it is read as the
+    usual temperature deficit (a plus sign would give no vortex in balance)."""
+    xr = X - centre[0] - speed[0] * t
+    yr = Y - centre[1] - speed[1] * t
+    r2 = xr * xr + yr * yr
+    T = 1.0 - (gamma - 1.0) * beta ** 2 / (8.0 * gamma * math.pi ** 2) * torch.exp(1.0 - r2)
+    rho = T ** (1.0 / (gamma - 1.0))
+    amp = beta / (2.0 * math.pi) * torch.exp(0.5 * (1.0 - r2))
+    u = speed[0] - amp * yr
+    v = speed[1] + amp * xr
+    return torch.stack([rho - 1.0, rho * u, rho * v, torch.zeros_like(rho), rho - 1.0])
