@@ -55,6 +55,20 @@ def rel_l2(a, b):
     return out
 
 
+def assert_fields(a, b, tol, what="", vector_momentum=False):
+    """Print the per-field and per-component relative L2 errors of a against b
+    (library layout [5, K, Np]) and assert the bound.  By default every one of the
+    five components is held to tol (random states: no component vanishes).  With
+    vector_momentum the momentum is held to tol as one vector field, for states
+    whose horizontal momentum vanishes by symmetry (the centred bubbles and the
+    density current), where a per-component bound sits below the rounding floor."""
+    err = field_errors(a, b)
+    comp = rel_l2(a, b)
+    print(what, "fields", ["%.2e" % x for x in err], "components", ["%.2e" % x for x in comp], flush=True)
+    bound = err if vector_momentum else comp
+    assert max(bound) <= tol, (what, err, comp)
+
+
 def oracle_phys(p):
     """oracle Phys with the same constants as a binding PhysParams."""
     return eu.Phys(cp=p.cp, cv=p.cv, P0=p.P0, g=p.g, background=p.background,

@@ -15,8 +15,8 @@ from oracle import forest as fo
 from paper_2404_16648_amd import adjoint as adj
 from paper_2404_16648_amd import dg
 from paper_2404_16648_amd.synth import random_direction, random_state
-from tests.helpers import (TOL_FP64, field_errors, oracle_desc, oracle_phys, random_refinements, rel_l2,
-                           tables_equal, to_elem, to_nodes)
+from tests.helpers import (TOL_FP64, assert_fields, oracle_desc, oracle_phys, random_refinements, tables_equal,
+                           to_elem, to_nodes)
 
 pytestmark = pytest.mark.gpu
 
@@ -40,11 +40,9 @@ def gpu(t):
 
 
 def check(a_gpu, b_oracle, tol=TOL_FP64, what=""):
-    b = to_nodes(b_oracle)
-    err = field_errors(a_gpu, b)
-    print(what, "fields", ["%.2e" % x for x in err], "components", ["%.2e" % x for x in rel_l2(a_gpu, b)],
-          flush=True)
-    assert max(err) <= tol, (what, err)
+    """Every component within tol in relative L2 (the adjoint weights are random:
+    no component vanishes)."""
+    assert_fields(a_gpu, to_nodes(b_oracle), tol, what)
 
 
 CASES = [
@@ -52,6 +50,7 @@ CASES = [
     dict(N=3, nroot=(2, 3, 2), periodic=(1, 0, 1), seed=32),
     dict(N=4, nroot=(2, 2, 2), periodic=(1, 1, 1), seed=33),
     dict(N=5, nroot=(2, 1, 2), periodic=(0, 1, 0), seed=34),
+    dict(N=6, nroot=(1, 2, 2), periodic=(0, 0, 1), seed=39),
     dict(N=7, nroot=(2, 2, 2), periodic=(0, 0, 0), seed=35),
 ]
 
@@ -92,18 +91,21 @@ def test_rhs_adjoint_zero_wind_bubble():
     check(out, eu.rhs_adjoint(op, q, to_elem(ln, 4)), what="adjoint at rest")
 
 
-def test_rk_stage_adjoint_combination():
-    od = oracle_desc(3, (2, 2, 2), 2, *BOX, (0, 0, 0))
-    lm, om = both_meshes(3, (2, 2, 2), 2, flag_seq=random_refinements(od, 1, 38))
+@pytest.mark.parametrize("N", [3, 6, 7])
+def test_rk_stage_adjoint_combination(N):
+    od = oracle_desc(N, (2, 2, 2), 2, *BOX, (0, 0, 0))
+    seed = {3: 41, 6: 44, 7: 46}[N]  # refinements that leave hanging faces
+    lm, om = both_meshes(N, (2, 2, 2), 2, flag_seq=random_refinements(od, 1, seed))
+    assert lm.info.n_hang > 0
     ph = dg.PhysParams()
     op = eu.Operator(om, oracle_phys(ph))
-    q, y, w1, w2 = (torch.as_tensor(random_state(om.K, 3, s)) for s in (40, 41, 42, 43))
+    q, y, w1, w2 = (torch.as_tensor(random_state(om.K, N, s + N)) for s in (40, 41, 42, 43))
     dt = 0.01
     out = lm.field()
     dg.dg_rk_stage_adjoint(lm, ph, 1 / 3, gpu(w1), 0.75, gpu(w2), 0.5, dt, gpu(q), gpu(y), out)
-    E = lambda t: to_elem(t, 3)
+    E = lambda t: to_elem(t, N)
     want = E(w1) / 3 + 0.75 * E(w2) + 0.5 * (E(y) + dt * eu.rhs_adjoint(op, E(q), E(y)))
-    check(out, want, what="stage adjoint")
+    check(out, want, what=f"stage adjoint N={N}")
     with pytest.raises(dg.DGError):
         yy = gpu(y)
         dg.dg_rk_stage_adjoint(lm, ph, 0.0, None, 0.0, None, 1.0, dt, gpu(q), yy, yy)

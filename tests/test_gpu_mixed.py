@@ -12,7 +12,7 @@ from oracle import euler as eu
 from oracle import forest as fo
 from paper_2404_16648_amd import dg
 from paper_2404_16648_amd.synth import random_state
-from tests.helpers import field_errors, oracle_desc, oracle_phys, random_refinements, rel_l2, tables_equal, \
+from tests.helpers import assert_fields, field_errors, oracle_desc, oracle_phys, random_refinements, tables_equal, \
     to_elem, to_nodes
 
 pytestmark = pytest.mark.gpu
@@ -38,12 +38,10 @@ def gpu(t):
     return t.to(DEV).contiguous()
 
 
-def check(a, b_oracle, what):
-    b = to_nodes(b_oracle)
-    err = field_errors(a, b)
-    print(what, "fields", ["%.2e" % x for x in err], "components", ["%.2e" % x for x in rel_l2(a, b)], flush=True)
-    assert max(err) <= TOL_MIXED, (what, err)
-    return err
+def check(a, b_oracle, what, vector_momentum=False):
+    """Every component within 1e-5 in relative L2 of the float64 oracle (bubble
+    states: momentum as one vector field)."""
+    assert_fields(a, to_nodes(b_oracle), TOL_MIXED, what, vector_momentum)
 
 
 @pytest.mark.parametrize("N", [2, 4, 7])
@@ -69,12 +67,12 @@ def test_mixed_rhs_and_steps_bubble():
     q = gpu(to_nodes(qo))
     R = lm.field()
     dg.dg_rhs(lm, MIXED, q, R)
-    check(R, op.rhs(qo), "mixed rhs bubble")
+    check(R, op.rhs(qo), "mixed rhs bubble", vector_momentum=True)
     q1, q2 = lm.field(), lm.field()
     for s in range(10):
         dg.ssp_rk3_step(lm, MIXED, 0.02, q, q1, q2)
         qo = eu.ssp_rk3_step(op, 0.02, qo)
-        check(q, qo, f"mixed step {s + 1}")
+        check(q, qo, f"mixed step {s + 1}", vector_momentum=True)
     # conservation drift of the float32 volume term (reported, not exact)
     JW = to_nodes(eu.quad_weights(op)[None])[0]
     dg.dg_rhs(lm, MIXED, q, R)
@@ -84,6 +82,37 @@ def test_mixed_rhs_and_steps_bubble():
         scale = float((JW * Rc[v].abs()).sum())
         print("mixed conservation drift", v, tot / scale, flush=True)
         assert abs(tot) <= 1e-5 * scale
+
+
+@pytest.mark.parametrize("N", [4, 7])
+def test_mixed_rk_stage_random_amr(N):
+    """A Shu-Osher stage in the precision split with q0 distinct from the stage
+    input (the non-streamed stage form that the AMR bubble runs at N = 7)."""
+    od = oracle_desc(N, (2, 2, 2), 2, *BOX, (0, 1, 0))
+    lm, om = both_meshes(N, (2, 2, 2), 2, (0, 1, 0), flag_seq=random_refinements(od, 2, 90 + N))
+    assert lm.info.n_hang > 0
+    op = eu.Operator(om, oracle_phys(MIXED))
+    q0 = torch.as_tensor(random_state(om.K, N, 91 + N))
+    qs = torch.as_tensor(random_state(om.K, N, 92 + N))
+    out = lm.field()
+    dg.dg_rk_stage(lm, MIXED, 0.75, 0.25, 0.002, gpu(q0), gpu(qs), out)
+    check(out, eu.rk_stage(op, 0.75, 0.25, 0.002, to_elem(q0, N), to_elem(qs, N)), f"mixed stage N={N}")
+
+
+def test_mixed_streamed_stage_density_current():
+    """Full-size density current (the three fields of a stage exceed the last-level
+    cache, so the stage streams q0 and its output): a Shu-Osher stage in the
+    precision split with q0 and the stage input distinct random states."""
+    from tests.test_gpu_configs import adapt_both
+    lo, hi = (0.0, 0.0, 0.0), (25600.0, 1600.0, 6400.0)
+    lm, om = adapt_both(4, (64, 4, 16), 2, lo, hi, eu.density_current_state, eu.IND_GRAD_THETA, 1e-3)
+    assert 3 * 5 * lm.K * lm.Np * 8 > 256 * 2 ** 20
+    op = eu.Operator(om, oracle_phys(MIXED))
+    q0 = torch.as_tensor(random_state(om.K, 4, 171))
+    qs = torch.as_tensor(random_state(om.K, 4, 172))
+    out = lm.field()
+    dg.dg_rk_stage(lm, MIXED, 0.75, 0.25, 0.01, gpu(q0), gpu(qs), out)
+    check(out, eu.rk_stage(op, 0.75, 0.25, 0.01, to_elem(q0, 4), to_elem(qs, 4)), "mixed streamed stage, C3")
 
 
 def test_mixed_hydrostatic_rest_exact():
@@ -97,7 +126,7 @@ def test_mixed_hydrostatic_rest_exact():
     assert torch.count_nonzero(R) == 0
 
 
-@pytest.mark.parametrize("N", [3, 7])
+@pytest.mark.parametrize("N", [3, 6, 7])
 def test_mixed_adjoint_random_amr(N):
     """dg_rhs_adjoint and dg_rk_stage_adjoint with the precision split (transposed
     volume contractions in float32) against the float64 oracle adjoint."""
