@@ -254,6 +254,23 @@ dg_status dg_rk_stage_adjoint(const dg_mesh* mesh, const dg_phys* phys, double a
 dg_status dg_budgets(const dg_mesh* mesh, const dg_phys* phys, const double* q, double* out_host,
                      void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the budgets of dg_budgets,
+ * written to out_dev (DEVICE double[4], caller-owned) on `stream`, with no
+ * allocation, no copy and no synchronisation.  The per-block partial sums go to
+ * one file-scope device array per GPU (8 * 1024 doubles = 64 KiB, held until the
+ * process ends), whose address is looked up once per device; every entry the
+ * reduction reads is written first by the same call, so nothing is cleared.
+ * Calls that overlap on one GPU (different streams, no ordering) share that
+ * array and race; order them.  The mesh must already have its device tables
+ * (made by any earlier field call on it: making them allocates) and its device
+ * must be current, else DG_EINVAL; no size of mesh exceeds the array (the
+ * reduction uses at most 1024 blocks), the check stays as a guard.  Non-finite
+ * budgets are not reported as DG_ENONFINITE (nothing is read back): the caller
+ * inspects out_dev. */
+dg_status dg_budgets_noalloc(const dg_mesh* mesh, const dg_phys* phys, const double* q, double* out_dev,
+                             void* stream);
+
 /* Adaptation indicator: eta (device double[K], may be NULL) and flags (host
  * int8[K]): +1 where eta > thr and level < max_level, -1 where eta <= thr and
  * level > 0, else 0.  kind is DG_IND_THETA or DG_IND_GRAD_THETA.

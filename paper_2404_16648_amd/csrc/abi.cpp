@@ -655,6 +655,36 @@ dg_status dg_budgets(const dg_mesh* mc, const dg_phys* phys, const double* q, do
     return DG_OK;
 }
 
+dg_status dg_budgets_noalloc(const dg_mesh* mc, const dg_phys* phys, const double* q, double* out_dev,
+                             void* stream) {
+    if (!mc) return fail(DG_EINVAL, "mesh is NULL");
+    if (mc->h.desc.host_only) return fail(DG_EINVAL, "mesh was built host_only");
+    // making the device tables allocates: this entry point only accepts a mesh that
+    // already has them
+    if (!mc->on_device)
+        return fail(DG_EINVAL, "mesh has no device tables yet (any other field call on it makes them)");
+    dg_status st = check_phys(phys);
+    if (st) return st;
+    if (!q || !out_dev) return fail(DG_EINVAL, "NULL argument");
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != mc->device) return fail(DG_EINVAL, "the mesh's device must be the current device");
+    dg_mesh* m = const_cast<dg_mesh*>(mc);
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = ensure_bg(m, phys, s))) return st;
+    const int64_t K = (int64_t)m->h.leaves.size();
+    const int nblk = budget_blocks(K);
+    if ((int64_t)nblk * 8 > kBudgetScratchDoubles)
+        return fail(DG_EINVAL, "budget partials exceed the static scratch (" +
+                                   std::to_string(kBudgetScratchDoubles) + " doubles)");
+    double* scr = nullptr;
+    HIP_TRY(budget_scratch(&scr));
+    BudgetArgs a{q, m->d_bg, m->d_geo, m->d_c1d, m->d_ops + 5 * (m->h.desc.N + 1) * (m->h.desc.N + 1),
+                 scr, K, phys->cp / phys->cv, phys->g, binom_coef(phys)};
+    HIP_TRY(launch_budgets(m->h.desc.N, a, nblk, out_dev, s));
+    return DG_OK;
+}
+
 dg_status dg_indicator(const dg_mesh* mc, const dg_phys* phys, const double* q, int32_t kind, double thr,
                        double* eta, int8_t* flags_host, void* stream) {
     dg_status st = check_dev_mesh(mc);

@@ -19,6 +19,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -1778,8 +1779,32 @@ hipError_t launch_coarsen(int N, bool adjoint, const XferArgs& a, hipStream_t s)
 }
 
 int budget_blocks(int64_t K) {
-    int64_t b = K < 1024 ? K : 1024;
+    int64_t b = K < kBudgetMaxBlocks ? K : kBudgetMaxBlocks;
     return (int)(b < 1 ? 1 : b);
+}
+
+// Partial sums of the allocation-free budgets: one file-scope array per device,
+// the most the reduction ever uses (kBudgetMaxBlocks blocks x 4 compensated
+// sums), so any mesh fits.  Host code never passes the array's name to a kernel:
+// its device address is looked up once per device with hipGetSymbolAddress.
+static __device__ __align__(256) double scratch[kBudgetScratchDoubles];
+
+hipError_t budget_scratch(double** out) {
+    static std::mutex mu;
+    static double* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<double*>(p);
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_budgets(int N, const BudgetArgs& a, int nblk, double* out_dev, hipStream_t s) {

@@ -149,7 +149,15 @@ hipError_t launch_fma_burst(int blocks, int iters, double* sink, hipStream_t s);
 // adjoint = false: the projection; true: its transpose
 hipError_t launch_refine(int N, bool adjoint, const XferArgs& a, hipStream_t s);
 hipError_t launch_coarsen(int N, bool adjoint, const XferArgs& a, hipStream_t s);
+// the budget reduction runs at most kBudgetMaxBlocks blocks, each leaving 4
+// compensated sums (8 doubles)
+constexpr int kBudgetMaxBlocks = 1024;
+constexpr int kBudgetScratchDoubles = 8 * kBudgetMaxBlocks;
+constexpr int kMaxDevices = 64;
 int budget_blocks(int64_t K);
+// device address of the allocation-free budgets' partial sums on the current
+// device (looked up once per device)
+hipError_t budget_scratch(double** out);
 hipError_t launch_budgets(int N, const BudgetArgs& a, int nblk, double* out_dev, hipStream_t s);
 hipError_t launch_indicator(int N, const IndArgs& a, hipStream_t s);
 

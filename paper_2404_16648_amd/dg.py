@@ -39,7 +39,7 @@ DG_KIND_FAMILY = 8
 EXPORTED = [
     "dg_mesh_build", "dg_mesh_free", "dg_mesh_info_get", "dg_mesh_export", "dg_node_coords",
     "dg_init_bell", "dg_rhs", "dg_rk_stage", "dg_refine_project", "dg_coarsen_project",
-    "dg_refine_project_adjoint", "dg_coarsen_project_adjoint", "dg_rhs_adjoint", "dg_rk_stage_adjoint", "dg_budgets", "dg_indicator", "dg_indicator_async", "dg_pass_changes", "dg_flags_buffer", "dg_fma_burst", "dg_last_error",
+    "dg_refine_project_adjoint", "dg_coarsen_project_adjoint", "dg_rhs_adjoint", "dg_rk_stage_adjoint", "dg_budgets", "dg_budgets_noalloc", "dg_indicator", "dg_indicator_async", "dg_pass_changes", "dg_flags_buffer", "dg_fma_burst", "dg_last_error",
 ]
 
 
@@ -104,6 +104,7 @@ def lib():
         L.dg_rk_stage_adjoint.argtypes = [P, C.POINTER(Phys), C.c_double, P, C.c_double, P, C.c_double,
                                           C.c_double, P, P, P, P]
         L.dg_budgets.argtypes = [P, C.POINTER(Phys), P, P, P]
+        L.dg_budgets_noalloc.argtypes = [P, C.POINTER(Phys), P, P, P]
         L.dg_fma_burst.argtypes = [C.c_int32, C.c_int32, P, P, P]
         L.dg_flags_buffer.argtypes = [P, P, C.c_int32]
         L.dg_indicator.argtypes = [P, C.POINTER(Phys), P, C.c_int32, C.c_double, P, P, P]
@@ -338,6 +339,19 @@ def dg_budgets(mesh: Mesh, phys: PhysParams, q, stream=None):
     p = phys.c()
     _check(lib().dg_budgets(mesh.handle, C.byref(p), _ptr(q), out, _stream(stream)))
     return tuple(out)
+
+
+def dg_budgets_noalloc(mesh: Mesh, phys: PhysParams, q, out_dev, stream=None):
+    """Budgets into the device float64 tensor out_dev[4], enqueued only (no
+    allocation, copy or synchronisation)."""
+    import torch
+    _shape_check(mesh, q)
+    if (not isinstance(out_dev, torch.Tensor) or not out_dev.is_cuda or out_dev.dtype != torch.float64
+            or out_dev.numel() < 4 or not out_dev.is_contiguous()):
+        raise ValueError("out_dev must be a contiguous float64 GPU tensor of at least 4 entries")
+    p = phys.c()
+    _check(lib().dg_budgets_noalloc(mesh.handle, C.byref(p), _ptr(q), C.c_void_p(out_dev.data_ptr()),
+                                    _stream(stream)))
 
 
 def dg_indicator(mesh: Mesh, phys: PhysParams, q, kind, thr, eta=None, stream=None):
