@@ -1,26 +1,31 @@
 """Benchmark of the DG-AMR hot path on one MI355X.
 
-Workload (default): the AMR warm-bubble case -- box 1000 m cubed, 8x8x8 base
-hexes, N = 7, refined two levels where |theta'| > 0.1 K with 2:1 balance,
-cosine-bell bubble +2 K radius 250 m at (500, 500, 350) m, no-flux walls,
-SSP-RK3 with dt = 0.001 s and re-adaptation every 10 steps by conservative
-projection.  One benchmark step = one SSP-RK3 step (3 fused stage launches);
-every 10th step also runs an adaptation cycle (indicator, coarsen pass and
-projection, refine pass and projection), inside the timed region; the host part
-of a cycle (flag download, forest passes) overlaps a step computed at once on
-the current mesh, kept when the cycle changes no leaf and made again on the
-adapted mesh otherwise (the same result either way).
+Workload (headline): the density current -- 25.6 x 1.6 x 6.4 km, 64 x 4 x 16
+base hexes, N = 4, cold cosine bell -15 K with radii 4 km x 2 km at x = 0,
+z = 3 km, refined two levels where |grad theta| > 1e-3 K/m with 2:1 balance,
+no-flux walls; SSP-RK3 with dt = 0.01 s and an adaptation cycle every 10
+steps (indicator, coarsen pass and projection, refine pass and projection)
+inside the timed region.  The host part of a cycle (flag download, forest
+passes) overlaps a step computed at once on the current mesh, kept when the
+cycle changes no leaf and made again on the adapted mesh otherwise (the same
+result either way).  One benchmark step = one SSP-RK3 step (3 fused stage
+launches, each behind a mortar pre-pass).
 
 Prints one JSON line: DOF-updates/s (5 variables x nodes x 3 RHS evaluations
-per step) over the timed steps, the roofline of the dominant kernel (the fused
-stage) from HIP events around the stage launches of a second pass of as many
-steps (the timed steps carry no events between stages: each timing marker
-costs the GPU a few microseconds), and the oracle timed on the host cores on a
-bounded sample of the same workload.
+per step) over the timed steps; the roofline of the dominant kernel pair (the
+mortar pre-pass and the fused stage kernel of one dg_rk_stage call) from HIP
+events around the stage launches of a second pass of as many steps (the timed
+steps carry no events between stages: each timing marker costs the GPU a few
+microseconds); the oracle timed on the host cores on one SSP-RK3 stage of the
+same workload (1 thread and all cores, median of 3), with the other
+configurations' oracle timings and the library-vs-oracle errors of that stage
+(float64 and the precision split).  The AMR warm bubble (N = 7) and the other
+workloads are in "extras".
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -30,29 +35,36 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_STAGE_FIRST = 80.0       # per node: read qs (40 B), write qout (40 B); a = 0
 BYTES_STAGE = 120.0            # per node: read q0 and qs, write qout
-STAGE_KERNEL = "k_mortar<7> + k_stage<7, 1, false>"
+STAGE_KERNEL = {"density_current": "k_mortar<4, false> + k_stage<4, 2, false>",
+                "amr_bubble": "k_mortar<7, false> + k_stage<7, 1, false>"}
 
-# Bytes beyond L2 per stage (the mortar pre-pass plus the fused stage kernel,
-# the two launches of one dg_rk_stage call) over the timed steps of the default
-# workload, from two counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per
-# dispatch, the two kernels summed), each scaled by the ratio of the bytes a
-# plain device copy of known size moves to what the same counter reads for it.
-# Valid only for the kernel sources they were taken on (SHA-256 below:
-# kernels.hip up to the adjoint section, the stage and mortar launchers,
-# kernels.hpp and facetypes.hpp); otherwise traffic is reported as null.
+# Density current: 25.6 x 1.6 x 6.4 km, 64 x 4 x 16 roots, N = 4, two levels on |grad theta|
+DC = dict(N=4, nroot=(64, 4, 16), L=2, lo=(0.0, 0.0, 0.0), hi=(25600.0, 1600.0, 6400.0),
+          bell=(-15.0, (0.0, 800.0, 3000.0), (4000.0, 0.0, 2000.0)), thr=1e-3, dt=0.01)
+# AMR warm bubble: 1000 m box, 8^3 roots, N = 7, two levels on |theta'|
+BUBBLE = dict(N=7, nroot=(8, 8, 8), L=2, lo=(0.0, 0.0, 0.0), hi=(1000.0, 1000.0, 1000.0),
+              bell=(2.0, (500.0, 500.0, 350.0), (250.0, 250.0, 250.0)), thr=0.1, dt=0.001)
+
+# Bytes beyond L2 per stage (the mortar pre-pass plus the fused stage kernel, the two
+# launches of one dg_rk_stage call) over the stage-timing steps of the default run,
+# from two counter runs of this command (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch, the two kernels summed), each scaled by the ratio of the bytes a plain
+# device copy of known size moves to what the same counter reads for it.  Valid only
+# for the kernel and forest sources they were taken on (SHA-256 below); otherwise
+# traffic is reported as null.  Not measured by the run that prints the line.
 TRAFFIC = {
-    "sources_sha256": "5a042cd026d0f0c865cb036dec607beb92a7261e7a7795db2df7f8bed8a4a0a9",
+    "sources_sha256": None,
     "fetch_scale": 1048576.0 / 524302.0,  # 1 GiB copy: FETCH_SIZE reads 524302.0 KiB
     "write_scale": 1048576.0 / 1048576.0,  # 1 GiB copy: WRITE_SIZE reads 1048576.0 KiB
-    # KiB per stage (mortar pre-pass + stage kernel), mean over the timed stages
-    "amr_bubble": {"fetch_kib": 77927.0, "write_kib": 73210.0},  # the 90 stages of the stage-timing pass
-    "density_current": {"fetch_kib": 168310.6, "write_kib": 131938.3},  # the 100 timed float64 stages
+    "density_current": {"fetch_kib": None, "write_kib": None},
+    "source": "profiles/k_stage_density_current_N4_traffic.md",
 }
 CSRC = os.path.join(ROOT, "paper_2404_16648_amd", "csrc")
 
 
 def kernel_sources_sha256():
-    """SHA-256 of the stage kernel's sources, or None if they cannot be delimited."""
+    """SHA-256 of the stage kernel's sources and of the forest (the leaf order sets
+    the memory access pattern), or None if they cannot be delimited."""
     import hashlib
     with open(os.path.join(CSRC, "kernels.hip")) as f:
         src = f.read()
@@ -69,13 +81,13 @@ def kernel_sources_sha256():
     h = hashlib.sha256()
     for part in parts:
         h.update(part.encode())
-    for name in ("kernels.hpp", "facetypes.hpp"):
+    for name in ("kernels.hpp", "facetypes.hpp", "forest.cpp"):
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def traffic_bytes_per_launch(workload="amr_bubble"):
+def traffic_bytes_per_launch(workload="density_current"):
     t = TRAFFIC
     w = t[workload]
     if t["sources_sha256"] is None or t["sources_sha256"] != kernel_sources_sha256() or w["fetch_kib"] is None:
@@ -86,85 +98,90 @@ def traffic_bytes_per_launch(workload="amr_bubble"):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--adapt-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--rtb-seconds", type=float, default=100.0,
                     help="simulated time of the rising-thermal-bubble long run in the extras (0: skip it; "
-                         "the counter passes skip it: its graph replays hold thousands of queued dispatches)")
+                         "counter passes skip it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run 4 plain device copies of MIB MiB each "
                          "(reference launches for the memory-traffic counters)")
     return ap.parse_args()
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
-        sys.exit(2)
-    import numpy as np
-    import torch
+def _progress(what):
+    print(f"[bench] {what}", file=sys.stderr, flush=True)
 
-    from paper_2404_16648_amd import dg
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+def adaptive_run(dg, torch, cfg, steps, warmup, every):
+    """SSP-RK3 with an adaptation cycle every `every` steps on the workload cfg:
+    `steps` timed steps without events (throughput), then `steps` more with one
+    event pair around the three stage launches of each step (stage duration)."""
     ph = dg.PhysParams()
-    N, nroot, L = 7, (8, 8, 8), 2
-    lo, hi = (0.0, 0.0, 0.0), (1000.0, 1000.0, 1000.0)
-    bell = (2.0, (500.0, 500.0, 350.0), (250.0, 250.0, 250.0))
-    thr, dt = 0.1, 0.001
-    mesh, q = dg.initial_mesh(N, nroot, L, lo, hi, (0, 0, 0), ph, bell, dg.DG_IND_THETA, thr)
+    kind = dg.DG_IND_GRAD_THETA if cfg is DC else dg.DG_IND_THETA
+    mesh, q = dg.initial_mesh(cfg["N"], cfg["nroot"], cfg["L"], cfg["lo"], cfg["hi"], (0, 0, 0), ph, cfg["bell"],
+                              kind, cfg["thr"])
     stream = torch.cuda.current_stream()
-
-    # SSP-RK3 with an adaptation cycle every adapt_every steps; the host part of each
-    # cycle (flag download, forest passes) overlaps a speculative step on the GPU
-    stepper = dg.AdaptiveStepper(mesh, ph, q, dt, args.adapt_every, dg.DG_IND_THETA, thr)
+    stepper = dg.AdaptiveStepper(mesh, ph, q, cfg["dt"], every, kind, cfg["thr"])
     state = {"dofs": 0}
 
     def one_step(record):
         ev = [] if record is not None else None
         stepper.step(ev)
         nodes = stepper.mesh.K * stepper.mesh.Np
-        if record is not None:  # one event pair around the three stage launches of the step
+        if record is not None:
             e0, e1 = ev[0]
             record.append((e0, e1, nodes * (BYTES_STAGE_FIRST + 2 * BYTES_STAGE), 3))
         state["dofs"] += 3 * 5 * nodes
 
-    _progress("warm-up steps")
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         one_step(None)
     torch.cuda.synchronize()
     state["dofs"] = 0
-    # throughput: the K timed steps carry no events of their own (a timing event
-    # between two stages costs the GPU ~5 us each)
+    cycles0, changed0 = stepper.cycles, stepper.changed
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(steps):
         one_step(None)
     t1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = t0.elapsed_time(t1)
-    dofs_timed = state["dofs"]
-    # stage timing for the roofline: the next K steps of the same run, one HIP event
-    # pair on the launching stream around the three stage launches of every step
-    # (the adaptation cycles stay outside the pairs)
+    dofs = state["dofs"]
+    cycles, changed = stepper.cycles - cycles0, stepper.changed - changed0
     events = []
-    for _ in range(args.steps):
+    for _ in range(steps):
         one_step(events)
     torch.cuda.synchronize()
     stage_ms = sum(e0.elapsed_time(e1) for e0, e1, _, _ in events)
     stage_bytes = sum(b for _, _, b, _ in events)
     n_launches = sum(n for _, _, _, n in events)
-    achieved = stage_bytes / (stage_ms * 1e-3) / 1e9
-    dofs_per_s = dofs_timed / (total_ms * 1e-3)
+    return {"stepper": stepper, "ph": ph, "dofs_per_s": dofs / (total_ms * 1e-3), "ms_per_step": total_ms / steps,
+            "wall_s": wall, "stage_us": 1e3 * stage_ms / n_launches,
+            "achieved_GBs": stage_bytes / (stage_ms * 1e-3) / 1e9, "alg_bytes_per_launch": stage_bytes / n_launches,
+            "cycles": cycles, "changed": changed}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only (no multi-GPU path); use --gpus 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2404_16648_amd import dg
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    _progress("density current: warm-up, timed steps, stage-timing steps")
+    r = adaptive_run(dg, torch, DC, args.steps, args.warmup, args.adapt_every)
+    stepper, ph = r["stepper"], r["ph"]
     m = stepper.mesh
     budgets = dg.dg_budgets(m, ph, stepper.q)
     calib = None
@@ -177,44 +194,47 @@ def main():
         torch.cuda.synchronize()
         calib = {"bytes_per_copy": nb, "copies": 4}
         del src, dst
-    alg_bytes = stage_bytes / max(1, n_launches)
-    traffic = traffic_bytes_per_launch()
-
+    traffic = traffic_bytes_per_launch("density_current")
+    alg = r["alg_bytes_per_launch"]
     result = {
         "metric": "DG RHS DOF-updates/s (FP64)",
-        "value": dofs_per_s,
+        "value": r["dofs_per_s"],
         "unit": "DOF-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": total_ms / args.steps,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "node_updates_per_s": dofs_per_s / 5.0,
+        "node_updates_per_s": r["dofs_per_s"] / 5.0,
         "dtype": "f64",
-        "data": "synthetic (analytic warm-bubble initial state)",
-        "config": {"workload": "AMR warm bubble: 1000 m box, 8x8x8 base, N=7, 2 levels where |theta'|>0.1 K, "
-                               "SSP-RK3 dt=0.001 s, adapt every 10 steps",
+        "data": "synthetic (analytic density-current initial state)",
+        "config": {"workload": "density current: 25.6 x 1.6 x 6.4 km, 64x4x16 base hexes, N=4, cold bell -15 K "
+                               "(4 km x 2 km at x=0, z=3 km), 2 levels where |grad theta| > 1e-3 K/m, walls, "
+                               "SSP-RK3 dt=0.01 s, adapt every 10 steps",
                    "leaves": m.K, "nodes": m.K * m.Np, "hanging_faces": int(m.info.n_hang),
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "traffic_unit": "B/launch", "algorithmic_bytes_per_launch": alg_bytes,
-                     "traffic_over_algorithmic": None if traffic is None else traffic / alg_bytes,
-                     "kernel": STAGE_KERNEL + " (mortar pre-pass, then fused volume+faces+lift+RK stage)",
-                     "avg_launch_us": 1e3 * stage_ms / max(1, n_launches)},
-        "wall_s": wall,
+        "roofline": {"bound": "hbm", "achieved": r["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": r["achieved_GBs"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "B/launch", "traffic_measured_in_this_run": False,
+                     "traffic_source": TRAFFIC["source"] + " (rocprofv3 --pmc FETCH_SIZE, WRITE_SIZE of this command)",
+                     "algorithmic_bytes_per_launch": alg,
+                     "traffic_over_algorithmic": None if traffic is None else traffic / alg,
+                     "kernel": STAGE_KERNEL["density_current"] +
+                               " (mortar pre-pass, then fused volume+faces+lift+RK stage; one dg_rk_stage call)",
+                     "avg_launch_us": r["stage_us"]},
+        "wall_s": r["wall_s"],
         "mass_prime_final": budgets[0],
-        "adaptation_cycles": {"run": stepper.cycles, "changed_mesh": stepper.changed},
+        "adaptation_cycles": {"run": r["cycles"], "changed_mesh": r["changed"]},
     }
     if calib is not None:
         result["copy_calibration"] = calib
     if not args.no_extras:
-        result["extras"] = extras(dg, torch, stepper.mesh, stepper.q, ph, dt, 1e3 * stage_ms / n_launches,
-                                  args.rtb_seconds)
+        result["extras"] = extras(dg, torch, stepper.mesh, stepper.q, ph, args)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline()
+        _progress("cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline(dg, torch)
     print(json.dumps(result), flush=True)
 
 
@@ -240,6 +260,13 @@ def _time_launches(torch, fn, reps, warmup=5, batches=5):
 
 
 def _cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
@@ -282,6 +309,8 @@ def forced_cycle(dg, torch, mesh, q, reps=5):
             "coarsen_project_us": med(kc), "refine_project_us": med(kr),
             "coarsen_project_GBs": bytes_c / (med(kc) * 1e-6) / 1e9,
             "refine_project_GBs": bytes_r / (med(kr) * 1e-6) / 1e9,
+            "coarsen_frac_hbm": bytes_c / (med(kc) * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "refine_frac_hbm": bytes_r / (med(kr) * 1e-6) / 1e9 / HBM_PEAK_GBS,
             "same_leaves_after_cycle": bool(mr.K == mesh.K)}
 
 
@@ -290,8 +319,9 @@ def rtb_long_run(dg, torch, t_end=100.0, regrid=25.0, dt=0.0025, seg=100):
     1000 m in x, z, one 100 m root periodic along y; 10 x 1 x 10 roots, N = 4, two
     levels where |theta'| > 0.05 K, warm bubble 0.5 K, radius 250 m at (500, 350) m,
     walls in x and z; no artificial viscosity), SSP-RK3 with a regrid every `regrid`
-    seconds.  Steps between regrids run as replays of a HIP graph of `seg` steps.
-    Reports the relative change of the total mass and energy over the run."""
+    seconds.  Steps between regrids run as replays of a HIP graph of `seg` steps; a
+    progress line goes to stderr at every regrid.  Reports the relative change of
+    the total mass and energy over the run."""
     if t_end <= 0:
         return {"skipped": True}
     ph = dg.PhysParams()
@@ -319,6 +349,8 @@ def rtb_long_run(dg, torch, t_end=100.0, regrid=25.0, dt=0.0025, seg=100):
             b1 = dg.dg_budgets(mesh, ph, q)
         except dg.DGError as err:  # a non-finite state ends the run
             return {"t_end_s": t_end, "dt_s": dt, "steps": steps, "non_finite_by_s": steps * dt, "error": str(err)}
+        _progress(f"long run: t = {steps * dt:.0f} s of {t_end:.0f} s, {mesh.K} leaves, "
+                  f"mass change {(b1[1] - b0[1]) / b0[1]:.2e}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return {"t_end_s": t_end, "regrid_s": regrid, "dt_s": dt, "steps": steps, "regrids": nreg - 1,
@@ -346,61 +378,84 @@ def _field_err(torch, a, b):
     return out
 
 
-def _progress(what):
-    print(f"[bench] {what}", file=sys.stderr, flush=True)
-
-
-def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us, rtb_seconds=100.0):
-    """Mixed/float64 speedup with the mixed error, the adjoint/forward cost ratio,
-    and the largest AMR configuration (density current)."""
-    _progress("extras: precision split")
-    from paper_2404_16648_amd import adjoint as adj
+def extras(dg, torch, mesh, q, ph, args):
+    """Precision split and adjoint costs on the headline mesh, the forced
+    adaptation cycle there, the AMR warm bubble, the adjoint configuration, the
+    uniform 4^3 case, the long run and the measured copy and FMA rates."""
     out = {}
-    # ---- precision split on the same mesh and state
+    dt = DC["dt"]
     mixed = dg.PhysParams(precision=dg.DG_MIXED)
+    _progress("extras: density current precision split and adjoint")
+    qs = torch.empty_like(q)
+    dg.dg_rk_stage(mesh, ph, 0.0, 1.0, dt, q, q, qs)      # a distinct stage input: q0 and qs both read
     q1 = torch.empty_like(q)
-    qs2 = torch.empty_like(q)
-    dg.dg_rk_stage(mesh, ph, 0.0, 1.0, dt, q, q, qs2)  # a distinct stage input: q0 and qs both read
-    mixed_us = _time_launches(torch, lambda: dg.dg_rk_stage(mesh, mixed, 0.75, 0.25, dt, q, qs2, q1), 20)
-    f64_us = _time_launches(torch, lambda: dg.dg_rk_stage(mesh, ph, 0.75, 0.25, dt, q, qs2, q1), 20)
+    nodes = mesh.K * mesh.Np
+    f64_us = _time_launches(torch, lambda: dg.dg_rk_stage(mesh, ph, 0.75, 0.25, dt, q, qs, q1), 20)
+    mixed_us = _time_launches(torch, lambda: dg.dg_rk_stage(mesh, mixed, 0.75, 0.25, dt, q, qs, q1), 20)
     Ra, Rb = torch.empty_like(q), torch.empty_like(q)
     dg.dg_rhs(mesh, ph, q, Ra)
     dg.dg_rhs(mesh, mixed, q, Rb)
-    out["mixed"] = {"stage_us_fp64": f64_us, "stage_us_mixed": mixed_us, "speedup": f64_us / mixed_us,
-                    "rhs_rel_l2_vs_fp64_fields(rho',momentum,Theta')": _field_err(torch, Rb, Ra),
-                    "mass_drift_per_step_rel_fp64": budget_drift(dg, torch, mesh, q, ph, dt),
-                    "mass_drift_per_step_rel_mixed": budget_drift(dg, torch, mesh, q, mixed, dt)}
-    # ---- forced adaptation cycle on the same mesh
-    _progress("extras: forced adaptation cycle")
-    out["forced_cycle"] = forced_cycle(dg, torch, mesh, q)
-    # ---- conservation gap at the hanging faces: mortars against pointwise matching,
-    # 10 SSP-RK3 steps from the same state, change of the rho' and Theta' budgets
-    # relative to the total mass (Theta' = rho theta, a tracer with c = theta)
-    gap = {}
-    for scheme, key in ((dg.DG_NC_MORTAR, "mortar"), (dg.DG_NC_POINTWISE, "pointwise")):
-        php = dg.PhysParams(nonconforming=scheme)
-        qg, g1, g2 = q.clone(), torch.empty_like(q), torch.empty_like(q)
-        b0 = dg.dg_budgets(mesh, php, qg)
-        for _ in range(10):
-            dg.ssp_rk3_step(mesh, php, dt, qg, g1, g2)
-        b1 = dg.dg_budgets(mesh, php, qg)
-        stage_us = _time_launches(torch, lambda: dg.dg_rk_stage(mesh, php, 0.75, 0.25, dt, q, qs2, q1), 20)
-        gap[key] = {"rho_prime_drift_rel_mass": abs(b1[0] - b0[0]) / abs(b0[1]),
-                    "theta_prime_drift_rel_mass": abs(b1[2] - b0[2]) / abs(b0[1]), "stage_us": stage_us}
-    out["nonconforming_gap_10_steps"] = gap
-    del qg, g1, g2
-    _progress("extras: adjoint")
-    # ---- adjoint cost: one transposed RHS vs one RHS on the same state
+    out["density_current_stage"] = {
+        "stage_us_fp64": f64_us, "stage_us_mixed": mixed_us, "speedup_mixed": f64_us / mixed_us,
+        "frac_hbm_fp64": nodes * BYTES_STAGE / (f64_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+        "frac_hbm_mixed": nodes * BYTES_STAGE / (mixed_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+        "mixed_rhs_rel_l2_vs_fp64_library(rho',momentum,Theta')": _field_err(torch, Rb, Ra),
+        "mass_drift_per_step_rel_fp64": budget_drift(dg, torch, mesh, q, ph, dt),
+        "mass_drift_per_step_rel_mixed": budget_drift(dg, torch, mesh, q, mixed, dt)}
     lam = torch.randn(q.shape, dtype=torch.float64, device=q.device, generator=torch.Generator(q.device).manual_seed(7))
     g = torch.empty_like(q)
     rhs_us = _time_launches(torch, lambda: dg.dg_rhs(mesh, ph, q, Ra), 20)
     adj_us = _time_launches(torch, lambda: dg.dg_rhs_adjoint(mesh, ph, q, lam, g), 20)
-    gm = torch.empty_like(q)
-    adjm_us = _time_launches(torch, lambda: dg.dg_rhs_adjoint(mesh, mixed, q, lam, gm), 20)
-    out["adjoint_rhs"] = {"rhs_us": rhs_us, "rhs_adjoint_us": adj_us, "ratio": adj_us / rhs_us,
-                          "rhs_adjoint_us_mixed": adjm_us,
-                          "mixed_rel_l2_vs_fp64_fields(rho',momentum,Theta')": _field_err(torch, gm, g)}
-    # ---- adjoint configuration: 16^3 hexes, N = 4, 50 SSP-RK3 steps, checkpoints every 10
+    out["density_current_adjoint_rhs"] = {"rhs_us": rhs_us, "rhs_adjoint_us": adj_us, "ratio": adj_us / rhs_us}
+    del lam, g, Ra, Rb, q1
+    _progress("extras: density current forced adaptation cycle")
+    out["density_current_forced_cycle"] = forced_cycle(dg, torch, mesh, q)
+    # ---- AMR warm bubble (N = 7): the adaptive run as for the headline
+    _progress("extras: AMR warm bubble")
+    rb = adaptive_run(dg, torch, BUBBLE, 30, 5, 10)
+    mb, qb = rb["stepper"].mesh, rb["stepper"].q
+    out["amr_bubble"] = {"workload": "1000 m box, 8x8x8 base, N=7, 2 levels where |theta'| > 0.1 K, SSP-RK3 "
+                                     "dt=0.001 s, adapt every 10 steps", "leaves": mb.K, "nodes": mb.K * mb.Np,
+                         "hanging_faces": int(mb.info.n_hang), "dof_updates_per_s": rb["dofs_per_s"],
+                         "ms_per_step": rb["ms_per_step"], "stage_us": rb["stage_us"],
+                         "kernel": STAGE_KERNEL["amr_bubble"], "achieved_GBs": rb["achieved_GBs"],
+                         "frac_hbm": rb["achieved_GBs"] / HBM_PEAK_GBS,
+                         "adaptation_cycles": {"run": rb["cycles"], "changed_mesh": rb["changed"]}}
+    qbs = torch.empty_like(qb)
+    dg.dg_rk_stage(mb, ph, 0.0, 1.0, BUBBLE["dt"], qb, qb, qbs)
+    qb1 = torch.empty_like(qb)
+    f64b = _time_launches(torch, lambda: dg.dg_rk_stage(mb, ph, 0.75, 0.25, BUBBLE["dt"], qb, qbs, qb1), 20)
+    mixb = _time_launches(torch, lambda: dg.dg_rk_stage(mb, mixed, 0.75, 0.25, BUBBLE["dt"], qb, qbs, qb1), 20)
+    Ra, Rb = torch.empty_like(qb), torch.empty_like(qb)
+    dg.dg_rhs(mb, ph, qb, Ra)
+    dg.dg_rhs(mb, mixed, qb, Rb)
+    out["amr_bubble"]["mixed"] = {"stage_us_fp64": f64b, "stage_us_mixed": mixb, "speedup": f64b / mixb,
+                                  "rhs_rel_l2_vs_fp64_library(rho',momentum,Theta')": _field_err(torch, Rb, Ra)}
+    lam = torch.randn(qb.shape, dtype=torch.float64, device=qb.device,
+                      generator=torch.Generator(qb.device).manual_seed(7))
+    g = torch.empty_like(qb)
+    rhs_us = _time_launches(torch, lambda: dg.dg_rhs(mb, ph, qb, Ra), 20)
+    adj_us = _time_launches(torch, lambda: dg.dg_rhs_adjoint(mb, ph, qb, lam, g), 20)
+    out["amr_bubble"]["adjoint_rhs"] = {"rhs_us": rhs_us, "rhs_adjoint_us": adj_us, "ratio": adj_us / rhs_us}
+    _progress("extras: AMR warm bubble forced cycle and conservation gap")
+    out["amr_bubble"]["forced_cycle"] = forced_cycle(dg, torch, mb, qb)
+    # conservation gap at the hanging faces: mortars against pointwise matching, 10
+    # SSP-RK3 steps from the same state, change of the rho' and Theta' budgets relative
+    # to the total mass (Theta' = rho theta, a tracer with c = theta)
+    gap = {}
+    for scheme, key in ((dg.DG_NC_MORTAR, "mortar"), (dg.DG_NC_POINTWISE, "pointwise")):
+        php = dg.PhysParams(nonconforming=scheme)
+        qg, g1, g2 = qb.clone(), torch.empty_like(qb), torch.empty_like(qb)
+        b0 = dg.dg_budgets(mb, php, qg)
+        for _ in range(10):
+            dg.ssp_rk3_step(mb, php, BUBBLE["dt"], qg, g1, g2)
+        b1 = dg.dg_budgets(mb, php, qg)
+        gap[key] = {"rho_prime_drift_rel_mass": abs(b1[0] - b0[0]) / abs(b0[1]),
+                    "theta_prime_drift_rel_mass": abs(b1[2] - b0[2]) / abs(b0[1])}
+    out["amr_bubble"]["nonconforming_gap_10_steps"] = gap
+    del qg, g1, g2, lam, g, Ra, Rb, qbs, qb1
+    _progress("extras: adjoint configuration")
+    from paper_2404_16648_amd import adjoint as adj
     m4 = dg.dg_mesh_build(4, (16, 16, 16), 0, (0.0, 0.0, 0.0), (1000.0, 1000.0, 1000.0))
     q4 = m4.field()
     dg.dg_init_bell(m4, ph, q4, 2.0, (500.0, 500.0, 350.0), (250.0, 250.0, 250.0))
@@ -419,27 +474,6 @@ def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us, rtb_seconds=100.0):
         t2 = time.perf_counter()
     out["adjoint_gradient"] = {"workload": "16^3 hexes, N=4, 50 SSP-RK3 steps (dt=0.005 s), checkpoints every 10",
                                "forward_s": t1 - t0, "backward_s": t2 - t1, "ratio": (t2 - t1) / (t1 - t0)}
-    _progress("extras: density current")
-    # ---- largest AMR configuration: density current, 64x4x16 base, N = 4, 2 levels on |grad theta|
-    m3, q3 = dg.initial_mesh(4, (64, 4, 16), 2, (0.0, 0.0, 0.0), (25600.0, 1600.0, 6400.0), (0, 0, 0), ph,
-                             (-15.0, (0.0, 800.0, 3000.0), (4000.0, 0.0, 2000.0)), dg.DG_IND_GRAD_THETA, 1e-3)
-    a3 = torch.empty_like(q3)
-    b3 = torch.empty_like(q3)
-    for _ in range(10):  # every field non-zero before timing
-        dg.ssp_rk3_step(m3, ph, 0.008, q3, a3, b3)
-    dg.dg_rk_stage(m3, ph, 0.0, 1.0, 0.008, q3, q3, b3)  # a distinct stage input: q0 and qs both read
-    nodes3 = m3.K * m3.Np
-    for prec, key in ((ph, "fp64"), (mixed, "mixed")):
-        us = _time_launches(torch, lambda: dg.dg_rk_stage(m3, prec, 0.75, 0.25, 0.008, q3, b3, a3), 20)
-        ach = nodes3 * BYTES_STAGE / (us * 1e-6) / 1e9
-        out["density_current_" + key] = {
-            "leaves": m3.K, "nodes": nodes3, "hanging_faces": int(m3.info.n_hang), "stage_us": us,
-            "dof_updates_per_s": 5 * nodes3 / (us * 1e-6), "achieved_GBs": ach, "frac_hbm": ach / HBM_PEAK_GBS}
-        if key == "fp64":
-            tr = traffic_bytes_per_launch("density_current")
-            out["density_current_fp64"]["traffic_B_per_stage"] = tr
-            out["density_current_fp64"]["traffic_over_algorithmic"] = (
-                None if tr is None else tr / (nodes3 * BYTES_STAGE))
     # ---- uniform bubble, 4^3 hexes, N = 4, dt = 0.05 s: launch-bound, reported only
     m1 = dg.dg_mesh_build(4, (4, 4, 4), 0, (0.0, 0.0, 0.0), (1000.0, 1000.0, 1000.0))
     q1c = m1.field()
@@ -459,55 +493,111 @@ def extras(dg, torch, mesh, q, ph, dt, fp64_stage_us, rtb_seconds=100.0):
                                "step_us": _time_launches(torch, step1, 20),
                                "step_us_hip_graph_of_10_steps": graph_us, "nodes": m1.K * m1.Np}
     _progress("extras: long run")
-    # ---- long adaptive run in the rising-thermal-bubble setting: mass and energy budgets
-    out["rtb_long_run"] = rtb_long_run(dg, torch, t_end=rtb_seconds)
+    out["rtb_long_run"] = rtb_long_run(dg, torch, t_end=args.rtb_seconds)
     # ---- measured copy bandwidth (1 GiB device-to-device) beside the 8 TB/s spec
     src = torch.ones(1 << 30, dtype=torch.uint8, device=q.device)
     dst = torch.empty_like(src)
     cu = _time_launches(torch, lambda: dst.copy_(src), 10)
     out["copy_1GiB_GBs"] = 2.0 * (1 << 30) / (cu * 1e-6) / 1e9
+    del src, dst
     # ---- measured float64 FMA rate (8 independent chains per thread) beside the 78.6 TF spec
     sink = torch.empty(256 * 4096, dtype=torch.float64, device=q.device)
     flops = dg.dg_fma_burst(4096, 4000, sink)
     fu = _time_launches(torch, lambda: dg.dg_fma_burst(4096, 4000, sink), 5)
     out["fma_f64_TFLOPs"] = flops / (fu * 1e-6) / 1e12
-    del src, dst
     return out
 
 
-def cpu_baseline():
-    """The oracle on the host cores: one SSP-RK3 step of the same workload (same
-    initial mesh and state), DOF-updates/s."""
+def cpu_baseline(dg, torch):
+    """The oracle on the host cores.  Sample: one Shu-Osher stage (a, b) = (3/4, 1/4)
+    of the density current (the headline mesh built by the oracle's own forest from
+    its own initial state and flags) from the analytic initial state plus a seeded
+    perturbation, as the stage input, with q0 the initial state; timed with 1
+    thread and with all the cores this process may use, median of 3 runs each.
+    The same stage of the other configurations (uniform 4^3 bubble, AMR warm
+    bubble, 16^3 adjoint configuration) with all cores, median of 3.  The library's
+    float64 and precision-split stage on the same inputs is compared with the
+    oracle's (relative L2 per field)."""
     import numpy as np
-    import torch
 
     from oracle import euler as eu
     from oracle import forest as fo
+    from paper_2404_16648_amd.synth import random_state
 
-    desc = fo.ForestDesc(7, 8, 8, 8, 2, (0.0, 0.0, 0.0), (1000.0, 1000.0, 1000.0), (0, 0, 0))
-    ph = eu.Phys()
-    m = fo.build(desc, None)
-    for _ in range(3):
-        op = eu.Operator(m, ph)
-        fl = eu.flags_from_indicator(m, eu.indicator(op, eu.bubble_state(op)).numpy(), 0.1)
-        fl[fl < 0] = 0
-        if not (fl > 0).any():
-            break
-        m = fo.build(desc, m, fl, fo.PASS_REFINE)
-    op = eu.Operator(m, ph)
-    q = eu.bubble_state(op)
-    t = time.perf_counter()
-    steps = 0
-    while True:
-        q = eu.ssp_rk3_step(op, 0.001, q)
-        steps += 1
-        if time.perf_counter() - t > 10.0:
-            break
-    el = time.perf_counter() - t
-    nodes = m.K * (m.N + 1) ** 3
-    return {"value": 3 * 5 * nodes * steps / el, "unit": "DOF-updates/s", "cores": torch.get_num_threads(),
-            "kind": "oracle", "sample": f"{steps} SSP-RK3 step(s) of the same workload (K={m.K}, N=7) "
-                                        f"in {el:.1f} s on {_cpu_model()}"}
+    cores = len(os.sched_getaffinity(0))
+    nthreads0 = torch.get_num_threads()
+
+    def build(cfg, state_fn, kind):
+        """The oracle's initial mesh (its own state and flags) and the flag sequence."""
+        desc = fo.ForestDesc(cfg["N"], *cfg["nroot"], cfg["L"], cfg["lo"], cfg["hi"], (0, 0, 0))
+        ph = eu.Phys()
+        m = fo.build(desc, None)
+        seq = []
+        for _ in range(cfg["L"]):
+            op = eu.Operator(m, ph)
+            fl = eu.flags_from_indicator(m, eu.indicator(op, state_fn(op), kind).numpy(), cfg["thr"])
+            fl[fl < 0] = 0
+            if not (fl > 0).any():
+                break
+            seq.append(fl)
+            m = fo.build(desc, m, fl, fo.PASS_REFINE)
+        return m, eu.Operator(m, ph), seq
+
+    def stage_rate(op, q0, qs, reps=3):
+        times, out = [], None
+        for _ in range(reps):
+            t = time.perf_counter()
+            out = eu.rk_stage(op, 0.75, 0.25, 0.01, q0, qs)
+            times.append(time.perf_counter() - t)
+        el = sorted(times)[len(times) // 2]
+        return 5 * op.K * (op.N + 1) ** 3 / el, el, out
+
+    def inputs(op, state_fn, seed):
+        q0 = state_fn(op)
+        pert = torch.as_tensor(random_state(op.K, op.N, seed, (1e-4, 1e-2, 1e-2, 1e-2, 1e-2)))
+        return q0, q0 + pert.reshape(q0.shape)
+
+    dc_state = lambda op: eu.density_current_state(op, dtheta=DC["bell"][0])
+    m, op, seq = build(DC, dc_state, eu.IND_GRAD_THETA)
+    q0, qs = inputs(op, dc_state, 11)
+    torch.set_num_threads(1)
+    v1, t1, _ = stage_rate(op, q0, qs)
+    torch.set_num_threads(cores)
+    vall, tall, want = stage_rate(op, q0, qs)
+    # the library on the same inputs (float64 and the precision split)
+    lm = dg.dg_mesh_build(DC["N"], DC["nroot"], DC["L"], DC["lo"], DC["hi"])
+    for fl in seq:  # the oracle's flags replayed on the library's forest
+        lm = dg.dg_mesh_build(prev=lm, flags=fl, pass_=dg.DG_PASS_REFINE)
+    same = lm.K == m.K and np.array_equal(lm.tables()["leaf"], np.array(m.leaves, dtype=np.int32).reshape(-1, 5))
+    parity = {"same_mesh": bool(same)}
+    if same:
+        g0 = q0.reshape(5, m.K, -1).contiguous().to("cuda")
+        gs = qs.reshape(5, m.K, -1).contiguous().to("cuda")
+        w = want.reshape(5, m.K, -1)
+        for key, prec in (("fp64", dg.DG_FP64), ("mixed", dg.DG_MIXED)):
+            out = torch.empty_like(g0)
+            dg.dg_rk_stage(lm, dg.PhysParams(precision=prec), 0.75, 0.25, 0.01, g0, gs, out)
+            torch.cuda.synchronize()
+            parity[key + "_stage_rel_l2_vs_oracle(rho',momentum,Theta')"] = _field_err(torch, out.cpu(), w)
+    del want
+    others = {}
+    for name, cfg, state_fn, kind in (
+            ("uniform_4x4x4_N4", dict(N=4, nroot=(4, 4, 4), L=0, lo=BUBBLE["lo"], hi=BUBBLE["hi"], thr=0.1),
+             eu.bubble_state, eu.IND_THETA),
+            ("amr_bubble_N7", BUBBLE, eu.bubble_state, eu.IND_THETA),
+            ("adjoint_config_16x16x16_N4", dict(N=4, nroot=(16, 16, 16), L=0, lo=BUBBLE["lo"], hi=BUBBLE["hi"],
+                                                thr=0.1), eu.bubble_state, eu.IND_THETA)):
+        mo, oo, _ = build(cfg, state_fn, kind)
+        a0, a1 = inputs(oo, state_fn, 12)
+        v, el, _ = stage_rate(oo, a0, a1)
+        others[name] = {"value": v, "unit": "DOF-updates/s", "stage_s": el, "leaves": mo.K, "N": mo.N}
+    torch.set_num_threads(nthreads0)
+    return {"value": vall, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"one SSP-RK3 stage of the density current (K={m.K}, N=4, {m.K * 125} nodes) from the "
+                      f"analytic state plus a seeded perturbation, median of 3: {tall:.2f} s on {cores} threads, "
+                      f"{t1:.2f} s on 1 thread",
+            "value_1_thread": v1, "cpu_model": _cpu_model(), "threads_all": cores,
+            "other_configs_all_cores": others, "library_vs_oracle_same_stage": parity}
 
 
 if __name__ == "__main__":

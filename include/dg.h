@@ -287,7 +287,17 @@ dg_status dg_indicator(const dg_mesh* mesh, const dg_phys* phys, const double* q
 dg_status dg_indicator_async(const dg_mesh* mesh, const dg_phys* phys, const double* q, int32_t kind,
                              double thr, double* eta, int8_t* flags_dev, void* stream);
 
-/* Message of the last failed call on this thread ("" if none). */
+/* Flags of the refine pass of an adaptation cycle whose coarsen pass built
+ * `coarsened` from the mesh the flags belong to (section 3.2: one regrid applies
+ * the indicator's coarsen and refine decisions): flags_out (host int8[K] of
+ * `coarsened`) is +1 where the leaf was kept by the coarsen pass and its flag was
+ * +1, else 0 (a parent the coarsen pass made is not refined in the same cycle; -1
+ * has no meaning in a refine pass).  flags is host int8[K] of the mesh the
+ * coarsen pass started from; a pass that changed no leaf has the identity
+ * transfer plan, so the flags carry over unchanged.  Host only.  DG_EINVAL on a
+ * NULL argument or a transfer plan out of range. */
+dg_status dg_flags_after_coarsen(const dg_mesh* coarsened, const int8_t* flags, int8_t* flags_out);
+
 /* Buffer zone around refinement (section 3.2: at least B coarse cells between a
  * feature and the coarse-fine interface, the same B in the tree-based code).
  * Reading: B rounds of face-neighbour dilation of the +1 flags, in place on the
@@ -297,15 +307,17 @@ dg_status dg_indicator_async(const dg_mesh* mesh, const dg_phys* phys, const dou
  * only (the mesh's host tables); B >= 0. */
 dg_status dg_flags_buffer(const dg_mesh* mesh, int8_t* flags, int32_t B);
 
-/* Calibration only, not part of the method: one launch of `blocks` workgroups of
- * 256 threads, every thread running `iters` rounds of 8 independent float64
- * fused multiply-adds, so that a caller timing it on `stream` can compare the
- * chip's achievable float64 vector rate with its published peak.  sink is a
- * device double[256*blocks] (one value per thread, keeps the work live);
- * *flops_out (host) receives 2*8*iters*256*blocks.  blocks, iters > 0. */
-dg_status dg_fma_burst(int32_t blocks, int32_t iters, double* sink, double* flops_out, void* stream);
-
+/* Message of the last failed call on this thread ("" if none). */
 const char* dg_last_error(void);
+
+/* ---- Benchmark calibration export, not part of the method (not in the paper).
+ * One launch of `blocks` workgroups of 256 threads, every thread running `iters`
+ * rounds of 8 independent float64 fused multiply-adds, so that a benchmark timing
+ * it on `stream` can compare the chip's achievable float64 vector rate with its
+ * published peak.  sink is a device double[256*blocks] (one value per thread,
+ * keeps the work live); *flops_out (host) receives 2*8*iters*256*blocks.
+ * blocks, iters > 0, else DG_EINVAL. */
+dg_status dg_fma_burst(int32_t blocks, int32_t iters, double* sink, double* flops_out, void* stream);
 
 #ifdef __cplusplus
 }

@@ -10,8 +10,10 @@ are:
 
 * A leaf is (r, l, ix, iy, iz): root index r = rx + nx*(ry + ny*rz), level l and
   integer anchor (ix, iy, iz) in [0, 2^l)^3 inside the root.  Leaves are sorted
-  by (r, Morton key); the key interleaves the bits of anchor * 2^(Lmax - l) with
-  x as the least significant bit.  Child c = a + 2b + 4c' (x, y, z bits).
+  by (root key, Morton key): the root key interleaves the bits of (rx, ry, rz),
+  the Morton key those of anchor * 2^(Lmax - l), x the least significant bit in
+  both, so the whole brick is one space-filling curve.  Child c = a + 2b + 4c'
+  (x, y, z bits).
 * Balance is 2:1 across faces only (including periodic wraps).  A refine pass
   applies the +1 flags (l < Lmax) and then refines every leaf that has a face
   neighbour two or more levels finer, repeated to a fixed point.
@@ -72,8 +74,18 @@ def morton_key(desc: ForestDesc, leaf) -> int:
     return key
 
 
+def root_key(desc: ForestDesc, r) -> int:
+    """Bits of the root coordinates (rx, ry, rz) interleaved, rx least significant."""
+    rc = root_coords(desc, r)
+    key = 0
+    for b in range(max(desc.nroot).bit_length()):
+        for a in range(3):
+            key |= ((rc[a] >> b) & 1) << (3 * b + a)
+    return key
+
+
 def sort_leaves(desc, leaves):
-    return sorted(leaves, key=lambda lf: (lf[0], morton_key(desc, lf)))
+    return sorted(leaves, key=lambda lf: (root_key(desc, lf[0]), morton_key(desc, lf)))
 
 
 def root_coords(desc, r):

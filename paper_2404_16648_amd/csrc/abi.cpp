@@ -48,6 +48,8 @@ RefOps refops_cached(int N) {
 }
 
 void free_device(dg_mesh* m) {
+    if (m->upload_done) (void)hipEventDestroy((hipEvent_t)m->upload_done);
+    m->upload_done = nullptr;
     if (m->d_base) (void)hipFree(m->d_base);
     m->d_base = nullptr;
     m->d_ops = m->d_geo = m->d_c1d = m->d_bg = m->d_red = m->d_eta = nullptr;
@@ -173,9 +175,26 @@ dg_status validate_mesh(const dg_mesh* m) {
     return DG_OK;
 }
 
-// one device allocation per mesh, filled from the host tables by one copy (on the
-// device the mesh was built on)
-dg_status build_device(dg_mesh* m) {
+// Pinned staging of the device-table uploads, shared by every mesh of the process:
+// a mesh's tables are written into it and copied asynchronously on the caller's
+// stream, so a new mesh costs no page faults of fresh host memory and no
+// synchronisation (a pageable copy of the ~10 MB of tables of a 25k-leaf mesh
+// faulted in ~2 ms, the pinned copy takes ~0.2 ms).  The next upload waits for the
+// previous copy out of the buffer before overwriting it.
+struct UploadStaging {
+    std::mutex mu;
+    char* buf = nullptr;
+    size_t cap = 0;
+    hipEvent_t last = nullptr;  // the copy that last read the buffer
+};
+UploadStaging& upload_staging() {
+    static UploadStaging s;
+    return s;
+}
+
+// one device allocation per mesh, filled from the host tables by one asynchronous
+// copy on stream s (on the device the mesh was built on)
+dg_status build_device(dg_mesh* m, hipStream_t s) {
     const HostMesh& h = m->h;
     const int64_t K = (int64_t)h.leaves.size();
     const int N = h.desc.N, N1 = N + 1;
@@ -184,7 +203,25 @@ dg_status build_device(dg_mesh* m) {
     const DevLayout L = dev_layout(K, N, m->red_len, m->n_hang);
     // one staging buffer and one copy for every table of the mesh; the background,
     // reduction and flag buffers are carved from the same block
-    std::vector<char> up(L.upload, 0);
+    UploadStaging& stg = upload_staging();
+    std::lock_guard<std::mutex> stg_lock(stg.mu);
+    if (stg.last) {
+        HIP_TRY(hipEventSynchronize(stg.last));
+        (void)hipEventDestroy(stg.last);
+        stg.last = nullptr;
+    }
+    if (stg.cap < L.upload) {
+        if (stg.buf) (void)hipHostFree(stg.buf);
+        stg.buf = nullptr;
+        stg.cap = 0;
+        const size_t want = std::max(L.upload + L.upload / 4, (size_t)1 << 20);
+        HIP_TRY(hipHostMalloc((void**)&stg.buf, want, hipHostMallocDefault));
+        stg.cap = want;
+    }
+    struct View {
+        char* p;
+        char* data() { return p; }
+    } up{stg.buf};
     // D, I0, I1, R0, R1 ([N1][N1] row-major), w [N1], then I0^T, I1^T, R0^T, R1^T (adjoint),
     // then P0, P1 (pointwise matching)
     double* ops = (double*)(up.data() + L.ops);
@@ -236,7 +273,15 @@ dg_status build_device(dg_mesh* m) {
     char* base = nullptr;
     HIP_TRY(hipMalloc((void**)&base, L.total));
     set_device_pointers(m, base, L);
-    HIP_TRY(hipMemcpy(base, up.data(), L.upload, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpyAsync(base, up.data(), L.upload, hipMemcpyHostToDevice, s));
+    hipEvent_t ev_stg = nullptr, ev_mesh = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&ev_stg, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(ev_stg, s));
+    stg.last = ev_stg;
+    HIP_TRY(hipEventCreateWithFlags(&ev_mesh, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(ev_mesh, s));
+    m->upload_done = ev_mesh;
+    m->upload_stream = s;
     m->on_device = true;
     return DG_OK;
 }
@@ -261,18 +306,32 @@ dg_status check_phys(const dg_phys* p) {
 // the device tables are made when a call first uses the mesh on the GPU (a mesh that
 // is only inspected on the host, such as a pass that changed no leaf and is
 // dropped, never costs an allocation or a copy)
-dg_status check_dev_mesh(const dg_mesh* mc) {
+// s is the stream of the call: the upload is enqueued on it, and a call on another
+// stream waits for the upload until it has completed
+dg_status check_dev_mesh(const dg_mesh* mc, hipStream_t s) {
     if (!mc) return fail(DG_EINVAL, "mesh is NULL");
     if (mc->h.desc.host_only) return fail(DG_EINVAL, "mesh was built host_only");
-    if (mc->on_device) return DG_OK;
     static std::mutex mu;
+    if (mc->on_device) {
+        if (!mc->upload_done) return DG_OK;
+        std::lock_guard<std::mutex> lock(mu);
+        dg_mesh* m = const_cast<dg_mesh*>(mc);
+        if (!m->upload_done) return DG_OK;
+        if (hipEventQuery((hipEvent_t)m->upload_done) == hipSuccess) {
+            (void)hipEventDestroy((hipEvent_t)m->upload_done);
+            m->upload_done = nullptr;
+        } else if ((void*)s != m->upload_stream) {
+            HIP_TRY(hipStreamWaitEvent(s, (hipEvent_t)m->upload_done, 0));
+        }
+        return DG_OK;
+    }
     std::lock_guard<std::mutex> lock(mu);
     if (mc->on_device) return DG_OK;
     dg_mesh* m = const_cast<dg_mesh*>(mc);
     int cur = 0;
     HIP_TRY(hipGetDevice(&cur));
     if (cur != m->device) HIP_TRY(hipSetDevice(m->device));
-    const dg_status st = build_device(m);
+    const dg_status st = build_device(m, s);
     if (st != DG_OK) free_device(m);
     if (cur != m->device) (void)hipSetDevice(cur);
     return st;
@@ -457,7 +516,7 @@ dg_status dg_mesh_export(const dg_mesh* m, const dg_mesh_tables* t) {
 }
 
 dg_status dg_node_coords(const dg_mesh* m, double* xyz, void* stream) {
-    dg_status st = check_dev_mesh(m);
+    dg_status st = check_dev_mesh(m, (hipStream_t)stream);
     if (st) return st;
     if (!xyz) return fail(DG_EINVAL, "xyz is NULL");
     HIP_TRY(launch_node_coords((int64_t)m->h.leaves.size(), m->h.desc.N, m->d_c1d, xyz, (hipStream_t)stream));
@@ -465,7 +524,7 @@ dg_status dg_node_coords(const dg_mesh* m, double* xyz, void* stream) {
 }
 
 dg_status dg_init_bell(const dg_mesh* mc, const dg_phys* phys, const dg_bell* bell, double* q, void* stream) {
-    dg_status st = check_dev_mesh(mc);
+    dg_status st = check_dev_mesh(mc, (hipStream_t)stream);
     if (st) return st;
     if ((st = check_phys(phys))) return st;
     if (!bell || !q) return fail(DG_EINVAL, "NULL argument");
@@ -479,7 +538,7 @@ dg_status dg_init_bell(const dg_mesh* mc, const dg_phys* phys, const dg_bell* be
 
 static dg_status stage_common(const dg_mesh* mc, const dg_phys* phys, int mode, double a, double b, double dt,
                               const double* q0, const double* qs, double* out, void* stream) {
-    dg_status st = check_dev_mesh(mc);
+    dg_status st = check_dev_mesh(mc, (hipStream_t)stream);
     if (st) return st;
     if ((st = check_phys(phys))) return st;
     if (!qs || !out) return fail(DG_EINVAL, "NULL field pointer");
@@ -515,9 +574,9 @@ dg_status dg_rk_stage(const dg_mesh* m, const dg_phys* phys, double a, double b,
 
 static dg_status xfer_common(const dg_mesh* from, const dg_mesh* to, const double* qin, double* qout,
                              void* stream, bool refine, bool adjoint) {
-    dg_status st = check_dev_mesh(from);
+    dg_status st = check_dev_mesh(from, (hipStream_t)stream);
     if (st) return st;
-    if ((st = check_dev_mesh(to))) return st;
+    if ((st = check_dev_mesh(to, (hipStream_t)stream))) return st;
     if (to->prev_id != from->id) return fail(DG_EINVAL, "`to` was not built from `from`");
     if (!qin || !qout) return fail(DG_EINVAL, "NULL field pointer");
     if (qin == qout) return fail(DG_EINVAL, "input and output fields must not alias");
@@ -556,7 +615,7 @@ dg_status dg_coarsen_project_adjoint(const dg_mesh* from, const dg_mesh* to, con
 static dg_status adjoint_common(const dg_mesh* mc, const dg_phys* phys, int mode, double a1, const double* w1,
                                 double a2, const double* w2, double b, double dt, const double* q, const double* lam,
                                 double* out, void* stream) {
-    dg_status st = check_dev_mesh(mc);
+    dg_status st = check_dev_mesh(mc, (hipStream_t)stream);
     if (st) return st;
     if ((st = check_phys(phys))) return st;
     if (phys->nonconforming != DG_NC_MORTAR)
@@ -607,6 +666,19 @@ dg_status dg_rk_stage_adjoint(const dg_mesh* m, const dg_phys* phys, double a1, 
     return adjoint_common(m, phys, MODE_RK, a1, w1, a2, w2, b, dt, q, y, out, stream);
 }
 
+dg_status dg_flags_after_coarsen(const dg_mesh* mc, const int8_t* flags, int8_t* flags_out) {
+    if (!mc || !flags || !flags_out) return fail(DG_EINVAL, "NULL argument");
+    const HostMesh& h = mc->h;
+    const int64_t K = (int64_t)h.leaves.size();
+    const int64_t Kp = mc->prev ? (int64_t)mc->prev->h.leaves.size() : K;
+    for (int64_t e = 0; e < K; ++e) {
+        const int32_t src = h.xfer_src[e];
+        if (src < 0 || src >= Kp) return fail(DG_EINVAL, "transfer plan out of range");
+        flags_out[e] = (h.xfer_kind[e] == DG_KIND_COPY && flags[src] > 0) ? 1 : 0;
+    }
+    return DG_OK;
+}
+
 dg_status dg_flags_buffer(const dg_mesh* m, int8_t* flags, int32_t B) {
     if (!m || !flags) return fail(DG_EINVAL, "NULL argument");
     if (B < 0) return fail(DG_EINVAL, "B must be >= 0");
@@ -635,7 +707,7 @@ dg_status dg_fma_burst(int32_t blocks, int32_t iters, double* sink, double* flop
 }
 
 dg_status dg_budgets(const dg_mesh* mc, const dg_phys* phys, const double* q, double* out_host, void* stream) {
-    dg_status st = check_dev_mesh(mc);
+    dg_status st = check_dev_mesh(mc, (hipStream_t)stream);
     if (st) return st;
     if ((st = check_phys(phys))) return st;
     if (!q || !out_host) return fail(DG_EINVAL, "NULL argument");
@@ -663,7 +735,10 @@ dg_status dg_budgets_noalloc(const dg_mesh* mc, const dg_phys* phys, const doubl
     // already has them
     if (!mc->on_device)
         return fail(DG_EINVAL, "mesh has no device tables yet (any other field call on it makes them)");
-    dg_status st = check_phys(phys);
+    // the tables exist: this only orders the call after their upload (no allocation)
+    dg_status st = check_dev_mesh(mc, (hipStream_t)stream);
+    if (st) return st;
+    st = check_phys(phys);
     if (st) return st;
     if (!q || !out_dev) return fail(DG_EINVAL, "NULL argument");
     int cur = 0;
@@ -687,7 +762,7 @@ dg_status dg_budgets_noalloc(const dg_mesh* mc, const dg_phys* phys, const doubl
 
 dg_status dg_indicator(const dg_mesh* mc, const dg_phys* phys, const double* q, int32_t kind, double thr,
                        double* eta, int8_t* flags_host, void* stream) {
-    dg_status st = check_dev_mesh(mc);
+    dg_status st = check_dev_mesh(mc, (hipStream_t)stream);
     if (st) return st;
     if ((st = check_phys(phys))) return st;
     if (!q || !flags_host) return fail(DG_EINVAL, "NULL argument");
@@ -706,7 +781,7 @@ dg_status dg_indicator(const dg_mesh* mc, const dg_phys* phys, const double* q, 
 
 dg_status dg_indicator_async(const dg_mesh* mc, const dg_phys* phys, const double* q, int32_t kind, double thr,
                              double* eta, int8_t* flags_dev, void* stream) {
-    dg_status st = check_dev_mesh(mc);
+    dg_status st = check_dev_mesh(mc, (hipStream_t)stream);
     if (st) return st;
     if ((st = check_phys(phys))) return st;
     if (!q || !flags_dev) return fail(DG_EINVAL, "NULL argument");

@@ -4,8 +4,11 @@
 // and transfer tables the kernels need.  Host-side integer work.
 //
 // Ordering and balance rules (the paper fixes none of them):
-//   * leaves sorted by (root, Morton key of the anchor scaled to max_level),
-//     x the least significant bit; child id c = a + 2b + 4c';
+//   * leaves sorted by (rank of the root along a Morton curve over the root
+//     coordinates, Morton key of the anchor scaled to max_level), x the least
+//     significant bit in both; child id c = a + 2b + 4c' (the whole brick is
+//     one space-filling curve, so face neighbours sit close together in memory
+//     along every axis);
 //   * refine pass: +1 flags below max_level, then refine every leaf with a face
 //     neighbour two or more levels finer until nothing changes;
 //   * coarsen pass: a family of 8 leaves all flagged -1 merges unless a leaf
@@ -22,14 +25,43 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
 
 #include "internal.hpp"
 
 namespace dgamr {
 namespace {
 
-// position key of a cell's lower corner: root (24 bits) | Morton key at max_level (36 bits)
-uint64_t pos_key(int L, const Leaf& c) {
+// rank of every root along the Morton curve over the root coordinates (bits of
+// rx, ry, rz interleaved, rx the least significant); cached per brick shape
+std::shared_ptr<const std::vector<uint32_t>> root_ranks(const dg_forest_desc& d) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int>, std::shared_ptr<const std::vector<uint32_t>>> cache;
+    const auto shape = std::make_tuple(d.nx, d.ny, d.nz);
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(shape);
+    if (it != cache.end()) return it->second;
+    const int64_t n = (int64_t)d.nx * d.ny * d.nz;
+    std::vector<std::pair<uint64_t, uint32_t>> kv((size_t)n);
+    for (int64_t r = 0; r < n; ++r) {
+        const uint64_t rc[3] = {(uint64_t)(r % d.nx), (uint64_t)((r / d.nx) % d.ny), (uint64_t)(r / ((int64_t)d.nx * d.ny))};
+        uint64_t k = 0;
+        for (int b = 0; b < 21; ++b)
+            for (int a = 0; a < 3; ++a) k |= ((rc[a] >> b) & 1ull) << (3 * b + a);
+        kv[(size_t)r] = {k, (uint32_t)r};
+    }
+    std::sort(kv.begin(), kv.end());
+    auto rank = std::make_shared<std::vector<uint32_t>>((size_t)n);
+    for (int64_t i = 0; i < n; ++i) (*rank)[kv[(size_t)i].second] = (uint32_t)i;
+    cache.emplace(shape, rank);
+    return rank;
+}
+
+// position key of a cell's lower corner: root rank (24 bits) | Morton key at max_level (36 bits)
+uint64_t pos_key(const uint32_t* rank, int L, const Leaf& c) {
     const uint64_t X = (uint64_t)c.a[0] << (L - c.l), Y = (uint64_t)c.a[1] << (L - c.l),
                    Z = (uint64_t)c.a[2] << (L - c.l);
     uint64_t k = 0;
@@ -38,7 +70,7 @@ uint64_t pos_key(int L, const Leaf& c) {
         k |= ((Y >> b) & 1ull) << (3 * b + 1);
         k |= ((Z >> b) & 1ull) << (3 * b + 2);
     }
-    return ((uint64_t)c.r << 36) | k;
+    return ((uint64_t)rank[c.r] << 36) | k;
 }
 
 Leaf parent_of(const Leaf& c) {
@@ -68,47 +100,122 @@ bool contains(const Leaf& x, const Leaf& c) {
     return (c.a[0] >> sh) == x.a[0] && (c.a[1] >> sh) == x.a[1] && (c.a[2] >> sh) == x.a[2];
 }
 
-// sorted leaf array with its keys
+// sorted leaf array with its keys: the leaves of a mesh are stored in this order
+// already and are used in place; any other sequence is sorted into an owned copy
 struct Sorted {
     const dg_forest_desc& desc;
     int L;
-    std::vector<Leaf> leaves;
+    std::shared_ptr<const std::vector<uint32_t>> rank_hold;
+    const uint32_t* rank;
+    std::vector<Leaf> own;
+    const std::vector<Leaf>* lv = nullptr;
     std::vector<uint64_t> keys;
 
-    Sorted(const dg_forest_desc& d, std::vector<Leaf> v) : desc(d), L(d.max_level), leaves(std::move(v)) {
-        keys.resize(leaves.size());
+    Sorted(const dg_forest_desc& d, const std::vector<Leaf>& v)
+        : desc(d), L(d.max_level), rank_hold(root_ranks(d)), rank(rank_hold->data()) {
+        if (!key_in_place(v)) sort_copy(v);
+    }
+    Sorted(const dg_forest_desc& d, std::vector<Leaf>&& v)
+        : desc(d), L(d.max_level), rank_hold(root_ranks(d)), rank(rank_hold->data()) {
+        own = std::move(v);
+        if (!key_in_place(own)) sort_copy(own);
+    }
+    const std::vector<Leaf>& leaves() const { return *lv; }
+    // the sorted leaves, moved out when owned
+    std::vector<Leaf> take() {
+        if (lv == &own) return std::move(own);
+        return *lv;
+    }
+
+  private:
+    bool key_in_place(const std::vector<Leaf>& v) {
+        keys.resize(v.size());
         bool sorted = true;
-        for (size_t i = 0; i < leaves.size(); ++i) {
-            keys[i] = pos_key(L, leaves[i]);
+        for (size_t i = 0; i < v.size(); ++i) {
+            keys[i] = pos_key(rank, L, v[i]);
             sorted = sorted && (i == 0 || keys[i - 1] < keys[i]);
         }
-        if (sorted) return;  // a mesh's own leaves are stored in this order
-        std::vector<std::pair<uint64_t, Leaf>> kv(leaves.size());
-        for (size_t i = 0; i < leaves.size(); ++i) kv[i] = {pos_key(L, leaves[i]), leaves[i]};
+        if (sorted) lv = &v;
+        return sorted;
+    }
+    void sort_copy(const std::vector<Leaf>& v) {
+        std::vector<std::pair<uint64_t, Leaf>> kv(v.size());
+        for (size_t i = 0; i < v.size(); ++i) kv[i] = {keys[i], v[i]};
         std::sort(kv.begin(), kv.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
-        keys.resize(kv.size());
+        std::vector<Leaf> sorted(kv.size());
         for (size_t i = 0; i < kv.size(); ++i) {
             keys[i] = kv[i].first;
-            leaves[i] = kv[i].second;
+            sorted[i] = kv[i].second;
         }
+        own = std::move(sorted);
+        lv = &own;
+    }
+
+  public:
+    // first index in [0, n) whose key exceeds k (upper) or is not below k (!upper),
+    // searched by galloping out from `hint`: face neighbours lie close together on
+    // the space-filling curve, so the bracket is usually a few entries wide
+    size_t gallop(uint64_t k, size_t hint, bool upper) const {
+        const size_t n = keys.size();
+        auto before = [&](size_t i) { return upper ? keys[i] <= k : keys[i] < k; };
+        size_t lo, hi;  // answer in (lo, hi]: before(lo) holds (or lo = npos), before(hi) fails (or hi = n)
+        if (hint >= n) hint = n ? n - 1 : 0;
+        if (n == 0) return 0;
+        if (before(hint)) {
+            size_t step = 1;
+            lo = hint;
+            hi = hint + 1;
+            while (hi < n && before(hi)) {
+                lo = hi;
+                step <<= 1;
+                hi = lo + step < n ? lo + step : n;
+            }
+            ++lo;
+        } else {
+            size_t step = 1;
+            hi = hint;
+            size_t cand = hint;
+            for (;;) {
+                if (cand == 0) {
+                    lo = 0;
+                    break;
+                }
+                const size_t nxt = cand >= step ? cand - step : 0;
+                if (before(nxt)) {
+                    lo = nxt + 1;
+                    break;
+                }
+                hi = nxt;
+                cand = nxt;
+                step <<= 1;
+            }
+        }
+        // binary search in [lo, hi)
+        while (lo < hi) {
+            const size_t mid = lo + (hi - lo) / 2;
+            if (before(mid))
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        return lo;
     }
 
     // index of the leaf equal to or containing cell c, or -1 if c is refined
-    int containing(const Leaf& c) const {
-        const uint64_t k = pos_key(L, c);
-        auto it = std::upper_bound(keys.begin(), keys.end(), k);
-        if (it == keys.begin()) return -1;
-        const int i = (int)(it - keys.begin()) - 1;
-        return contains(leaves[i], c) ? i : -1;
+    int containing(const Leaf& c, size_t hint = 0) const {
+        const uint64_t k = pos_key(rank, L, c);
+        const size_t it = gallop(k, hint, true);
+        if (it == 0) return -1;
+        const int i = (int)it - 1;
+        return contains((*lv)[i], c) ? i : -1;
     }
 
     // index of the leaf equal to cell c, or -1
-    int find(const Leaf& c) const {
-        const uint64_t k = pos_key(L, c);
-        auto it = std::lower_bound(keys.begin(), keys.end(), k);
-        if (it == keys.end() || *it != k) return -1;
-        const int i = (int)(it - keys.begin());
-        return leaves[i].l == c.l ? i : -1;
+    int find(const Leaf& c, size_t hint = 0) const {
+        const uint64_t k = pos_key(rank, L, c);
+        const size_t i = gallop(k, hint, false);
+        if (i == keys.size() || keys[i] != k) return -1;
+        return (*lv)[i].l == c.l ? (int)i : -1;
     }
 
     // same-level cell across face f = 2d + s; false at a wall
@@ -165,7 +272,8 @@ std::string forest_uniform(const dg_forest_desc& desc, HostMesh& out) {
     out.desc = desc;
     const int nr = desc.nx * desc.ny * desc.nz;
     out.leaves.resize(nr);
-    for (int r = 0; r < nr; ++r) out.leaves[r] = Leaf{r, 0, {0, 0, 0}};
+    const auto rank = root_ranks(desc);
+    for (int r = 0; r < nr; ++r) out.leaves[(*rank)[r]] = Leaf{r, 0, {0, 0, 0}};
     out.xfer_src.resize(nr);
     out.xfer_kind.assign(nr, DG_KIND_COPY);
     for (int r = 0; r < nr; ++r) out.xfer_src[r] = r;
@@ -205,18 +313,18 @@ std::string forest_refine(const HostMesh& prev, const int8_t* flags, HostMesh& o
     // ripple: refine leaves that have a face neighbour two or more levels finer
     for (;;) {
         Sorted S(desc, std::move(cur));
-        std::vector<char> todo(S.leaves.size(), 0);
+        std::vector<char> todo(S.leaves().size(), 0);
         int any = 0;
-        const int64_t nl = (int64_t)S.leaves.size();
+        const int64_t nl = (int64_t)S.leaves().size();
 #pragma omp parallel for schedule(static) reduction(| : any)
         for (int64_t zi = 0; zi < nl; ++zi) {
-            const Leaf& z = S.leaves[zi];
+            const Leaf& z = S.leaves()[zi];
             if (z.l < 2) continue;
             for (int f = 0; f < 6; ++f) {
                 Leaf c;
                 if (!S.neighbor(z, f, c)) continue;
-                const int x = S.containing(c);
-                if (x >= 0 && S.leaves[x].l <= z.l - 2) {
+                const int x = S.containing(c, (size_t)zi);
+                if (x >= 0 && S.leaves()[x].l <= z.l - 2) {
 #pragma omp atomic write
                     todo[x] = 1;
                     any = 1;
@@ -224,12 +332,12 @@ std::string forest_refine(const HostMesh& prev, const int8_t* flags, HostMesh& o
             }
         }
         if (!any) {
-            cur = std::move(S.leaves);
+            cur = S.take();
             break;
         }
         cur.clear();
-        for (size_t i = 0; i < S.leaves.size(); ++i) {
-            const Leaf& z = S.leaves[i];
+        for (size_t i = 0; i < S.leaves().size(); ++i) {
+            const Leaf& z = S.leaves()[i];
             if (!todo[i]) {
                 cur.push_back(z);
                 continue;
@@ -250,12 +358,14 @@ std::string forest_refine(const HostMesh& prev, const int8_t* flags, HostMesh& o
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (int64_t e = 0; e < (int64_t)K; ++e) {
         const Leaf& lf = out.leaves[e];
-        const int old = P.find(lf);
+        // an old leaf kept or refined sits near position e * K_prev / K of the new order
+        const size_t hint = (size_t)((double)e * (double)P.leaves().size() / (double)K);
+        const int old = P.find(lf, hint);
         if (old >= 0) {
             out.xfer_src[e] = old;
             out.xfer_kind[e] = DG_KIND_COPY;
         } else {
-            const int ip = P.find(parent_of(lf));
+            const int ip = P.find(parent_of(lf), hint);
             if (ip < 0) {
                 bad = 1;
                 continue;
@@ -277,40 +387,36 @@ std::string forest_refine(const HostMesh& prev, const int8_t* flags, HostMesh& o
 static int64_t coarsen_families(const HostMesh& prev, const int8_t* flags, std::vector<char>& merge) {
     const dg_forest_desc& desc = prev.desc;
     Sorted P(desc, prev.leaves);
-    const size_t K0 = P.leaves.size();
+    const size_t K0 = P.leaves().size();
     // candidate families: 8 consecutive leaves (Morton order keeps a family
-    // contiguous) that are the 8 children of one parent, all flagged -1
+    // contiguous) that are the 8 children of one parent, all flagged -1; a family
+    // starts at a child 0, so two candidates never overlap and each is judged on
+    // its own (in parallel)
     merge.assign(K0, 0);
+    const std::vector<Leaf>& lv = P.leaves();
     int64_t nmerged = 0;
-    for (size_t e = 0; e + 8 <= K0;) {
-        const Leaf& lf = P.leaves[e];
-        if (lf.l == 0 || child_id_of(lf) != 0) {
-            ++e;
-            continue;
-        }
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : nmerged)
+    for (int64_t e = 0; e <= (int64_t)K0 - 8; ++e) {
+        const Leaf& lf = lv[e];
+        if (lf.l == 0 || child_id_of(lf) != 0 || flags[e] >= 0) continue;
         const Leaf p = parent_of(lf);
         bool fam = true;
-        for (int c = 0; c < 8 && fam; ++c)
-            fam = same_cell(P.leaves[e + c], child_of(p, c)) && flags[e + c] < 0;
-        if (!fam) {
-            ++e;
-            continue;
-        }
+        for (int c = 0; c < 8 && fam; ++c) fam = same_cell(lv[e + c], child_of(p, c)) && flags[e + c] < 0;
+        if (!fam) continue;
         bool veto = false;
         for (int f = 0; f < 6 && !veto; ++f) {
             Leaf c;
             if (!P.neighbor(p, f, c)) continue;
-            if (P.containing(c) >= 0) continue;  // neighbour leaf no finer than the parent
+            if (P.containing(c, (size_t)e) >= 0) continue;  // neighbour leaf no finer than the parent
             Leaf fc[4];
             face_children(c, f >> 1, 1 - (f & 1), fc);
             for (int q = 0; q < 4; ++q)
-                if (P.find(fc[q]) < 0) veto = true;
+                if (P.find(fc[q], (size_t)e) < 0) veto = true;
         }
         if (!veto) {
             merge[e] = 1;
             ++nmerged;
         }
-        e += 8;
     }
     return nmerged;
 }
@@ -362,8 +468,12 @@ std::string forest_coarsen(const HostMesh& prev, const int8_t* flags, HostMesh& 
 
 void forest_tables(HostMesh& m) {
     const dg_forest_desc& desc = m.desc;
-    Sorted S(desc, m.leaves);
-    m.leaves = S.leaves;  // canonical order
+    std::unique_ptr<Sorted> Sp(new Sorted(desc, m.leaves));
+    if (Sp->lv != &m.leaves) {  // into canonical order, then index it in place
+        m.leaves = Sp->take();
+        Sp.reset(new Sorted(desc, m.leaves));
+    }
+    const Sorted& S = *Sp;
     const int64_t K = (int64_t)m.leaves.size();
     m.ftype.assign(K * 6, -1);
     m.fnb.assign(K * 24, -1);
@@ -378,9 +488,9 @@ void forest_tables(HostMesh& m) {
                 m.ftype[e * 6 + f] = FT_WALL;
                 continue;
             }
-            const int x = S.containing(c);
+            const int x = S.containing(c, (size_t)e);
             if (x >= 0) {
-                if (S.leaves[x].l == lf.l) {
+                if (S.leaves()[x].l == lf.l) {
                     const int rz = lf.r / (desc.nx * desc.ny);
                     const bool wrap_z = d == 2 && (s ? rz == desc.nz - 1 && lf.a[2] == (1 << lf.l) - 1
                                                      : rz == 0 && lf.a[2] == 0);
@@ -396,14 +506,24 @@ void forest_tables(HostMesh& m) {
                 Leaf fc[4];
                 face_children(c, d, 1 - s, fc);
                 m.ftype[e * 6 + f] = FT_COARSE;
-                for (int q = 0; q < 4; ++q) m.fnb[(e * 6 + f) * 4 + q] = S.find(fc[q]);  // leaves, by balance
+                for (int q = 0; q < 4; ++q) m.fnb[(e * 6 + f) * 4 + q] = S.find(fc[q], (size_t)e);  // leaves, by balance
             }
         }
     }
-    // the global lists in (leaf, face) order
+    // the global lists in (leaf, face) order, sized first
+    int64_t nconf = 0, nbnd = 0, nhang = 0;
+    for (int64_t i = 0; i < K * 6; ++i) {
+        const int type = m.ftype[i] & 0xff;
+        nconf += type == FT_CONF && (i % 6) % 2 == 1;
+        nbnd += type == FT_WALL;
+        nhang += type == FT_COARSE;
+    }
     m.conf.clear();
     m.bnd.clear();
     m.hang.clear();
+    m.conf.reserve(3 * nconf);
+    m.bnd.reserve(2 * nbnd);
+    m.hang.reserve(6 * nhang);
     for (int64_t e = 0; e < K; ++e)
         for (int f = 0; f < 6; ++f) {
             const int type = m.ftype[e * 6 + f] & 0xff;

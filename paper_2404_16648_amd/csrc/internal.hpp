@@ -58,6 +58,10 @@ struct dg_mesh {
     uint64_t id = 0, prev_id = 0;
     std::atomic<bool> on_device{false};  // device tables made (at first GPU use)
     int device = 0;
+    // the asynchronous upload of the device tables: until its event has completed,
+    // a call on another stream than upload_stream waits for it
+    void* upload_done = nullptr;    // hipEvent_t
+    void* upload_stream = nullptr;  // hipStream_t
     char* d_base = nullptr;       // the one device allocation holding everything below
     // device tables
     double* d_ops = nullptr;      // D, I0, I1, R0, R1 ([N1][N1] each), w [N1]

@@ -39,7 +39,7 @@ DG_KIND_FAMILY = 8
 EXPORTED = [
     "dg_mesh_build", "dg_mesh_free", "dg_mesh_info_get", "dg_mesh_export", "dg_node_coords",
     "dg_init_bell", "dg_rhs", "dg_rk_stage", "dg_refine_project", "dg_coarsen_project",
-    "dg_refine_project_adjoint", "dg_coarsen_project_adjoint", "dg_rhs_adjoint", "dg_rk_stage_adjoint", "dg_budgets", "dg_budgets_noalloc", "dg_indicator", "dg_indicator_async", "dg_pass_changes", "dg_flags_buffer", "dg_fma_burst", "dg_last_error",
+    "dg_refine_project_adjoint", "dg_coarsen_project_adjoint", "dg_rhs_adjoint", "dg_rk_stage_adjoint", "dg_budgets", "dg_budgets_noalloc", "dg_indicator", "dg_indicator_async", "dg_pass_changes", "dg_flags_after_coarsen", "dg_flags_buffer", "dg_fma_burst", "dg_last_error",
 ]
 
 
@@ -107,6 +107,7 @@ def lib():
         L.dg_budgets_noalloc.argtypes = [P, C.POINTER(Phys), P, P, P]
         L.dg_fma_burst.argtypes = [C.c_int32, C.c_int32, P, P, P]
         L.dg_flags_buffer.argtypes = [P, P, C.c_int32]
+        L.dg_flags_after_coarsen.argtypes = [P, P, P]
         L.dg_indicator.argtypes = [P, C.POINTER(Phys), P, C.c_int32, C.c_double, P, P, P]
         L.dg_indicator_async.argtypes = [P, C.POINTER(Phys), P, C.c_int32, C.c_double, P, P, P]
         L.dg_pass_changes.argtypes = [P, P, C.c_int32, C.POINTER(C.c_int32)]
@@ -315,6 +316,16 @@ def dg_rk_stage_adjoint(mesh: Mesh, phys: PhysParams, a1, w1, a2, w2, b, dt, q, 
                                      _ptr(y), _ptr(out), _stream(stream)))
 
 
+def dg_flags_after_coarsen(coarsened: Mesh, flags):
+    """Refine-pass flags on `coarsened` from the cycle's flags on the mesh its
+    coarsen pass started from (a new array)."""
+    fl = np.ascontiguousarray(np.asarray(flags, dtype=np.int8))
+    out = np.zeros(coarsened.K, dtype=np.int8)
+    _check(lib().dg_flags_after_coarsen(coarsened.handle, C.c_void_p(fl.ctypes.data),
+                                        C.c_void_p(out.ctypes.data) if coarsened.K else None))
+    return out
+
+
 def dg_flags_buffer(mesh: Mesh, flags, B):
     """Buffer zone: B rounds of face-neighbour dilation of the +1 flags (returns a new array)."""
     fl = np.ascontiguousarray(np.asarray(flags, dtype=np.int8)).copy()
@@ -402,11 +413,9 @@ def adapt_meshes_from_flags(mesh: Mesh, flags, buffer=0):
     mc = mesh
     if dg_pass_changes(mesh, flags, DG_PASS_COARSEN):
         mc = dg_mesh_build(prev=mesh, flags=flags, pass_=DG_PASS_COARSEN)
-        t = mc.tables()
-        fl2 = np.where(t["xfer_kind"] == DG_KIND_COPY, flags[t["xfer_src"]], 0).astype(np.int8)
+        fl2 = dg_flags_after_coarsen(mc, flags)
     else:
-        fl2 = np.array(flags, dtype=np.int8)  # identity transfer plan: the flags index the same leaves
-    fl2[fl2 < 0] = 0
+        fl2 = np.where(np.asarray(flags) > 0, 1, 0).astype(np.int8)  # the same leaves
     mr = mc
     if dg_pass_changes(mc, fl2, DG_PASS_REFINE):
         mr = dg_mesh_build(prev=mc, flags=fl2, pass_=DG_PASS_REFINE)
