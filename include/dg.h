@@ -143,8 +143,12 @@ typedef struct {
     double radius[3];
 } dg_bell;
 
-/* Build a mesh.  prev == NULL: uniform level-0 forest from desc (flags, pass
- * ignored).  Otherwise one pass over prev (desc is taken from prev and the
+/* Build a mesh (section 3.1: every root hex is a tree and only leaves are kept,
+ * flagged leaves replaced by their children or merged into their parent;
+ * section 4.3: 2:1 balance; the leaf order, balance algorithm and table formats
+ * are not in the paper: leaves follow one Morton curve over the brick, roots in
+ * Morton order of their coordinates, then the Morton order inside the root).
+ * prev == NULL: uniform level-0 forest from desc (flags, pass ignored).  Otherwise one pass over prev (desc is taken from prev and the
  * argument may be NULL): DG_PASS_REFINE applies the +1 flags of `flags` (host
  * int8[K(prev)]) to leaves below max_level and then refines every leaf that
  * has a face neighbour two or more levels finer, to a fixed point (2:1 face
@@ -165,15 +169,28 @@ dg_status dg_mesh_build(const dg_forest_desc* desc, const dg_mesh* prev, const i
  * unknown pass. */
 dg_status dg_pass_changes(const dg_mesh* mesh, const int8_t* flags, int32_t pass, int32_t* changes);
 
+/* Release a mesh handle with its host tables and device block (not in the
+ * paper; handle management).  NULL is accepted.  Work still enqueued on the
+ * mesh must have completed (the device block is freed). */
 dg_status dg_mesh_free(dg_mesh* mesh);
+/* Sizes of a mesh (not in the paper): leaves, nodes per leaf, face counts and the
+ * pass that built it; host only.  DG_EINVAL on a NULL argument. */
 dg_status dg_mesh_info_get(const dg_mesh* mesh, dg_mesh_info* info);
+/* Host copies of the integer tables into caller-owned arrays sized from
+ * dg_mesh_info (the tables of section 3.1's forest, formats not in the paper);
+ * host only.  DG_EINVAL on a NULL argument. */
 dg_status dg_mesh_export(const dg_mesh* mesh, const dg_mesh_tables* tables);
 
-/* Node coordinates xyz[3][K][Np] (device, float64):
- * x = lo + (hi-lo)/n * (r + (anchor + (1 + xi)/2) / 2^level) per axis. */
+/* Node coordinates xyz[3][K][Np] (device, float64, caller-owned) of the LGL
+ * nodes (section 2.2 nodal dGSEM; the mapping of a brick leaf is not in the
+ * paper): x = lo + (hi-lo)/n * (r + (anchor + (1 + xi)/2) / 2^level) per axis,
+ * in this association so that two leaves sharing a face give bitwise-identical
+ * coordinates there.  Enqueued on stream.  DG_EINVAL on a NULL argument. */
 dg_status dg_node_coords(const dg_mesh* mesh, double* xyz, void* stream);
 
-/* q (device [5][K][Np]) := cosine-bell perturbation described by *bell. */
+/* q (device [5][K][Np], caller-owned) := the cosine-bell perturbation described
+ * by *bell about phys's background (sections 4.2 and 4.3; see dg_bell).
+ * Enqueued on stream.  DG_EINVAL on a NULL argument or bad phys. */
 dg_status dg_init_bell(const dg_mesh* mesh, const dg_phys* phys, const dg_bell* bell, double* q,
                        void* stream);
 
@@ -182,7 +199,9 @@ dg_status dg_init_bell(const dg_mesh* mesh, const dg_phys* phys, const dg_bell* 
  * with F the Euler flux carrying the pressure perturbation P', S the buoyancy
  * -rho' g on rho*w, F* the Rusanov flux (local max wave speed, jump of the
  * perturbation variables), mirror states at walls and L2 mortars on hanging
- * faces (section 3.3).  rhs must not alias q.  The mortars are evaluated by a
+ * faces (section 3.3).  rhs must not alias q.  A mesh periodic along z needs
+ * a background constant in z (g = 0 or DG_BG_CONSTANT; a hydrostatic profile
+ * cannot be periodic), else DG_EINVAL (also for the stage and adjoint calls).  The mortars are evaluated by a
  * pre-pass into a workspace owned by the mesh, so calls of dg_rhs,
  * dg_rk_stage, dg_rhs_adjoint and dg_rk_stage_adjoint on one mesh must be
  * ordered (one stream, or synchronised); concurrent calls on different meshes
@@ -190,9 +209,13 @@ dg_status dg_init_bell(const dg_mesh* mesh, const dg_phys* phys, const dg_bell* 
 dg_status dg_rhs(const dg_mesh* mesh, const dg_phys* phys, const double* q, double* rhs,
                  void* stream);
 
-/* One Shu-Osher stage: qout := a*q0 + b*(qs + dt*R(qs)).  SSP-RK3 uses
- * (a,b) = (0,1), (3/4,1/4), (1/3,2/3).  qout may alias q0 but not qs; q0 is
- * not read when a == 0. */
+/* One Shu-Osher stage: qout := a*q0 + b*(qs + dt*R(qs)), with R as in dg_rhs
+ * (sections 2.2 and 3.3) fused into the update; the paper integrates with an
+ * explicit Runge-Kutta scheme, SSP-RK3 (not named in the paper) uses
+ * (a,b) = (0,1), (3/4,1/4), (1/3,2/3).  Device fields [5][K][Np]; qout may
+ * alias q0 but not qs; q0 is not read when a == 0.  Enqueued on stream (mortar
+ * pre-pass, then the fused kernel).  DG_EINVAL on NULL or aliased fields or bad
+ * phys. */
 dg_status dg_rk_stage(const dg_mesh* mesh, const dg_phys* phys, double a, double b, double dt,
                       const double* q0, const double* qs, double* qout, void* stream);
 
@@ -222,7 +245,8 @@ dg_status dg_refine_project_adjoint(const dg_mesh* from, const dg_mesh* to, cons
 dg_status dg_coarsen_project_adjoint(const dg_mesh* from, const dg_mesh* to, const double* qbar_to,
                                      double* qbar_from, void* stream);
 
-/* qbar := (dR/dq)^T lam, the exact transpose of the linearised right-hand side
+/* Not in the paper (the discrete adjoint of section 2.2's right-hand side):
+ * qbar := (dR/dq)^T lam, the exact transpose of the linearised right-hand side
  * in the Euclidean inner product on the DOF vector (d|x|/dx := 0 at 0, a max
  * tie splits the derivative 1/2, 1/2).  qbar must not alias q or lam.  With
  * phys->precision == DG_MIXED the transposed volume contractions D^T lam run in
@@ -247,10 +271,14 @@ dg_status dg_rk_stage_adjoint(const dg_mesh* mesh, const dg_phys* phys, double a
                               const double* w2, double b, double dt, const double* q, const double* y, double* out,
                               void* stream);
 
-/* Budgets over the mesh with weights J_e W_n = (hx hy hz / 8) w_i w_j w_k:
+/* Mass and energy budgets (section 2.1: mass is conserved discretely, energy
+ * is not; section 4.3 reports both losses; the energy density is not in the
+ * paper), over the mesh with weights J_e W_n = (hx hy hz / 8) w_i w_j w_k:
  * out_host[0] = sum rho', [1] = sum (rhobar + rho'), [2] = sum Theta',
  * [3] = sum P/(gamma-1) + |U|^2/(2 rho) + rho g z.  Compensated float64
- * summation in a fixed order (deterministic).  Synchronises the stream. */
+ * summation in a fixed order (deterministic).  q is device [5][K][Np];
+ * out_host is host double[4].  Synchronises the stream; DG_ENONFINITE when a
+ * budget is not finite, DG_EINVAL on a NULL argument. */
 dg_status dg_budgets(const dg_mesh* mesh, const dg_phys* phys, const double* q, double* out_host,
                      void* stream);
 
@@ -271,10 +299,13 @@ dg_status dg_budgets(const dg_mesh* mesh, const dg_phys* phys, const double* q, 
 dg_status dg_budgets_noalloc(const dg_mesh* mesh, const dg_phys* phys, const double* q, double* out_dev,
                              void* stream);
 
-/* Adaptation indicator: eta (device double[K], may be NULL) and flags (host
- * int8[K]): +1 where eta > thr and level < max_level, -1 where eta <= thr and
- * level > 0, else 0.  kind is DG_IND_THETA or DG_IND_GRAD_THETA.
- * Synchronises the stream. */
+/* Adaptation indicator (section 3.2: regrid from a criterion every T steps;
+ * section 4.3: the potential temperature as the criterion; the two measures and
+ * the flag rule are not in the paper): eta_e = max over the leaf's nodes of
+ * |theta'| (DG_IND_THETA) or |grad theta| (DG_IND_GRAD_THETA), into eta (device
+ * double[K], may be NULL), and flags (host int8[K]): +1 where eta > thr and
+ * level < max_level, -1 where eta <= thr and level > 0, else 0.  Synchronises
+ * the stream.  DG_EINVAL on a NULL q or flags_host or an unknown kind. */
 dg_status dg_indicator(const dg_mesh* mesh, const dg_phys* phys, const double* q, int32_t kind,
                        double thr, double* eta, int8_t* flags_host, void* stream);
 
@@ -298,7 +329,7 @@ dg_status dg_indicator_async(const dg_mesh* mesh, const dg_phys* phys, const dou
  * NULL argument or a transfer plan out of range. */
 dg_status dg_flags_after_coarsen(const dg_mesh* coarsened, const int8_t* flags, int8_t* flags_out);
 
-/* Buffer zone around refinement (section 3.2: at least B coarse cells between a
+/* Buffer zone around refinement (section 3.2: a margin of B coarse cells between a
  * feature and the coarse-fine interface, the same B in the tree-based code).
  * Reading: B rounds of face-neighbour dilation of the +1 flags, in place on the
  * host array flags (int8[K], as from dg_indicator): in each round every leaf

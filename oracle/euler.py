@@ -14,7 +14,7 @@ Plain PyTorch CPU float64 code written from the paper's statements:
 * Rusanov flux (section 2.2): F* = {F} + n |c|/2 [[q]].
 * Mortars (section 3.3): the coarse face trace is projected onto the two
   half-interval mortars per tangential axis (the fine side projection is the
-  identity), the Riemann problem is solved on the mortars and the flux is
+  identity), the Rusanov flux is evaluated at the mortar points and it is
   projected back with sum_i s_i M^{-1} S^T, s_i = 1/2 per axis.
 * Pointwise matching (section 3.3, the simpler alternative the paper compares
   the mortars with; ``Operator(..., nonconforming="pointwise")``): each side
@@ -220,6 +220,9 @@ class Operator:
     def __init__(self, mesh: fo.Mesh, phys: Phys, nonconforming: str = "mortar"):
         if nonconforming not in ("mortar", "pointwise"):
             raise ValueError("nonconforming must be 'mortar' or 'pointwise'")
+        # a hydrostatic background that varies with z cannot be periodic in z
+        if mesh.desc.periodic[2] and phys.background == BG_NEUTRAL and phys.g != 0.0:
+            raise ValueError("a periodic z axis needs a background constant in z (g = 0 or BG_CONSTANT)")
         self.mesh, self.phys = mesh, phys
         self.nonconforming = nonconforming
         N = mesh.N

@@ -375,7 +375,7 @@ def leaf_boxes(mesh: Mesh):
 
 
 def buffer_flags(mesh: Mesh, flags, B: int):
-    """Buffer zone around refinement (section 3.2: at least B coarse cells between a
+    """Buffer zone around refinement (section 3.2: a margin of B coarse cells between a
     feature and the coarse-fine interface; the tree-based code uses the same B).
     Reading: B rounds of face-neighbour dilation of the +1 flags; in each round
     every leaf that shares a face with a leaf flagged +1 is flagged +1 (0 and -1

@@ -337,6 +337,15 @@ dg_status check_dev_mesh(const dg_mesh* mc, hipStream_t s) {
     return st;
 }
 
+// a background that varies with z (the neutral atmosphere under gravity) cannot be
+// periodic in z: the two sides of a z wrap would carry different hydrostatic
+// states, and no choice of background at a face across the wrap is consistent
+dg_status check_wrap(const dg_mesh* m, const dg_phys* p) {
+    if (m->h.desc.periodic[2] && p->background == DG_BG_NEUTRAL && p->g != 0.0)
+        return fail(DG_EINVAL, "a periodic z axis needs a background that does not vary with z (g = 0 or DG_BG_CONSTANT)");
+    return DG_OK;
+}
+
 bool same_bg(const dg_phys& a, const dg_phys& b) {
     return a.cp == b.cp && a.cv == b.cv && a.P0 == b.P0 && a.g == b.g && a.background == b.background &&
            a.theta0 == b.theta0 && a.rho0 == b.rho0 && a.Theta0 == b.Theta0;
@@ -541,6 +550,7 @@ static dg_status stage_common(const dg_mesh* mc, const dg_phys* phys, int mode, 
     dg_status st = check_dev_mesh(mc, (hipStream_t)stream);
     if (st) return st;
     if ((st = check_phys(phys))) return st;
+    if ((st = check_wrap(mc, phys))) return st;
     if (!qs || !out) return fail(DG_EINVAL, "NULL field pointer");
     if (out == qs) return fail(DG_EINVAL, "output must not alias the stage input");
     if (mode == MODE_RK && a != 0.0 && !q0) return fail(DG_EINVAL, "q0 is NULL while a != 0");
@@ -618,6 +628,7 @@ static dg_status adjoint_common(const dg_mesh* mc, const dg_phys* phys, int mode
     dg_status st = check_dev_mesh(mc, (hipStream_t)stream);
     if (st) return st;
     if ((st = check_phys(phys))) return st;
+    if ((st = check_wrap(mc, phys))) return st;
     if (phys->nonconforming != DG_NC_MORTAR)
         return fail(DG_EUNSUPPORTED, "the adjoint is provided for the mortar scheme only");
     if (!q || !lam || !out) return fail(DG_EINVAL, "NULL field pointer");

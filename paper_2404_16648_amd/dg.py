@@ -430,18 +430,28 @@ def adapt_cycle(mesh: Mesh, phys: PhysParams, q, kind, thr, stream=None, buffer=
     return project_cycle(mesh, *adapt_meshes(mesh, phys, q, kind, thr, stream, buffer), q, stream)
 
 
+def _on(stream):
+    """Context in which torch allocates for `stream` (its caching allocator hands a
+    block freed there only to later work on the same stream); None: as is."""
+    import contextlib
+    import torch
+    return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+
+
 def project_cycle(mesh: Mesh, mc: Mesh, mr: Mesh, q, stream=None):
     """The projections of one adaptation cycle (mesh -> mc coarsening, mc -> mr
-    refinement; a pass that changed nothing is skipped).  Returns (mr, q on mr)."""
+    refinement; a pass that changed nothing is skipped).  Returns (mr, q on mr);
+    the new fields are allocated for `stream`."""
     import torch
     qc = q
-    if mc is not mesh:
-        qc = torch.empty(5, mc.K, mc.Np, dtype=torch.float64, device=q.device)
-        dg_coarsen_project(mesh, mc, q, qc, stream)
-    qr = qc
-    if mr is not mc:
-        qr = torch.empty(5, mr.K, mr.Np, dtype=torch.float64, device=q.device)
-        dg_refine_project(mc, mr, qc, qr, stream)
+    with _on(stream):
+        if mc is not mesh:
+            qc = torch.empty(5, mc.K, mc.Np, dtype=torch.float64, device=q.device)
+            dg_coarsen_project(mesh, mc, q, qc, stream)
+        qr = qc
+        if mr is not mc:
+            qr = torch.empty(5, mr.K, mr.Np, dtype=torch.float64, device=q.device)
+            dg_refine_project(mc, mr, qc, qr, stream)
     return mr, qr
 
 
@@ -492,6 +502,11 @@ class AdaptiveStepper:
         self.mesh, self.phys, self.q, self.dt = mesh, phys, q, dt
         self.every, self.kind, self.thr, self.buffer = every, kind, thr, buffer
         self.stream = stream
+        if stream is not None:
+            # the caller's state was made on another stream: the stepper's stream
+            # waits for it, and the tensor is marked as used there
+            stream.wait_stream(torch.cuda.current_stream())
+            q.record_stream(stream)
         self.n = 0           # steps made
         self.cycles = 0      # adaptation cycles run
         self.changed = 0     # cycles that changed the mesh (speculative step dropped)
@@ -506,12 +521,14 @@ class AdaptiveStepper:
 
     def _bufs(self, q):
         import torch
-        self._q1, self._q2, self._spec = torch.empty_like(q), torch.empty_like(q), torch.empty_like(q)
+        with _on(self.stream):  # allocated for the stream that uses them
+            self._q1, self._q2, self._spec = torch.empty_like(q), torch.empty_like(q), torch.empty_like(q)
 
     def _reserve(self, K):
         import torch
         if self._dev.numel() < K:
-            self._dev = torch.empty(2 * K, dtype=torch.int8, device=self.q.device)
+            with _on(self.stream):
+                self._dev = torch.empty(2 * K, dtype=torch.int8, device=self.q.device)
         if self._host.numel() < K:
             self._host = torch.empty(2 * K, dtype=torch.int8).pin_memory()
 

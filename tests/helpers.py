@@ -69,6 +69,16 @@ def assert_fields(a, b, tol, what="", vector_momentum=False):
     assert max(bound) <= tol, (what, err, comp)
 
 
+def phys_for(periodic, **kw):
+    """Library physics for a mesh with the given periodicity: a periodic z axis
+    takes g = 0 (the neutral background is then constant; a hydrostatic profile
+    cannot be periodic in z)."""
+    from paper_2404_16648_amd import dg
+    if periodic[2]:
+        kw.setdefault("g", 0.0)
+    return dg.PhysParams(**kw)
+
+
 def oracle_phys(p):
     """oracle Phys with the same constants as a binding PhysParams."""
     return eu.Phys(cp=p.cp, cv=p.cv, P0=p.P0, g=p.g, background=p.background,

@@ -195,3 +195,33 @@ def test_size_limit_at_the_kernels_indexing_bound():
     with pytest.raises(dg.DGError) as e:
         dg.dg_mesh_build(7, (95, 95, 95), 0, host_only=True)
     assert e.value.code == dg.DG_EINVAL and "too large" in str(e.value)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_flags_after_coarsen(seed):
+    """dg_flags_after_coarsen against the cycle read off the oracle's own coarsen
+    pass: a kept leaf keeps a +1 flag, a parent made by the pass and every other
+    leaf get 0; with a pass that changes nothing the flags carry over."""
+    c = dict(N=3, nroot=(3, 2, 2), L=2, periodic=(1, 0, 0))
+    od = oracle_desc(c["N"], c["nroot"], c["L"], (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), c["periodic"])
+    om = fo.build(od, None)
+    lm = dg.dg_mesh_build(c["N"], c["nroot"], c["L"], (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), c["periodic"],
+                          host_only=True)
+    rng = np.random.default_rng(seed)
+    for _ in range(2):
+        fl = (rng.random(om.K) < 0.4).astype(np.int8)
+        om = fo.build(od, om, fl, fo.PASS_REFINE)
+        lm = dg.dg_mesh_build(prev=lm, flags=fl, pass_=dg.DG_PASS_REFINE)
+    flags = random_flags(om.K, 100 + seed, p_refine=0.3, p_coarsen=0.6)
+    oc = fo.build(od, om, flags, fo.PASS_COARSEN)
+    lc = dg.dg_mesh_build(prev=lm, flags=flags, pass_=dg.DG_PASS_COARSEN)
+    assert tables_equal(lc.tables(), oc)
+    want = np.zeros(oc.K, np.int8)
+    for e in range(oc.K):
+        if oc.xfer_kind[e] == fo.KIND_COPY and flags[oc.xfer_src[e]] > 0:
+            want[e] = 1
+    assert np.array_equal(dg.dg_flags_after_coarsen(lc, flags), want)
+    # no family flagged: the identity plan carries the flags over (-1 dropped)
+    flags2 = np.where(flags < 0, 0, flags).astype(np.int8)
+    lc2 = dg.dg_mesh_build(prev=lm, flags=flags2, pass_=dg.DG_PASS_COARSEN)
+    assert np.array_equal(dg.dg_flags_after_coarsen(lc2, flags2), flags2)

@@ -15,8 +15,8 @@ from oracle import forest as fo
 from paper_2404_16648_amd import adjoint as adj
 from paper_2404_16648_amd import dg
 from paper_2404_16648_amd.synth import random_direction, random_state
-from tests.helpers import (TOL_FP64, assert_fields, oracle_desc, oracle_phys, random_refinements, tables_equal,
-                           to_elem, to_nodes)
+from tests.helpers import (TOL_FP64, assert_fields, oracle_desc, oracle_phys, phys_for, random_refinements,
+                           tables_equal, to_elem, to_nodes)
 
 pytestmark = pytest.mark.gpu
 
@@ -60,7 +60,7 @@ def test_rhs_adjoint_random_amr(case):
     N = case["N"]
     od = oracle_desc(N, case["nroot"], 2, *BOX, case["periodic"])
     lm, om = both_meshes(N, case["nroot"], 2, case["periodic"], random_refinements(od, 2, case["seed"]))
-    ph = dg.PhysParams()
+    ph = phys_for(case["periodic"])
     op = eu.Operator(om, oracle_phys(ph))
     qn = torch.as_tensor(random_state(om.K, N, case["seed"]))
     ln = torch.as_tensor(random_state(om.K, N, case["seed"] + 100, (1.0, 1.0, 1.0, 1.0, 1.0)))

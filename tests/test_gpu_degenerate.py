@@ -8,7 +8,7 @@ import torch
 from oracle import euler as eu
 from paper_2404_16648_amd import dg
 from paper_2404_16648_amd.synth import random_state
-from tests.helpers import oracle_phys, to_elem
+from tests.helpers import oracle_phys, phys_for, to_elem
 from tests.test_gpu_parity import both_meshes, check, gpu
 
 pytestmark = pytest.mark.gpu
@@ -22,7 +22,7 @@ def test_single_root_meshes(N, shape):
     seq = [torch.ones(1, dtype=torch.int8).numpy()] if shape == "refined_periodic" else []
     lm, om = both_meshes(N, (1, 1, 1), 1, periodic, flag_seq=seq)
     assert lm.K == (8 if seq else 1)
-    ph = dg.PhysParams()
+    ph = phys_for(periodic)
     op = eu.Operator(om, oracle_phys(ph))
     qn = torch.as_tensor(random_state(om.K, N, 40 + N))
     R = lm.field()

@@ -11,8 +11,8 @@ from oracle import euler as eu
 from oracle import forest as fo
 from paper_2404_16648_amd import dg
 from paper_2404_16648_amd.synth import random_state
-from tests.helpers import (TOL_FP64, assert_fields, oracle_desc, oracle_phys, random_refinements, tables_equal,
-                           to_elem, to_nodes)
+from tests.helpers import (TOL_FP64, assert_fields, oracle_desc, oracle_phys, phys_for, random_refinements,
+                           tables_equal, to_elem, to_nodes)
 
 pytestmark = pytest.mark.gpu
 
@@ -82,7 +82,7 @@ def test_rhs_random_state_amr(case):
     seq = random_refinements(od, 2, case["seed"])
     lm, om = both_meshes(case["N"], case["nroot"], case["L"], case["periodic"], flag_seq=seq)
     assert lm.info.n_hang > 0
-    ph = dg.PhysParams()
+    ph = phys_for(case["periodic"])
     op = eu.Operator(om, oracle_phys(ph))
     qn = torch.as_tensor(random_state(om.K, om.N, case["seed"]))
     q = to_elem(qn, om.N)
@@ -96,10 +96,11 @@ def test_rhs_random_state_amr(case):
 def test_rhs_large_theta_perturbation(N):
     """Theta' up to ~+-25% of Thetabar: P' leaves the short binomial series and takes
     the kernels' wide-range path (log-halving), checked against the oracle's
-    expm1/log1p form, on faces, mortars and volume, with a periodic z wrap."""
-    od = oracle_desc(N, (2, 2, 2), 2, *BOX, (0, 0, 1))
+    expm1/log1p form, on faces, mortars and volume, with a periodic wrap along x
+    and walls along z (gravity on: the background varies with z)."""
+    od = oracle_desc(N, (2, 2, 2), 2, *BOX, (1, 0, 0))
     seq = random_refinements(od, 2, 31 + N)
-    lm, om = both_meshes(N, (2, 2, 2), 2, (0, 0, 1), flag_seq=seq)
+    lm, om = both_meshes(N, (2, 2, 2), 2, (1, 0, 0), flag_seq=seq)
     assert lm.info.n_hang > 0
     ph = dg.PhysParams()
     op = eu.Operator(om, oracle_phys(ph))
@@ -124,7 +125,7 @@ def test_rk_stage_random_state_amr(case):
     od = oracle_desc(case["N"], case["nroot"], case["L"], *BOX, case["periodic"])
     seq = random_refinements(od, 2, case["seed"] + 100)
     lm, om = both_meshes(case["N"], case["nroot"], case["L"], case["periodic"], flag_seq=seq)
-    ph = dg.PhysParams()
+    ph = phys_for(case["periodic"])
     op = eu.Operator(om, oracle_phys(ph))
     N = om.N
     q0 = torch.as_tensor(random_state(om.K, N, case["seed"] + 200))
@@ -323,6 +324,21 @@ def test_unchanged_pass_clones_device_tables():
     dg.dg_coarsen_project(m2, m3, q, qc)
     torch.cuda.synchronize()
     assert torch.equal(qc, q)
+
+
+def test_z_periodic_mesh_refuses_a_z_dependent_background():
+    """A periodic z axis with gravity on the neutral background is refused (the
+    hydrostatic profile cannot be periodic); with g = 0 the same mesh runs."""
+    lm = dg.dg_mesh_build(3, (1, 1, 2), 0, *BOX, (0, 0, 1))
+    q, R = lm.field(), lm.field()
+    with pytest.raises(dg.DGError) as e:
+        dg.dg_rhs(lm, dg.PhysParams(), q, R)
+    assert e.value.code == dg.DG_EINVAL
+    with pytest.raises(dg.DGError):
+        dg.dg_rhs_adjoint(lm, dg.PhysParams(), q, q.clone(), R)
+    dg.dg_rhs(lm, phys_for((0, 0, 1)), q, R)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(R) == 0
 
 
 @pytest.mark.parametrize("N", [4, 7])

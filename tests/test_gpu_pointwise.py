@@ -10,7 +10,7 @@ import torch
 from oracle import euler as eu
 from paper_2404_16648_amd import dg
 from paper_2404_16648_amd.synth import random_state
-from tests.helpers import oracle_desc, oracle_phys, random_refinements, to_elem, to_nodes
+from tests.helpers import oracle_desc, oracle_phys, phys_for, random_refinements, to_elem, to_nodes
 from tests.test_gpu_parity import AMR_CASES, BOX, both_meshes, check, gpu
 
 pytestmark = pytest.mark.gpu
@@ -26,7 +26,7 @@ def test_pointwise_rhs_and_stage_amr(case):
     seq = random_refinements(od, 2, case["seed"])
     lm, om = both_meshes(case["N"], case["nroot"], case["L"], case["periodic"], flag_seq=seq)
     assert lm.info.n_hang > 0
-    ph = _pw(dg.PhysParams())
+    ph = _pw(phys_for(case["periodic"]))
     op = eu.Operator(om, oracle_phys(ph), nonconforming="pointwise")
     N = om.N
     qn = torch.as_tensor(random_state(om.K, N, case["seed"]))

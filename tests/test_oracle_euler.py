@@ -44,6 +44,14 @@ def rand_q(op, seed):
         5, op.K, op.N + 1, op.N + 1, op.N + 1)
 
 
+def test_z_periodic_background_must_be_constant_in_z():
+    m = fo.build(fo.ForestDesc(2, 1, 1, 2, 0, periodic=(0, 0, 1)), None)
+    with pytest.raises(ValueError):
+        eu.Operator(m, eu.Phys())
+    eu.Operator(m, eu.Phys(g=0.0))
+    eu.Operator(m, eu.Phys(background=eu.BG_CONSTANT))
+
+
 def test_hydrostatic_rest_is_exact():
     m = amr_mesh(4, seed=1)
     op = eu.Operator(m, eu.Phys())
@@ -72,7 +80,7 @@ def test_free_stream_preserved_with_mortars():
 @pytest.mark.parametrize("periodic", [(0, 0, 0), (1, 1, 1), (1, 0, 1)])
 def test_discrete_conservation(periodic):
     m = amr_mesh(3, periodic=periodic, seed=3)
-    ph = eu.Phys()
+    ph = eu.Phys(g=0.0) if periodic[2] else eu.Phys()
     op = eu.Operator(m, ph)
     q = rand_q(op, 5)
     R = op.rhs(q)
@@ -459,8 +467,8 @@ def test_pointwise_loses_conservation_mortar_keeps_it():
     (= rho theta, a tracer with c = theta) to round-off, pointwise matching does
     not; on the fine faces the two schemes agree exactly."""
     m = amr_mesh(3, periodic=(1, 0, 1), seed=3)
-    op_m = eu.Operator(m, eu.Phys())
-    op_p = eu.Operator(m, eu.Phys(), nonconforming="pointwise")
+    op_m = eu.Operator(m, eu.Phys(g=0.0))
+    op_p = eu.Operator(m, eu.Phys(g=0.0), nonconforming="pointwise")
     q = rand_q(op_m, 5)
     Rm, Rp = op_m.rhs(q), op_p.rhs(q)
     JW = eu.quad_weights(op_m)
