@@ -337,6 +337,115 @@ class Operator:
         return self.volume(q) + self.surface(q)
 
 
+# ----------------------------------------------------------------------------- passive tracer
+
+def tracer_flux_dir(q, C, bg, phys, d):
+    """Tracer flux C u_d along axis d (section 2.1: the flux of C = rho c is C U / rho)."""
+    rho, u, _, _ = primitives(q, bg, phys)
+    return C * u[d]
+
+
+def tracer_rusanov(qL, CL, bgL, qR, CR, bgR, phys, d, sgn):
+    """Tracer part of the Rusanov flux for n = sgn e_d: {C u.n} + 1/2 lambda (C- - C+),
+    with lambda the same local maximum wave speed as the Euler system's flux."""
+    rhoL, uL, _, PL = primitives(qL, bgL, phys)
+    rhoR, uR, _, PR = primitives(qR, bgR, phys)
+    lamL = torch.abs(uL[d]) + sound_speed(rhoL, PL, phys.gamma)
+    lamR = torch.abs(uR[d]) + sound_speed(rhoR, PR, phys.gamma)
+    lam = torch.maximum(lamL, lamR)
+    FL = sgn * CL * uL[d]
+    FR = sgn * CR * uR[d]
+    return 0.5 * (FL + FR) + 0.5 * lam * (CL - CR)
+
+
+def tracer_rhs(op: Operator, q, C):
+    """R_C(q, C): the strong-form dGSEM right-hand side of the tracer equation
+    dC/dt + div(C u) = 0 (section 2.1), u = U/rho from the Euler state q, with the
+    same Rusanov flux, mirror walls (no tracer flux through a wall) and the same
+    hanging-face scheme (mortars or pointwise matching) as the Euler operator.
+    C is [K, N+1, N+1, N+1]; so is the result."""
+    N, K, ph = op.N, op.K, op.phys
+    nf = (N + 1) ** 2
+    g2 = 2.0 / op.h
+    # volume: -sum_d (2/h_d) D_d (C u_d)
+    Fx = tracer_flux_dir(q, C, op.bg, ph, 0)
+    Fy = tracer_flux_dir(q, C, op.bg, ph, 1)
+    Fz = tracer_flux_dir(q, C, op.bg, ph, 2)
+    R = -(g2[:, 0, None, None, None] * torch.einsum('im,ekjm->ekji', op.D, Fx)
+          + g2[:, 1, None, None, None] * torch.einsum('jm,ekmi->ekji', op.D, Fy)
+          + g2[:, 2, None, None, None] * torch.einsum('km,emji->ekji', op.D, Fz))
+    delta = [torch.zeros(K, nf, dtype=F64) for _ in range(6)]
+    lift = 2.0 / op.wN / op.h
+
+    def trace(f, elems):
+        qt, bgt = op._trace(q, f, elems)
+        return qt, face_slice(C[None], f, N)[0][elems], bgt
+
+    for d in range(3):
+        sel = op.conf[:, 2] == d
+        if not bool(sel.any()):
+            continue
+        eM, eP = op.conf[sel, 0], op.conf[sel, 1]
+        qL, cL, bL = trace(2 * d + 1, eM)
+        qR, cR, bR = trace(2 * d, eP)
+        Fs = tracer_rusanov(qL, cL, bL, qR, cR, bR, ph, d, 1.0)
+        delta[2 * d + 1] = delta[2 * d + 1].index_add(0, eM, Fs - tracer_flux_dir(qL, cL, bL, ph, d))
+        delta[2 * d] = delta[2 * d].index_add(0, eP, -Fs + tracer_flux_dir(qR, cR, bR, ph, d))
+    for f in range(6):
+        sel = op.bnd[:, 1] == f
+        if not bool(sel.any()):
+            continue
+        d, s = f // 2, f % 2
+        sgn = 1.0 if s == 1 else -1.0
+        e = op.bnd[sel, 0]
+        qL, cL, bL = trace(f, e)
+        qR = torch.stack([qL[0]] + [(-qL[1 + m] if m == d else qL[1 + m]) for m in range(3)] + [qL[4]])
+        Fs = tracer_rusanov(qL, cL, bL, qR, cL, bL, ph, d, sgn)
+        delta[f] = delta[f].index_add(0, e, Fs - sgn * tracer_flux_dir(qL, cL, bL, ph, d))
+    for f in range(6):
+        sel = op.hang[:, 1] == f
+        if not bool(sel.any()):
+            continue
+        d, s = f // 2, f % 2
+        sgn = 1.0 if s == 1 else -1.0
+        fo_ = 2 * d + (1 - s)
+        ec = op.hang[sel, 0]
+        qc, cc, bc = trace(f, ec)
+        proj = torch.zeros_like(cc)          # mortar: projected flux; pointwise: fine C at coarse nodes
+        projq = torch.zeros_like(qc)         # pointwise: fine state at coarse nodes
+        for quad in range(4):
+            a, b = quad & 1, quad >> 1
+            ef = op.hang[sel, 2 + quad]
+            qf, cf, bf = trace(fo_, ef)
+            qm = interp2(op.I[a], op.I[b], qc, N)
+            cm = interp2(op.I[a], op.I[b], cc, N)
+            Fs = tracer_rusanov(qm, cm, bf, qf, cf, bf, ph, d, sgn)      # F*.n_c on the mortar
+            if op.nonconforming == "mortar":
+                proj = proj + interp2(op.Rm[a], op.Rm[b], Fs, N)
+            else:
+                proj = proj + interp2(op.P[a], op.P[b], cf, N)
+                projq = projq + interp2(op.P[a], op.P[b], qf, N)
+            delta[fo_] = delta[fo_].index_add(0, ef, -Fs + sgn * tracer_flux_dir(qf, cf, bf, ph, d))
+        if op.nonconforming == "pointwise":
+            proj = tracer_rusanov(qc, cc, bc, projq, proj, bc, ph, d, sgn)
+        delta[f] = delta[f].index_add(0, ec, proj - sgn * tracer_flux_dir(qc, cc, bc, ph, d))
+    for f in range(6):
+        d = f // 2
+        R = R - face_embed((delta[f] * lift[:, d, None])[None], f, N, K)[0]
+    return R
+
+
+def tracer_stage(op: Operator, a, b, dt, qs, C0, Cs):
+    """C_out = a C0 + b (Cs + dt R_C(qs, Cs)): the tracer part of one Shu-Osher
+    stage, with the Euler stage input qs supplying the velocity."""
+    return a * C0 + b * (Cs + dt * tracer_rhs(op, qs, Cs))
+
+
+def tracer_mass(op: Operator, C):
+    """Integral of C (exactly rounded sum of J_e W_n C)."""
+    return math.fsum((quad_weights(op) * C).reshape(-1).tolist())
+
+
 def rhs(mesh, phys, q):
     return Operator(mesh, phys).rhs(q)
 
