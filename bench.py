@@ -407,7 +407,16 @@ def extras(dg, torch, mesh, q, ph, args):
     rhs_us = _time_launches(torch, lambda: dg.dg_rhs(mesh, ph, q, Ra), 20)
     adj_us = _time_launches(torch, lambda: dg.dg_rhs_adjoint(mesh, ph, q, lam, g), 20)
     out["density_current_adjoint_rhs"] = {"rhs_us": rhs_us, "rhs_adjoint_us": adj_us, "ratio": adj_us / rhs_us}
-    del lam, g, Ra, Rb, q1
+    # passive tracer (section 2.1's C = rho c) on the same mesh: its stage beside the Euler stage
+    c0 = 1.0 + 0.1 * torch.rand(mesh.K, mesh.Np, dtype=torch.float64, device=q.device,
+                                generator=torch.Generator(q.device).manual_seed(5))
+    cs, c1 = c0.clone(), torch.empty_like(c0)
+    tr_us = _time_launches(torch, lambda: dg.dg_tracer_stage(mesh, ph, 0.75, 0.25, dt, qs, c0, cs, c1), 20)
+    out["density_current_tracer_stage"] = {
+        "stage_us": tr_us, "bytes_per_node": 64.0, "kernels": "k_tracer_mortar<4, false> + k_tracer_stage<4, 1>",
+        "note": "reads the Euler stage input (40 B/node) and c0, cs, writes the tracer (8 B each)",
+        "frac_hbm": nodes * 64.0 / (tr_us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+    del lam, g, Ra, Rb, q1, c0, cs, c1
     _progress("extras: density current forced adaptation cycle")
     out["density_current_forced_cycle"] = forced_cycle(dg, torch, mesh, q)
     # ---- AMR warm bubble (N = 7): the adaptive run as for the headline
@@ -453,6 +462,19 @@ def extras(dg, torch, mesh, q, ph, args):
         gap[key] = {"rho_prime_drift_rel_mass": abs(b1[0] - b0[0]) / abs(b0[1]),
                     "theta_prime_drift_rel_mass": abs(b1[2] - b0[2]) / abs(b0[1])}
     out["amr_bubble"]["nonconforming_gap_10_steps"] = gap
+    # the same comparison on a passive tracer carried with the Euler state (section 4.2's tracer loss)
+    tgap = {}
+    for scheme, key in ((dg.DG_NC_MORTAR, "mortar"), (dg.DG_NC_POINTWISE, "pointwise")):
+        php = dg.PhysParams(nonconforming=scheme)
+        qg, g1, g2 = qb.clone(), torch.empty_like(qb), torch.empty_like(qb)
+        c = 1.0 + 0.1 * torch.rand(mb.K, mb.Np, dtype=torch.float64, device=qb.device,
+                                   generator=torch.Generator(qb.device).manual_seed(6))
+        c1, c2 = torch.empty_like(c), torch.empty_like(c)
+        m0 = dg.dg_tracer_mass(mb, c)
+        for _ in range(10):
+            dg.ssp_rk3_step_tracer(mb, php, BUBBLE["dt"], qg, g1, g2, c, c1, c2)
+        tgap[key] = abs(dg.dg_tracer_mass(mb, c) - m0) / abs(m0)
+    out["amr_bubble"]["tracer_loss_10_steps_rel"] = tgap
     del qg, g1, g2, lam, g, Ra, Rb, qbs, qb1
     _progress("extras: adjoint configuration")
     from paper_2404_16648_amd import adjoint as adj

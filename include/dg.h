@@ -231,6 +231,14 @@ dg_status dg_refine_project(const dg_mesh* from, const dg_mesh* to, const double
 dg_status dg_coarsen_project(const dg_mesh* from, const dg_mesh* to, const double* q_from,
                              double* q_to, void* stream);
 
+/* The same conservative transfer for any set of nvar fields [nvar][K][Np]
+ * (1 <= nvar <= 5; e.g. a passive tracer, nvar = 1), in the direction of the
+ * pass that built `to` (refine, or coarsen; a pass that changed no leaf copies).
+ * Same checks and errors as dg_refine_project; DG_EINVAL for nvar out of range.
+ * (Section 3.3: the same projection matrices serve every field.) */
+dg_status dg_project_fields(const dg_mesh* from, const dg_mesh* to, int32_t nvar, const double* q_from,
+                            double* q_to, void* stream);
+
 /* Transposes of the transfers, for the adjoint through an adaptation: with P
  * the linear map q_from -> q_to of dg_refine_project (resp.
  * dg_coarsen_project) from `from` to `to`, qbar_from := P^T qbar_to in the
@@ -270,6 +278,30 @@ dg_status dg_rhs_adjoint(const dg_mesh* mesh, const dg_phys* phys, const double*
 dg_status dg_rk_stage_adjoint(const dg_mesh* mesh, const dg_phys* phys, double a1, const double* w1, double a2,
                               const double* w2, double b, double dt, const double* q, const double* y, double* out,
                               void* stream);
+
+/* Passive tracer (section 2.1: C = rho c, dC/dt + div(C u) = 0, u = U/rho;
+ * section 4.2 compares its loss under mortars and pointwise matching).  c and
+ * the outputs are DEVICE float64 [K][Np] (leaf-major like one variable plane of
+ * q); q / qs is the Euler state [5][K][Np] that supplies u and the Rusanov wave
+ * speed (the same local maximum |u.n| + c as the Euler flux; the tracer jump is
+ * C- - C+).  Walls carry no tracer flux; hanging faces use phys->nonconforming
+ * (mortars: the tracer's integral is conserved to round-off; pointwise: not),
+ * through a pre-pass into the mesh's tracer workspace (calls on one mesh must be
+ * ordered, as for dg_rhs).  dg_tracer_rhs: rhs := R_C(q, c).  dg_tracer_stage:
+ * cout := a c0 + b (cs + dt R_C(qs, cs)), the tracer part of the Shu-Osher
+ * stage whose Euler part is dg_rk_stage(a, b, dt, q0, qs, ...) (call it before
+ * that stage overwrites qs, or with a distinct output); cout may alias c0 but
+ * not cs or qs; c0 is not read when a == 0.  Enqueued on stream.  DG_EINVAL on
+ * NULL or aliased fields, bad phys or a z-periodic mesh with a z-dependent
+ * background. */
+dg_status dg_tracer_rhs(const dg_mesh* mesh, const dg_phys* phys, const double* q, const double* c, double* rhs,
+                        void* stream);
+dg_status dg_tracer_stage(const dg_mesh* mesh, const dg_phys* phys, double a, double b, double dt, const double* qs,
+                          const double* c0, const double* cs, double* cout, void* stream);
+/* Integral of a tracer field c (device [K][Np]) with the weights of dg_budgets,
+ * compensated and deterministic, into out_host[0] (host).  Synchronises the
+ * stream; DG_ENONFINITE if not finite. */
+dg_status dg_tracer_mass(const dg_mesh* mesh, const double* c, double* out_host, void* stream);
 
 /* Mass and energy budgets (section 2.1: mass is conserved discretely, energy
  * is not; section 4.3 reports both losses; the energy density is not in the

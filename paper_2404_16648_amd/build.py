@@ -32,6 +32,7 @@ SOURCES = [
     ("forest.cpp", "cxx"),
     ("abi.cpp", "hip"),
     ("kernels.hip", "hip"),
+    ("tracer.hip", "hip"),
 ]
 
 

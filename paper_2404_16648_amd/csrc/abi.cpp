@@ -56,13 +56,14 @@ void free_device(dg_mesh* m) {
     m->d_ftype = m->d_fnb = m->d_level = m->d_xsrc = m->d_xkind = nullptr;
     m->d_hslot = m->d_hang = nullptr;
     m->d_mort = nullptr;
+    m->d_mortC = nullptr;
     m->d_flags = nullptr;
 }
 
 // byte offsets of the arrays in a mesh's one device block, 256-byte aligned;
 // [0, upload) is copied from the host, the rest is device workspace
 struct DevLayout {
-    size_t ops, geo, c1d, ft, nb, hs, hg, lv, xs, xk, sr, upload, bg, red, eta, fl, mort, total;
+    size_t ops, geo, c1d, ft, nb, hs, hg, lv, xs, xk, sr, upload, bg, red, eta, fl, mort, mortC, total;
 };
 
 DevLayout dev_layout(int64_t K, int N, int64_t red_len, int64_t n_hang) {
@@ -91,6 +92,7 @@ DevLayout dev_layout(int64_t K, int N, int64_t red_len, int64_t n_hang) {
     L.eta = take(sizeof(double) * (k > 0 ? k : 1));
     L.fl = take(k > 0 ? k : 1);
     L.mort = take(sizeof(double) * 25 * N1 * N1 * (size_t)n_hang);
+    L.mortC = take(sizeof(double) * 5 * N1 * N1 * (size_t)n_hang);
     L.total = end;
     return L;
 }
@@ -105,6 +107,7 @@ void set_device_pointers(dg_mesh* m, char* base, const DevLayout& L) {
     m->d_hslot = (int32_t*)(base + L.hs);
     m->d_hang = (int32_t*)(base + L.hg);
     m->d_mort = (double*)(base + L.mort);
+    m->d_mortC = (double*)(base + L.mortC);
     m->d_level = (int32_t*)(base + L.lv);
     m->d_xsrc = (int32_t*)(base + L.xs);
     m->d_xkind = (int32_t*)(base + L.xk);
@@ -583,7 +586,7 @@ dg_status dg_rk_stage(const dg_mesh* m, const dg_phys* phys, double a, double b,
 }
 
 static dg_status xfer_common(const dg_mesh* from, const dg_mesh* to, const double* qin, double* qout,
-                             void* stream, bool refine, bool adjoint) {
+                             void* stream, bool refine, bool adjoint, int32_t nvar = 5) {
     dg_status st = check_dev_mesh(from, (hipStream_t)stream);
     if (st) return st;
     if ((st = check_dev_mesh(to, (hipStream_t)stream))) return st;
@@ -593,7 +596,7 @@ static dg_status xfer_common(const dg_mesh* from, const dg_mesh* to, const doubl
     if (refine && to->h.n_coarsened) return fail(DG_EINVAL, "`to` was built by a coarsen pass");
     if (!refine && to->h.n_refined) return fail(DG_EINVAL, "`to` was built by a refine pass");
     const int64_t Kf = (int64_t)from->h.leaves.size(), Kt = (int64_t)to->h.leaves.size();
-    XferArgs a{qin, qout, to->d_ops, to->d_xsrc, to->d_xkind, adjoint ? Kt : Kf, adjoint ? Kf : Kt, Kt};
+    XferArgs a{qin, qout, to->d_ops, to->d_xsrc, to->d_xkind, adjoint ? Kt : Kf, adjoint ? Kf : Kt, Kt, nvar};
     hipStream_t s = (hipStream_t)stream;
     if (refine)
         HIP_TRY(launch_refine(to->h.desc.N, adjoint, a, s));
@@ -620,6 +623,66 @@ dg_status dg_refine_project_adjoint(const dg_mesh* from, const dg_mesh* to, cons
 dg_status dg_coarsen_project_adjoint(const dg_mesh* from, const dg_mesh* to, const double* qbar_to,
                                      double* qbar_from, void* stream) {
     return xfer_common(from, to, qbar_to, qbar_from, stream, false, true);
+}
+
+static dg_status tracer_common(const dg_mesh* mc, const dg_phys* phys, int mode, double a, double b, double dt,
+                               const double* qs, const double* c0, const double* cs, double* out, void* stream) {
+    dg_status st = check_dev_mesh(mc, (hipStream_t)stream);
+    if (st) return st;
+    if ((st = check_phys(phys))) return st;
+    if ((st = check_wrap(mc, phys))) return st;
+    if (!qs || !cs || !out) return fail(DG_EINVAL, "NULL field pointer");
+    if (out == cs) return fail(DG_EINVAL, "output must not alias the tracer stage input");
+    if ((const double*)out == qs) return fail(DG_EINVAL, "output must not alias the Euler state");
+    if (mode == MODE_RK && a != 0.0 && !c0) return fail(DG_EINVAL, "c0 is NULL while a != 0");
+    dg_mesh* m = const_cast<dg_mesh*>(mc);
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = ensure_bg(m, phys, s))) return st;
+    const int64_t K = (int64_t)m->h.leaves.size();
+    const double gamma = phys->cp / phys->cv;
+    const BinomCoef bc = binom_coef(phys);
+    if (m->n_hang) {
+        TracerMortArgs ma{qs, cs, m->d_mortC, m->d_ops, m->d_geo, m->d_bg, m->d_hang, m->n_hang, K, gamma, bc,
+                          phys->nonconforming == DG_NC_POINTWISE ? 1 : 0};
+        HIP_TRY(launch_tracer_mortar(m->h.desc.N, ma, s));
+    }
+    TracerArgs ta{qs, c0, cs, out, m->d_ops, m->d_geo, m->d_bg, m->d_srec, m->d_mortC, K, a, b, dt, gamma, bc};
+    HIP_TRY(launch_tracer_stage(m->h.desc.N, mode, ta, s));
+    return DG_OK;
+}
+
+dg_status dg_tracer_rhs(const dg_mesh* m, const dg_phys* phys, const double* q, const double* c, double* rhs,
+                        void* stream) {
+    return tracer_common(m, phys, MODE_RHS, 0.0, 1.0, 0.0, q, nullptr, c, rhs, stream);
+}
+
+dg_status dg_tracer_stage(const dg_mesh* m, const dg_phys* phys, double a, double b, double dt, const double* qs,
+                          const double* c0, const double* cs, double* cout, void* stream) {
+    return tracer_common(m, phys, MODE_RK, a, b, dt, qs, c0, cs, cout, stream);
+}
+
+dg_status dg_project_fields(const dg_mesh* from, const dg_mesh* to, int32_t nvar, const double* q_from,
+                            double* q_to, void* stream) {
+    if (nvar < 1 || nvar > 5) return fail(DG_EINVAL, "nvar must be in [1, 5]");
+    if (!to) return fail(DG_EINVAL, "to is NULL");
+    return xfer_common(from, to, q_from, q_to, stream, to->h.n_coarsened == 0, false, nvar);
+}
+
+dg_status dg_tracer_mass(const dg_mesh* mc, const double* c, double* out_host, void* stream) {
+    dg_status st = check_dev_mesh(mc, (hipStream_t)stream);
+    if (st) return st;
+    if (!c || !out_host) return fail(DG_EINVAL, "NULL argument");
+    dg_mesh* m = const_cast<dg_mesh*>(mc);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t K = (int64_t)m->h.leaves.size();
+    const int nblk = budget_blocks(K);
+    double* out_dev = m->d_red + (int64_t)nblk * 8;
+    HIP_TRY(launch_weighted_sum(m->h.desc.N, c, m->d_geo, m->d_ops + 5 * (m->h.desc.N + 1) * (m->h.desc.N + 1), K,
+                                nblk, m->d_red, out_dev, s));
+    HIP_TRY(hipMemcpyAsync(out_host, out_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (!std::isfinite(out_host[0])) return fail(DG_ENONFINITE, "non-finite tracer mass");
+    return DG_OK;
 }
 
 static dg_status adjoint_common(const dg_mesh* mc, const dg_phys* phys, int mode, double a1, const double* w1,

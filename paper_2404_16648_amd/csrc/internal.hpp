@@ -76,6 +76,7 @@ struct dg_mesh {
     int32_t* d_hang = nullptr;    // [n_hang][6]: coarse leaf, its face, 4 fine leaves
     int32_t* d_srec = nullptr;    // [K][kStageRec]: face tables of the stage kernel
     double* d_mort = nullptr;     // [n_hang][5][5][NF]: mortar pre-pass output (workspace)
+    double* d_mortC = nullptr;    // [n_hang][5][NF]: tracer mortar pre-pass output (workspace)
     int64_t n_hang = 0;
     // background profile [3][K][N1] for bg_phys (computed on first use)
     double* d_bg = nullptr;

@@ -110,6 +110,39 @@ struct XferArgs {
     const int32_t* src;
     const int32_t* kind;
     int64_t Kin, Kout, Kto;
+    int32_t nvar;          // fields [nvar][K][Np], 1 <= nvar <= 5
+};
+
+// passive tracer stage: out = R_C(qs, cs) (MODE_RHS) or a c0 + b (cs + dt R_C) (MODE_RK)
+struct TracerArgs {
+    const double* qs;      // [5][K][Np] Euler stage input (the velocity and wave speed)
+    const double* c0;      // [K][Np] (read only when a != 0)
+    const double* cs;      // [K][Np] tracer stage input
+    double* out;           // [K][Np]
+    const double* ops;
+    const double* geo;
+    const double* bg;
+    const int32_t* srec;   // [K][kStageRec]
+    const double* mortC;   // [n_hang][5][NF]: lifted tracer mortar contributions
+    int64_t K;
+    double a, b, dt;
+    double gamma;
+    BinomCoef binom;
+};
+
+// tracer mortar pre-pass: one workgroup per hanging face
+struct TracerMortArgs {
+    const double* qs;
+    const double* cs;
+    double* mortC;         // [n_hang][5][NF] output
+    const double* ops;
+    const double* geo;
+    const double* bg;
+    const int32_t* hang;
+    int64_t n_hang, K;
+    double gamma;
+    BinomCoef binom;
+    int32_t pointwise;
 };
 
 struct BudgetArgs {
@@ -160,5 +193,11 @@ int budget_blocks(int64_t K);
 hipError_t budget_scratch(double** out);
 hipError_t launch_budgets(int N, const BudgetArgs& a, int nblk, double* out_dev, hipStream_t s);
 hipError_t launch_indicator(int N, const IndArgs& a, hipStream_t s);
+hipError_t launch_tracer_mortar(int N, const TracerMortArgs& a, hipStream_t s);
+hipError_t launch_tracer_stage(int N, int mode, const TracerArgs& a, hipStream_t s);
+// integral of c [K][Np] with the weights J_e W_n (w the 1-D LGL weights): nblk <= budget_blocks(K)
+// blocks leave 2 doubles each in partial, the total goes to out_dev[0]
+hipError_t launch_weighted_sum(int N, const double* c, const double* geo, const double* w, int64_t K, int nblk,
+                               double* partial, double* out_dev, hipStream_t s);
 
 }  // namespace dgamr

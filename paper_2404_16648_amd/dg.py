@@ -39,7 +39,8 @@ DG_KIND_FAMILY = 8
 EXPORTED = [
     "dg_mesh_build", "dg_mesh_free", "dg_mesh_info_get", "dg_mesh_export", "dg_node_coords",
     "dg_init_bell", "dg_rhs", "dg_rk_stage", "dg_refine_project", "dg_coarsen_project",
-    "dg_refine_project_adjoint", "dg_coarsen_project_adjoint", "dg_rhs_adjoint", "dg_rk_stage_adjoint", "dg_budgets", "dg_budgets_noalloc", "dg_indicator", "dg_indicator_async", "dg_pass_changes", "dg_flags_after_coarsen", "dg_flags_buffer", "dg_fma_burst", "dg_last_error",
+    "dg_refine_project_adjoint", "dg_coarsen_project_adjoint", "dg_rhs_adjoint", "dg_rk_stage_adjoint", "dg_budgets", "dg_budgets_noalloc", "dg_indicator", "dg_indicator_async", "dg_pass_changes", "dg_flags_after_coarsen", "dg_tracer_rhs", "dg_tracer_stage", "dg_tracer_mass",
+    "dg_project_fields", "dg_flags_buffer", "dg_fma_burst", "dg_last_error",
 ]
 
 
@@ -108,6 +109,10 @@ def lib():
         L.dg_fma_burst.argtypes = [C.c_int32, C.c_int32, P, P, P]
         L.dg_flags_buffer.argtypes = [P, P, C.c_int32]
         L.dg_flags_after_coarsen.argtypes = [P, P, P]
+        L.dg_tracer_rhs.argtypes = [P, C.POINTER(Phys), P, P, P, P]
+        L.dg_tracer_stage.argtypes = [P, C.POINTER(Phys), C.c_double, C.c_double, C.c_double, P, P, P, P, P]
+        L.dg_tracer_mass.argtypes = [P, P, P, P]
+        L.dg_project_fields.argtypes = [P, P, C.c_int32, P, P, P]
         L.dg_indicator.argtypes = [P, C.POINTER(Phys), P, C.c_int32, C.c_double, P, P, P]
         L.dg_indicator_async.argtypes = [P, C.POINTER(Phys), P, C.c_int32, C.c_double, P, P, P]
         L.dg_pass_changes.argtypes = [P, P, C.c_int32, C.POINTER(C.c_int32)]
@@ -301,6 +306,58 @@ def dg_coarsen_project_adjoint(src: Mesh, dst: Mesh, qbar_to, qbar_from, stream=
     _shape_check(src, qbar_from)
     _check(lib().dg_coarsen_project_adjoint(src.handle, dst.handle, _ptr(qbar_to), _ptr(qbar_from),
                                             _stream(stream)))
+
+
+def _tracer_check(mesh, *ts):
+    for t in ts:
+        if t is not None and tuple(t.shape) != (mesh.K, mesh.Np):
+            raise ValueError(f"tracer shape {tuple(t.shape)} != ({mesh.K}, {mesh.Np})")
+
+
+def dg_tracer_rhs(mesh: Mesh, phys: PhysParams, q, c, rhs, stream=None):
+    """rhs := R_C(q, c), the tracer right-hand side (c, rhs: [K, Np])."""
+    _shape_check(mesh, q)
+    _tracer_check(mesh, c, rhs)
+    p = phys.c()
+    _check(lib().dg_tracer_rhs(mesh.handle, C.byref(p), _ptr(q), _ptr(c), _ptr(rhs), _stream(stream)))
+
+
+def dg_tracer_stage(mesh: Mesh, phys: PhysParams, a, b, dt, qs, c0, cs, cout, stream=None):
+    """cout := a c0 + b (cs + dt R_C(qs, cs))."""
+    _shape_check(mesh, qs)
+    _tracer_check(mesh, c0, cs, cout)
+    p = phys.c()
+    _check(lib().dg_tracer_stage(mesh.handle, C.byref(p), a, b, dt, _ptr(qs), _ptr(c0), _ptr(cs), _ptr(cout),
+                                 _stream(stream)))
+
+
+def dg_tracer_mass(mesh: Mesh, c, stream=None):
+    _tracer_check(mesh, c)
+    out = (C.c_double * 1)()
+    _check(lib().dg_tracer_mass(mesh.handle, _ptr(c), out, _stream(stream)))
+    return out[0]
+
+
+def dg_project_fields(src: Mesh, dst: Mesh, q_from, q_to, stream=None):
+    """Conservative transfer of nvar fields [nvar, K, Np] (or one field [K, Np])."""
+    nv = 1 if q_from.dim() == 2 else int(q_from.shape[0])
+    for t, m in ((q_from, src), (q_to, dst)):
+        shape = (m.K, m.Np) if nv == 1 and t.dim() == 2 else (nv, m.K, m.Np)
+        if tuple(t.shape) != shape:
+            raise ValueError(f"field shape {tuple(t.shape)} != {shape}")
+    _check(lib().dg_project_fields(src.handle, dst.handle, nv, _ptr(q_from), _ptr(q_to), _stream(stream)))
+
+
+def ssp_rk3_step_tracer(mesh: Mesh, phys: PhysParams, dt, q, q1, q2, c, c1, c2, stream=None):
+    """One SSP-RK3 step of the Euler state and a passive tracer, in place on q and
+    c (stage buffers q1, q2, c1, c2): each tracer stage runs before the Euler stage
+    that could overwrite its input."""
+    dg_tracer_stage(mesh, phys, *SSP_RK3[0], dt, q, c, c, c1, stream)
+    dg_rk_stage(mesh, phys, *SSP_RK3[0], dt, q, q, q1, stream)
+    dg_tracer_stage(mesh, phys, *SSP_RK3[1], dt, q1, c, c1, c2, stream)
+    dg_rk_stage(mesh, phys, *SSP_RK3[1], dt, q, q1, q2, stream)
+    dg_tracer_stage(mesh, phys, *SSP_RK3[2], dt, q2, c, c2, c, stream)
+    dg_rk_stage(mesh, phys, *SSP_RK3[2], dt, q, q2, q, stream)
 
 
 def dg_rhs_adjoint(mesh: Mesh, phys: PhysParams, q, lam, qbar, stream=None):
