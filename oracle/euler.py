@@ -78,6 +78,7 @@ class Phys:
     theta0: float = 300.0
     rho0: float = 1.0
     Theta0: float = 300.0
+    mu: float = 0.0          # artificial viscosity (m^2/s), 0: none
 
     @property
     def R(self):
@@ -334,7 +335,79 @@ class Operator:
         return R
 
     def rhs(self, q):
-        return self.volume(q) + self.surface(q)
+        R = self.volume(q) + self.surface(q)
+        if self.phys.mu > 0.0:
+            R = R + self.viscous(q)
+        return R
+
+    # ------------------------------------------------------------------ artificial viscosity
+    def _central_face_terms(self, X, which, wall_zero_flux):
+        """Lifted face terms lift * sgn * (X* - X-) of a 5-variable field on the faces
+        normal to axis d of every leaf, for X = which(d) (a tensor [5, K, ...]):
+        X* = 1/2 (X- + X+) at conforming faces; at walls X* = X- (gradient pass) or
+        X*.n = 0 (flux pass, wall_zero_flux); on hanging faces the central average is
+        formed on the mortars, (I_a x I_b) X_coarse with X_fine, the fine side takes it
+        there and the coarse side its projection sum_ab (R_a x R_b).  Returns the
+        contributions embedded at the face nodes, [3][5, K, ...] (one per axis)."""
+        N, K = self.N, self.K
+        nf = (N + 1) ** 2
+        lift = 2.0 / self.wN / self.h
+        out = []
+        for d in range(3):
+            Xd = which(d)
+            delta = {f: torch.zeros(5, K, nf, dtype=F64) for f in (2 * d, 2 * d + 1)}
+            sel = self.conf[:, 2] == d
+            if bool(sel.any()):
+                eM, eP = self.conf[sel, 0], self.conf[sel, 1]
+                XL = face_slice(Xd, 2 * d + 1, N)[:, eM]
+                XR = face_slice(Xd, 2 * d, N)[:, eP]
+                avg = 0.5 * (XL + XR)
+                delta[2 * d + 1] = delta[2 * d + 1].index_add(1, eM, avg - XL)      # sgn = +1
+                delta[2 * d] = delta[2 * d].index_add(1, eP, -(avg - XR))          # sgn = -1
+            for f in (2 * d, 2 * d + 1):
+                sgn = 1.0 if f % 2 else -1.0
+                sel = self.bnd[:, 1] == f
+                if bool(sel.any()) and wall_zero_flux:
+                    e = self.bnd[sel, 0]
+                    Xw = face_slice(Xd, f, N)[:, e]
+                    delta[f] = delta[f].index_add(1, e, sgn * (0.0 - Xw))
+                sel = self.hang[:, 1] == f
+                if not bool(sel.any()):
+                    continue
+                fo_ = f ^ 1
+                ec = self.hang[sel, 0]
+                Xc = face_slice(Xd, f, N)[:, ec]
+                proj = torch.zeros_like(Xc)
+                for quad in range(4):
+                    a, b = quad & 1, quad >> 1
+                    ef = self.hang[sel, 2 + quad]
+                    Xf = face_slice(Xd, fo_, N)[:, ef]
+                    avg = 0.5 * (interp2(self.I[a], self.I[b], Xc, N) + Xf)
+                    proj = proj + interp2(self.Rm[a], self.Rm[b], avg, N)
+                    delta[fo_] = delta[fo_].index_add(1, ef, -sgn * (avg - Xf))    # n_f = -n_c
+                delta[f] = delta[f].index_add(1, ec, sgn * (proj - Xc))
+            T = torch.zeros(5, K, N + 1, N + 1, N + 1, dtype=F64)
+            for f in (2 * d, 2 * d + 1):
+                T = T + face_embed(delta[f] * lift[None, :, d, None], f, N, K)
+            out.append(T)
+        return out
+
+    def viscous(self, q):
+        """Artificial viscosity div(mu grad q') of every perturbation variable (section
+        4.3 applies mu = 1.5 m^2/s to the rising bubble; the form is a reading), by the
+        two-pass central scheme: sigma_d = (2/h_d) D_d q' + lifted (q* - q-) n_d, then
+        R = (2/h_d) D_d (mu sigma_d) + lifted (G* - G-).n; walls carry no diffusive flux."""
+        mu = self.phys.mu
+        g2 = 2.0 / self.h
+        dq = [torch.einsum('im,vekjm->vekji', self.D, q), torch.einsum('jm,vekmi->vekji', self.D, q),
+              torch.einsum('km,vemji->vekji', self.D, q)]
+        Tq = self._central_face_terms(q, lambda d: q, wall_zero_flux=False)
+        sigma = [g2[None, :, d, None, None, None] * dq[d] + Tq[d] for d in range(3)]
+        G = [mu * s for s in sigma]
+        dG = [torch.einsum('im,vekjm->vekji', self.D, G[0]), torch.einsum('jm,vekmi->vekji', self.D, G[1]),
+              torch.einsum('km,vemji->vekji', self.D, G[2])]
+        TG = self._central_face_terms(None, lambda d: G[d], wall_zero_flux=True)
+        return sum(g2[None, :, d, None, None, None] * dG[d] + TG[d] for d in range(3))
 
 
 # ----------------------------------------------------------------------------- passive tracer

@@ -82,7 +82,7 @@ def phys_for(periodic, **kw):
 def oracle_phys(p):
     """oracle Phys with the same constants as a binding PhysParams."""
     return eu.Phys(cp=p.cp, cv=p.cv, P0=p.P0, g=p.g, background=p.background,
-                   theta0=p.theta0, rho0=p.rho0, Theta0=p.Theta0)
+                   theta0=p.theta0, rho0=p.rho0, Theta0=p.Theta0, mu=p.mu)
 
 
 def oracle_desc(N, nroot, max_level, lo, hi, periodic):
