@@ -92,13 +92,20 @@ typedef struct {
  * DG_NC_POINTWISE (the fine side solves its Riemann problem against the coarse
  * polynomial at its nodes, the coarse side against the fine polynomial at its
  * nodes, averaged over the quadrants on a shared mid-line, with no projection;
- * the adjoint calls return DG_EUNSUPPORTED for it). */
+ * the adjoint calls return DG_EUNSUPPORTED for it).  mu >= 0 is an artificial
+ * viscosity in m^2/s (section 4.3 runs the rising bubble with mu = 1.5): when
+ * positive, dg_rhs and dg_rk_stage add div(mu grad q') of every perturbation
+ * variable (a reading: the paper gives the coefficient, not the operator),
+ * discretised by the two-pass central scheme with mortars on hanging faces and
+ * no diffusive flux through walls; the adjoint calls return DG_EUNSUPPORTED for
+ * mu > 0, and the passive tracer is not diffused. */
 typedef struct {
     double cp, cv, P0, g;
     int32_t background;
     int32_t precision;
     double theta0, rho0, Theta0;
     int32_t nonconforming;
+    double mu;
 } dg_phys;
 
 typedef struct {

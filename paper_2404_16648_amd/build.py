@@ -33,6 +33,7 @@ SOURCES = [
     ("abi.cpp", "hip"),
     ("kernels.hip", "hip"),
     ("tracer.hip", "hip"),
+    ("viscous.hip", "hip"),
 ]
 
 

@@ -58,6 +58,8 @@ void free_device(dg_mesh* m) {
     m->d_mort = nullptr;
     m->d_mortC = nullptr;
     m->d_flags = nullptr;
+    if (m->d_sigma) (void)hipFree(m->d_sigma);
+    m->d_sigma = nullptr;
 }
 
 // byte offsets of the arrays in a mesh's one device block, 256-byte aligned;
@@ -303,6 +305,7 @@ dg_status check_phys(const dg_phys* p) {
     if (p->precision != DG_FP64 && p->precision != DG_MIXED) return fail(DG_EINVAL, "unknown precision");
     if (p->nonconforming != DG_NC_MORTAR && p->nonconforming != DG_NC_POINTWISE)
         return fail(DG_EINVAL, "unknown nonconforming-face scheme");
+    if (!(p->mu >= 0.0) || !std::isfinite(p->mu)) return fail(DG_EINVAL, "need a finite mu >= 0");
     return DG_OK;
 }
 
@@ -374,6 +377,31 @@ BinomCoef binom_coef(const dg_phys* p) {
         b.c[k - 1] = (double)c;
     }
     return b;
+}
+
+// the viscous gradient workspace [3][5][K][Np], allocated at the first call with
+// mu > 0 on this mesh (not while stream s is being captured into a graph)
+dg_status ensure_sigma(dg_mesh* m, hipStream_t s) {
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
+    if (m->d_sigma) return DG_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(DG_EINVAL, "the viscous workspace of this mesh is allocated by the first call with mu > 0, "
+                               "which must not be captured into a graph");
+    const size_t n1 = (size_t)m->h.desc.N + 1;
+    const size_t bytes = 15 * m->h.leaves.size() * n1 * n1 * n1 * sizeof(double);
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != m->device) HIP_TRY(hipSetDevice(m->device));
+    const hipError_t e = hipMalloc((void**)&m->d_sigma, bytes ? bytes : 256);
+    if (cur != m->device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) {
+        m->d_sigma = nullptr;
+        return fail(DG_ENOMEM, "viscous workspace: hipMalloc failed");
+    }
+    return DG_OK;
 }
 
 StageArgs stage_args(const dg_mesh* m, const dg_phys* p) {
@@ -573,6 +601,13 @@ static dg_status stage_common(const dg_mesh* mc, const dg_phys* phys, int mode, 
     args.b = b;
     args.dt = dt;
     HIP_TRY(launch_stage(m->h.desc.N, mode, phys->precision == DG_MIXED, args, s));
+    if (phys->mu > 0.0) {
+        // the stage is linear in R: add b dt R_visc(qs) (R_visc for dg_rhs) to its output
+        if ((st = ensure_sigma(m, s))) return st;
+        ViscArgs va{qs, m->d_sigma, out, m->d_mort, m->d_ops, m->d_geo, m->d_srec, m->d_hang, m->n_hang, args.K,
+                    phys->mu, mode == MODE_RHS ? 1.0 : b * dt};
+        HIP_TRY(launch_viscous(m->h.desc.N, va, s));
+    }
     return DG_OK;
 }
 
@@ -694,6 +729,7 @@ static dg_status adjoint_common(const dg_mesh* mc, const dg_phys* phys, int mode
     if ((st = check_wrap(mc, phys))) return st;
     if (phys->nonconforming != DG_NC_MORTAR)
         return fail(DG_EUNSUPPORTED, "the adjoint is provided for the mortar scheme only");
+    if (phys->mu > 0.0) return fail(DG_EUNSUPPORTED, "the adjoint is provided without the artificial viscosity (mu = 0)");
     if (!q || !lam || !out) return fail(DG_EINVAL, "NULL field pointer");
     if (out == q || out == lam) return fail(DG_EINVAL, "output must not alias q or lam");
     if ((a1 != 0.0 && !w1) || (a2 != 0.0 && !w2)) return fail(DG_EINVAL, "NULL w1/w2 with a non-zero weight");

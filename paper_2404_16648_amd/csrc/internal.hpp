@@ -87,4 +87,5 @@ struct dg_mesh {
     int64_t red_len = 0;
     int8_t* d_flags = nullptr;    // [K]
     double* d_eta = nullptr;      // [K]
+    double* d_sigma = nullptr;    // [3][5][K][Np]: viscous gradient (own allocation, at first use)
 };

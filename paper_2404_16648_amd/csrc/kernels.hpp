@@ -145,6 +145,34 @@ struct TracerMortArgs {
     int32_t pointwise;
 };
 
+// artificial viscosity, added to a stage's output: out += scale R_visc(q) with
+// R_visc = div(mu grad q) in the two-pass central form
+struct ViscArgs {
+    const double* q;       // [5][K][Np] stage input
+    double* sigma;         // [3][5][K][Np] workspace: the gradient, one field per axis
+    double* out;           // [5][K][Np], accumulated into
+    double* mort;          // [n_hang][5][5][NF] workspace: lifted central mortar terms
+    const double* ops;
+    const double* geo;
+    const int32_t* srec;   // [K][kStageRec]
+    const int32_t* hang;   // [n_hang][6]
+    int64_t n_hang, K;
+    double mu, scale;
+};
+
+// central averages on the mortars of the hanging faces: x + d axis_stride is the
+// 5-variable field of the face's normal axis d; out as ViscArgs::mort, times mul
+struct CentralMortArgs {
+    const double* x;
+    int64_t axis_stride;
+    double* out;
+    const double* ops;
+    const double* geo;
+    const int32_t* hang;
+    int64_t n_hang, K;
+    double mul;
+};
+
 struct BudgetArgs {
     const double* q;
     const double* bg;
@@ -195,6 +223,8 @@ hipError_t launch_budgets(int N, const BudgetArgs& a, int nblk, double* out_dev,
 hipError_t launch_indicator(int N, const IndArgs& a, hipStream_t s);
 hipError_t launch_tracer_mortar(int N, const TracerMortArgs& a, hipStream_t s);
 hipError_t launch_tracer_stage(int N, int mode, const TracerArgs& a, hipStream_t s);
+// the two viscous passes (mortars, gradient; mortars, divergence) on stream s
+hipError_t launch_viscous(int N, const ViscArgs& a, hipStream_t s);
 // integral of c [K][Np] with the weights J_e W_n (w the 1-D LGL weights): nblk <= budget_blocks(K)
 // blocks leave 2 doubles each in partial, the total goes to out_dev[0]
 hipError_t launch_weighted_sum(int N, const double* c, const double* geo, const double* w, int64_t K, int nblk,

@@ -60,7 +60,7 @@ class Phys(C.Structure):
     _fields_ = [("cp", C.c_double), ("cv", C.c_double), ("P0", C.c_double), ("g", C.c_double),
                 ("background", C.c_int32), ("precision", C.c_int32),
                 ("theta0", C.c_double), ("rho0", C.c_double), ("Theta0", C.c_double),
-                ("nonconforming", C.c_int32)]
+                ("nonconforming", C.c_int32), ("mu", C.c_double)]
 
 
 class MeshInfo(C.Structure):
@@ -161,10 +161,11 @@ class PhysParams:
     rho0: float = 1.0
     Theta0: float = 300.0
     nonconforming: int = DG_NC_MORTAR
+    mu: float = 0.0          # artificial viscosity (m^2/s)
 
     def c(self):
         return Phys(self.cp, self.cv, self.P0, self.g, self.background, self.precision,
-                    self.theta0, self.rho0, self.Theta0, self.nonconforming)
+                    self.theta0, self.rho0, self.Theta0, self.nonconforming, self.mu)
 
 
 class Mesh:
