@@ -314,17 +314,17 @@ def forced_cycle(dg, torch, mesh, q, reps=5):
             "same_leaves_after_cycle": bool(mr.K == mesh.K)}
 
 
-def rtb_long_run(dg, torch, t_end=100.0, regrid=25.0, dt=0.0025, seg=100):
+def rtb_long_run(dg, torch, t_end=100.0, regrid=25.0, dt=0.0025, seg=100, mu=1.5):
     """Rising-thermal-bubble-style long run (section 4.3's setting, quasi-2-D: 1000 m x
     1000 m in x, z, one 100 m root periodic along y; 10 x 1 x 10 roots, N = 4, two
     levels where |theta'| > 0.05 K, warm bubble 0.5 K, radius 250 m at (500, 350) m,
-    walls in x and z; no artificial viscosity), SSP-RK3 with a regrid every `regrid`
+    walls in x and z; artificial viscosity mu = 1.5 m^2/s as in that section), SSP-RK3 with a regrid every `regrid`
     seconds.  Steps between regrids run as replays of a HIP graph of `seg` steps; a
     progress line goes to stderr at every regrid.  Reports the relative change of
     the total mass and energy over the run."""
     if t_end <= 0:
         return {"skipped": True}
-    ph = dg.PhysParams()
+    ph = dg.PhysParams(mu=mu)
     thr = 0.05
     mesh, q = dg.initial_mesh(4, (10, 1, 10), 2, (0.0, 0.0, 0.0), (1000.0, 100.0, 1000.0), (0, 1, 0), ph,
                               (0.5, (500.0, 50.0, 350.0), (250.0, 0.0, 250.0)), dg.DG_IND_THETA, thr)
@@ -353,7 +353,7 @@ def rtb_long_run(dg, torch, t_end=100.0, regrid=25.0, dt=0.0025, seg=100):
                   f"mass change {(b1[1] - b0[1]) / b0[1]:.2e}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return {"t_end_s": t_end, "regrid_s": regrid, "dt_s": dt, "steps": steps, "regrids": nreg - 1,
+    return {"t_end_s": t_end, "regrid_s": regrid, "dt_s": dt, "mu_m2_s": mu, "steps": steps, "regrids": nreg - 1,
             "leaves_min_max": [min(leaves), max(leaves)], "wall_s": wall,
             "mass_rel_change": (b1[1] - b0[1]) / b0[1], "energy_rel_change": (b1[3] - b0[3]) / abs(b0[3])}
 

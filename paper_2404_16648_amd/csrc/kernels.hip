@@ -279,7 +279,8 @@ k_stage(const StageArgs A) {
     __shared__ double sFr[MIX ? 15 : 1];  // MIX: reference flux [direction][variable]
 
     const int64_t K = A.K;
-    const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t e = A.order ? (int64_t)A.order[bid] : bid;
     const int32_t* const rec = A.srec + e * kStageRec;
     const int t = threadIdx.x;
     const double gamma = A.gamma;
@@ -303,6 +304,17 @@ k_stage(const StageArgs A) {
         tfs[f] = rec[f];
         nbs[f] = rec[6 + f];
         hss[f] = rec[12 + f];
+    }
+    if (A.skip_hanging) {
+        // this launch leaves the leaves with a hanging face to a second launch that
+        // follows the mortar pre-pass (uniform: the whole workgroup returns)
+        bool hanging = false;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const int type = tfs[f] & 0xff;
+            hanging = hanging || type == FT_FINE || type == FT_COARSE;
+        }
+        if (hanging) return;
     }
     if (t < 6) {
         sType[t] = rec[t];
@@ -427,6 +439,24 @@ k_stage(const StageArgs A) {
     }
     __syncthreads();
 
+    // q0 of the update (stage form, a != 0): requested before the faces when the
+    // tile came in one batch, so its latency runs under the face work
+    double q0v[5] = {0, 0, 0, 0, 0};
+    const bool use_q0 = (MODE == MODE_RK || MODE == MODE_RK_STREAM) && A.a != 0.0;
+    auto load_q0 = [&]() {
+        if (use_q0 && t < NP)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const double* src = reinterpret_cast<const double*>(
+                    reinterpret_cast<const char*>(A.q0 + (int64_t)v * KNP) + (eoff + (uint32_t)t * 8u));
+                if constexpr (MODE == MODE_RK_STREAM)
+                    q0v[v] = __builtin_nontemporal_load(src);
+                else
+                    q0v[v] = *src;
+            }
+    };
+    if (GATHER) load_q0();
+
     // ---- faces, every (face, node) item of a wall or conforming face: Rusanov flux
     // from the own trace (tile) and the neighbour trace (sS), lifted in place;
     // hanging faces already hold the pre-pass contributions
@@ -512,18 +542,8 @@ k_stage(const StageArgs A) {
 
     // ---- volume term: R = S - sum_d (2/h_d) D_d F^d, fluxes staged in LDS; q from
     // the tile, q0 of the update (stage form, a != 0) loaded now, used at the end
-    double q[5] = {0, 0, 0, 0, 0}, q0v[5] = {0, 0, 0, 0, 0};
-    const bool use_q0 = MODE != MODE_RHS && A.a != 0.0;
-    if (use_q0 && t < NP)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            const double* src = reinterpret_cast<const double*>(reinterpret_cast<const char*>(A.q0 + (int64_t)v * KNP) +
-                                                                (eoff + (uint32_t)t * 8u));
-            if constexpr (MODE == MODE_RK_STREAM)
-                q0v[v] = __builtin_nontemporal_load(src);
-            else
-                q0v[v] = *src;
-        }
+    double q[5] = {0, 0, 0, 0, 0};
+    if (!GATHER) load_q0();
     double rinv = 0.0, Pp = 0.0, Th = 0.0;
     double R[5] = {0, 0, 0, 0, 0};
     if (t < NP) {
@@ -589,7 +609,88 @@ k_stage(const StageArgs A) {
             }
         }
     };
-    if (ALL3) {
+    // float64: the contraction by lines.  One task per (variable, line along d) reads
+    // the line's N+1 fluxes once, forms the N+1 sums of D F along it (D from the
+    // uniform operator table: scalar operands) and writes them over the line in
+    // place (lines are disjoint); after a barrier every node adds -(2/h_d) times its
+    // own sum.  The same fma chains as a per-node contraction, with a fifth of its
+    // LDS reads and no per-lane reads of D, which sits in scalar registers: for
+    // N <= 4 (at higher orders D and the line no longer fit the register budget,
+    // and the per-node contraction below is used).
+    constexpr bool LINES = !MIX && N <= 4;
+    auto lines = [&](int d, int plane) {
+        const int stride = d == 0 ? 1 : d == 1 ? N1 : NF;
+        for (int task = t; task < 5 * NF; task += NT) {
+            const int v = task / NF, l = task - v * NF;
+            const int base = d == 0 ? N1 * l : d == 1 ? (l % N1) + NF * (l / N1) : l;
+            double* const F = sW + (plane * 5 + v) * NP + base;
+            double f[N1];
+#pragma unroll
+            for (int m = 0; m < N1; ++m) f[m] = F[m * stride];
+#pragma unroll
+            for (int o = 0; o < N1; ++o) {
+                double acc = 0.0;
+#pragma unroll
+                for (int m = 0; m < N1; ++m) acc = fma(A.ops[o * N1 + m], f[m], acc);
+                F[o * stride] = acc;
+            }
+        }
+    };
+    auto gather_line_sums = [&](int d, int plane) {
+        const double g2 = A.geo[e * 4 + d];  // uniform: a scalar load
+        const double* const S = sW + plane * 5 * NP + t;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) R[v] = fma(-g2, S[v * NP], R[v]);
+    };
+    if constexpr (LINES) {
+        if (ALL3) {
+            if (t < NP) {
+                put_flux(0, 0);
+                put_flux(1, 1);
+                put_flux(2, 2);
+            }
+            __syncthreads();
+            lines(0, 0);
+            lines(1, 1);
+            lines(2, 2);
+            __syncthreads();
+            if (t < NP) {
+                gather_line_sums(0, 0);
+                gather_line_sums(1, 1);
+                gather_line_sums(2, 2);
+            }
+        } else if (StageLds<N, MIX>::PLANES == 10) {
+            if (t < NP) {
+                put_flux(0, 0);
+                put_flux(1, 1);
+            }
+            __syncthreads();
+            lines(0, 0);
+            lines(1, 1);
+            __syncthreads();
+            if (t < NP) {
+                gather_line_sums(0, 0);
+                gather_line_sums(1, 1);
+                put_flux(2, 0);  // the node's own entries: read above, then overwritten
+            }
+            __syncthreads();
+            lines(2, 0);
+            __syncthreads();
+            if (t < NP) gather_line_sums(2, 0);
+        } else {
+            if (t < NP) put_flux(0, 0);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                __syncthreads();
+                lines(d, 0);
+                __syncthreads();
+                if (t < NP) {
+                    gather_line_sums(d, 0);
+                    if (d < 2) put_flux(d + 1, 0);
+                }
+            }
+        }
+    } else if (ALL3) {
         if (t < NP) {
             put_flux(0, 0);
             put_flux(1, 1);
@@ -633,22 +734,17 @@ k_stage(const StageArgs A) {
         const double* px = sS + (i == N ? 5 : 0) * NF + j + N1 * k;
         const double* py = sS + (j == N ? 15 : 10) * NF + i + N1 * k;
         const double* pz = sS + (k == N ? 25 : 20) * NF + i + N1 * j;
-        const bool ox = i == 0 || i == N, oy = j == 0 || j == N, oz = k == 0 || k == N;
+        // R - w a with w = 1 on a face of the axis and 0 off it: one fma per term
+        // (exactly R - a, or R), one select per axis
+        const double wx = (i == 0 || i == N) ? -1.0 : -0.0;
+        const double wy = (j == 0 || j == N) ? -1.0 : -0.0;
+        const double wz = (k == 0 || k == N) ? -1.0 : -0.0;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            const double a = px[v * NF];
-            R[v] -= ox ? a : 0.0;
-        }
+        for (int v = 0; v < 5; ++v) R[v] = fma(wx, px[v * NF], R[v]);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            const double a = py[v * NF];
-            R[v] -= oy ? a : 0.0;
-        }
+        for (int v = 0; v < 5; ++v) R[v] = fma(wy, py[v * NF], R[v]);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            const double a = pz[v * NF];
-            R[v] -= oz ? a : 0.0;
-        }
+        for (int v = 0; v < 5; ++v) R[v] = fma(wz, pz[v * NF], R[v]);
     }
     const int64_t base = e * NP + t;
     if (MODE == MODE_RHS) {
@@ -1454,9 +1550,20 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_indicator(const IndArgs A) {
     }
 
 hipError_t launch_stage(int N, int mode, bool mixed, const StageArgs& a, hipStream_t s) {
-    if (a.K <= 0) return hipSuccess;
-    const dim3 grid((unsigned)a.K);
+    const int64_t nblk = a.order ? a.nblk : a.K;
+    if (nblk <= 0) return hipSuccess;
+    const dim3 grid((unsigned)nblk);
     const bool stream = mode == MODE_RK && a.stream_io;
+    // a == 0 (the first SSP-RK3 stage): q0 is not read, and the kernel without it
+    // keeps the register count of the right-hand side (one more wave per SIMD)
+    if (mode == MODE_RK && a.a == 0.0) {
+        if (mixed) {
+            DG_DISPATCH_N(N, (k_stage<NN, MODE_RK_NOQ0, true><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        } else {
+            DG_DISPATCH_N(N, (k_stage<NN, MODE_RK_NOQ0, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        }
+        return hipGetLastError();
+    }
     if (mixed) {
         if (mode == MODE_RHS) {
             DG_DISPATCH_N(N, (k_stage<NN, MODE_RHS, true><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));

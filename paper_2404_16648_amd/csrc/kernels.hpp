@@ -21,6 +21,7 @@ struct BinomCoef {
 constexpr int MODE_RHS = 0;
 constexpr int MODE_RK = 1;
 constexpr int MODE_RK_STREAM = 2;  // MODE_RK with q0 and the output streamed (non-temporal)
+constexpr int MODE_RK_NOQ0 = 3;    // MODE_RK for a == 0: q0 never read (fewer registers)
 
 // per-leaf record of the stage kernel's face tables: per face f its type (f), first
 // neighbour (6 + f) and hanging-face row or -1 (12 + f); two ints of padding
@@ -38,6 +39,11 @@ struct StageArgs {
     const int32_t* hslot;  // [K][6]: row of the hanging-face table, or -1
     const double* mort;    // [n_hang][5][5][NF]: lifted mortar contributions (k_mortar)
     const int32_t* srec;   // [K][kStageRec]: face tables, one record per leaf
+    // leaves of the launch: order == nullptr: all K leaves (skip_hanging: those with
+    // a hanging face return at once); otherwise the nblk leaves order[0..nblk)
+    const int32_t* order;
+    int64_t nblk;
+    int32_t skip_hanging;
     int64_t K;
     double a, b, dt;
     double gamma, g;
