@@ -1271,19 +1271,29 @@ __global__ void k_node_coords(int64_t K, int N1, const double* c1d, double* xyz)
 // k_family_reduce: one leaf = (A x A x A) applied to a family block, A an
 //   (N+1) x (2N+2) matrix: coarsening, A = [R_0 | R_1]; transpose of refinement,
 //   A = [I_0^T | I_1^T].
-// Three separable passes per variable; kept leaves are copied.  The block of a
-// refined family is the one at child 0; the others return at once.  The
-// opposite direction (one leaf to its children) is k_expand, one child per block.
+// Three separable passes; one workgroup per plan entry and field, so a merged
+// family's work is spread over as many workgroups as it has fields; kept leaves
+// are copied.  The block of a refined family is the one at child 0; the others
+// return at once.  The opposite direction (one leaf to its children) is
+// k_expand, one child and field per block.
 
-// copy of a kept leaf: forward q_to[e] = q_from[src]; transpose qbar_from[src] = qbar_to[e]
+// copy of a kept leaf, fields v0 .. v0 + nf - 1 (nf <= 5, all loads issued before the
+// stores): forward q_to[e] = q_from[src]; transpose qbar_from[src] = qbar_to[e]
 template <int N, bool ADJ>
-__device__ __forceinline__ void xfer_copy(const XferArgs& A, int64_t e, int64_t src, int t) {
+__device__ __forceinline__ void xfer_copy(const XferArgs& A, int64_t e, int64_t src, int v0, int nf, int t) {
     constexpr int NP = Sz<N>::NP;
     const int64_t li = ADJ ? e : src, lo = ADJ ? src : e;
-    if (t < NP)
-        for (int v = 0; v < A.nvar; ++v) A.qout[v * A.Kout * NP + lo * NP + t] = A.qin[v * A.Kin * NP + li * NP + t];
+    if (t >= NP) return;
+    double x[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f)
+        if (f < nf) x[f] = A.qin[(v0 + f) * A.Kin * NP + li * NP + t];
+#pragma unroll
+    for (int f = 0; f < 5; ++f)
+        if (f < nf) A.qout[(v0 + f) * A.Kout * NP + lo * NP + t] = x[f];
 }
 
+// field blockIdx.y of one plan entry per workgroup
 template <int N, bool ADJ>
 __global__ void __launch_bounds__(Sz<N>::NT) k_family_reduce(const XferArgs A) {
     constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
@@ -1293,82 +1303,87 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_family_reduce(const XferArgs A) {
     __shared__ double sA[N1 * M];      // sA[i M + m]
     double* const s2 = sF;             // [M][N1][N1]
     const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
+    const int v = (int)blockIdx.y;
     const int t = threadIdx.x;
     const int64_t src = A.src[e];
     const int kind = A.kind[e];
-    if (kind == DG_KIND_COPY) {  // uniform over the block
-        xfer_copy<N, ADJ>(A, e, src, t);
+    if (kind == DG_KIND_COPY) {  // uniform over the block: every field, by the block of field 0
+        if (v == 0) xfer_copy<N, ADJ>(A, e, src, 0, A.nvar, t);
         return;
     }
     if (ADJ && kind != 0) return;  // refined family: handled by the block of child 0
     const int64_t fine0 = ADJ ? e : src, lo = ADJ ? src : e;
     const int64_t KinNP = A.Kin * NP, KoutNP = A.Kout * NP;
+    const int ic = t % N1, jc = (t / N1) % N1, kc = t / NF;
+    // the eight children's values at this node, requested before the operator is staged
+    double pf[8];
+    if (t < NP)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) pf[c] = A.qin[v * KinNP + (fine0 + c) * NP + t];
     for (int x = t; x < N1 * M; x += NT) {
         const int i = x / M, m = x % M, h = m / N1, r = m % N1;
         sA[x] = ADJ ? A.ops[(1 + h) * NF + r * N1 + i]    // I_h^T[i][r]
                     : A.ops[(3 + h) * NF + i * N1 + r];   // R_h[i][r]
     }
-    const int ic = t % N1, jc = (t / N1) % N1, kc = t / NF;
-    double pf[8];
     if (t < NP)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) pf[c] = A.qin[(fine0 + c) * NP + t];
-#pragma unroll 1
-    for (int v = 0; v < A.nvar; ++v) {
-        __syncthreads();
-        if (t < NP)
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const int I = (c & 1) * N1 + ic, J = ((c >> 1) & 1) * N1 + jc, Kf = (c >> 2) * N1 + kc;
-                sF[(Kf * M + J) * M + I] = pf[c];
-            }
-        __syncthreads();
-        if (v + 1 < A.nvar && t < NP)  // the next variable's loads, in flight during the passes
-#pragma unroll
-            for (int c = 0; c < 8; ++c) pf[c] = A.qin[(v + 1) * KinNP + (fine0 + c) * NP + t];
-        // x: s1[K'][J'][i] = sum_m A[i][m] F[K'][J'][m]
-        for (int x = t; x < N1 * M * M; x += NT) {
-            const int i = x % N1, row = x / N1;
-            double acc = 0.0;
-#pragma unroll
-            for (int m = 0; m < M; ++m) acc = fma(sA[i * M + m], sF[row * M + m], acc);
-            s1[x] = acc;
+        for (int c = 0; c < 8; ++c) {
+            const int I = (c & 1) * N1 + ic, J = ((c >> 1) & 1) * N1 + jc, Kf = (c >> 2) * N1 + kc;
+            sF[(Kf * M + J) * M + I] = pf[c];
         }
-        __syncthreads();
-        // y: s2[K'][j][i] = sum_m A[j][m] s1[K'][m][i]
-        for (int x = t; x < N1 * N1 * M; x += NT) {
-            const int i = x % N1, j = (x / N1) % N1, kk = x / NF;
-            double acc = 0.0;
+    __syncthreads();
+    // x: s1[K'][J'][i] = sum_m A[i][m] F[K'][J'][m]
+    for (int x = t; x < N1 * M * M; x += NT) {
+        const int i = x % N1, row = x / N1;
+        double acc = 0.0;
 #pragma unroll
-            for (int m = 0; m < M; ++m) acc = fma(sA[j * M + m], s1[(kk * M + m) * N1 + i], acc);
-            s2[x] = acc;
-        }
-        __syncthreads();
-        // z: out[k][j][i] = sum_m A[k][m] s2[m][j][i]
-        if (t < NP) {
-            double acc = 0.0;
+        for (int m = 0; m < M; ++m) acc = fma(sA[i * M + m], sF[row * M + m], acc);
+        s1[x] = acc;
+    }
+    __syncthreads();
+    // y: s2[K'][j][i] = sum_m A[j][m] s1[K'][m][i]
+    for (int x = t; x < N1 * N1 * M; x += NT) {
+        const int i = x % N1, j = (x / N1) % N1, kk = x / NF;
+        double acc = 0.0;
 #pragma unroll
-            for (int m = 0; m < M; ++m) acc = fma(sA[kc * M + m], s2[m * NF + ic + N1 * jc], acc);
-            A.qout[v * KoutNP + lo * NP + t] = acc;
-        }
+        for (int m = 0; m < M; ++m) acc = fma(sA[j * M + m], s1[(kk * M + m) * N1 + i], acc);
+        s2[x] = acc;
+    }
+    __syncthreads();
+    // z: out[k][j][i] = sum_m A[k][m] s2[m][j][i]
+    if (t < NP) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < M; ++m) acc = fma(sA[kc * M + m], s2[m * NF + ic + N1 * jc], acc);
+        A.qout[v * KoutNP + lo * NP + t] = acc;
     }
 }
 
 // One child of a family per workgroup: child c = (a, b, c') of leaf li gets
-// (B_a x B_b x B_c') applied to it, three separable passes per variable:
-// refinement, B_h = I_h (grid over the plan's child entries); transpose of
-// coarsening, B_h = R_h^T (grid over the plan's entries x 8 children).
-template <int N, bool ADJ>
+// (B_a x B_b x B_c') applied to it, three separable passes: refinement,
+// B_h = I_h (grid over the plan's child entries); transpose of coarsening,
+// B_h = R_h^T (grid over the plan's entries x 8 children).  Kept leaves are
+// copied (by the blocks of child index 0).  FB fields per workgroup (grid z over
+// the groups of FB fields), their loads issued together and every pass run over
+// all FB at once, so a workgroup has FB times the bytes in flight and the same
+// three barriers; the kernel is bound by the bytes in flight per CU (the counters
+// show exactly the algorithmic traffic).  (One workgroup per family producing all
+// eight children, with the leaf read once, measured slower: 2576 such workgroups
+// of the density current against 20608.)
+template <int N, bool ADJ, int FB>
 __global__ void __launch_bounds__(Sz<N>::NT) k_expand(const XferArgs A) {
     constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
-    __shared__ double sIn[NP], s1[NP], s2[NP];
+    __shared__ double sIn[FB * NP], s1[FB * NP];  // the second pass writes over sIn
     __shared__ double sM[3 * NF];  // the 1-D operator along x, y, z: sM[d NF + r (N+1) + col]
+    double* const s2 = sIn;
     const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
+    const int v0 = (int)blockIdx.z * FB;
+    const int nf = A.nvar - v0 < FB ? A.nvar - v0 : FB;
     const int t = threadIdx.x;
     const int64_t src = A.src[e];
     const int kind = A.kind[e];
     if (kind == DG_KIND_COPY) {  // uniform over the block
-        if (blockIdx.y == 0) xfer_copy<N, ADJ>(A, e, src, t);
+        if (blockIdx.y == 0) xfer_copy<N, ADJ>(A, e, src, v0, nf, t);
         return;
     }
     int c;
@@ -1384,45 +1399,53 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_expand(const XferArgs A) {
         li = e;
         lo = src + c;
     }
+    const int64_t KinNP = A.Kin * NP, KoutNP = A.Kout * NP;
+    const int i = t % N1, j = (t / N1) % N1, k = t / NF;
+    double p[FB];  // requested before the operator is staged
+#pragma unroll
+    for (int f = 0; f < FB; ++f) p[f] = (t < NP && f < nf) ? A.qin[(v0 + f) * KinNP + li * NP + t] : 0.0;
     for (int x = t; x < 3 * NF; x += NT) {
         const int d = x / NF, r = (x % NF) / N1, col = x % N1, h = (c >> d) & 1;
         sM[x] = ADJ ? A.ops[(3 + h) * NF + col * N1 + r]    // R_h^T[r][col]
                     : A.ops[(1 + h) * NF + r * N1 + col];   // I_h[r][col]
     }
-    const int64_t KinNP = A.Kin * NP, KoutNP = A.Kout * NP;
-    const int i = t % N1, j = (t / N1) % N1, k = t / NF;
-    double p[5] = {0, 0, 0, 0, 0};  // the leaf's values at this node (up to five fields), loaded at once
     if (t < NP)
 #pragma unroll
-        for (int v = 0; v < 5; ++v)
-            if (v < A.nvar) p[v] = A.qin[v * KinNP + li * NP + t];
-#pragma unroll 1
-    for (int v = 0; v < A.nvar; ++v) {
-        __syncthreads();
-        if (t < NP) sIn[t] = p[v];
-        __syncthreads();
-        if (t < NP) {
+        for (int f = 0; f < FB; ++f) sIn[f * NP + t] = p[f];
+    __syncthreads();
+    if (t < NP)
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
             double acc = 0.0;
 #pragma unroll
-            for (int m = 0; m < N1; ++m) acc = fma(sM[i * N1 + m], sIn[m + N1 * (j + N1 * k)], acc);
-            s1[t] = acc;
+            for (int m = 0; m < N1; ++m) acc = fma(sM[i * N1 + m], sIn[f * NP + m + N1 * (j + N1 * k)], acc);
+            s1[f * NP + t] = acc;
         }
-        __syncthreads();
-        if (t < NP) {
+    __syncthreads();
+    if (t < NP)
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
             double acc = 0.0;
 #pragma unroll
-            for (int m = 0; m < N1; ++m) acc = fma(sM[NF + j * N1 + m], s1[i + N1 * (m + N1 * k)], acc);
-            s2[t] = acc;
+            for (int m = 0; m < N1; ++m) acc = fma(sM[NF + j * N1 + m], s1[f * NP + i + N1 * (m + N1 * k)], acc);
+            s2[f * NP + t] = acc;
         }
-        __syncthreads();
-        if (t < NP) {
+    __syncthreads();
+    if (t < NP)
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+            if (f >= nf) break;
             double acc = 0.0;
 #pragma unroll
-            for (int m = 0; m < N1; ++m) acc = fma(sM[2 * NF + k * N1 + m], s2[i + N1 * (j + N1 * m)], acc);
-            A.qout[v * KoutNP + lo * NP + t] = acc;
+            for (int m = 0; m < N1; ++m) acc = fma(sM[2 * NF + k * N1 + m], s2[f * NP + i + N1 * (j + N1 * m)], acc);
+            A.qout[(v0 + f) * KoutNP + lo * NP + t] = acc;
         }
-    }
 }
+
+// fields per k_expand workgroup: all five (measured: density current refine
+// 65 -> 47 us, AMR bubble 41 -> 36 us against one field per workgroup)
+template <int N>
+constexpr int expand_fields() { return 5; }
 
 // ---------------------------------------------------------------- budgets
 
@@ -1662,24 +1685,27 @@ hipError_t launch_node_coords(int64_t K, int N, const double* c1d, double* xyz, 
     return hipGetLastError();
 }
 
+// one workgroup per plan entry and field (and child, where a family expands)
 hipError_t launch_refine(int N, bool adjoint, const XferArgs& a, hipStream_t s) {
     if (a.Kto <= 0) return hipSuccess;
-    const dim3 grid((unsigned)a.Kto);
+    if (a.nvar < 1 || a.nvar > 5) return hipErrorInvalidValue;
+    const unsigned nv = (unsigned)a.nvar;
     if (adjoint) {
-        DG_DISPATCH_N(N, (k_family_reduce<NN, true><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        DG_DISPATCH_N(N, (k_family_reduce<NN, true><<<dim3((unsigned)a.Kto, nv), dim3(Sz<NN>::NT), 0, s>>>(a)));
     } else {
-        DG_DISPATCH_N(N, (k_expand<NN, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        DG_DISPATCH_N(N, (k_expand<NN, false, expand_fields<NN>()><<<dim3((unsigned)a.Kto, 1, (nv + expand_fields<NN>() - 1) / expand_fields<NN>()), dim3(Sz<NN>::NT), 0, s>>>(a)));
     }
     return hipGetLastError();
 }
 
 hipError_t launch_coarsen(int N, bool adjoint, const XferArgs& a, hipStream_t s) {
     if (a.Kto <= 0) return hipSuccess;
-    const dim3 grid((unsigned)a.Kto);
+    if (a.nvar < 1 || a.nvar > 5) return hipErrorInvalidValue;
+    const unsigned nv = (unsigned)a.nvar;
     if (adjoint) {
-        DG_DISPATCH_N(N, (k_expand<NN, true><<<dim3((unsigned)a.Kto, 8), dim3(Sz<NN>::NT), 0, s>>>(a)));
+        DG_DISPATCH_N(N, (k_expand<NN, true, expand_fields<NN>()><<<dim3((unsigned)a.Kto, 8, (nv + expand_fields<NN>() - 1) / expand_fields<NN>()), dim3(Sz<NN>::NT), 0, s>>>(a)));
     } else {
-        DG_DISPATCH_N(N, (k_family_reduce<NN, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        DG_DISPATCH_N(N, (k_family_reduce<NN, false><<<dim3((unsigned)a.Kto, nv), dim3(Sz<NN>::NT), 0, s>>>(a)));
     }
     return hipGetLastError();
 }
