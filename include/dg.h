@@ -57,6 +57,9 @@ typedef int32_t dg_status;
 
 #define DG_BG_NEUTRAL   0    /* constant theta0: exner = 1 - g z/(cp theta0) */
 #define DG_BG_CONSTANT  1    /* rhobar = rho0, Thetabar = Theta0 everywhere  */
+#define DG_BG_ISOTHERMAL 2   /* temperature theta0 everywhere (section 4.4's
+                                shell): Pbar = P0 exp(-g z/(R theta0)),
+                                rhobar = Pbar/(R theta0); z = height */
 
 #define DG_FP64         0    /* every operation in float64 */
 #define DG_MIXED        1    /* volume flux contractions in float32, rest float64 */
@@ -84,6 +87,18 @@ typedef struct {
     double lo[3], hi[3];
     int32_t host_only;
 } dg_forest_desc;
+
+/* A cubed-sphere shell (section 3.4 spherical geometry, section 4.4 global
+ * tests): six equiangular panels of n x n elements, nz layers between the radii
+ * r_e and r_e + H, order N; elements are isoparametric (the mapping is
+ * interpolated at the LGL nodes).  Element e = ((p nz + ir) n + ib) n + ia for
+ * panel p, row ib, column ia, layer ir; reference axes: the panel's two angles,
+ * then outward.  host_only as for dg_forest_desc. */
+typedef struct {
+    int32_t N, n, nz;
+    double r_e, H;
+    int32_t host_only;
+} dg_sphere_desc;
 
 /* Gas constants (section 2.1: R = cp - cv, gamma = cp/cv, P = P0 (R Theta/P0)^gamma),
  * gravity g and the hydrostatic background (section 2.1 perturbation form;
@@ -167,6 +182,31 @@ typedef struct {
  * projections.  Host work only (the device copy is made at first GPU use). */
 dg_status dg_mesh_build(const dg_forest_desc* desc, const dg_mesh* prev, const int8_t* flags,
                         int32_t pass, dg_mesh** out);
+
+/* Build a uniform cubed-sphere shell mesh (sections 3.4, 4.4; the equiangular
+ * panels, their orientation and the element order are not in the paper).
+ * Walls at the bottom and top (mirror state), every lateral face conforming,
+ * across panel edges with the neighbour's face and orientation recorded.  The
+ * geometry is made on the host at first GPU use: node positions from the exact
+ * mapping, metric terms J a^i in the conservative curl form (so a uniform flow
+ * stays uniform up to rounding), the Jacobian, and per face node the unit
+ * normal and face Jacobian, taken for a shared face from the (leaf, face) pair
+ * that comes first so that both sides use bitwise-opposite normals.  dg_rhs,
+ * dg_rk_stage, dg_budgets and dg_node_coords accept such meshes (float64,
+ * mu = 0; background z is the height above r_e); the other calls return
+ * DG_EUNSUPPORTED (no refinement on the shell).  DG_EINVAL on bad sizes. */
+dg_status dg_sphere_mesh_build(const dg_sphere_desc* desc, dg_mesh** out);
+/* Face connectivity of a shell mesh (not in the paper): nb[K][6][3] (host,
+ * caller-owned) = neighbour element (-1 at the walls), its face, and 1 when
+ * the neighbour's face-local first axis runs opposite.  Host only.  DG_EINVAL
+ * for a NULL argument or a brick mesh. */
+dg_status dg_sphere_faces(const dg_mesh* mesh, int32_t* nb);
+/* Geometry of a shell mesh into host arrays (caller-owned): metric[10][K][Np]
+ * (J, then J a^i_c at 1 + 3 i + c, c the Cartesian component), fgeo
+ * [K][6][(N+1)^2][4] (unit outward normal, face Jacobian |J a^d|), c1d
+ * [3][K][N+1] (tan of the two panel angles, height above r_e).  Host only.
+ * DG_EINVAL for a NULL argument or a brick mesh. */
+dg_status dg_sphere_geometry(const dg_mesh* mesh, double* metric, double* fgeo, double* c1d);
 /* Whether dg_mesh_build(prev = mesh, flags, pass) would change a leaf of mesh
  * (section 3.1: a refine pass splits leaves flagged +1 below max_level; a
  * coarsen pass merges complete sibling families flagged -1 that pass the 2:1

@@ -1,0 +1,417 @@
+"""Oracle: compressible Euler on a cubed-sphere shell with curvilinear elements
+(test infrastructure only).
+
+Written from the paper's statements on spherical geometry (section 3.4) and its
+global tests (section 4.4), with the same perturbation form, Rusanov flux and
+strong-form dGSEM as the box operator in ``euler.py``:
+
+* Grid: the cubed sphere of six panels, each split into n x n elements along
+  the two equiangular panel coordinates and nz layers along the radius between
+  r_e and r_e + H; elements are isoparametric (the mapping is interpolated by
+  the same LGL polynomials as the fields, section 4.4).
+* Curvilinear strong form: with x(xi) the element mapping, J its Jacobian and
+  J a^i the contravariant metric terms, dq/dt = -(1/J) sum_i d/dxi_i (J a^i . F)
+  + S - (1/(J w_N)) (s F*(n) - J a^d . F(q-) sgn) at face nodes, s = |J a^d| the
+  face Jacobian and n the unit outward normal.
+* Radial gravity: the buoyancy is -rho' g r_hat on the momentum; the background
+  is hydrostatic in the height h = |x| - r_e (neutral, isothermal or constant).
+
+Readings where the paper is silent (listed in the design notes):
+
+* Equiangular gnomonic panels: a panel point is the cube point (1, tan a, tan b)
+  rotated to the panel, normalised to radius r.
+* Metric terms in the conservative curl form of Kopriva (2006), so the discrete
+  divergence of the metric terms vanishes and a uniform flow stays uniform up to
+  rounding: (J a^i)_n = -(curl_xi (X_l grad_xi X_m))_i with (n, m, l) cyclic, X
+  the interpolated coordinates, X_l relative to the element's first node.
+* The face normal and face Jacobian of a face shared by two elements are taken
+  from the element with the smaller (leaf, face) pair, and its neighbour uses
+  the same values with the normal reversed (both see bitwise-opposite normals).
+* Walls at r_e and r_e + H: mirror state (rho', U - 2 (U.n) n, Theta').
+* Isothermal background at T0: Pbar = P0 exp(-g h / (R T0)), rhobar = Pbar/(R T0),
+  Thetabar from the equation of state.
+
+Elements are ordered panel, layer, row, column: e = ((p nz + ir) n + ib) n + ia.
+Local axes: xi along the panel's first coordinate, eta along the second, zeta
+outward (every panel frame is right-handed, so J > 0).  Fields are [5, K, N+1,
+N+1, N+1] indexed [v][e][k][j][i] like the box operator.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import euler as eu
+from .refelem import refelem
+
+F64 = torch.float64
+BG_NEUTRAL, BG_CONSTANT, BG_ISOTHERMAL = 0, 1, 2
+
+
+@dataclass(frozen=True)
+class SphereDesc:
+    N: int
+    n: int                 # elements per panel edge
+    nz: int                # radial layers
+    r_e: float = 6.371e6   # the earth radius of section 4.4
+    H: float = 1.0e4       # model top of section 4.4
+
+
+# cube point of local panel coordinates (X, Y) with the panel's fixed coordinate c
+# (c = 1 for real coordinates, c = n for the integer lattice of grid lines)
+def panel_point(p, X, Y, c=1):
+    return [(c, X, Y), (-X, c, Y), (-c, -X, Y), (X, -c, Y), (-Y, X, c), (Y, X, -c)][p]
+
+
+def leaf_index(desc: SphereDesc, p, ia, ib, ir):
+    return ((p * desc.nz + ir) * desc.n + ib) * desc.n + ia
+
+
+class SphereMesh:
+    """Elements and face connectivity: nb[e, f] = (neighbour leaf, its face,
+    flip), or (-1, -1, 0) for the walls at the bottom and top; flip = 1 when the
+    neighbour's face-local first axis runs opposite to this face's."""
+
+    def __init__(self, desc: SphereDesc):
+        n, nz = desc.n, desc.nz
+        self.desc, self.N = desc, desc.N
+        self.K = 6 * n * n * nz
+        self.leaves = np.array([(p, ia, ib, ir) for p in range(6) for ir in range(nz) for ib in range(n)
+                                for ia in range(n)], dtype=np.int64)
+        nb = -np.ones((self.K, 6, 3), dtype=np.int64)
+        nb[:, :, 2] = 0
+        # lateral faces: key = (the two horizontal end points as integer lattice cube
+        # points, layer), value = (leaf, face, the point at the face's a = 0 end)
+        faces = {}
+        for e, (p, ia, ib, ir) in enumerate(self.leaves):
+            x0, x1, y0, y1 = 2 * ia - n, 2 * ia + 2 - n, 2 * ib - n, 2 * ib + 2 - n
+            ends = {0: ((x0, y0), (x0, y1)), 1: ((x1, y0), (x1, y1)),
+                    2: ((x0, y0), (x1, y0)), 3: ((x0, y1), (x1, y1))}
+            for f, (a0, a1) in ends.items():
+                P0 = panel_point(p, *a0, c=n)
+                P1 = panel_point(p, *a1, c=n)
+                faces.setdefault((frozenset((P0, P1)), ir), []).append((e, f, P0))
+            # radial faces
+            if ir > 0:
+                nb[e, 4] = (leaf_index(desc, p, ia, ib, ir - 1), 5, 0)
+            if ir < nz - 1:
+                nb[e, 5] = (leaf_index(desc, p, ia, ib, ir + 1), 4, 0)
+        for key, ends in faces.items():
+            if len(ends) != 2:
+                raise RuntimeError("unmatched lateral face")
+            (e0, f0, p0), (e1, f1, p1) = ends
+            flip = 0 if p0 == p1 else 1
+            nb[e0, f0] = (e1, f1, flip)
+            nb[e1, f1] = (e0, f0, flip)
+        self.nb = nb
+
+
+LD = np.longdouble
+PI_LD = np.longdouble("3.141592653589793238462643383279502884")
+
+
+def _tan_grid(s, n):
+    """tan of the equiangular angle s pi/(4n) in long double, exactly +-1 on the
+    panel edges"""
+    s = np.asarray(s, dtype=LD)
+    t = np.tan(s * PI_LD / (LD(4) * n))
+    t = np.where(s == n, LD(1), t)
+    return np.where(s == -n, LD(-1), t)
+
+
+def face_perm(N, flip):
+    """index map m -> m' of face-local nodes m = a + (N+1) b to the neighbour's face"""
+    n1 = N + 1
+    m = np.arange(n1 * n1)
+    a, b = m % n1, m // n1
+    return (N - a) + n1 * b if flip else m
+
+
+def _dxi(D, t, d):
+    """derivative along reference axis d of a nodal field [K, k, j, i] (numpy),
+    applied to the field minus its value at the line's first node (D annihilates
+    constants; the shift keeps an offset far larger than the variation along the
+    line, such as the earth radius in a node position, out of the sums)"""
+    if d == 0:
+        return np.einsum('im,ekjm->ekji', D, t - t[..., :1])
+    if d == 1:
+        return np.einsum('jm,ekmi->ekji', D, t - t[..., :1, :])
+    return np.einsum('km,emji->ekji', D, t - t[:, :1, :, :])
+
+
+def _face(t, f, N):
+    """numpy version of the face trace [K, (N+1)^2] of a nodal field [K, k, j, i]"""
+    d, s = f // 2, f % 2
+    idx = N if s == 1 else 0
+    tr = t[..., idx] if d == 0 else (t[..., idx, :] if d == 1 else t[..., idx, :, :])
+    return tr.reshape(*tr.shape[:-2], (N + 1) ** 2)
+
+
+class SphereGeometry:
+    """Nodes, metric terms, Jacobian, radial unit vector and face normals.
+
+    The geometry of a thin shell is ill-conditioned in float64 (the curl-form
+    metric terms cancel in proportion to the element aspect ratio, several hundred
+    for the shells of section 4.4), so it is evaluated in long double and rounded
+    once to float64."""
+
+    def __init__(self, mesh: SphereMesh):
+        desc, N = mesh.desc, mesh.N
+        n, nz = desc.n, desc.nz
+        re = refelem(N)
+        K, n1 = mesh.K, N + 1
+        self.N, self.K = N, K
+        xi = np.asarray(re.x, dtype=np.float64).astype(LD)
+        Dl = np.asarray(re.D, dtype=np.float64).astype(LD)
+        self.D = torch.as_tensor(re.D, dtype=F64)
+        p, ia, ib, ir = (mesh.leaves[:, c] for c in range(4))
+        # 1-D node parameters per leaf: X = tan alpha, Y = tan beta, height h
+        sX = (2 * ia - n).astype(LD)[:, None] + (xi[None, :] + LD(1))
+        sY = (2 * ib - n).astype(LD)[:, None] + (xi[None, :] + LD(1))
+        X1, Y1 = _tan_grid(sX, n), _tan_grid(sY, n)                      # [K, N+1]
+        h1 = LD(desc.H) * (ir.astype(LD)[:, None] + LD(0.5) * (xi[None, :] + LD(1))) / nz
+        self.X1, self.Y1, self.h1 = X1.astype(np.float64), Y1.astype(np.float64), h1.astype(np.float64)
+        X = np.broadcast_to(X1[:, None, None, :], (K, n1, n1, n1))
+        Y = np.broadcast_to(Y1[:, None, :, None], (K, n1, n1, n1))
+        r = np.broadcast_to((LD(desc.r_e) + h1)[:, :, None, None], (K, n1, n1, n1))
+        cube = [np.zeros((K, n1, n1, n1), dtype=LD) for _ in range(3)]
+        for pp in range(6):
+            sel = p == pp
+            v = panel_point(pp, X[sel], Y[sel], np.ones_like(X[sel]))
+            for c in range(3):
+                cube[c][sel] = v[c]
+        norm = np.sqrt(cube[0] ** 2 + cube[1] ** 2 + cube[2] ** 2)
+        rhat = [c / norm for c in cube]
+        x = [r * u for u in rhat]
+        dX = [[_dxi(Dl, x[c], d) for d in range(3)] for c in range(3)]   # dX[c][d] = d x_c / d xi_d
+        J = (dX[0][0] * (dX[1][1] * dX[2][2] - dX[1][2] * dX[2][1])
+             - dX[0][1] * (dX[1][0] * dX[2][2] - dX[1][2] * dX[2][0])
+             + dX[0][2] * (dX[1][0] * dX[2][1] - dX[1][1] * dX[2][0]))
+        # curl form: Ja[i][n] = -(curl_xi V)_i, V_d = X_l d_d X_m, (n, m, l) cyclic; X_l
+        # is taken relative to the element's first node (the discrete curl of
+        # c grad X_m vanishes for a constant c, so the shift changes only the rounding)
+        Ja = [[None] * 3 for _ in range(3)]
+        for nn in range(3):
+            m, l = (nn + 1) % 3, (nn + 2) % 3
+            Xl = x[l] - x[l][:, :1, :1, :1]
+            V = [Xl * dX[m][d] for d in range(3)]
+            curl = [_dxi(Dl, V[2], 1) - _dxi(Dl, V[1], 2), _dxi(Dl, V[0], 2) - _dxi(Dl, V[2], 0),
+                    _dxi(Dl, V[1], 0) - _dxi(Dl, V[0], 1)]
+            for i in range(3):
+                Ja[i][nn] = -curl[i]
+        # face normals and face Jacobians, [K, 6, (N+1)^2] each; shared faces from the
+        # (leaf, face) pair that comes first
+        nf = n1 * n1
+        own_n = np.zeros((3, K, 6, nf), dtype=LD)
+        own_s = np.zeros((K, 6, nf), dtype=LD)
+        for f in range(6):
+            d, sgn = f // 2, (LD(1) if f % 2 else LD(-1))
+            v = [sgn * _face(Ja[d][c], f, N) for c in range(3)]
+            sf = np.sqrt(v[0] ** 2 + v[1] ** 2 + v[2] ** 2)
+            own_s[:, f] = sf
+            for c in range(3):
+                own_n[c, :, f] = v[c] / sf
+        own_n, own_s = own_n.astype(np.float64), own_s.astype(np.float64)
+        nrm = np.zeros((3, K, 6, nf))
+        sJ = np.zeros((K, 6, nf))
+        for e in range(K):
+            for f in range(6):
+                e2, f2, flip = (int(x_) for x_ in mesh.nb[e, f])
+                if e2 < 0 or (e, f) < (e2, f2):
+                    nrm[:, e, f] = own_n[:, e, f]
+                    sJ[e, f] = own_s[e, f]
+                else:
+                    perm = face_perm(N, flip)
+                    nrm[:, e, f] = -own_n[:, e2, f2][:, perm]
+                    sJ[e, f] = own_s[e2, f2][perm]
+        t64 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64))
+        self.rhat = [t64(u) for u in rhat]                      # radial unit vector
+        self.x = [t64(c) for c in x]                            # node positions
+        self.height = t64(r - LD(desc.r_e))
+        self.J = t64(J)
+        self.Ja = [[t64(Ja[i][c]) for c in range(3)] for i in range(3)]
+        self.nrm, self.sJ = t64(nrm), t64(sJ)
+
+    def dxi(self, t, d):
+        """derivative along reference axis d of a float64 nodal field [K, k, j, i]"""
+        D = self.D
+        if d == 0:
+            return torch.einsum('im,ekjm->ekji', D, t)
+        if d == 1:
+            return torch.einsum('jm,ekmi->ekji', D, t)
+        return torch.einsum('km,emji->ekji', D, t)
+
+    def face_positions(self, f):
+        return [eu.face_slice(x, f, self.N) for x in self.x]
+
+
+def background(geo: SphereGeometry, phys: eu.Phys, kind):
+    """(rhobar, Thetabar, Pbar) at every node as functions of the height h."""
+    h = geo.height
+    R, gam = phys.R, phys.gamma
+    if kind == BG_ISOTHERMAL:
+        T0 = phys.theta0
+        P_b = phys.P0 * torch.exp(-phys.g * h / (R * T0))
+        rho_b = P_b / (R * T0)
+        Th_b = (phys.P0 / R) * (P_b / phys.P0) ** (1.0 / gam)
+        return rho_b, Th_b, P_b
+    if kind == BG_NEUTRAL:
+        exner = 1.0 - phys.g * h / (phys.cp * phys.theta0)
+        rho_b = phys.P0 * exner ** (phys.cv / R) / (R * phys.theta0)
+        Th_b = rho_b * phys.theta0
+    elif kind == BG_CONSTANT:
+        rho_b = torch.full_like(h, phys.rho0)
+        Th_b = torch.full_like(h, phys.Theta0)
+    else:
+        raise ValueError("unknown background")
+    P_b = phys.P0 * (R * Th_b / phys.P0) ** gam
+    return rho_b, Th_b, P_b
+
+
+def flux_normal(q, bg, phys, nv):
+    """F.n for the unit vector n = (n0, n1, n2) (tensors of the trace's shape)."""
+    rho, u, Pp, _ = eu.primitives(q, bg, phys)
+    un = u[0] * nv[0] + u[1] * nv[1] + u[2] * nv[2]
+    Th = bg[1] + q[4]
+    return torch.stack([q[1] * nv[0] + q[2] * nv[1] + q[3] * nv[2],
+                        q[1] * un + Pp * nv[0], q[2] * un + Pp * nv[1], q[3] * un + Pp * nv[2], Th * un])
+
+
+def rusanov_normal(qL, bgL, qR, bgR, phys, nv):
+    """F*.n = {F.n} + 1/2 lambda (q'- - q'+), lambda = max(|u.n| + c) of both sides."""
+    rhoL, uL, _, PL = eu.primitives(qL, bgL, phys)
+    rhoR, uR, _, PR = eu.primitives(qR, bgR, phys)
+    lamL = torch.abs(uL[0] * nv[0] + uL[1] * nv[1] + uL[2] * nv[2]) + eu.sound_speed(rhoL, PL, phys.gamma)
+    lamR = torch.abs(uR[0] * nv[0] + uR[1] * nv[1] + uR[2] * nv[2]) + eu.sound_speed(rhoR, PR, phys.gamma)
+    lam = torch.maximum(lamL, lamR)
+    return 0.5 * (flux_normal(qL, bgL, phys, nv) + flux_normal(qR, bgR, phys, nv)) + 0.5 * lam * (qL - qR)
+
+
+class SphereOperator:
+    """The curvilinear right-hand side on a cubed-sphere shell."""
+
+    def __init__(self, mesh: SphereMesh, phys: eu.Phys, background_kind=BG_ISOTHERMAL):
+        self.mesh, self.phys, self.N, self.K = mesh, phys, mesh.N, mesh.K
+        self.geo = SphereGeometry(mesh)
+        self.bg = background(self.geo, phys, background_kind)
+        self.wN = 2.0 / (self.N * (self.N + 1))
+        re = refelem(self.N)
+        self.re = re
+
+    def contravariant(self, q):
+        F = [eu.flux_dir(q, self.bg, self.phys, c) for c in range(3)]   # Cartesian fluxes
+        Ja = self.geo.Ja
+        return [Ja[i][0][None] * F[0] + Ja[i][1][None] * F[1] + Ja[i][2][None] * F[2] for i in range(3)]
+
+    def volume(self, q):
+        """-(1/J) sum_i D_i (J a^i . F) + S, S = -rho' g r_hat on the momentum"""
+        Ft = self.contravariant(q)
+        D = self.geo.D
+        div = (torch.einsum('im,vekjm->vekji', D, Ft[0]) + torch.einsum('jm,vekmi->vekji', D, Ft[1])
+               + torch.einsum('km,vemji->vekji', D, Ft[2]))
+        R = -div / self.geo.J[None]
+        g = self.phys.g
+        z = torch.zeros_like(q[0])
+        S = torch.stack([z] + [-q[0] * g * self.geo.rhat[c] for c in range(3)] + [z])
+        return R + S
+
+    def surface(self, q, walls=True):
+        """Lifted face terms -(1/(J w_N)) (s F*(n) - sgn J a^d . F(q-)) at the face nodes."""
+        N, K, ph, geo = self.N, self.K, self.phys, self.geo
+        Ft = self.contravariant(q)
+        R = torch.zeros(5, K, N + 1, N + 1, N + 1, dtype=F64)
+        nb = torch.as_tensor(self.mesh.nb)
+        for f in range(6):
+            d, sgn = f // 2, (1.0 if f % 2 else -1.0)
+            qL = eu.face_slice(q, f, N)
+            bL = tuple(eu.face_slice(b, f, N) for b in self.bg)
+            nv = [geo.nrm[c, :, f] for c in range(3)]
+            s = geo.sJ[:, f]
+            qR = torch.empty_like(qL)
+            bR = tuple(torch.empty_like(b) for b in bL)
+            wall = nb[:, f, 0] < 0
+            for f2 in range(6):
+                for flip in (0, 1):
+                    sel = (~wall) & (nb[:, f, 1] == f2) & (nb[:, f, 2] == flip)
+                    if not bool(sel.any()):
+                        continue
+                    e2 = nb[sel, f, 0]
+                    perm = torch.as_tensor(face_perm(N, flip))
+                    qR[:, sel] = eu.face_slice(q, f2, N)[:, e2][:, :, perm]
+                    for bi in range(3):
+                        bR[bi][sel] = eu.face_slice(self.bg[bi], f2, N)[e2][:, perm]
+            if bool(wall.any()):
+                w = wall
+                Un = qL[1][w] * nv[0][w] + qL[2][w] * nv[1][w] + qL[3][w] * nv[2][w]
+                qR[0][w] = qL[0][w]
+                for c in range(3):
+                    qR[1 + c][w] = qL[1 + c][w] - 2.0 * Un * nv[c][w]
+                qR[4][w] = qL[4][w]
+                for bi in range(3):
+                    bR[bi][w] = bL[bi][w]
+            act = torch.ones(K, dtype=torch.bool) if walls else ~wall
+            Fs = rusanov_normal(qL, bL, qR, bR, ph, nv)
+            delta = s[None] * Fs - sgn * eu.face_slice(Ft[d], f, N)
+            JF = eu.face_slice(geo.J, f, N)
+            delta = torch.where(act[None, :, None], delta / (JF[None] * self.wN), torch.zeros_like(delta))
+            R = R - eu.face_embed(delta, f, N, K)
+        return R
+
+    def rhs(self, q):
+        return self.volume(q) + self.surface(q)
+
+
+def quad_weights(op: SphereOperator):
+    """J W at every node (the element volume quadrature)."""
+    w = torch.as_tensor(op.re.w, dtype=F64)
+    return op.geo.J * w[:, None, None] * w[None, :, None] * w[None, None, :]
+
+
+def budgets(op: SphereOperator, q):
+    """(mass', total mass, integral of Theta', energy) with the potential energy
+    rho g h (h the height above r_e), each an exactly rounded sum."""
+    ph = op.phys
+    JW = quad_weights(op)
+    rho_b, Th_b, P_b = op.bg
+    rho = rho_b + q[0]
+    P = P_b + eu.pressure_perturbation(q[4], Th_b, P_b, ph.gamma)
+    E = P / (ph.gamma - 1.0) + (q[1] ** 2 + q[2] ** 2 + q[3] ** 2) / (2.0 * rho) + rho * ph.g * op.geo.height
+
+    def fsum(t):
+        return math.fsum(t.detach().reshape(-1).tolist())
+
+    return (fsum(JW * q[0]), fsum(JW * rho), fsum(JW * q[4]), fsum(JW * E))
+
+
+# ----------------------------------------------------------------------------- areas (section 3.4)
+
+def _angle(A, B, C):
+    """interior angle at A of the spherical triangle ABC (unit vectors)"""
+    tB = B - np.dot(A, B) * A
+    tC = C - np.dot(A, C) * A
+    return math.atan2(np.linalg.norm(np.cross(tB, tC)), np.dot(tB, tC))
+
+
+def spherical_excess(A, B, C):
+    """area of the spherical triangle ABC on the unit sphere: the sum of its
+    interior angles minus pi"""
+    return _angle(A, B, C) + _angle(B, C, A) + _angle(C, A, B) - math.pi
+
+
+def element_areas(mesh: SphereMesh, radius):
+    """area of every element's footprint on the sphere of the given radius, as
+    two spherical triangles of its corner points (section 3.4's area formula)"""
+    n = mesh.desc.n
+    out = np.zeros(mesh.K)
+    for e, (p, ia, ib, ir) in enumerate(mesh.leaves):
+        corners = []
+        for sx, sy in ((2 * ia - n, 2 * ib - n), (2 * ia + 2 - n, 2 * ib - n), (2 * ia + 2 - n, 2 * ib + 2 - n),
+                       (2 * ia - n, 2 * ib + 2 - n)):
+            v = np.array(panel_point(p, float(_tan_grid(sx, n)), float(_tan_grid(sy, n))), dtype=np.float64)
+            corners.append(v / np.linalg.norm(v))
+        out[e] = radius * radius * (spherical_excess(corners[0], corners[1], corners[2])
+                                    + spherical_excess(corners[0], corners[2], corners[3]))
+    return out

@@ -30,10 +30,12 @@ CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-fopenmp", "-Wall", "-Wextra", "-Wno
 SOURCES = [
     ("refelem.cpp", "cxx"),
     ("forest.cpp", "cxx"),
+    ("sphere.cpp", "cxx"),
     ("abi.cpp", "hip"),
     ("kernels.hip", "hip"),
     ("tracer.hip", "hip"),
     ("viscous.hip", "hip"),
+    ("sphere.hip", "hip"),
 ]
 
 

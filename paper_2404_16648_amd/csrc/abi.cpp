@@ -58,6 +58,7 @@ void free_device(dg_mesh* m) {
     m->d_mort = nullptr;
     m->d_mortC = nullptr;
     m->d_flags = nullptr;
+    m->d_metric = m->d_fgeo = nullptr;
     if (m->d_sigma) (void)hipFree(m->d_sigma);
     m->d_sigma = nullptr;
 }
@@ -65,10 +66,10 @@ void free_device(dg_mesh* m) {
 // byte offsets of the arrays in a mesh's one device block, 256-byte aligned;
 // [0, upload) is copied from the host, the rest is device workspace
 struct DevLayout {
-    size_t ops, geo, c1d, ft, nb, hs, hg, lv, xs, xk, sr, hl, upload, bg, red, eta, fl, mort, mortC, total;
+    size_t ops, geo, c1d, ft, nb, hs, hg, lv, xs, xk, sr, hl, met, fg, upload, bg, red, eta, fl, mort, mortC, total;
 };
 
-DevLayout dev_layout(int64_t K, int N, int64_t red_len, int64_t n_hang, int64_t n_hleaves) {
+DevLayout dev_layout(int64_t K, int N, int64_t red_len, int64_t n_hang, int64_t n_hleaves, bool sphere) {
     const size_t N1 = (size_t)N + 1, k = (size_t)K;
     size_t end = 0;
     auto take = [&](size_t bytes) {
@@ -89,6 +90,9 @@ DevLayout dev_layout(int64_t K, int N, int64_t red_len, int64_t n_hang, int64_t 
     L.xk = take(sizeof(int32_t) * k);
     L.sr = take(sizeof(int32_t) * kStageRec * k);
     L.hl = take(sizeof(int32_t) * (size_t)n_hleaves);
+    // shell meshes: metric terms and face geometry
+    L.met = take(sphere ? sizeof(double) * 10 * k * N1 * N1 * N1 : 0);
+    L.fg = take(sphere ? sizeof(double) * 24 * k * N1 * N1 : 0);
     L.upload = end;
     L.bg = take(sizeof(double) * 3 * k * N1);
     L.red = take(sizeof(double) * (size_t)red_len);
@@ -116,6 +120,8 @@ void set_device_pointers(dg_mesh* m, char* base, const DevLayout& L) {
     m->d_xkind = (int32_t*)(base + L.xk);
     m->d_srec = (int32_t*)(base + L.sr);
     m->d_hleaves = (int32_t*)(base + L.hl);
+    m->d_metric = m->h.sphere ? (double*)(base + L.met) : nullptr;
+    m->d_fgeo = m->h.sphere ? (double*)(base + L.fg) : nullptr;
     m->d_bg = (double*)(base + L.bg);
     m->d_red = (double*)(base + L.red);
     m->d_eta = (double*)(base + L.eta);
@@ -219,7 +225,7 @@ dg_status build_device(dg_mesh* m, hipStream_t s) {
             }
         }
     m->n_hleaves = (int64_t)hleaves.size();
-    const DevLayout L = dev_layout(K, N, m->red_len, m->n_hang, m->n_hleaves);
+    const DevLayout L = dev_layout(K, N, m->red_len, m->n_hang, m->n_hleaves, h.sphere);
     // one staging buffer and one copy for every table of the mesh; the background,
     // reduction and flag buffers are carved from the same block
     UploadStaging& stg = upload_staging();
@@ -254,15 +260,22 @@ dg_status build_device(dg_mesh* m, hipStream_t s) {
     double* geo = (double*)(up.data() + L.geo);
     double* c1d = (double*)(up.data() + L.c1d);
     int32_t* level = (int32_t*)(up.data() + L.lv);
-    for (int64_t e = 0; e < K; ++e) {
-        double hh[3], c[3 * 8];  // N + 1 <= 8
-        leaf_geometry(h.desc, h.leaves[e], m->ops.x, hh, c);
-        for (int d = 0; d < 3; ++d) {
-            geo[e * 4 + d] = 2.0 / hh[d];
-            for (int j = 0; j < N1; ++j) c1d[(d * K + e) * N1 + j] = c[d * N1 + j];
+    if (h.sphere) {
+        // shell: the curvilinear geometry (geo unused: zeros)
+        std::memset(geo, 0, sizeof(double) * 4 * K);
+        std::memset(level, 0, sizeof(int32_t) * K);
+        sphere_geometry(h, m->ops, (double*)(up.data() + L.met), (double*)(up.data() + L.fg), c1d);
+    } else {
+        for (int64_t e = 0; e < K; ++e) {
+            double hh[3], c[3 * 8];  // N + 1 <= 8
+            leaf_geometry(h.desc, h.leaves[e], m->ops.x, hh, c);
+            for (int d = 0; d < 3; ++d) {
+                geo[e * 4 + d] = 2.0 / hh[d];
+                for (int j = 0; j < N1; ++j) c1d[(d * K + e) * N1 + j] = c[d * N1 + j];
+            }
+            geo[e * 4 + 3] = hh[0] * hh[1] * hh[2] / 8.0;
+            level[e] = h.leaves[e].l;
         }
-        geo[e * 4 + 3] = hh[0] * hh[1] * hh[2] / 8.0;
-        level[e] = h.leaves[e].l;
     }
     std::memcpy(up.data() + L.ft, h.ftype.data(), sizeof(int32_t) * 6 * K);
     std::memcpy(up.data() + L.nb, h.fnb.data(), sizeof(int32_t) * 24 * K);
@@ -288,6 +301,14 @@ dg_status build_device(dg_mesh* m, hipStream_t s) {
             rec[12 + f] = hs[e * 6 + f];
         }
         rec[18] = rec[19] = 0;
+        if (h.sphere) {
+            // shell: per face the neighbour's face and the flip (4 bits), the panel
+            for (int f = 0; f < 6; ++f) {
+                const int32_t* nb = &h.snb[(e * 6 + f) * 3];
+                if (nb[0] >= 0) rec[18] |= (int32_t)((nb[1] & 7) | ((nb[2] & 1) << 3)) << (4 * f);
+            }
+            rec[19] = h.leaves[e].r;
+        }
     }
     if (m->n_hleaves) std::memcpy(up.data() + L.hl, hleaves.data(), sizeof(int32_t) * m->n_hleaves);
     char* base = nullptr;
@@ -306,11 +327,18 @@ dg_status build_device(dg_mesh* m, hipStream_t s) {
     return DG_OK;
 }
 
+// calls that shell meshes do not provide (no refinement, mortars, adjoint,
+// tracer or indicator on the shell)
+dg_status no_sphere(const dg_mesh* m) {
+    if (m && m->h.sphere) return fail(DG_EUNSUPPORTED, "not provided for cubed-sphere shell meshes");
+    return DG_OK;
+}
+
 dg_status check_phys(const dg_phys* p) {
     if (!p) return fail(DG_EINVAL, "phys is NULL");
     if (!(p->cv > 0.0) || !(p->cp > p->cv)) return fail(DG_EINVAL, "need cp > cv > 0");
     if (!(p->P0 > 0.0)) return fail(DG_EINVAL, "need P0 > 0");
-    if (p->background == DG_BG_NEUTRAL) {
+    if (p->background == DG_BG_NEUTRAL || p->background == DG_BG_ISOTHERMAL) {
         if (!(p->theta0 > 0.0)) return fail(DG_EINVAL, "need theta0 > 0");
     } else if (p->background == DG_BG_CONSTANT) {
         if (!(p->rho0 > 0.0) || !(p->Theta0 > 0.0)) return fail(DG_EINVAL, "need rho0, Theta0 > 0");
@@ -486,6 +514,10 @@ dg_status dg_mesh_build(const dg_forest_desc* desc, const dg_mesh* prev, const i
             }
             err = forest_uniform(*desc, m->h);
         } else {
+            if (prev->h.sphere) {
+                delete m;
+                return fail(DG_EUNSUPPORTED, "no refinement of cubed-sphere shell meshes");
+            }
             if (!flags && !prev->h.leaves.empty()) {
                 delete m;
                 return fail(DG_EINVAL, "flags is NULL");
@@ -531,8 +563,60 @@ dg_status dg_mesh_build(const dg_forest_desc* desc, const dg_mesh* prev, const i
     return DG_OK;
 }
 
+dg_status dg_sphere_mesh_build(const dg_sphere_desc* desc, dg_mesh** out) {
+    if (!out) return fail(DG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!desc) return fail(DG_EINVAL, "desc is NULL");
+    if (desc->N > 5) return fail(DG_EINVAL, "shell meshes support N = 2..5");
+    dg_mesh* m = nullptr;
+    try {
+        m = new dg_mesh();
+        const std::string err = sphere_build(*desc, m->h);
+        if (!err.empty()) {
+            delete m;
+            return fail(DG_EINVAL, err);
+        }
+        m->h.desc.host_only = desc->host_only;
+        m->ops = refops_cached(desc->N);
+        m->id = g_next_id++;
+        dg_status st = validate_mesh(m);
+        if (st == DG_OK && !desc->host_only) {
+            const hipError_t e = hipGetDevice(&m->device);
+            if (e != hipSuccess) st = hip_fail(e, "hipGetDevice");
+        }
+        if (st != DG_OK) {
+            delete m;
+            return st;
+        }
+    } catch (const std::bad_alloc&) {
+        delete m;
+        return fail(DG_ENOMEM, "host allocation failed");
+    }
+    *out = m;
+    return DG_OK;
+}
+
+dg_status dg_sphere_faces(const dg_mesh* m, int32_t* nb) {
+    if (!m || !nb) return fail(DG_EINVAL, "NULL argument");
+    if (!m->h.sphere) return fail(DG_EINVAL, "not a shell mesh");
+    std::memcpy(nb, m->h.snb.data(), m->h.snb.size() * sizeof(int32_t));
+    return DG_OK;
+}
+
+dg_status dg_sphere_geometry(const dg_mesh* m, double* metric, double* fgeo, double* c1d) {
+    if (!m || !metric || !fgeo || !c1d) return fail(DG_EINVAL, "NULL argument");
+    if (!m->h.sphere) return fail(DG_EINVAL, "not a shell mesh");
+    try {
+        sphere_geometry(m->h, m->ops, metric, fgeo, c1d);
+    } catch (const std::bad_alloc&) {
+        return fail(DG_ENOMEM, "host allocation failed");
+    }
+    return DG_OK;
+}
+
 dg_status dg_pass_changes(const dg_mesh* m, const int8_t* flags, int32_t pass, int32_t* changes) {
     if (!m || !changes) return fail(DG_EINVAL, "NULL argument");
+    if (dg_status st = no_sphere(m)) return st;
     if (!flags && !m->h.leaves.empty()) return fail(DG_EINVAL, "flags is NULL");
     if (pass != DG_PASS_REFINE && pass != DG_PASS_COARSEN) return fail(DG_EINVAL, "unknown pass");
     try {
@@ -557,6 +641,11 @@ dg_status dg_mesh_info_get(const dg_mesh* m, dg_mesh_info* info) {
     info->N = h.desc.N;
     info->Np = (int64_t)(h.desc.N + 1) * (h.desc.N + 1) * (h.desc.N + 1);
     info->n_conf = (int64_t)h.conf.size() / 3;
+    if (h.sphere) {  // shell: conforming face pairs counted from the connectivity
+        int64_t pairs = 0;
+        for (size_t i = 0; i < h.snb.size(); i += 3) pairs += h.snb[i] >= 0 ? 1 : 0;
+        info->n_conf = pairs / 2;
+    }
     info->n_bnd = (int64_t)h.bnd.size() / 2;
     info->n_hang = (int64_t)h.hang.size() / 6;
     info->n_refined = h.n_refined;
@@ -595,13 +684,19 @@ dg_status dg_node_coords(const dg_mesh* m, double* xyz, void* stream) {
     dg_status st = check_dev_mesh(m, (hipStream_t)stream);
     if (st) return st;
     if (!xyz) return fail(DG_EINVAL, "xyz is NULL");
+    if (m->h.sphere) {
+        HIP_TRY(launch_node_coords_sphere((int64_t)m->h.leaves.size(), m->h.desc.N, m->d_c1d, m->d_srec,
+                                          m->h.sdesc.r_e, xyz, (hipStream_t)stream));
+        return DG_OK;
+    }
     HIP_TRY(launch_node_coords((int64_t)m->h.leaves.size(), m->h.desc.N, m->d_c1d, xyz, (hipStream_t)stream));
     return DG_OK;
 }
 
 dg_status dg_init_bell(const dg_mesh* mc, const dg_phys* phys, const dg_bell* bell, double* q, void* stream) {
-    dg_status st = check_dev_mesh(mc, (hipStream_t)stream);
+    dg_status st = no_sphere(mc);
     if (st) return st;
+    if ((st = check_dev_mesh(mc, (hipStream_t)stream))) return st;
     if ((st = check_phys(phys))) return st;
     if (!bell || !q) return fail(DG_EINVAL, "NULL argument");
     dg_mesh* m = const_cast<dg_mesh*>(mc);
@@ -624,6 +719,14 @@ static dg_status stage_common(const dg_mesh* mc, const dg_phys* phys, int mode, 
     dg_mesh* m = const_cast<dg_mesh*>(mc);
     hipStream_t s = (hipStream_t)stream;
     if ((st = ensure_bg(m, phys, s))) return st;
+    if (m->h.sphere) {
+        if (phys->precision != DG_FP64) return fail(DG_EUNSUPPORTED, "shell meshes run in float64");
+        if (phys->mu > 0.0) return fail(DG_EUNSUPPORTED, "no artificial viscosity on shell meshes");
+        SphereStageArgs sa{q0, qs, out, m->d_ops, m->d_bg, m->d_c1d, m->d_srec, m->d_metric, m->d_fgeo,
+                           (int64_t)m->h.leaves.size(), a, b, dt, phys->cp / phys->cv, phys->g, binom_coef(phys)};
+        HIP_TRY(launch_stage_sphere(m->h.desc.N, mode, sa, s));
+        return DG_OK;
+    }
     StageArgs args = stage_args(m, phys);
     args.q0 = q0;
     args.qs = qs;
@@ -682,6 +785,8 @@ dg_status dg_rk_stage(const dg_mesh* m, const dg_phys* phys, double a, double b,
 
 static dg_status xfer_common(const dg_mesh* from, const dg_mesh* to, const double* qin, double* qout,
                              void* stream, bool refine, bool adjoint, int32_t nvar = 5) {
+    if (dg_status st0 = no_sphere(from)) return st0;
+    if (dg_status st0 = no_sphere(to)) return st0;
     dg_status st = check_dev_mesh(from, (hipStream_t)stream);
     if (st) return st;
     if ((st = check_dev_mesh(to, (hipStream_t)stream))) return st;
@@ -722,8 +827,9 @@ dg_status dg_coarsen_project_adjoint(const dg_mesh* from, const dg_mesh* to, con
 
 static dg_status tracer_common(const dg_mesh* mc, const dg_phys* phys, int mode, double a, double b, double dt,
                                const double* qs, const double* c0, const double* cs, double* out, void* stream) {
-    dg_status st = check_dev_mesh(mc, (hipStream_t)stream);
+    dg_status st = no_sphere(mc);
     if (st) return st;
+    if ((st = check_dev_mesh(mc, (hipStream_t)stream))) return st;
     if ((st = check_phys(phys))) return st;
     if ((st = check_wrap(mc, phys))) return st;
     if (!qs || !cs || !out) return fail(DG_EINVAL, "NULL field pointer");
@@ -783,6 +889,7 @@ dg_status dg_tracer_mass(const dg_mesh* mc, const double* c, double* out_host, v
 static dg_status adjoint_common(const dg_mesh* mc, const dg_phys* phys, int mode, double a1, const double* w1,
                                 double a2, const double* w2, double b, double dt, const double* q, const double* lam,
                                 double* out, void* stream) {
+    if (dg_status st0 = no_sphere(mc)) return st0;
     dg_status st = check_dev_mesh(mc, (hipStream_t)stream);
     if (st) return st;
     if ((st = check_phys(phys))) return st;
@@ -838,6 +945,7 @@ dg_status dg_rk_stage_adjoint(const dg_mesh* m, const dg_phys* phys, double a1, 
 
 dg_status dg_flags_after_coarsen(const dg_mesh* mc, const int8_t* flags, int8_t* flags_out) {
     if (!mc || !flags || !flags_out) return fail(DG_EINVAL, "NULL argument");
+    if (dg_status st = no_sphere(mc)) return st;
     const HostMesh& h = mc->h;
     const int64_t K = (int64_t)h.leaves.size();
     const int64_t Kp = mc->prev ? (int64_t)mc->prev->h.leaves.size() : K;
@@ -852,6 +960,7 @@ dg_status dg_flags_after_coarsen(const dg_mesh* mc, const int8_t* flags, int8_t*
 dg_status dg_flags_buffer(const dg_mesh* m, int8_t* flags, int32_t B) {
     if (!m || !flags) return fail(DG_EINVAL, "NULL argument");
     if (B < 0) return fail(DG_EINVAL, "B must be >= 0");
+    if (dg_status st = no_sphere(m)) return st;
     const HostMesh& h = m->h;
     const int64_t K = (int64_t)h.leaves.size();
     std::vector<int8_t> cur((size_t)K);
@@ -886,7 +995,8 @@ dg_status dg_budgets(const dg_mesh* mc, const dg_phys* phys, const double* q, do
     if ((st = ensure_bg(m, phys, s))) return st;
     const int64_t K = (int64_t)m->h.leaves.size();
     const int nblk = budget_blocks(K);
-    BudgetArgs a{q, m->d_bg, m->d_geo, m->d_c1d, m->d_ops + 5 * (m->h.desc.N + 1) * (m->h.desc.N + 1),
+    BudgetArgs a{q, m->d_bg, m->d_geo, m->h.sphere ? m->d_metric : nullptr, m->d_c1d,
+                 m->d_ops + 5 * (m->h.desc.N + 1) * (m->h.desc.N + 1),
                  m->d_red, K, phys->cp / phys->cv, phys->g, binom_coef(phys)};
     double* out_dev = m->d_red + (int64_t)nblk * 8;
     HIP_TRY(launch_budgets(m->h.desc.N, a, nblk, out_dev, s));
@@ -924,7 +1034,8 @@ dg_status dg_budgets_noalloc(const dg_mesh* mc, const dg_phys* phys, const doubl
                                    std::to_string(kBudgetScratchDoubles) + " doubles)");
     double* scr = nullptr;
     HIP_TRY(budget_scratch(&scr));
-    BudgetArgs a{q, m->d_bg, m->d_geo, m->d_c1d, m->d_ops + 5 * (m->h.desc.N + 1) * (m->h.desc.N + 1),
+    BudgetArgs a{q, m->d_bg, m->d_geo, m->h.sphere ? m->d_metric : nullptr, m->d_c1d,
+                 m->d_ops + 5 * (m->h.desc.N + 1) * (m->h.desc.N + 1),
                  scr, K, phys->cp / phys->cv, phys->g, binom_coef(phys)};
     HIP_TRY(launch_budgets(m->h.desc.N, a, nblk, out_dev, s));
     return DG_OK;
@@ -932,8 +1043,9 @@ dg_status dg_budgets_noalloc(const dg_mesh* mc, const dg_phys* phys, const doubl
 
 dg_status dg_indicator(const dg_mesh* mc, const dg_phys* phys, const double* q, int32_t kind, double thr,
                        double* eta, int8_t* flags_host, void* stream) {
-    dg_status st = check_dev_mesh(mc, (hipStream_t)stream);
+    dg_status st = no_sphere(mc);
     if (st) return st;
+    if ((st = check_dev_mesh(mc, (hipStream_t)stream))) return st;
     if ((st = check_phys(phys))) return st;
     if (!q || !flags_host) return fail(DG_EINVAL, "NULL argument");
     if (kind != DG_IND_THETA && kind != DG_IND_GRAD_THETA) return fail(DG_EINVAL, "unknown indicator kind");
@@ -951,8 +1063,9 @@ dg_status dg_indicator(const dg_mesh* mc, const dg_phys* phys, const double* q, 
 
 dg_status dg_indicator_async(const dg_mesh* mc, const dg_phys* phys, const double* q, int32_t kind, double thr,
                              double* eta, int8_t* flags_dev, void* stream) {
-    dg_status st = check_dev_mesh(mc, (hipStream_t)stream);
+    dg_status st = no_sphere(mc);
     if (st) return st;
+    if ((st = check_dev_mesh(mc, (hipStream_t)stream))) return st;
     if ((st = check_phys(phys))) return st;
     if (!q || !flags_dev) return fail(DG_EINVAL, "NULL argument");
     if (kind != DG_IND_THETA && kind != DG_IND_GRAD_THETA) return fail(DG_EINVAL, "unknown indicator kind");

@@ -35,6 +35,11 @@ struct HostMesh {
     std::vector<int32_t> ftype, fnb;             // [K][6], [K][6][4]
     int64_t n_refined = 0, n_coarsened = 0;
     bool same_as_prev = false;                   // the pass changed no leaf: tables copied
+    // cubed-sphere shell (leaf r = panel, a = (ia, ib, ir)): per face the neighbour
+    // leaf (-1: wall), its face and the flip of the face-local first axis
+    bool sphere = false;
+    dg_sphere_desc sdesc{};
+    std::vector<int32_t> snb;                    // [K][6][3]
 };
 
 // forest passes (host, integer work); return "" or an error message
@@ -44,6 +49,12 @@ std::string forest_coarsen(const HostMesh& prev, const int8_t* flags, HostMesh& 
 void forest_tables(HostMesh& m);
 // whether forest_refine (refine) or forest_coarsen (!refine) would change a leaf
 bool pass_changes(const HostMesh& prev, const int8_t* flags, bool refine);
+
+// cubed-sphere shell: mesh and tables; geometry into device layouts
+// (metric [10][K][Np]: J, then J a^i_c at 1 + 3 i + c; fgeo [K][6][NF][4]: unit
+// normal and face Jacobian; c1d [3][K][N+1]: tan of the two panel angles, height)
+std::string sphere_build(const dg_sphere_desc& d, HostMesh& out);
+void sphere_geometry(const HostMesh& h, const RefOps& ops, double* metric, double* fgeo, double* c1d);
 
 // geometry of leaf e: h[3] and 1-D node coordinates c[3][N+1]
 void leaf_geometry(const dg_forest_desc& desc, const Leaf& lf, const std::vector<double>& xi,
@@ -90,4 +101,6 @@ struct dg_mesh {
     int8_t* d_flags = nullptr;    // [K]
     double* d_eta = nullptr;      // [K]
     double* d_sigma = nullptr;    // [3][5][K][Np]: viscous gradient (own allocation, at first use)
+    double* d_metric = nullptr;   // sphere: [10][K][Np] J and metric terms
+    double* d_fgeo = nullptr;     // sphere: [K][6][NF][4] face normal and face Jacobian
 };

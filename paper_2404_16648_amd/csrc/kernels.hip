@@ -1216,6 +1216,14 @@ __global__ void k_background(int64_t K, int N1, const double* c1d, double* bg, B
     const double z = c1d[2 * K * N1 + idx];
     const double R = p.cp - p.cv, gamma = p.cp / p.cv;
     double rho, Th;
+    if (p.kind == DG_BG_ISOTHERMAL) {
+        // temperature theta0: Pbar = P0 exp(-g z/(R theta0)), Thetabar from the equation of state
+        const double Pb = p.P0 * exp(-p.g * z / (R * p.theta0));
+        bg[idx] = Pb / (R * p.theta0);
+        bg[K * N1 + idx] = (p.P0 / R) * pow(Pb / p.P0, 1.0 / gamma);
+        bg[2 * K * N1 + idx] = Pb;
+        return;
+    }
     if (p.kind == DG_BG_NEUTRAL) {
         const double exner = 1.0 - p.g * z / (p.cp * p.theta0);
         rho = p.P0 * pow(exner, p.cv / R) / (R * p.theta0);
@@ -1465,7 +1473,7 @@ __global__ void __launch_bounds__(256) k_budgets(const BudgetArgs A) {
         const double J = A.geo[e * 4 + 3];
         for (int n = t; n < NP; n += NT) {
             const int i = n % N1, j = (n / N1) % N1, k = n / (N1 * N1);
-            const double W = J * A.w[i] * A.w[j] * A.w[k];
+            const double W = (A.Jn ? A.Jn[e * NP + n] : J) * A.w[i] * A.w[j] * A.w[k];
             const double rp = A.q[e * NP + n];
             const double U = A.q[K * NP + e * NP + n], V = A.q[2 * K * NP + e * NP + n],
                          Wm = A.q[3 * K * NP + e * NP + n], Thp = A.q[4 * K * NP + e * NP + n];

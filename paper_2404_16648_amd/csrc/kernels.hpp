@@ -179,10 +179,28 @@ struct CentralMortArgs {
     double mul;
 };
 
+// cubed-sphere shell stage: out = R(qs) (MODE_RHS) or a q0 + b (qs + dt R(qs)) (MODE_RK)
+struct SphereStageArgs {
+    const double* q0;
+    const double* qs;
+    double* out;
+    const double* ops;     // D first
+    const double* bg;      // [3][K][N1] as functions of the height
+    const double* c1d;     // [3][K][N1]: tan of the panel angles, height
+    const int32_t* srec;   // [K][kStageRec]: 18 = neighbour face | flip << 3 per face (4 bits), 19 = panel
+    const double* metric;  // [10][K][Np]
+    const double* fgeo;    // [K][6][NF][4]
+    int64_t K;
+    double a, b, dt;
+    double gamma, g;
+    BinomCoef binom;
+};
+
 struct BudgetArgs {
     const double* q;
     const double* bg;
     const double* geo;
+    const double* Jn;      // [K][Np] per-node Jacobian (shell meshes), or null: geo's constant J
     const double* c1d;
     const double* w;
     double* partial;
@@ -231,6 +249,10 @@ hipError_t launch_tracer_mortar(int N, const TracerMortArgs& a, hipStream_t s);
 hipError_t launch_tracer_stage(int N, int mode, const TracerArgs& a, hipStream_t s);
 // the two viscous passes (mortars, gradient; mortars, divergence) on stream s
 hipError_t launch_viscous(int N, const ViscArgs& a, hipStream_t s);
+// cubed-sphere shell (N = 2..5): the stage and the node positions
+hipError_t launch_stage_sphere(int N, int mode, const SphereStageArgs& a, hipStream_t s);
+hipError_t launch_node_coords_sphere(int64_t K, int N, const double* c1d, const int32_t* srec, double r_e,
+                                     double* xyz, hipStream_t s);
 // integral of c [K][Np] with the weights J_e W_n (w the 1-D LGL weights): nblk <= budget_blocks(K)
 // blocks leave 2 doubles each in partial, the total goes to out_dev[0]
 hipError_t launch_weighted_sum(int N, const double* c, const double* geo, const double* w, int64_t K, int nblk,

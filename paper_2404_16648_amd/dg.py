@@ -27,6 +27,7 @@ DG_PASS_COARSEN = 0
 DG_PASS_REFINE = 1
 DG_BG_NEUTRAL = 0
 DG_BG_CONSTANT = 1
+DG_BG_ISOTHERMAL = 2
 DG_FP64 = 0
 DG_MIXED = 1
 DG_NC_MORTAR = 0
@@ -40,7 +41,8 @@ EXPORTED = [
     "dg_mesh_build", "dg_mesh_free", "dg_mesh_info_get", "dg_mesh_export", "dg_node_coords",
     "dg_init_bell", "dg_rhs", "dg_rk_stage", "dg_refine_project", "dg_coarsen_project",
     "dg_refine_project_adjoint", "dg_coarsen_project_adjoint", "dg_rhs_adjoint", "dg_rk_stage_adjoint", "dg_budgets", "dg_budgets_noalloc", "dg_indicator", "dg_indicator_async", "dg_pass_changes", "dg_flags_after_coarsen", "dg_tracer_rhs", "dg_tracer_stage", "dg_tracer_mass",
-    "dg_project_fields", "dg_flags_buffer", "dg_fma_burst", "dg_last_error",
+    "dg_project_fields", "dg_flags_buffer", "dg_fma_burst", "dg_sphere_mesh_build", "dg_sphere_faces",
+    "dg_sphere_geometry", "dg_last_error",
 ]
 
 
@@ -54,6 +56,11 @@ class ForestDesc(C.Structure):
     _fields_ = [("N", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("max_level", C.c_int32), ("periodic", C.c_int32 * 3),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("host_only", C.c_int32)]
+
+
+class SphereDesc(C.Structure):
+    _fields_ = [("N", C.c_int32), ("n", C.c_int32), ("nz", C.c_int32), ("r_e", C.c_double), ("H", C.c_double),
+                ("host_only", C.c_int32)]
 
 
 class Phys(C.Structure):
@@ -116,6 +123,9 @@ def lib():
         L.dg_indicator.argtypes = [P, C.POINTER(Phys), P, C.c_int32, C.c_double, P, P, P]
         L.dg_indicator_async.argtypes = [P, C.POINTER(Phys), P, C.c_int32, C.c_double, P, P, P]
         L.dg_pass_changes.argtypes = [P, P, C.c_int32, C.POINTER(C.c_int32)]
+        L.dg_sphere_mesh_build.argtypes = [C.POINTER(SphereDesc), C.POINTER(P)]
+        L.dg_sphere_faces.argtypes = [P, P]
+        L.dg_sphere_geometry.argtypes = [P, P, P, P]
         L.dg_last_error.restype = C.c_char_p
         for name in EXPORTED:
             if name != "dg_last_error":
@@ -237,6 +247,32 @@ def dg_mesh_build(N=None, nroot=None, max_level=0, lo=(0.0, 0.0, 0.0), hi=(1.0, 
             raise ValueError("flags must have one entry per leaf of prev")
         _check(lib().dg_mesh_build(None, prev.handle, C.c_void_p(fl.ctypes.data), pass_, C.byref(out)))
     return Mesh(out.value, prev)
+
+
+def dg_sphere_mesh_build(N, n, nz, r_e=6.371e6, H=1.0e4, host_only=False) -> Mesh:
+    """Uniform cubed-sphere shell mesh (six panels of n x n elements, nz layers)."""
+    out = C.c_void_p()
+    d = SphereDesc(N, n, nz, r_e, H, 1 if host_only else 0)
+    _check(lib().dg_sphere_mesh_build(C.byref(d), C.byref(out)))
+    return Mesh(out.value)
+
+
+def dg_sphere_faces(mesh: Mesh):
+    """Face connectivity of a shell mesh: int32 [K, 6, 3] (neighbour, its face, flip)."""
+    nb = np.zeros((mesh.K, 6, 3), np.int32)
+    _check(lib().dg_sphere_faces(mesh.handle, C.c_void_p(nb.ctypes.data)))
+    return nb
+
+
+def dg_sphere_geometry(mesh: Mesh):
+    """Host geometry of a shell mesh: metric [10, K, Np], fgeo [K, 6, (N+1)^2, 4], c1d [3, K, N+1]."""
+    n1 = mesh.N + 1
+    metric = np.zeros((10, mesh.K, mesh.Np))
+    fgeo = np.zeros((mesh.K, 6, n1 * n1, 4))
+    c1d = np.zeros((3, mesh.K, n1))
+    _check(lib().dg_sphere_geometry(mesh.handle, C.c_void_p(metric.ctypes.data), C.c_void_p(fgeo.ctypes.data),
+                                    C.c_void_p(c1d.ctypes.data)))
+    return metric, fgeo, c1d
 
 
 def dg_pass_changes(mesh: Mesh, flags, pass_) -> bool:
