@@ -358,6 +358,54 @@ def rtb_long_run(dg, torch, t_end=100.0, regrid=25.0, dt=0.0025, seg=100, mu=1.5
             "mass_rel_change": (b1[1] - b0[1]) / b0[1], "energy_rel_change": (b1[3] - b0[3]) / abs(b0[3])}
 
 
+# bytes per node of one shell stage with a != 0: q0, the stage input and the output
+# (120), the Jacobian and nine metric terms (80), the face normals and face Jacobians
+# of the element's 6 (N+1)^2 face nodes (6 x 25 x 32 / 125 = 38.4 at N = 4)
+def sphere_bytes_per_node(N):
+    n1 = N + 1
+    return 120.0 + 80.0 + 6.0 * n1 * n1 * 32.0 / n1 ** 3
+
+
+def sphere_shell(dg, torch, N=4, n=24, nz=8, dt=0.1, steps=10):
+    """Cubed-sphere shell of section 4.4's size (6 panels of 24 x 24 elements, 8
+    layers, N = 4, r_e = 6371 km, 10 km top; uniform, no refinement), isothermal
+    300 K background, a Gaussian theta' of 1 K and 500 km half-width at latitude 0,
+    longitude 0: stage and right-hand-side durations, the HBM fraction of the stage
+    and the mass change over SSP-RK3 steps."""
+    ph = dg.PhysParams(background=dg.DG_BG_ISOTHERMAL)
+    m = dg.dg_sphere_mesh_build(N, n, nz)
+    xyz = torch.empty(3, m.K, m.Np, dtype=torch.float64, device="cuda")
+    dg.dg_node_coords(m, xyz)
+    r = torch.sqrt(xyz[0] ** 2 + xyz[1] ** 2 + xyz[2] ** 2)
+    r_e, R, T0 = 6.371e6, ph.cp - ph.cv, ph.theta0
+    rho_b = ph.P0 * torch.exp(-ph.g * (r - r_e) / (R * T0)) / (R * T0)
+    dist = r_e * torch.arccos(torch.clamp(xyz[0] / r, -1.0, 1.0))
+    q = m.field()
+    q[4] = rho_b * torch.exp(-(dist / 5.0e5) ** 2)
+    del xyz, r, rho_b, dist
+    qs, q1 = torch.empty_like(q), torch.empty_like(q)
+    dg.dg_rk_stage(m, ph, 0.0, 1.0, dt, q, q, qs)
+    nodes = m.K * m.Np
+    st_us = _time_launches(torch, lambda: dg.dg_rk_stage(m, ph, 0.75, 0.25, dt, q, qs, q1), 20)
+    R1 = torch.empty_like(q)
+    rhs_us = _time_launches(torch, lambda: dg.dg_rhs(m, ph, q, R1), 20)
+    bpn = sphere_bytes_per_node(N)
+    b0 = dg.dg_budgets(m, ph, q)
+    a, b = torch.empty_like(q), torch.empty_like(q)
+    x = q.clone()
+    for _ in range(steps):
+        dg.ssp_rk3_step(m, ph, dt, x, a, b)
+    b1 = dg.dg_budgets(m, ph, x)
+    return {"workload": "cubed-sphere shell 6 x 24 x 24 x 8, N=4, r_e 6371 km, top 10 km, isothermal 300 K, "
+                        "theta' Gaussian 1 K / 500 km, SSP-RK3 dt=0.1 s",
+            "leaves": m.K, "nodes": nodes, "kernel": "k_stage_sphere<4, 1>",
+            "stage_us": st_us, "rhs_us": rhs_us, "bytes_per_node": bpn,
+            "frac_hbm": nodes * bpn / (st_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "dof_updates_per_s": 5.0 * nodes / (st_us * 1e-6),
+            "mass_prime_change_10_steps_rel_mass": (b1[0] - b0[0]) / b0[1],
+            "energy_rel_change_10_steps": (b1[3] - b0[3]) / abs(b0[3])}
+
+
 def budget_drift(dg, torch, mesh, q, ph, dt, steps=10):
     """Change of the integral of rho' per SSP-RK3 step over `steps` steps (no
     adaptation), relative to the integral of rho = rho_bar + rho'."""
@@ -514,6 +562,8 @@ def extras(dg, torch, mesh, q, ph, args):
     out["uniform_4x4x4_N4"] = {"rhs_us": _time_launches(torch, lambda: dg.dg_rhs(m1, ph, q1c, r1), 20),
                                "step_us": _time_launches(torch, step1, 20),
                                "step_us_hip_graph_of_10_steps": graph_us, "nodes": m1.K * m1.Np}
+    _progress("extras: cubed-sphere shell")
+    out["sphere_shell"] = sphere_shell(dg, torch)
     _progress("extras: long run")
     out["rtb_long_run"] = rtb_long_run(dg, torch, t_end=args.rtb_seconds)
     # ---- measured copy bandwidth (1 GiB device-to-device) beside the 8 TB/s spec
