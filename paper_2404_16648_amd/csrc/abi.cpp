@@ -54,7 +54,7 @@ void free_device(dg_mesh* m) {
     m->d_base = nullptr;
     m->d_ops = m->d_geo = m->d_c1d = m->d_bg = m->d_red = m->d_eta = nullptr;
     m->d_ftype = m->d_fnb = m->d_level = m->d_xsrc = m->d_xkind = nullptr;
-    m->d_hslot = m->d_hang = m->d_hleaves = nullptr;
+    m->d_hslot = m->d_hang = nullptr;
     m->d_mort = nullptr;
     m->d_mortC = nullptr;
     m->d_flags = nullptr;
@@ -66,10 +66,10 @@ void free_device(dg_mesh* m) {
 // byte offsets of the arrays in a mesh's one device block, 256-byte aligned;
 // [0, upload) is copied from the host, the rest is device workspace
 struct DevLayout {
-    size_t ops, geo, c1d, ft, nb, hs, hg, lv, xs, xk, sr, hl, met, fg, upload, bg, red, eta, fl, mort, mortC, total;
+    size_t ops, geo, c1d, ft, nb, hs, hg, lv, xs, xk, sr, met, fg, upload, bg, red, eta, fl, mort, mortC, total;
 };
 
-DevLayout dev_layout(int64_t K, int N, int64_t red_len, int64_t n_hang, int64_t n_hleaves, bool sphere) {
+DevLayout dev_layout(int64_t K, int N, int64_t red_len, int64_t n_hang, bool sphere) {
     const size_t N1 = (size_t)N + 1, k = (size_t)K;
     size_t end = 0;
     auto take = [&](size_t bytes) {
@@ -89,7 +89,6 @@ DevLayout dev_layout(int64_t K, int N, int64_t red_len, int64_t n_hang, int64_t 
     L.xs = take(sizeof(int32_t) * k);
     L.xk = take(sizeof(int32_t) * k);
     L.sr = take(sizeof(int32_t) * kStageRec * k);
-    L.hl = take(sizeof(int32_t) * (size_t)n_hleaves);
     // shell meshes: metric terms and face geometry
     L.met = take(sphere ? sizeof(double) * 10 * k * N1 * N1 * N1 : 0);
     L.fg = take(sphere ? sizeof(double) * 24 * k * N1 * N1 : 0);
@@ -119,7 +118,6 @@ void set_device_pointers(dg_mesh* m, char* base, const DevLayout& L) {
     m->d_xsrc = (int32_t*)(base + L.xs);
     m->d_xkind = (int32_t*)(base + L.xk);
     m->d_srec = (int32_t*)(base + L.sr);
-    m->d_hleaves = (int32_t*)(base + L.hl);
     m->d_metric = m->h.sphere ? (double*)(base + L.met) : nullptr;
     m->d_fgeo = m->h.sphere ? (double*)(base + L.fg) : nullptr;
     m->d_bg = (double*)(base + L.bg);
@@ -213,19 +211,7 @@ dg_status build_device(dg_mesh* m, hipStream_t s) {
     const int N = h.desc.N, N1 = N + 1;
     m->red_len = (int64_t)budget_blocks(K) * 8 + 8;
     m->n_hang = (int64_t)h.hang.size() / 6;
-    // the leaves with a hanging face (a stage runs them in a launch of their own,
-    // after the mortar pre-pass)
-    std::vector<int32_t> hleaves;
-    for (int64_t e = 0; e < K; ++e)
-        for (int f = 0; f < 6; ++f) {
-            const int type = h.ftype[e * 6 + f] & 0xff;
-            if (type == FT_FINE || type == FT_COARSE) {
-                hleaves.push_back((int32_t)e);
-                break;
-            }
-        }
-    m->n_hleaves = (int64_t)hleaves.size();
-    const DevLayout L = dev_layout(K, N, m->red_len, m->n_hang, m->n_hleaves, h.sphere);
+    const DevLayout L = dev_layout(K, N, m->red_len, m->n_hang, h.sphere);
     // one staging buffer and one copy for every table of the mesh; the background,
     // reduction and flag buffers are carved from the same block
     UploadStaging& stg = upload_staging();
@@ -310,7 +296,6 @@ dg_status build_device(dg_mesh* m, hipStream_t s) {
             rec[19] = h.leaves[e].r;
         }
     }
-    if (m->n_hleaves) std::memcpy(up.data() + L.hl, hleaves.data(), sizeof(int32_t) * m->n_hleaves);
     char* base = nullptr;
     HIP_TRY(hipMalloc((void**)&base, L.total));
     set_device_pointers(m, base, L);
@@ -444,27 +429,6 @@ dg_status ensure_sigma(dg_mesh* m, hipStream_t s) {
         m->d_sigma = nullptr;
         return fail(DG_ENOMEM, "viscous workspace: hipMalloc failed");
     }
-    return DG_OK;
-}
-
-// A stream of the library's own per device, beside the caller's (default
-// priority, non-blocking): a stage on a mesh with hanging faces runs its mortar
-// pre-pass and then its leaves with a hanging face there, while the launch over
-// every other leaf runs on the caller's stream; fork and join by events, so the
-// call stays ordered on the caller's stream (and can be captured into a graph).
-// The mutex keeps each call's record / wait sequence whole.
-struct SideStream {
-    std::mutex mu;
-    hipStream_t s = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
-};
-
-dg_status side_stream(SideStream** out) {
-    static SideStream ss[kMaxDevices];
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    if (dev < 0 || dev >= kMaxDevices) return fail(DG_EINVAL, "device index out of range");
-    *out = &ss[dev];
     return DG_OK;
 }
 
@@ -737,33 +701,11 @@ static dg_status stage_common(const dg_mesh* mc, const dg_phys* phys, int mode, 
     const int N = m->h.desc.N;
     const bool mixed = phys->precision == DG_MIXED;
     if (m->n_hang) {
-        // fork: mortar pre-pass, then the leaves with a hanging face, on the side
-        // stream; every other leaf on the caller's stream meanwhile; join
-        SideStream* ss = nullptr;
-        if ((st = side_stream(&ss))) return st;
-        std::lock_guard<std::mutex> lock(ss->mu);
-        if (!ss->s) {
-            HIP_TRY(hipStreamCreateWithFlags(&ss->s, hipStreamNonBlocking));
-            HIP_TRY(hipEventCreateWithFlags(&ss->fork, hipEventDisableTiming));
-            HIP_TRY(hipEventCreateWithFlags(&ss->join, hipEventDisableTiming));
-        }
         MortArgs ma{qs, m->d_mort, m->d_ops, m->d_geo, m->d_bg, m->d_hang, m->n_hang, args.K, args.gamma, args.binom,
                     phys->nonconforming == DG_NC_POINTWISE ? 1 : 0};
-        StageArgs hb = args;
-        hb.order = m->d_hleaves;
-        hb.nblk = m->n_hleaves;
-        StageArgs rest = args;
-        rest.skip_hanging = 1;
-        HIP_TRY(hipEventRecord(ss->fork, s));
-        HIP_TRY(hipStreamWaitEvent(ss->s, ss->fork, 0));
-        HIP_TRY(launch_mortar(N, ma, ss->s));
-        HIP_TRY(launch_stage(N, mode, mixed, hb, ss->s));
-        HIP_TRY(hipEventRecord(ss->join, ss->s));
-        HIP_TRY(launch_stage(N, mode, mixed, rest, s));
-        HIP_TRY(hipStreamWaitEvent(s, ss->join, 0));
-    } else {
-        HIP_TRY(launch_stage(N, mode, mixed, args, s));
+        HIP_TRY(launch_mortar(N, ma, s));
     }
+    HIP_TRY(launch_stage(N, mode, mixed, args, s));
     if (phys->mu > 0.0) {
         // the stage is linear in R: add b dt R_visc(qs) (R_visc for dg_rhs) to its output
         if ((st = ensure_sigma(m, s))) return st;

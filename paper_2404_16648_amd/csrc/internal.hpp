@@ -89,8 +89,6 @@ struct dg_mesh {
     double* d_mort = nullptr;     // [n_hang][5][5][NF]: mortar pre-pass output (workspace)
     double* d_mortC = nullptr;    // [n_hang][5][NF]: tracer mortar pre-pass output (workspace)
     int64_t n_hang = 0;
-    int32_t* d_hleaves = nullptr; // [n_hleaves]: the leaves with a hanging face, in leaf order
-    int64_t n_hleaves = 0;
     // background profile [3][K][N1] for bg_phys (computed on first use)
     double* d_bg = nullptr;
     dg_phys bg_phys{};

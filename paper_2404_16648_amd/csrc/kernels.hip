@@ -279,8 +279,7 @@ k_stage(const StageArgs A) {
     __shared__ double sFr[MIX ? 15 : 1];  // MIX: reference flux [direction][variable]
 
     const int64_t K = A.K;
-    const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t e = A.order ? (int64_t)A.order[bid] : bid;
+    const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
     const int32_t* const rec = A.srec + e * kStageRec;
     const int t = threadIdx.x;
     const double gamma = A.gamma;
@@ -304,17 +303,6 @@ k_stage(const StageArgs A) {
         tfs[f] = rec[f];
         nbs[f] = rec[6 + f];
         hss[f] = rec[12 + f];
-    }
-    if (A.skip_hanging) {
-        // this launch leaves the leaves with a hanging face to a second launch that
-        // follows the mortar pre-pass (uniform: the whole workgroup returns)
-        bool hanging = false;
-#pragma unroll
-        for (int f = 0; f < 6; ++f) {
-            const int type = tfs[f] & 0xff;
-            hanging = hanging || type == FT_FINE || type == FT_COARSE;
-        }
-        if (hanging) return;
     }
     if (t < 6) {
         sType[t] = rec[t];
@@ -1581,9 +1569,8 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_indicator(const IndArgs A) {
     }
 
 hipError_t launch_stage(int N, int mode, bool mixed, const StageArgs& a, hipStream_t s) {
-    const int64_t nblk = a.order ? a.nblk : a.K;
-    if (nblk <= 0) return hipSuccess;
-    const dim3 grid((unsigned)nblk);
+    if (a.K <= 0) return hipSuccess;
+    const dim3 grid((unsigned)a.K);
     const bool stream = mode == MODE_RK && a.stream_io;
     // a == 0 (the first SSP-RK3 stage): q0 is not read, and the kernel without it
     // keeps the register count of the right-hand side (one more wave per SIMD)

@@ -39,11 +39,6 @@ struct StageArgs {
     const int32_t* hslot;  // [K][6]: row of the hanging-face table, or -1
     const double* mort;    // [n_hang][5][5][NF]: lifted mortar contributions (k_mortar)
     const int32_t* srec;   // [K][kStageRec]: face tables, one record per leaf
-    // leaves of the launch: order == nullptr: all K leaves (skip_hanging: those with
-    // a hanging face return at once); otherwise the nblk leaves order[0..nblk)
-    const int32_t* order;
-    int64_t nblk;
-    int32_t skip_hanging;
     int64_t K;
     double a, b, dt;
     double gamma, g;
