@@ -81,7 +81,7 @@ def kernel_sources_sha256():
     h = hashlib.sha256()
     for part in parts:
         h.update(part.encode())
-    for name in ("kernels.hpp", "facetypes.hpp", "forest.cpp"):
+    for name in ("kernels.hpp", "device_common.hpp", "facetypes.hpp", "forest.cpp"):
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
