@@ -53,10 +53,10 @@ BUBBLE = dict(N=7, nroot=(8, 8, 8), L=2, lo=(0.0, 0.0, 0.0), hi=(1000.0, 1000.0,
 # for the kernel and forest sources they were taken on (SHA-256 below); otherwise
 # traffic is reported as null.  Not measured by the run that prints the line.
 TRAFFIC = {
-    "sources_sha256": None,
-    "fetch_scale": 1048576.0 / 524302.0,  # 1 GiB copy: FETCH_SIZE reads 524302.0 KiB
+    "sources_sha256": "4b57c628a5461653bbd15aa43118f3f7787fa8bb538adfbaaa70b6d417c6bda4",
+    "fetch_scale": 1048576.0 / 524299.5,  # 1 GiB copy: FETCH_SIZE reads 524299.5 KiB
     "write_scale": 1048576.0 / 1048576.0,  # 1 GiB copy: WRITE_SIZE reads 1048576.0 KiB
-    "density_current": {"fetch_kib": None, "write_kib": None},
+    "density_current": {"fetch_kib": 132938.1, "write_kib": 128849.0},
     "source": "profiles/k_stage_density_current_N4_traffic.md",
 }
 CSRC = os.path.join(ROOT, "paper_2404_16648_amd", "csrc")
