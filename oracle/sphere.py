@@ -415,3 +415,141 @@ def element_areas(mesh: SphereMesh, radius):
         out[e] = radius * radius * (spherical_excess(corners[0], corners[1], corners[2])
                                     + spherical_excess(corners[0], corners[2], corners[3]))
     return out
+
+
+def element_volumes(mesh: SphereMesh):
+    """volume of every element from its spherical-excess footprint on the unit
+    sphere (section 3.4's area formula) times the radial integral of r^2:
+    A_1 (r_top^3 - r_bot^3)/3, the difference of cubes written as (r_top - r_bot)
+    (r_top^2 + r_top r_bot + r_bot^2)/3 to keep its digits"""
+    d = mesh.desc
+    A1 = element_areas(mesh, 1.0)
+    ir = mesh.leaves[:, 3].astype(np.float64)
+    r0 = d.r_e + d.H * ir / d.nz
+    r1 = d.r_e + d.H * (ir + 1.0) / d.nz
+    return A1 * (r1 - r0) * (r1 * r1 + r1 * r0 + r0 * r0) / 3.0
+
+
+def discrete_volume(op: SphereOperator):
+    """the volume the isoparametric elements enclose, sum of J W over all nodes"""
+    return math.fsum(quad_weights(op).reshape(-1).tolist())
+
+
+# ----------------------------------------------------------------------------- shell transfers (section 3.4)
+#
+# Transfers between two uniform shells, the fine one with twice the elements per
+# panel edge and twice the layers: every element of the coarse shell is the parent
+# of the eight fine elements (p, 2 ia + ax, 2 ib + ay, 2 ir + az), child
+# a = ax + 2 ay + 4 az, whose reference box is half ax, ay, az of the parent's along
+# its three local axes.  Only the reference-element matrices are used (I_a, R_a),
+# corrected as the paper prescribes for curved elements:
+#
+# * coarsening: the parent is the sum over its children of R_ax x R_ay x R_az q_a
+#   (the reference projection, whose element mean weighs every child by an eighth),
+#   plus the constant that makes the parent's mean the children's means weighted by
+#   their volumes, V_p m(q_p) = sum_a V_a m(q_a) with the spherical-excess volumes
+#   and m the mean over the reference cube, (1/8) sum W q: the finite-volume
+#   balance; a constant stays constant;
+# * refinement: every child takes I_ax x I_ay x I_az of its parent, then one scale
+#   factor s, the total mass before over the total mass after (the J W quadrature
+#   of rho = rhobar + rho' on each shell), multiplies every conserved field,
+#   rho, rho u and Theta (background included), in every child; velocity and
+#   potential temperature keep their interpolated values.
+
+def _check_pair(coarse: SphereMesh, fine: SphereMesh):
+    dc, df = coarse.desc, fine.desc
+    if (df.n, df.nz, df.N) != (2 * dc.n, 2 * dc.nz, dc.N) or (df.r_e, df.H) != (dc.r_e, dc.H):
+        raise ValueError("the fine shell must have twice the elements per edge and layers of the coarse one")
+
+
+def children(coarse: SphereMesh, fine: SphereMesh):
+    """ch[e, a] = index of child a of coarse element e in the fine shell"""
+    _check_pair(coarse, fine)
+    ch = np.zeros((coarse.K, 8), dtype=np.int64)
+    for e, (p, ia, ib, ir) in enumerate(coarse.leaves):
+        for a in range(8):
+            ax, ay, az = a & 1, (a >> 1) & 1, a >> 2
+            ch[e, a] = leaf_index(fine.desc, p, 2 * ia + ax, 2 * ib + ay, 2 * ir + az)
+    return ch
+
+
+def _apply3(A, B, C, t):
+    """(C x B x A) applied to nodal fields [..., k, j, i]: A along i, B along j, C along k"""
+    A, B, C = (torch.as_tensor(M, dtype=F64) for M in (A, B, C))
+    return torch.einsum('im,jn,kl,...lnm->...kji', A, B, C, t)
+
+
+def refine_shell(op_c: SphereOperator, op_f: SphereOperator, q_c):
+    """section 3.4 (b): reference interpolation into the children, then one mass
+    scale factor s applied to all conserved fields.  Returns (q_f, s)."""
+    ch = children(op_c.mesh, op_f.mesh)
+    I = op_c.re.I
+    q_f = torch.zeros(5, op_f.K, *q_c.shape[2:], dtype=F64)
+    for a in range(8):
+        ax, ay, az = a & 1, (a >> 1) & 1, a >> 2
+        q_f[:, torch.as_tensor(ch[:, a])] = _apply3(I[ax], I[ay], I[az], q_c)
+    mass_c = budgets(op_c, q_c)[1]
+    mass_f = budgets(op_f, q_f)[1]
+    s = mass_c / mass_f
+    rho_b, Th_b, _ = op_f.bg
+    out = q_f.clone()
+    out[0] = s * q_f[0] + (s - 1.0) * rho_b
+    out[1:4] = s * q_f[1:4]
+    out[4] = s * q_f[4] + (s - 1.0) * Th_b
+    return out, s
+
+
+def coarsen_shell(op_f: SphereOperator, op_c: SphereOperator, q_f):
+    """section 3.4 (a): the children's reference projections, plus per field the
+    constant that weighs the children's means by their volumes.  Returns (q_c, w)
+    with w[e, a] = V_a / sum_b V_b the volume fraction of child a of e."""
+    ch = children(op_c.mesh, op_f.mesh)
+    V = element_volumes(op_f.mesh)
+    Vc = V[ch]                                               # [Kc, 8]
+    w = Vc / Vc.sum(axis=1, keepdims=True)
+    Rm = op_c.re.R
+    q_c = torch.zeros(5, op_c.K, *q_f.shape[2:], dtype=F64)
+    shift = torch.zeros(5, op_c.K, dtype=F64)
+    for a in range(8):
+        ax, ay, az = a & 1, (a >> 1) & 1, a >> 2
+        qa = q_f[:, torch.as_tensor(ch[:, a])]
+        q_c = q_c + _apply3(Rm[ax], Rm[ay], Rm[az], qa)
+        shift = shift + (torch.as_tensor(w[:, a], dtype=F64)[None] - 0.125) * reference_means(qa)
+    return q_c + shift[:, :, None, None, None], w
+
+
+def reference_means(q):
+    """mean of each field over each element's reference cube, (1/8) sum W q, as
+    [5, K] (the quantity the finite-volume reading of the coarsening conserves)"""
+    N = q.shape[-1] - 1
+    w = torch.as_tensor(refelem(N).w, dtype=F64)
+    W = w[:, None, None] * w[None, :, None] * w[None, None, :]
+    return (q * W).sum(dim=(-3, -2, -1)) / 8.0
+
+
+# ----------------------------------------------------------------------------- acoustic wave (section 4.4)
+
+def acoustic_state(op: SphereOperator, h_max=100.0, r_c=None, lon=0.0, lat=0.0, n_v=1):
+    """Section 4.4's acoustic wave around the globe: a pressure perturbation
+    p' = f g on the background at rest, f the cosine bell (amplitude h_max, zero
+    beyond the geodesic radius r_c, r_e/3 by default) about longitude lon and
+    latitude lat (radians), g = sin(n_v pi h / H) with h the height.  Reading:
+    potential temperature is left unperturbed (the pressure rise is isentropic),
+    so Theta = (P0/R) (P/P0)^(1/gamma) at P = Pbar + p' and rho' = Theta'/thetabar.
+    Returns the state [5, K, N+1, N+1, N+1]."""
+    d, ph, geo = op.mesh.desc, op.phys, op.geo
+    if r_c is None:
+        r_c = d.r_e / 3.0
+    cx = (math.cos(lat) * math.cos(lon), math.cos(lat) * math.sin(lon), math.sin(lat))
+    cosang = geo.rhat[0] * cx[0] + geo.rhat[1] * cx[1] + geo.rhat[2] * cx[2]
+    dist = d.r_e * torch.arccos(torch.clamp(cosang, -1.0, 1.0))
+    f = torch.where(dist <= r_c, 0.5 * h_max * (1.0 + torch.cos(math.pi * dist / r_c)), torch.zeros_like(dist))
+    g = torch.sin(n_v * math.pi * geo.height / d.H)
+    pp = f * g
+    rho_b, Th_b, P_b = op.bg
+    Th = (ph.P0 / ph.R) * ((P_b + pp) / ph.P0) ** (1.0 / ph.gamma)
+    Thp = Th - Th_b
+    q = torch.zeros(5, *pp.shape, dtype=F64)
+    q[4] = Thp
+    q[0] = Thp * rho_b / Th_b
+    return q

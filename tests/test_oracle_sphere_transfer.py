@@ -1,0 +1,222 @@
+"""Pins of the oracle's shell transfers, element volumes and acoustic state
+(section 3.4: solution transfer on curved elements with the reference matrices,
+spherical-excess volumes, volume loss; section 4.4: the acoustic wave), no GPU.
+
+What the geometry and the definitions fix, independently of the code:
+  * the spherical-excess volumes of a shell's elements add up to the volume of the
+    spherical shell in closed form, and the eight children of an element add up to
+    their parent (the refined footprints tile the coarse ones exactly);
+  * a child's nodes are the parent's isoparametric mapping evaluated at the child's
+    reference points, up to the geometry's interpolation error (the child map and
+    its local axes);
+  * coarsening balances the children's volume-weighted element means exactly and
+    keeps a constant field constant;
+  * refinement keeps the total mass of the J W quadrature exactly and leaves the
+    velocity and the potential temperature at their interpolated values; on a
+    background of constant density at rest its scale factor is the ratio of the two
+    shells' discrete volumes, the volume-loss metric;
+  * the acoustic state's pressure perturbation is the cosine bell times
+    sin(pi h / H) and its potential temperature is unperturbed.
+Planted mistakes at the end: each must make one of these fail.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import euler as eu
+from oracle import sphere as sp
+
+F64 = torch.float64
+
+
+def _pair(N, n, nz, kind=sp.BG_ISOTHERMAL, ph=None):
+    ph = ph or eu.Phys()
+    oc = sp.SphereOperator(sp.SphereMesh(sp.SphereDesc(N=N, n=n, nz=nz)), ph, kind)
+    of = sp.SphereOperator(sp.SphereMesh(sp.SphereDesc(N=N, n=2 * n, nz=2 * nz)), ph, kind)
+    return oc, of
+
+
+def _fsum(t):
+    return math.fsum(np.asarray(t).reshape(-1).tolist())
+
+
+# ----------------------------------------------------------------------------- pins
+def check_volumes(n=3, nz=2):
+    m = sp.SphereMesh(sp.SphereDesc(N=3, n=n, nz=nz))
+    d = m.desc
+    V = sp.element_volumes(m)
+    Vex = 4.0 / 3.0 * math.pi * ((d.r_e + d.H) ** 3 - d.r_e ** 3)
+    assert abs(_fsum(V) - Vex) <= 1e-13 * Vex, (_fsum(V), Vex)
+    mf = sp.SphereMesh(sp.SphereDesc(N=3, n=2 * n, nz=2 * nz))
+    Vf = sp.element_volumes(mf)
+    ch = sp.children(m, mf)
+    assert float(np.abs(Vf[ch].sum(axis=1) - V).max()) <= 1e-13 * float(V.max())
+
+
+def check_child_geometry(N=4, n=2, nz=1):
+    oc, of = _pair(N, n, nz)
+    ch = torch.as_tensor(sp.children(oc.mesh, of.mesh))
+    I = oc.re.I
+    width = 0.5 * math.pi * oc.mesh.desc.r_e / (2 * n)     # a child's width at the panel centre
+    err = 0.0
+    for a in range(8):
+        ax, ay, az = a & 1, (a >> 1) & 1, a >> 2
+        for c in range(3):
+            xi = sp._apply3(I[ax], I[ay], I[az], oc.geo.x[c][None])[0]
+            err = max(err, float((of.geo.x[c][ch[:, a]] - xi).abs().max()))
+    # the coarse mapping interpolates the sphere at its own nodes: its error at the
+    # child's nodes is a small fraction of a child's width (a wrong child or axis
+    # moves a node by about a whole child width)
+    assert err <= 1e-3 * width, (err, width)
+
+
+def check_coarsen_balance_and_constants(N=4, n=2, nz=1, seed=5):
+    oc, of = _pair(N, n, nz)
+    g = torch.Generator().manual_seed(seed)
+    qf = torch.randn(5, of.K, N + 1, N + 1, N + 1, generator=g, dtype=F64)
+    qc, w = sp.coarsen_shell(of, oc, qf)
+    V = sp.element_volumes(of.mesh)
+    ch = sp.children(oc.mesh, of.mesh)
+    mf = sp.reference_means(qf).numpy()
+    mc = sp.reference_means(qc).numpy()
+    lhs = V[ch].sum(axis=1)[None] * mc
+    rhs = (V[ch][None] * mf[:, ch]).sum(axis=-1)
+    scale = float((V[ch][None] * np.abs(mf[:, ch])).sum(axis=-1).max())
+    assert float(np.abs(lhs - rhs).max()) <= 1e-14 * scale
+    const = torch.full_like(qf, 3.0)
+    qcc, _ = sp.coarsen_shell(of, oc, const)
+    assert float((qcc - 3.0).abs().max()) <= 1e-13 * 3.0
+
+
+def check_refine_mass_and_primitives(N=4, n=2, nz=1):
+    oc, of = _pair(N, n, nz)
+    q = sp.acoustic_state(oc)
+    q[1] = 1e-3 * oc.geo.x[1] / 6.4e3       # some momentum, so the scale on it is seen
+    qf, s = sp.refine_shell(oc, of, q)
+    m0, m1 = sp.budgets(oc, q)[1], sp.budgets(of, qf)[1]
+    assert abs(m1 - m0) <= 2e-16 * m0, (m0, m1)
+    ch = torch.as_tensor(sp.children(oc.mesh, of.mesh))
+    I = oc.re.I
+    rho_bc, Th_bc, _ = oc.bg
+    rho_bf, Th_bf, _ = of.bg
+    for a in range(8):
+        ax, ay, az = a & 1, (a >> 1) & 1, a >> 2
+        ip = lambda t: sp._apply3(I[ax], I[ay], I[az], t[None])[0]
+        rho_i = rho_bf[ch[:, a]] + ip(q[0])     # the interpolated perturbation on the child's background
+        u_i = ip(q[1]) / rho_i
+        th_i = (Th_bf[ch[:, a]] + ip(q[4])) / rho_i
+        rho_f = rho_bf[ch[:, a]] + qf[0][ch[:, a]]
+        assert float((qf[1][ch[:, a]] / rho_f - u_i).abs().max()) <= 1e-15 * float(u_i.abs().max())
+        assert float(((Th_bf[ch[:, a]] + qf[4][ch[:, a]]) / rho_f - th_i).abs().max()) <= 1e-15 * 300.0
+    assert 0.0 < abs(s - 1.0) < 1e-5
+
+
+def check_scale_is_volume_ratio(N=3, n=2, nz=1):
+    oc, of = _pair(N, n, nz, sp.BG_CONSTANT, eu.Phys(g=0.0))
+    q = torch.zeros(5, oc.K, N + 1, N + 1, N + 1, dtype=F64)
+    _, s = sp.refine_shell(oc, of, q)
+    Vc, Vf = sp.discrete_volume(oc), sp.discrete_volume(of)
+    assert abs(s - Vc / Vf) <= 4e-16, (s, Vc / Vf)
+    # the isoparametric shell gains volume under refinement (its coarse elements
+    # cut the curved surfaces), and the gain shrinks as the coarse shell is refined
+    oc2, of2 = _pair(N, 2 * n, nz, sp.BG_CONSTANT, eu.Phys(g=0.0))
+    _, s2 = sp.refine_shell(oc2, of2, torch.zeros(5, oc2.K, N + 1, N + 1, N + 1, dtype=F64))
+    assert s < 1.0 and s2 < 1.0 and abs(s2 - 1.0) < abs(s - 1.0) / 10.0, (s, s2)
+
+
+def check_acoustic_state(N=4, n=4, nz=1):
+    op = sp.SphereOperator(sp.SphereMesh(sp.SphereDesc(N=N, n=n, nz=nz)), eu.Phys(), sp.BG_ISOTHERMAL)
+    q = sp.acoustic_state(op)
+    rho_b, Th_b, P_b = op.bg
+    pp = eu.pressure_perturbation(q[4], Th_b, P_b, op.phys.gamma)
+    d = op.mesh.desc
+    dist = d.r_e * torch.arccos(torch.clamp(op.geo.rhat[0], -1.0, 1.0))
+    r_c = d.r_e / 3.0
+    f = torch.where(dist <= r_c, 50.0 * (1.0 + torch.cos(math.pi * dist / r_c)), torch.zeros_like(dist))
+    ref = f * torch.sin(math.pi * op.geo.height / d.H)
+    assert float((pp - ref).abs().max()) <= 1e-12 * 100.0
+    assert float(ref.abs().max()) > 50.0     # the bell is resolved
+    theta = (Th_b + q[4]) / (rho_b + q[0])
+    assert float((theta - Th_b / rho_b).abs().max()) <= 1e-13 * 300.0
+    assert float(q[1:4].abs().max()) == 0.0
+
+
+# ----------------------------------------------------------------------------- tests
+def test_element_volumes_exact_and_additive():
+    check_volumes()
+
+
+def test_children_are_the_parent_mapping():
+    check_child_geometry()
+
+
+def test_coarsen_finite_volume_balance_and_constants():
+    check_coarsen_balance_and_constants()
+
+
+def test_refine_keeps_mass_velocity_and_theta():
+    check_refine_mass_and_primitives()
+
+
+def test_refine_scale_is_the_volume_ratio():
+    check_scale_is_volume_ratio()
+
+
+def test_acoustic_state():
+    check_acoustic_state()
+
+
+# ----------------------------------------------------------------------------- planted mistakes
+def _literal_weights(mp):
+    """every child's projection multiplied by 8 V_a / V_p, with no mean correction"""
+    def coarsen(op_f, op_c, q_f):
+        ch = sp.children(op_c.mesh, op_f.mesh)
+        V = sp.element_volumes(op_f.mesh)[ch]
+        w = V / V.sum(axis=1, keepdims=True)
+        Rm = op_c.re.R
+        q_c = torch.zeros(5, op_c.K, *q_f.shape[2:], dtype=F64)
+        for a in range(8):
+            ax, ay, az = a & 1, (a >> 1) & 1, a >> 2
+            wa = torch.as_tensor(8.0 * w[:, a], dtype=F64)[None, :, None, None, None]
+            q_c = q_c + wa * sp._apply3(Rm[ax], Rm[ay], Rm[az], q_f[:, torch.as_tensor(ch[:, a])])
+        return q_c, w
+    mp.setattr(sp, "coarsen_shell", coarsen)
+
+
+def _scale_perturbation_only(mp):
+    orig = sp.refine_shell
+
+    def refine(op_c, op_f, q_c):
+        out, s = orig(op_c, op_f, q_c)
+        rho_b, Th_b, _ = op_f.bg
+        out = out.clone()
+        out[0] = out[0] - (s - 1.0) * rho_b
+        out[4] = out[4] - (s - 1.0) * Th_b
+        return out, s
+    mp.setattr(sp, "refine_shell", refine)
+
+
+def _swapped_child_axes(mp):
+    orig = sp.children
+
+    def children(coarse, fine):
+        ch = orig(coarse, fine)
+        return ch[:, [0, 2, 1, 3, 4, 6, 5, 7]]
+    mp.setattr(sp, "children", children)
+
+
+MUTANTS = {
+    "volume weights multiplying the projections": (_literal_weights, check_coarsen_balance_and_constants),
+    "scale factor on the perturbations only": (_scale_perturbation_only, check_refine_mass_and_primitives),
+    "child axes swapped": (_swapped_child_axes, check_child_geometry),
+}
+
+
+@pytest.mark.parametrize("name", list(MUTANTS))
+def test_planted_mistake_is_caught(name, monkeypatch):
+    plant, check = MUTANTS[name]
+    plant(monkeypatch)
+    with pytest.raises(AssertionError):
+        check()
