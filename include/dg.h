@@ -193,8 +193,10 @@ dg_status dg_mesh_build(const dg_forest_desc* desc, const dg_mesh* prev, const i
  * normal and face Jacobian, taken for a shared face from the (leaf, face) pair
  * that comes first so that both sides use bitwise-opposite normals.  dg_rhs,
  * dg_rk_stage, dg_budgets and dg_node_coords accept such meshes (float64,
- * mu = 0; background z is the height above r_e); the other calls return
- * DG_EUNSUPPORTED (no refinement on the shell).  DG_EINVAL on bad sizes. */
+ * mu = 0; background z is the height above r_e), and the dg_sphere_* transfers
+ * between a shell and the shell with twice its resolution; the other calls
+ * return DG_EUNSUPPORTED (no local refinement on the shell).  N = 2..5.
+ * DG_EINVAL on bad sizes. */
 dg_status dg_sphere_mesh_build(const dg_sphere_desc* desc, dg_mesh** out);
 /* Face connectivity of a shell mesh (not in the paper): nb[K][6][3] (host,
  * caller-owned) = neighbour element (-1 at the walls), its face, and 1 when
@@ -207,6 +209,48 @@ dg_status dg_sphere_faces(const dg_mesh* mesh, int32_t* nb);
  * [3][K][N+1] (tan of the two panel angles, height above r_e).  Host only.
  * DG_EINVAL for a NULL argument or a brick mesh. */
 dg_status dg_sphere_geometry(const dg_mesh* mesh, double* metric, double* fgeo, double* c1d);
+/* Volumes of a shell's elements (section 3.4: areas of the curved elements from
+ * the spherical excess of their footprints, and the volume loss of a
+ * refinement).  vol (host [K], caller-owned, or NULL): each element's footprint
+ * area on the unit sphere (spherical excess of its two great-circle triangles,
+ * by the formula of Van Oosterom and Strackee) times (r_top^3 - r_bot^3)/3;
+ * these add up exactly across a refinement.  totals (host [2]): the volume the
+ * isoparametric elements enclose (J W summed over every node, from the same
+ * geometry the kernels use) and the sum of vol; the volume loss of a
+ * refinement is the relative change of totals[0] between the two shells.
+ * Host work (one evaluation of the geometry).  DG_EINVAL for a NULL totals or a
+ * brick mesh. */
+dg_status dg_sphere_volumes(const dg_mesh* mesh, double* vol, double* totals);
+/* Refinement transfer from a shell to the shell with twice the elements per
+ * panel edge and twice the layers (same N, r_e, H), section 3.4 (b) with the
+ * reference matrices only: each fine element (p, 2 ia + ax, 2 ib + ay,
+ * 2 ir + az) takes I_ax x I_ay x I_az of its parent, then one scale factor
+ * s = (total mass of the coarse state) / (total mass of the interpolated
+ * state), both the J W quadrature of rhobar + rho' on their own shell,
+ * multiplies every conserved field of every fine element, background included
+ * (rho' := s rho' + (s - 1) rhobar, U := s U, Theta' := s Theta' + (s - 1)
+ * Thetabar; a reading: velocity and potential temperature keep their
+ * interpolated values).  q_coarse, q_fine: device [5][K][Np] of their shells,
+ * caller-owned, not aliased; phys float64 without viscosity (its background
+ * gives rhobar, Thetabar).  If scale (host) is not NULL it receives s and the
+ * call waits for the stream; otherwise the call only enqueues.  Uses both
+ * meshes' reduction workspaces.  DG_EINVAL for shells that are not such a
+ * pair; DG_EUNSUPPORTED for DG_MIXED or mu > 0; DG_ENONFINITE for a non-finite
+ * s (only when scale is requested). */
+dg_status dg_sphere_refine_project(const dg_mesh* coarse, const dg_mesh* fine, const dg_phys* phys,
+                                   const double* q_coarse, double* q_fine, double* scale, void* stream);
+/* Coarsening transfer, the reverse pair, section 3.4 (a): each coarse element
+ * is the sum over its eight children of R_ax x R_ay x R_az q_a (the reference
+ * projection, in whose element mean every child counts for an eighth) plus,
+ * per field, the constant sum_a (w_a - 1/8) m(q_a) that weighs the children's
+ * means by their volumes instead (w_a: the child's spherical-excess volume over
+ * its family's, m: the mean over the reference cube, (1/8) sum of W q).  A
+ * reading: the element means obey the finite-volume balance V_p m(q_p) =
+ * sum_a V_a m(q_a) exactly and a constant field stays constant.  Linear, no
+ * background.  Fields as for dg_sphere_refine_project; enqueued on stream.
+ * DG_EINVAL for shells that are not such a pair. */
+dg_status dg_sphere_coarsen_project(const dg_mesh* fine, const dg_mesh* coarse, const double* q_fine,
+                                    double* q_coarse, void* stream);
 /* Whether dg_mesh_build(prev = mesh, flags, pass) would change a leaf of mesh
  * (section 3.1: a refine pass splits leaves flagged +1 below max_level; a
  * coarsen pass merges complete sibling families flagged -1 that pass the 2:1

@@ -58,7 +58,7 @@ void free_device(dg_mesh* m) {
     m->d_mort = nullptr;
     m->d_mortC = nullptr;
     m->d_flags = nullptr;
-    m->d_metric = m->d_fgeo = nullptr;
+    m->d_metric = m->d_fgeo = m->d_cw = nullptr;
     if (m->d_sigma) (void)hipFree(m->d_sigma);
     m->d_sigma = nullptr;
 }
@@ -66,7 +66,7 @@ void free_device(dg_mesh* m) {
 // byte offsets of the arrays in a mesh's one device block, 256-byte aligned;
 // [0, upload) is copied from the host, the rest is device workspace
 struct DevLayout {
-    size_t ops, geo, c1d, ft, nb, hs, hg, lv, xs, xk, sr, met, fg, upload, bg, red, eta, fl, mort, mortC, total;
+    size_t ops, geo, c1d, ft, nb, hs, hg, lv, xs, xk, sr, met, fg, cw, upload, bg, red, eta, fl, mort, mortC, total;
 };
 
 DevLayout dev_layout(int64_t K, int N, int64_t red_len, int64_t n_hang, bool sphere) {
@@ -92,6 +92,7 @@ DevLayout dev_layout(int64_t K, int N, int64_t red_len, int64_t n_hang, bool sph
     // shell meshes: metric terms and face geometry
     L.met = take(sphere ? sizeof(double) * 10 * k * N1 * N1 * N1 : 0);
     L.fg = take(sphere ? sizeof(double) * 24 * k * N1 * N1 : 0);
+    L.cw = take(sphere ? sizeof(double) * k : 0);
     L.upload = end;
     L.bg = take(sizeof(double) * 3 * k * N1);
     L.red = take(sizeof(double) * (size_t)red_len);
@@ -120,6 +121,7 @@ void set_device_pointers(dg_mesh* m, char* base, const DevLayout& L) {
     m->d_srec = (int32_t*)(base + L.sr);
     m->d_metric = m->h.sphere ? (double*)(base + L.met) : nullptr;
     m->d_fgeo = m->h.sphere ? (double*)(base + L.fg) : nullptr;
+    m->d_cw = m->h.sphere ? (double*)(base + L.cw) : nullptr;
     m->d_bg = (double*)(base + L.bg);
     m->d_red = (double*)(base + L.red);
     m->d_eta = (double*)(base + L.eta);
@@ -251,6 +253,24 @@ dg_status build_device(dg_mesh* m, hipStream_t s) {
         std::memset(geo, 0, sizeof(double) * 4 * K);
         std::memset(level, 0, sizeof(int32_t) * K);
         sphere_geometry(h, m->ops, (double*)(up.data() + L.met), (double*)(up.data() + L.fg), c1d);
+        // volume fraction of every element within its parent in the shell with half
+        // the elements per edge and layers (the weights of the coarsening); zeros when
+        // n or nz is odd (no such shell)
+        double* cw = (double*)(up.data() + L.cw);
+        std::fill(cw, cw + K, 0.0);
+        const dg_sphere_desc& sd = h.sdesc;
+        if (sd.n % 2 == 0 && sd.nz % 2 == 0) {
+            std::vector<long double> vol(K);
+            sphere_volumes(h, vol.data());
+            for (int64_t e = 0; e < K; ++e) {
+                const Leaf& L0 = h.leaves[e];
+                const int pa = L0.a[0] & ~1, pb = L0.a[1] & ~1, pr = L0.a[2] & ~1;
+                long double tot = 0.0L;
+                for (int c = 0; c < 8; ++c)
+                    tot += vol[sphere_leaf(sd, L0.r, pa + (c & 1), pb + ((c >> 1) & 1), pr + (c >> 2))];
+                cw[e] = (double)(vol[e] / tot);
+            }
+        }
     } else {
         for (int64_t e = 0; e < K; ++e) {
             double hh[3], c[3 * 8];  // N + 1 <= 8
@@ -575,6 +595,98 @@ dg_status dg_sphere_geometry(const dg_mesh* m, double* metric, double* fgeo, dou
     } catch (const std::bad_alloc&) {
         return fail(DG_ENOMEM, "host allocation failed");
     }
+    return DG_OK;
+}
+
+dg_status dg_sphere_volumes(const dg_mesh* m, double* vol, double* totals) {
+    if (!m || !totals) return fail(DG_EINVAL, "NULL argument");
+    if (!m->h.sphere) return fail(DG_EINVAL, "not a shell mesh");
+    try {
+        const int64_t K = (int64_t)m->h.leaves.size();
+        const int N1 = m->h.desc.N + 1, NP = N1 * N1 * N1;
+        std::vector<long double> v(K);
+        sphere_volumes(m->h, v.data());
+        long double ex = 0.0L;
+        for (int64_t e = 0; e < K; ++e) {
+            ex += v[e];
+            if (vol) vol[e] = (double)v[e];
+        }
+        // the isoparametric volume: J W summed over every node, J from the geometry
+        // the kernels use
+        std::vector<double> metric((size_t)10 * K * NP), fgeo((size_t)24 * K * N1 * N1), c1d((size_t)3 * K * N1);
+        sphere_geometry(m->h, m->ops, metric.data(), fgeo.data(), c1d.data());
+        const std::vector<double>& w = m->ops.w;
+        long double disc = 0.0L;
+        for (int64_t e = 0; e < K; ++e)
+            for (int n = 0; n < NP; ++n)
+                disc += (long double)metric[(size_t)e * NP + n] * w[n % N1] * w[(n / N1) % N1] * w[n / (N1 * N1)];
+        totals[0] = (double)disc;
+        totals[1] = (double)ex;
+    } catch (const std::bad_alloc&) {
+        return fail(DG_ENOMEM, "host allocation failed");
+    }
+    return DG_OK;
+}
+
+// a shell and the shell with twice the elements per panel edge and twice the layers
+static dg_status shell_pair(const dg_mesh* coarse, const dg_mesh* fine) {
+    if (!coarse || !fine) return fail(DG_EINVAL, "mesh is NULL");
+    if (!coarse->h.sphere || !fine->h.sphere) return fail(DG_EINVAL, "not a shell mesh");
+    const dg_sphere_desc &c = coarse->h.sdesc, &f = fine->h.sdesc;
+    if (f.N != c.N || f.n != 2 * c.n || f.nz != 2 * c.nz || f.r_e != c.r_e || f.H != c.H)
+        return fail(DG_EINVAL, "the fine shell must have the same N, r_e and H and twice the elements per "
+                               "panel edge and twice the layers of the coarse one");
+    if (coarse->device != fine->device) return fail(DG_EINVAL, "the two shells are on different devices");
+    return DG_OK;
+}
+
+dg_status dg_sphere_refine_project(const dg_mesh* coarse, const dg_mesh* fine, const dg_phys* phys,
+                                   const double* q_coarse, double* q_fine, double* scale, void* stream) {
+    dg_status st = shell_pair(coarse, fine);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = check_dev_mesh(coarse, s)) || (st = check_dev_mesh(fine, s))) return st;
+    if ((st = check_phys(phys))) return st;
+    if (!q_coarse || !q_fine) return fail(DG_EINVAL, "NULL field pointer");
+    if (phys->precision != DG_FP64 || phys->mu != 0.0)
+        return fail(DG_EUNSUPPORTED, "the shell transfer takes float64 physics without viscosity");
+    dg_mesh* mc = const_cast<dg_mesh*>(coarse);
+    dg_mesh* mf = const_cast<dg_mesh*>(fine);
+    if ((st = ensure_bg(mc, phys, s)) || (st = ensure_bg(mf, phys, s))) return st;
+    const int N = coarse->h.desc.N;
+    const int64_t Kc = (int64_t)coarse->h.leaves.size(), Kf = (int64_t)fine->h.leaves.size();
+    ShellXferArgs a{q_coarse, q_fine, fine->d_ops, fine->d_cw, Kc, Kf, coarse->h.sdesc.n, coarse->h.sdesc.nz};
+    HIP_TRY(launch_shell_refine(N, a, s));
+    // total mass before (coarse) and after (fine, interpolated): the budget reductions
+    const double* w = fine->d_ops + 5 * (N + 1) * (N + 1);
+    const int nbc = budget_blocks(Kc), nbf = budget_blocks(Kf);
+    double* out_c = mc->d_red + (int64_t)nbc * 8;
+    double* out_f = mf->d_red + (int64_t)nbf * 8;
+    BudgetArgs bc{q_coarse, mc->d_bg, mc->d_geo, mc->d_metric, mc->d_c1d, w, mc->d_red, Kc,
+                  phys->cp / phys->cv, phys->g, binom_coef(phys)};
+    BudgetArgs bf{q_fine, mf->d_bg, mf->d_geo, mf->d_metric, mf->d_c1d, w, mf->d_red, Kf,
+                  phys->cp / phys->cv, phys->g, binom_coef(phys)};
+    HIP_TRY(launch_budgets(N, bc, nbc, out_c, s));
+    HIP_TRY(launch_budgets(N, bf, nbf, out_f, s));
+    HIP_TRY(launch_shell_scale(N, q_fine, mf->d_bg, Kf, out_c, out_f, out_f + 4, s));
+    if (scale) {
+        HIP_TRY(hipMemcpyAsync(scale, out_f + 4, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (!std::isfinite(*scale)) return fail(DG_ENONFINITE, "non-finite scale factor");
+    }
+    return DG_OK;
+}
+
+dg_status dg_sphere_coarsen_project(const dg_mesh* fine, const dg_mesh* coarse, const double* q_fine,
+                                    double* q_coarse, void* stream) {
+    dg_status st = shell_pair(coarse, fine);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = check_dev_mesh(coarse, s)) || (st = check_dev_mesh(fine, s))) return st;
+    if (!q_coarse || !q_fine) return fail(DG_EINVAL, "NULL field pointer");
+    const int64_t Kc = (int64_t)coarse->h.leaves.size(), Kf = (int64_t)fine->h.leaves.size();
+    ShellXferArgs a{q_fine, q_coarse, fine->d_ops, fine->d_cw, Kf, Kc, coarse->h.sdesc.n, coarse->h.sdesc.nz};
+    HIP_TRY(launch_shell_coarsen(coarse->h.desc.N, a, s));
     return DG_OK;
 }
 

@@ -55,6 +55,10 @@ bool pass_changes(const HostMesh& prev, const int8_t* flags, bool refine);
 // normal and face Jacobian; c1d [3][K][N+1]: tan of the two panel angles, height)
 std::string sphere_build(const dg_sphere_desc& d, HostMesh& out);
 void sphere_geometry(const HostMesh& h, const RefOps& ops, double* metric, double* fgeo, double* c1d);
+// spherical-excess volume of every element [K]
+void sphere_volumes(const HostMesh& h, long double* vol);
+// index of element (panel p, column ia, row ib, layer ir)
+int64_t sphere_leaf(const dg_sphere_desc& d, int p, int ia, int ib, int ir);
 
 // geometry of leaf e: h[3] and 1-D node coordinates c[3][N+1]
 void leaf_geometry(const dg_forest_desc& desc, const Leaf& lf, const std::vector<double>& xi,
@@ -101,4 +105,5 @@ struct dg_mesh {
     double* d_sigma = nullptr;    // [3][5][K][Np]: viscous gradient (own allocation, at first use)
     double* d_metric = nullptr;   // sphere: [10][K][Np] J and metric terms
     double* d_fgeo = nullptr;     // sphere: [K][6][NF][4] face normal and face Jacobian
+    double* d_cw = nullptr;       // sphere with even n, nz: [K] volume fraction of the element in its parent
 };

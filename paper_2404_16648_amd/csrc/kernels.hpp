@@ -248,6 +248,22 @@ hipError_t launch_viscous(int N, const ViscArgs& a, hipStream_t s);
 hipError_t launch_stage_sphere(int N, int mode, const SphereStageArgs& a, hipStream_t s);
 hipError_t launch_node_coords_sphere(int64_t K, int N, const double* c1d, const int32_t* srec, double r_e,
                                      double* xyz, hipStream_t s);
+// transfers between a shell (nc per panel edge, nzc layers) and the shell with twice
+// both (N = 2..7): refine reads the coarse src and writes the fine dst, coarsen the
+// reverse; cw is the fine shell's volume fraction of each element in its parent
+struct ShellXferArgs {
+    const double* src;
+    double* dst;
+    const double* ops;
+    const double* cw;
+    int64_t Ksrc, Kdst;
+    int nc, nzc;
+};
+hipError_t launch_shell_refine(int N, const ShellXferArgs& a, hipStream_t s);
+hipError_t launch_shell_coarsen(int N, const ShellXferArgs& a, hipStream_t s);
+// s = tot_before[1] / tot_after[1] on every conserved field of q (the fine shell), s to s_out[0]
+hipError_t launch_shell_scale(int N, double* q, const double* bg, int64_t K, const double* tot_before,
+                              const double* tot_after, double* s_out, hipStream_t s);
 // integral of c [K][Np] with the weights J_e W_n (w the 1-D LGL weights): nblk <= budget_blocks(K)
 // blocks leave 2 doubles each in partial, the total goes to out_dev[0]
 hipError_t launch_weighted_sum(int N, const double* c, const double* geo, const double* w, int64_t K, int nblk,

@@ -246,4 +246,50 @@ void sphere_geometry(const HostMesh& h, const RefOps& ops, double* metric, doubl
         }
 }
 
+namespace {
+
+using V3 = std::array<ld, 3>;
+
+V3 unit_corner(int p, int sx, int sy, int n) {
+    const auto c = panel_point<ld>(p, tan_grid((ld)sx, n), tan_grid((ld)sy, n), 1.0L);
+    const ld r = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    return {c[0] / r, c[1] / r, c[2] / r};
+}
+
+ld dot3(const V3& a, const V3& b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// spherical excess (area on the unit sphere) of the triangle abc with great-circle
+// edges, by the formula of Van Oosterom and Strackee (1983):
+// tan(E/2) = |a . (b x c)| / (1 + a.b + b.c + c.a)
+ld tri_excess(const V3& a, const V3& b, const V3& c) {
+    const V3 bxc{b[1] * c[2] - b[2] * c[1], b[2] * c[0] - b[0] * c[2], b[0] * c[1] - b[1] * c[0]};
+    const ld num = std::fabs(dot3(a, bxc));
+    const ld den = 1.0L + dot3(a, b) + dot3(b, c) + dot3(c, a);
+    return 2.0L * std::atan2(num, den);
+}
+
+}  // namespace
+
+// Element volumes from the areas of their footprints (section 3.4: spherical
+// excess of the curved elements, whose edges are great-circle arcs on an
+// equiangular panel): area on the unit sphere (two triangles) times the radial
+// integral of r^2, (r1^3 - r0^3)/3 written as (r1 - r0)(r1^2 + r1 r0 + r0^2)/3.
+// Long double throughout.
+void sphere_volumes(const HostMesh& h, long double* vol) {
+    const dg_sphere_desc& d = h.sdesc;
+    const int n = d.n;
+    const int64_t K = (int64_t)h.leaves.size();
+    for (int64_t e = 0; e < K; ++e) {
+        const Leaf& L = h.leaves[e];
+        const int p = L.r, ia = L.a[0], ib = L.a[1], ir = L.a[2];
+        const int x0 = 2 * ia - n, x1 = x0 + 2, y0 = 2 * ib - n, y1 = y0 + 2;
+        const V3 c00 = unit_corner(p, x0, y0, n), c10 = unit_corner(p, x1, y0, n);
+        const V3 c11 = unit_corner(p, x1, y1, n), c01 = unit_corner(p, x0, y1, n);
+        const ld area = tri_excess(c00, c10, c11) + tri_excess(c00, c11, c01);
+        const ld r0 = (ld)d.r_e + (ld)d.H * (ld)ir / (ld)d.nz;
+        const ld r1 = (ld)d.r_e + (ld)d.H * (ld)(ir + 1) / (ld)d.nz;
+        vol[e] = area * (r1 - r0) * (r1 * r1 + r1 * r0 + r0 * r0) / 3.0L;
+    }
+}
+
 }  // namespace dgamr

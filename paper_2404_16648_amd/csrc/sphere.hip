@@ -213,6 +213,145 @@ __global__ void k_node_coords_sphere(int64_t K, int N1, const double* c1d, const
     for (int c = 0; c < 3; ++c) xyz[c * K * NP + idx] = r * (cp[c] / nrm);
 }
 
+// ---------------------------------------------------------------- shell transfers
+// Between a shell (nc x nc per panel, nzc layers) and the shell with twice the
+// elements per edge and twice the layers: child a = ax + 2 ay + 4 az of coarse
+// element (p, ia, ib, ir) is fine element (p, 2 ia + ax, 2 ib + ay, 2 ir + az), and
+// its reference box is half ax, ay, az of the parent's along the local axes.
+
+// one separable pass over the five fields of a tile in LDS: out[v][node] =
+// sum_m M[idx(node, axis)][m] in[v][node with that index replaced by m]
+template <int N>
+__device__ __forceinline__ void tile_pass(const double* in, double* out, const double* M, int axis, int t) {
+    constexpr int N1 = N + 1, NP = N1 * N1 * N1, NF = N1 * N1;
+    if (t >= NP) return;
+    const int i = t % N1, j = (t / N1) % N1, k = t / NF;
+    const int id = axis == 0 ? i : axis == 1 ? j : k;
+    const int stride = axis == 0 ? 1 : axis == 1 ? N1 : NF;
+    const int base = t - id * stride;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) acc = fma(M[id * N1 + m], in[v * NP + base + m * stride], acc);
+        out[v * NP + t] = acc;
+    }
+}
+
+// refinement: every fine element is I_ax x I_ay x I_az of its parent
+template <int N>
+__global__ void __launch_bounds__(Sz<N>::NT) k_shell_refine(const ShellXferArgs A) {
+    constexpr int N1 = N + 1, NP = N1 * N1 * N1, NF = N1 * N1, NT = Sz<N>::NT;
+    __shared__ double sT[5 * NP], sU[5 * NP], sM[3 * NF];
+    const int t = threadIdx.x;
+    const int64_t ef = blockIdx.x;
+    const int nf = 2 * A.nc, nzf = 2 * A.nzc;
+    const int iaf = (int)(ef % nf), ibf = (int)((ef / nf) % nf), irf = (int)((ef / ((int64_t)nf * nf)) % nzf);
+    const int p = (int)(ef / ((int64_t)nf * nf * nzf));
+    const int64_t ec = (((int64_t)p * A.nzc + (irf >> 1)) * A.nc + (ibf >> 1)) * A.nc + (iaf >> 1);
+    const int hal[3] = {iaf & 1, ibf & 1, irf & 1};
+    for (int x = t; x < 3 * NF; x += NT) {
+        const int ax = x / NF;
+        sM[x] = A.ops[(1 + hal[ax]) * NF + (x - ax * NF)];  // I_0 or I_1
+    }
+    if (t < NP)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sT[v * NP + t] = A.src[(v * A.Ksrc + ec) * NP + t];
+    __syncthreads();
+    tile_pass<N>(sT, sU, sM, 0, t);
+    __syncthreads();
+    tile_pass<N>(sU, sT, sM + NF, 1, t);
+    __syncthreads();
+    if (t < NP) {
+        const int k = t / NF, base = t - k * NF;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m < N1; ++m) acc = fma(sM[2 * NF + k * N1 + m], sT[v * NP + base + m * NF], acc);
+            A.dst[(v * A.Kdst + ef) * NP + t] = acc;
+        }
+    }
+}
+
+// coarsening: the parent is sum_a (R_ax x R_ay x R_az) q_a plus, per field, the
+// constant sum_a (w_a - 1/8) m(q_a), w_a the child's volume fraction and m the mean
+// over the reference cube, (1/8) sum W q
+template <int N>
+__global__ void __launch_bounds__(Sz<N>::NT) k_shell_coarsen(const ShellXferArgs A) {
+    constexpr int N1 = N + 1, NP = N1 * N1 * N1, NF = N1 * N1, NT = Sz<N>::NT;
+    __shared__ double sT[5 * NP], sU[5 * NP], sR[2 * NF], sW[N1], sShift[5];
+    const int t = threadIdx.x;
+    const int64_t ec = blockIdx.x;
+    const int nc = A.nc, nzc = A.nzc, nf = 2 * nc, nzf = 2 * nzc;
+    const int ia = (int)(ec % nc), ib = (int)((ec / nc) % nc), ir = (int)((ec / ((int64_t)nc * nc)) % nzc);
+    const int p = (int)(ec / ((int64_t)nc * nc * nzc));
+    for (int x = t; x < 2 * NF; x += NT) sR[x] = A.ops[3 * NF + x];  // R_0, R_1
+    if (t < N1) sW[t] = A.ops[5 * NF + t];
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double shift = 0.0;  // thread v < 5: the constant of field v
+    for (int a = 0; a < 8; ++a) {
+        const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+        const int64_t ef = (((int64_t)p * nzf + 2 * ir + az) * nf + 2 * ib + ay) * nf + 2 * ia + ax;
+        __syncthreads();  // the previous child's last pass has read sT
+        if (t < NP)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sT[v * NP + t] = A.src[(v * A.Ksrc + ef) * NP + t];
+        __syncthreads();
+        if (t < 5) {
+            double m = 0.0;
+            for (int nn = 0; nn < NP; ++nn) {
+                const int i = nn % N1, j = (nn / N1) % N1, k = nn / NF;
+                m = fma(sW[i] * sW[j] * sW[k], sT[t * NP + nn], m);
+            }
+            shift = fma(A.cw[ef] - 0.125, 0.125 * m, shift);
+        }
+        tile_pass<N>(sT, sU, sR + ax * NF, 0, t);
+        __syncthreads();
+        tile_pass<N>(sU, sT, sR + ay * NF, 1, t);
+        __syncthreads();
+        if (t < NP) {
+            const int k = t / NF, base = t - k * NF;
+            const double* Rz = sR + az * NF;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                double s = 0.0;
+#pragma unroll
+                for (int m = 0; m < N1; ++m) s = fma(Rz[k * N1 + m], sT[v * NP + base + m * NF], s);
+                acc[v] += s;
+            }
+        }
+    }
+    if (t < 5) sShift[t] = shift;
+    __syncthreads();
+    if (t < NP)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) A.dst[(v * A.Kdst + ec) * NP + t] = acc[v] + sShift[v];
+}
+
+// the refinement's scale factor s = (total mass before) / (total mass after) on
+// every conserved field of the fine shell: rho' <- s rho' + (s - 1) rhobar,
+// U <- s U, Theta' <- s Theta' + (s - 1) Thetabar
+template <int N>
+__global__ void __launch_bounds__(Sz<N>::NT) k_shell_scale(double* q, const double* bg, int64_t K,
+                                                           const double* tot_before, const double* tot_after,
+                                                           double* s_out) {
+    constexpr int N1 = N + 1, NP = N1 * N1 * N1;
+    const int t = threadIdx.x;
+    const int64_t e = blockIdx.x;
+    const double s = tot_before[1] / tot_after[1];
+    if (e == 0 && t == 0) s_out[0] = s;
+    if (t >= NP) return;
+    const int k = t / (N1 * N1);
+    const int64_t KNP = K * NP, idx = e * NP + t;
+    const double rb = bg[e * N1 + k], Tb = bg[K * N1 + e * N1 + k];
+    q[idx] = s * q[idx] + (s - 1.0) * rb;
+    q[KNP + idx] = s * q[KNP + idx];
+    q[2 * KNP + idx] = s * q[2 * KNP + idx];
+    q[3 * KNP + idx] = s * q[3 * KNP + idx];
+    q[4 * KNP + idx] = s * q[4 * KNP + idx] + (s - 1.0) * Tb;
+}
+
 }  // namespace
 
 // orders 2..5: the tile, the three contravariant flux planes and the face slots
@@ -242,6 +381,38 @@ hipError_t launch_node_coords_sphere(int64_t K, int N, const double* c1d, const 
     const int64_t n = K * (N + 1) * (N + 1) * (N + 1);
     if (n <= 0) return hipSuccess;
     k_node_coords_sphere<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(K, N + 1, c1d, srec, r_e, xyz);
+    return hipGetLastError();
+}
+
+// transfers: orders 2..7 (two tiles and three 1-D operators in LDS)
+#define DG_DISPATCH_XFER(N_, CALL)                                  \
+    switch (N_) {                                                   \
+        case 2: { constexpr int NN = 2; CALL; } break;              \
+        case 3: { constexpr int NN = 3; CALL; } break;              \
+        case 4: { constexpr int NN = 4; CALL; } break;              \
+        case 5: { constexpr int NN = 5; CALL; } break;              \
+        case 6: { constexpr int NN = 6; CALL; } break;              \
+        case 7: { constexpr int NN = 7; CALL; } break;              \
+        default: return hipErrorInvalidValue;                        \
+    }
+
+hipError_t launch_shell_refine(int N, const ShellXferArgs& a, hipStream_t s) {
+    if (a.Kdst <= 0) return hipSuccess;
+    DG_DISPATCH_XFER(N, (k_shell_refine<NN><<<dim3((unsigned)a.Kdst), dim3(Sz<NN>::NT), 0, s>>>(a)));
+    return hipGetLastError();
+}
+
+hipError_t launch_shell_coarsen(int N, const ShellXferArgs& a, hipStream_t s) {
+    if (a.Kdst <= 0) return hipSuccess;
+    DG_DISPATCH_XFER(N, (k_shell_coarsen<NN><<<dim3((unsigned)a.Kdst), dim3(Sz<NN>::NT), 0, s>>>(a)));
+    return hipGetLastError();
+}
+
+hipError_t launch_shell_scale(int N, double* q, const double* bg, int64_t K, const double* tot_before,
+                              const double* tot_after, double* s_out, hipStream_t s) {
+    if (K <= 0) return hipSuccess;
+    DG_DISPATCH_XFER(N, (k_shell_scale<NN><<<dim3((unsigned)K), dim3(Sz<NN>::NT), 0, s>>>(q, bg, K, tot_before,
+                                                                                       tot_after, s_out)));
     return hipGetLastError();
 }
 

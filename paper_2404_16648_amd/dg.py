@@ -42,7 +42,8 @@ EXPORTED = [
     "dg_init_bell", "dg_rhs", "dg_rk_stage", "dg_refine_project", "dg_coarsen_project",
     "dg_refine_project_adjoint", "dg_coarsen_project_adjoint", "dg_rhs_adjoint", "dg_rk_stage_adjoint", "dg_budgets", "dg_budgets_noalloc", "dg_indicator", "dg_indicator_async", "dg_pass_changes", "dg_flags_after_coarsen", "dg_tracer_rhs", "dg_tracer_stage", "dg_tracer_mass",
     "dg_project_fields", "dg_flags_buffer", "dg_fma_burst", "dg_sphere_mesh_build", "dg_sphere_faces",
-    "dg_sphere_geometry", "dg_last_error",
+    "dg_sphere_geometry", "dg_sphere_volumes", "dg_sphere_refine_project", "dg_sphere_coarsen_project",
+    "dg_last_error",
 ]
 
 
@@ -126,6 +127,9 @@ def lib():
         L.dg_sphere_mesh_build.argtypes = [C.POINTER(SphereDesc), C.POINTER(P)]
         L.dg_sphere_faces.argtypes = [P, P]
         L.dg_sphere_geometry.argtypes = [P, P, P, P]
+        L.dg_sphere_volumes.argtypes = [P, P, P]
+        L.dg_sphere_refine_project.argtypes = [P, P, C.POINTER(Phys), P, P, P, P]
+        L.dg_sphere_coarsen_project.argtypes = [P, P, P, P, P]
         L.dg_last_error.restype = C.c_char_p
         for name in EXPORTED:
             if name != "dg_last_error":
@@ -273,6 +277,34 @@ def dg_sphere_geometry(mesh: Mesh):
     _check(lib().dg_sphere_geometry(mesh.handle, C.c_void_p(metric.ctypes.data), C.c_void_p(fgeo.ctypes.data),
                                     C.c_void_p(c1d.ctypes.data)))
     return metric, fgeo, c1d
+
+
+def dg_sphere_volumes(mesh: Mesh):
+    """Spherical-excess volume of every element (float64 [K]) and the totals
+    (isoparametric volume sum J W, sum of the spherical-excess volumes)."""
+    vol = np.zeros(mesh.K)
+    tot = np.zeros(2)
+    _check(lib().dg_sphere_volumes(mesh.handle, C.c_void_p(vol.ctypes.data), C.c_void_p(tot.ctypes.data)))
+    return vol, (float(tot[0]), float(tot[1]))
+
+
+def dg_sphere_refine_project(coarse: Mesh, fine: Mesh, phys: PhysParams, q_coarse, q_fine, stream=None):
+    """Refinement transfer between a shell and its refinement; returns the mass scale factor."""
+    _shape_check(coarse, q_coarse)
+    _shape_check(fine, q_fine)
+    ph = phys.c()
+    s = np.zeros(1)
+    _check(lib().dg_sphere_refine_project(coarse.handle, fine.handle, C.byref(ph), _ptr(q_coarse), _ptr(q_fine),
+                                          C.c_void_p(s.ctypes.data), _stream(stream)))
+    return float(s[0])
+
+
+def dg_sphere_coarsen_project(fine: Mesh, coarse: Mesh, q_fine, q_coarse, stream=None):
+    """Coarsening transfer from a shell's refinement back to the shell."""
+    _shape_check(fine, q_fine)
+    _shape_check(coarse, q_coarse)
+    _check(lib().dg_sphere_coarsen_project(fine.handle, coarse.handle, _ptr(q_fine), _ptr(q_coarse),
+                                           _stream(stream)))
 
 
 def dg_pass_changes(mesh: Mesh, flags, pass_) -> bool:

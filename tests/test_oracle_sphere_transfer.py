@@ -168,6 +168,48 @@ def test_acoustic_state():
     check_acoustic_state()
 
 
+# ----------------------------------------------------------------------------- library host side
+def _lib_available():
+    try:
+        from paper_2404_16648_amd import dg
+        dg.lib()
+        return True
+    except RuntimeError:
+        return False
+
+
+@pytest.mark.skipif(not _lib_available(), reason="library not built")
+@pytest.mark.parametrize("N,n,nz", [(3, 2, 2), (4, 3, 1)])
+def test_library_volumes_match(N, n, nz):
+    """dg_sphere_volumes (long double, the excess by the tangent half-angle formula)
+    against the oracle (float64, the excess from interior angles)"""
+    from paper_2404_16648_amd import dg
+    lm = dg.dg_sphere_mesh_build(N, n, nz, host_only=True)
+    om = sp.SphereMesh(sp.SphereDesc(N=N, n=n, nz=nz))
+    vol, (v_disc, v_exc) = dg.dg_sphere_volumes(lm)
+    ref = sp.element_volumes(om)
+    assert float(np.abs(vol - ref).max()) <= 1e-13 * float(ref.max())
+    assert abs(v_exc - _fsum(ref)) <= 1e-13 * v_exc
+    op = sp.SphereOperator(om, eu.Phys(), sp.BG_ISOTHERMAL)
+    assert abs(v_disc - sp.discrete_volume(op)) <= 1e-13 * v_disc
+
+
+@pytest.mark.skipif(not _lib_available(), reason="library not built")
+def test_library_transfer_refusals():
+    """pairs that are not a shell and its refinement are refused before any device work"""
+    from paper_2404_16648_amd import dg
+    L = dg.lib()
+    a = dg.dg_sphere_mesh_build(3, 2, 1, host_only=True)
+    for b in (dg.dg_sphere_mesh_build(3, 4, 1, host_only=True),          # layers not doubled
+              dg.dg_sphere_mesh_build(4, 4, 2, host_only=True),          # another order
+              dg.dg_sphere_mesh_build(3, 4, 2, H=2.0e4, host_only=True)):  # another top
+        assert L.dg_sphere_coarsen_project(b.handle, a.handle, None, None, None) == dg.DG_EINVAL
+        assert b"twice" in L.dg_last_error()
+    box = dg.dg_mesh_build(3, (1, 1, 1), host_only=True)
+    assert L.dg_sphere_coarsen_project(box.handle, a.handle, None, None, None) == dg.DG_EINVAL
+    assert L.dg_sphere_volumes(box.handle, None, None) == dg.DG_EINVAL
+
+
 # ----------------------------------------------------------------------------- planted mistakes
 def _literal_weights(mp):
     """every child's projection multiplied by 8 V_a / V_p, with no mean correction"""
