@@ -406,6 +406,104 @@ def sphere_shell(dg, torch, N=4, n=24, nz=8, dt=0.1, steps=10):
             "energy_rel_change_10_steps": (b1[3] - b0[3]) / abs(b0[3])}
 
 
+def shell_transfers(dg, torch, N=4, n=12, nz=4):
+    """Section 3.4's transfer between the shell 6 x n x n x nz and its refinement
+    6 x 2n x 2n x 2nz (the shell of sphere_shell): refinement (reference
+    interpolation, the two mass reductions and the scale factor) and coarsening
+    (reference projections and the volume-weighted mean) durations, the scale
+    factor, the volume loss (isoparametric volumes) and the mass change of each
+    transfer, on the Gaussian theta' state of sphere_shell."""
+    ph = dg.PhysParams(background=dg.DG_BG_ISOTHERMAL)
+    mc, mf = dg.dg_sphere_mesh_build(N, n, nz), dg.dg_sphere_mesh_build(N, 2 * n, 2 * nz)
+    xyz = torch.empty(3, mc.K, mc.Np, dtype=torch.float64, device="cuda")
+    dg.dg_node_coords(mc, xyz)
+    r = torch.sqrt(xyz[0] ** 2 + xyz[1] ** 2 + xyz[2] ** 2)
+    r_e, R, T0 = 6.371e6, ph.cp - ph.cv, ph.theta0
+    rho_b = ph.P0 * torch.exp(-ph.g * (r - r_e) / (R * T0)) / (R * T0)
+    dist = r_e * torch.arccos(torch.clamp(xyz[0] / r, -1.0, 1.0))
+    qc = mc.field()
+    qc[4] = rho_b * torch.exp(-(dist / 5.0e5) ** 2)
+    del xyz, r, rho_b, dist
+    qf, qc2 = mf.field(), mc.field()
+    s = dg.dg_sphere_refine_project(mc, mf, ph, qc, qf)
+    b0, b1 = dg.dg_budgets(mc, ph, qc), dg.dg_budgets(mf, ph, qf)
+    dg.dg_sphere_coarsen_project(mf, mc, qf, qc2)
+    b2 = dg.dg_budgets(mc, ph, qc2)
+    ref_us = _time_launches(torch, lambda: dg.dg_sphere_refine_project(mc, mf, ph, qc, qf, scale=False), 10)
+    crs_us = _time_launches(torch, lambda: dg.dg_sphere_coarsen_project(mf, mc, qf, qc2), 10)
+    _, (vc, _) = dg.dg_sphere_volumes(mc)
+    _, (vf, ve) = dg.dg_sphere_volumes(mf)
+    byt = 40.0 * (mc.K + mf.K) * mc.Np      # one read of the source, one write of the target
+    return {"workload": f"6 x {n} x {n} x {nz} <-> 6 x {2 * n} x {2 * n} x {2 * nz}, N={N}, isothermal, "
+                        "theta' Gaussian 1 K / 500 km",
+            "refine_us": ref_us, "coarsen_us": crs_us,
+            "refine_note": "k_shell_refine + two mass reductions + k_shell_scale",
+            "coarsen_GBs": byt / (crs_us * 1e-6) / 1e9,
+            "scale_factor_minus_1": s - 1.0,
+            "volume_loss_rel": vf / vc - 1.0, "fine_volume_vs_spherical_excess_rel": vf / ve - 1.0,
+            "refine_mass_change_rel": (b1[1] - b0[1]) / b0[1],
+            "coarsen_mass_change_rel": (b2[1] - b1[1]) / b1[1]}
+
+
+def acoustic_wave(dg, torch, N=4, n=12, nz=1, dt=0.9, hours=18.0):
+    """Section 4.4's acoustic wave as the paper's two-dimensional shallow-atmosphere
+    problem (no gravity, uniform 300 K background): a cosine bell of 100 Pa and
+    radius r_e/3 about latitude 0, longitude 0 times sin(pi h / H), potential
+    temperature unperturbed; SSP-RK3 on 6 x n x n x nz.  Reports when the pressure
+    pulse at the antipode (mean over the nodes within 300 km) crosses zero between
+    its positive and negative lobes, against pi r_e / c, and the mass and energy
+    change over the run."""
+    import math
+    ph = dg.PhysParams(background=dg.DG_BG_ISOTHERMAL, g=0.0)
+    m = dg.dg_sphere_mesh_build(N, n, nz)
+    xyz = torch.empty(3, m.K, m.Np, dtype=torch.float64, device="cuda")
+    dg.dg_node_coords(m, xyz)
+    r = torch.sqrt(xyz[0] ** 2 + xyz[1] ** 2 + xyz[2] ** 2)
+    r_e, H, R, T0, P0 = 6.371e6, 1.0e4, ph.cp - ph.cv, ph.theta0, ph.P0
+    gam = ph.cp / ph.cv
+    dist = r_e * torch.arccos(torch.clamp(xyz[0] / r, -1.0, 1.0))
+    r_c = r_e / 3.0
+    f = torch.where(dist <= r_c, 50.0 * (1.0 + torch.cos(math.pi * dist / r_c)), torch.zeros_like(dist))
+    pp = f * torch.sin(math.pi * (r - r_e) / H)
+    Thb = P0 / R                                   # uniform background: P = P0, rho = P0 / (R T0)
+    q = m.field()
+    q[4] = (P0 / R) * ((P0 + pp) / P0) ** (1.0 / gam) - Thb
+    q[0] = q[4] / T0
+    anti = r_e * torch.arccos(torch.clamp(-xyz[0] / r, -1.0, 1.0)) <= 3.0e5
+    idx = torch.nonzero(anti.reshape(-1)).reshape(-1)
+    del xyz, r, dist, f, pp, anti
+    a, b = m.field(), m.field()
+    b0 = dg.dg_budgets(m, ph, q)
+    every, t_first = 300.0, 14.0 * 3600.0
+    times, vals = [], []
+    t, steps, nxt = 0.0, 0, t_first
+    t0 = time.perf_counter()
+    while t < hours * 3600.0 - 1e-9:
+        dg.ssp_rk3_step(m, ph, dt, q, a, b)
+        t += dt
+        steps += 1
+        if t >= nxt - 1e-9:
+            thp = q[4].reshape(-1)[idx]
+            times.append(t)
+            vals.append(float((P0 * ((R * (Thb + thp) / P0) ** gam - 1.0)).mean()))
+            nxt += every
+        if steps % 20000 == 0:
+            _progress(f"acoustic wave: t = {t / 3600.0:.1f} h")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b1 = dg.dg_budgets(m, ph, q)
+    i_max = max(range(len(vals)), key=lambda i: vals[i])
+    j = next((k for k in range(i_max, len(vals)) if vals[k] < 0.0), None)
+    t_zero = None if j is None else times[j - 1] + every * vals[j - 1] / (vals[j - 1] - vals[j])
+    c = math.sqrt(gam * R * T0)
+    return {"workload": f"cubed-sphere shell 6 x {n} x {n} x {nz}, N={N}, no gravity, 300 K, bell 100 Pa, "
+                        f"r_c = r_e/3, SSP-RK3 dt={dt} s, {hours} h",
+            "steps": steps, "wall_s": wall, "antipode_max_Pa": max(vals), "antipode_min_Pa": min(vals),
+            "antipode_zero_crossing_h": None if t_zero is None else t_zero / 3600.0,
+            "pi_r_e_over_c_h": math.pi * r_e / c / 3600.0, "c_m_s": c,
+            "mass_rel_change": (b1[1] - b0[1]) / b0[1], "energy_rel_change": (b1[3] - b0[3]) / abs(b0[3])}
+
+
 def budget_drift(dg, torch, mesh, q, ph, dt, steps=10):
     """Change of the integral of rho' per SSP-RK3 step over `steps` steps (no
     adaptation), relative to the integral of rho = rho_bar + rho'."""
@@ -564,6 +662,10 @@ def extras(dg, torch, mesh, q, ph, args):
                                "step_us_hip_graph_of_10_steps": graph_us, "nodes": m1.K * m1.Np}
     _progress("extras: cubed-sphere shell")
     out["sphere_shell"] = sphere_shell(dg, torch)
+    _progress("extras: shell transfers")
+    out["sphere_shell_transfers"] = shell_transfers(dg, torch)
+    _progress("extras: acoustic wave on the shell")
+    out["sphere_acoustic_wave"] = acoustic_wave(dg, torch)
     _progress("extras: long run")
     out["rtb_long_run"] = rtb_long_run(dg, torch, t_end=args.rtb_seconds)
     # ---- measured copy bandwidth (1 GiB device-to-device) beside the 8 TB/s spec

@@ -288,15 +288,17 @@ def dg_sphere_volumes(mesh: Mesh):
     return vol, (float(tot[0]), float(tot[1]))
 
 
-def dg_sphere_refine_project(coarse: Mesh, fine: Mesh, phys: PhysParams, q_coarse, q_fine, stream=None):
-    """Refinement transfer between a shell and its refinement; returns the mass scale factor."""
+def dg_sphere_refine_project(coarse: Mesh, fine: Mesh, phys: PhysParams, q_coarse, q_fine, stream=None,
+                             scale=True):
+    """Refinement transfer between a shell and its refinement; returns the mass
+    scale factor (waiting for the stream), or None with scale=False (enqueue only)."""
     _shape_check(coarse, q_coarse)
     _shape_check(fine, q_fine)
     ph = phys.c()
     s = np.zeros(1)
     _check(lib().dg_sphere_refine_project(coarse.handle, fine.handle, C.byref(ph), _ptr(q_coarse), _ptr(q_fine),
-                                          C.c_void_p(s.ctypes.data), _stream(stream)))
-    return float(s[0])
+                                          C.c_void_p(s.ctypes.data) if scale else None, _stream(stream)))
+    return float(s[0]) if scale else None
 
 
 def dg_sphere_coarsen_project(fine: Mesh, coarse: Mesh, q_fine, q_coarse, stream=None):
