@@ -58,6 +58,7 @@ class SphereDesc:
     nz: int                # radial layers
     r_e: float = 6.371e6   # the earth radius of section 4.4
     H: float = 1.0e4       # model top of section 4.4
+    max_level: int = 0     # refinement levels allowed above the unrefined shell
 
 
 # cube point of local panel coordinates (X, Y) with the panel's fixed coordinate c
@@ -70,43 +71,266 @@ def leaf_index(desc: SphereDesc, p, ia, ib, ir):
     return ((p * desc.nz + ir) * desc.n + ib) * desc.n + ia
 
 
-class SphereMesh:
-    """Elements and face connectivity: nb[e, f] = (neighbour leaf, its face,
-    flip), or (-1, -1, 0) for the walls at the bottom and top; flip = 1 when the
-    neighbour's face-local first axis runs opposite to this face's."""
+WALL, CONF, FINE, COARSE = 0, 1, 2, 3     # face kinds
 
-    def __init__(self, desc: SphereDesc):
+
+def _panel_coords(p, P, m):
+    """(X, Y) of the cube point P on panel p (P[fixed axis] = +-m), or None if
+    P does not lie on that panel"""
+    x, y, z = P
+    fixed = [(x, m), (y, m), (x, -m), (y, -m), (z, m), (z, -m)][p]
+    if fixed[0] != fixed[1]:
+        return None
+    return [(y, z), (-x, z), (-y, z), (x, z), (y, -x), (y, x)][p]
+
+
+def lateral_neighbour(p, m, gx, gy, f):
+    """Same-size neighbour across lateral face f of the cell (gx, gy) of panel p at
+    resolution m (cells per panel edge): (p2, gx2, gy2, f2, flip), flip = 1 when the
+    two faces' first axes run opposite.  Found on the integer lattice of grid lines
+    (a cell face's end points are cube points with integer coordinates in units of
+    half a cell), so faces across a panel edge match exactly."""
+    X0, Y0 = 2 * gx - m, 2 * gy - m
+    X1, Y1 = X0 + 2, Y0 + 2
+    a0, a1 = [((X0, Y0), (X0, Y1)), ((X1, Y0), (X1, Y1)), ((X0, Y0), (X1, Y0)), ((X0, Y1), (X1, Y1))][f]
+    step = [(-1, 0), (1, 0), (0, -1), (0, 1)][f]
+    gx2, gy2 = gx + step[0], gy + step[1]
+    if 0 <= gx2 < m and 0 <= gy2 < m:
+        return p, gx2, gy2, f ^ 1, 0
+    P0, P1 = panel_point(p, *a0, c=m), panel_point(p, *a1, c=m)
+    for p2 in range(6):
+        if p2 == p:
+            continue
+        b0, b1 = _panel_coords(p2, P0, m), _panel_coords(p2, P1, m)
+        if b0 is None or b1 is None:
+            continue
+        if b0[0] == b1[0]:              # a face of constant X: faces 0 / 1, first axis Y
+            f2 = 0 if b0[0] == -m else 1
+            gx2, gy2 = (0 if f2 == 0 else m - 1), (min(b0[1], b1[1]) + m) // 2
+            first = b0[1] < b1[1]       # does P0 sit at the neighbour face's a = 0 end
+        else:                           # constant Y: faces 2 / 3, first axis X
+            f2 = 2 if b0[1] == -m else 3
+            gx2, gy2 = (min(b0[0], b1[0]) + m) // 2, (0 if f2 == 2 else m - 1)
+            first = b0[0] < b1[0]
+        return p2, gx2, gy2, f2, 0 if first else 1
+    raise RuntimeError("no panel across a panel edge")
+
+
+def cell_neighbour(desc: SphereDesc, cell, f):
+    """Same-level neighbour of cell (p, l, gx, gy, gz) across face f: (cell2, f2,
+    flip), or None at the bottom and top walls"""
+    p, l, gx, gy, gz = cell
+    if f >= 4:
+        gz2 = gz + (1 if f == 5 else -1)
+        if not 0 <= gz2 < desc.nz << l:
+            return None
+        return (p, l, gx, gy, gz2), f ^ 1, 0
+    p2, gx2, gy2, f2, flip = lateral_neighbour(p, desc.n << l, gx, gy, f)
+    return (p2, l, gx2, gy2, gz), f2, flip
+
+
+def cell_children(cell):
+    """child c = bx + 2 by + 4 bz"""
+    p, l, gx, gy, gz = cell
+    return [(p, l + 1, 2 * gx + (c & 1), 2 * gy + ((c >> 1) & 1), 2 * gz + (c >> 2)) for c in range(8)]
+
+
+def cell_parent(cell):
+    p, l, gx, gy, gz = cell
+    return (p, l - 1, gx >> 1, gy >> 1, gz >> 1)
+
+
+def cell_child_id(cell):
+    return (cell[2] & 1) | ((cell[3] & 1) << 1) | ((cell[4] & 1) << 2)
+
+
+def _tangential(d):
+    return [(1, 2), (0, 2), (0, 1)][d]
+
+
+def leaf_key(desc: SphereDesc, cell):
+    """order: panel, root element (layer, row, column of the unrefined shell), then
+    the Morton key of the position inside the root at the finest level (x least
+    significant); the unrefined shell keeps e = ((p nz + ir) n + ib) n + ia"""
+    p, l, gx, gy, gz = cell
+    L = desc.max_level
+    lx, ly, lz = (g & ((1 << l) - 1) for g in (gx, gy, gz))
+    lx, ly, lz = lx << (L - l), ly << (L - l), lz << (L - l)
+    key = 0
+    for bit in range(L):
+        key |= (((lx >> bit) & 1) | (((ly >> bit) & 1) << 1) | (((lz >> bit) & 1) << 2)) << (3 * bit)
+    return (p, gz >> l, gy >> l, gx >> l, key)
+
+
+class SphereMesh:
+    """Leaves (p, l, gx, gy, gz): panel, level, and the cell's column, row and layer
+    among the n 2^l x n 2^l x nz 2^l cells of its panel at that level.  The
+    unrefined shell (level 0 everywhere) unless leaves are given.  Face tables per
+    leaf and face: kind[e, f] (WALL at the bottom and top, CONF, FINE: this leaf is
+    one of four fine sides of a hanging face, COARSE: its coarse side);
+    nb[e, f] = (neighbour leaf, its face, flip) for CONF, (coarse leaf, its face,
+    flip) for FINE, (hanging row, the fine leaves' face, flip) for COARSE,
+    (-1, -1, 0) at walls; aux[e, f] = the quadrant in the coarse face's axes for
+    FINE.  Hanging rows hang[h] = (coarse leaf, its face, the fine leaves by
+    quadrant qa + 2 qb over the coarse face's first and second axes), with the
+    fine leaves' face hang_ff[h] and flip hang_flip[h].  flip = 1 when the two
+    faces' first axes run opposite.  Transfer plan xfer_src, xfer_kind as for the
+    brick forest (-1 copy, 0..7 child, 8 family)."""
+
+    def __init__(self, desc: SphereDesc, leaves=None, xfer=None):
         n, nz = desc.n, desc.nz
         self.desc, self.N = desc, desc.N
-        self.K = 6 * n * n * nz
-        self.leaves = np.array([(p, ia, ib, ir) for p in range(6) for ir in range(nz) for ib in range(n)
-                                for ia in range(n)], dtype=np.int64)
-        nb = -np.ones((self.K, 6, 3), dtype=np.int64)
+        if leaves is None:
+            leaves = [(p, 0, ia, ib, ir) for p in range(6) for ir in range(nz) for ib in range(n) for ia in range(n)]
+        leaves = sorted(set(tuple(int(x) for x in lf) for lf in leaves), key=lambda c: leaf_key(desc, c))
+        self.leaves = np.array(leaves, dtype=np.int64).reshape(-1, 5)
+        self.K = len(leaves)
+        self.index = {lf: e for e, lf in enumerate(leaves)}
+        if xfer is None:
+            xfer = (np.arange(self.K), -np.ones(self.K, dtype=np.int64))
+        self.xfer_src, self.xfer_kind = (np.asarray(x, dtype=np.int64) for x in xfer)
+        self._tables()
+
+    def containing(self, cell):
+        """the leaf equal to or containing the cell, or None (the cell is refined)"""
+        p, l, gx, gy, gz = cell
+        for lv in range(l, -1, -1):
+            sh = l - lv
+            c = (p, lv, gx >> sh, gy >> sh, gz >> sh)
+            if c in self.index:
+                return c
+        return None
+
+    def _tables(self):
+        K = self.K
+        kind = np.zeros((K, 6), dtype=np.int64)
+        nb = -np.ones((K, 6, 3), dtype=np.int64)
         nb[:, :, 2] = 0
-        # lateral faces: key = (the two horizontal end points as integer lattice cube
-        # points, layer), value = (leaf, face, the point at the face's a = 0 end)
-        faces = {}
-        for e, (p, ia, ib, ir) in enumerate(self.leaves):
-            x0, x1, y0, y1 = 2 * ia - n, 2 * ia + 2 - n, 2 * ib - n, 2 * ib + 2 - n
-            ends = {0: ((x0, y0), (x0, y1)), 1: ((x1, y0), (x1, y1)),
-                    2: ((x0, y0), (x1, y0)), 3: ((x0, y1), (x1, y1))}
-            for f, (a0, a1) in ends.items():
-                P0 = panel_point(p, *a0, c=n)
-                P1 = panel_point(p, *a1, c=n)
-                faces.setdefault((frozenset((P0, P1)), ir), []).append((e, f, P0))
-            # radial faces
-            if ir > 0:
-                nb[e, 4] = (leaf_index(desc, p, ia, ib, ir - 1), 5, 0)
-            if ir < nz - 1:
-                nb[e, 5] = (leaf_index(desc, p, ia, ib, ir + 1), 4, 0)
-        for key, ends in faces.items():
-            if len(ends) != 2:
-                raise RuntimeError("unmatched lateral face")
-            (e0, f0, p0), (e1, f1, p1) = ends
-            flip = 0 if p0 == p1 else 1
-            nb[e0, f0] = (e1, f1, flip)
-            nb[e1, f1] = (e0, f0, flip)
-        self.nb = nb
+        aux = np.zeros((K, 6), dtype=np.int64)
+        hang, hang_ff, hang_flip = [], [], []
+        for e, lf in enumerate(map(tuple, self.leaves.tolist())):
+            for f in range(6):
+                got = cell_neighbour(self.desc, lf, f)
+                if got is None:
+                    continue
+                c, f2, flip = got
+                x = self.containing(c)
+                if x is not None and x[1] == lf[1]:
+                    kind[e, f], nb[e, f] = CONF, (self.index[x], f2, flip)
+                elif x is not None:
+                    # fine side: c lies inside the coarse leaf x; its quadrant on x's
+                    # face f2 is given by c's bits along that face's two axes
+                    t1, t2 = _tangential(f2 // 2)
+                    bits = (c[2] & 1, c[3] & 1, c[4] & 1)
+                    kind[e, f], nb[e, f], aux[e, f] = FINE, (self.index[x], f2, flip), bits[t1] + 2 * bits[t2]
+                else:
+                    # coarse side: the four children of c on its face f2, placed by
+                    # their bits along c's face axes (the first reversed when flipped)
+                    d2, s2 = f2 // 2, f2 % 2
+                    t1, t2 = _tangential(d2)
+                    fine = [None] * 4
+                    for ch in cell_children(c):
+                        b = (ch[2] & 1, ch[3] & 1, ch[4] & 1)
+                        if b[d2] != s2:
+                            continue
+                        qa = 1 - b[t1] if flip else b[t1]
+                        fine[qa + 2 * b[t2]] = self.index[ch]
+                    kind[e, f], nb[e, f] = COARSE, (len(hang), f2, flip)
+                    hang.append((e, f) + tuple(fine))
+                    hang_ff.append(f2)
+                    hang_flip.append(flip)
+        self.kind, self.nb, self.aux = kind, nb, aux
+        self.hang = np.array(hang, dtype=np.int64).reshape(-1, 6)
+        self.hang_ff = np.array(hang_ff, dtype=np.int64)
+        self.hang_flip = np.array(hang_flip, dtype=np.int64)
+
+
+def _ripple(desc, mesh_leaves):
+    """leaves with a face neighbour two or more levels finer (the 2:1 face balance)"""
+    tmp = SphereMesh.__new__(SphereMesh)
+    tmp.index = {lf: 0 for lf in mesh_leaves}
+    out = set()
+    for lf in mesh_leaves:
+        for f in range(6):
+            got = cell_neighbour(desc, lf, f)
+            if got is None:
+                continue
+            x = SphereMesh.containing(tmp, got[0])
+            if x is not None and x[1] <= lf[1] - 2:
+                out.add(x)
+    return out
+
+
+def refine_pass(prev: SphereMesh, flags) -> SphereMesh:
+    """section 3.1 refinement on the shell: leaves flagged +1 below max_level are
+    split, then every leaf with a face neighbour two levels finer, to a fixed point"""
+    desc = prev.desc
+    leaves = set(map(tuple, prev.leaves.tolist()))
+    for e, lf in enumerate(map(tuple, prev.leaves.tolist())):
+        if flags[e] > 0 and lf[1] < desc.max_level:
+            leaves.discard(lf)
+            leaves.update(cell_children(lf))
+    while True:
+        todo = _ripple(desc, leaves)
+        if not todo:
+            break
+        for x in todo:
+            leaves.discard(x)
+            leaves.update(cell_children(x))
+    new = sorted(leaves, key=lambda c: leaf_key(desc, c))
+    src, kind = np.zeros(len(new), dtype=np.int64), np.zeros(len(new), dtype=np.int64)
+    for e, lf in enumerate(new):
+        if lf in prev.index:
+            src[e], kind[e] = prev.index[lf], -1
+        else:
+            par = cell_parent(lf)
+            if par not in prev.index:
+                raise RuntimeError("a leaf was refined twice in one pass")
+            src[e], kind[e] = prev.index[par], cell_child_id(lf)
+    return SphereMesh(desc, new, (src, kind))
+
+
+def coarsen_pass(prev: SphereMesh, flags) -> SphereMesh:
+    """section 3.1 coarsening on the shell: a family of eight leaves, all flagged -1,
+    is replaced by its parent unless a leaf face-adjacent to the parent is two or
+    more levels finer than the parent (judged on the mesh before the pass)"""
+    desc = prev.desc
+    parents = set()
+    for e, lf in enumerate(map(tuple, prev.leaves.tolist())):
+        if lf[1] == 0 or flags[e] >= 0:
+            continue
+        par = cell_parent(lf)
+        if par in parents:
+            continue
+        fam = cell_children(par)
+        if not all(c in prev.index and flags[prev.index[c]] < 0 for c in fam):
+            continue
+        vetoed = False
+        for f in range(6):
+            got = cell_neighbour(desc, par, f)
+            if got is None:
+                continue
+            c, f2, _ = got
+            if prev.containing(c) is not None:
+                continue
+            d2, s2 = f2 // 2, f2 % 2
+            for ch in cell_children(c):
+                if (ch[2 + d2] & 1) == s2 and ch not in prev.index:
+                    vetoed = True
+        if not vetoed:
+            parents.add(par)
+    leaves = set(map(tuple, prev.leaves.tolist()))
+    for par in parents:
+        leaves.difference_update(cell_children(par))
+        leaves.add(par)
+    new = sorted(leaves, key=lambda c: leaf_key(desc, c))
+    src, kind = np.zeros(len(new), dtype=np.int64), np.zeros(len(new), dtype=np.int64)
+    for e, lf in enumerate(new):
+        if lf in prev.index:
+            src[e], kind[e] = prev.index[lf], -1
+        else:
+            src[e], kind[e] = prev.index[cell_children(lf)[0]], 8
+    return SphereMesh(desc, new, (src, kind))
 
 
 LD = np.longdouble
@@ -115,9 +339,10 @@ PI_LD = np.longdouble("3.141592653589793238462643383279502884")
 
 def _tan_grid(s, n):
     """tan of the equiangular angle s pi/(4n) in long double, exactly +-1 on the
-    panel edges"""
+    panel edges (n may be an array broadcast against s)"""
     s = np.asarray(s, dtype=LD)
-    t = np.tan(s * PI_LD / (LD(4) * n))
+    n = np.asarray(n)
+    t = np.tan(s * PI_LD / (LD(4) * n.astype(LD)))
     t = np.where(s == n, LD(1), t)
     return np.where(s == -n, LD(-1), t)
 
@@ -167,12 +392,14 @@ class SphereGeometry:
         xi = np.asarray(re.x, dtype=np.float64).astype(LD)
         Dl = np.asarray(re.D, dtype=np.float64).astype(LD)
         self.D = torch.as_tensor(re.D, dtype=F64)
-        p, ia, ib, ir = (mesh.leaves[:, c] for c in range(4))
+        p, lv, gx, gy, gz = (mesh.leaves[:, c] for c in range(5))
+        m = (n << lv)[:, None]                     # cells per panel edge at each leaf's level
+        mz = (nz << lv).astype(LD)[:, None]
         # 1-D node parameters per leaf: X = tan alpha, Y = tan beta, height h
-        sX = (2 * ia - n).astype(LD)[:, None] + (xi[None, :] + LD(1))
-        sY = (2 * ib - n).astype(LD)[:, None] + (xi[None, :] + LD(1))
-        X1, Y1 = _tan_grid(sX, n), _tan_grid(sY, n)                      # [K, N+1]
-        h1 = LD(desc.H) * (ir.astype(LD)[:, None] + LD(0.5) * (xi[None, :] + LD(1))) / nz
+        sX = (2 * gx - (n << lv)).astype(LD)[:, None] + (xi[None, :] + LD(1))
+        sY = (2 * gy - (n << lv)).astype(LD)[:, None] + (xi[None, :] + LD(1))
+        X1, Y1 = _tan_grid(sX, m), _tan_grid(sY, m)                      # [K, N+1]
+        h1 = LD(desc.H) * (gz.astype(LD)[:, None] + LD(0.5) * (xi[None, :] + LD(1))) / mz
         self.X1, self.Y1, self.h1 = X1.astype(np.float64), Y1.astype(np.float64), h1.astype(np.float64)
         X = np.broadcast_to(X1[:, None, None, :], (K, n1, n1, n1))
         Y = np.broadcast_to(Y1[:, None, :, None], (K, n1, n1, n1))
@@ -220,7 +447,7 @@ class SphereGeometry:
         for e in range(K):
             for f in range(6):
                 e2, f2, flip = (int(x_) for x_ in mesh.nb[e, f])
-                if e2 < 0 or (e, f) < (e2, f2):
+                if mesh.kind[e, f] != CONF or (e, f) < (e2, f2):
                     nrm[:, e, f] = own_n[:, e, f]
                     sJ[e, f] = own_s[e, f]
                 else:
@@ -319,23 +546,25 @@ class SphereOperator:
         return R + S
 
     def surface(self, q, walls=True):
-        """Lifted face terms -(1/(J w_N)) (s F*(n) - sgn J a^d . F(q-)) at the face nodes."""
+        """Lifted face terms -(1/(J w_N)) (s F*(n) - sgn J a^d . F(q-)) at the face nodes
+        of conforming faces and walls, then the hanging faces (mortars)."""
         N, K, ph, geo = self.N, self.K, self.phys, self.geo
         Ft = self.contravariant(q)
         R = torch.zeros(5, K, N + 1, N + 1, N + 1, dtype=F64)
         nb = torch.as_tensor(self.mesh.nb)
+        kind = torch.as_tensor(self.mesh.kind)
         for f in range(6):
             d, sgn = f // 2, (1.0 if f % 2 else -1.0)
             qL = eu.face_slice(q, f, N)
             bL = tuple(eu.face_slice(b, f, N) for b in self.bg)
             nv = [geo.nrm[c, :, f] for c in range(3)]
             s = geo.sJ[:, f]
-            qR = torch.empty_like(qL)
-            bR = tuple(torch.empty_like(b) for b in bL)
-            wall = nb[:, f, 0] < 0
+            qR = qL.clone()
+            bR = tuple(b.clone() for b in bL)
+            wall, conf = kind[:, f] == WALL, kind[:, f] == CONF
             for f2 in range(6):
                 for flip in (0, 1):
-                    sel = (~wall) & (nb[:, f, 1] == f2) & (nb[:, f, 2] == flip)
+                    sel = conf & (nb[:, f, 1] == f2) & (nb[:, f, 2] == flip)
                     if not bool(sel.any()):
                         continue
                     e2 = nb[sel, f, 0]
@@ -346,18 +575,59 @@ class SphereOperator:
             if bool(wall.any()):
                 w = wall
                 Un = qL[1][w] * nv[0][w] + qL[2][w] * nv[1][w] + qL[3][w] * nv[2][w]
-                qR[0][w] = qL[0][w]
                 for c in range(3):
                     qR[1 + c][w] = qL[1 + c][w] - 2.0 * Un * nv[c][w]
-                qR[4][w] = qL[4][w]
-                for bi in range(3):
-                    bR[bi][w] = bL[bi][w]
-            act = torch.ones(K, dtype=torch.bool) if walls else ~wall
+            act = conf | wall if walls else conf
             Fs = rusanov_normal(qL, bL, qR, bR, ph, nv)
             delta = s[None] * Fs - sgn * eu.face_slice(Ft[d], f, N)
             JF = eu.face_slice(geo.J, f, N)
             delta = torch.where(act[None, :, None], delta / (JF[None] * self.wN), torch.zeros_like(delta))
             R = R - eu.face_embed(delta, f, N, K)
+        return R + self.mortars(q, Ft)
+
+    def mortars(self, q, Ft):
+        """Hanging faces (section 3.3 on curved faces): on each fine face the coarse
+        trace is interpolated to the fine face nodes (I_qa x I_qb in the coarse face's
+        axes, reordered by the orientation) and the Riemann problem is solved there
+        along the fine face's own normal and with the fine nodes' background; the fine
+        side lifts s_f F* like a conforming face.  The coarse side takes the flux with
+        the sign reversed per coarse reference area, 4 s_f (-F*) (a fine face covers a
+        quarter of the coarse reference face), projected back with R_qa x R_qb and
+        summed over the four quadrants: both sides see the same flux integral."""
+        N, K, ph, geo, re = self.N, self.K, self.phys, self.geo, self.re
+        mesh = self.mesh
+        R = torch.zeros(5, K, N + 1, N + 1, N + 1, dtype=F64)
+        I = [torch.as_tensor(M, dtype=F64) for M in re.I]
+        Rm = [torch.as_tensor(M, dtype=F64) for M in re.R]
+        for h in range(len(mesh.hang)):
+            ec, fc = int(mesh.hang[h, 0]), int(mesh.hang[h, 1])
+            ff, flip = int(mesh.hang_ff[h]), int(mesh.hang_flip[h])
+            perm = torch.as_tensor(face_perm(N, flip))
+            tc = eu.face_slice(q, fc, N)[:, ec]                              # [5, NF]
+            proj = torch.zeros_like(tc)
+            for quad in range(4):
+                qa, qb = quad & 1, quad >> 1
+                ef = int(mesh.hang[h, 2 + quad])
+                tf = eu.face_slice(q, ff, N)[:, ef]
+                qm = eu.interp2(I[qa], I[qb], tc, N)[:, perm]                # at the fine face nodes
+                bf = tuple(eu.face_slice(b, ff, N)[ef] for b in self.bg)
+                nv = [geo.nrm[c, ef, ff] for c in range(3)]
+                sf = geo.sJ[ef, ff]
+                Fs = rusanov_normal(tf, bf, qm, bf, ph, nv)
+                sgn_f = 1.0 if ff % 2 else -1.0
+                delta = sf[None] * Fs - sgn_f * eu.face_slice(Ft[ff // 2], ff, N)[:, ef]
+                JF = eu.face_slice(geo.J, ff, N)[ef]
+                d = torch.zeros(5, K, (N + 1) ** 2, dtype=F64)
+                d[:, ef] = delta / (JF[None] * self.wN)
+                R = R - eu.face_embed(d, ff, N, K)
+                g = (4.0 * sf)[None] * (-Fs)
+                proj = proj + eu.interp2(Rm[qa], Rm[qb], g[:, perm], N)
+            sgn_c = 1.0 if fc % 2 else -1.0
+            delta = proj - sgn_c * eu.face_slice(Ft[fc // 2], fc, N)[:, ec]
+            JF = eu.face_slice(geo.J, fc, N)[ec]
+            d = torch.zeros(5, K, (N + 1) ** 2, dtype=F64)
+            d[:, ec] = delta / (JF[None] * self.wN)
+            R = R - eu.face_embed(d, fc, N, K)
         return R
 
     def rhs(self, q):
@@ -404,9 +674,9 @@ def spherical_excess(A, B, C):
 def element_areas(mesh: SphereMesh, radius):
     """area of every element's footprint on the sphere of the given radius, as
     two spherical triangles of its corner points (section 3.4's area formula)"""
-    n = mesh.desc.n
     out = np.zeros(mesh.K)
-    for e, (p, ia, ib, ir) in enumerate(mesh.leaves):
+    for e, (p, lv, ia, ib, _) in enumerate(mesh.leaves):
+        n = mesh.desc.n << int(lv)
         corners = []
         for sx, sy in ((2 * ia - n, 2 * ib - n), (2 * ia + 2 - n, 2 * ib - n), (2 * ia + 2 - n, 2 * ib + 2 - n),
                        (2 * ia - n, 2 * ib + 2 - n)):
@@ -424,9 +694,10 @@ def element_volumes(mesh: SphereMesh):
     (r_top^2 + r_top r_bot + r_bot^2)/3 to keep its digits"""
     d = mesh.desc
     A1 = element_areas(mesh, 1.0)
-    ir = mesh.leaves[:, 3].astype(np.float64)
-    r0 = d.r_e + d.H * ir / d.nz
-    r1 = d.r_e + d.H * (ir + 1.0) / d.nz
+    ir = mesh.leaves[:, 4].astype(np.float64)
+    mz = (d.nz << mesh.leaves[:, 1]).astype(np.float64)
+    r0 = d.r_e + d.H * ir / mz
+    r1 = d.r_e + d.H * (ir + 1.0) / mz
     return A1 * (r1 - r0) * (r1 * r1 + r1 * r0 + r0 * r0) / 3.0
 
 
@@ -466,7 +737,7 @@ def children(coarse: SphereMesh, fine: SphereMesh):
     """ch[e, a] = index of child a of coarse element e in the fine shell"""
     _check_pair(coarse, fine)
     ch = np.zeros((coarse.K, 8), dtype=np.int64)
-    for e, (p, ia, ib, ir) in enumerate(coarse.leaves):
+    for e, (p, _, ia, ib, ir) in enumerate(coarse.leaves):
         for a in range(8):
             ax, ay, az = a & 1, (a >> 1) & 1, a >> 2
             ch[e, a] = leaf_index(fine.desc, p, 2 * ia + ax, 2 * ib + ay, 2 * ir + az)
@@ -553,3 +824,57 @@ def acoustic_state(op: SphereOperator, h_max=100.0, r_c=None, lon=0.0, lat=0.0, 
     q[4] = Thp
     q[0] = Thp * rho_b / Th_b
     return q
+
+
+# ----------------------------------------------------------------------------- transfers of a refinement pass (section 3.4)
+
+def _subset_mass(op: SphereOperator, q, elems):
+    """J W quadrature of rho = rhobar + rho' over the given leaves, exactly rounded"""
+    JW = quad_weights(op)[elems]
+    rho = op.bg[0][elems] + q[0][elems]
+    return math.fsum((JW * rho).reshape(-1).tolist())
+
+
+def adapt_project(op_from: SphereOperator, op_to: SphereOperator, q):
+    """Section 3.4's transfer along the plan of a refine or coarsen pass (op_to's
+    mesh built from op_from's): kept leaves are copied; a child takes the
+    reference interpolation of its parent, and one scale factor s (the mass of the
+    refined parents over the mass of their interpolated children) multiplies every
+    conserved field of every child, background included; a merged family becomes
+    the sum of its children's reference projections plus, per field, the constant
+    that weighs their means by their spherical-excess volumes.  Returns (q_to, s),
+    s = 1 when nothing was refined."""
+    mesh = op_to.mesh
+    src, kind = mesh.xfer_src, mesh.xfer_kind
+    I, Rm = op_to.re.I, op_to.re.R
+    out = torch.zeros(5, op_to.K, *q.shape[2:], dtype=F64)
+    V = element_volumes(op_from.mesh)
+    children_new, parents_old = [], set()
+    for e in range(op_to.K):
+        k, sidx = int(kind[e]), int(src[e])
+        if k == -1:
+            out[:, e] = q[:, sidx]
+        elif k < 8:
+            ax, ay, az = k & 1, (k >> 1) & 1, k >> 2
+            out[:, e] = _apply3(I[ax], I[ay], I[az], q[:, sidx][:, None])[:, 0]
+            children_new.append(e)
+            parents_old.add(sidx)
+        else:
+            fam = list(range(sidx, sidx + 8))
+            w = V[fam] / V[fam].sum()
+            acc = torch.zeros_like(q[:, sidx])
+            shift = torch.zeros(5, dtype=F64)
+            for a, ea in enumerate(fam):
+                ax, ay, az = a & 1, (a >> 1) & 1, a >> 2
+                acc = acc + _apply3(Rm[ax], Rm[ay], Rm[az], q[:, ea][:, None])[:, 0]
+                shift = shift + (float(w[a]) - 0.125) * reference_means(q[:, ea][:, None])[:, 0]
+            out[:, e] = acc + shift[:, None, None, None]
+    s = 1.0
+    if children_new:
+        s = _subset_mass(op_from, q, sorted(parents_old)) / _subset_mass(op_to, out, children_new)
+        ch = torch.as_tensor(children_new)
+        rho_b, Th_b, _ = op_to.bg
+        out[0, ch] = s * out[0, ch] + (s - 1.0) * rho_b[ch]
+        out[1:4, ch] = s * out[1:4, ch]
+        out[4, ch] = s * out[4, ch] + (s - 1.0) * Th_b[ch]
+    return out, s

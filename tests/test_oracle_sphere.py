@@ -158,7 +158,7 @@ def test_volume_converges_and_areas_exact():
     assert errs[-1] < 1e-8 and all(errs[i + 1] < errs[i] for i in range(3)), errs
     m = sp.SphereMesh(sp.SphereDesc(N=3, n=3, nz=2))
     A = sp.element_areas(m, m.desc.r_e)
-    layer = m.leaves[:, 3] == 0
+    layer = m.leaves[:, 4] == 0
     assert abs(math.fsum(A[layer]) - 4.0 * math.pi * m.desc.r_e ** 2) <= 1e-14 * 4.0 * math.pi * m.desc.r_e ** 2
 
 
@@ -204,7 +204,7 @@ def test_library_tables_and_geometry_match(N, n, nz):
     lm = dg.dg_sphere_mesh_build(N, n, nz, host_only=True)
     om = sp.SphereMesh(sp.SphereDesc(N=N, n=n, nz=nz))
     assert np.array_equal(dg.dg_sphere_faces(lm), om.nb.astype(np.int32))
-    assert np.array_equal(lm.tables()["leaf"][:, [0, 2, 3, 4]], om.leaves.astype(np.int32))
+    assert np.array_equal(lm.tables()["leaf"], om.leaves.astype(np.int32))
     metric, fgeo, c1d = dg.dg_sphere_geometry(lm)
     g = sp.SphereGeometry(om)
     J = g.J.reshape(om.K, -1).numpy()

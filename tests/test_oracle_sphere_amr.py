@@ -1,0 +1,273 @@
+"""Pins of the oracle's refinement on the cubed-sphere shell (sections 3.1 and 3.3
+on the curved elements of section 3.4), no GPU.
+
+What the geometry and the definitions fix, independently of the code:
+  * the face tables are closed: a conforming face points back, every fine face of a
+    hanging row names its coarse leaf, face, quadrant and orientation, and the
+    coarse face names its row; face neighbours differ by at most one level;
+  * a fine face's nodes are the coarse face's mapping at the fine nodes' places in
+    the recorded quadrant and orientation, up to the geometry's interpolation error;
+  * refining every leaf once gives the cells of the unrefined shell with twice the
+    resolution, and the operator on them is that shell's operator;
+  * with hanging faces a rest state is exact, and the integrals of R_rho and
+    R_Theta vanish to round-off (the mortars conserve mass and Theta);
+  * for a smooth state, the right-hand side on fine leaves beside hanging faces is
+    close to that on the uniformly refined shell (the mortar reads the coarse trace
+    at the right places);
+  * the transfers of a refinement pass keep the total mass exactly, those of a
+    coarsening pass balance the volume-weighted element means exactly, and a
+    coarsening pass undoes a refinement pass on the leaves.
+Planted mistakes at the end: each must make one of these fail.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import euler as eu
+from oracle import sphere as sp
+from paper_2404_16648_amd.synth import random_state
+
+F64 = torch.float64
+
+
+def _amr_mesh(N=3, n=2, nz=1, L=2, seed=1, frac=(0.3, 0.2)):
+    d = sp.SphereDesc(N=N, n=n, nz=nz, max_level=L)
+    m = sp.SphereMesh(d)
+    rng = np.random.default_rng(seed)
+    for fr in frac[:L]:
+        m = sp.refine_pass(m, (rng.random(m.K) < fr).astype(int))
+    return m
+
+
+def _smooth_state(op):
+    x = op.geo.x
+    r = torch.sqrt(x[0] ** 2 + x[1] ** 2 + x[2] ** 2)
+    q = torch.zeros(5, op.K, op.N + 1, op.N + 1, op.N + 1, dtype=F64)
+    q[0] = 1e-3 * torch.exp(-((x[0] / r - 0.7) ** 2 + (x[1] / r - 0.5) ** 2) * 3.0) * torch.sin(
+        math.pi * op.geo.height / op.mesh.desc.H)
+    Om = (0.3e-5, -0.5e-5, 1.0e-5)
+    q[1] = Om[1] * x[2] - Om[2] * x[1]
+    q[2] = Om[2] * x[0] - Om[0] * x[2]
+    q[3] = Om[0] * x[1] - Om[1] * x[0]
+    q[4] = 600.0 * q[0]
+    return q
+
+
+# ----------------------------------------------------------------------------- pins
+def check_tables(m=None):
+    m = m or _amr_mesh()
+    d = m.desc
+    assert int((m.kind == sp.COARSE).sum()) == len(m.hang)
+    assert int((m.kind == sp.FINE).sum()) == 4 * len(m.hang)
+    for e in range(m.K):
+        for f in range(6):
+            k = int(m.kind[e, f])
+            e2, f2, flip = (int(x) for x in m.nb[e, f])
+            if k == sp.CONF:
+                assert m.kind[e2, f2] == sp.CONF and tuple(int(x) for x in m.nb[e2, f2]) == (e, f, flip)
+                assert m.leaves[e, 1] == m.leaves[e2, 1]
+            elif k == sp.WALL:
+                assert f >= 4
+    for h, row in enumerate(m.hang):
+        ec, fc = int(row[0]), int(row[1])
+        assert m.kind[ec, fc] == sp.COARSE and int(m.nb[ec, fc, 0]) == h
+        for quad in range(4):
+            ef = int(row[2 + quad])
+            ff = int(m.hang_ff[h])
+            assert m.kind[ef, ff] == sp.FINE
+            assert tuple(int(x) for x in m.nb[ef, ff]) == (ec, fc, int(m.hang_flip[h]))
+            assert int(m.aux[ef, ff]) == quad
+            assert m.leaves[ef, 1] == m.leaves[ec, 1] + 1
+    # 2:1 across every face
+    for e, lf in enumerate(map(tuple, m.leaves.tolist())):
+        for f in range(6):
+            got = sp.cell_neighbour(d, lf, f)
+            if got is None:
+                continue
+            x = m.containing(got[0])
+            assert x is None or lf[1] - x[1] <= 1
+
+
+def check_hanging_geometry(N=4):
+    m = _amr_mesh(N=N, n=2, nz=1, L=1, frac=(0.4,))
+    op = sp.SphereOperator(m, eu.Phys(), sp.BG_ISOTHERMAL)
+    g, re = op.geo, op.re
+    I = [torch.as_tensor(M, dtype=F64) for M in re.I]
+    err, width = 0.0, 0.5 * math.pi * m.desc.r_e / (2 * m.desc.n)
+    assert len(m.hang) > 0
+    for h, row in enumerate(m.hang):
+        ec, fc, ff, flip = int(row[0]), int(row[1]), int(m.hang_ff[h]), int(m.hang_flip[h])
+        perm = torch.as_tensor(sp.face_perm(N, flip))
+        for quad in range(4):
+            ef = int(row[2 + quad])
+            for c in range(3):
+                xc = eu.face_slice(g.x[c], fc, N)[ec]
+                xm = eu.interp2(I[quad & 1], I[quad >> 1], xc, N)[perm]
+                xf = eu.face_slice(g.x[c], ff, N)[ef]
+                err = max(err, float((xf - xm).abs().max()))
+    assert err <= 1e-3 * width, (err, width)
+
+
+def check_refined_everywhere_is_the_finer_shell(N=3, n=2, nz=1, seed=4):
+    d = sp.SphereDesc(N=N, n=n, nz=nz, max_level=1)
+    m1 = sp.refine_pass(sp.SphereMesh(d), np.ones(6 * n * n * nz, dtype=int))
+    mu = sp.SphereMesh(sp.SphereDesc(N=N, n=2 * n, nz=2 * nz))
+    assert len(m1.hang) == 0 and m1.K == mu.K
+    perm = np.array([mu.index[(p, 0, x, y, z)] for (p, _, x, y, z) in m1.leaves.tolist()])
+    o1 = sp.SphereOperator(m1, eu.Phys(), sp.BG_ISOTHERMAL)
+    ou = sp.SphereOperator(mu, eu.Phys(), sp.BG_ISOTHERMAL)
+    for c in range(3):
+        assert torch.equal(o1.geo.x[c], ou.geo.x[c][perm])
+    q = torch.as_tensor(random_state(m1.K, N, seed), dtype=F64).reshape(5, m1.K, N + 1, N + 1, N + 1) * 0.1
+    qu = torch.zeros_like(q)
+    qu[:, perm] = q
+    R1, Ru = o1.rhs(q), ou.rhs(qu)[:, perm]
+    for v in range(5):
+        assert float((R1[v] - Ru[v]).norm()) <= 1e-13 * float(Ru[v].norm()), v
+
+
+def check_conservation_and_rest(N=3, seed=3):
+    m = _amr_mesh(N=N)
+    assert len(m.hang) > 0
+    op = sp.SphereOperator(m, eu.Phys(), sp.BG_ISOTHERMAL)
+    z = torch.zeros(5, m.K, N + 1, N + 1, N + 1, dtype=F64)
+    assert float(op.rhs(z).abs().max()) == 0.0
+    q = torch.as_tensor(random_state(m.K, N, seed), dtype=F64).reshape(5, m.K, N + 1, N + 1, N + 1) * 0.1
+    R = op.rhs(q)
+    JW = sp.quad_weights(op)
+    for v in (0, 4):
+        tot = math.fsum((JW * R[v]).reshape(-1).tolist())
+        scale = float((JW * R[v].abs()).sum())
+        assert abs(tot) <= 1e-14 * scale, (v, tot, scale)
+
+
+def check_smooth_consistency(N=4):
+    d = sp.SphereDesc(N=N, n=2, nz=1, max_level=1)
+    m0 = sp.SphereMesh(d)
+    fl = np.zeros(m0.K, dtype=int)
+    fl[[0, 1, 5, 9, 14]] = 1
+    ma, mf = sp.refine_pass(m0, fl), sp.refine_pass(m0, np.ones(m0.K, dtype=int))
+    oa = sp.SphereOperator(ma, eu.Phys(), sp.BG_ISOTHERMAL)
+    of = sp.SphereOperator(mf, eu.Phys(), sp.BG_ISOTHERMAL)
+    Ra, Rf = oa.rhs(_smooth_state(oa)), of.rhs(_smooth_state(of))
+    fine = sorted(set(int(x) for x in ma.hang[:, 2:].reshape(-1)))
+    idx = [mf.index[tuple(ma.leaves[e].tolist())] for e in fine]
+    for v in range(5):
+        a, b = Ra[v][fine], Rf[v][idx]
+        # measured 5e-5 .. 1e-4 (N = 4, elements of about 5000 km)
+        assert float((a - b).norm()) <= 2e-3 * float(b.norm()), v
+
+
+def check_adapt_transfers(N=3, seed=6):
+    d = sp.SphereDesc(N=N, n=2, nz=1, max_level=1)
+    m0 = sp.SphereMesh(d)
+    fl = np.zeros(m0.K, dtype=int)
+    fl[[0, 3, 7, 12, 20]] = 1
+    m1 = sp.refine_pass(m0, fl)
+    o0, o1 = (sp.SphereOperator(m, eu.Phys(), sp.BG_ISOTHERMAL) for m in (m0, m1))
+    q0 = torch.as_tensor(random_state(m0.K, N, seed), dtype=F64).reshape(5, m0.K, N + 1, N + 1, N + 1) * 0.1
+    q1, s = sp.adapt_project(o0, o1, q0)
+    M0, M1 = sp.budgets(o0, q0)[1], sp.budgets(o1, q1)[1]
+    assert abs(M1 - M0) <= 2e-16 * M0 and 0.0 < abs(s - 1.0) < 1e-3
+    # coarsening every refined family back: the leaves return, the means balance
+    back = -np.ones(m1.K, dtype=int)
+    m2 = sp.coarsen_pass(m1, back)
+    assert np.array_equal(m2.leaves, m0.leaves)
+    o2 = sp.SphereOperator(m2, eu.Phys(), sp.BG_ISOTHERMAL)
+    q2, s2 = sp.adapt_project(o1, o2, q1)
+    assert s2 == 1.0
+    V = sp.element_volumes(m1)
+    mu1, mu2 = sp.reference_means(q1).numpy(), sp.reference_means(q2).numpy()
+    for e in range(m2.K):
+        if m2.xfer_kind[e] != 8:
+            assert torch.equal(q2[:, e], q1[:, int(m2.xfer_src[e])])
+            continue
+        fam = list(range(int(m2.xfer_src[e]), int(m2.xfer_src[e]) + 8))
+        lhs = V[fam].sum() * mu2[:, e]
+        rhs = (V[fam][None] * mu1[:, fam]).sum(axis=1)
+        assert np.abs(lhs - rhs).max() <= 1e-14 * np.abs(V[fam][None] * mu1[:, fam]).sum(axis=1).max()
+
+
+# ----------------------------------------------------------------------------- tests
+def test_tables_closed_and_balanced():
+    check_tables()
+    check_tables(_amr_mesh(N=2, n=1, nz=2, L=2, seed=9, frac=(0.5, 0.3)))
+
+
+def test_hanging_face_geometry():
+    check_hanging_geometry()
+
+
+def test_refined_everywhere_is_the_finer_shell():
+    check_refined_everywhere_is_the_finer_shell()
+
+
+def test_conservation_and_rest_with_hanging_faces():
+    check_conservation_and_rest()
+
+
+def test_smooth_consistency_at_hanging_faces():
+    check_smooth_consistency()
+
+
+def test_transfers_of_the_passes():
+    check_adapt_transfers()
+
+
+# ----------------------------------------------------------------------------- planted mistakes
+ORIG_MORT = sp.SphereOperator.mortars
+
+
+def _unflipped_mortar(mp):
+    """the coarse trace read in the coarse face's order on every fine face (the
+    orientation across a panel edge ignored by the mortars)"""
+    orig = sp.SphereMesh._tables
+
+    def tables(self):
+        orig(self)
+        self.hang_flip = np.zeros_like(self.hang_flip)
+    mp.setattr(sp.SphereMesh, "_tables", tables)
+
+
+def _scaled_projection(fac):
+    def mortars(self, q, Ft):
+        re = self.re
+        saved = re.R
+        re.R = [fac * M for M in saved]
+        try:
+            return ORIG_MORT(self, q, Ft)
+        finally:
+            re.R = saved
+    return mortars
+
+
+def _quadrants_swapped(mp):
+    """the fine leaves of a hanging row taken in the order of the fine face's own
+    axes instead of the coarse face's"""
+    orig = sp.SphereMesh._tables
+
+    def tables(self):
+        orig(self)
+        for h in range(len(self.hang)):
+            if self.hang_flip[h]:
+                r = self.hang[h].copy()
+                self.hang[h, 2:] = r[[3, 2, 5, 4]]
+    mp.setattr(sp.SphereMesh, "_tables", tables)
+
+
+MUTANTS = {
+    "orientation ignored on the mortars": (_unflipped_mortar, check_smooth_consistency),
+    "coarse flux per fine reference area (the factor 4 dropped)": (
+        lambda mp: mp.setattr(sp.SphereOperator, "mortars", _scaled_projection(0.25)), check_conservation_and_rest),
+    "quadrants in the fine face's axes": (_quadrants_swapped, check_hanging_geometry),
+}
+
+
+@pytest.mark.parametrize("name", list(MUTANTS))
+def test_planted_mistake_is_caught(name, monkeypatch):
+    plant, check = MUTANTS[name]
+    plant(monkeypatch)
+    with pytest.raises(AssertionError):
+        check()
