@@ -70,6 +70,7 @@ typedef int32_t dg_status;
 
 #define DG_IND_THETA      0  /* eta_e = max |theta'| over the leaf's nodes   */
 #define DG_IND_GRAD_THETA 1  /* eta_e = max |grad theta| over the leaf's nodes */
+#define DG_IND_PPRIME     2  /* eta_e = max |P'| over the leaf's nodes (section 4.4 regrids on it) */
 
 #define DG_KIND_COPY   -1    /* transfer: new leaf is old leaf src */
 #define DG_KIND_FAMILY  8    /* transfer: new leaf is the parent of old src..src+7 */
@@ -98,6 +99,7 @@ typedef struct {
     int32_t N, n, nz;
     double r_e, H;
     int32_t host_only;
+    int32_t max_level;   /* refinement levels allowed above the unrefined shell (0: none) */
 } dg_sphere_desc;
 
 /* Gas constants (section 2.1: R = cp - cv, gamma = cp/cv, P = P0 (R Theta/P0)^gamma),
@@ -193,15 +195,24 @@ dg_status dg_mesh_build(const dg_forest_desc* desc, const dg_mesh* prev, const i
  * normal and face Jacobian, taken for a shared face from the (leaf, face) pair
  * that comes first so that both sides use bitwise-opposite normals.  dg_rhs,
  * dg_rk_stage, dg_budgets and dg_node_coords accept such meshes (float64,
- * mu = 0; background z is the height above r_e), and the dg_sphere_* transfers
- * between a shell and the shell with twice its resolution; the other calls
- * return DG_EUNSUPPORTED (no local refinement on the shell).  N = 2..5.
+ * mu = 0, mortars at hanging faces; background z is the height above r_e), and
+ * the dg_sphere_* transfers between a shell and the shell with twice its
+ * resolution.  With desc->max_level > 0 the shell is the root level of a forest
+ * of oct-trees (section 3.1) and dg_mesh_build(prev = shell, flags, pass) refines
+ * or coarsens it with 2:1 balance across faces, also across panel edges; hanging
+ * faces take curved mortars (the coarse trace interpolated to the fine face nodes,
+ * the Riemann problem along the fine face's normal, the coarse side's flux
+ * 4 s_f (-F*) per coarse reference area projected back), and dg_indicator (theta'
+ * or P'), dg_pass_changes, dg_flags_after_coarsen, dg_flags_buffer and
+ * dg_sphere_adapt_project accept them.  The adjoint, the tracer, the precision
+ * split, viscosity and pointwise matching return DG_EUNSUPPORTED.  N = 2..5.
  * DG_EINVAL on bad sizes. */
 dg_status dg_sphere_mesh_build(const dg_sphere_desc* desc, dg_mesh** out);
 /* Face connectivity of a shell mesh (not in the paper): nb[K][6][3] (host,
  * caller-owned) = neighbour element (-1 at the walls), its face, and 1 when
- * the neighbour's face-local first axis runs opposite.  Host only.  DG_EINVAL
- * for a NULL argument or a brick mesh. */
+ * the neighbour's face-local first axis runs opposite (on a refined shell, see
+ * dg_sphere_face_kinds for the hanging faces).  Host only.  DG_EINVAL for a NULL
+ * argument or a brick mesh. */
 dg_status dg_sphere_faces(const dg_mesh* mesh, int32_t* nb);
 /* Geometry of a shell mesh into host arrays (caller-owned): metric[10][K][Np]
  * (J, then J a^i_c at 1 + 3 i + c, c the Cartesian component), fgeo
@@ -251,6 +262,30 @@ dg_status dg_sphere_refine_project(const dg_mesh* coarse, const dg_mesh* fine, c
  * DG_EINVAL for shells that are not such a pair. */
 dg_status dg_sphere_coarsen_project(const dg_mesh* fine, const dg_mesh* coarse, const double* q_fine,
                                     double* q_coarse, void* stream);
+/* The transfer of a refine or coarsen pass of a shell built with max_level > 0
+ * (section 3.4's transfer on curved elements, with the reference matrices only):
+ * `to` was built by dg_mesh_build(prev = from, ...).  Kept leaves are copied; a
+ * child takes I_ax x I_ay x I_az of its parent, and one scale factor s = (mass of
+ * the refined parents) / (mass of their interpolated children), both the J W
+ * quadrature of rhobar + rho', multiplies every conserved field of every child,
+ * background included, as in dg_sphere_refine_project; a merged family becomes the
+ * sum of its children's reference projections plus the volume-weighted mean
+ * constant, as in dg_sphere_coarsen_project.  q_from, q_to: device [5][K][Np] of
+ * their meshes, caller-owned, not aliased; phys float64 without viscosity.  If
+ * scale (host) is not NULL it receives s (1 when nothing was refined) and the call
+ * waits for the stream; otherwise it only enqueues.  Uses both meshes' reduction
+ * workspaces.  DG_EINVAL for meshes that are not such a pair; DG_EUNSUPPORTED for
+ * DG_MIXED or mu > 0. */
+dg_status dg_sphere_adapt_project(const dg_mesh* from, const dg_mesh* to, const dg_phys* phys, const double* q_from,
+                                  double* q_to, double* scale, void* stream);
+/* Face kinds of a shell (section 3.1's tree on the panels; the encoding is not in
+ * the paper): kind[K][6] (host, caller-owned) = 0 wall, 1 conforming, 2 fine side
+ * of a hanging face + 4 * its quadrant in the coarse face's axes, 3 coarse side.
+ * dg_sphere_faces then gives per face the neighbour, its face and the flip
+ * (conforming), the coarse leaf, its face and the flip (fine side), or the row of
+ * the hanging-face table of dg_mesh_export, the fine leaves' face and the flip
+ * (coarse side).  Host only.  DG_EINVAL for a NULL argument or a brick mesh. */
+dg_status dg_sphere_face_kinds(const dg_mesh* mesh, int32_t* kind);
 /* Whether dg_mesh_build(prev = mesh, flags, pass) would change a leaf of mesh
  * (section 3.1: a refine pass splits leaves flagged +1 below max_level; a
  * coarsen pass merges complete sibling families flagged -1 that pass the 2:1

@@ -878,3 +878,29 @@ def adapt_project(op_from: SphereOperator, op_to: SphereOperator, q):
         out[1:4, ch] = s * out[1:4, ch]
         out[4, ch] = s * out[4, ch] + (s - 1.0) * Th_b[ch]
     return out, s
+
+
+# ----------------------------------------------------------------------------- regrid indicator (section 4.4)
+
+IND_THETA, IND_PPRIME = 0, 2
+
+
+def indicator(op: SphereOperator, q, kind=IND_PPRIME):
+    """Per-leaf eta: max over its nodes of |theta'| (IND_THETA) or of |P'|
+    (IND_PPRIME, the pressure perturbation section 4.4 regrids on)."""
+    rho_b, Th_b, P_b = op.bg
+    if kind == IND_PPRIME:
+        val = torch.abs(eu.pressure_perturbation(q[4], Th_b, P_b, op.phys.gamma))
+    else:
+        val = torch.abs((Th_b + q[4]) / (rho_b + q[0]) - Th_b / rho_b)
+    return val.reshape(op.K, -1).max(dim=1).values
+
+
+def flags_from_indicator(mesh: SphereMesh, eta, thr):
+    """+1 where eta > thr below max_level; -1 where eta <= thr above level 0; else 0"""
+    lev = mesh.leaves[:, 1]
+    eta = np.asarray(eta)
+    fl = np.zeros(mesh.K, dtype=np.int8)
+    fl[(eta > thr) & (lev < mesh.desc.max_level)] = 1
+    fl[(eta <= thr) & (lev > 0)] = -1
+    return fl

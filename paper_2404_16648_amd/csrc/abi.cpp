@@ -59,6 +59,7 @@ void free_device(dg_mesh* m) {
     m->d_mortC = nullptr;
     m->d_flags = nullptr;
     m->d_metric = m->d_fgeo = m->d_cw = nullptr;
+    m->d_xlist = nullptr;
     if (m->d_sigma) (void)hipFree(m->d_sigma);
     m->d_sigma = nullptr;
 }
@@ -66,10 +67,10 @@ void free_device(dg_mesh* m) {
 // byte offsets of the arrays in a mesh's one device block, 256-byte aligned;
 // [0, upload) is copied from the host, the rest is device workspace
 struct DevLayout {
-    size_t ops, geo, c1d, ft, nb, hs, hg, lv, xs, xk, sr, met, fg, cw, upload, bg, red, eta, fl, mort, mortC, total;
+    size_t ops, geo, c1d, ft, nb, hs, hg, lv, xs, xk, sr, met, fg, cw, xl, upload, bg, red, eta, fl, mort, mortC, total;
 };
 
-DevLayout dev_layout(int64_t K, int N, int64_t red_len, int64_t n_hang, bool sphere) {
+DevLayout dev_layout(int64_t K, int N, int64_t red_len, int64_t n_hang, bool sphere, int64_t n_xlist) {
     const size_t N1 = (size_t)N + 1, k = (size_t)K;
     size_t end = 0;
     auto take = [&](size_t bytes) {
@@ -93,6 +94,7 @@ DevLayout dev_layout(int64_t K, int N, int64_t red_len, int64_t n_hang, bool sph
     L.met = take(sphere ? sizeof(double) * 10 * k * N1 * N1 * N1 : 0);
     L.fg = take(sphere ? sizeof(double) * 24 * k * N1 * N1 : 0);
     L.cw = take(sphere ? sizeof(double) * k : 0);
+    L.xl = take(sphere ? sizeof(int32_t) * (size_t)n_xlist : 0);
     L.upload = end;
     L.bg = take(sizeof(double) * 3 * k * N1);
     L.red = take(sizeof(double) * (size_t)red_len);
@@ -122,6 +124,7 @@ void set_device_pointers(dg_mesh* m, char* base, const DevLayout& L) {
     m->d_metric = m->h.sphere ? (double*)(base + L.met) : nullptr;
     m->d_fgeo = m->h.sphere ? (double*)(base + L.fg) : nullptr;
     m->d_cw = m->h.sphere ? (double*)(base + L.cw) : nullptr;
+    m->d_xlist = m->h.sphere ? (int32_t*)(base + L.xl) : nullptr;
     m->d_bg = (double*)(base + L.bg);
     m->d_red = (double*)(base + L.red);
     m->d_eta = (double*)(base + L.eta);
@@ -213,7 +216,17 @@ dg_status build_device(dg_mesh* m, hipStream_t s) {
     const int N = h.desc.N, N1 = N + 1;
     m->red_len = (int64_t)budget_blocks(K) * 8 + 8;
     m->n_hang = (int64_t)h.hang.size() / 6;
-    const DevLayout L = dev_layout(K, N, m->red_len, m->n_hang, h.sphere);
+    // shells: the children of the plan and their parents (the refinement's scale factor)
+    std::vector<int32_t> xlist;
+    if (h.sphere) {
+        for (int64_t e = 0; e < K; ++e)
+            if (h.xfer_kind[e] >= 0 && h.xfer_kind[e] < 8) xlist.push_back((int32_t)e);
+        m->n_xch = (int64_t)xlist.size();
+        for (int64_t e = 0; e < K; ++e)
+            if (h.xfer_kind[e] == 0) xlist.push_back(h.xfer_src[e]);
+        m->n_xpar = (int64_t)xlist.size() - m->n_xch;
+    }
+    const DevLayout L = dev_layout(K, N, m->red_len, m->n_hang, h.sphere, (int64_t)xlist.size());
     // one staging buffer and one copy for every table of the mesh; the background,
     // reduction and flag buffers are carved from the same block
     UploadStaging& stg = upload_staging();
@@ -251,25 +264,25 @@ dg_status build_device(dg_mesh* m, hipStream_t s) {
     if (h.sphere) {
         // shell: the curvilinear geometry (geo unused: zeros)
         std::memset(geo, 0, sizeof(double) * 4 * K);
-        std::memset(level, 0, sizeof(int32_t) * K);
+        for (int64_t e = 0; e < K; ++e) level[e] = h.leaves[e].l;
         sphere_geometry(h, m->ops, (double*)(up.data() + L.met), (double*)(up.data() + L.fg), c1d);
-        // volume fraction of every element within its parent in the shell with half
-        // the elements per edge and layers (the weights of the coarsening); zeros when
-        // n or nz is odd (no such shell)
+        // volume fraction of every element within its parent, the cell one level up
+        // (at level 0, the element of the shell with half the elements per edge and
+        // layers): the weights of the coarsening; zero at level 0 when n or nz is odd
+        if (!xlist.empty()) std::memcpy(up.data() + L.xl, xlist.data(), sizeof(int32_t) * xlist.size());
         double* cw = (double*)(up.data() + L.cw);
-        std::fill(cw, cw + K, 0.0);
         const dg_sphere_desc& sd = h.sdesc;
-        if (sd.n % 2 == 0 && sd.nz % 2 == 0) {
-            std::vector<long double> vol(K);
-            sphere_volumes(h, vol.data());
-            for (int64_t e = 0; e < K; ++e) {
-                const Leaf& L0 = h.leaves[e];
-                const int pa = L0.a[0] & ~1, pb = L0.a[1] & ~1, pr = L0.a[2] & ~1;
-                long double tot = 0.0L;
-                for (int c = 0; c < 8; ++c)
-                    tot += vol[sphere_leaf(sd, L0.r, pa + (c & 1), pb + ((c >> 1) & 1), pr + (c >> 2))];
-                cw[e] = (double)(vol[e] / tot);
+        for (int64_t e = 0; e < K; ++e) {
+            const Leaf& L0 = h.leaves[e];
+            cw[e] = 0.0;
+            if (L0.l == 0 && (sd.n % 2 || sd.nz % 2)) continue;
+            long double tot = 0.0L;
+            for (int c = 0; c < 8; ++c) {
+                const Leaf sib{L0.r, L0.l, {(L0.a[0] & ~1) + (c & 1), (L0.a[1] & ~1) + ((c >> 1) & 1),
+                                            (L0.a[2] & ~1) + (c >> 2)}};
+                tot += sphere_cell_volume(sd, sib);
             }
+            cw[e] = (double)(sphere_cell_volume(sd, L0) / tot);
         }
     } else {
         for (int64_t e = 0; e < K; ++e) {
@@ -291,7 +304,9 @@ dg_status build_device(dg_mesh* m, hipStream_t s) {
     for (int64_t r = 0; r < m->n_hang; ++r) {
         const int32_t* row = &h.hang[6 * r];
         hs[row[0] * 6 + row[1]] = (int32_t)r;
-        for (int q = 0; q < 4; ++q) hs[row[2 + q] * 6 + (row[1] ^ 1)] = (int32_t)r;
+        // the fine leaves' face: the opposite one in a brick, recorded per row on a shell
+        const int ff = h.sphere ? h.snb[(row[0] * 6 + row[1]) * 3 + 1] : (row[1] ^ 1);
+        for (int q = 0; q < 4; ++q) hs[row[2 + q] * 6 + ff] = (int32_t)r;
     }
     if (m->n_hang) std::memcpy(up.data() + L.hg, h.hang.data(), sizeof(int32_t) * 6 * m->n_hang);
     std::memcpy(up.data() + L.xs, h.xfer_src.data(), sizeof(int32_t) * K);
@@ -498,20 +513,23 @@ dg_status dg_mesh_build(const dg_forest_desc* desc, const dg_mesh* prev, const i
             }
             err = forest_uniform(*desc, m->h);
         } else {
-            if (prev->h.sphere) {
+            if (prev->h.sphere && prev->h.sdesc.max_level == 0) {
                 delete m;
-                return fail(DG_EUNSUPPORTED, "no refinement of cubed-sphere shell meshes");
+                return fail(DG_EUNSUPPORTED, "the shell was built with max_level = 0 (no refinement)");
             }
             if (!flags && !prev->h.leaves.empty()) {
                 delete m;
                 return fail(DG_EINVAL, "flags is NULL");
             }
-            if (pass == DG_PASS_REFINE)
-                err = forest_refine(prev->h, flags, m->h);
-            else if (pass == DG_PASS_COARSEN)
-                err = forest_coarsen(prev->h, flags, m->h);
-            else
+            if (pass != DG_PASS_REFINE && pass != DG_PASS_COARSEN)
                 err = "unknown pass";
+            else if (prev->h.sphere)
+                err = pass == DG_PASS_REFINE ? sphere_refine(prev->h, flags, m->h)
+                                             : sphere_coarsen(prev->h, flags, m->h);
+            else if (pass == DG_PASS_REFINE)
+                err = forest_refine(prev->h, flags, m->h);
+            else
+                err = forest_coarsen(prev->h, flags, m->h);
             m->prev = prev;
             m->prev_id = prev->id;
         }
@@ -690,13 +708,64 @@ dg_status dg_sphere_coarsen_project(const dg_mesh* fine, const dg_mesh* coarse, 
     return DG_OK;
 }
 
+dg_status dg_sphere_adapt_project(const dg_mesh* from, const dg_mesh* to, const dg_phys* phys, const double* q_from,
+                                  double* q_to, double* scale, void* stream) {
+    if (!from || !to) return fail(DG_EINVAL, "mesh is NULL");
+    if (!from->h.sphere || !to->h.sphere) return fail(DG_EINVAL, "not a shell mesh");
+    if (to->prev_id != from->id) return fail(DG_EINVAL, "`to` was not built from `from`");
+    hipStream_t s = (hipStream_t)stream;
+    dg_status st = check_dev_mesh(from, s);
+    if (st || (st = check_dev_mesh(to, s))) return st;
+    if ((st = check_phys(phys))) return st;
+    if (phys->precision != DG_FP64 || phys->mu != 0.0)
+        return fail(DG_EUNSUPPORTED, "the shell transfer takes float64 physics without viscosity");
+    if (!q_from || !q_to) return fail(DG_EINVAL, "NULL field pointer");
+    if (q_from == q_to) return fail(DG_EINVAL, "input and output fields must not alias");
+    dg_mesh* mf = const_cast<dg_mesh*>(from);
+    dg_mesh* mt = const_cast<dg_mesh*>(to);
+    if ((st = ensure_bg(mf, phys, s)) || (st = ensure_bg(mt, phys, s))) return st;
+    const int N = to->h.desc.N;
+    const int64_t Kf = (int64_t)from->h.leaves.size(), Kt = (int64_t)to->h.leaves.size();
+    ShellPlanArgs a{q_from, q_to, to->d_ops, from->d_cw, to->d_xsrc, to->d_xkind, Kf, Kt};
+    HIP_TRY(launch_shell_plan(N, a, s));
+    if (to->n_xch > 0) {
+        // the refined parents' mass (source) and their children's (target), then the factor
+        const double* w = to->d_ops + 5 * (N + 1) * (N + 1);
+        double* out_f = mf->d_red + (int64_t)budget_blocks(Kf) * 8 + 4;
+        double* out_t = mt->d_red + (int64_t)budget_blocks(Kt) * 8 + 4;
+        HIP_TRY(launch_shell_mass(N, q_from, mf->d_bg, mf->d_metric, w, to->d_xlist + to->n_xch, to->n_xpar, Kf,
+                                  mf->d_red, budget_blocks(to->n_xpar), out_f, s));
+        HIP_TRY(launch_shell_mass(N, q_to, mt->d_bg, mt->d_metric, w, to->d_xlist, to->n_xch, Kt, mt->d_red,
+                                  budget_blocks(to->n_xch), out_t, s));
+        HIP_TRY(launch_shell_scale_list(N, q_to, mt->d_bg, Kt, to->d_xlist, to->n_xch, out_f, out_t, out_t + 1, s));
+        if (scale) {
+            HIP_TRY(hipMemcpyAsync(scale, out_t + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (!std::isfinite(*scale)) return fail(DG_ENONFINITE, "non-finite scale factor");
+        }
+    } else if (scale) {
+        *scale = 1.0;
+    }
+    return DG_OK;
+}
+
+dg_status dg_sphere_face_kinds(const dg_mesh* m, int32_t* kind) {
+    if (!m || !kind) return fail(DG_EINVAL, "NULL argument");
+    if (!m->h.sphere) return fail(DG_EINVAL, "not a shell mesh");
+    for (size_t i = 0; i < m->h.skind.size(); ++i) kind[i] = m->h.skind[i] + 4 * m->h.saux[i];
+    return DG_OK;
+}
+
 dg_status dg_pass_changes(const dg_mesh* m, const int8_t* flags, int32_t pass, int32_t* changes) {
     if (!m || !changes) return fail(DG_EINVAL, "NULL argument");
-    if (dg_status st = no_sphere(m)) return st;
     if (!flags && !m->h.leaves.empty()) return fail(DG_EINVAL, "flags is NULL");
     if (pass != DG_PASS_REFINE && pass != DG_PASS_COARSEN) return fail(DG_EINVAL, "unknown pass");
     try {
-        *changes = pass_changes(m->h, flags, pass == DG_PASS_REFINE) ? 1 : 0;
+        const bool refine = pass == DG_PASS_REFINE;
+        if (m->h.sphere)
+            *changes = m->h.sdesc.max_level > 0 && sphere_pass_changes(m->h, flags, refine) ? 1 : 0;
+        else
+            *changes = pass_changes(m->h, flags, refine) ? 1 : 0;
     } catch (const std::bad_alloc&) {
         return fail(DG_ENOMEM, "host allocation failed");
     }
@@ -719,7 +788,7 @@ dg_status dg_mesh_info_get(const dg_mesh* m, dg_mesh_info* info) {
     info->n_conf = (int64_t)h.conf.size() / 3;
     if (h.sphere) {  // shell: conforming face pairs counted from the connectivity
         int64_t pairs = 0;
-        for (size_t i = 0; i < h.snb.size(); i += 3) pairs += h.snb[i] >= 0 ? 1 : 0;
+        for (size_t i = 0; i < h.skind.size(); ++i) pairs += h.skind[i] == SK_CONF ? 1 : 0;
         info->n_conf = pairs / 2;
     }
     info->n_bnd = (int64_t)h.bnd.size() / 2;
@@ -798,8 +867,16 @@ static dg_status stage_common(const dg_mesh* mc, const dg_phys* phys, int mode, 
     if (m->h.sphere) {
         if (phys->precision != DG_FP64) return fail(DG_EUNSUPPORTED, "shell meshes run in float64");
         if (phys->mu > 0.0) return fail(DG_EUNSUPPORTED, "no artificial viscosity on shell meshes");
+        if (phys->nonconforming != DG_NC_MORTAR)
+            return fail(DG_EUNSUPPORTED, "shell meshes take the mortars at hanging faces");
+        const int64_t K = (int64_t)m->h.leaves.size();
+        if (m->n_hang) {
+            SphereMortArgs ma{qs, m->d_mort, m->d_ops, m->d_bg, m->d_srec, m->d_hang, m->d_metric, m->d_fgeo,
+                              m->n_hang, K, phys->cp / phys->cv, binom_coef(phys)};
+            HIP_TRY(launch_mortar_sphere(m->h.desc.N, ma, s));
+        }
         SphereStageArgs sa{q0, qs, out, m->d_ops, m->d_bg, m->d_c1d, m->d_srec, m->d_metric, m->d_fgeo,
-                           (int64_t)m->h.leaves.size(), a, b, dt, phys->cp / phys->cv, phys->g, binom_coef(phys)};
+                           m->d_mort, K, a, b, dt, phys->cp / phys->cv, phys->g, binom_coef(phys)};
         HIP_TRY(launch_stage_sphere(m->h.desc.N, mode, sa, s));
         return DG_OK;
     }
@@ -999,7 +1076,6 @@ dg_status dg_rk_stage_adjoint(const dg_mesh* m, const dg_phys* phys, double a1, 
 
 dg_status dg_flags_after_coarsen(const dg_mesh* mc, const int8_t* flags, int8_t* flags_out) {
     if (!mc || !flags || !flags_out) return fail(DG_EINVAL, "NULL argument");
-    if (dg_status st = no_sphere(mc)) return st;
     const HostMesh& h = mc->h;
     const int64_t K = (int64_t)h.leaves.size();
     const int64_t Kp = mc->prev ? (int64_t)mc->prev->h.leaves.size() : K;
@@ -1014,7 +1090,6 @@ dg_status dg_flags_after_coarsen(const dg_mesh* mc, const int8_t* flags, int8_t*
 dg_status dg_flags_buffer(const dg_mesh* m, int8_t* flags, int32_t B) {
     if (!m || !flags) return fail(DG_EINVAL, "NULL argument");
     if (B < 0) return fail(DG_EINVAL, "B must be >= 0");
-    if (dg_status st = no_sphere(m)) return st;
     const HostMesh& h = m->h;
     const int64_t K = (int64_t)h.leaves.size();
     std::vector<int8_t> cur((size_t)K);
@@ -1097,18 +1172,20 @@ dg_status dg_budgets_noalloc(const dg_mesh* mc, const dg_phys* phys, const doubl
 
 dg_status dg_indicator(const dg_mesh* mc, const dg_phys* phys, const double* q, int32_t kind, double thr,
                        double* eta, int8_t* flags_host, void* stream) {
-    dg_status st = no_sphere(mc);
+    dg_status st = check_dev_mesh(mc, (hipStream_t)stream);
     if (st) return st;
-    if ((st = check_dev_mesh(mc, (hipStream_t)stream))) return st;
     if ((st = check_phys(phys))) return st;
     if (!q || !flags_host) return fail(DG_EINVAL, "NULL argument");
-    if (kind != DG_IND_THETA && kind != DG_IND_GRAD_THETA) return fail(DG_EINVAL, "unknown indicator kind");
+    if (kind != DG_IND_THETA && kind != DG_IND_GRAD_THETA && kind != DG_IND_PPRIME)
+        return fail(DG_EINVAL, "unknown indicator kind");
+    if (mc->h.sphere && kind == DG_IND_GRAD_THETA)
+        return fail(DG_EUNSUPPORTED, "the gradient indicator takes brick meshes");
     dg_mesh* m = const_cast<dg_mesh*>(mc);
     hipStream_t s = (hipStream_t)stream;
     if ((st = ensure_bg(m, phys, s))) return st;
     const int64_t K = (int64_t)m->h.leaves.size();
     IndArgs a{q, m->d_bg, m->d_geo, m->d_ops, m->d_level, eta ? eta : m->d_eta, m->d_flags, K, kind,
-              m->h.desc.max_level, thr};
+              m->h.desc.max_level, thr, phys->cp / phys->cv, binom_coef(phys)};
     HIP_TRY(launch_indicator(m->h.desc.N, a, s));
     if (K > 0) HIP_TRY(hipMemcpyAsync(flags_host, m->d_flags, K, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -1117,18 +1194,20 @@ dg_status dg_indicator(const dg_mesh* mc, const dg_phys* phys, const double* q, 
 
 dg_status dg_indicator_async(const dg_mesh* mc, const dg_phys* phys, const double* q, int32_t kind, double thr,
                              double* eta, int8_t* flags_dev, void* stream) {
-    dg_status st = no_sphere(mc);
+    dg_status st = check_dev_mesh(mc, (hipStream_t)stream);
     if (st) return st;
-    if ((st = check_dev_mesh(mc, (hipStream_t)stream))) return st;
     if ((st = check_phys(phys))) return st;
     if (!q || !flags_dev) return fail(DG_EINVAL, "NULL argument");
-    if (kind != DG_IND_THETA && kind != DG_IND_GRAD_THETA) return fail(DG_EINVAL, "unknown indicator kind");
+    if (kind != DG_IND_THETA && kind != DG_IND_GRAD_THETA && kind != DG_IND_PPRIME)
+        return fail(DG_EINVAL, "unknown indicator kind");
+    if (mc->h.sphere && kind == DG_IND_GRAD_THETA)
+        return fail(DG_EUNSUPPORTED, "the gradient indicator takes brick meshes");
     dg_mesh* m = const_cast<dg_mesh*>(mc);
     hipStream_t s = (hipStream_t)stream;
     if ((st = ensure_bg(m, phys, s))) return st;
     const int64_t K = (int64_t)m->h.leaves.size();
     IndArgs a{q, m->d_bg, m->d_geo, m->d_ops, m->d_level, eta ? eta : m->d_eta, flags_dev, K, kind,
-              m->h.desc.max_level, thr};
+              m->h.desc.max_level, thr, phys->cp / phys->cv, binom_coef(phys)};
     HIP_TRY(launch_indicator(m->h.desc.N, a, s));
     return DG_OK;
 }

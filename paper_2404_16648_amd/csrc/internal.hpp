@@ -40,6 +40,7 @@ struct HostMesh {
     bool sphere = false;
     dg_sphere_desc sdesc{};
     std::vector<int32_t> snb;                    // [K][6][3]
+    std::vector<int8_t> skind, saux;             // [K][6]: SK_* kind; quadrant on a fine side
 };
 
 // forest passes (host, integer work); return "" or an error message
@@ -55,8 +56,17 @@ bool pass_changes(const HostMesh& prev, const int8_t* flags, bool refine);
 // normal and face Jacobian; c1d [3][K][N+1]: tan of the two panel angles, height)
 std::string sphere_build(const dg_sphere_desc& d, HostMesh& out);
 void sphere_geometry(const HostMesh& h, const RefOps& ops, double* metric, double* fgeo, double* c1d);
-// spherical-excess volume of every element [K]
+// shell face kinds (skind): wall, conforming, fine side or coarse side of a hanging face
+constexpr int8_t SK_WALL = 0, SK_CONF = 1, SK_FINE = 2, SK_COARSE = 3;
+// refine and coarsen passes of a shell with max_level > 0 (2:1 across faces, the
+// transfer plan as for the brick forest); whether a pass would change a leaf
+std::string sphere_refine(const HostMesh& prev, const int8_t* flags, HostMesh& out);
+std::string sphere_coarsen(const HostMesh& prev, const int8_t* flags, HostMesh& out);
+bool sphere_pass_changes(const HostMesh& prev, const int8_t* flags, bool refine);
+void sphere_forest_tables(HostMesh& out);
+// spherical-excess volume of every element [K]; of any cell (panel, level, g)
 void sphere_volumes(const HostMesh& h, long double* vol);
+long double sphere_cell_volume(const dg_sphere_desc& d, const Leaf& c);
 // index of element (panel p, column ia, row ib, layer ir)
 int64_t sphere_leaf(const dg_sphere_desc& d, int p, int ia, int ib, int ir);
 
@@ -106,4 +116,6 @@ struct dg_mesh {
     double* d_metric = nullptr;   // sphere: [10][K][Np] J and metric terms
     double* d_fgeo = nullptr;     // sphere: [K][6][NF][4] face normal and face Jacobian
     double* d_cw = nullptr;       // sphere with even n, nz: [K] volume fraction of the element in its parent
+    int32_t* d_xlist = nullptr;   // sphere: the children of this mesh's plan, then their parents in prev
+    int64_t n_xch = 0, n_xpar = 0;
 };

@@ -1518,6 +1518,8 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_indicator(const IndArgs A) {
         const double theta = (Thb + Thp) / (rhob + rp);
         sTh[t] = theta;
         val = fabs(theta - Thb / rhob);
+        if (A.kind == DG_IND_PPRIME)
+            val = fabs(pprime(Thp, 1.0 / Thb, A.bg[2 * K * N1 + e * N1 + k], A.gamma, A.binom));
     }
     __syncthreads();
     if (A.kind == DG_IND_GRAD_THETA && t < NP) {

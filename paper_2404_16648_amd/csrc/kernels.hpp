@@ -185,11 +185,50 @@ struct SphereStageArgs {
     const int32_t* srec;   // [K][kStageRec]: 18 = neighbour face | flip << 3 per face (4 bits), 19 = panel
     const double* metric;  // [10][K][Np]
     const double* fgeo;    // [K][6][NF][4]
+    const double* mort;    // [n_hang][5][5][NF]: the mortar pre-pass output (hanging faces), or null
     int64_t K;
     double a, b, dt;
     double gamma, g;
     BinomCoef binom;
 };
+
+// the shell's mortar pre-pass: per hanging row (coarse leaf, its face, four fine
+// leaves by quadrant) the lifted face terms of the coarse face (slot 0) and of the
+// four fine faces (slots 1..4), each in its own face's node order
+struct SphereMortArgs {
+    const double* qs;
+    double* mort;
+    const double* ops;
+    const double* bg;
+    const int32_t* srec;
+    const int32_t* hang;   // [n_hang][6]
+    const double* metric;
+    const double* fgeo;
+    int64_t n_hang, K;
+    double gamma;
+    BinomCoef binom;
+};
+hipError_t launch_mortar_sphere(int N, const SphereMortArgs& a, hipStream_t s);
+
+// transfers of a shell's refine or coarsen pass along the plan (src, kind) of the
+// target mesh: copies, children by reference interpolation, families by the
+// reference projections plus the volume-weighted mean (cw: the source mesh's
+// volume fraction of each leaf in its parent)
+struct ShellPlanArgs {
+    const double* src;
+    double* dst;
+    const double* ops;
+    const double* cw;
+    const int32_t* xsrc;
+    const int32_t* xkind;
+    int64_t Ksrc, Kdst;
+};
+hipError_t launch_shell_plan(int N, const ShellPlanArgs& a, hipStream_t s);
+// J W quadrature of rhobar + rho' over the leaves list[0..n) (compensated sums):
+// partial [nblk][2], the total to out[0]
+hipError_t launch_shell_mass(int N, const double* q, const double* bg, const double* metric, const double* w,
+                             const int32_t* list, int64_t n, int64_t K, double* partial, int nblk, double* out,
+                             hipStream_t s);
 
 struct BudgetArgs {
     const double* q;
@@ -215,6 +254,8 @@ struct IndArgs {
     int64_t K;
     int32_t kind, max_level;
     double thr;
+    double gamma;          // DG_IND_PPRIME: P' from Theta'
+    BinomCoef binom;
 };
 
 hipError_t launch_stage(int N, int mode, bool mixed, const StageArgs& a, hipStream_t s);
@@ -264,6 +305,10 @@ hipError_t launch_shell_coarsen(int N, const ShellXferArgs& a, hipStream_t s);
 // s = tot_before[1] / tot_after[1] on every conserved field of q (the fine shell), s to s_out[0]
 hipError_t launch_shell_scale(int N, double* q, const double* bg, int64_t K, const double* tot_before,
                               const double* tot_after, double* s_out, hipStream_t s);
+// the same with s = tot_before[0] / tot_after[0] on the leaves list[0..n) of q only
+hipError_t launch_shell_scale_list(int N, double* q, const double* bg, int64_t K, const int32_t* list, int64_t n,
+                                   const double* tot_before, const double* tot_after, double* s_out,
+                                   hipStream_t s);
 // integral of c [K][Np] with the weights J_e W_n (w the 1-D LGL weights): nblk <= budget_blocks(K)
 // blocks leave 2 doubles each in partial, the total goes to out_dev[0]
 hipError_t launch_weighted_sum(int N, const double* c, const double* geo, const double* w, int64_t K, int nblk,

@@ -109,6 +109,14 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_stage_sphere(const SphereStageArg
     const int32_t packed = rec[18];
     for (int it = t; it < 6 * NF; it += NT) {
         const int f = it / NF, m = it % NF, d = f >> 1;
+        const int type = rec[f] & 0xff;
+        if (type == FT_FINE || type == FT_COARSE) {
+            // hanging face: the lifted term from the mortar pre-pass
+            const int64_t row = (int64_t)rec[12 + f] * 5 + (type == FT_COARSE ? 0 : 1 + ((rec[f] >> 8) & 0xff));
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = A.mort[(row * 5 + v) * NF + m];
+            continue;
+        }
         const double sgn = (f & 1) ? 1.0 : -1.0;
         const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
         double qL[5], qR[5];
@@ -119,7 +127,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_stage_sphere(const SphereStageArg
         const double nv[3] = {fg[0], fg[1], fg[2]};
         const double sface = fg[3];
         Bg bR = bL;
-        if ((rec[f] & 0xff) == FT_WALL) {
+        if (type == FT_WALL) {
             // mirror state: the normal momentum reversed
             const double Un = qL[1] * nv[0] + qL[2] * nv[1] + qL[3] * nv[2];
             qR[0] = qL[0];
@@ -213,6 +221,140 @@ __global__ void k_node_coords_sphere(int64_t K, int N1, const double* c1d, const
     for (int c = 0; c < 3; ++c) xyz[c * K * NP + idx] = r * (cp[c] / nrm);
 }
 
+// J a^d . F(q) at one node: the Cartesian fluxes contracted with the metric row d
+__device__ __forceinline__ void contravariant_flux(const double q[5], const Bg& b, double Pp, const double* metric,
+                                                   int64_t KNP, int64_t node, int d, double out[5]) {
+    const double rinv = rcp_pos(b.rho + q[0]);
+    const double Th = b.Th + q[4];
+    double F[3][5];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double uc = q[1 + c] * rinv;
+        F[c][0] = q[1 + c];
+        F[c][1] = c == 0 ? q[1] * uc + Pp : q[1] * uc;
+        F[c][2] = c == 1 ? q[2] * uc + Pp : q[2] * uc;
+        F[c][3] = c == 2 ? q[3] * uc + Pp : q[3] * uc;
+        F[c][4] = Th * uc;
+    }
+    const double j0 = metric[(1 + 3 * d + 0) * KNP + node], j1 = metric[(1 + 3 * d + 1) * KNP + node],
+                 j2 = metric[(1 + 3 * d + 2) * KNP + node];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) out[v] = j0 * F[0][v] + j1 * F[1][v] + j2 * F[2][v];
+}
+
+template <int N>
+struct MortSz {
+    static constexpr int NF = (N + 1) * (N + 1);
+    static constexpr int NT = ((4 * NF + 63) / 64) * 64;  // one thread per fine face node of the four quadrants
+};
+
+// Mortar pre-pass of the shell (section 3.3 on the curved faces of section 3.4), one
+// workgroup per hanging row.  On each fine face the coarse trace is interpolated to
+// the fine nodes (I_qa x I_qb in the coarse face's axes, read through the
+// orientation) and the Riemann problem is solved there along the fine face's own
+// normal with the fine nodes' background; the fine face's lifted term is
+// (s_f F* - sgn J a^d . F(q_f)) / (J w_N).  The coarse side takes 4 s_f (-F*) (the
+// flux per coarse reference area: a fine face covers a quarter of it), projected back
+// with R_qa x R_qb and summed over the quadrants, minus its own contravariant flux.
+template <int N>
+__global__ void __launch_bounds__(MortSz<N>::NT) k_mortar_sphere(const SphereMortArgs A) {
+    constexpr int N1 = N + 1, NP = N1 * N1 * N1, NF = N1 * N1, NT = MortSz<N>::NT;
+    __shared__ double sTc[5 * NF], sG[20 * NF], sI[2 * NF], sR[2 * NF];
+    const int t = threadIdx.x;
+    const int64_t h = blockIdx.x;
+    const int32_t* row = A.hang + h * 6;
+    const int64_t ec = row[0];
+    const int fc = row[1];
+    const int32_t packed = A.srec[ec * kStageRec + 18];
+    const int ff = (packed >> (4 * fc)) & 7, flip = (packed >> (4 * fc + 3)) & 1;
+    const int64_t K = A.K, KNP = K * NP, KN1 = K * N1;
+    const double gamma = A.gamma;
+    const double wN = 2.0 / (N * (N + 1));
+    for (int x = t; x < 2 * NF; x += NT) {
+        sI[x] = A.ops[NF + x];      // I_0, I_1
+        sR[x] = A.ops[3 * NF + x];  // R_0, R_1
+    }
+    if (t < NF) {
+        const int n = face_node<N>(fc, t);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sTc[v * NF + t] = A.qs[v * KNP + ec * NP + n];
+    }
+    __syncthreads();
+    if (t < 4 * NF) {
+        const int quad = t / NF, mf = t - quad * NF;
+        const int qa = quad & 1, qb = quad >> 1;
+        const int64_t ef = row[2 + quad];
+        const int af = mf % N1, bf = mf / N1;
+        const int a2 = flip ? N - af : af, b2 = bf;  // the node in the coarse face's axes
+        const double* Ia = sI + qa * NF;
+        const double* Ib = sI + qb * NF;
+        double qm[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            double acc = 0.0;
+            for (int a = 0; a < N1; ++a) {
+                double tb = 0.0;
+                for (int b = 0; b < N1; ++b) tb = fma(Ib[b2 * N1 + b], sTc[v * NF + a + N1 * b], tb);
+                acc = fma(Ia[a2 * N1 + a], tb, acc);
+            }
+            qm[v] = acc;
+        }
+        const int nf = face_node<N>(ff, mf), kf = face_k<N>(ff, mf);
+        double qf[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qf[v] = A.qs[v * KNP + ef * NP + nf];
+        const Bg b = bg_make(A.bg[ef * N1 + kf], A.bg[KN1 + ef * N1 + kf], A.bg[2 * KN1 + ef * N1 + kf]);
+        const double* fg = A.fgeo + ((ef * 6 + ff) * NF + mf) * 4;
+        const double nv[3] = {fg[0], fg[1], fg[2]};
+        const double sf = fg[3];
+        const double PpL = pprime(qf[4], b.rTh, b.P, gamma, A.binom);
+        const double PpR = pprime(qm[4], b.rTh, b.P, gamma, A.binom);
+        double FL[5], FR[5], lL, lR, Fc[5];
+        flux_normal(qf, b, PpL, nv, gamma, FL, lL);
+        flux_normal(qm, b, PpR, nv, gamma, FR, lR);
+        contravariant_flux(qf, b, PpL, A.metric, KNP, ef * NP + nf, ff >> 1, Fc);
+        const double lam = fmax(lL, lR);
+        const double sgn = (ff & 1) ? 1.0 : -1.0;
+        const double JwN = A.metric[ef * NP + nf] * wN;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            const double Fs = 0.5 * (FL[v] + FR[v]) + 0.5 * lam * (qf[v] - qm[v]);
+            A.mort[((h * 5 + 1 + quad) * 5 + v) * NF + mf] = (sf * Fs - sgn * Fc[v]) / JwN;
+            sG[(quad * 5 + v) * NF + a2 + N1 * b2] = (4.0 * sf) * (-Fs);
+        }
+    }
+    __syncthreads();
+    if (t < NF) {
+        const int a = t % N1, b = t / N1;
+        double proj[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int quad = 0; quad < 4; ++quad) {
+            const double* Ra = sR + (quad & 1) * NF;
+            const double* Rb = sR + (quad >> 1) * NF;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                double acc = 0.0;
+                for (int a2 = 0; a2 < N1; ++a2) {
+                    double tb = 0.0;
+                    for (int b2 = 0; b2 < N1; ++b2) tb = fma(Rb[b * N1 + b2], sG[(quad * 5 + v) * NF + a2 + N1 * b2], tb);
+                    acc = fma(Ra[a * N1 + a2], tb, acc);
+                }
+                proj[v] = proj[v] + acc;
+            }
+        }
+        const int nc = face_node<N>(fc, t), kc = face_k<N>(fc, t);
+        double qc[5], Fc[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qc[v] = sTc[v * NF + t];
+        const Bg bc = bg_make(A.bg[ec * N1 + kc], A.bg[KN1 + ec * N1 + kc], A.bg[2 * KN1 + ec * N1 + kc]);
+        const double Ppc = pprime(qc[4], bc.rTh, bc.P, gamma, A.binom);
+        contravariant_flux(qc, bc, Ppc, A.metric, KNP, ec * NP + nc, fc >> 1, Fc);
+        const double sgn = (fc & 1) ? 1.0 : -1.0;
+        const double JwN = A.metric[ec * NP + nc] * wN;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) A.mort[((h * 5 + 0) * 5 + v) * NF + t] = (proj[v] - sgn * Fc[v]) / JwN;
+    }
+}
+
 // ---------------------------------------------------------------- shell transfers
 // Between a shell (nc x nc per panel, nzc layers) and the shell with twice the
 // elements per edge and twice the layers: child a = ax + 2 ay + 4 az of coarse
@@ -238,25 +380,20 @@ __device__ __forceinline__ void tile_pass(const double* in, double* out, const d
     }
 }
 
-// refinement: every fine element is I_ax x I_ay x I_az of its parent
+// one child: dst[e] = (I_ax x I_ay x I_az) src[parent], ax, ay, az the bits of child
 template <int N>
-__global__ void __launch_bounds__(Sz<N>::NT) k_shell_refine(const ShellXferArgs A) {
+__device__ __forceinline__ void child_of_parent(const double* src, int64_t Ksrc, int64_t parent, double* dst,
+                                                int64_t Kdst, int64_t e, int child, const double* ops, double* sT,
+                                                double* sU, double* sM, int t) {
     constexpr int N1 = N + 1, NP = N1 * N1 * N1, NF = N1 * N1, NT = Sz<N>::NT;
-    __shared__ double sT[5 * NP], sU[5 * NP], sM[3 * NF];
-    const int t = threadIdx.x;
-    const int64_t ef = blockIdx.x;
-    const int nf = 2 * A.nc, nzf = 2 * A.nzc;
-    const int iaf = (int)(ef % nf), ibf = (int)((ef / nf) % nf), irf = (int)((ef / ((int64_t)nf * nf)) % nzf);
-    const int p = (int)(ef / ((int64_t)nf * nf * nzf));
-    const int64_t ec = (((int64_t)p * A.nzc + (irf >> 1)) * A.nc + (ibf >> 1)) * A.nc + (iaf >> 1);
-    const int hal[3] = {iaf & 1, ibf & 1, irf & 1};
+    const int hal[3] = {child & 1, (child >> 1) & 1, child >> 2};
     for (int x = t; x < 3 * NF; x += NT) {
         const int ax = x / NF;
-        sM[x] = A.ops[(1 + hal[ax]) * NF + (x - ax * NF)];  // I_0 or I_1
+        sM[x] = ops[(1 + hal[ax]) * NF + (x - ax * NF)];  // I_0 or I_1
     }
     if (t < NP)
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sT[v * NP + t] = A.src[(v * A.Ksrc + ec) * NP + t];
+        for (int v = 0; v < 5; ++v) sT[v * NP + t] = src[(v * Ksrc + parent) * NP + t];
     __syncthreads();
     tile_pass<N>(sT, sU, sM, 0, t);
     __syncthreads();
@@ -269,34 +406,31 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_shell_refine(const ShellXferArgs 
             double acc = 0.0;
 #pragma unroll
             for (int m = 0; m < N1; ++m) acc = fma(sM[2 * NF + k * N1 + m], sT[v * NP + base + m * NF], acc);
-            A.dst[(v * A.Kdst + ef) * NP + t] = acc;
+            dst[(v * Kdst + e) * NP + t] = acc;
         }
     }
 }
 
-// coarsening: the parent is sum_a (R_ax x R_ay x R_az) q_a plus, per field, the
-// constant sum_a (w_a - 1/8) m(q_a), w_a the child's volume fraction and m the mean
-// over the reference cube, (1/8) sum W q
+// one family: dst[e] = sum_a (R_ax x R_ay x R_az) src[kid_a] plus, per field, the
+// constant sum_a (w_a - 1/8) m(src[kid_a]), w_a = cw[kid_a] the child's volume
+// fraction and m the mean over the reference cube, (1/8) sum W q
 template <int N>
-__global__ void __launch_bounds__(Sz<N>::NT) k_shell_coarsen(const ShellXferArgs A) {
+__device__ __forceinline__ void family_to_parent(const double* src, int64_t Ksrc, const int64_t kids[8], double* dst,
+                                                 int64_t Kdst, int64_t e, const double* ops, const double* cw,
+                                                 double* sT, double* sU, double* sR, double* sW, double* sShift,
+                                                 int t) {
     constexpr int N1 = N + 1, NP = N1 * N1 * N1, NF = N1 * N1, NT = Sz<N>::NT;
-    __shared__ double sT[5 * NP], sU[5 * NP], sR[2 * NF], sW[N1], sShift[5];
-    const int t = threadIdx.x;
-    const int64_t ec = blockIdx.x;
-    const int nc = A.nc, nzc = A.nzc, nf = 2 * nc, nzf = 2 * nzc;
-    const int ia = (int)(ec % nc), ib = (int)((ec / nc) % nc), ir = (int)((ec / ((int64_t)nc * nc)) % nzc);
-    const int p = (int)(ec / ((int64_t)nc * nc * nzc));
-    for (int x = t; x < 2 * NF; x += NT) sR[x] = A.ops[3 * NF + x];  // R_0, R_1
-    if (t < N1) sW[t] = A.ops[5 * NF + t];
+    for (int x = t; x < 2 * NF; x += NT) sR[x] = ops[3 * NF + x];  // R_0, R_1
+    if (t < N1) sW[t] = ops[5 * NF + t];
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     double shift = 0.0;  // thread v < 5: the constant of field v
     for (int a = 0; a < 8; ++a) {
         const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
-        const int64_t ef = (((int64_t)p * nzf + 2 * ir + az) * nf + 2 * ib + ay) * nf + 2 * ia + ax;
+        const int64_t ef = kids[a];
         __syncthreads();  // the previous child's last pass has read sT
         if (t < NP)
 #pragma unroll
-            for (int v = 0; v < 5; ++v) sT[v * NP + t] = A.src[(v * A.Ksrc + ef) * NP + t];
+            for (int v = 0; v < 5; ++v) sT[v * NP + t] = src[(v * Ksrc + ef) * NP + t];
         __syncthreads();
         if (t < 5) {
             double m = 0.0;
@@ -304,7 +438,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_shell_coarsen(const ShellXferArgs
                 const int i = nn % N1, j = (nn / N1) % N1, k = nn / NF;
                 m = fma(sW[i] * sW[j] * sW[k], sT[t * NP + nn], m);
             }
-            shift = fma(A.cw[ef] - 0.125, 0.125 * m, shift);
+            shift = fma(cw[ef] - 0.125, 0.125 * m, shift);
         }
         tile_pass<N>(sT, sU, sR + ax * NF, 0, t);
         __syncthreads();
@@ -326,7 +460,117 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_shell_coarsen(const ShellXferArgs
     __syncthreads();
     if (t < NP)
 #pragma unroll
-        for (int v = 0; v < 5; ++v) A.dst[(v * A.Kdst + ec) * NP + t] = acc[v] + sShift[v];
+        for (int v = 0; v < 5; ++v) dst[(v * Kdst + e) * NP + t] = acc[v] + sShift[v];
+}
+
+// refinement between the shell pair: every fine element from its parent
+template <int N>
+__global__ void __launch_bounds__(Sz<N>::NT) k_shell_refine(const ShellXferArgs A) {
+    constexpr int NP = Sz<N>::NP, NF = Sz<N>::NF;
+    __shared__ double sT[5 * NP], sU[5 * NP], sM[3 * NF];
+    const int64_t ef = blockIdx.x;
+    const int nf = 2 * A.nc, nzf = 2 * A.nzc;
+    const int iaf = (int)(ef % nf), ibf = (int)((ef / nf) % nf), irf = (int)((ef / ((int64_t)nf * nf)) % nzf);
+    const int p = (int)(ef / ((int64_t)nf * nf * nzf));
+    const int64_t ec = (((int64_t)p * A.nzc + (irf >> 1)) * A.nc + (ibf >> 1)) * A.nc + (iaf >> 1);
+    const int child = (iaf & 1) | ((ibf & 1) << 1) | ((irf & 1) << 2);
+    child_of_parent<N>(A.src, A.Ksrc, ec, A.dst, A.Kdst, ef, child, A.ops, sT, sU, sM, threadIdx.x);
+}
+
+// coarsening between the shell pair: every coarse element from its eight children
+template <int N>
+__global__ void __launch_bounds__(Sz<N>::NT) k_shell_coarsen(const ShellXferArgs A) {
+    constexpr int N1 = N + 1, NP = Sz<N>::NP, NF = Sz<N>::NF;
+    __shared__ double sT[5 * NP], sU[5 * NP], sR[2 * NF], sW[N1], sShift[5];
+    const int64_t ec = blockIdx.x;
+    const int nc = A.nc, nzc = A.nzc, nf = 2 * nc, nzf = 2 * nzc;
+    const int ia = (int)(ec % nc), ib = (int)((ec / nc) % nc), ir = (int)((ec / ((int64_t)nc * nc)) % nzc);
+    const int p = (int)(ec / ((int64_t)nc * nc * nzc));
+    int64_t kids[8];
+    for (int a = 0; a < 8; ++a)
+        kids[a] = (((int64_t)p * nzf + 2 * ir + (a >> 2)) * nf + 2 * ib + ((a >> 1) & 1)) * nf + 2 * ia + (a & 1);
+    family_to_parent<N>(A.src, A.Ksrc, kids, A.dst, A.Kdst, ec, A.ops, A.cw, sT, sU, sR, sW, sShift, threadIdx.x);
+}
+
+// a refine or coarsen pass of a shell, along the target's plan: kind -1 copies
+// leaf src, 0..7 is child kind of leaf src, 8 merges the family src..src+7
+template <int N>
+__global__ void __launch_bounds__(Sz<N>::NT) k_shell_plan(const ShellPlanArgs A) {
+    constexpr int N1 = N + 1, NP = Sz<N>::NP, NF = Sz<N>::NF;
+    __shared__ double sT[5 * NP], sU[5 * NP], sM[3 * NF], sW[N1], sShift[5];
+    const int64_t e = blockIdx.x;
+    const int t = threadIdx.x;
+    const int kind = A.xkind[e];
+    const int64_t src = A.xsrc[e];
+    if (kind < 0) {
+        if (t < NP)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) A.dst[(v * A.Kdst + e) * NP + t] = A.src[(v * A.Ksrc + src) * NP + t];
+    } else if (kind < 8) {
+        child_of_parent<N>(A.src, A.Ksrc, src, A.dst, A.Kdst, e, kind, A.ops, sT, sU, sM, t);
+    } else {
+        int64_t kids[8];
+        for (int a = 0; a < 8; ++a) kids[a] = src + a;
+        family_to_parent<N>(A.src, A.Ksrc, kids, A.dst, A.Kdst, e, A.ops, A.cw, sT, sU, sM, sW, sShift, t);
+    }
+}
+
+// J W quadrature of rhobar + rho' over the leaves list[0..n), compensated sums:
+// block b takes a contiguous share of the list, partial[b] = (sum, correction)
+template <int N>
+__global__ void __launch_bounds__(256) k_shell_mass(const double* q, const double* bg, const double* metric,
+                                                    const double* w, const int32_t* list, int64_t n, int64_t K,
+                                                    double* partial) {
+    constexpr int N1 = N + 1, NP = N1 * N1 * N1, NT = 256;
+    __shared__ Comp sh[4 * NT];
+    const int t = threadIdx.x;
+    Comp acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t i0 = blockIdx.x * per, i1 = (i0 + per < n) ? i0 + per : n;
+    for (int64_t i = i0; i < i1; ++i) {
+        const int64_t e = list[i];
+        for (int nn = t; nn < NP; nn += NT) {
+            const int ii = nn % N1, jj = (nn / N1) % N1, k = nn / (N1 * N1);
+            const double W = metric[e * NP + nn] * w[ii] * w[jj] * w[k];
+            acc[0] = comp_add(acc[0], W * (bg[e * N1 + k] + q[e * NP + nn]));
+        }
+    }
+    block_reduce4<NT>(acc, sh);
+    if (t == 0) {
+        partial[blockIdx.x * 2 + 0] = acc[0].s;
+        partial[blockIdx.x * 2 + 1] = acc[0].c;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_shell_mass_final(const double* partial, int nblk, double* out) {
+    constexpr int NT = 256;
+    __shared__ Comp sh[4 * NT];
+    const int t = threadIdx.x;
+    Comp acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    for (int b = t; b < nblk; b += NT) acc[0] = comp_merge(acc[0], Comp{partial[b * 2], partial[b * 2 + 1]});
+    block_reduce4<NT>(acc, sh);
+    if (t == 0) out[0] = acc[0].s + acc[0].c;
+}
+
+// s = before[0] / after[0] on every conserved field of the leaves list[b]
+template <int N>
+__global__ void __launch_bounds__(Sz<N>::NT) k_shell_scale_list(double* q, const double* bg, int64_t K,
+                                                                const int32_t* list, const double* before,
+                                                                const double* after, double* s_out) {
+    constexpr int N1 = N + 1, NP = N1 * N1 * N1;
+    const int t = threadIdx.x;
+    const int64_t e = list[blockIdx.x];
+    const double s = before[0] / after[0];
+    if (blockIdx.x == 0 && t == 0) s_out[0] = s;
+    if (t >= NP) return;
+    const int k = t / (N1 * N1);
+    const int64_t KNP = K * NP, idx = e * NP + t;
+    const double rb = bg[e * N1 + k], Tb = bg[K * N1 + e * N1 + k];
+    q[idx] = s * q[idx] + (s - 1.0) * rb;
+    q[KNP + idx] = s * q[KNP + idx];
+    q[2 * KNP + idx] = s * q[2 * KNP + idx];
+    q[3 * KNP + idx] = s * q[3 * KNP + idx];
+    q[4 * KNP + idx] = s * q[4 * KNP + idx] + (s - 1.0) * Tb;
 }
 
 // the refinement's scale factor s = (total mass before) / (total mass after) on
@@ -413,6 +657,39 @@ hipError_t launch_shell_scale(int N, double* q, const double* bg, int64_t K, con
     if (K <= 0) return hipSuccess;
     DG_DISPATCH_XFER(N, (k_shell_scale<NN><<<dim3((unsigned)K), dim3(Sz<NN>::NT), 0, s>>>(q, bg, K, tot_before,
                                                                                        tot_after, s_out)));
+    return hipGetLastError();
+}
+
+hipError_t launch_mortar_sphere(int N, const SphereMortArgs& a, hipStream_t s) {
+    if (a.n_hang <= 0) return hipSuccess;
+    DG_DISPATCH_N(N, (k_mortar_sphere<NN><<<dim3((unsigned)a.n_hang), dim3(MortSz<NN>::NT), 0, s>>>(a)));
+    return hipGetLastError();
+}
+
+hipError_t launch_shell_plan(int N, const ShellPlanArgs& a, hipStream_t s) {
+    if (a.Kdst <= 0) return hipSuccess;
+    DG_DISPATCH_XFER(N, (k_shell_plan<NN><<<dim3((unsigned)a.Kdst), dim3(Sz<NN>::NT), 0, s>>>(a)));
+    return hipGetLastError();
+}
+
+hipError_t launch_shell_mass(int N, const double* q, const double* bg, const double* metric, const double* w,
+                             const int32_t* list, int64_t n, int64_t K, double* partial, int nblk, double* out,
+                             hipStream_t s) {
+    if (nblk < 1) return hipErrorInvalidValue;
+    if (n > 0) {
+        DG_DISPATCH_XFER(N, (k_shell_mass<NN><<<dim3((unsigned)nblk), dim3(256), 0, s>>>(q, bg, metric, w, list, n, K,
+                                                                                       partial)));
+    }
+    k_shell_mass_final<<<dim3(1), dim3(256), 0, s>>>(partial, n > 0 ? nblk : 0, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_shell_scale_list(int N, double* q, const double* bg, int64_t K, const int32_t* list, int64_t n,
+                                   const double* tot_before, const double* tot_after, double* s_out,
+                                   hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    DG_DISPATCH_XFER(N, (k_shell_scale_list<NN><<<dim3((unsigned)n), dim3(Sz<NN>::NT), 0, s>>>(
+                            q, bg, K, list, tot_before, tot_after, s_out)));
     return hipGetLastError();
 }
 

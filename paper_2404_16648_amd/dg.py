@@ -34,6 +34,7 @@ DG_NC_MORTAR = 0
 DG_NC_POINTWISE = 1
 DG_IND_THETA = 0
 DG_IND_GRAD_THETA = 1
+DG_IND_PPRIME = 2
 DG_KIND_COPY = -1
 DG_KIND_FAMILY = 8
 
@@ -43,7 +44,7 @@ EXPORTED = [
     "dg_refine_project_adjoint", "dg_coarsen_project_adjoint", "dg_rhs_adjoint", "dg_rk_stage_adjoint", "dg_budgets", "dg_budgets_noalloc", "dg_indicator", "dg_indicator_async", "dg_pass_changes", "dg_flags_after_coarsen", "dg_tracer_rhs", "dg_tracer_stage", "dg_tracer_mass",
     "dg_project_fields", "dg_flags_buffer", "dg_fma_burst", "dg_sphere_mesh_build", "dg_sphere_faces",
     "dg_sphere_geometry", "dg_sphere_volumes", "dg_sphere_refine_project", "dg_sphere_coarsen_project",
-    "dg_last_error",
+    "dg_sphere_adapt_project", "dg_sphere_face_kinds", "dg_last_error",
 ]
 
 
@@ -61,7 +62,7 @@ class ForestDesc(C.Structure):
 
 class SphereDesc(C.Structure):
     _fields_ = [("N", C.c_int32), ("n", C.c_int32), ("nz", C.c_int32), ("r_e", C.c_double), ("H", C.c_double),
-                ("host_only", C.c_int32)]
+                ("host_only", C.c_int32), ("max_level", C.c_int32)]
 
 
 class Phys(C.Structure):
@@ -130,6 +131,8 @@ def lib():
         L.dg_sphere_volumes.argtypes = [P, P, P]
         L.dg_sphere_refine_project.argtypes = [P, P, C.POINTER(Phys), P, P, P, P]
         L.dg_sphere_coarsen_project.argtypes = [P, P, P, P, P]
+        L.dg_sphere_adapt_project.argtypes = [P, P, C.POINTER(Phys), P, P, P, P]
+        L.dg_sphere_face_kinds.argtypes = [P, P]
         L.dg_last_error.restype = C.c_char_p
         for name in EXPORTED:
             if name != "dg_last_error":
@@ -188,6 +191,7 @@ class Mesh:
     def __init__(self, handle, prev=None):
         self._h = C.c_void_p(handle)
         self.prev = prev          # keeps the source mesh alive for the projections
+        self.shell = bool(getattr(prev, "shell", False))   # a cubed-sphere shell (set by dg_sphere_mesh_build)
         info = MeshInfo()
         _check(lib().dg_mesh_info_get(self._h, C.byref(info)))
         self.info = info
@@ -253,12 +257,15 @@ def dg_mesh_build(N=None, nroot=None, max_level=0, lo=(0.0, 0.0, 0.0), hi=(1.0, 
     return Mesh(out.value, prev)
 
 
-def dg_sphere_mesh_build(N, n, nz, r_e=6.371e6, H=1.0e4, host_only=False) -> Mesh:
-    """Uniform cubed-sphere shell mesh (six panels of n x n elements, nz layers)."""
+def dg_sphere_mesh_build(N, n, nz, r_e=6.371e6, H=1.0e4, host_only=False, max_level=0) -> Mesh:
+    """Cubed-sphere shell mesh (six panels of n x n elements, nz layers), the root
+    level of a forest refinable max_level times."""
     out = C.c_void_p()
-    d = SphereDesc(N, n, nz, r_e, H, 1 if host_only else 0)
+    d = SphereDesc(N, n, nz, r_e, H, 1 if host_only else 0, max_level)
     _check(lib().dg_sphere_mesh_build(C.byref(d), C.byref(out)))
-    return Mesh(out.value)
+    m = Mesh(out.value)
+    m.shell = True
+    return m
 
 
 def dg_sphere_faces(mesh: Mesh):
@@ -299,6 +306,26 @@ def dg_sphere_refine_project(coarse: Mesh, fine: Mesh, phys: PhysParams, q_coars
     _check(lib().dg_sphere_refine_project(coarse.handle, fine.handle, C.byref(ph), _ptr(q_coarse), _ptr(q_fine),
                                           C.c_void_p(s.ctypes.data) if scale else None, _stream(stream)))
     return float(s[0]) if scale else None
+
+
+def dg_sphere_adapt_project(src: Mesh, dst: Mesh, phys: PhysParams, q_from, q_to, stream=None, scale=True):
+    """Transfer of a shell's refine or coarsen pass (dst built from src); returns
+    the refinement's mass scale factor (waiting for the stream), or None with
+    scale=False (enqueue only)."""
+    _shape_check(src, q_from)
+    _shape_check(dst, q_to)
+    ph = phys.c()
+    s = np.zeros(1)
+    _check(lib().dg_sphere_adapt_project(src.handle, dst.handle, C.byref(ph), _ptr(q_from), _ptr(q_to),
+                                         C.c_void_p(s.ctypes.data) if scale else None, _stream(stream)))
+    return float(s[0]) if scale else None
+
+
+def dg_sphere_face_kinds(mesh: Mesh):
+    """Face kinds of a shell, int32 [K, 6]: 0 wall, 1 conforming, 2 + 4 quadrant fine side, 3 coarse side."""
+    k = np.zeros((mesh.K, 6), np.int32)
+    _check(lib().dg_sphere_face_kinds(mesh.handle, C.c_void_p(k.ctypes.data)))
+    return k
 
 
 def dg_sphere_coarsen_project(fine: Mesh, coarse: Mesh, q_fine, q_coarse, stream=None):
@@ -555,7 +582,7 @@ def adapt_cycle(mesh: Mesh, phys: PhysParams, q, kind, thr, stream=None, buffer=
     its conservative projection (host control flow; every arithmetic step runs in
     the library).  Returns (new_mesh, new_q); when neither pass changes a leaf,
     the input mesh and field themselves."""
-    return project_cycle(mesh, *adapt_meshes(mesh, phys, q, kind, thr, stream, buffer), q, stream)
+    return project_cycle(mesh, *adapt_meshes(mesh, phys, q, kind, thr, stream, buffer), q, stream, phys)
 
 
 def _on(stream):
@@ -566,20 +593,29 @@ def _on(stream):
     return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
 
 
-def project_cycle(mesh: Mesh, mc: Mesh, mr: Mesh, q, stream=None):
+def project_cycle(mesh: Mesh, mc: Mesh, mr: Mesh, q, stream=None, phys: PhysParams | None = None):
     """The projections of one adaptation cycle (mesh -> mc coarsening, mc -> mr
     refinement; a pass that changed nothing is skipped).  Returns (mr, q on mr);
-    the new fields are allocated for `stream`."""
+    the new fields are allocated for `stream`.  A shell takes the transfer of
+    section 3.4 (its refinement's scale factor needs phys for the background)."""
     import torch
+    if mesh.shell and phys is None:
+        raise ValueError("a shell's projections need phys")
     qc = q
     with _on(stream):
         if mc is not mesh:
             qc = torch.empty(5, mc.K, mc.Np, dtype=torch.float64, device=q.device)
-            dg_coarsen_project(mesh, mc, q, qc, stream)
+            if mesh.shell:
+                dg_sphere_adapt_project(mesh, mc, phys, q, qc, stream, scale=False)
+            else:
+                dg_coarsen_project(mesh, mc, q, qc, stream)
         qr = qc
         if mr is not mc:
             qr = torch.empty(5, mr.K, mr.Np, dtype=torch.float64, device=q.device)
-            dg_refine_project(mc, mr, qc, qr, stream)
+            if mesh.shell:
+                dg_sphere_adapt_project(mc, mr, phys, qc, qr, stream, scale=False)
+            else:
+                dg_refine_project(mc, mr, qc, qr, stream)
     return mr, qr
 
 
@@ -700,7 +736,7 @@ class AdaptiveStepper:
                 self.q, self._spec = spec, q  # the old state's buffer takes the next speculation
             else:
                 self.changed += 1
-                mr2, qn = project_cycle(mesh, mc, mr, q, self.stream)
+                mr2, qn = project_cycle(mesh, mc, mr, q, self.stream, self.phys)
                 mr2.prev = None
                 self.mesh, self.q = mr2, qn
                 self._reserve(mr2.K)

@@ -271,3 +271,88 @@ def test_planted_mistake_is_caught(name, monkeypatch):
     plant(monkeypatch)
     with pytest.raises(AssertionError):
         check()
+
+
+# ----------------------------------------------------------------------------- library host side
+def _lib_available():
+    try:
+        from paper_2404_16648_amd import dg
+        dg.lib()
+        return True
+    except RuntimeError:
+        return False
+
+
+def _tables_match(lm, om):
+    from paper_2404_16648_amd import dg
+    t = lm.tables()
+    assert np.array_equal(t["leaf"], om.leaves.astype(np.int32))
+    assert np.array_equal(dg.dg_sphere_faces(lm), om.nb.astype(np.int32))
+    assert np.array_equal(dg.dg_sphere_face_kinds(lm), (om.kind + 4 * om.aux).astype(np.int32))
+    assert np.array_equal(t["hang"], om.hang.astype(np.int32))
+    assert np.array_equal(t["xfer_src"], om.xfer_src.astype(np.int32))
+    assert np.array_equal(t["xfer_kind"], om.xfer_kind.astype(np.int32))
+
+
+@pytest.mark.skipif(not _lib_available(), reason="library not built")
+@pytest.mark.parametrize("N,n,nz,L,seed", [(3, 2, 1, 2, 1), (2, 1, 2, 3, 2), (4, 3, 1, 1, 3)])
+def test_library_passes_match_the_oracle(N, n, nz, L, seed):
+    """random refine and coarsen flag sequences applied by the library's forest and
+    the oracle's: bit-exact leaves, face tables, hanging rows and transfer plans,
+    and dg_pass_changes against what each pass builds"""
+    from paper_2404_16648_amd import dg
+    lm = dg.dg_sphere_mesh_build(N, n, nz, host_only=True, max_level=L)
+    om = sp.SphereMesh(sp.SphereDesc(N=N, n=n, nz=nz, max_level=L))
+    _tables_match(lm, om)
+    rng = np.random.default_rng(seed)
+    for step in range(5):
+        refine = step % 3 != 2
+        fl = np.where(rng.random(om.K) < (0.3 if refine else 0.7), 1 if refine else -1, 0).astype(np.int8)
+        p = dg.DG_PASS_REFINE if refine else dg.DG_PASS_COARSEN
+        changes = dg.dg_pass_changes(lm, fl, p)
+        lm2 = dg.dg_mesh_build(prev=lm, flags=fl, pass_=p)
+        om2 = sp.refine_pass(om, fl) if refine else sp.coarsen_pass(om, fl)
+        _tables_match(lm2, om2)
+        assert changes == (not np.array_equal(om2.leaves, om.leaves) or om2.K != om.K)
+        lm, om = lm2, om2
+    assert len(om.hang) > 0
+
+
+@pytest.mark.skipif(not _lib_available(), reason="library not built")
+def test_library_geometry_of_a_refined_shell():
+    from paper_2404_16648_amd import dg
+    N = 3
+    lm = dg.dg_sphere_mesh_build(N, 2, 1, host_only=True, max_level=2)
+    om = sp.SphereMesh(sp.SphereDesc(N=N, n=2, nz=1, max_level=2))
+    rng = np.random.default_rng(5)
+    for _ in range(2):
+        fl = (rng.random(om.K) < 0.3).astype(np.int8)
+        lm = dg.dg_mesh_build(prev=lm, flags=fl, pass_=dg.DG_PASS_REFINE)
+        om = sp.refine_pass(om, fl)
+    _tables_match(lm, om)
+    metric, fgeo, c1d = dg.dg_sphere_geometry(lm)
+    g = sp.SphereGeometry(om)
+    J = g.J.reshape(om.K, -1).numpy()
+    assert np.abs(metric[0] - J).max() <= 1e-13 * np.abs(J).max()
+    for i in range(3):
+        row = max(np.abs(g.Ja[i][c].numpy()).max() for c in range(3))
+        for c in range(3):
+            assert np.abs(metric[1 + 3 * i + c] - g.Ja[i][c].reshape(om.K, -1).numpy()).max() <= 1e-13 * row
+    assert np.abs(fgeo[..., :3] - g.nrm.permute(1, 2, 3, 0).numpy()).max() <= 1e-13
+    assert np.abs(fgeo[..., 3] - g.sJ.numpy()).max() <= 1e-13 * g.sJ.numpy().max()
+    vol, (v_disc, v_exc) = dg.dg_sphere_volumes(lm)
+    assert np.abs(vol - sp.element_volumes(om)).max() <= 1e-13 * vol.max()
+
+
+@pytest.mark.skipif(not _lib_available(), reason="library not built")
+def test_library_level_zero_tables_two_ways():
+    """the unrefined shell's connectivity from the lattice matching (max_level 0)
+    and from the forest's neighbour search (max_level 1) are the same"""
+    from paper_2404_16648_amd import dg
+    a = dg.dg_sphere_mesh_build(3, 3, 2, host_only=True)
+    b = dg.dg_sphere_mesh_build(3, 3, 2, host_only=True, max_level=1)
+    assert np.array_equal(dg.dg_sphere_faces(a), dg.dg_sphere_faces(b))
+    assert np.array_equal(dg.dg_sphere_face_kinds(a), dg.dg_sphere_face_kinds(b))
+    with pytest.raises(dg.DGError) as e:
+        dg.dg_mesh_build(prev=a, flags=np.ones(a.K, np.int8), pass_=dg.DG_PASS_REFINE)
+    assert e.value.code == dg.DG_EUNSUPPORTED
