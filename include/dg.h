@@ -252,16 +252,16 @@ dg_status dg_sphere_refine_project(const dg_mesh* coarse, const dg_mesh* fine, c
                                    const double* q_coarse, double* q_fine, double* scale, void* stream);
 /* Coarsening transfer, the reverse pair, section 3.4 (a): each coarse element
  * is the sum over its eight children of R_ax x R_ay x R_az q_a (the reference
- * projection, in whose element mean every child counts for an eighth) plus,
- * per field, the constant sum_a (w_a - 1/8) m(q_a) that weighs the children's
- * means by their volumes instead (w_a: the child's spherical-excess volume over
- * its family's, m: the mean over the reference cube, (1/8) sum of W q).  A
- * reading: the element means obey the finite-volume balance V_p m(q_p) =
- * sum_a V_a m(q_a) exactly and a constant field stays constant.  Linear, no
- * background.  Fields as for dg_sphere_refine_project; enqueued on stream.
- * DG_EINVAL for shells that are not such a pair. */
-dg_status dg_sphere_coarsen_project(const dg_mesh* fine, const dg_mesh* coarse, const double* q_fine,
-                                    double* q_coarse, void* stream);
+ * projection) plus, per conserved field, the constant that makes the element's
+ * J W integral the sum of its children's (each child weighs in with its own
+ * volume integral, a finite-volume balance on the elements' discrete volumes; rho'
+ * and Theta' are balanced with their background, so the total mass and Theta are
+ * kept exactly).  A reading: the paper weighs each child by its volume without
+ * fixing the measure; this one keeps the quadrature the solver conserves.  phys
+ * gives the backgrounds.  Fields as for dg_sphere_refine_project; enqueued on
+ * stream.  DG_EINVAL for shells that are not such a pair. */
+dg_status dg_sphere_coarsen_project(const dg_mesh* fine, const dg_mesh* coarse, const dg_phys* phys,
+                                    const double* q_fine, double* q_coarse, void* stream);
 /* The transfer of a refine or coarsen pass of a shell built with max_level > 0
  * (section 3.4's transfer on curved elements, with the reference matrices only):
  * `to` was built by dg_mesh_build(prev = from, ...).  Kept leaves are copied; a
@@ -269,8 +269,9 @@ dg_status dg_sphere_coarsen_project(const dg_mesh* fine, const dg_mesh* coarse, 
  * the refined parents) / (mass of their interpolated children), both the J W
  * quadrature of rhobar + rho', multiplies every conserved field of every child,
  * background included, as in dg_sphere_refine_project; a merged family becomes the
- * sum of its children's reference projections plus the volume-weighted mean
- * constant, as in dg_sphere_coarsen_project.  q_from, q_to: device [5][K][Np] of
+ * sum of its children's reference projections plus the constant that keeps its
+ * J W integrals, as in dg_sphere_coarsen_project: both passes keep the total
+ * mass and Theta exactly.  q_from, q_to: device [5][K][Np] of
  * their meshes, caller-owned, not aliased; phys float64 without viscosity.  If
  * scale (host) is not NULL it receives s (1 when nothing was refined) and the call
  * waits for the stream; otherwise it only enqueues.  Uses both meshes' reduction

@@ -716,11 +716,11 @@ def discrete_volume(op: SphereOperator):
 # corrected as the paper prescribes for curved elements:
 #
 # * coarsening: the parent is the sum over its children of R_ax x R_ay x R_az q_a
-#   (the reference projection, whose element mean weighs every child by an eighth),
-#   plus the constant that makes the parent's mean the children's means weighted by
-#   their volumes, V_p m(q_p) = sum_a V_a m(q_a) with the spherical-excess volumes
-#   and m the mean over the reference cube, (1/8) sum W q: the finite-volume
-#   balance; a constant stays constant;
+#   (the reference projection) plus, per conserved field (rho and Theta with their
+#   background), the constant that makes the parent's J W integral the sum of its
+#   children's: each child contributes its own volume integral, the finite-volume
+#   balance on the elements' discrete volumes, so the quadrature the solver
+#   conserves between regrids is kept exactly;
 # * refinement: every child takes I_ax x I_ay x I_az of its parent, then one scale
 #   factor s, the total mass before over the total mass after (the J W quadrature
 #   of rho = rhobar + rho' on each shell), multiplies every conserved field,
@@ -770,23 +770,38 @@ def refine_shell(op_c: SphereOperator, op_f: SphereOperator, q_c):
     return out, s
 
 
+def _conserved_background(op: SphereOperator):
+    """the background part of each conserved field, [rhobar, 0, 0, 0, Thetabar]"""
+    rho_b, Th_b, _ = op.bg
+    z = torch.zeros_like(rho_b)
+    return torch.stack([rho_b, z, z, z, Th_b])
+
+
+def _family_constant(JW_kids, full_kids, JW_par, full_par):
+    """per field, (sum of the children's J W integrals - the parent's) / the
+    parent's J W volume, on the conserved fields (background included)"""
+    inside = (JW_kids[None] * full_kids).sum(dim=(-4, -3, -2, -1))
+    mine = (JW_par[None] * full_par).sum(dim=(-3, -2, -1))
+    return (inside - mine) / JW_par.sum()
+
+
 def coarsen_shell(op_f: SphereOperator, op_c: SphereOperator, q_f):
-    """section 3.4 (a): the children's reference projections, plus per field the
-    constant that weighs the children's means by their volumes.  Returns (q_c, w)
-    with w[e, a] = V_a / sum_b V_b the volume fraction of child a of e."""
+    """section 3.4 (a): the children's reference projections, plus per conserved
+    field the constant that keeps each family's J W integral (background included).
+    Returns q_c."""
     ch = children(op_c.mesh, op_f.mesh)
-    V = element_volumes(op_f.mesh)
-    Vc = V[ch]                                               # [Kc, 8]
-    w = Vc / Vc.sum(axis=1, keepdims=True)
     Rm = op_c.re.R
+    JWf, JWc = quad_weights(op_f), quad_weights(op_c)
     q_c = torch.zeros(5, op_c.K, *q_f.shape[2:], dtype=F64)
-    shift = torch.zeros(5, op_c.K, dtype=F64)
     for a in range(8):
         ax, ay, az = a & 1, (a >> 1) & 1, a >> 2
-        qa = q_f[:, torch.as_tensor(ch[:, a])]
-        q_c = q_c + _apply3(Rm[ax], Rm[ay], Rm[az], qa)
-        shift = shift + (torch.as_tensor(w[:, a], dtype=F64)[None] - 0.125) * reference_means(qa)
-    return q_c + shift[:, :, None, None, None], w
+        q_c = q_c + _apply3(Rm[ax], Rm[ay], Rm[az], q_f[:, torch.as_tensor(ch[:, a])])
+    Bf, Bc = _conserved_background(op_f), _conserved_background(op_c)
+    for e in range(op_c.K):
+        kids = torch.as_tensor(ch[e])
+        c = _family_constant(JWf[kids], Bf[:, kids] + q_f[:, kids], JWc[e], Bc[:, e] + q_c[:, e])
+        q_c[:, e] = q_c[:, e] + c[:, None, None, None]
+    return q_c
 
 
 def reference_means(q):
@@ -841,14 +856,15 @@ def adapt_project(op_from: SphereOperator, op_to: SphereOperator, q):
     reference interpolation of its parent, and one scale factor s (the mass of the
     refined parents over the mass of their interpolated children) multiplies every
     conserved field of every child, background included; a merged family becomes
-    the sum of its children's reference projections plus, per field, the constant
-    that weighs their means by their spherical-excess volumes.  Returns (q_to, s),
-    s = 1 when nothing was refined."""
+    the sum of its children's reference projections plus, per conserved field, the
+    constant that keeps the family's J W integral (background included).  Returns
+    (q_to, s), s = 1 when nothing was refined."""
     mesh = op_to.mesh
     src, kind = mesh.xfer_src, mesh.xfer_kind
     I, Rm = op_to.re.I, op_to.re.R
     out = torch.zeros(5, op_to.K, *q.shape[2:], dtype=F64)
-    V = element_volumes(op_from.mesh)
+    JW_from, JW_to = quad_weights(op_from), quad_weights(op_to)
+    B_from, B_to = _conserved_background(op_from), _conserved_background(op_to)
     children_new, parents_old = [], set()
     for e in range(op_to.K):
         k, sidx = int(kind[e]), int(src[e])
@@ -861,14 +877,13 @@ def adapt_project(op_from: SphereOperator, op_to: SphereOperator, q):
             parents_old.add(sidx)
         else:
             fam = list(range(sidx, sidx + 8))
-            w = V[fam] / V[fam].sum()
             acc = torch.zeros_like(q[:, sidx])
-            shift = torch.zeros(5, dtype=F64)
             for a, ea in enumerate(fam):
                 ax, ay, az = a & 1, (a >> 1) & 1, a >> 2
                 acc = acc + _apply3(Rm[ax], Rm[ay], Rm[az], q[:, ea][:, None])[:, 0]
-                shift = shift + (float(w[a]) - 0.125) * reference_means(q[:, ea][:, None])[:, 0]
-            out[:, e] = acc + shift[:, None, None, None]
+            kids = torch.as_tensor(fam)
+            c = _family_constant(JW_from[kids], B_from[:, kids] + q[:, kids], JW_to[e], B_to[:, e] + acc)
+            out[:, e] = acc + c[:, None, None, None]
     s = 1.0
     if children_new:
         s = _subset_mass(op_from, q, sorted(parents_old)) / _subset_mass(op_to, out, children_new)

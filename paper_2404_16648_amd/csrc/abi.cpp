@@ -58,7 +58,7 @@ void free_device(dg_mesh* m) {
     m->d_mort = nullptr;
     m->d_mortC = nullptr;
     m->d_flags = nullptr;
-    m->d_metric = m->d_fgeo = m->d_cw = nullptr;
+    m->d_metric = m->d_fgeo = nullptr;
     m->d_xlist = nullptr;
     if (m->d_sigma) (void)hipFree(m->d_sigma);
     m->d_sigma = nullptr;
@@ -67,7 +67,7 @@ void free_device(dg_mesh* m) {
 // byte offsets of the arrays in a mesh's one device block, 256-byte aligned;
 // [0, upload) is copied from the host, the rest is device workspace
 struct DevLayout {
-    size_t ops, geo, c1d, ft, nb, hs, hg, lv, xs, xk, sr, met, fg, cw, xl, upload, bg, red, eta, fl, mort, mortC, total;
+    size_t ops, geo, c1d, ft, nb, hs, hg, lv, xs, xk, sr, met, fg, xl, upload, bg, red, eta, fl, mort, mortC, total;
 };
 
 DevLayout dev_layout(int64_t K, int N, int64_t red_len, int64_t n_hang, bool sphere, int64_t n_xlist) {
@@ -93,7 +93,6 @@ DevLayout dev_layout(int64_t K, int N, int64_t red_len, int64_t n_hang, bool sph
     // shell meshes: metric terms and face geometry
     L.met = take(sphere ? sizeof(double) * 10 * k * N1 * N1 * N1 : 0);
     L.fg = take(sphere ? sizeof(double) * 24 * k * N1 * N1 : 0);
-    L.cw = take(sphere ? sizeof(double) * k : 0);
     L.xl = take(sphere ? sizeof(int32_t) * (size_t)n_xlist : 0);
     L.upload = end;
     L.bg = take(sizeof(double) * 3 * k * N1);
@@ -123,7 +122,6 @@ void set_device_pointers(dg_mesh* m, char* base, const DevLayout& L) {
     m->d_srec = (int32_t*)(base + L.sr);
     m->d_metric = m->h.sphere ? (double*)(base + L.met) : nullptr;
     m->d_fgeo = m->h.sphere ? (double*)(base + L.fg) : nullptr;
-    m->d_cw = m->h.sphere ? (double*)(base + L.cw) : nullptr;
     m->d_xlist = m->h.sphere ? (int32_t*)(base + L.xl) : nullptr;
     m->d_bg = (double*)(base + L.bg);
     m->d_red = (double*)(base + L.red);
@@ -266,24 +264,7 @@ dg_status build_device(dg_mesh* m, hipStream_t s) {
         std::memset(geo, 0, sizeof(double) * 4 * K);
         for (int64_t e = 0; e < K; ++e) level[e] = h.leaves[e].l;
         sphere_geometry(h, m->ops, (double*)(up.data() + L.met), (double*)(up.data() + L.fg), c1d);
-        // volume fraction of every element within its parent, the cell one level up
-        // (at level 0, the element of the shell with half the elements per edge and
-        // layers): the weights of the coarsening; zero at level 0 when n or nz is odd
         if (!xlist.empty()) std::memcpy(up.data() + L.xl, xlist.data(), sizeof(int32_t) * xlist.size());
-        double* cw = (double*)(up.data() + L.cw);
-        const dg_sphere_desc& sd = h.sdesc;
-        for (int64_t e = 0; e < K; ++e) {
-            const Leaf& L0 = h.leaves[e];
-            cw[e] = 0.0;
-            if (L0.l == 0 && (sd.n % 2 || sd.nz % 2)) continue;
-            long double tot = 0.0L;
-            for (int c = 0; c < 8; ++c) {
-                const Leaf sib{L0.r, L0.l, {(L0.a[0] & ~1) + (c & 1), (L0.a[1] & ~1) + ((c >> 1) & 1),
-                                            (L0.a[2] & ~1) + (c >> 2)}};
-                tot += sphere_cell_volume(sd, sib);
-            }
-            cw[e] = (double)(sphere_cell_volume(sd, L0) / tot);
-        }
     } else {
         for (int64_t e = 0; e < K; ++e) {
             double hh[3], c[3 * 8];  // N + 1 <= 8
@@ -673,7 +654,8 @@ dg_status dg_sphere_refine_project(const dg_mesh* coarse, const dg_mesh* fine, c
     if ((st = ensure_bg(mc, phys, s)) || (st = ensure_bg(mf, phys, s))) return st;
     const int N = coarse->h.desc.N;
     const int64_t Kc = (int64_t)coarse->h.leaves.size(), Kf = (int64_t)fine->h.leaves.size();
-    ShellXferArgs a{q_coarse, q_fine, fine->d_ops, fine->d_cw, Kc, Kf, coarse->h.sdesc.n, coarse->h.sdesc.nz};
+    ShellXferArgs a{q_coarse, q_fine, fine->d_ops, nullptr, nullptr, nullptr, nullptr, Kc, Kf, coarse->h.sdesc.n,
+                    coarse->h.sdesc.nz};
     HIP_TRY(launch_shell_refine(N, a, s));
     // total mass before (coarse) and after (fine, interpolated): the budget reductions
     const double* w = fine->d_ops + 5 * (N + 1) * (N + 1);
@@ -695,15 +677,20 @@ dg_status dg_sphere_refine_project(const dg_mesh* coarse, const dg_mesh* fine, c
     return DG_OK;
 }
 
-dg_status dg_sphere_coarsen_project(const dg_mesh* fine, const dg_mesh* coarse, const double* q_fine,
-                                    double* q_coarse, void* stream) {
+dg_status dg_sphere_coarsen_project(const dg_mesh* fine, const dg_mesh* coarse, const dg_phys* phys,
+                                    const double* q_fine, double* q_coarse, void* stream) {
     dg_status st = shell_pair(coarse, fine);
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
     if ((st = check_dev_mesh(coarse, s)) || (st = check_dev_mesh(fine, s))) return st;
+    if ((st = check_phys(phys))) return st;
     if (!q_coarse || !q_fine) return fail(DG_EINVAL, "NULL field pointer");
+    dg_mesh* mc = const_cast<dg_mesh*>(coarse);
+    dg_mesh* mf = const_cast<dg_mesh*>(fine);
+    if ((st = ensure_bg(mc, phys, s)) || (st = ensure_bg(mf, phys, s))) return st;
     const int64_t Kc = (int64_t)coarse->h.leaves.size(), Kf = (int64_t)fine->h.leaves.size();
-    ShellXferArgs a{q_fine, q_coarse, fine->d_ops, fine->d_cw, Kf, Kc, coarse->h.sdesc.n, coarse->h.sdesc.nz};
+    ShellXferArgs a{q_fine, q_coarse, fine->d_ops, mf->d_metric, mc->d_metric, mf->d_bg, mc->d_bg, Kf, Kc,
+                    coarse->h.sdesc.n, coarse->h.sdesc.nz};
     HIP_TRY(launch_shell_coarsen(coarse->h.desc.N, a, s));
     return DG_OK;
 }
@@ -726,7 +713,8 @@ dg_status dg_sphere_adapt_project(const dg_mesh* from, const dg_mesh* to, const 
     if ((st = ensure_bg(mf, phys, s)) || (st = ensure_bg(mt, phys, s))) return st;
     const int N = to->h.desc.N;
     const int64_t Kf = (int64_t)from->h.leaves.size(), Kt = (int64_t)to->h.leaves.size();
-    ShellPlanArgs a{q_from, q_to, to->d_ops, from->d_cw, to->d_xsrc, to->d_xkind, Kf, Kt};
+    ShellPlanArgs a{q_from, q_to, to->d_ops, mf->d_metric, mt->d_metric, mf->d_bg, mt->d_bg, to->d_xsrc,
+                    to->d_xkind, Kf, Kt};
     HIP_TRY(launch_shell_plan(N, a, s));
     if (to->n_xch > 0) {
         // the refined parents' mass (source) and their children's (target), then the factor

@@ -115,7 +115,6 @@ struct dg_mesh {
     double* d_sigma = nullptr;    // [3][5][K][Np]: viscous gradient (own allocation, at first use)
     double* d_metric = nullptr;   // sphere: [10][K][Np] J and metric terms
     double* d_fgeo = nullptr;     // sphere: [K][6][NF][4] face normal and face Jacobian
-    double* d_cw = nullptr;       // sphere with even n, nz: [K] volume fraction of the element in its parent
     int32_t* d_xlist = nullptr;   // sphere: the children of this mesh's plan, then their parents in prev
     int64_t n_xch = 0, n_xpar = 0;
 };

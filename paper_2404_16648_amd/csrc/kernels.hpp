@@ -212,13 +212,15 @@ hipError_t launch_mortar_sphere(int N, const SphereMortArgs& a, hipStream_t s);
 
 // transfers of a shell's refine or coarsen pass along the plan (src, kind) of the
 // target mesh: copies, children by reference interpolation, families by the
-// reference projections plus the volume-weighted mean (cw: the source mesh's
-// volume fraction of each leaf in its parent)
+// reference projections plus the constant that keeps their J W integrals
 struct ShellPlanArgs {
     const double* src;
     double* dst;
     const double* ops;
-    const double* cw;
+    const double* met_src;
+    const double* met_dst;
+    const double* bg_src;
+    const double* bg_dst;
     const int32_t* xsrc;
     const int32_t* xkind;
     int64_t Ksrc, Kdst;
@@ -291,12 +293,16 @@ hipError_t launch_node_coords_sphere(int64_t K, int N, const double* c1d, const 
                                      double* xyz, hipStream_t s);
 // transfers between a shell (nc per panel edge, nzc layers) and the shell with twice
 // both (N = 2..7): refine reads the coarse src and writes the fine dst, coarsen the
-// reverse; cw is the fine shell's volume fraction of each element in its parent
+// reverse; the coarsening's constant takes the J of both shells (metric plane 0) and
+// their backgrounds
 struct ShellXferArgs {
     const double* src;
     double* dst;
     const double* ops;
-    const double* cw;
+    const double* met_src;
+    const double* met_dst;
+    const double* bg_src;
+    const double* bg_dst;
     int64_t Ksrc, Kdst;
     int nc, nzc;
 };

@@ -412,18 +412,21 @@ __device__ __forceinline__ void child_of_parent(const double* src, int64_t Ksrc,
 }
 
 // one family: dst[e] = sum_a (R_ax x R_ay x R_az) src[kid_a] plus, per field, the
-// constant sum_a (w_a - 1/8) m(src[kid_a]), w_a = cw[kid_a] the child's volume
-// fraction and m the mean over the reference cube, (1/8) sum W q
+// constant c = (sum of the children's J W integrals - the parent's) / the parent's
+// J W volume, taken on the conserved fields (rho' and Theta' with their background):
+// the family's quadrature of every conserved field is kept.  sRed: [NT][11] doubles.
 template <int N>
 __device__ __forceinline__ void family_to_parent(const double* src, int64_t Ksrc, const int64_t kids[8], double* dst,
-                                                 int64_t Kdst, int64_t e, const double* ops, const double* cw,
-                                                 double* sT, double* sU, double* sR, double* sW, double* sShift,
+                                                 int64_t Kdst, int64_t e, const double* ops, const double* met_src,
+                                                 const double* met_dst, const double* bg_src, const double* bg_dst,
+                                                 double* sT, double* sU, double* sR, double* sW, double* sRed,
                                                  int t) {
     constexpr int N1 = N + 1, NP = N1 * N1 * N1, NF = N1 * N1, NT = Sz<N>::NT;
     for (int x = t; x < 2 * NF; x += NT) sR[x] = ops[3 * NF + x];  // R_0, R_1
     if (t < N1) sW[t] = ops[5 * NF + t];
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    double shift = 0.0;  // thread v < 5: the constant of field v
+    double inside[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const int ii = t % N1, jj = (t / N1) % N1, kk = t / NF;
     for (int a = 0; a < 8; ++a) {
         const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
         const int64_t ef = kids[a];
@@ -432,13 +435,14 @@ __device__ __forceinline__ void family_to_parent(const double* src, int64_t Ksrc
 #pragma unroll
             for (int v = 0; v < 5; ++v) sT[v * NP + t] = src[(v * Ksrc + ef) * NP + t];
         __syncthreads();
-        if (t < 5) {
-            double m = 0.0;
-            for (int nn = 0; nn < NP; ++nn) {
-                const int i = nn % N1, j = (nn / N1) % N1, k = nn / NF;
-                m = fma(sW[i] * sW[j] * sW[k], sT[t * NP + nn], m);
+        if (t < NP) {
+            const double JW = met_src[ef * NP + t] * (sW[ii] * sW[jj] * sW[kk]);
+            const double b0 = bg_src[ef * N1 + kk], b4 = bg_src[Ksrc * N1 + ef * N1 + kk];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const double full = v == 0 ? b0 + sT[t] : v == 4 ? b4 + sT[4 * NP + t] : sT[v * NP + t];
+                inside[v] = fma(JW, full, inside[v]);
             }
-            shift = fma(cw[ef] - 0.125, 0.125 * m, shift);
         }
         tile_pass<N>(sT, sU, sR + ax * NF, 0, t);
         __syncthreads();
@@ -456,11 +460,34 @@ __device__ __forceinline__ void family_to_parent(const double* src, int64_t Ksrc
             }
         }
     }
-    if (t < 5) sShift[t] = shift;
+    // the eleven sums: inside[5], the projection's integrals[5], the parent's volume
+    double part[11];
+#pragma unroll
+    for (int x = 0; x < 11; ++x) part[x] = 0.0;
+    if (t < NP) {
+        const double JW = met_dst[e * NP + t] * (sW[ii] * sW[jj] * sW[kk]);
+        const double b0 = bg_dst[e * N1 + kk], b4 = bg_dst[Kdst * N1 + e * N1 + kk];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            part[v] = inside[v];
+            part[5 + v] = JW * (v == 0 ? b0 + acc[0] : v == 4 ? b4 + acc[4] : acc[v]);
+        }
+        part[10] = JW;
+    }
     __syncthreads();
+#pragma unroll
+    for (int x = 0; x < 11; ++x) sRed[x * NT + t] = part[x];
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (t < w)
+#pragma unroll
+            for (int x = 0; x < 11; ++x) sRed[x * NT + t] += sRed[x * NT + t + w];
+        __syncthreads();
+    }
     if (t < NP)
 #pragma unroll
-        for (int v = 0; v < 5; ++v) dst[(v * Kdst + e) * NP + t] = acc[v] + sShift[v];
+        for (int v = 0; v < 5; ++v)
+            dst[(v * Kdst + e) * NP + t] = acc[v] + (sRed[v * NT] - sRed[(5 + v) * NT]) / sRed[10 * NT];
 }
 
 // refinement between the shell pair: every fine element from its parent
@@ -481,7 +508,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_shell_refine(const ShellXferArgs 
 template <int N>
 __global__ void __launch_bounds__(Sz<N>::NT) k_shell_coarsen(const ShellXferArgs A) {
     constexpr int N1 = N + 1, NP = Sz<N>::NP, NF = Sz<N>::NF;
-    __shared__ double sT[5 * NP], sU[5 * NP], sR[2 * NF], sW[N1], sShift[5];
+    __shared__ double sT[5 * NP], sU[5 * NP], sR[2 * NF], sW[N1], sRed[11 * Sz<N>::NT];
     const int64_t ec = blockIdx.x;
     const int nc = A.nc, nzc = A.nzc, nf = 2 * nc, nzf = 2 * nzc;
     const int ia = (int)(ec % nc), ib = (int)((ec / nc) % nc), ir = (int)((ec / ((int64_t)nc * nc)) % nzc);
@@ -489,7 +516,8 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_shell_coarsen(const ShellXferArgs
     int64_t kids[8];
     for (int a = 0; a < 8; ++a)
         kids[a] = (((int64_t)p * nzf + 2 * ir + (a >> 2)) * nf + 2 * ib + ((a >> 1) & 1)) * nf + 2 * ia + (a & 1);
-    family_to_parent<N>(A.src, A.Ksrc, kids, A.dst, A.Kdst, ec, A.ops, A.cw, sT, sU, sR, sW, sShift, threadIdx.x);
+    family_to_parent<N>(A.src, A.Ksrc, kids, A.dst, A.Kdst, ec, A.ops, A.met_src, A.met_dst, A.bg_src, A.bg_dst, sT,
+                        sU, sR, sW, sRed, threadIdx.x);
 }
 
 // a refine or coarsen pass of a shell, along the target's plan: kind -1 copies
@@ -497,7 +525,7 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_shell_coarsen(const ShellXferArgs
 template <int N>
 __global__ void __launch_bounds__(Sz<N>::NT) k_shell_plan(const ShellPlanArgs A) {
     constexpr int N1 = N + 1, NP = Sz<N>::NP, NF = Sz<N>::NF;
-    __shared__ double sT[5 * NP], sU[5 * NP], sM[3 * NF], sW[N1], sShift[5];
+    __shared__ double sT[5 * NP], sU[5 * NP], sM[3 * NF], sW[N1], sRed[11 * Sz<N>::NT];
     const int64_t e = blockIdx.x;
     const int t = threadIdx.x;
     const int kind = A.xkind[e];
@@ -511,7 +539,8 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_shell_plan(const ShellPlanArgs A)
     } else {
         int64_t kids[8];
         for (int a = 0; a < 8; ++a) kids[a] = src + a;
-        family_to_parent<N>(A.src, A.Ksrc, kids, A.dst, A.Kdst, e, A.ops, A.cw, sT, sU, sM, sW, sShift, t);
+        family_to_parent<N>(A.src, A.Ksrc, kids, A.dst, A.Kdst, e, A.ops, A.met_src, A.met_dst, A.bg_src, A.bg_dst,
+                            sT, sU, sM, sW, sRed, t);
     }
 }
 

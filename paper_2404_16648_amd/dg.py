@@ -130,7 +130,7 @@ def lib():
         L.dg_sphere_geometry.argtypes = [P, P, P, P]
         L.dg_sphere_volumes.argtypes = [P, P, P]
         L.dg_sphere_refine_project.argtypes = [P, P, C.POINTER(Phys), P, P, P, P]
-        L.dg_sphere_coarsen_project.argtypes = [P, P, P, P, P]
+        L.dg_sphere_coarsen_project.argtypes = [P, P, C.POINTER(Phys), P, P, P]
         L.dg_sphere_adapt_project.argtypes = [P, P, C.POINTER(Phys), P, P, P, P]
         L.dg_sphere_face_kinds.argtypes = [P, P]
         L.dg_last_error.restype = C.c_char_p
@@ -328,11 +328,12 @@ def dg_sphere_face_kinds(mesh: Mesh):
     return k
 
 
-def dg_sphere_coarsen_project(fine: Mesh, coarse: Mesh, q_fine, q_coarse, stream=None):
+def dg_sphere_coarsen_project(fine: Mesh, coarse: Mesh, phys: PhysParams, q_fine, q_coarse, stream=None):
     """Coarsening transfer from a shell's refinement back to the shell."""
     _shape_check(fine, q_fine)
     _shape_check(coarse, q_coarse)
-    _check(lib().dg_sphere_coarsen_project(fine.handle, coarse.handle, _ptr(q_fine), _ptr(q_coarse),
+    ph = phys.c()
+    _check(lib().dg_sphere_coarsen_project(fine.handle, coarse.handle, C.byref(ph), _ptr(q_fine), _ptr(q_coarse),
                                            _stream(stream)))
 
 

@@ -69,6 +69,20 @@ def assert_fields(a, b, tol, what="", vector_momentum=False):
     assert max(bound) <= tol, (what, err, comp)
 
 
+def assert_conserved_fields(a, b, bg, tol, what=""):
+    """As assert_fields, but rho' and Theta' compared as the full conserved fields
+    rhobar + rho' and Thetabar + Theta' (bg = (rhobar, Thetabar) in the library
+    layout [K, Np]): for a result that carries a constant fixed on the full fields
+    (the coarsening's integral balance), whose rounding is relative to them."""
+    import torch
+    a = a.detach().double().cpu().clone()
+    b = b.detach().double().cpu().clone()
+    for v, bv in ((0, bg[0]), (4, bg[1])):
+        a[v] += bv
+        b[v] += bv
+    assert_fields(a, b, tol, what)
+
+
 def phys_for(periodic, **kw):
     """Library physics for a mesh with the given periodicity: a periodic z axis
     takes g = 0 (the neutral background is then constant; a hydrostatic profile

@@ -108,5 +108,8 @@ def test_sphere_refusals():
         dg.dg_rhs(lm, dg.PhysParams(background=dg.DG_BG_ISOTHERMAL, mu=1.5), q, r)
     assert e.value.code == dg.DG_EUNSUPPORTED
     with pytest.raises(dg.DGError) as e:
-        dg.dg_indicator(lm, PH, q, dg.DG_IND_THETA, 0.1)
+        dg.dg_indicator(lm, PH, q, dg.DG_IND_GRAD_THETA, 0.1)
+    assert e.value.code == dg.DG_EUNSUPPORTED
+    with pytest.raises(dg.DGError) as e:
+        dg.dg_rhs(lm, dg.PhysParams(background=dg.DG_BG_ISOTHERMAL, nonconforming=dg.DG_NC_POINTWISE), q, r)
     assert e.value.code == dg.DG_EUNSUPPORTED

@@ -23,7 +23,7 @@ from oracle import euler as eu
 from oracle import sphere as sp
 from paper_2404_16648_amd import dg
 from paper_2404_16648_amd.synth import random_state
-from tests.helpers import TOL_FP64, assert_fields, to_elem, to_nodes
+from tests.helpers import TOL_FP64, assert_conserved_fields, assert_fields, to_elem, to_nodes
 from tests.test_gpu_parity import gpu
 
 pytestmark = pytest.mark.gpu
@@ -56,10 +56,11 @@ def test_shell_transfers_against_oracle(N, n, nz):
     # coarsening of a state on the fine shell (the refined one plus its own noise)
     qfn = qf.cpu() + torch.as_tensor(random_state(of.K, N, 70 + N)) * 0.05
     qc = lc.field()
-    dg.dg_sphere_coarsen_project(lf, lc, gpu(qfn), qc)
+    dg.dg_sphere_coarsen_project(lf, lc, PH, gpu(qfn), qc)
     torch.cuda.synchronize()
-    qc_ref, _ = sp.coarsen_shell(of, oc, to_elem(qfn, N))
-    assert_fields(qc, to_nodes(qc_ref), TOL_FP64, "shell coarsen")
+    qc_ref = sp.coarsen_shell(of, oc, to_elem(qfn, N))
+    assert_conserved_fields(qc, to_nodes(qc_ref), (to_nodes(oc.bg[0][None])[0], to_nodes(oc.bg[1][None])[0]), TOL_FP64,
+                            "shell coarsen")
 
 
 def test_scale_factor_is_the_volume_ratio():

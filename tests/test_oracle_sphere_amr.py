@@ -15,7 +15,7 @@ What the geometry and the definitions fix, independently of the code:
     close to that on the uniformly refined shell (the mortar reads the coarse trace
     at the right places);
   * the transfers of a refinement pass keep the total mass exactly, those of a
-    coarsening pass balance the volume-weighted element means exactly, and a
+    coarsening pass keep every family's J W integral of every field exactly, and a
     coarsening pass undoes a refinement pass on the leaves.
 Planted mistakes at the end: each must make one of these fail.
 """
@@ -178,16 +178,20 @@ def check_adapt_transfers(N=3, seed=6):
     o2 = sp.SphereOperator(m2, eu.Phys(), sp.BG_ISOTHERMAL)
     q2, s2 = sp.adapt_project(o1, o2, q1)
     assert s2 == 1.0
-    V = sp.element_volumes(m1)
-    mu1, mu2 = sp.reference_means(q1).numpy(), sp.reference_means(q2).numpy()
+    JW1, JW2 = sp.quad_weights(o1), sp.quad_weights(o2)
+    full1 = [o1.bg[0] + q1[0], q1[1], q1[2], q1[3], o1.bg[1] + q1[4]]
+    full2 = [o2.bg[0] + q2[0], q2[1], q2[2], q2[3], o2.bg[1] + q2[4]]
     for e in range(m2.K):
         if m2.xfer_kind[e] != 8:
             assert torch.equal(q2[:, e], q1[:, int(m2.xfer_src[e])])
             continue
-        fam = list(range(int(m2.xfer_src[e]), int(m2.xfer_src[e]) + 8))
-        lhs = V[fam].sum() * mu2[:, e]
-        rhs = (V[fam][None] * mu1[:, fam]).sum(axis=1)
-        assert np.abs(lhs - rhs).max() <= 1e-14 * np.abs(V[fam][None] * mu1[:, fam]).sum(axis=1).max()
+        fam = torch.arange(int(m2.xfer_src[e]), int(m2.xfer_src[e]) + 8)
+        for v in range(5):
+            inside = math.fsum((JW1[fam] * full1[v][fam]).reshape(-1).tolist())
+            scale = math.fsum((JW1[fam] * full1[v][fam].abs()).reshape(-1).tolist())
+            assert abs(math.fsum((JW2[e] * full2[v][e]).reshape(-1).tolist()) - inside) <= 1e-14 * scale
+    M2 = sp.budgets(o2, q2)[1]
+    assert abs(M2 - M1) <= 2e-16 * M1
 
 
 # ----------------------------------------------------------------------------- tests

@@ -9,8 +9,9 @@ What the geometry and the definitions fix, independently of the code:
   * a child's nodes are the parent's isoparametric mapping evaluated at the child's
     reference points, up to the geometry's interpolation error (the child map and
     its local axes);
-  * coarsening balances the children's volume-weighted element means exactly and
-    keeps a constant field constant;
+  * coarsening keeps every family's J W integral of every conserved field
+    (background included) exactly, and maps a constant momentum to that constant
+    times the family's discrete volume over the parent's (the volume loss);
   * refinement keeps the total mass of the J W quadrature exactly and leaves the
     velocity and the potential temperature at their interpolated values; on a
     background of constant density at rest its scale factor is the ratio of the two
@@ -72,22 +73,30 @@ def check_child_geometry(N=4, n=2, nz=1):
     assert err <= 1e-3 * width, (err, width)
 
 
-def check_coarsen_balance_and_constants(N=4, n=2, nz=1, seed=5):
+def check_coarsen_integrals_and_constants(N=4, n=2, nz=1, seed=5):
     oc, of = _pair(N, n, nz)
     g = torch.Generator().manual_seed(seed)
-    qf = torch.randn(5, of.K, N + 1, N + 1, N + 1, generator=g, dtype=F64)
-    qc, w = sp.coarsen_shell(of, oc, qf)
-    V = sp.element_volumes(of.mesh)
+    qf = torch.randn(5, of.K, N + 1, N + 1, N + 1, generator=g, dtype=F64) * 0.1
+    qc = sp.coarsen_shell(of, oc, qf)
     ch = sp.children(oc.mesh, of.mesh)
-    mf = sp.reference_means(qf).numpy()
-    mc = sp.reference_means(qc).numpy()
-    lhs = V[ch].sum(axis=1)[None] * mc
-    rhs = (V[ch][None] * mf[:, ch]).sum(axis=-1)
-    scale = float((V[ch][None] * np.abs(mf[:, ch])).sum(axis=-1).max())
-    assert float(np.abs(lhs - rhs).max()) <= 1e-14 * scale
-    const = torch.full_like(qf, 3.0)
-    qcc, _ = sp.coarsen_shell(of, oc, const)
-    assert float((qcc - 3.0).abs().max()) <= 1e-13 * 3.0
+    JWf, JWc = sp.quad_weights(of), sp.quad_weights(oc)
+    bf, bc = of.bg, oc.bg
+    full_f = [bf[0] + qf[0], qf[1], qf[2], qf[3], bf[1] + qf[4]]
+    full_c = [bc[0] + qc[0], qc[1], qc[2], qc[3], bc[1] + qc[4]]
+    for e in range(oc.K):
+        kids = torch.as_tensor(ch[e])
+        for v in range(5):
+            inside = _fsum((JWf[kids] * full_f[v][kids]).numpy())
+            scale = _fsum((JWf[kids] * full_f[v][kids].abs()).numpy())
+            assert abs(_fsum((JWc[e] * full_c[v][e]).numpy()) - inside) <= 1e-14 * scale, (e, v)
+    # momentum carries no background: a constant becomes that constant times the
+    # family's discrete volume over the parent's (the volume loss)
+    const = torch.zeros_like(qf)
+    const[1] = 3.0
+    qcc = sp.coarsen_shell(of, oc, const)
+    for e in range(oc.K):
+        ratio = _fsum(JWf[torch.as_tensor(ch[e])].numpy()) / _fsum(JWc[e].numpy())
+        assert float((qcc[1, e] - 3.0 * ratio).abs().max()) <= 1e-13 * 3.0
 
 
 def check_refine_mass_and_primitives(N=4, n=2, nz=1):
@@ -152,8 +161,8 @@ def test_children_are_the_parent_mapping():
     check_child_geometry()
 
 
-def test_coarsen_finite_volume_balance_and_constants():
-    check_coarsen_balance_and_constants()
+def test_coarsen_keeps_integrals():
+    check_coarsen_integrals_and_constants()
 
 
 def test_refine_keeps_mass_velocity_and_theta():
@@ -203,27 +212,24 @@ def test_library_transfer_refusals():
     for b in (dg.dg_sphere_mesh_build(3, 4, 1, host_only=True),          # layers not doubled
               dg.dg_sphere_mesh_build(4, 4, 2, host_only=True),          # another order
               dg.dg_sphere_mesh_build(3, 4, 2, H=2.0e4, host_only=True)):  # another top
-        assert L.dg_sphere_coarsen_project(b.handle, a.handle, None, None, None) == dg.DG_EINVAL
+        assert L.dg_sphere_coarsen_project(b.handle, a.handle, None, None, None, None) == dg.DG_EINVAL
         assert b"twice" in L.dg_last_error()
     box = dg.dg_mesh_build(3, (1, 1, 1), host_only=True)
-    assert L.dg_sphere_coarsen_project(box.handle, a.handle, None, None, None) == dg.DG_EINVAL
+    assert L.dg_sphere_coarsen_project(box.handle, a.handle, None, None, None, None) == dg.DG_EINVAL
     assert L.dg_sphere_volumes(box.handle, None, None) == dg.DG_EINVAL
 
 
 # ----------------------------------------------------------------------------- planted mistakes
-def _literal_weights(mp):
-    """every child's projection multiplied by 8 V_a / V_p, with no mean correction"""
+def _no_constant(mp):
+    """the plain reference projection (no constant for the curved volumes)"""
     def coarsen(op_f, op_c, q_f):
         ch = sp.children(op_c.mesh, op_f.mesh)
-        V = sp.element_volumes(op_f.mesh)[ch]
-        w = V / V.sum(axis=1, keepdims=True)
         Rm = op_c.re.R
         q_c = torch.zeros(5, op_c.K, *q_f.shape[2:], dtype=F64)
         for a in range(8):
             ax, ay, az = a & 1, (a >> 1) & 1, a >> 2
-            wa = torch.as_tensor(8.0 * w[:, a], dtype=F64)[None, :, None, None, None]
-            q_c = q_c + wa * sp._apply3(Rm[ax], Rm[ay], Rm[az], q_f[:, torch.as_tensor(ch[:, a])])
-        return q_c, w
+            q_c = q_c + sp._apply3(Rm[ax], Rm[ay], Rm[az], q_f[:, torch.as_tensor(ch[:, a])])
+        return q_c
     mp.setattr(sp, "coarsen_shell", coarsen)
 
 
@@ -250,7 +256,7 @@ def _swapped_child_axes(mp):
 
 
 MUTANTS = {
-    "volume weights multiplying the projections": (_literal_weights, check_coarsen_balance_and_constants),
+    "coarsening without the constant": (_no_constant, check_coarsen_integrals_and_constants),
     "scale factor on the perturbations only": (_scale_perturbation_only, check_refine_mass_and_primitives),
     "child axes swapped": (_swapped_child_axes, check_child_geometry),
 }
