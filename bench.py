@@ -427,10 +427,10 @@ def shell_transfers(dg, torch, N=4, n=12, nz=4):
     qf, qc2 = mf.field(), mc.field()
     s = dg.dg_sphere_refine_project(mc, mf, ph, qc, qf)
     b0, b1 = dg.dg_budgets(mc, ph, qc), dg.dg_budgets(mf, ph, qf)
-    dg.dg_sphere_coarsen_project(mf, mc, qf, qc2)
+    dg.dg_sphere_coarsen_project(mf, mc, ph, qf, qc2)
     b2 = dg.dg_budgets(mc, ph, qc2)
     ref_us = _time_launches(torch, lambda: dg.dg_sphere_refine_project(mc, mf, ph, qc, qf, scale=False), 10)
-    crs_us = _time_launches(torch, lambda: dg.dg_sphere_coarsen_project(mf, mc, qf, qc2), 10)
+    crs_us = _time_launches(torch, lambda: dg.dg_sphere_coarsen_project(mf, mc, ph, qf, qc2), 10)
     _, (vc, _) = dg.dg_sphere_volumes(mc)
     _, (vf, ve) = dg.dg_sphere_volumes(mf)
     byt = 40.0 * (mc.K + mf.K) * mc.Np      # one read of the source, one write of the target
@@ -502,6 +502,120 @@ def acoustic_wave(dg, torch, N=4, n=12, nz=1, dt=0.9, hours=18.0):
             "antipode_zero_crossing_h": None if t_zero is None else t_zero / 3600.0,
             "pi_r_e_over_c_h": math.pi * r_e / c / 3600.0, "c_m_s": c,
             "mass_rel_change": (b1[1] - b0[1]) / b0[1], "energy_rel_change": (b1[3] - b0[3]) / abs(b0[3])}
+
+
+def _acoustic_state(dg, torch, m, ph, xyz):
+    """section 4.4's acoustic initial state without gravity (uniform 300 K
+    background): P' = bell(100 Pa, r_e/3) x sin(pi h / H), theta unperturbed"""
+    import math
+    r = torch.sqrt(xyz[0] ** 2 + xyz[1] ** 2 + xyz[2] ** 2)
+    r_e, H, R, T0, P0 = 6.371e6, 1.0e4, ph.cp - ph.cv, ph.theta0, ph.P0
+    gam = ph.cp / ph.cv
+    dist = r_e * torch.arccos(torch.clamp(xyz[0] / r, -1.0, 1.0))
+    r_c = r_e / 3.0
+    f = torch.where(dist <= r_c, 50.0 * (1.0 + torch.cos(math.pi * dist / r_c)), torch.zeros_like(dist))
+    pp = f * torch.sin(math.pi * (r - r_e) / H)
+    q = m.field()
+    q[4] = (P0 / R) * ((P0 + pp) / P0) ** (1.0 / gam) - P0 / R
+    q[0] = q[4] / T0
+    return q
+
+
+def acoustic_wave_adaptive(dg, torch, N=4, n=12, nz=1, dt=0.45, hours=18.0, thr=5.0, regrid_h=1.0, seg=100):
+    """Section 4.4's acoustic wave with adaptation: the 6 x n x n x nz shell may
+    refine once (max_level 1; the oct-tree splits the layer too), regridded every
+    hour on |P'| > thr (the pressure-perturbation criterion), steps between regrids
+    replayed as HIP graphs of `seg` steps; no gravity (the paper's two-dimensional
+    shallow-atmosphere problem).  Reports the antipode pulse's zero crossing against
+    pi r_e / c, the leaf counts, and the total mass and energy change over the run,
+    regrids included (the shell transfers keep the J W quadrature of the mass)."""
+    import math
+    ph = dg.PhysParams(background=dg.DG_BG_ISOTHERMAL, g=0.0)
+    m = dg.dg_sphere_mesh_build(N, n, nz, max_level=1)
+    xyz = torch.empty(3, m.K, m.Np, dtype=torch.float64, device="cuda")
+    dg.dg_node_coords(m, xyz)
+    q = _acoustic_state(dg, torch, m, ph, xyz)
+    fl = dg.dg_indicator(m, ph, q, dg.DG_IND_PPRIME, thr)
+    fl[fl < 0] = 0
+    m = dg.dg_mesh_build(prev=m, flags=fl, pass_=dg.DG_PASS_REFINE)
+    m.prev = None
+    xyz = torch.empty(3, m.K, m.Np, dtype=torch.float64, device="cuda")
+    dg.dg_node_coords(m, xyz)
+    q = _acoustic_state(dg, torch, m, ph, xyz)
+    b0 = dg.dg_budgets(m, ph, q)
+    R, P0, gam = ph.cp - ph.cv, ph.P0, ph.cp / ph.cv
+    per_regrid = int(round(regrid_h * 3600.0 / dt)) // seg
+    sample_every = max(1, int(round(270.0 / (seg * dt))))
+    times, vals, leaves = [], [], [m.K]
+    t, steps = 0.0, 0
+    t0 = time.perf_counter()
+    nreg = int(round(hours / regrid_h))
+    for c in range(nreg):
+        if c > 0:
+            m2, q = dg.adapt_cycle(m, ph, q, dg.DG_IND_PPRIME, thr)
+            m2.prev = None
+            m = m2
+            leaves.append(m.K)
+        xyz = torch.empty(3, m.K, m.Np, dtype=torch.float64, device="cuda")
+        dg.dg_node_coords(m, xyz)
+        r = torch.sqrt(xyz[0] ** 2 + xyz[1] ** 2 + xyz[2] ** 2)
+        anti = 6.371e6 * torch.arccos(torch.clamp(-xyz[0] / r, -1.0, 1.0)) <= 3.0e5
+        idx = torch.nonzero(anti.reshape(-1)).reshape(-1)
+        del xyz, r, anti
+        g = dg.GraphedSteps(m, ph, dt, q, seg)
+        for k in range(per_regrid):
+            g.replay()
+            t += seg * dt
+            steps += seg
+            if t >= 14.0 * 3600.0 and (k + 1) % sample_every == 0:
+                thp = g.q[4].reshape(-1)[idx]
+                times.append(t)
+                vals.append(float((P0 * ((R * (P0 / R + thp) / P0) ** gam - 1.0)).mean()))
+        q = g.q
+        del g
+        _progress(f"adaptive acoustic wave: t = {t / 3600.0:.0f} h, {m.K} leaves")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b1 = dg.dg_budgets(m, ph, q)
+    i_max = max(range(len(vals)), key=lambda i: vals[i]) if vals else 0
+    j = next((k for k in range(i_max, len(vals)) if vals[k] < 0.0), None)
+    t_zero = None if j is None or j == 0 else times[j - 1] + (times[j] - times[j - 1]) * vals[j - 1] / (
+        vals[j - 1] - vals[j])
+    c = math.sqrt(gam * R * ph.theta0)
+    return {"workload": f"cubed-sphere shell 6 x {n} x {n} x {nz}, N={N}, max_level 1, regrid every {regrid_h} h on "
+                        f"|P'| > {thr} Pa, no gravity, 300 K, bell 100 Pa, SSP-RK3 dt={dt} s, {hours} h",
+            "steps": steps, "regrids": nreg - 1, "leaves_min_max": [min(leaves), max(leaves)], "wall_s": wall,
+            "antipode_max_Pa": max(vals) if vals else None,
+            "antipode_zero_crossing_h": None if t_zero is None else t_zero / 3600.0,
+            "pi_r_e_over_c_h": math.pi * 6.371e6 / c / 3600.0,
+            "mass_rel_change": (b1[1] - b0[1]) / b0[1], "energy_rel_change": (b1[3] - b0[3]) / abs(b0[3])}
+
+
+def sphere_shell_refined(dg, torch, N=4, n=24, nz=8, dt=0.05, thr=20.0):
+    """The shell of sphere_shell refined once where the acoustic state's |P'| exceeds
+    thr (section 4.4's regrid criterion; no gravity): stage duration with the mortar
+    pre-pass of the hanging faces, and its HBM fraction at the shell's bytes per node."""
+    ph = dg.PhysParams(background=dg.DG_BG_ISOTHERMAL, g=0.0)
+    m = dg.dg_sphere_mesh_build(N, n, nz, max_level=1)
+    xyz = torch.empty(3, m.K, m.Np, dtype=torch.float64, device="cuda")
+    dg.dg_node_coords(m, xyz)
+    q = _acoustic_state(dg, torch, m, ph, xyz)
+    fl = dg.dg_indicator(m, ph, q, dg.DG_IND_PPRIME, thr)
+    fl[fl < 0] = 0
+    mr = dg.dg_mesh_build(prev=m, flags=fl, pass_=dg.DG_PASS_REFINE)
+    qr = mr.field()
+    dg.dg_sphere_adapt_project(m, mr, ph, q, qr)
+    del xyz, q
+    qs, q1 = torch.empty_like(qr), torch.empty_like(qr)
+    dg.dg_rk_stage(mr, ph, 0.0, 1.0, dt, qr, qr, qs)
+    st_us = _time_launches(torch, lambda: dg.dg_rk_stage(mr, ph, 0.75, 0.25, dt, qr, qs, q1), 20)
+    nodes = mr.K * mr.Np
+    bpn = sphere_bytes_per_node(N)
+    return {"workload": f"cubed-sphere shell 6 x {n} x {n} x {nz}, N={N}, refined once where |P'| > {thr} Pa of the "
+                        "acoustic state, no gravity",
+            "leaves": mr.K, "hanging_faces": mr.info.n_hang, "nodes": nodes,
+            "kernels": "k_mortar_sphere<4> + k_stage_sphere<4, 1>", "stage_us": st_us, "bytes_per_node": bpn,
+            "frac_hbm": nodes * bpn / (st_us * 1e-6) / 1e9 / HBM_PEAK_GBS}
 
 
 def budget_drift(dg, torch, mesh, q, ph, dt, steps=10):
@@ -666,6 +780,10 @@ def extras(dg, torch, mesh, q, ph, args):
     out["sphere_shell_transfers"] = shell_transfers(dg, torch)
     _progress("extras: acoustic wave on the shell")
     out["sphere_acoustic_wave"] = acoustic_wave(dg, torch)
+    _progress("extras: refined shell")
+    out["sphere_shell_refined"] = sphere_shell_refined(dg, torch)
+    _progress("extras: adaptive acoustic wave on the shell")
+    out["sphere_acoustic_wave_adaptive"] = acoustic_wave_adaptive(dg, torch)
     _progress("extras: long run")
     out["rtb_long_run"] = rtb_long_run(dg, torch, t_end=args.rtb_seconds)
     # ---- measured copy bandwidth (1 GiB device-to-device) beside the 8 TB/s spec
