@@ -48,140 +48,199 @@ __device__ __forceinline__ void flux_normal(const double q[5], const Bg& b, doub
     lam = fabs(un) + sqrt_pos(gamma * (b.P + Pp) * rinv);
 }
 
+// The shell's stage, one workgroup per element, one thread per node.  (1) One batch
+// of loads: the tile into LDS, J, the first metric row, and for the thread's face
+// items the face geometry and the neighbour's trace.  (2) Faces: every face node's
+// Rusanov flux along the face's unit normal, s F*/(J w_N), for conforming faces and
+// walls (both sides of a conforming face sit at the same height: one background);
+// hanging faces copy their full lifted term from the mortar pre-pass.  (3) Volume,
+// one reference direction d at a time in the LDS the tile used: the contravariant
+// flux G_d = J a^d . F at each node (the next direction's metric row in flight),
+// the contraction by lines (one task per variable and line reads the line's fluxes
+// once and writes the N+1 sums D G along it in place; D from the uniform operator
+// table), each node adding -(1/J) times its own sum; a node on a conforming or wall
+// face of axis d also adds sgn G_d/(J w_N), the own-flux part of that face's term.
+// Radial buoyancy -rho' g r_hat.
 template <int N, int MODE>
 __global__ void __launch_bounds__(Sz<N>::NT) k_stage_sphere(const SphereStageArgs A) {
     constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
-    __shared__ double sQ[5 * NP];
-    __shared__ double sF[15 * NP];  // [i][v][node]: J a^i . F
-    __shared__ double sS[30 * NF];  // [f][v][m]: lifted face terms
+    constexpr int ITEMS = (6 * NF + NT - 1) / NT;
+    __shared__ double sQ[5 * NP];   // the tile, then the contravariant flux of one direction
+    __shared__ double sS[30 * NF];  // [f][v][m]: s F*/(J w_N), or the pre-pass's full term
     __shared__ double sJ[NP];
-    __shared__ double sD[N1 * N1];
     const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
     const int32_t* const rec = A.srec + e * kStageRec;
     const int t = threadIdx.x;
     const int64_t K = A.K, KNP = K * NP, KN1 = K * N1;
     const double gamma = A.gamma;
     const int i = t % N1, j = (t / N1) % N1, k = t / NF;
-    for (int ii = t; ii < N1 * N1; ii += NT) sD[ii] = A.ops[ii];
+    const double wN = 2.0 / (N * (N + 1));  // the LGL end weight
     double q[5] = {0, 0, 0, 0, 0}, R[5] = {0, 0, 0, 0, 0};
-    double Jv = 1.0;
+    // one batch of loads: the tile, J, the first metric row, and for this thread's
+    // face items the face geometry and the neighbour's trace
+    double jr[3] = {0.0, 0.0, 0.0};
     if (t < NP) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) q[v] = A.qs[v * KNP + e * NP + t];
-        Jv = A.metric[e * NP + t];
-        double Ja[9];
+        for (int v = 0; v < 5; ++v) sQ[v * NP + t] = A.qs[v * KNP + e * NP + t];
+        sJ[t] = A.metric[e * NP + t];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) Ja[c] = A.metric[(1 + c) * KNP + e * NP + t];
-        const Bg b = bg_make(A.bg[e * N1 + k], A.bg[KN1 + e * N1 + k], A.bg[2 * KN1 + e * N1 + k]);
-        const double Pp = pprime(q[4], b.rTh, b.P, gamma, A.binom);
-        const double rinv = rcp_pos(b.rho + q[0]);
-        const double Th = b.Th + q[4];
-        double F[3][5];
+        for (int c = 0; c < 3; ++c) jr[c] = A.metric[(1 + c) * KNP + e * NP + t];
+    }
+    const int32_t packed = rec[18];
+    int f_[ITEMS], m_[ITEMS];
+    double qR_[ITEMS][5], nv_[ITEMS][4];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double uc = q[1 + c] * rinv;
-            F[c][0] = q[1 + c];
-            F[c][1] = c == 0 ? q[1] * uc + Pp : q[1] * uc;
-            F[c][2] = c == 1 ? q[2] * uc + Pp : q[2] * uc;
-            F[c][3] = c == 2 ? q[3] * uc + Pp : q[3] * uc;
-            F[c][4] = Th * uc;
+    for (int u = 0; u < ITEMS; ++u) {
+        const int it = t + u * NT;
+        f_[u] = -1;
+        if (it >= 6 * NF) continue;
+        const int f = it / NF, m = it - f * NF;
+        const int type = rec[f] & 0xff;
+        f_[u] = f;
+        m_[u] = m;
+        if (type == FT_FINE || type == FT_COARSE) continue;
+        const double* fg = A.fgeo + ((e * 6 + f) * NF + m) * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) nv_[u][c] = fg[c];
+        if (type != FT_WALL) {
+            const int64_t e2 = rec[6 + f];
+            const int f2 = (packed >> (4 * f)) & 7, flip = (packed >> (4 * f + 3)) & 1;
+            const int a = m % N1, bb = m / N1;
+            const int n2 = face_node<N>(f2, (flip ? N - a : a) + N1 * bb);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qR_[u][v] = A.qs[v * KNP + e2 * NP + n2];
         }
+    }
+    __syncthreads();
+
+    // ---- faces
+    {
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+        for (int u = 0; u < ITEMS; ++u) {
+            if (f_[u] < 0) continue;
+            const int f = f_[u], m = m_[u];
+            const int type = rec[f] & 0xff;
+            if (type == FT_FINE || type == FT_COARSE) {
+                // hanging face: the full lifted term from the mortar pre-pass
+                const int64_t row = (int64_t)rec[12 + f] * 5 + (type == FT_COARSE ? 0 : 1 + ((rec[f] >> 8) & 0xff));
 #pragma unroll
-            for (int v = 0; v < 5; ++v)
-                sF[(a * 5 + v) * NP + t] = Ja[a * 3 + 0] * F[0][v] + Ja[a * 3 + 1] * F[1][v] + Ja[a * 3 + 2] * F[2][v];
+                for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = A.mort[(row * 5 + v) * NF + m];
+                continue;
+            }
+            const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
+            double qL[5], qR[5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sQ[v * NP + t] = q[v];
-        sJ[t] = Jv;
-        // radial buoyancy -rho' g r_hat
+            for (int v = 0; v < 5; ++v) qL[v] = sQ[v * NP + n];
+            // both sides of a conforming face sit at the same height: one background
+            const Bg b = bg_make(A.bg[e * N1 + kk], A.bg[KN1 + e * N1 + kk], A.bg[2 * KN1 + e * N1 + kk]);
+            const double nv[3] = {nv_[u][0], nv_[u][1], nv_[u][2]};
+            if (type == FT_WALL) {
+                // mirror state: the normal momentum reversed
+                const double Un = qL[1] * nv[0] + qL[2] * nv[1] + qL[3] * nv[2];
+                qR[0] = qL[0];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) qR[1 + c] = qL[1 + c] - (2.0 * Un) * nv[c];
+                qR[4] = qL[4];
+            } else {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) qR[v] = qR_[u][v];
+            }
+            const double PpL = pprime(qL[4], b.rTh, b.P, gamma, A.binom);
+            const double PpR = pprime(qR[4], b.rTh, b.P, gamma, A.binom);
+            double FL[5], FR[5], lL, lR;
+            flux_normal(qL, b, PpL, nv, gamma, FL, lL);
+            flux_normal(qR, b, PpR, nv, gamma, FR, lR);
+            const double lam = fmax(lL, lR);
+            const double sface = nv_[u][3] / (sJ[n] * wN);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const double Fs = 0.5 * (FL[v] + FR[v]) + 0.5 * lam * (qL[v] - qR[v]);
+                sS[(f * 5 + v) * NF + m] = sface * Fs;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- volume, one direction at a time: G_d in sQ, the contraction by lines in place;
+    // G_d = J a^d . F = (U . Ja_d, U (u . Ja_d) + P' Ja_d, Theta u . Ja_d) with the
+    // metric row Ja_d read per direction
+    double Pp = 0.0, rinv = 0.0, Th = 0.0, Jv = 1.0;
+    if (t < NP) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) q[v] = sQ[v * NP + t];  // the tile, before the fluxes overwrite it
+        Jv = sJ[t];
+        const Bg b = bg_make(A.bg[e * N1 + k], A.bg[KN1 + e * N1 + k], A.bg[2 * KN1 + e * N1 + k]);
+        Pp = pprime(q[4], b.rTh, b.P, gamma, A.binom);
+        rinv = rcp_pos(b.rho + q[0]);
+        Th = b.Th + q[4];
+    }
+    const int ids[3] = {i, j, k};
+    double div[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double G[5];
+        if (t < NP) {
+            const double j0 = jr[0], j1 = jr[1], j2 = jr[2];
+            if (d < 2)  // the next direction's metric row, in flight across this direction's passes
+#pragma unroll
+                for (int c = 0; c < 3; ++c) jr[c] = A.metric[(1 + 3 * (d + 1) + c) * KNP + e * NP + t];
+            const double un = (q[1] * rinv) * j0 + (q[2] * rinv) * j1 + (q[3] * rinv) * j2;
+            G[0] = q[1] * j0 + q[2] * j1 + q[3] * j2;
+            G[1] = q[1] * un + Pp * j0;
+            G[2] = q[2] * un + Pp * j1;
+            G[3] = q[3] * un + Pp * j2;
+            G[4] = Th * un;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sQ[v * NP + t] = G[v];
+        }
+        __syncthreads();
+        const int stride = d == 0 ? 1 : d == 1 ? N1 : NF;
+        for (int task = t; task < 5 * NF; task += NT) {
+            const int v = task / NF, l = task - v * NF;
+            const int base = d == 0 ? N1 * l : d == 1 ? (l % N1) + NF * (l / N1) : l;
+            double* const Gl = sQ + v * NP + base;
+            double g[N1];
+#pragma unroll
+            for (int mm = 0; mm < N1; ++mm) g[mm] = Gl[mm * stride];
+#pragma unroll
+            for (int o = 0; o < N1; ++o) {
+                double acc = 0.0;
+#pragma unroll
+                for (int mm = 0; mm < N1; ++mm) acc = fma(A.ops[o * N1 + mm], g[mm], acc);
+                Gl[o * stride] = acc;
+            }
+        }
+        __syncthreads();
+        if (t < NP) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) div[v] = div[v] + sQ[v * NP + t];
+            // the own-flux part of a conforming or wall face of axis d at this node
+            if (ids[d] == 0 || ids[d] == N) {
+                const int f = 2 * d + (ids[d] == N ? 1 : 0);
+                const int type = rec[f] & 0xff;
+                if (type != FT_FINE && type != FT_COARSE) {
+                    const double sg = (f & 1) ? 1.0 : -1.0;
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) R[v] = R[v] + (sg * G[v]) / (Jv * wN);
+                }
+            }
+        }
+        __syncthreads();  // every node has read its sums before the next direction's fluxes
+    }
+    if (t >= NP) return;
+    // radial buoyancy -rho' g r_hat
+    {
         double cp[3];
         panel_point(rec[19], A.c1d[e * N1 + i], A.c1d[KN1 + e * N1 + j], cp);
         const double nrm = sqrt(cp[0] * cp[0] + cp[1] * cp[1] + cp[2] * cp[2]);
         const double gb = -q[0] * A.g;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) R[1 + c] = gb * (cp[c] / nrm);
-    }
-    __syncthreads();
-
-    // ---- faces: s F*(n) - sgn J a^d . F(q-), divided by J w_N at the face node
-    const double wN = 2.0 / (N * (N + 1));  // the LGL end weight
-    const int32_t packed = rec[18];
-    for (int it = t; it < 6 * NF; it += NT) {
-        const int f = it / NF, m = it % NF, d = f >> 1;
-        const int type = rec[f] & 0xff;
-        if (type == FT_FINE || type == FT_COARSE) {
-            // hanging face: the lifted term from the mortar pre-pass
-            const int64_t row = (int64_t)rec[12 + f] * 5 + (type == FT_COARSE ? 0 : 1 + ((rec[f] >> 8) & 0xff));
-#pragma unroll
-            for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = A.mort[(row * 5 + v) * NF + m];
-            continue;
-        }
-        const double sgn = (f & 1) ? 1.0 : -1.0;
-        const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
-        double qL[5], qR[5];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) qL[v] = sQ[v * NP + n];
-        const Bg bL = bg_make(A.bg[e * N1 + kk], A.bg[KN1 + e * N1 + kk], A.bg[2 * KN1 + e * N1 + kk]);
-        const double* fg = A.fgeo + ((e * 6 + f) * NF + m) * 4;
-        const double nv[3] = {fg[0], fg[1], fg[2]};
-        const double sface = fg[3];
-        Bg bR = bL;
-        if (type == FT_WALL) {
-            // mirror state: the normal momentum reversed
-            const double Un = qL[1] * nv[0] + qL[2] * nv[1] + qL[3] * nv[2];
-            qR[0] = qL[0];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) qR[1 + c] = qL[1 + c] - (2.0 * Un) * nv[c];
-            qR[4] = qL[4];
-        } else {
-            const int64_t e2 = rec[6 + f];
-            const int f2 = (packed >> (4 * f)) & 7, flip = (packed >> (4 * f + 3)) & 1;
-            const int a = m % N1, bb = m / N1;
-            const int m2 = (flip ? N - a : a) + N1 * bb;
-            const int n2 = face_node<N>(f2, m2), k2 = face_k<N>(f2, m2);
-#pragma unroll
-            for (int v = 0; v < 5; ++v) qR[v] = A.qs[v * KNP + e2 * NP + n2];
-            bR = bg_make(A.bg[e2 * N1 + k2], A.bg[KN1 + e2 * N1 + k2], A.bg[2 * KN1 + e2 * N1 + k2]);
-        }
-        const double PpL = pprime(qL[4], bL.rTh, bL.P, gamma, A.binom);
-        const double PpR = pprime(qR[4], bR.rTh, bR.P, gamma, A.binom);
-        double FL[5], FR[5], lL, lR;
-        flux_normal(qL, bL, PpL, nv, gamma, FL, lL);
-        flux_normal(qR, bR, PpR, nv, gamma, FR, lR);
-        const double lam = fmax(lL, lR);
-        const double JwN = sJ[n] * wN;
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            const double Fs = 0.5 * (FL[v] + FR[v]) + 0.5 * lam * (qL[v] - qR[v]);
-            const double delta = sface * Fs - sgn * sF[(d * 5 + v) * NP + n];
-            sS[(f * 5 + v) * NF + m] = delta / JwN;
-        }
-    }
-    __syncthreads();
-    if (t >= NP) return;
-
-    // ---- volume: -(1/J) sum_i D_i (J a^i . F), then the face terms at face nodes
-    double div[5] = {0, 0, 0, 0, 0};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const int id = d == 0 ? i : d == 1 ? j : k;
-        const int stride = d == 0 ? 1 : d == 1 ? N1 : NF;
-        const int base = t - id * stride;
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            const double* Fp = sF + (d * 5 + v) * NP + base;
-            double acc = 0.0;
-#pragma unroll
-            for (int mm = 0; mm < N1; ++mm) acc = fma(sD[id * N1 + mm], Fp[mm * stride], acc);
-            div[v] = div[v] + acc;
-        }
+        for (int c = 0; c < 3; ++c) R[1 + c] = R[1 + c] + gb * (cp[c] / nrm);
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) R[v] = -div[v] / Jv + R[v];
     // a node lies on at most one face per axis
     const int fm[3] = {j + N1 * k, i + N1 * k, i + N1 * j};
-    const int ids[3] = {i, j, k};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         if (ids[d] == 0 || ids[d] == N) {
