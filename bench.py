@@ -53,10 +53,10 @@ BUBBLE = dict(N=7, nroot=(8, 8, 8), L=2, lo=(0.0, 0.0, 0.0), hi=(1000.0, 1000.0,
 # for the kernel and forest sources they were taken on (SHA-256 below); otherwise
 # traffic is reported as null.  Not measured by the run that prints the line.
 TRAFFIC = {
-    "sources_sha256": "4b57c628a5461653bbd15aa43118f3f7787fa8bb538adfbaaa70b6d417c6bda4",
-    "fetch_scale": 1048576.0 / 524299.5,  # 1 GiB copy: FETCH_SIZE reads 524299.5 KiB
+    "sources_sha256": "4d4b2b55d3d9984df242428652782397fa1b15fb27c30bf6b094a015fa401fc6",
+    "fetch_scale": 1048576.0 / 524300.5,  # 1 GiB copy: FETCH_SIZE reads 524300.5 KiB
     "write_scale": 1048576.0 / 1048576.0,  # 1 GiB copy: WRITE_SIZE reads 1048576.0 KiB
-    "density_current": {"fetch_kib": 132938.1, "write_kib": 128849.0},
+    "density_current": {"fetch_kib": 130905.5, "write_kib": 128961.0},
     "source": "profiles/k_stage_density_current_N4_traffic.md",
 }
 CSRC = os.path.join(ROOT, "paper_2404_16648_amd", "csrc")
@@ -106,6 +106,9 @@ def parse():
     ap.add_argument("--rtb-seconds", type=float, default=100.0,
                     help="simulated time of the rising-thermal-bubble long run in the extras (0: skip it; "
                          "counter passes skip it)")
+    ap.add_argument("--acoustic-hours", type=float, default=18.0,
+                    help="simulated hours of the two acoustic-wave runs on the shell in the extras (0: skip "
+                         "them; counter passes skip them)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run 4 plain device copies of MIB MiB each "
                          "(reference launches for the memory-traffic counters)")
@@ -779,11 +782,13 @@ def extras(dg, torch, mesh, q, ph, args):
     _progress("extras: shell transfers")
     out["sphere_shell_transfers"] = shell_transfers(dg, torch)
     _progress("extras: acoustic wave on the shell")
-    out["sphere_acoustic_wave"] = acoustic_wave(dg, torch)
+    out["sphere_acoustic_wave"] = (acoustic_wave(dg, torch, hours=args.acoustic_hours) if args.acoustic_hours > 0
+                                   else {"skipped": True})
     _progress("extras: refined shell")
     out["sphere_shell_refined"] = sphere_shell_refined(dg, torch)
     _progress("extras: adaptive acoustic wave on the shell")
-    out["sphere_acoustic_wave_adaptive"] = acoustic_wave_adaptive(dg, torch)
+    out["sphere_acoustic_wave_adaptive"] = (acoustic_wave_adaptive(dg, torch, hours=args.acoustic_hours)
+                                            if args.acoustic_hours > 0 else {"skipped": True})
     _progress("extras: long run")
     out["rtb_long_run"] = rtb_long_run(dg, torch, t_end=args.rtb_seconds)
     # ---- measured copy bandwidth (1 GiB device-to-device) beside the 8 TB/s spec
