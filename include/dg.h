@@ -204,8 +204,11 @@ dg_status dg_mesh_build(const dg_forest_desc* desc, const dg_mesh* prev, const i
  * the Riemann problem along the fine face's normal, the coarse side's flux
  * 4 s_f (-F*) per coarse reference area projected back), and dg_indicator (theta'
  * or P'), dg_pass_changes, dg_flags_after_coarsen, dg_flags_buffer and
- * dg_sphere_adapt_project accept them.  The adjoint, the tracer, the precision
- * split, viscosity and pointwise matching return DG_EUNSUPPORTED.  N = 2..5.
+ * dg_sphere_adapt_project accept them.  dg_rhs_adjoint and dg_rk_stage_adjoint
+ * accept shells in float64: the transpose of the curvilinear right-hand side,
+ * with the curved mortars transposed in their own pre-pass.  The tracer, the
+ * precision split, viscosity and pointwise matching return DG_EUNSUPPORTED (the
+ * adjoint's too).  N = 2..5.
  * DG_EINVAL on bad sizes. */
 dg_status dg_sphere_mesh_build(const dg_sphere_desc* desc, dg_mesh** out);
 /* Face connectivity of a shell mesh (not in the paper): nb[K][6][3] (host,

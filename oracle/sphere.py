@@ -841,6 +841,20 @@ def acoustic_state(op: SphereOperator, h_max=100.0, r_c=None, lon=0.0, lat=0.0, 
     return q
 
 
+def vortex_state(op: SphereOperator, amp=1.0, width=5.0e5, lon=0.0, lat=0.0):
+    """A Gaussian potential-temperature perturbation theta' = amp exp(-(d / width)^2),
+    d the great-circle distance from longitude lon, latitude lat (radians), at
+    unperturbed density (rho' = 0, Theta' = rhobar theta'), at rest.  Returns the
+    state [5, K, N+1, N+1, N+1]."""
+    d, geo = op.mesh.desc, op.geo
+    cx = (math.cos(lat) * math.cos(lon), math.cos(lat) * math.sin(lon), math.sin(lat))
+    cosang = geo.rhat[0] * cx[0] + geo.rhat[1] * cx[1] + geo.rhat[2] * cx[2]
+    dist = d.r_e * torch.arccos(torch.clamp(cosang, -1.0, 1.0))
+    q = torch.zeros(5, *dist.shape, dtype=F64)
+    q[4] = op.bg[0] * (amp * torch.exp(-(dist / width) ** 2))
+    return q
+
+
 # ----------------------------------------------------------------------------- transfers of a refinement pass (section 3.4)
 
 def _subset_mass(op: SphereOperator, q, elems):

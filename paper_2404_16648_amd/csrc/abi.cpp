@@ -1008,7 +1008,6 @@ dg_status dg_tracer_mass(const dg_mesh* mc, const double* c, double* out_host, v
 static dg_status adjoint_common(const dg_mesh* mc, const dg_phys* phys, int mode, double a1, const double* w1,
                                 double a2, const double* w2, double b, double dt, const double* q, const double* lam,
                                 double* out, void* stream) {
-    if (dg_status st0 = no_sphere(mc)) return st0;
     dg_status st = check_dev_mesh(mc, (hipStream_t)stream);
     if (st) return st;
     if ((st = check_phys(phys))) return st;
@@ -1022,6 +1021,20 @@ static dg_status adjoint_common(const dg_mesh* mc, const dg_phys* phys, int mode
     dg_mesh* m = const_cast<dg_mesh*>(mc);
     hipStream_t s = (hipStream_t)stream;
     if ((st = ensure_bg(m, phys, s))) return st;
+    if (m->h.sphere) {
+        if (phys->precision != DG_FP64) return fail(DG_EUNSUPPORTED, "the shell's adjoint runs in float64");
+        const int64_t K = (int64_t)m->h.leaves.size();
+        const double gamma = phys->cp / phys->cv;
+        if (m->n_hang) {
+            SphereMortAdjArgs ma{q, lam, m->d_mort, m->d_ops, m->d_bg, m->d_srec, m->d_hang, m->d_metric, m->d_fgeo,
+                                 m->n_hang, K, gamma, binom_coef(phys)};
+            HIP_TRY(launch_mortar_sphere_adjoint(m->h.desc.N, ma, s));
+        }
+        SphereAdjArgs sa{q, lam, w1, w2, out, m->d_ops, m->d_bg, m->d_c1d, m->d_srec, m->d_metric, m->d_fgeo,
+                         m->d_mort, K, a1, a2, b, dt, gamma, phys->g, binom_coef(phys)};
+        HIP_TRY(launch_adjoint_sphere(m->h.desc.N, mode, sa, s));
+        return DG_OK;
+    }
     AdjArgs a{};
     a.q = q;
     a.lam = lam;

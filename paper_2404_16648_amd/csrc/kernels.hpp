@@ -210,6 +210,47 @@ struct SphereMortArgs {
 };
 hipError_t launch_mortar_sphere(int N, const SphereMortArgs& a, hipStream_t s);
 
+// transposed shell stage: out = (dR/dq)^T lam (MODE_RHS) or a1 w1 + a2 w2 + b (lam +
+// dt (dR/dq)^T lam) (MODE_RK), R the shell's right-hand side at q
+struct SphereAdjArgs {
+    const double* q;
+    const double* lam;
+    const double* w1;
+    const double* w2;
+    double* out;
+    const double* ops;     // D first
+    const double* bg;
+    const double* c1d;
+    const int32_t* srec;
+    const double* metric;
+    const double* fgeo;
+    const double* mort;    // [n_hang][5][5][NF]: the transposed mortar pre-pass output, or null
+    int64_t K;
+    double a1, a2, b, dt;
+    double gamma, g;
+    BinomCoef binom;
+};
+hipError_t launch_adjoint_sphere(int N, int mode, const SphereAdjArgs& a, hipStream_t s);
+
+// transposed mortar pre-pass of the shell: per hanging row the contributions of the
+// row's mortar terms to qbar at the coarse face (slot 0) and the four fine faces
+// (slots 1..4), each in its own face's node order
+struct SphereMortAdjArgs {
+    const double* q;
+    const double* lam;
+    double* mort;
+    const double* ops;
+    const double* bg;
+    const int32_t* srec;
+    const int32_t* hang;
+    const double* metric;
+    const double* fgeo;
+    int64_t n_hang, K;
+    double gamma;
+    BinomCoef binom;
+};
+hipError_t launch_mortar_sphere_adjoint(int N, const SphereMortAdjArgs& a, hipStream_t s);
+
 // transfers of a shell's refine or coarsen pass along the plan (src, kind) of the
 // target mesh: copies, children by reference interpolation, families by the
 // reference projections plus the constant that keeps their J W integrals

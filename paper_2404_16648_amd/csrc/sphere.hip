@@ -351,6 +351,7 @@ __global__ void __launch_bounds__(MortSz<N>::NT) k_mortar_sphere(const SphereMor
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
             double acc = 0.0;
+            #pragma unroll 1
             for (int a = 0; a < N1; ++a) {
                 double tb = 0.0;
                 for (int b = 0; b < N1; ++b) tb = fma(Ib[b2 * N1 + b], sTc[v * NF + a + N1 * b], tb);
@@ -392,6 +393,7 @@ __global__ void __launch_bounds__(MortSz<N>::NT) k_mortar_sphere(const SphereMor
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 double acc = 0.0;
+                #pragma unroll 1
                 for (int a2 = 0; a2 < N1; ++a2) {
                     double tb = 0.0;
                     for (int b2 = 0; b2 < N1; ++b2) tb = fma(Rb[b * N1 + b2], sG[(quad * 5 + v) * NF + a2 + N1 * b2], tb);
@@ -411,6 +413,428 @@ __global__ void __launch_bounds__(MortSz<N>::NT) k_mortar_sphere(const SphereMor
         const double JwN = A.metric[ec * NP + nc] * wN;
 #pragma unroll
         for (int v = 0; v < 5; ++v) A.mort[((h * 5 + 0) * 5 + v) * NF + t] = (proj[v] - sgn * Fc[v]) / JwN;
+    }
+}
+
+// ---------------------------------------------------------------- adjoint (transpose of the shell stage)
+
+// g += J^T a for the flux along the vector m at a node, F.m = (U.m, U (u.m) + P' m,
+// Theta u.m) with u = U / rho (m a unit normal, or a metric row J a^d); rinv = 1/rho,
+// Th = Thetabar + Theta', dPdT = dP'/dTheta' = gamma P / Th
+__device__ __forceinline__ void flux_along_vjp(const double q[5], double rinv, double Th, double dPdT,
+                                               const double m[3], const double a[5], double g[5]) {
+    const double un = (q[1] * m[0] + q[2] * m[1] + q[3] * m[2]) * rinv;
+    const double ubar = a[1] * q[1] + a[2] * q[2] + a[3] * q[3] + a[4] * Th;
+    const double am = a[1] * m[0] + a[2] * m[1] + a[3] * m[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[1 + c] += a[0] * m[c] + a[1 + c] * un + ubar * m[c] * rinv;
+    g[0] -= ubar * un * rinv;
+    g[4] += a[4] * un + am * dPdT;
+}
+
+// pointwise state along a unit normal n: 1/rho, Theta, dP'/dTheta', the wave speed
+// lam = |u.n| + c and its gradient (d lam/d U_c = dlamU n_c; d|x|/dx = 0 at x = 0)
+struct NormState {
+    double rinv, Th, dPdT, lam, dlam0, dlamU, dlam4;
+};
+
+__device__ __forceinline__ NormState norm_state(const double q[5], const Bg& b, double Pp, const double n[3],
+                                                double gamma) {
+    NormState s;
+    s.rinv = rcp_pos(b.rho + q[0]);
+    const double un = (q[1] * n[0] + q[2] * n[1] + q[3] * n[2]) * s.rinv;
+    s.Th = b.Th + q[4];
+    const double P = b.P + Pp;
+    s.dPdT = gamma * P / s.Th;
+    const double c = sqrt_pos(gamma * P * s.rinv);
+    const double au = fabs(un);
+    s.lam = au + c;
+    s.dlam0 = -(au + 0.5 * c) * s.rinv;
+    s.dlamU = (un > 0.0 ? 1.0 : (un < 0.0 ? -1.0 : 0.0)) * s.rinv;
+    s.dlam4 = 0.5 * gamma * c / s.Th;
+    return s;
+}
+
+// gL (and gR if non-null) = derivative of w . F*(qL, qR, n) with respect to qL (qR),
+// F* the Rusanov flux along the unit normal n with one background on both sides; a
+// max tie splits the derivative 1/2, 1/2
+__device__ __forceinline__ void rusanov_along_vjp(const double qL[5], double PpL, const double qR[5], double PpR,
+                                                  const Bg& b, const double n[3], double gamma, const double w[5],
+                                                  double gL[5], double* gR) {
+    const NormState L = norm_state(qL, b, PpL, n, gamma);
+    const NormState Rr = norm_state(qR, b, PpR, n, gamma);
+    const double hl = 0.5 * fmax(L.lam, Rr.lam);
+    const double tL = L.lam > Rr.lam ? 1.0 : (L.lam < Rr.lam ? 0.0 : 0.5);
+    double wj = 0.0, a[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        wj += w[v] * (qL[v] - qR[v]);
+        a[v] = 0.5 * w[v];
+        gL[v] = hl * w[v];
+    }
+    flux_along_vjp(qL, L.rinv, L.Th, L.dPdT, n, a, gL);
+    const double cL = 0.5 * wj * tL;
+    gL[0] += cL * L.dlam0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gL[1 + c] += cL * L.dlamU * n[c];
+    gL[4] += cL * L.dlam4;
+    if (gR) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) gR[v] = -hl * w[v];
+        flux_along_vjp(qR, Rr.rinv, Rr.Th, Rr.dPdT, n, a, gR);
+        const double cR = 0.5 * wj * (1.0 - tL);
+        gR[0] += cR * Rr.dlam0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gR[1 + c] += cR * Rr.dlamU * n[c];
+        gR[4] += cR * Rr.dlam4;
+    }
+}
+
+// g += the gradient of a . J a^d . F(q) at a node (the own-flux part of a face term)
+__device__ __forceinline__ void contravariant_flux_vjp(const double q[5], const Bg& b, double Pp,
+                                                       const double* metric, int64_t KNP, int64_t node, int d,
+                                                       double gamma, const double a[5], double g[5]) {
+    const double rinv = rcp_pos(b.rho + q[0]);
+    const double Th = b.Th + q[4];
+    const double dPdT = gamma * (b.P + Pp) / Th;
+    const double m[3] = {metric[(1 + 3 * d + 0) * KNP + node], metric[(1 + 3 * d + 1) * KNP + node],
+                         metric[(1 + 3 * d + 2) * KNP + node]};
+    flux_along_vjp(q, rinv, Th, dPdT, m, a, g);
+}
+
+// Transposed mortar pre-pass of the shell, one workgroup per hanging row.  With
+// mu_c = lam_c / (J w_N) on the coarse face, a mortar point of quadrant (qa, qb)
+// carries w . F*(q_f, q_m, n_f) of <lam, R>, w = s_f (4 ((R_qa x R_qb)^T mu_c) -
+// lam_f / (J_f w_N)): its gradient with respect to the fine state goes to the fine
+// face (slot 1 + quad, with the fine side's own-flux term sgn J a^d . F / (J w_N)),
+// its gradient with respect to the mortar state q_m = (I_qa x I_qb) q_c back to the
+// coarse face through (I_qa x I_qb)^T (slot 0, with the coarse side's own-flux term).
+template <int N>
+__global__ void __launch_bounds__(MortSz<N>::NT) k_mortar_sphere_adjoint(const SphereMortAdjArgs A) {
+    constexpr int N1 = N + 1, NP = N1 * N1 * N1, NF = N1 * N1, NT = MortSz<N>::NT;
+    // sTc: the coarse trace; sMu: mu_c; sG: per quadrant, first (R_qa x R_qb)^T mu_c,
+    // then the mortar-state gradient, at the fine points in the coarse face's axes
+    __shared__ double sTc[5 * NF], sMu[5 * NF], sG[20 * NF], sI[2 * NF], sR[2 * NF];
+    const int t = threadIdx.x;
+    const int64_t h = blockIdx.x;
+    const int32_t* row = A.hang + h * 6;
+    const int64_t ec = row[0];
+    const int fc = row[1];
+    const int32_t packed = A.srec[ec * kStageRec + 18];
+    const int ff = (packed >> (4 * fc)) & 7, flip = (packed >> (4 * fc + 3)) & 1;
+    const int64_t K = A.K, KNP = K * NP, KN1 = K * N1;
+    const double gamma = A.gamma;
+    const double wN = 2.0 / (N * (N + 1));
+    for (int x = t; x < 2 * NF; x += NT) {
+        sI[x] = A.ops[NF + x];      // I_0, I_1
+        sR[x] = A.ops[3 * NF + x];  // R_0, R_1
+    }
+    if (t < NF) {
+        const int n = face_node<N>(fc, t);
+        const double JwN = A.metric[ec * NP + n] * wN;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            sTc[v * NF + t] = A.q[v * KNP + ec * NP + n];
+            sMu[v * NF + t] = A.lam[v * KNP + ec * NP + n] / JwN;
+        }
+    }
+    // this thread's fine point: quadrant t / NF, node mf of the fine face
+    const int quad = t / NF, mf = t - quad * NF;
+    const int qa = quad & 1, qb = quad >> 1;
+    const int af = mf % N1, bf = mf / N1;
+    const int a2 = flip ? N - af : af, b2 = bf;  // the node in the coarse face's axes
+    double qf[5] = {0, 0, 0, 0, 0}, lf[5] = {0, 0, 0, 0, 0}, fg[4] = {0, 0, 0, 1};
+    double JwNf = 1.0;
+    int64_t ef = 0;
+    int nf = 0, kf = 0;
+    if (t < 4 * NF) {
+        ef = row[2 + quad];
+        nf = face_node<N>(ff, mf);
+        kf = face_k<N>(ff, mf);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            qf[v] = A.q[v * KNP + ef * NP + nf];
+            lf[v] = A.lam[v * KNP + ef * NP + nf];
+        }
+        const double* g4 = A.fgeo + ((ef * 6 + ff) * NF + mf) * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) fg[c] = g4[c];
+        JwNf = A.metric[ef * NP + nf] * wN;
+    }
+    __syncthreads();
+    double qm[5], rm[5];
+    if (t < 4 * NF) {
+        // q_m = (I_qa x I_qb) q_c and (R_qa x R_qb)^T mu_c at (a2, b2)
+        const double* Ia = sI + qa * NF;
+        const double* Ib = sI + qb * NF;
+        const double* Ra = sR + qa * NF;
+        const double* Rb = sR + qb * NF;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            double acc = 0.0, accr = 0.0;
+            #pragma unroll 1
+            for (int a = 0; a < N1; ++a) {
+                double tb = 0.0, tr = 0.0;
+                for (int b = 0; b < N1; ++b) {
+                    tb = fma(Ib[b2 * N1 + b], sTc[v * NF + a + N1 * b], tb);
+                    tr = fma(Rb[b * N1 + b2], sMu[v * NF + a + N1 * b], tr);
+                }
+                acc = fma(Ia[a2 * N1 + a], tb, acc);
+                accr = fma(Ra[a * N1 + a2], tr, accr);
+            }
+            qm[v] = acc;
+            rm[v] = accr;
+        }
+        const Bg b = bg_make(A.bg[ef * N1 + kf], A.bg[KN1 + ef * N1 + kf], A.bg[2 * KN1 + ef * N1 + kf]);
+        const double nv[3] = {fg[0], fg[1], fg[2]};
+        const double sf = fg[3];
+        const double PpF = pprime(qf[4], b.rTh, b.P, gamma, A.binom);
+        const double PpM = pprime(qm[4], b.rTh, b.P, gamma, A.binom);
+        double w[5], gF[5], gM[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) w[v] = sf * (4.0 * rm[v] - lf[v] / JwNf);
+        rusanov_along_vjp(qf, PpF, qm, PpM, b, nv, gamma, w, gF, gM);
+        // the fine side's own-flux term +sgn J a^d . F(q_f) / (J w_N)
+        const double sgn = (ff & 1) ? 1.0 : -1.0;
+        double ao[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) ao[v] = sgn * lf[v] / JwNf;
+        contravariant_flux_vjp(qf, b, PpF, A.metric, KNP, ef * NP + nf, ff >> 1, gamma, ao, gF);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            A.mort[((h * 5 + 1 + quad) * 5 + v) * NF + mf] = gF[v];
+            sG[(quad * 5 + v) * NF + a2 + N1 * b2] = gM[v];
+        }
+    }
+    __syncthreads();
+    if (t < NF) {
+        // back to the coarse face: sum over quadrants of (I_qa x I_qb)^T gM
+        const int a = t % N1, b = t / N1;
+        double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int qd = 0; qd < 4; ++qd) {
+            const double* Ia = sI + (qd & 1) * NF;
+            const double* Ib = sI + (qd >> 1) * NF;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                double acc = 0.0;
+                #pragma unroll 1
+                for (int x2 = 0; x2 < N1; ++x2) {
+                    double tb = 0.0;
+                    for (int y2 = 0; y2 < N1; ++y2) tb = fma(Ib[y2 * N1 + b], sG[(qd * 5 + v) * NF + x2 + N1 * y2], tb);
+                    acc = fma(Ia[x2 * N1 + a], tb, acc);
+                }
+                g[v] = g[v] + acc;
+            }
+        }
+        const int nc = face_node<N>(fc, t), kc = face_k<N>(fc, t);
+        double qc[5], ao[5];
+        const double sgn = (fc & 1) ? 1.0 : -1.0;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            qc[v] = sTc[v * NF + t];
+            ao[v] = sgn * sMu[v * NF + t];
+        }
+        const Bg bc = bg_make(A.bg[ec * N1 + kc], A.bg[KN1 + ec * N1 + kc], A.bg[2 * KN1 + ec * N1 + kc]);
+        const double Ppc = pprime(qc[4], bc.rTh, bc.P, gamma, A.binom);
+        contravariant_flux_vjp(qc, bc, Ppc, A.metric, KNP, ec * NP + nc, fc >> 1, gamma, ao, g);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) A.mort[((h * 5 + 0) * 5 + v) * NF + t] = g[v];
+    }
+}
+
+// The transposed shell stage, one workgroup per element, one thread per node: with
+// mu = -lam / J, (1) faces: at each conforming face node the Rusanov VJP with weight
+// w = -s_L lam_L + s_R lam_R (s = face Jacobian / (J w_N) on each side: the
+// neighbour's term at its node is +s_R F*(qL, qR, n) by antisymmetry), at a wall the
+// VJP through the mirror state, at a hanging face the transposed pre-pass's
+// contribution; (2) volume: for each reference direction d the transposed
+// contraction Gbar_d = D_d^T mu (plus sgn lam / (J w_N) at the nodes of a conforming
+// or wall face of axis d, the own-flux part) and the chain rule through G_d = J a^d.F;
+// (3) buoyancy -rho' g r_hat transposed.
+template <int N, int MODE>
+__global__ void __launch_bounds__(Sz<N>::NT) k_adjoint_sphere(const SphereAdjArgs A) {
+    constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
+    constexpr int ITEMS = (6 * NF + NT - 1) / NT;
+    __shared__ double sQ[5 * NP];   // the tile
+    __shared__ double sMu[5 * NP];  // -lam / J
+    __shared__ double sS[30 * NF];  // [f][v][m]: the face contributions to qbar
+    __shared__ double sJ[NP];
+    const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
+    const int32_t* const rec = A.srec + e * kStageRec;
+    const int t = threadIdx.x;
+    const int64_t K = A.K, KNP = K * NP, KN1 = K * N1;
+    const double gamma = A.gamma;
+    const int i = t % N1, j = (t / N1) % N1, k = t / NF;
+    const double wN = 2.0 / (N * (N + 1));
+    double q[5] = {0, 0, 0, 0, 0}, lam[5] = {0, 0, 0, 0, 0};
+    if (t < NP) {
+        const double Jv = A.metric[e * NP + t];
+        sJ[t] = Jv;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            q[v] = A.q[v * KNP + e * NP + t];
+            lam[v] = A.lam[v * KNP + e * NP + t];
+            sQ[v * NP + t] = q[v];
+            sMu[v * NP + t] = -lam[v] / Jv;
+        }
+    }
+    // the face items' loads: face geometry, the neighbour's state, weights, face
+    // Jacobian and J at its node
+    const int32_t packed = rec[18];
+    int f_[ITEMS], m_[ITEMS];
+    double qR_[ITEMS][5], lR_[ITEMS][5], nv_[ITEMS][4], sR_[ITEMS];
+#pragma unroll
+    for (int u = 0; u < ITEMS; ++u) {
+        const int it = t + u * NT;
+        f_[u] = -1;
+        if (it >= 6 * NF) continue;
+        const int f = it / NF, m = it - f * NF;
+        const int type = rec[f] & 0xff;
+        f_[u] = f;
+        m_[u] = m;
+        if (type == FT_FINE || type == FT_COARSE) continue;
+        const double* fg = A.fgeo + ((e * 6 + f) * NF + m) * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) nv_[u][c] = fg[c];
+        if (type != FT_WALL) {
+            const int64_t e2 = rec[6 + f];
+            const int f2 = (packed >> (4 * f)) & 7, flip = (packed >> (4 * f + 3)) & 1;
+            const int a = m % N1, bb = m / N1;
+            const int m2 = (flip ? N - a : a) + N1 * bb;
+            const int n2 = face_node<N>(f2, m2);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                qR_[u][v] = A.q[v * KNP + e2 * NP + n2];
+                lR_[u][v] = A.lam[v * KNP + e2 * NP + n2];
+            }
+            sR_[u] = A.fgeo[((e2 * 6 + f2) * NF + m2) * 4 + 3] / (A.metric[e2 * NP + n2] * wN);
+        }
+    }
+    __syncthreads();
+
+    // ---- faces
+#pragma unroll
+    for (int u = 0; u < ITEMS; ++u) {
+        if (f_[u] < 0) continue;
+        const int f = f_[u], m = m_[u];
+        const int type = rec[f] & 0xff;
+        if (type == FT_FINE || type == FT_COARSE) {
+            const int64_t row = (int64_t)rec[12 + f] * 5 + (type == FT_COARSE ? 0 : 1 + ((rec[f] >> 8) & 0xff));
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = A.mort[(row * 5 + v) * NF + m];
+            continue;
+        }
+        const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
+        double qL[5], qR[5], w[5], g[5];
+        const double nv[3] = {nv_[u][0], nv_[u][1], nv_[u][2]};
+        // -s_L lam_L = face Jacobian * mu_L / w_N
+        const double cL = nv_[u][3] / wN;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            qL[v] = sQ[v * NP + n];
+            w[v] = cL * sMu[v * NP + n];
+        }
+        const Bg b = bg_make(A.bg[e * N1 + kk], A.bg[KN1 + e * N1 + kk], A.bg[2 * KN1 + e * N1 + kk]);
+        const double PpL = pprime(qL[4], b.rTh, b.P, gamma, A.binom);
+        if (type == FT_WALL) {
+            // qR = M qL, M reverses the normal momentum (symmetric: M^T = M)
+            const double Un = qL[1] * nv[0] + qL[2] * nv[1] + qL[3] * nv[2];
+            qR[0] = qL[0];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) qR[1 + c] = qL[1 + c] - (2.0 * Un) * nv[c];
+            qR[4] = qL[4];
+            double gR[5];
+            rusanov_along_vjp(qL, PpL, qR, PpL, b, nv, gamma, w, g, gR);
+            const double gn = gR[1] * nv[0] + gR[2] * nv[1] + gR[3] * nv[2];
+            g[0] += gR[0];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) g[1 + c] += gR[1 + c] - (2.0 * gn) * nv[c];
+            g[4] += gR[4];
+        } else {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                qR[v] = qR_[u][v];
+                w[v] = fma(sR_[u], lR_[u][v], w[v]);
+            }
+            const double PpR = pprime(qR[4], b.rTh, b.P, gamma, A.binom);
+            rusanov_along_vjp(qL, PpL, qR, PpR, b, nv, gamma, w, g, nullptr);
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sS[(f * 5 + v) * NF + m] = g[v];
+    }
+    __syncthreads();
+
+    if (t >= NP) return;
+    // ---- volume: Gbar_d = D_d^T mu (+ the own-flux part), then the chain rule through
+    // G_d = J a^d . F
+    double g[5] = {0, 0, 0, 0, 0};
+    {
+        const Bg b = bg_make(A.bg[e * N1 + k], A.bg[KN1 + e * N1 + k], A.bg[2 * KN1 + e * N1 + k]);
+        const double Pp = pprime(q[4], b.rTh, b.P, gamma, A.binom);
+        const double rinv = rcp_pos(b.rho + q[0]);
+        const double Th = b.Th + q[4];
+        const double dPdT = gamma * (b.P + Pp) / Th;
+        const double Jv = sJ[t];
+        const int ids[3] = {i, j, k};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int id = ids[d];
+            const int stride = d == 0 ? 1 : d == 1 ? N1 : NF;
+            const int base = t - id * stride;
+            double a[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const double* Mu = sMu + v * NP + base;
+                double acc = 0.0;
+#pragma unroll
+                for (int o = 0; o < N1; ++o) acc = fma(A.ops[o * N1 + id], Mu[o * stride], acc);
+                a[v] = acc;
+            }
+            if (id == 0 || id == N) {
+                const int f = 2 * d + (id == N ? 1 : 0);
+                const int type = rec[f] & 0xff;
+                if (type != FT_FINE && type != FT_COARSE) {
+                    const double sg = (f & 1) ? 1.0 : -1.0;
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) a[v] += (sg * lam[v]) / (Jv * wN);
+                }
+            }
+            const double m[3] = {A.metric[(1 + 3 * d + 0) * KNP + e * NP + t],
+                                 A.metric[(1 + 3 * d + 1) * KNP + e * NP + t],
+                                 A.metric[(1 + 3 * d + 2) * KNP + e * NP + t]};
+            flux_along_vjp(q, rinv, Th, dPdT, m, a, g);
+        }
+    }
+    // ---- buoyancy -rho' g r_hat on the momentum
+    {
+        double cp[3];
+        panel_point(rec[19], A.c1d[e * N1 + i], A.c1d[KN1 + e * N1 + j], cp);
+        const double nrm = sqrt(cp[0] * cp[0] + cp[1] * cp[1] + cp[2] * cp[2]);
+        g[0] -= A.g * (lam[1] * (cp[0] / nrm) + lam[2] * (cp[1] / nrm) + lam[3] * (cp[2] / nrm));
+    }
+    // ---- the faces that touch this node (at most one per axis)
+    const int fm[3] = {j + N1 * k, i + N1 * k, i + N1 * j};
+    const int ids[3] = {i, j, k};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (ids[d] == 0 || ids[d] == N) {
+            const int f = 2 * d + (ids[d] == N ? 1 : 0);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) g[v] += sS[(f * 5 + v) * NF + fm[d]];
+        }
+    }
+    const int64_t base = e * NP + t;
+    if (MODE == MODE_RHS) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) A.out[v * KNP + base] = g[v];
+    } else {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            double o = A.b * fma(A.dt, g[v], lam[v]);
+            if (A.a1 != 0.0) o = fma(A.a1, A.w1[v * KNP + base], o);
+            if (A.a2 != 0.0) o = fma(A.a2, A.w2[v * KNP + base], o);
+            A.out[v * KNP + base] = o;
+        }
     }
 }
 
@@ -751,6 +1175,23 @@ hipError_t launch_shell_scale(int N, double* q, const double* bg, int64_t K, con
 hipError_t launch_mortar_sphere(int N, const SphereMortArgs& a, hipStream_t s) {
     if (a.n_hang <= 0) return hipSuccess;
     DG_DISPATCH_N(N, (k_mortar_sphere<NN><<<dim3((unsigned)a.n_hang), dim3(MortSz<NN>::NT), 0, s>>>(a)));
+    return hipGetLastError();
+}
+
+hipError_t launch_mortar_sphere_adjoint(int N, const SphereMortAdjArgs& a, hipStream_t s) {
+    if (a.n_hang <= 0) return hipSuccess;
+    DG_DISPATCH_N(N, (k_mortar_sphere_adjoint<NN><<<dim3((unsigned)a.n_hang), dim3(MortSz<NN>::NT), 0, s>>>(a)));
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_sphere(int N, int mode, const SphereAdjArgs& a, hipStream_t s) {
+    if (a.K <= 0) return hipSuccess;
+    const dim3 grid((unsigned)a.K);
+    if (mode == MODE_RHS) {
+        DG_DISPATCH_N(N, (k_adjoint_sphere<NN, MODE_RHS><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+    } else {
+        DG_DISPATCH_N(N, (k_adjoint_sphere<NN, MODE_RK><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+    }
     return hipGetLastError();
 }
 

@@ -99,7 +99,7 @@ def test_sphere_refusals():
     lm, _ = _meshes(3, 1, 1)
     q, r = lm.field(), lm.field()
     with pytest.raises(dg.DGError) as e:
-        dg.dg_rhs_adjoint(lm, PH, q, q.clone(), r)
+        dg.dg_rhs_adjoint(lm, dg.PhysParams(background=dg.DG_BG_ISOTHERMAL, precision=dg.DG_MIXED), q, q.clone(), r)
     assert e.value.code == dg.DG_EUNSUPPORTED
     with pytest.raises(dg.DGError) as e:
         dg.dg_rhs(lm, dg.PhysParams(background=dg.DG_BG_ISOTHERMAL, precision=dg.DG_MIXED), q, r)

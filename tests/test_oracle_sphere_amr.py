@@ -16,7 +16,10 @@ What the geometry and the definitions fix, independently of the code:
     at the right places);
   * the transfers of a refinement pass keep the total mass exactly, those of a
     coarsening pass keep every family's J W integral of every field exactly, and a
-    coarsening pass undoes a refinement pass on the leaves.
+    coarsening pass undoes a refinement pass on the leaves;
+  * the shell's discrete adjoint (reverse-mode derivative of the operator, hanging
+    faces included) agrees with central differences of the operator itself, and
+    the Gaussian theta vortex state has its stated amplitude, width and rest.
 Planted mistakes at the end: each must make one of these fail.
 """
 import math
@@ -218,6 +221,41 @@ def test_smooth_consistency_at_hanging_faces():
 
 def test_transfers_of_the_passes():
     check_adapt_transfers()
+
+
+def test_shell_adjoint_against_central_differences():
+    """<rhs_adjoint(q, lam), v> against <lam, (R(q + eps v) - R(q - eps v)) / (2 eps)>
+    on a refined shell with hanging faces: the transposed derivative the library's
+    shell adjoint is compared with, pinned by the operator alone"""
+    N = 2
+    m = sp.SphereMesh(sp.SphereDesc(N=N, n=1, nz=1, max_level=1))
+    m = sp.refine_pass(m, (np.arange(m.K) % 3 == 0).astype(np.int8))
+    assert len(m.hang) > 0
+    op = sp.SphereOperator(m, eu.Phys(), sp.BG_ISOTHERMAL)
+    shape = (5, m.K, N + 1, N + 1, N + 1)
+    q = torch.as_tensor(random_state(m.K, N, 31)).reshape(shape) * 0.1 + sp.vortex_state(op, width=2.0e6)
+    lam = torch.as_tensor(random_state(m.K, N, 32)).reshape(shape)
+    v = torch.as_tensor(random_state(m.K, N, 33)).reshape(shape)
+    ad = float((eu.rhs_adjoint(op, q, lam) * v).sum())
+    eps = 1e-5
+    fd = float((lam * (op.rhs(q + eps * v) - op.rhs(q - eps * v))).sum()) / (2 * eps)
+    assert abs(ad - fd) <= 1e-7 * abs(ad), (ad, fd)
+
+
+def test_vortex_state():
+    """theta' = Theta'/rhobar is 1 K times exp(-(d / w)^2) in the great-circle distance
+    d from the centre, rho' and the momentum vanish"""
+    m = sp.SphereMesh(sp.SphereDesc(N=3, n=4, nz=1))
+    op = sp.SphereOperator(m, eu.Phys(), sp.BG_ISOTHERMAL)
+    q = sp.vortex_state(op, amp=1.0, width=5.0e5, lon=0.5, lat=0.2)
+    assert float(q[:4].abs().max()) == 0.0
+    thp = q[4] / op.bg[0]
+    c = (math.cos(0.2) * math.cos(0.5), math.cos(0.2) * math.sin(0.5), math.sin(0.2))
+    x = [op.geo.x[k] / (6.371e6 + op.geo.height) for k in range(3)]
+    chord = torch.sqrt((x[0] - c[0]) ** 2 + (x[1] - c[1]) ** 2 + (x[2] - c[2]) ** 2)
+    d = 2.0 * 6.371e6 * torch.arcsin(0.5 * chord)
+    assert float((thp - torch.exp(-(d / 5.0e5) ** 2)).abs().max()) <= 1e-12
+    assert 0.0 < float(thp.max()) <= 1.0
 
 
 # ----------------------------------------------------------------------------- planted mistakes
