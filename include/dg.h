@@ -206,9 +206,12 @@ dg_status dg_mesh_build(const dg_forest_desc* desc, const dg_mesh* prev, const i
  * or P'), dg_pass_changes, dg_flags_after_coarsen, dg_flags_buffer and
  * dg_sphere_adapt_project accept them.  dg_rhs_adjoint and dg_rk_stage_adjoint
  * accept shells in float64: the transpose of the curvilinear right-hand side,
- * with the curved mortars transposed in their own pre-pass.  The tracer, the
- * precision split, viscosity and pointwise matching return DG_EUNSUPPORTED (the
- * adjoint's too).  N = 2..5.
+ * with the curved mortars transposed in their own pre-pass.  The precision
+ * split (DG_MIXED) runs the stage's line contractions in float32 (G_d minus its
+ * value at the element's first node, D in float32 high and low parts, float32
+ * accumulation; faces, mortars, metric terms and the update in float64).  The
+ * tracer, viscosity, pointwise matching and the mixed adjoint return
+ * DG_EUNSUPPORTED.  N = 2..5.
  * DG_EINVAL on bad sizes. */
 dg_status dg_sphere_mesh_build(const dg_sphere_desc* desc, dg_mesh** out);
 /* Face connectivity of a shell mesh (not in the paper): nb[K][6][3] (host,
@@ -245,12 +248,12 @@ dg_status dg_sphere_volumes(const dg_mesh* mesh, double* vol, double* totals);
  * (rho' := s rho' + (s - 1) rhobar, U := s U, Theta' := s Theta' + (s - 1)
  * Thetabar; a reading: velocity and potential temperature keep their
  * interpolated values).  q_coarse, q_fine: device [5][K][Np] of their shells,
- * caller-owned, not aliased; phys float64 without viscosity (its background
- * gives rhobar, Thetabar).  If scale (host) is not NULL it receives s and the
- * call waits for the stream; otherwise the call only enqueues.  Uses both
- * meshes' reduction workspaces.  DG_EINVAL for shells that are not such a
- * pair; DG_EUNSUPPORTED for DG_MIXED or mu > 0; DG_ENONFINITE for a non-finite
- * s (only when scale is requested). */
+ * caller-owned, not aliased; phys without viscosity (its background gives
+ * rhobar, Thetabar; the transfer runs in float64 for either precision).  If
+ * scale (host) is not NULL it receives s and the call waits for the stream;
+ * otherwise the call only enqueues.  Uses both meshes' reduction workspaces.
+ * DG_EINVAL for shells that are not such a pair; DG_EUNSUPPORTED for mu > 0;
+ * DG_ENONFINITE for a non-finite s (only when scale is requested). */
 dg_status dg_sphere_refine_project(const dg_mesh* coarse, const dg_mesh* fine, const dg_phys* phys,
                                    const double* q_coarse, double* q_fine, double* scale, void* stream);
 /* Coarsening transfer, the reverse pair, section 3.4 (a): each coarse element
@@ -274,12 +277,12 @@ dg_status dg_sphere_coarsen_project(const dg_mesh* fine, const dg_mesh* coarse, 
  * background included, as in dg_sphere_refine_project; a merged family becomes the
  * sum of its children's reference projections plus the constant that keeps its
  * J W integrals, as in dg_sphere_coarsen_project: both passes keep the total
- * mass and Theta exactly.  q_from, q_to: device [5][K][Np] of
- * their meshes, caller-owned, not aliased; phys float64 without viscosity.  If
- * scale (host) is not NULL it receives s (1 when nothing was refined) and the call
- * waits for the stream; otherwise it only enqueues.  Uses both meshes' reduction
- * workspaces.  DG_EINVAL for meshes that are not such a pair; DG_EUNSUPPORTED for
- * DG_MIXED or mu > 0. */
+ * mass and Theta exactly.  q_from, q_to: device [5][K][Np] of their meshes,
+ * caller-owned, not aliased; phys without viscosity (float64 for either
+ * precision).  If scale (host) is not NULL it receives s (1 when nothing was
+ * refined) and the call waits for the stream; otherwise it only enqueues.  Uses
+ * both meshes' reduction workspaces.  DG_EINVAL for meshes that are not such a
+ * pair; DG_EUNSUPPORTED for mu > 0. */
 dg_status dg_sphere_adapt_project(const dg_mesh* from, const dg_mesh* to, const dg_phys* phys, const double* q_from,
                                   double* q_to, double* scale, void* stream);
 /* Face kinds of a shell (section 3.1's tree on the panels; the encoding is not in

@@ -647,8 +647,8 @@ dg_status dg_sphere_refine_project(const dg_mesh* coarse, const dg_mesh* fine, c
     if ((st = check_dev_mesh(coarse, s)) || (st = check_dev_mesh(fine, s))) return st;
     if ((st = check_phys(phys))) return st;
     if (!q_coarse || !q_fine) return fail(DG_EINVAL, "NULL field pointer");
-    if (phys->precision != DG_FP64 || phys->mu != 0.0)
-        return fail(DG_EUNSUPPORTED, "the shell transfer takes float64 physics without viscosity");
+    if (phys->mu != 0.0)  // the transfers run in float64 for either precision of the stage
+        return fail(DG_EUNSUPPORTED, "the shell transfer takes physics without viscosity");
     dg_mesh* mc = const_cast<dg_mesh*>(coarse);
     dg_mesh* mf = const_cast<dg_mesh*>(fine);
     if ((st = ensure_bg(mc, phys, s)) || (st = ensure_bg(mf, phys, s))) return st;
@@ -704,8 +704,8 @@ dg_status dg_sphere_adapt_project(const dg_mesh* from, const dg_mesh* to, const 
     dg_status st = check_dev_mesh(from, s);
     if (st || (st = check_dev_mesh(to, s))) return st;
     if ((st = check_phys(phys))) return st;
-    if (phys->precision != DG_FP64 || phys->mu != 0.0)
-        return fail(DG_EUNSUPPORTED, "the shell transfer takes float64 physics without viscosity");
+    if (phys->mu != 0.0)  // the transfers run in float64 for either precision of the stage
+        return fail(DG_EUNSUPPORTED, "the shell transfer takes physics without viscosity");
     if (!q_from || !q_to) return fail(DG_EINVAL, "NULL field pointer");
     if (q_from == q_to) return fail(DG_EINVAL, "input and output fields must not alias");
     dg_mesh* mf = const_cast<dg_mesh*>(from);
@@ -853,7 +853,6 @@ static dg_status stage_common(const dg_mesh* mc, const dg_phys* phys, int mode, 
     hipStream_t s = (hipStream_t)stream;
     if ((st = ensure_bg(m, phys, s))) return st;
     if (m->h.sphere) {
-        if (phys->precision != DG_FP64) return fail(DG_EUNSUPPORTED, "shell meshes run in float64");
         if (phys->mu > 0.0) return fail(DG_EUNSUPPORTED, "no artificial viscosity on shell meshes");
         if (phys->nonconforming != DG_NC_MORTAR)
             return fail(DG_EUNSUPPORTED, "shell meshes take the mortars at hanging faces");
@@ -865,7 +864,7 @@ static dg_status stage_common(const dg_mesh* mc, const dg_phys* phys, int mode, 
         }
         SphereStageArgs sa{q0, qs, out, m->d_ops, m->d_bg, m->d_c1d, m->d_srec, m->d_metric, m->d_fgeo,
                            m->d_mort, K, a, b, dt, phys->cp / phys->cv, phys->g, binom_coef(phys)};
-        HIP_TRY(launch_stage_sphere(m->h.desc.N, mode, sa, s));
+        HIP_TRY(launch_stage_sphere(m->h.desc.N, mode, phys->precision == DG_MIXED, sa, s));
         return DG_OK;
     }
     StageArgs args = stage_args(m, phys);

@@ -329,7 +329,7 @@ hipError_t launch_tracer_stage(int N, int mode, const TracerArgs& a, hipStream_t
 // the two viscous passes (mortars, gradient; mortars, divergence) on stream s
 hipError_t launch_viscous(int N, const ViscArgs& a, hipStream_t s);
 // cubed-sphere shell (N = 2..5): the stage and the node positions
-hipError_t launch_stage_sphere(int N, int mode, const SphereStageArgs& a, hipStream_t s);
+hipError_t launch_stage_sphere(int N, int mode, bool mixed, const SphereStageArgs& a, hipStream_t s);
 hipError_t launch_node_coords_sphere(int64_t K, int N, const double* c1d, const int32_t* srec, double r_e,
                                      double* xyz, hipStream_t s);
 // transfers between a shell (nc per panel edge, nzc layers) and the shell with twice

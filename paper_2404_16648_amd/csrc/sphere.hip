@@ -60,14 +60,19 @@ __device__ __forceinline__ void flux_normal(const double q[5], const Bg& b, doub
 // once and writes the N+1 sums D G along it in place; D from the uniform operator
 // table), each node adding -(1/J) times its own sum; a node on a conforming or wall
 // face of axis d also adds sgn G_d/(J w_N), the own-flux part of that face's term.
-// Radial buoyancy -rho' g r_hat.
-template <int N, int MODE>
+// Radial buoyancy -rho' g r_hat.  MIX (the precision split): the contraction of
+// each line in float32, on G_d minus its value at the element's first node (exact:
+// D annihilates constants) rounded to float32, with D split into float32 high and
+// low parts and float32 accumulation; everything else stays float64.
+template <int N, int MODE, bool MIX>
 __global__ void __launch_bounds__(Sz<N>::NT) k_stage_sphere(const SphereStageArgs A) {
     constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
     constexpr int ITEMS = (6 * NF + NT - 1) / NT;
     __shared__ double sQ[5 * NP];   // the tile, then the contravariant flux of one direction
     __shared__ double sS[30 * NF];  // [f][v][m]: s F*/(J w_N), or the pre-pass's full term
     __shared__ double sJ[NP];
+    __shared__ float sD32[MIX ? 2 * NF : 1];  // MIX: D high and low parts
+    __shared__ double sRef[MIX ? 5 : 1];      // MIX: G_d at the element's first node
     const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
     const int32_t* const rec = A.srec + e * kStageRec;
     const int t = threadIdx.x;
@@ -86,6 +91,13 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_stage_sphere(const SphereStageArg
 #pragma unroll
         for (int c = 0; c < 3; ++c) jr[c] = A.metric[(1 + c) * KNP + e * NP + t];
     }
+    if (MIX)
+        for (int x = t; x < NF; x += NT) {
+            const double dv = A.ops[x];
+            const float hi = (float)dv;
+            sD32[x] = hi;
+            sD32[NF + x] = (float)(dv - (double)hi);
+        }
     const int32_t packed = rec[18];
     int f_[ITEMS], m_[ITEMS];
     double qR_[ITEMS][5], nv_[ITEMS][4];
@@ -192,6 +204,9 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_stage_sphere(const SphereStageArg
             G[4] = Th * un;
 #pragma unroll
             for (int v = 0; v < 5; ++v) sQ[v * NP + t] = G[v];
+            if (MIX && t == 0)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) sRef[v] = G[v];
         }
         __syncthreads();
         const int stride = d == 0 ? 1 : d == 1 ? N1 : NF;
@@ -199,15 +214,32 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_stage_sphere(const SphereStageArg
             const int v = task / NF, l = task - v * NF;
             const int base = d == 0 ? N1 * l : d == 1 ? (l % N1) + NF * (l / N1) : l;
             double* const Gl = sQ + v * NP + base;
-            double g[N1];
+            if constexpr (MIX) {
+                const double ref = sRef[v];
+                float g[N1];
 #pragma unroll
-            for (int mm = 0; mm < N1; ++mm) g[mm] = Gl[mm * stride];
+                for (int mm = 0; mm < N1; ++mm) g[mm] = (float)(Gl[mm * stride] - ref);
 #pragma unroll
-            for (int o = 0; o < N1; ++o) {
-                double acc = 0.0;
+                for (int o = 0; o < N1; ++o) {
+                    float ah = 0.0f, al = 0.0f;
 #pragma unroll
-                for (int mm = 0; mm < N1; ++mm) acc = fma(A.ops[o * N1 + mm], g[mm], acc);
-                Gl[o * stride] = acc;
+                    for (int mm = 0; mm < N1; ++mm) {
+                        ah = fmaf(sD32[o * N1 + mm], g[mm], ah);
+                        al = fmaf(sD32[NF + o * N1 + mm], g[mm], al);
+                    }
+                    Gl[o * stride] = (double)ah + (double)al;
+                }
+            } else {
+                double g[N1];
+#pragma unroll
+                for (int mm = 0; mm < N1; ++mm) g[mm] = Gl[mm * stride];
+#pragma unroll
+                for (int o = 0; o < N1; ++o) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int mm = 0; mm < N1; ++mm) acc = fma(A.ops[o * N1 + mm], g[mm], acc);
+                    Gl[o * stride] = acc;
+                }
             }
         }
         __syncthreads();
@@ -1121,13 +1153,21 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_shell_scale(double* q, const doub
         default: return hipErrorInvalidValue;                        \
     }
 
-hipError_t launch_stage_sphere(int N, int mode, const SphereStageArgs& a, hipStream_t s) {
+hipError_t launch_stage_sphere(int N, int mode, bool mixed, const SphereStageArgs& a, hipStream_t s) {
     if (a.K <= 0) return hipSuccess;
     const dim3 grid((unsigned)a.K);
     if (mode == MODE_RHS) {
-        DG_DISPATCH_N(N, (k_stage_sphere<NN, MODE_RHS><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        if (mixed) {
+            DG_DISPATCH_N(N, (k_stage_sphere<NN, MODE_RHS, true><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        } else {
+            DG_DISPATCH_N(N, (k_stage_sphere<NN, MODE_RHS, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        }
     } else {
-        DG_DISPATCH_N(N, (k_stage_sphere<NN, MODE_RK><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        if (mixed) {
+            DG_DISPATCH_N(N, (k_stage_sphere<NN, MODE_RK, true><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        } else {
+            DG_DISPATCH_N(N, (k_stage_sphere<NN, MODE_RK, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        }
     }
     return hipGetLastError();
 }

@@ -78,7 +78,7 @@ def test_scale_factor_is_the_volume_ratio():
 def test_shell_transfer_refusals():
     lc, lf = dg.dg_sphere_mesh_build(3, 2, 1), dg.dg_sphere_mesh_build(3, 4, 2)
     with pytest.raises(dg.DGError) as e:
-        dg.dg_sphere_refine_project(lc, lf, dg.PhysParams(background=dg.DG_BG_ISOTHERMAL, precision=dg.DG_MIXED),
+        dg.dg_sphere_refine_project(lc, lf, dg.PhysParams(background=dg.DG_BG_ISOTHERMAL, mu=1.5),
                                     lc.field(), lf.field())
     assert e.value.code == dg.DG_EUNSUPPORTED
     with pytest.raises(dg.DGError) as e:
