@@ -621,6 +621,67 @@ def sphere_shell_refined(dg, torch, N=4, n=24, nz=8, dt=0.05, thr=20.0):
             "frac_hbm": nodes * bpn / (st_us * 1e-6) / 1e9 / HBM_PEAK_GBS}
 
 
+def sphere_vortex(dg, torch, N=4, n=24, nz=8, thr=0.1, dt=0.1, steps=20):
+    """The shell configuration of section 4.4's size with the isothermal 300 K
+    atmosphere under gravity and a Gaussian theta vortex (1 K, 500 km, at latitude 0,
+    longitude 0, at unperturbed density), refined once where theta' > thr: the
+    float64 and precision-split stage durations and the split's error against the
+    float64 stage (the library's float64 stage is held to the oracle by the parity
+    tests; the oracle is too slow at this size), the transposed right-hand side
+    against the right-hand side, and the gradient of a final-time functional over
+    `steps` checkpointed SSP-RK3 steps against the forward integration."""
+    from paper_2404_16648_amd import adjoint as adj
+    ph = dg.PhysParams(background=dg.DG_BG_ISOTHERMAL)
+    pm = dg.PhysParams(background=dg.DG_BG_ISOTHERMAL, precision=dg.DG_MIXED)
+    m = dg.dg_sphere_mesh_build(N, n, nz, max_level=1)
+
+    def vortex(mesh):
+        xyz = torch.empty(3, mesh.K, mesh.Np, dtype=torch.float64, device="cuda")
+        dg.dg_node_coords(mesh, xyz)
+        r = torch.sqrt(xyz[0] ** 2 + xyz[1] ** 2 + xyz[2] ** 2)
+        r_e, R, T0 = 6.371e6, ph.cp - ph.cv, ph.theta0
+        rho_b = ph.P0 * torch.exp(-ph.g * (r - r_e) / (R * T0)) / (R * T0)
+        dist = r_e * torch.arccos(torch.clamp(xyz[0] / r, -1.0, 1.0))
+        q = mesh.field()
+        q[4] = rho_b * torch.exp(-(dist / 5.0e5) ** 2)
+        return q
+
+    fl = dg.dg_indicator(m, ph, vortex(m), dg.DG_IND_THETA, thr)
+    fl[fl < 0] = 0
+    mr = dg.dg_mesh_build(prev=m, flags=fl, pass_=dg.DG_PASS_REFINE)
+    q = vortex(mr)
+    del m
+    q1, o64, o32 = torch.empty_like(q), torch.empty_like(q), torch.empty_like(q)
+    dg.dg_rk_stage(mr, ph, 0.0, 1.0, dt, q, q, q1)
+    st64 = _time_launches(torch, lambda: dg.dg_rk_stage(mr, ph, 0.75, 0.25, dt, q, q1, o64), 20)
+    st32 = _time_launches(torch, lambda: dg.dg_rk_stage(mr, pm, 0.75, 0.25, dt, q, q1, o32), 20)
+    # the split's error on the stage increment (the stage output minus its input)
+    err = _field_err(torch, o32 - q1, o64 - q1)
+    lam = torch.randn(q.shape, dtype=torch.float64, device=q.device, generator=torch.Generator(q.device).manual_seed(5))
+    R, g = torch.empty_like(q), torch.empty_like(q)
+    rhs_us = _time_launches(torch, lambda: dg.dg_rhs(mr, ph, q1, R), 20)
+    adj_us = _time_launches(torch, lambda: dg.dg_rhs_adjoint(mr, ph, q1, lam, g), 20)
+    for rep in range(2):  # the first pass loads the kernels; the second is timed
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = q.clone().requires_grad_(True)
+        qT = adj.integrate(x, mr, ph, dt, steps, 10)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        (gx,) = torch.autograd.grad(qT, x, grad_outputs=lam)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+    finite = bool(torch.isfinite(gx).all())
+    return {"workload": f"cubed-sphere shell 6 x {n} x {n} x {nz}, N={N}, isothermal 300 K under gravity, theta' "
+                        f"Gaussian 1 K / 500 km, refined once where theta' > {thr} K",
+            "leaves": mr.K, "hanging_faces": mr.info.n_hang, "nodes": mr.K * mr.Np,
+            "stage_fp64_us": st64, "stage_mixed_us": st32, "mixed_speedup": st64 / st32,
+            "mixed_stage_increment_rel_l2_vs_fp64(rho',momentum,Theta')": err,
+            "rhs_us": rhs_us, "rhs_adjoint_us": adj_us, "adjoint_over_rhs": adj_us / rhs_us,
+            "gradient": {"steps": steps, "dt": dt, "checkpoint_every": 10, "forward_s": t1 - t0,
+                         "backward_s": t2 - t1, "ratio": (t2 - t1) / (t1 - t0), "finite": finite}}
+
+
 def budget_drift(dg, torch, mesh, q, ph, dt, steps=10):
     """Change of the integral of rho' per SSP-RK3 step over `steps` steps (no
     adaptation), relative to the integral of rho = rho_bar + rho'."""
@@ -786,6 +847,8 @@ def extras(dg, torch, mesh, q, ph, args):
                                    else {"skipped": True})
     _progress("extras: refined shell")
     out["sphere_shell_refined"] = sphere_shell_refined(dg, torch)
+    _progress("extras: shell with the theta vortex (precision split, adjoint)")
+    out["sphere_vortex"] = sphere_vortex(dg, torch)
     _progress("extras: adaptive acoustic wave on the shell")
     out["sphere_acoustic_wave_adaptive"] = (acoustic_wave_adaptive(dg, torch, hours=args.acoustic_hours)
                                             if args.acoustic_hours > 0 else {"skipped": True})
