@@ -661,16 +661,25 @@ def sphere_vortex(dg, torch, N=4, n=24, nz=8, thr=0.1, dt=0.1, steps=20):
     R, g = torch.empty_like(q), torch.empty_like(q)
     rhs_us = _time_launches(torch, lambda: dg.dg_rhs(mr, ph, q1, R), 20)
     adj_us = _time_launches(torch, lambda: dg.dg_rhs_adjoint(mr, ph, q1, lam, g), 20)
-    for rep in range(2):  # the first pass loads the kernels; the second is timed
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        x = q.clone().requires_grad_(True)
-        qT = adj.integrate(x, mr, ph, dt, steps, 10)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        (gx,) = torch.autograd.grad(qT, x, grad_outputs=lam)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
+    gm = torch.empty_like(q)
+    adjm_us = _time_launches(torch, lambda: dg.dg_rhs_adjoint(mr, pm, q1, lam, gm), 20)
+    adj_err = _field_err(torch, gm, g)
+
+    def gradient(phys):
+        for rep in range(2):  # the first pass loads the kernels; the second is timed
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x = q.clone().requires_grad_(True)
+            qT = adj.integrate(x, mr, phys, dt, steps, 10)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            (gx,) = torch.autograd.grad(qT, x, grad_outputs=lam)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+        return gx, t1 - t0, t2 - t1
+
+    gx, fw, bw = gradient(ph)
+    gxm, fwm, bwm = gradient(pm)
     finite = bool(torch.isfinite(gx).all())
     return {"workload": f"cubed-sphere shell 6 x {n} x {n} x {nz}, N={N}, isothermal 300 K under gravity, theta' "
                         f"Gaussian 1 K / 500 km, refined once where theta' > {thr} K",
@@ -678,8 +687,12 @@ def sphere_vortex(dg, torch, N=4, n=24, nz=8, thr=0.1, dt=0.1, steps=20):
             "stage_fp64_us": st64, "stage_mixed_us": st32, "mixed_speedup": st64 / st32,
             "mixed_stage_increment_rel_l2_vs_fp64(rho',momentum,Theta')": err,
             "rhs_us": rhs_us, "rhs_adjoint_us": adj_us, "adjoint_over_rhs": adj_us / rhs_us,
-            "gradient": {"steps": steps, "dt": dt, "checkpoint_every": 10, "forward_s": t1 - t0,
-                         "backward_s": t2 - t1, "ratio": (t2 - t1) / (t1 - t0), "finite": finite}}
+            "rhs_adjoint_mixed_us": adjm_us, "mixed_adjoint_speedup": adj_us / adjm_us,
+            "mixed_adjoint_rel_l2_vs_fp64(rho',momentum,Theta')": adj_err,
+            "gradient": {"steps": steps, "dt": dt, "checkpoint_every": 10, "forward_s": fw, "backward_s": bw,
+                         "ratio": bw / fw, "finite": finite,
+                         "mixed": {"forward_s": fwm, "backward_s": bwm, "ratio": bwm / fwm,
+                                   "rel_l2_vs_fp64(rho',momentum,Theta')": _field_err(torch, gxm, gx)}}}
 
 
 def budget_drift(dg, torch, mesh, q, ph, dt, steps=10):

@@ -205,13 +205,13 @@ dg_status dg_mesh_build(const dg_forest_desc* desc, const dg_mesh* prev, const i
  * 4 s_f (-F*) per coarse reference area projected back), and dg_indicator (theta'
  * or P'), dg_pass_changes, dg_flags_after_coarsen, dg_flags_buffer and
  * dg_sphere_adapt_project accept them.  dg_rhs_adjoint and dg_rk_stage_adjoint
- * accept shells in float64: the transpose of the curvilinear right-hand side,
- * with the curved mortars transposed in their own pre-pass.  The precision
- * split (DG_MIXED) runs the stage's line contractions in float32 (G_d minus its
- * value at the element's first node, D in float32 high and low parts, float32
- * accumulation; faces, mortars, metric terms and the update in float64).  The
- * tracer, viscosity, pointwise matching and the mixed adjoint return
- * DG_EUNSUPPORTED.  N = 2..5.
+ * accept shells: the transpose of the curvilinear right-hand side, with the
+ * curved mortars transposed in their own pre-pass.  The precision split
+ * (DG_MIXED) runs the stage's line contractions in float32 (G_d minus its value
+ * at the element's first node, D in float32 high and low parts, float32
+ * accumulation; faces, mortars, metric terms and the update in float64), and the
+ * adjoint's transposed contractions D^T (-lam/J) in float32 likewise.  The
+ * tracer, viscosity and pointwise matching return DG_EUNSUPPORTED.  N = 2..5.
  * DG_EINVAL on bad sizes. */
 dg_status dg_sphere_mesh_build(const dg_sphere_desc* desc, dg_mesh** out);
 /* Face connectivity of a shell mesh (not in the paper): nb[K][6][3] (host,

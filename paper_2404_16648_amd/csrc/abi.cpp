@@ -1021,7 +1021,6 @@ static dg_status adjoint_common(const dg_mesh* mc, const dg_phys* phys, int mode
     hipStream_t s = (hipStream_t)stream;
     if ((st = ensure_bg(m, phys, s))) return st;
     if (m->h.sphere) {
-        if (phys->precision != DG_FP64) return fail(DG_EUNSUPPORTED, "the shell's adjoint runs in float64");
         const int64_t K = (int64_t)m->h.leaves.size();
         const double gamma = phys->cp / phys->cv;
         if (m->n_hang) {
@@ -1031,7 +1030,7 @@ static dg_status adjoint_common(const dg_mesh* mc, const dg_phys* phys, int mode
         }
         SphereAdjArgs sa{q, lam, w1, w2, out, m->d_ops, m->d_bg, m->d_c1d, m->d_srec, m->d_metric, m->d_fgeo,
                          m->d_mort, K, a1, a2, b, dt, gamma, phys->g, binom_coef(phys)};
-        HIP_TRY(launch_adjoint_sphere(m->h.desc.N, mode, sa, s));
+        HIP_TRY(launch_adjoint_sphere(m->h.desc.N, mode, phys->precision == DG_MIXED, sa, s));
         return DG_OK;
     }
     AdjArgs a{};

@@ -230,7 +230,7 @@ struct SphereAdjArgs {
     double gamma, g;
     BinomCoef binom;
 };
-hipError_t launch_adjoint_sphere(int N, int mode, const SphereAdjArgs& a, hipStream_t s);
+hipError_t launch_adjoint_sphere(int N, int mode, bool mixed, const SphereAdjArgs& a, hipStream_t s);
 
 // transposed mortar pre-pass of the shell: per hanging row the contributions of the
 // row's mortar terms to qbar at the coarse face (slot 0) and the four fine faces

@@ -682,8 +682,10 @@ __global__ void __launch_bounds__(MortSz<N>::NT) k_mortar_sphere_adjoint(const S
 // contribution; (2) volume: for each reference direction d the transposed
 // contraction Gbar_d = D_d^T mu (plus sgn lam / (J w_N) at the nodes of a conforming
 // or wall face of axis d, the own-flux part) and the chain rule through G_d = J a^d.F;
-// (3) buoyancy -rho' g r_hat transposed.
-template <int N, int MODE>
+// (3) buoyancy -rho' g r_hat transposed.  MIX: the transposed contractions in
+// float32 (mu rounded to float32, D split into float32 high and low parts, float32
+// accumulation); faces, mortars, the chain rule and the output stay float64.
+template <int N, int MODE, bool MIX>
 __global__ void __launch_bounds__(Sz<N>::NT) k_adjoint_sphere(const SphereAdjArgs A) {
     constexpr int N1 = Sz<N>::N1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
     constexpr int ITEMS = (6 * NF + NT - 1) / NT;
@@ -691,6 +693,8 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_adjoint_sphere(const SphereAdjArg
     __shared__ double sMu[5 * NP];  // -lam / J
     __shared__ double sS[30 * NF];  // [f][v][m]: the face contributions to qbar
     __shared__ double sJ[NP];
+    __shared__ float sMuf[MIX ? 5 * NP : 1];  // MIX: mu in float32
+    __shared__ float sD32[MIX ? 2 * NF : 1];  // MIX: D high and low parts
     const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
     const int32_t* const rec = A.srec + e * kStageRec;
     const int t = threadIdx.x;
@@ -707,9 +711,18 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_adjoint_sphere(const SphereAdjArg
             q[v] = A.q[v * KNP + e * NP + t];
             lam[v] = A.lam[v * KNP + e * NP + t];
             sQ[v * NP + t] = q[v];
-            sMu[v * NP + t] = -lam[v] / Jv;
+            const double mu = -lam[v] / Jv;
+            sMu[v * NP + t] = mu;
+            if (MIX) sMuf[v * NP + t] = (float)mu;
         }
     }
+    if (MIX)
+        for (int x = t; x < NF; x += NT) {
+            const double dv = A.ops[x];
+            const float hi = (float)dv;
+            sD32[x] = hi;
+            sD32[NF + x] = (float)(dv - (double)hi);
+        }
     // the face items' loads: face geometry, the neighbour's state, weights, face
     // Jacobian and J at its node
     const int32_t packed = rec[18];
@@ -816,11 +829,23 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_adjoint_sphere(const SphereAdjArg
             double a[5];
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
-                const double* Mu = sMu + v * NP + base;
-                double acc = 0.0;
+                if constexpr (MIX) {
+                    const float* Mu = sMuf + v * NP + base;
+                    float ah = 0.0f, al = 0.0f;
 #pragma unroll
-                for (int o = 0; o < N1; ++o) acc = fma(A.ops[o * N1 + id], Mu[o * stride], acc);
-                a[v] = acc;
+                    for (int o = 0; o < N1; ++o) {
+                        const float mv = Mu[o * stride];
+                        ah = fmaf(sD32[o * N1 + id], mv, ah);
+                        al = fmaf(sD32[NF + o * N1 + id], mv, al);
+                    }
+                    a[v] = (double)ah + (double)al;
+                } else {
+                    const double* Mu = sMu + v * NP + base;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int o = 0; o < N1; ++o) acc = fma(A.ops[o * N1 + id], Mu[o * stride], acc);
+                    a[v] = acc;
+                }
             }
             if (id == 0 || id == N) {
                 const int f = 2 * d + (id == N ? 1 : 0);
@@ -1224,13 +1249,21 @@ hipError_t launch_mortar_sphere_adjoint(int N, const SphereMortAdjArgs& a, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_sphere(int N, int mode, const SphereAdjArgs& a, hipStream_t s) {
+hipError_t launch_adjoint_sphere(int N, int mode, bool mixed, const SphereAdjArgs& a, hipStream_t s) {
     if (a.K <= 0) return hipSuccess;
     const dim3 grid((unsigned)a.K);
     if (mode == MODE_RHS) {
-        DG_DISPATCH_N(N, (k_adjoint_sphere<NN, MODE_RHS><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        if (mixed) {
+            DG_DISPATCH_N(N, (k_adjoint_sphere<NN, MODE_RHS, true><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        } else {
+            DG_DISPATCH_N(N, (k_adjoint_sphere<NN, MODE_RHS, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        }
     } else {
-        DG_DISPATCH_N(N, (k_adjoint_sphere<NN, MODE_RK><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        if (mixed) {
+            DG_DISPATCH_N(N, (k_adjoint_sphere<NN, MODE_RK, true><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        } else {
+            DG_DISPATCH_N(N, (k_adjoint_sphere<NN, MODE_RK, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
+        }
     }
     return hipGetLastError();
 }

@@ -99,9 +99,6 @@ def test_sphere_refusals():
     lm, _ = _meshes(3, 1, 1)
     q, r = lm.field(), lm.field()
     with pytest.raises(dg.DGError) as e:
-        dg.dg_rhs_adjoint(lm, dg.PhysParams(background=dg.DG_BG_ISOTHERMAL, precision=dg.DG_MIXED), q, q.clone(), r)
-    assert e.value.code == dg.DG_EUNSUPPORTED
-    with pytest.raises(dg.DGError) as e:
         dg.dg_rhs(lm, dg.PhysParams(background=dg.DG_BG_ISOTHERMAL, mu=1.5), q, r)
     assert e.value.code == dg.DG_EUNSUPPORTED
     with pytest.raises(dg.DGError) as e:

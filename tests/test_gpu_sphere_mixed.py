@@ -1,10 +1,12 @@
 """The precision split on the cubed-sphere shell on the GPU: the stage's line
 contractions in float32 (the contravariant flux minus its value at the element's
 first node, D split into float32 high and low parts, float32 accumulation),
-faces, curved mortars, metric terms and the update in float64.  Judged against
-the float64 oracle at relative L2 <= 1e-5 for every component, on uniform and
-refined shells at N = 2..5, and over ten SSP-RK3 steps of a Gaussian theta vortex
-on a shell refined around it.  The float32 contractions break the exact
+faces, curved mortars, metric terms and the update in float64; in the adjoint the
+transposed contractions in float32 likewise.  Judged against the float64 oracle
+at relative L2 <= 1e-5 for every component, on uniform and refined shells at
+N = 2..5, over ten SSP-RK3 steps of a Gaussian theta vortex on a shell refined
+around it, and for the checkpointed gradient through 20 steps against the
+float64 gradient.  The float32 contractions break the exact
 summation-by-parts cancellation of the volume term against the faces, so the
 total mass drifts by a float32 rounding of the flux divergence (reported, and
 bounded far below the field tolerance)."""
@@ -74,3 +76,47 @@ def test_mixed_shell_vortex_steps():
     print(f"mixed vortex shell K={om.K}: worst relative L2 over 10 steps (rho', momentum, Theta') "
           f"{['%.2e' % w for w in worst]}, mass change {(b1[1] - b0[1]) / b0[1]:.2e}", flush=True)
     assert abs(b1[1] - b0[1]) <= 1e-12 * b0[1]
+
+
+@pytest.mark.parametrize("case", [SHELLS[1], SHELLS[2], SHELLS[5], SHELLS[7]], ids=_id)
+def test_mixed_shell_adjoint(case):
+    """dg_rhs_adjoint and dg_rk_stage_adjoint with the precision split (the transposed
+    contractions in float32) against the float64 oracle's adjoint"""
+    N = case["N"]
+    lm, om = _shell(**case)
+    op = sp.SphereOperator(om, OPH, sp.BG_ISOTHERMAL)
+    qn = torch.as_tensor(random_state(om.K, N, 60 + N)) * 0.1 + to_nodes(sp.vortex_state(op, width=2.0e6))
+    ln = torch.as_tensor(random_state(om.K, N, 61 + N))
+    wn = torch.as_tensor(random_state(om.K, N, 62 + N))
+    want = to_nodes(eu.rhs_adjoint(op, to_elem(qn, N), to_elem(ln, N)))
+    g = lm.field()
+    dg.dg_rhs_adjoint(lm, MIXED, gpu(qn), gpu(ln), g)
+    assert_fields(g, want, TOL_MIXED, f"mixed shell adjoint N={N}")
+    dt = 2.0
+    dg.dg_rk_stage_adjoint(lm, MIXED, 0.5, gpu(wn), 0.0, None, 0.25, dt, gpu(qn), gpu(ln), g)
+    assert_fields(g, 0.5 * wn + 0.25 * (ln + dt * want), TOL_MIXED, f"mixed shell stage adjoint N={N}")
+
+
+def test_mixed_shell_gradient_through_steps():
+    """the checkpointed gradient of a functional through 20 SSP-RK3 steps on a shell
+    refined around the vortex, forward and adjoint with the precision split, against
+    the float64 gradient (both from the library; the float64 path is pinned to the
+    oracle and to central differences)"""
+    from paper_2404_16648_amd import adjoint as adj
+    N, dt = 3, 2.0
+    lm, om = _shell(N=N, n=3, nz=1, L=1, seed=31, fracs=(0.3,))
+    op = sp.SphereOperator(om, OPH, sp.BG_ISOTHERMAL)
+    q0 = gpu(to_nodes(sp.vortex_state(op, width=2.0e6)))
+    wm = gpu(to_nodes(sp.quad_weights(op)[None])[0])
+    fp64 = dg.PhysParams(background=dg.DG_BG_ISOTHERMAL)
+
+    def grad(phys):
+        x = q0.clone().requires_grad_(True)
+        qT = adj.integrate(x, lm, phys, dt, 20, 10)
+        (g,) = torch.autograd.grad((wm * qT[4] * qT[4]).sum() + (wm * qT[0] * qT[0]).sum(), x)
+        return g
+
+    g64, gmx = grad(fp64), grad(MIXED)
+    err = field_errors(gmx, g64)
+    print("mixed shell gradient vs float64", ["%.2e" % x for x in err], flush=True)
+    assert max(err) <= TOL_MIXED
