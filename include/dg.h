@@ -285,6 +285,26 @@ dg_status dg_sphere_coarsen_project(const dg_mesh* fine, const dg_mesh* coarse, 
  * pair; DG_EUNSUPPORTED for mu > 0. */
 dg_status dg_sphere_adapt_project(const dg_mesh* from, const dg_mesh* to, const dg_phys* phys, const double* q_from,
                                   double* q_to, double* scale, void* stream);
+/* Not in the paper (the adjoint through a shell's adaptation): the transpose of the
+ * derivative of dg_sphere_adapt_project at q_from, qbar_from := (dq_to/dq_from)^T
+ * qbar_to in the Euclidean inner product on the DOF vectors.  Kept leaves copy
+ * qbar.  A refined parent p gets s sum_a (I_a x I_a x I_a)^T qbar_a over its
+ * children, plus on rho' (D / M) (w_p - s sum_a (I_a x I_a x I_a)^T w_a): w = J W,
+ * M the refined parents' mass under q_from, D the sum over every child of
+ * qbar_to . (q_to + background) (the derivative of the scale factor s through
+ * both masses).  A merged family's child a gets (R_a x R_a x R_a)^T qbar_p plus,
+ * per field, (the sum of qbar_p over the parent's nodes / the parent's J W volume)
+ * (w_a - (R_a x R_a x R_a)^T w_p) (the derivative of the integral constant).
+ * q_from, q_to: the forward call's input and output, scale its factor (host);
+ * needed, and checked, only when the pass refines (may be NULL otherwise).
+ * qbar_to [5][K_to][Np], qbar_from [5][K_from][Np]: device, caller-owned, not
+ * aliased; every entry of qbar_from is written.  Uses both meshes' reduction
+ * workspaces; enqueued on stream.  DG_EINVAL as dg_sphere_adapt_project, for a
+ * non-positive or non-finite scale, or a plan whose refined families are not
+ * consecutive; DG_EUNSUPPORTED for mu > 0. */
+dg_status dg_sphere_adapt_project_adjoint(const dg_mesh* from, const dg_mesh* to, const dg_phys* phys,
+                                          const double* q_from, const double* q_to, double scale,
+                                          const double* qbar_to, double* qbar_from, void* stream);
 /* Face kinds of a shell (section 3.1's tree on the panels; the encoding is not in
  * the paper): kind[K][6] (host, caller-owned) = 0 wall, 1 conforming, 2 fine side
  * of a hanging face + 4 * its quadrant in the coarse face's axes, 3 coarse side.

@@ -858,10 +858,16 @@ def vortex_state(op: SphereOperator, amp=1.0, width=5.0e5, lon=0.0, lat=0.0):
 # ----------------------------------------------------------------------------- transfers of a refinement pass (section 3.4)
 
 def _subset_mass(op: SphereOperator, q, elems):
-    """J W quadrature of rho = rhobar + rho' over the given leaves, exactly rounded"""
+    """J W quadrature of rho = rhobar + rho' over the given leaves, exactly rounded.
+    When q carries a gradient the value is the same exactly rounded sum, returned
+    as a tensor whose derivative is that of the plain sum (for the adjoint)."""
     JW = quad_weights(op)[elems]
     rho = op.bg[0][elems] + q[0][elems]
-    return math.fsum((JW * rho).reshape(-1).tolist())
+    exact = math.fsum((JW * rho).reshape(-1).tolist())
+    if not q.requires_grad:
+        return exact
+    plain = (JW * rho).sum()
+    return exact + (plain - plain.detach())
 
 
 def adapt_project(op_from: SphereOperator, op_to: SphereOperator, q):
@@ -907,6 +913,17 @@ def adapt_project(op_from: SphereOperator, op_to: SphereOperator, q):
         out[1:4, ch] = s * out[1:4, ch]
         out[4, ch] = s * out[4, ch] + (s - 1.0) * Th_b[ch]
     return out, s
+
+
+def adapt_project_adjoint(op_from: SphereOperator, op_to: SphereOperator, q, qbar_to):
+    """The transpose of the derivative of adapt_project at q: qbar_from = (d q_to /
+    d q)^T qbar_to in the Euclidean inner product on the DOF vectors, by
+    reverse-mode differentiation of adapt_project (the refinement's scale factor
+    depends on q, so the map is affine only for a coarsening)."""
+    x = q.detach().clone().requires_grad_(True)
+    out, _ = adapt_project(op_from, op_to, x)
+    (g,) = torch.autograd.grad(out, x, grad_outputs=qbar_to)
+    return g
 
 
 # ----------------------------------------------------------------------------- regrid indicator (section 4.4)

@@ -5,8 +5,9 @@ Forward: n SSP-RK3 steps with dg_rk_stage, keeping the state every
 steps once from the checkpoint (keeping the three stage inputs of every step)
 and run the transposed stages with dg_rk_stage_adjoint.  Through an adaptation
 cycle the gradient flows back through the transposes of the conservative
-transfers (section 3.3) along the recorded mesh sequence.  All arithmetic runs
-in the HIP library; this module only orders calls and holds buffers.
+transfers (section 3.3; on a shell, of section 3.4's transfer) along the
+recorded mesh sequence.  All arithmetic runs in the HIP library; this module
+only orders calls and holds buffers.
 """
 from __future__ import annotations
 
@@ -98,6 +99,29 @@ class Transfer(torch.autograd.Function):
         return out, None, None, None
 
 
+class ShellTransfer(torch.autograd.Function):
+    """q_to = T(q_from) for the transfer of a shell's refine or coarsen pass
+    (dg_sphere_adapt_project: affine for a coarsening, nonlinear through the
+    refinement's scale factor); the backward applies the transpose of its
+    derivative at q_from with dg_sphere_adapt_project_adjoint."""
+
+    @staticmethod
+    def forward(ctx, q, src, dst, phys):
+        qd = q.detach().contiguous()
+        out = torch.empty(5, dst.K, dst.Np, dtype=torch.float64, device=q.device)
+        s = dg.dg_sphere_adapt_project(src, dst, phys, qd, out)
+        ctx.save_for_backward(qd, out)
+        ctx.src, ctx.dst, ctx.phys, ctx.s = src, dst, phys, s
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        qd, out = ctx.saved_tensors
+        gin = torch.empty(5, ctx.src.K, ctx.src.Np, dtype=torch.float64, device=g.device)
+        dg.dg_sphere_adapt_project_adjoint(ctx.src, ctx.dst, ctx.phys, qd, out, ctx.s, g.detach().contiguous(), gin)
+        return gin, None, None, None
+
+
 class AdaptPlan:
     """Mesh sequence of an adaptive run: (mesh_c, mesh_r) of every cycle, as
     :func:`dg.adapt_meshes` returns them.  The flags are piecewise constant in
@@ -129,8 +153,8 @@ def integrate_adaptive(q0, mesh, phys, dt, nsteps, adapt_every, kind=None, thr=N
         else:
             mc, mr = plan.cycles[cyc]
         if mc is not m:
-            q = Transfer.apply(q, m, mc, False)
+            q = ShellTransfer.apply(q, m, mc, phys) if m.shell else Transfer.apply(q, m, mc, False)
         if mr is not mc:
-            q = Transfer.apply(q, mc, mr, True)
+            q = ShellTransfer.apply(q, mc, mr, phys) if mc.shell else Transfer.apply(q, mc, mr, True)
         m, cyc = mr, cyc + 1
     return q, m, plan

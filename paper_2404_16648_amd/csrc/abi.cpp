@@ -737,6 +737,53 @@ dg_status dg_sphere_adapt_project(const dg_mesh* from, const dg_mesh* to, const 
     return DG_OK;
 }
 
+dg_status dg_sphere_adapt_project_adjoint(const dg_mesh* from, const dg_mesh* to, const dg_phys* phys,
+                                          const double* q_from, const double* q_to, double scale,
+                                          const double* qbar_to, double* qbar_from, void* stream) {
+    if (!from || !to) return fail(DG_EINVAL, "mesh is NULL");
+    if (!from->h.sphere || !to->h.sphere) return fail(DG_EINVAL, "not a shell mesh");
+    if (to->prev_id != from->id) return fail(DG_EINVAL, "`to` was not built from `from`");
+    hipStream_t s = (hipStream_t)stream;
+    dg_status st = check_dev_mesh(from, s);
+    if (st || (st = check_dev_mesh(to, s))) return st;
+    if ((st = check_phys(phys))) return st;
+    if (phys->mu != 0.0) return fail(DG_EUNSUPPORTED, "the shell transfer takes physics without viscosity");
+    if (!qbar_to || !qbar_from) return fail(DG_EINVAL, "NULL field pointer");
+    if (qbar_to == qbar_from) return fail(DG_EINVAL, "input and output fields must not alias");
+    if (to->n_xch > 0) {
+        if (!q_from || !q_to) return fail(DG_EINVAL, "NULL q_from or q_to for a pass that refines");
+        if (!std::isfinite(scale) || scale <= 0.0) return fail(DG_EINVAL, "scale must be the transfer's positive factor");
+    }
+    // a refined family's children are consecutive entries of the plan, in child order
+    const HostMesh& ht = to->h;
+    const int64_t Kf = (int64_t)from->h.leaves.size(), Kt = (int64_t)ht.leaves.size();
+    for (int64_t e = 0; e < Kt; ++e) {
+        if (ht.xfer_kind[e] != 0) continue;
+        if (e + 7 >= Kt) return fail(DG_EINVAL, "transfer plan: a refined family runs past the end");
+        for (int a = 1; a < 8; ++a)
+            if (ht.xfer_kind[e + a] != a || ht.xfer_src[e + a] != ht.xfer_src[e])
+                return fail(DG_EINVAL, "transfer plan: a refined family is not consecutive");
+    }
+    dg_mesh* mf = const_cast<dg_mesh*>(from);
+    dg_mesh* mt = const_cast<dg_mesh*>(to);
+    if ((st = ensure_bg(mf, phys, s)) || (st = ensure_bg(mt, phys, s))) return st;
+    const int N = ht.desc.N;
+    double* out_f = mf->d_red + (int64_t)budget_blocks(Kf) * 8 + 4;
+    double* out_t = mt->d_red + (int64_t)budget_blocks(Kt) * 8 + 4;
+    if (to->n_xch > 0) {
+        // the refined parents' mass under q_from, and qbar_to . (q_to + background) over the children
+        const double* w = to->d_ops + 5 * (N + 1) * (N + 1);
+        HIP_TRY(launch_shell_mass(N, q_from, mf->d_bg, mf->d_metric, w, to->d_xlist + to->n_xch, to->n_xpar, Kf,
+                                  mf->d_red, budget_blocks(to->n_xpar), out_f, s));
+        HIP_TRY(launch_shell_dot(N, qbar_to, q_to, mt->d_bg, to->d_xlist, to->n_xch, Kt, mt->d_red,
+                                 budget_blocks(to->n_xch), out_t, s));
+    }
+    ShellPlanAdjArgs a{qbar_to, qbar_from, to->d_ops, mf->d_metric, mt->d_metric, to->d_xsrc, to->d_xkind,
+                       out_f, out_t, to->n_xch > 0 ? scale : 1.0, Kf, Kt};
+    HIP_TRY(launch_shell_plan_adjoint(N, a, s));
+    return DG_OK;
+}
+
 dg_status dg_sphere_face_kinds(const dg_mesh* m, int32_t* kind) {
     if (!m || !kind) return fail(DG_EINVAL, "NULL argument");
     if (!m->h.sphere) return fail(DG_EINVAL, "not a shell mesh");

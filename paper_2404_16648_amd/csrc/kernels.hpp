@@ -267,6 +267,27 @@ struct ShellPlanArgs {
     int64_t Ksrc, Kdst;
 };
 hipError_t launch_shell_plan(int N, const ShellPlanArgs& a, hipStream_t s);
+
+// the transpose of a pass's shell transfer at the state it was applied to: qbar on
+// the target (gto) to qbar on the source (gfrom); mass = the refined parents' mass
+// under q_from, dot = sum over the children of qbar_to . (q_to + background), s the
+// transfer's scale factor (device scalars mass, dot; read only with children)
+struct ShellPlanAdjArgs {
+    const double* gto;
+    double* gfrom;
+    const double* ops;
+    const double* met_from;
+    const double* met_to;
+    const int32_t* xsrc;
+    const int32_t* xkind;
+    const double* mass;
+    const double* dot;
+    double s;
+    int64_t Kfrom, Kto;
+};
+hipError_t launch_shell_plan_adjoint(int N, const ShellPlanAdjArgs& a, hipStream_t s);
+hipError_t launch_shell_dot(int N, const double* g, const double* q, const double* bg, const int32_t* list, int64_t n,
+                            int64_t K, double* partial, int nblk, double* out, hipStream_t s);
 // J W quadrature of rhobar + rho' over the leaves list[0..n) (compensated sums):
 // partial [nblk][2], the total to out[0]
 hipError_t launch_shell_mass(int N, const double* q, const double* bg, const double* metric, const double* w,

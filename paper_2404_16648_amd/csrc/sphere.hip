@@ -901,9 +901,9 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_adjoint_sphere(const SphereAdjArg
 // element (p, ia, ib, ir) is fine element (p, 2 ia + ax, 2 ib + ay, 2 ir + az), and
 // its reference box is half ax, ay, az of the parent's along the local axes.
 
-// one separable pass over the five fields of a tile in LDS: out[v][node] =
+// one separable pass over the NFLD fields of a tile in LDS: out[v][node] =
 // sum_m M[idx(node, axis)][m] in[v][node with that index replaced by m]
-template <int N>
+template <int N, int NFLD = 5>
 __device__ __forceinline__ void tile_pass(const double* in, double* out, const double* M, int axis, int t) {
     constexpr int N1 = N + 1, NP = N1 * N1 * N1, NF = N1 * N1;
     if (t >= NP) return;
@@ -912,7 +912,7 @@ __device__ __forceinline__ void tile_pass(const double* in, double* out, const d
     const int stride = axis == 0 ? 1 : axis == 1 ? N1 : NF;
     const int base = t - id * stride;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
+    for (int v = 0; v < NFLD; ++v) {
         double acc = 0.0;
 #pragma unroll
         for (int m = 0; m < N1; ++m) acc = fma(M[id * N1 + m], in[v * NP + base + m * stride], acc);
@@ -1165,6 +1165,152 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_shell_scale(double* q, const doub
     q[4 * KNP + idx] = s * q[4 * KNP + idx] + (s - 1.0) * Tb;
 }
 
+
+// ---------------------------------------------------------------- transposed shell transfers
+// The transpose of the derivative of a pass's transfer (dg_sphere_adapt_project) at
+// the state it was applied to.  Kept leaves copy qbar.  A refined parent p with
+// children a (q_a = s (I_a q_p + B) - B, B the background part of each conserved
+// field, s = M_c / M_f the ratio of the parents' mass to the interpolated
+// children's): qbar_p = s sum_a I_a^T qbar_a, plus on rho' (dot / M_c) (w_p -
+// s sum_a I_a^T w_a), dot = sum over all children of qbar . (q_to + B), w = J W (the
+// derivative of s, through both masses).  A merged family (q_p = sum_a R_a q_a + c,
+// c per field the constant of the J W integrals): qbar_a = R_a^T qbar_p + (sum of
+// qbar_p over the parent's nodes / V_p) (w_a - R_a^T w_p), V_p = sum of w_p.
+
+// sum over the leaves list[0..n) of qbar . (q + B) (B: rhobar on rho', Thetabar on
+// Theta'), compensated; block b takes a contiguous share, partial[b] = (sum, correction)
+template <int N>
+__global__ void __launch_bounds__(256) k_shell_dot(const double* g, const double* q, const double* bg,
+                                                   const int32_t* list, int64_t n, int64_t K, double* partial) {
+    constexpr int N1 = N + 1, NP = N1 * N1 * N1, NT = 256;
+    __shared__ Comp sh[4 * NT];
+    const int t = threadIdx.x;
+    Comp acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t i0 = blockIdx.x * per, i1 = (i0 + per < n) ? i0 + per : n;
+    const int64_t KNP = K * NP;
+    for (int64_t i = i0; i < i1; ++i) {
+        const int64_t e = list[i];
+        for (int nn = t; nn < NP; nn += NT) {
+            const int k = nn / (N1 * N1);
+            const int64_t x = e * NP + nn;
+            double d = g[x] * (q[x] + bg[e * N1 + k]);
+#pragma unroll
+            for (int v = 1; v < 4; ++v) d = fma(g[v * KNP + x], q[v * KNP + x], d);
+            d = fma(g[4 * KNP + x], q[4 * KNP + x] + bg[K * N1 + e * N1 + k], d);
+            acc[0] = comp_add(acc[0], d);
+        }
+    }
+    block_reduce4<NT>(acc, sh);
+    if (t == 0) {
+        partial[blockIdx.x * 2 + 0] = acc[0].s;
+        partial[blockIdx.x * 2 + 1] = acc[0].c;
+    }
+}
+
+// one workgroup per entry of the target's plan (a refined family is handled by the
+// entry of its first child)
+template <int N>
+__global__ void __launch_bounds__(Sz<N>::NT) k_shell_plan_adjoint(const ShellPlanAdjArgs A) {
+    constexpr int N1 = N + 1, NP = Sz<N>::NP, NF = Sz<N>::NF, NT = Sz<N>::NT;
+    __shared__ double sP[6 * NP], sT[6 * NP], sU[6 * NP], sM[3 * NF], sRed[6 * NT];
+    const int64_t e = blockIdx.x;
+    const int t = threadIdx.x;
+    const int kind = A.xkind[e];
+    const int64_t src = A.xsrc[e];
+    const int64_t Kf = A.Kfrom, Kt = A.Kto;
+    const double* w1 = A.ops + 5 * NF;
+    const int i = t % N1, j = (t / N1) % N1, k = t / NF;
+    const double Wn = t < NP ? w1[i] * w1[j] * w1[k] : 0.0;
+    if (kind < 0) {
+        if (t < NP)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) A.gfrom[(v * Kf + src) * NP + t] = A.gto[(v * Kt + e) * NP + t];
+        return;
+    }
+    if (kind > 0 && kind < 8) return;
+    if (kind == 0) {
+        // the refined parent src; its children are the entries e .. e + 7
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        for (int a = 0; a < 8; ++a) {
+            const int hal[3] = {a & 1, (a >> 1) & 1, a >> 2};
+            const int64_t ec = e + a;
+            if (t < NP) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) sT[v * NP + t] = A.gto[(v * Kt + ec) * NP + t];
+                sT[5 * NP + t] = A.met_to[ec * NP + t] * Wn;
+            }
+            for (int x = t; x < 3 * NF; x += NT) {
+                const int ax = x / NF;
+                sM[x] = A.ops[5 * NF + N1 + hal[ax] * NF + (x - ax * NF)];  // I_0^T or I_1^T
+            }
+            __syncthreads();
+            tile_pass<N, 6>(sT, sU, sM, 0, t);
+            __syncthreads();
+            tile_pass<N, 6>(sU, sT, sM + NF, 1, t);
+            __syncthreads();
+            tile_pass<N, 6>(sT, sU, sM + 2 * NF, 2, t);
+            __syncthreads();
+            if (t < NP)
+#pragma unroll
+                for (int f = 0; f < 6; ++f) acc[f] += sU[f * NP + t];
+        }
+        if (t < NP) {
+            const double s = A.s;
+            const double coef = A.dot[0] / A.mass[0];
+            const double wp = A.met_from[src * NP + t] * Wn;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                double o = s * acc[v];
+                if (v == 0) o = fma(coef, wp - s * acc[5], o);
+                A.gfrom[(v * Kf + src) * NP + t] = o;
+            }
+        }
+        return;
+    }
+    // a family src .. src + 7 merged into the target parent e: qbar_p and w_p into sP,
+    // the per-field sums over the parent's nodes and its volume by one block reduction
+    if (t < NP) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sP[v * NP + t] = A.gto[(v * Kt + e) * NP + t];
+        sP[5 * NP + t] = A.met_to[e * NP + t] * Wn;
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) sRed[f * NT + t] = t < NP ? sP[f * NP + t] : 0.0;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (t < w)
+#pragma unroll
+            for (int f = 0; f < 6; ++f) sRed[f * NT + t] += sRed[f * NT + t + w];
+        __syncthreads();
+    }
+    double cpar[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) cpar[v] = sRed[v * NT] / sRed[5 * NT];
+    for (int a = 0; a < 8; ++a) {
+        const int hal[3] = {a & 1, (a >> 1) & 1, a >> 2};
+        for (int x = t; x < 3 * NF; x += NT) {
+            const int ax = x / NF;
+            sM[x] = A.ops[7 * NF + N1 + hal[ax] * NF + (x - ax * NF)];  // R_0^T or R_1^T
+        }
+        __syncthreads();
+        tile_pass<N, 6>(sP, sT, sM, 0, t);
+        __syncthreads();
+        tile_pass<N, 6>(sT, sU, sM + NF, 1, t);
+        __syncthreads();
+        tile_pass<N, 6>(sU, sT, sM + 2 * NF, 2, t);
+        __syncthreads();
+        if (t < NP) {
+            const int64_t ea = src + a;
+            const double wa = A.met_from[ea * NP + t] * Wn;
+#pragma unroll
+            for (int v = 0; v < 5; ++v)
+                A.gfrom[(v * Kf + ea) * NP + t] = fma(cpar[v], wa - sT[5 * NP + t], sT[v * NP + t]);
+        }
+        __syncthreads();  // sM and sT are rewritten by the next child
+    }
+}
+
 }  // namespace
 
 // orders 2..5: the tile, the three contravariant flux planes and the face slots
@@ -1265,6 +1411,22 @@ hipError_t launch_adjoint_sphere(int N, int mode, bool mixed, const SphereAdjArg
             DG_DISPATCH_N(N, (k_adjoint_sphere<NN, MODE_RK, false><<<grid, dim3(Sz<NN>::NT), 0, s>>>(a)));
         }
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_shell_plan_adjoint(int N, const ShellPlanAdjArgs& a, hipStream_t s) {
+    if (a.Kto <= 0) return hipSuccess;
+    DG_DISPATCH_N(N, (k_shell_plan_adjoint<NN><<<dim3((unsigned)a.Kto), dim3(Sz<NN>::NT), 0, s>>>(a)));
+    return hipGetLastError();
+}
+
+hipError_t launch_shell_dot(int N, const double* g, const double* q, const double* bg, const int32_t* list, int64_t n,
+                            int64_t K, double* partial, int nblk, double* out, hipStream_t s) {
+    if (nblk < 1) return hipErrorInvalidValue;
+    if (n > 0) {
+        DG_DISPATCH_N(N, (k_shell_dot<NN><<<dim3((unsigned)nblk), dim3(256), 0, s>>>(g, q, bg, list, n, K, partial)));
+    }
+    k_shell_mass_final<<<dim3(1), dim3(256), 0, s>>>(partial, n > 0 ? nblk : 0, out);
     return hipGetLastError();
 }
 

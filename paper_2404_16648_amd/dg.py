@@ -44,7 +44,7 @@ EXPORTED = [
     "dg_refine_project_adjoint", "dg_coarsen_project_adjoint", "dg_rhs_adjoint", "dg_rk_stage_adjoint", "dg_budgets", "dg_budgets_noalloc", "dg_indicator", "dg_indicator_async", "dg_pass_changes", "dg_flags_after_coarsen", "dg_tracer_rhs", "dg_tracer_stage", "dg_tracer_mass",
     "dg_project_fields", "dg_flags_buffer", "dg_fma_burst", "dg_sphere_mesh_build", "dg_sphere_faces",
     "dg_sphere_geometry", "dg_sphere_volumes", "dg_sphere_refine_project", "dg_sphere_coarsen_project",
-    "dg_sphere_adapt_project", "dg_sphere_face_kinds", "dg_last_error",
+    "dg_sphere_adapt_project", "dg_sphere_adapt_project_adjoint", "dg_sphere_face_kinds", "dg_last_error",
 ]
 
 
@@ -132,6 +132,7 @@ def lib():
         L.dg_sphere_refine_project.argtypes = [P, P, C.POINTER(Phys), P, P, P, P]
         L.dg_sphere_coarsen_project.argtypes = [P, P, C.POINTER(Phys), P, P, P]
         L.dg_sphere_adapt_project.argtypes = [P, P, C.POINTER(Phys), P, P, P, P]
+        L.dg_sphere_adapt_project_adjoint.argtypes = [P, P, C.POINTER(Phys), P, P, C.c_double, P, P, P]
         L.dg_sphere_face_kinds.argtypes = [P, P]
         L.dg_last_error.restype = C.c_char_p
         for name in EXPORTED:
@@ -319,6 +320,23 @@ def dg_sphere_adapt_project(src: Mesh, dst: Mesh, phys: PhysParams, q_from, q_to
     _check(lib().dg_sphere_adapt_project(src.handle, dst.handle, C.byref(ph), _ptr(q_from), _ptr(q_to),
                                          C.c_void_p(s.ctypes.data) if scale else None, _stream(stream)))
     return float(s[0]) if scale else None
+
+
+def dg_sphere_adapt_project_adjoint(src: Mesh, dst: Mesh, phys: PhysParams, q_from, q_to, scale, qbar_to, qbar_from,
+                                    stream=None):
+    """The transpose of the derivative of dg_sphere_adapt_project at q_from (q_to its
+    output, scale its factor): qbar_from from qbar_to."""
+    _shape_check(dst, qbar_to)
+    _shape_check(src, qbar_from)
+    if q_from is not None:
+        _shape_check(src, q_from)
+    if q_to is not None:
+        _shape_check(dst, q_to)
+    ph = phys.c()
+    _check(lib().dg_sphere_adapt_project_adjoint(src.handle, dst.handle, C.byref(ph),
+                                                 _ptr(q_from) if q_from is not None else None,
+                                                 _ptr(q_to) if q_to is not None else None, float(scale),
+                                                 _ptr(qbar_to), _ptr(qbar_from), _stream(stream)))
 
 
 def dg_sphere_face_kinds(mesh: Mesh):

@@ -6,7 +6,9 @@ reverse-mode derivative of its own shell operator at N = 2..5, the dot-product
 test against the oracle's forward-mode JVP, SSP-RK3 steps transposed against the
 oracle, and the gradient of a forecast functional over 20 checkpointed SSP-RK3
 steps on a shell refined once around a Gaussian theta vortex against central
-differences."""
+differences; the transposed shell transfers of refine and coarsen passes against
+the oracle's, and the gradient through two adaptation cycles of a shell (a
+replayed sequence of passes) against the oracle and central differences."""
 import math
 
 import numpy as np
@@ -164,3 +166,119 @@ def test_shell_vortex_gradient_20_steps():
         worst = max(worst, gap)
         assert gap <= 1e-7, (k, fd, ad)
     print("vortex shell: worst FD relative gap over 10 directions at eps = 1e-4", worst, flush=True)
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_shell_transfer_adjoint_against_oracle(N):
+    """dg_sphere_adapt_project_adjoint for a refine pass (the scale factor's
+    derivative included) and for the coarsen pass that undoes it, against the
+    oracle's reverse-mode derivative of its own transfer"""
+    lm, om = _shell(N=N, n=2, nz=1, L=2, seed=41, fracs=(0.3,))
+    fl = (np.random.default_rng(42).random(om.K) < 0.3).astype(np.int8)
+    lm2 = dg.dg_mesh_build(prev=lm, flags=fl, pass_=dg.DG_PASS_REFINE)
+    om2 = sp.refine_pass(om, fl)
+    assert np.array_equal(lm2.tables()["leaf"], om2.leaves.astype(np.int32))
+    o1, o2 = sp.SphereOperator(om, OPH, sp.BG_ISOTHERMAL), sp.SphereOperator(om2, OPH, sp.BG_ISOTHERMAL)
+    qn = torch.as_tensor(random_state(om.K, N, 43)) * 0.1 + to_nodes(sp.acoustic_state(o1))
+    q2 = lm2.field()
+    s = dg.dg_sphere_adapt_project(lm, lm2, PH, gpu(qn), q2)
+    gb = torch.as_tensor(random_state(om2.K, N, 44))
+    g = lm.field()
+    dg.dg_sphere_adapt_project_adjoint(lm, lm2, PH, gpu(qn), q2, s, gpu(gb), g)
+    ref = to_nodes(sp.adapt_project_adjoint(o1, o2, to_elem(qn, N), to_elem(gb, N)))
+    # rho' carries the scale factor's derivative (dot / M) (w_p - s sum_a I_a^T w_a),
+    # a difference of two terms that agree to 1e-4..1e-5 (the children's weights
+    # interpolate back to nearly the parent's), so both sides' rounding is relative
+    # to those terms: its bound adds their magnitude |dot / M| |w_p|.  The other
+    # fields are held to the plain bound.
+    q2o, s_o = sp.adapt_project(o1, o2, to_elem(qn, N))
+    ch = [e for e in range(om2.K) if 0 <= om2.xfer_kind[e] < 8]
+    par = sorted({int(om2.xfer_src[e]) for e in ch})
+    JW1, JW2 = sp.quad_weights(o1), sp.quad_weights(o2)
+    q1e = to_elem(qn, N)
+    M = float((JW1[par] * (o1.bg[0][par] + q1e[0][par])).sum())
+    B2 = torch.stack([o2.bg[0], 0 * o2.bg[0], 0 * o2.bg[0], 0 * o2.bg[0], o2.bg[1]])
+    dot = float((to_elem(gb, N)[:, ch] * (q2o[:, ch] + B2[:, ch])).sum())
+    cancel = abs(dot / M) * float(torch.linalg.vector_norm(JW1[par]))
+    err0 = float(torch.linalg.vector_norm(g[0].cpu() - ref[0]))
+    print(f"refine pass transfer adjoint rho': {err0 / float(torch.linalg.vector_norm(ref[0])):.2e} of the field, "
+          f"{err0 / (float(torch.linalg.vector_norm(ref[0])) + cancel):.2e} of field + cancelling terms", flush=True)
+    assert err0 <= TOL_FP64 * (float(torch.linalg.vector_norm(ref[0])) + cancel)
+    assert_fields(torch.cat([ref[:1], g[1:].cpu()]), ref, TOL_FP64, "refine pass transfer adjoint (U, Theta')")
+    back = -np.ones(om2.K, dtype=np.int8)
+    lm3 = dg.dg_mesh_build(prev=lm2, flags=back, pass_=dg.DG_PASS_COARSEN)
+    om3 = sp.coarsen_pass(om2, back)
+    o3 = sp.SphereOperator(om3, OPH, sp.BG_ISOTHERMAL)
+    gb3 = torch.as_tensor(random_state(om3.K, N, 45))
+    g2 = lm2.field()
+    dg.dg_sphere_adapt_project_adjoint(lm2, lm3, PH, None, None, 1.0, gpu(gb3), g2)
+    ref3 = sp.adapt_project_adjoint(o2, o3, to_elem(q2.cpu(), N), to_elem(gb3, N))
+    assert_fields(g2, to_nodes(ref3), TOL_FP64, "coarsen pass transfer adjoint")
+
+
+def test_shell_gradient_through_adaptation():
+    """J(q_T) through 6 SSP-RK3 steps with two adaptation cycles on a shell (a
+    replayed sequence of coarsen and refine passes): the library's gradient against
+    the oracle's reverse-mode derivative of its own steps and transfers, and against
+    central differences on seeded directions along the same sequence"""
+    N, dt, nsteps, every = 3, 2.0, 6, 2
+    lm, om = _shell(N=N, n=2, nz=1, L=1, seed=51, fracs=(0.4,))
+    rng = np.random.default_rng(52)
+    cycles, ocycles = [], []
+    m, o = lm, om
+    for _ in range(2):
+        flc = np.where(o.leaves[:, 1] == 1, -1, 0).astype(np.int8)
+        mc = dg.dg_mesh_build(prev=m, flags=flc, pass_=dg.DG_PASS_COARSEN)
+        oc = sp.coarsen_pass(o, flc)
+        assert mc.info.n_coarsened > 0
+        flr = (rng.random(oc.K) < 0.4).astype(np.int8)
+        mr = dg.dg_mesh_build(prev=mc, flags=flr, pass_=dg.DG_PASS_REFINE)
+        orr = sp.refine_pass(oc, flr)
+        assert mr.info.n_refined > 0 and np.array_equal(mr.tables()["leaf"], orr.leaves.astype(np.int32))
+        cycles.append((mc, mr))
+        ocycles.append((oc, orr))
+        m, o = mr, orr
+    plan = adj.AdaptPlan(cycles)
+    opT = sp.SphereOperator(ocycles[-1][1], OPH, sp.BG_ISOTHERMAL)
+    cap = (6.371e6 * torch.arccos(torch.clamp(opT.geo.rhat[0], -1.0, 1.0)) <= 4.0e6).double()
+    wq = sp.quad_weights(opT) * cap
+    rbo, tbo = opT.bg[0], opT.bg[1]
+    wm, rb, tb = (gpu(to_nodes(x[None])[0]) for x in (wq, rbo, tbo))
+
+    def J(q):
+        thp = (tb + q[4]) / (rb + q[0]) - tb / rb
+        return (wm * thp * thp).sum()
+
+    op0 = sp.SphereOperator(om, OPH, sp.BG_ISOTHERMAL)
+    q0o = sp.vortex_state(op0, width=2.0e6) + 0.01 * to_elem(torch.as_tensor(random_state(om.K, N, 53)), N)
+    q0 = gpu(to_nodes(q0o))
+    x = q0.clone().requires_grad_(True)
+    qT, mT, _ = adj.integrate_adaptive(x, lm, PH, dt, nsteps, every, plan=plan, ckpt_every=2)
+    assert mT is plan.cycles[-1][1]
+    (g,) = torch.autograd.grad(J(qT), x)
+    xo = q0o.clone().requires_grad_(True)
+    qo, o, cyc = xo, om, 0
+    for n in range(nsteps):
+        qo = eu.ssp_rk3_step(sp.SphereOperator(o, OPH, sp.BG_ISOTHERMAL), dt, qo)
+        if (n + 1) % every == 0 and n + 1 < nsteps:
+            oc, orr = ocycles[cyc]
+            o_from = sp.SphereOperator(o, OPH, sp.BG_ISOTHERMAL)
+            o_c = sp.SphereOperator(oc, OPH, sp.BG_ISOTHERMAL)
+            qo = sp.adapt_project(o_from, o_c, qo)[0]
+            qo = sp.adapt_project(o_c, sp.SphereOperator(orr, OPH, sp.BG_ISOTHERMAL), qo)[0]
+            o, cyc = orr, cyc + 1
+    thp = (tbo + qo[4]) / (rbo + qo[0]) - tbo / rbo
+    (go,) = torch.autograd.grad((wq * thp * thp).sum(), xo)
+    assert_fields(g, to_nodes(go), TOL_FP64, "shell adaptive gradient vs oracle")
+
+    def Jonly(y):
+        with torch.no_grad():
+            return float(J(adj.integrate_adaptive(y, lm, PH, dt, nsteps, every, plan=plan)[0]))
+
+    for k in range(1, 4):
+        d = gpu(torch.as_tensor(random_direction(om.K, N, 60 + k)))
+        eps = 1e-4
+        fd = (Jonly(q0 + eps * d) - Jonly(q0 - eps * d)) / (2 * eps)
+        ad = float((g * d).sum())
+        print("shell adaptive direction", k, "fd", fd, "adjoint", ad, flush=True)
+        assert abs(fd - ad) <= 1e-7 * max(abs(fd), abs(ad)), (k, fd, ad)

@@ -18,7 +18,8 @@ What the geometry and the definitions fix, independently of the code:
     coarsening pass keep every family's J W integral of every field exactly, and a
     coarsening pass undoes a refinement pass on the leaves;
   * the shell's discrete adjoint (reverse-mode derivative of the operator, hanging
-    faces included) agrees with central differences of the operator itself, and
+    faces included) and the transposed transfers of the passes agree with central
+    differences of the operator and the transfers themselves, and
     the Gaussian theta vortex state has its stated amplitude, width and rest.
 Planted mistakes at the end: each must make one of these fail.
 """
@@ -221,6 +222,32 @@ def test_smooth_consistency_at_hanging_faces():
 
 def test_transfers_of_the_passes():
     check_adapt_transfers()
+
+
+def test_transfer_adjoint_against_central_differences():
+    """adapt_project_adjoint (reverse mode through the transfer, the refinement's
+    scale factor included) against central differences of adapt_project itself,
+    for a refine pass and the coarsen pass that undoes it"""
+    N = 2
+    m = sp.SphereMesh(sp.SphereDesc(N=N, n=1, nz=1, max_level=2))
+    m = sp.refine_pass(m, (np.arange(m.K) % 2 == 0).astype(np.int8))
+    m2 = sp.refine_pass(m, (np.arange(m.K) % 3 == 1).astype(np.int8))
+    m3 = sp.coarsen_pass(m2, -np.ones(m2.K, dtype=np.int8))
+    o1, o2, o3 = (sp.SphereOperator(x, eu.Phys(), sp.BG_ISOTHERMAL) for x in (m, m2, m3))
+    shape = lambda K: (5, K, N + 1, N + 1, N + 1)
+    q = torch.as_tensor(random_state(m.K, N, 71)).reshape(shape(m.K)) * 0.1 + sp.acoustic_state(o1)
+    for oa, ob, x in ((o1, o2, q), (o2, o3, sp.adapt_project(o1, o2, q)[0])):
+        gb = torch.as_tensor(random_state(ob.K, N, 72)).reshape(shape(ob.K))
+        v = torch.as_tensor(random_state(oa.K, N, 73)).reshape(shape(oa.K))
+        ad = float((sp.adapt_project_adjoint(oa, ob, x, gb) * v).sum())
+        eps = 1e-4
+        fd = float((gb * (sp.adapt_project(oa, ob, x + eps * v)[0] - sp.adapt_project(oa, ob, x - eps * v)[0])).sum())
+        fd /= 2 * eps
+        assert abs(ad - fd) <= 1e-8 * abs(ad), (ad, fd)
+    # the value of the transfer is unchanged by the derivative path
+    a0, s0 = sp.adapt_project(o1, o2, q)
+    a1, s1 = sp.adapt_project(o1, o2, q.clone().requires_grad_(True))
+    assert torch.equal(a0, a1.detach()) and s0 == float(s1)
 
 
 def test_shell_adjoint_against_central_differences():
