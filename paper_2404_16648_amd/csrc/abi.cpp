@@ -266,16 +266,7 @@ dg_status build_device(dg_mesh* m, hipStream_t s) {
         sphere_geometry(h, m->ops, (double*)(up.data() + L.met), (double*)(up.data() + L.fg), c1d);
         if (!xlist.empty()) std::memcpy(up.data() + L.xl, xlist.data(), sizeof(int32_t) * xlist.size());
     } else {
-        for (int64_t e = 0; e < K; ++e) {
-            double hh[3], c[3 * 8];  // N + 1 <= 8
-            leaf_geometry(h.desc, h.leaves[e], m->ops.x, hh, c);
-            for (int d = 0; d < 3; ++d) {
-                geo[e * 4 + d] = 2.0 / hh[d];
-                for (int j = 0; j < N1; ++j) c1d[(d * K + e) * N1 + j] = c[d * N1 + j];
-            }
-            geo[e * 4 + 3] = hh[0] * hh[1] * hh[2] / 8.0;
-            level[e] = h.leaves[e].l;
-        }
+        box_leaf_arrays(h, m->ops.x, geo, c1d, level);
     }
     std::memcpy(up.data() + L.ft, h.ftype.data(), sizeof(int32_t) * 6 * K);
     std::memcpy(up.data() + L.nb, h.fnb.data(), sizeof(int32_t) * 24 * K);
@@ -294,24 +285,7 @@ dg_status build_device(dg_mesh* m, hipStream_t s) {
     std::memcpy(up.data() + L.xk, h.xfer_kind.data(), sizeof(int32_t) * K);
     // the stage kernel's face tables, one contiguous record per leaf (read with scalar
     // loads): per face type, first neighbour, hanging-face row or -1
-    int32_t* sr = (int32_t*)(up.data() + L.sr);
-    for (int64_t e = 0; e < K; ++e) {
-        int32_t* rec = sr + e * kStageRec;
-        for (int f = 0; f < 6; ++f) {
-            rec[f] = h.ftype[e * 6 + f];
-            rec[6 + f] = h.fnb[e * 24 + f * 4];
-            rec[12 + f] = hs[e * 6 + f];
-        }
-        rec[18] = rec[19] = 0;
-        if (h.sphere) {
-            // shell: per face the neighbour's face and the flip (4 bits), the panel
-            for (int f = 0; f < 6; ++f) {
-                const int32_t* nb = &h.snb[(e * 6 + f) * 3];
-                if (nb[0] >= 0) rec[18] |= (int32_t)((nb[1] & 7) | ((nb[2] & 1) << 3)) << (4 * f);
-            }
-            rec[19] = h.leaves[e].r;
-        }
-    }
+    stage_records(h, hs, kStageRec, (int32_t*)(up.data() + L.sr));
     char* base = nullptr;
     HIP_TRY(hipMalloc((void**)&base, L.total));
     set_device_pointers(m, base, L);
@@ -849,7 +823,7 @@ dg_status dg_mesh_export(const dg_mesh* m, const dg_mesh_tables* t) {
             row[3] = lf.a[1];
             row[4] = lf.a[2];
         }
-    auto cp = [](int32_t* dst, const std::vector<int32_t>& src) {
+    auto cp = [](int32_t* dst, const ivec& src) {
         if (dst && !src.empty()) std::memcpy(dst, src.data(), src.size() * sizeof(int32_t));
     };
     cp(t->conf, h.conf);

@@ -28,6 +28,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <stdexcept>
 #include <tuple>
 
 #include "internal.hpp"
@@ -129,14 +130,15 @@ struct Sorted {
 
   private:
     bool key_in_place(const std::vector<Leaf>& v) {
-        keys.resize(v.size());
-        bool sorted = true;
-        for (size_t i = 0; i < v.size(); ++i) {
-            keys[i] = pos_key(rank, L, v[i]);
-            sorted = sorted && (i == 0 || keys[i - 1] < keys[i]);
-        }
-        if (sorted) lv = &v;
-        return sorted;
+        const int64_t n = (int64_t)v.size();
+        keys.resize(n);
+#pragma omp parallel for schedule(static) if (n > 4096)
+        for (int64_t i = 0; i < n; ++i) keys[i] = pos_key(rank, L, v[i]);
+        int unsorted = 0;
+#pragma omp parallel for schedule(static) reduction(| : unsorted) if (n > 4096)
+        for (int64_t i = 1; i < n; ++i) unsorted |= keys[i - 1] >= keys[i];
+        if (!unsorted) lv = &v;
+        return !unsorted;
     }
     void sort_copy(const std::vector<Leaf>& v) {
         std::vector<std::pair<uint64_t, Leaf>> kv(v.size());
@@ -291,6 +293,140 @@ static void unchanged(const HostMesh& prev, HostMesh& out) {
     out.same_as_prev = true;
 }
 
+// the face tables of one leaf e of the sorted mesh m (its row of ftype and fnb)
+static void leaf_faces(HostMesh& m, const Sorted& S, int64_t e) {
+    const dg_forest_desc& desc = m.desc;
+    const Leaf& lf = m.leaves[e];
+    for (int f = 0; f < 6; ++f) {
+        const int d = f >> 1, s = f & 1;
+        int32_t* nb = &m.fnb[(e * 6 + f) * 4];
+        for (int q = 0; q < 4; ++q) nb[q] = -1;
+        Leaf c;
+        if (!S.neighbor(lf, f, c)) {
+            m.ftype[e * 6 + f] = FT_WALL;
+            continue;
+        }
+        const int x = S.containing(c, (size_t)e);
+        if (x >= 0) {
+            if (S.leaves()[x].l == lf.l) {
+                const int rz = lf.r / (desc.nx * desc.ny);
+                const bool wrap_z = d == 2 && (s ? rz == desc.nz - 1 && lf.a[2] == (1 << lf.l) - 1
+                                                 : rz == 0 && lf.a[2] == 0);
+                m.ftype[e * 6 + f] = FT_CONF | (wrap_z ? FT_BG_NB : 0);
+            } else {
+                // this leaf is the fine side: quadrant from its tangential anchor bits
+                const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+                const int q = (lf.a[t1] & 1) | ((lf.a[t2] & 1) << 1);
+                m.ftype[e * 6 + f] = FT_FINE | (q << 8);
+            }
+            nb[0] = x;
+        } else {
+            Leaf fc[4];
+            face_children(c, d, 1 - s, fc);
+            m.ftype[e * 6 + f] = FT_COARSE;
+            for (int q = 0; q < 4; ++q) nb[q] = S.find(fc[q], (size_t)e);  // leaves, by balance
+        }
+    }
+}
+
+// the global face lists of m from its per-leaf tables, in (leaf, face) order:
+// per-leaf counts, their prefix sums, then every leaf writes its own entries
+static void face_lists(HostMesh& m) {
+    const int64_t K = (int64_t)m.leaves.size();
+    std::vector<int64_t, NoInit<int64_t>> oc(K + 1), ob(K + 1), oh(K + 1);
+    oc[0] = ob[0] = oh[0] = 0;
+#pragma omp parallel for schedule(static) if (K > 4096)
+    for (int64_t e = 0; e < K; ++e) {
+        int c = 0, b = 0, h = 0;
+        for (int f = 0; f < 6; ++f) {
+            const int type = m.ftype[e * 6 + f] & 0xff;
+            c += type == FT_CONF && (f & 1);
+            b += type == FT_WALL;
+            h += type == FT_COARSE;
+        }
+        oc[e + 1] = c;
+        ob[e + 1] = b;
+        oh[e + 1] = h;
+    }
+    for (int64_t e = 0; e < K; ++e) {
+        oc[e + 1] += oc[e];
+        ob[e + 1] += ob[e];
+        oh[e + 1] += oh[e];
+    }
+    m.conf.resize(3 * oc[K]);
+    m.bnd.resize(2 * ob[K]);
+    m.hang.resize(6 * oh[K]);
+#pragma omp parallel for schedule(static) if (K > 4096)
+    for (int64_t e = 0; e < K; ++e) {
+        int32_t* pc = m.conf.data() + 3 * oc[e];
+        int32_t* pb = m.bnd.data() + 2 * ob[e];
+        int32_t* ph = m.hang.data() + 6 * oh[e];
+        for (int f = 0; f < 6; ++f) {
+            const int type = m.ftype[e * 6 + f] & 0xff;
+            const int32_t* nb = &m.fnb[(e * 6 + f) * 4];
+            if (type == FT_WALL) {
+                *pb++ = (int32_t)e;
+                *pb++ = f;
+            } else if (type == FT_CONF && (f & 1)) {
+                *pc++ = (int32_t)e;
+                *pc++ = nb[0];
+                *pc++ = f >> 1;
+            } else if (type == FT_COARSE) {
+                *ph++ = (int32_t)e;
+                *ph++ = f;
+                for (int q = 0; q < 4; ++q) *ph++ = nb[q];
+            }
+        }
+    }
+}
+
+// the face tables of m, a pass's result in canonical order with its plan from prev:
+// a kept leaf none of whose face neighbours in prev changed has the same faces, so
+// its rows are prev's with the neighbour indices renumbered; every other leaf (new,
+// or beside a leaf that was refined or merged) is searched as in forest_tables
+static void tables_from(HostMesh& m, const HostMesh& prev) {
+    const int64_t K = (int64_t)m.leaves.size(), K0 = (int64_t)prev.leaves.size();
+    ivec renum(K0);  // the new index of every kept old leaf, else -1
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < K0; ++x) renum[x] = -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < K; ++e)
+        if (m.xfer_kind[e] == DG_KIND_COPY) renum[m.xfer_src[e]] = (int32_t)e;
+    m.ftype.resize(K * 6);  // every row is written below: copied, or searched
+    m.fnb.resize(K * 24);
+    std::vector<char> dirty(K, 0);
+    int64_t ndirty = 0;
+#pragma omp parallel for schedule(static) reduction(+ : ndirty)
+    for (int64_t e = 0; e < K; ++e) {
+        bool d = m.xfer_kind[e] != DG_KIND_COPY;
+        const int64_t x = m.xfer_src[e];
+        for (int i = 0; i < 24 && !d; ++i) {
+            const int32_t y = prev.fnb[x * 24 + i];
+            d = y >= 0 && renum[y] < 0;
+        }
+        if (!d) {
+            for (int f = 0; f < 6; ++f) m.ftype[e * 6 + f] = prev.ftype[x * 6 + f];
+            for (int i = 0; i < 24; ++i) {
+                const int32_t y = prev.fnb[x * 24 + i];
+                m.fnb[e * 24 + i] = y >= 0 ? renum[y] : -1;
+            }
+        }
+        dirty[e] = d;
+        ndirty += d;
+    }
+    if (ndirty > 0) {
+        Sorted S(m.desc, m.leaves);
+        if (S.lv != &m.leaves) throw std::logic_error("internal: a pass left the leaves out of order");
+        std::vector<int64_t> list;
+        list.reserve(ndirty);
+        for (int64_t e = 0; e < K; ++e)
+            if (dirty[e]) list.push_back(e);
+#pragma omp parallel for schedule(static) if (ndirty > 256)
+        for (int64_t i = 0; i < ndirty; ++i) leaf_faces(m, S, list[i]);
+    }
+    face_lists(m);
+}
+
 std::string forest_refine(const HostMesh& prev, const int8_t* flags, HostMesh& out) {
     const dg_forest_desc& desc = prev.desc;
     const int L = desc.max_level;
@@ -300,85 +436,92 @@ std::string forest_refine(const HostMesh& prev, const int8_t* flags, HostMesh& o
         unchanged(prev, out);
         return "";
     }
-    // old leaf index of every leaf of the result that is an old leaf or a child of one
-    std::vector<Leaf> cur;
-    cur.reserve(prev.leaves.size() * 2);
-    for (size_t e = 0; e < prev.leaves.size(); ++e) {
+    // the result in canonical order (children take their parent's place, in child
+    // order) with its plan: an old leaf kept (COPY, its index) or child id of old
+    // leaf src
+    const int64_t K0 = (int64_t)prev.leaves.size();
+    std::vector<int64_t> at(K0 + 1, 0);  // first position of old leaf e in the result
+    for (int64_t e = 0; e < K0; ++e) at[e + 1] = at[e] + ((flags[e] > 0 && prev.leaves[e].l < L) ? 8 : 1);
+    std::vector<Leaf> cur(at[K0]);
+    ivec src(at[K0]), kind(at[K0]);
+#pragma omp parallel for schedule(static) if (K0 > 4096)
+    for (int64_t e = 0; e < K0; ++e) {
         const Leaf& lf = prev.leaves[e];
-        if (flags[e] > 0 && lf.l < L)
-            for (int c = 0; c < 8; ++c) cur.push_back(child_of(lf, c));
-        else
-            cur.push_back(lf);
+        const int64_t p = at[e];
+        if (at[e + 1] - p == 8) {
+            for (int c = 0; c < 8; ++c) {
+                cur[p + c] = child_of(lf, c);
+                src[p + c] = (int32_t)e;
+                kind[p + c] = c;
+            }
+        } else {
+            cur[p] = lf;
+            src[p] = (int32_t)e;
+            kind[p] = DG_KIND_COPY;
+        }
     }
-    // ripple: refine leaves that have a face neighbour two or more levels finer
+    // ripple: refine leaves that have a face neighbour two or more levels finer.
+    // prev is balanced, so such a neighbour is always a new leaf: only new leaves
+    // are checked
     for (;;) {
-        Sorted S(desc, std::move(cur));
-        std::vector<char> todo(S.leaves().size(), 0);
+        Sorted S(desc, cur);
+        if (S.lv != &cur) return "internal: refined leaves out of order";
+        std::vector<int64_t> fresh;
+        for (int64_t i = 0; i < (int64_t)cur.size(); ++i)
+            if (kind[i] != DG_KIND_COPY && cur[i].l >= 2) fresh.push_back(i);
+        std::vector<char> todo(cur.size(), 0);
         int any = 0;
-        const int64_t nl = (int64_t)S.leaves().size();
-#pragma omp parallel for schedule(static) reduction(| : any)
-        for (int64_t zi = 0; zi < nl; ++zi) {
-            const Leaf& z = S.leaves()[zi];
-            if (z.l < 2) continue;
+        const int64_t nf = (int64_t)fresh.size();
+#pragma omp parallel for schedule(static) reduction(| : any) if (nf > 256)
+        for (int64_t k = 0; k < nf; ++k) {
+            const int64_t zi = fresh[k];
+            const Leaf& z = cur[zi];
             for (int f = 0; f < 6; ++f) {
                 Leaf c;
                 if (!S.neighbor(z, f, c)) continue;
                 const int x = S.containing(c, (size_t)zi);
-                if (x >= 0 && S.leaves()[x].l <= z.l - 2) {
+                if (x >= 0 && cur[x].l <= z.l - 2) {
 #pragma omp atomic write
                     todo[x] = 1;
                     any = 1;
                 }
             }
         }
-        if (!any) {
-            cur = S.take();
-            break;
-        }
-        cur.clear();
-        for (size_t i = 0; i < S.leaves().size(); ++i) {
-            const Leaf& z = S.leaves()[i];
+        if (!any) break;
+        std::vector<Leaf> nxt;
+        ivec nsrc, nkind;
+        nxt.reserve(cur.size() + 64);
+        nsrc.reserve(cur.size() + 64);
+        nkind.reserve(cur.size() + 64);
+        for (size_t i = 0; i < cur.size(); ++i) {
+            const Leaf& z = cur[i];
             if (!todo[i]) {
-                cur.push_back(z);
+                nxt.push_back(z);
+                nsrc.push_back(src[i]);
+                nkind.push_back(kind[i]);
                 continue;
             }
             if (z.l >= L) return "balance would exceed max_level";
-            for (int c = 0; c < 8; ++c) cur.push_back(child_of(z, c));
+            if (kind[i] != DG_KIND_COPY) return "internal: a leaf was refined twice in one pass";
+            for (int c = 0; c < 8; ++c) {
+                nxt.push_back(child_of(z, c));
+                nsrc.push_back(src[i]);
+                nkind.push_back(c);
+            }
         }
+        cur.swap(nxt);
+        src.swap(nsrc);
+        kind.swap(nkind);
     }
     out = HostMesh();
     out.desc = desc;
-    out.leaves = std::move(cur);  // sorted by the last Sorted pass
-    const size_t K = out.leaves.size();
-    out.xfer_src.resize(K);
-    out.xfer_kind.resize(K);
-    Sorted P(desc, prev.leaves);  // prev is sorted already; keys recomputed
-    std::vector<char> refined(prev.leaves.size(), 0);
-    int bad = 0;
-#pragma omp parallel for schedule(static) reduction(| : bad)
-    for (int64_t e = 0; e < (int64_t)K; ++e) {
-        const Leaf& lf = out.leaves[e];
-        // an old leaf kept or refined sits near position e * K_prev / K of the new order
-        const size_t hint = (size_t)((double)e * (double)P.leaves().size() / (double)K);
-        const int old = P.find(lf, hint);
-        if (old >= 0) {
-            out.xfer_src[e] = old;
-            out.xfer_kind[e] = DG_KIND_COPY;
-        } else {
-            const int ip = P.find(parent_of(lf), hint);
-            if (ip < 0) {
-                bad = 1;
-                continue;
-            }
-            out.xfer_src[e] = ip;
-            out.xfer_kind[e] = child_id_of(lf);
-#pragma omp atomic write
-            refined[ip] = 1;
-        }
-    }
-    if (bad) return "internal: a leaf was refined twice in one pass";
-    out.n_refined = std::count(refined.begin(), refined.end(), 1);
-    forest_tables(out);
+    out.leaves = std::move(cur);
+    out.xfer_src = std::move(src);
+    out.xfer_kind = std::move(kind);
+    int64_t nref = 0;
+    for (int32_t k : out.xfer_kind) nref += k == 0;
+    out.n_refined = nref;
+    tables_from(out, prev);
     return "";
 }
 
@@ -440,29 +583,35 @@ std::string forest_coarsen(const HostMesh& prev, const int8_t* flags, HostMesh& 
         unchanged(prev, out);
         return "";
     }
-    // prev's leaves are in canonical (sorted) order, the order the families were found in
+    // prev's leaves are in canonical (sorted) order, the order the families were found
+    // in; an old leaf that stays, or starts a merged family, moves down by 7 for every
+    // family merged before it
     const std::vector<Leaf>& src = prev.leaves;
-    const size_t K0 = src.size();
+    const int64_t K0 = (int64_t)src.size();
+    std::vector<int64_t, NoInit<int64_t>> before(K0 + 1);
+    before[0] = 0;
+    for (int64_t e = 0; e < K0; ++e) before[e + 1] = before[e] + merge[e];
+    std::vector<char> inside(K0, 0);  // the children 1..7 of a merged family
+#pragma omp parallel for schedule(static) if (K0 > 4096)
+    for (int64_t e = 0; e < K0; ++e)
+        if (merge[e])
+            for (int c = 1; c < 8; ++c) inside[e + c] = 1;
     out = HostMesh();
     out.desc = desc;
-    out.leaves.reserve(K0);
-    out.xfer_src.reserve(K0);
-    out.xfer_kind.reserve(K0);
-    for (size_t e = 0; e < K0;) {
-        if (merge[e]) {
-            out.leaves.push_back(parent_of(src[e]));
-            out.xfer_src.push_back((int32_t)e);
-            out.xfer_kind.push_back(DG_KIND_FAMILY);
-            e += 8;
-        } else {
-            out.leaves.push_back(src[e]);
-            out.xfer_src.push_back((int32_t)e);
-            out.xfer_kind.push_back(DG_KIND_COPY);
-            ++e;
-        }
+    const int64_t K = K0 - 7 * nmerged;
+    out.leaves.resize(K);
+    out.xfer_src.resize(K);
+    out.xfer_kind.resize(K);
+#pragma omp parallel for schedule(static) if (K0 > 4096)
+    for (int64_t e = 0; e < K0; ++e) {
+        if (inside[e]) continue;
+        const int64_t i = e - 7 * before[e];
+        out.leaves[i] = merge[e] ? parent_of(src[e]) : src[e];
+        out.xfer_src[i] = (int32_t)e;
+        out.xfer_kind[i] = merge[e] ? DG_KIND_FAMILY : DG_KIND_COPY;
     }
     out.n_coarsened = nmerged;
-    forest_tables(out);
+    tables_from(out, prev);
     return "";
 }
 
@@ -479,68 +628,45 @@ void forest_tables(HostMesh& m) {
     m.fnb.assign(K * 24, -1);
     // per leaf and face: type and neighbours (independent, in parallel)
 #pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < K; ++e) leaf_faces(m, S, e);
+    face_lists(m);
+}
+
+void box_leaf_arrays(const HostMesh& h, const std::vector<double>& xi, double* geo, double* c1d, int32_t* level) {
+    const int64_t K = (int64_t)h.leaves.size();
+    const int N1 = h.desc.N + 1;
+#pragma omp parallel for schedule(static) if (K > 4096)
     for (int64_t e = 0; e < K; ++e) {
-        const Leaf& lf = m.leaves[e];
+        double hh[3], c[3 * 8];  // N + 1 <= 8
+        leaf_geometry(h.desc, h.leaves[e], xi, hh, c);
+        for (int d = 0; d < 3; ++d) {
+            geo[e * 4 + d] = 2.0 / hh[d];
+            for (int j = 0; j < N1; ++j) c1d[(d * K + e) * N1 + j] = c[d * N1 + j];
+        }
+        geo[e * 4 + 3] = hh[0] * hh[1] * hh[2] / 8.0;
+        level[e] = h.leaves[e].l;
+    }
+}
+
+void stage_records(const HostMesh& h, const int32_t* hs, int rec_len, int32_t* srec) {
+    const int64_t K = (int64_t)h.leaves.size();
+#pragma omp parallel for schedule(static) if (K > 4096)
+    for (int64_t e = 0; e < K; ++e) {
+        int32_t* rec = srec + e * rec_len;
         for (int f = 0; f < 6; ++f) {
-            const int d = f >> 1, s = f & 1;
-            Leaf c;
-            if (!S.neighbor(lf, f, c)) {
-                m.ftype[e * 6 + f] = FT_WALL;
-                continue;
+            rec[f] = h.ftype[e * 6 + f];
+            rec[6 + f] = h.fnb[e * 24 + f * 4];
+            rec[12 + f] = hs[e * 6 + f];
+        }
+        rec[18] = rec[19] = 0;
+        if (h.sphere) {
+            for (int f = 0; f < 6; ++f) {
+                const int32_t* nb = &h.snb[(e * 6 + f) * 3];
+                if (nb[0] >= 0) rec[18] |= (int32_t)((nb[1] & 7) | ((nb[2] & 1) << 3)) << (4 * f);
             }
-            const int x = S.containing(c, (size_t)e);
-            if (x >= 0) {
-                if (S.leaves()[x].l == lf.l) {
-                    const int rz = lf.r / (desc.nx * desc.ny);
-                    const bool wrap_z = d == 2 && (s ? rz == desc.nz - 1 && lf.a[2] == (1 << lf.l) - 1
-                                                     : rz == 0 && lf.a[2] == 0);
-                    m.ftype[e * 6 + f] = FT_CONF | (wrap_z ? FT_BG_NB : 0);
-                } else {
-                    // this leaf is the fine side: quadrant from its tangential anchor bits
-                    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-                    const int q = (lf.a[t1] & 1) | ((lf.a[t2] & 1) << 1);
-                    m.ftype[e * 6 + f] = FT_FINE | (q << 8);
-                }
-                m.fnb[(e * 6 + f) * 4] = x;
-            } else {
-                Leaf fc[4];
-                face_children(c, d, 1 - s, fc);
-                m.ftype[e * 6 + f] = FT_COARSE;
-                for (int q = 0; q < 4; ++q) m.fnb[(e * 6 + f) * 4 + q] = S.find(fc[q], (size_t)e);  // leaves, by balance
-            }
+            rec[19] = h.leaves[e].r;
         }
     }
-    // the global lists in (leaf, face) order, sized first
-    int64_t nconf = 0, nbnd = 0, nhang = 0;
-    for (int64_t i = 0; i < K * 6; ++i) {
-        const int type = m.ftype[i] & 0xff;
-        nconf += type == FT_CONF && (i % 6) % 2 == 1;
-        nbnd += type == FT_WALL;
-        nhang += type == FT_COARSE;
-    }
-    m.conf.clear();
-    m.bnd.clear();
-    m.hang.clear();
-    m.conf.reserve(3 * nconf);
-    m.bnd.reserve(2 * nbnd);
-    m.hang.reserve(6 * nhang);
-    for (int64_t e = 0; e < K; ++e)
-        for (int f = 0; f < 6; ++f) {
-            const int type = m.ftype[e * 6 + f] & 0xff;
-            const int32_t* nb = &m.fnb[(e * 6 + f) * 4];
-            if (type == FT_WALL) {
-                m.bnd.push_back((int32_t)e);
-                m.bnd.push_back(f);
-            } else if (type == FT_CONF && (f & 1)) {
-                m.conf.push_back((int32_t)e);
-                m.conf.push_back(nb[0]);
-                m.conf.push_back(f >> 1);
-            } else if (type == FT_COARSE) {
-                m.hang.push_back((int32_t)e);
-                m.hang.push_back(f);
-                for (int q = 0; q < 4; ++q) m.hang.push_back(nb[q]);
-            }
-        }
 }
 
 void leaf_geometry(const dg_forest_desc& desc, const Leaf& lf, const std::vector<double>& xi, double h[3],

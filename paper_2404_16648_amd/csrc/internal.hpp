@@ -3,7 +3,9 @@
 
 #include <atomic>
 #include <cstdint>
+#include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "dg.h"
@@ -27,12 +29,33 @@ struct RefOps {
 };
 RefOps make_refops(int N);
 
+// an allocator under which a vector's new elements of a trivial type are left
+// uninitialised (resize without a value): the large tables of a pass are first
+// touched by the parallel loops that fill them, not by a serial zero fill
+template <class T>
+struct NoInit : std::allocator<T> {
+    using std::allocator<T>::allocator;
+    template <class U>
+    struct rebind {
+        using other = NoInit<U>;
+    };
+    template <class U>
+    void construct(U* p) noexcept {
+        ::new ((void*)p) U;
+    }
+    template <class U, class... A>
+    void construct(U* p, A&&... a) {
+        ::new ((void*)p) U(std::forward<A>(a)...);
+    }
+};
+using ivec = std::vector<int32_t, NoInit<int32_t>>;
+
 struct HostMesh {
     dg_forest_desc desc{};
     std::vector<Leaf> leaves;
-    std::vector<int32_t> conf, bnd, hang;        // flattened tables (3, 2, 6 per row)
-    std::vector<int32_t> xfer_src, xfer_kind;
-    std::vector<int32_t> ftype, fnb;             // [K][6], [K][6][4]
+    ivec conf, bnd, hang;                        // flattened tables (3, 2, 6 per row)
+    ivec xfer_src, xfer_kind;
+    ivec ftype, fnb;                             // [K][6], [K][6][4]
     int64_t n_refined = 0, n_coarsened = 0;
     bool same_as_prev = false;                   // the pass changed no leaf: tables copied
     // cubed-sphere shell (leaf r = panel, a = (ia, ib, ir)): per face the neighbour
@@ -50,6 +73,13 @@ std::string forest_coarsen(const HostMesh& prev, const int8_t* flags, HostMesh& 
 void forest_tables(HostMesh& m);
 // whether forest_refine (refine) or forest_coarsen (!refine) would change a leaf
 bool pass_changes(const HostMesh& prev, const int8_t* flags, bool refine);
+// per-leaf device arrays of a brick mesh, in parallel: geo [K][4] (2/h per axis,
+// volume / 8), c1d [3][K][N+1] node coordinates per axis, level [K]
+void box_leaf_arrays(const HostMesh& h, const std::vector<double>& xi, double* geo, double* c1d, int32_t* level);
+// the stage kernel's per-leaf face records (rec_len int32 each), in parallel: per
+// face the type, the first neighbour and the hanging-face row (hs [K][6]); on a
+// shell, entry 18 packs per face the neighbour's face and the flip, entry 19 the panel
+void stage_records(const HostMesh& h, const int32_t* hs, int rec_len, int32_t* srec);
 
 // cubed-sphere shell: mesh and tables; geometry into device layouts
 // (metric [10][K][Np]: J, then J a^i_c at 1 + 3 i + c; fgeo [K][6][NF][4]: unit

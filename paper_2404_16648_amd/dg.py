@@ -612,10 +612,12 @@ def _on(stream):
     return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
 
 
-def project_cycle(mesh: Mesh, mc: Mesh, mr: Mesh, q, stream=None, phys: PhysParams | None = None):
+def project_cycle(mesh: Mesh, mc: Mesh, mr: Mesh, q, stream=None, phys: PhysParams | None = None, out_c=None,
+                  out_r=None):
     """The projections of one adaptation cycle (mesh -> mc coarsening, mc -> mr
     refinement; a pass that changed nothing is skipped).  Returns (mr, q on mr);
-    the new fields are allocated for `stream`.  A shell takes the transfer of
+    the new fields are out_c / out_r when given ([5, K, Np] of their meshes, not
+    aliasing q), else allocated for `stream`.  A shell takes the transfer of
     section 3.4 (its refinement's scale factor needs phys for the background)."""
     import torch
     if mesh.shell and phys is None:
@@ -623,14 +625,14 @@ def project_cycle(mesh: Mesh, mc: Mesh, mr: Mesh, q, stream=None, phys: PhysPara
     qc = q
     with _on(stream):
         if mc is not mesh:
-            qc = torch.empty(5, mc.K, mc.Np, dtype=torch.float64, device=q.device)
+            qc = out_c if out_c is not None else torch.empty(5, mc.K, mc.Np, dtype=torch.float64, device=q.device)
             if mesh.shell:
                 dg_sphere_adapt_project(mesh, mc, phys, q, qc, stream, scale=False)
             else:
                 dg_coarsen_project(mesh, mc, q, qc, stream)
         qr = qc
         if mr is not mc:
-            qr = torch.empty(5, mr.K, mr.Np, dtype=torch.float64, device=q.device)
+            qr = out_r if out_r is not None else torch.empty(5, mr.K, mr.Np, dtype=torch.float64, device=q.device)
             if mesh.shell:
                 dg_sphere_adapt_project(mc, mr, phys, qc, qr, stream, scale=False)
             else:
@@ -698,14 +700,27 @@ class AdaptiveStepper:
         self._dev = torch.empty(0, dtype=torch.int8, device=q.device)
         self._host = torch.empty(0, dtype=torch.int8).pin_memory()
         self._reserve(mesh.K)
-        # stage buffers and the speculative step's output, kept across steps (swapped
-        # with the state when the speculative step is kept)
-        self._bufs(q)
+        # four flat buffers: the state, the speculative step's output and the two
+        # stage buffers (the state and the speculation swap when the speculation is
+        # kept); a cycle that changes the mesh projects into the speculation's buffer
+        # (through a stage buffer when both passes change) and takes the new mesh's
+        # fields as views of them, so it allocates nothing unless the mesh outgrows
+        # them (then all four are made again with a quarter to spare)
+        self._flat = [q.view(-1)] + self._new_flats(3, q.numel() + q.numel() // 4)
+        self._roles = [0, 1, 2, 3]   # state, speculation, stage 1, stage 2
+        self._views(mesh.K)
 
-    def _bufs(self, q):
+    def _new_flats(self, n, cap):
         import torch
         with _on(self.stream):  # allocated for the stream that uses them
-            self._q1, self._q2, self._spec = torch.empty_like(q), torch.empty_like(q), torch.empty_like(q)
+            return [torch.empty(cap, dtype=torch.float64, device=self.q.device) for _ in range(n)]
+
+    def _view(self, i, K):
+        return self._flat[i][:5 * K * self.mesh.Np].view(5, K, self.mesh.Np)
+
+    def _views(self, K):
+        st, sp, a, b = self._roles
+        self._spec, self._q1, self._q2 = self._view(sp, K), self._view(a, K), self._view(b, K)
 
     def _reserve(self, K):
         import torch
@@ -753,13 +768,28 @@ class AdaptiveStepper:
             mc, mr = adapt_meshes_from_flags(mesh, flags, self.buffer)
             if mr is mesh:
                 self.q, self._spec = spec, q  # the old state's buffer takes the next speculation
+                r = self._roles
+                self._roles = [r[1], r[0], r[2], r[3]]
             else:
                 self.changed += 1
-                mr2, qn = project_cycle(mesh, mc, mr, q, self.stream, self.phys)
+                need = 5 * max(mc.K, mr.K) * mesh.Np
+                if min(f.numel() for f in self._flat) < need:
+                    # q stays alive (and its buffer in use on the stream) until the
+                    # projection below has read it
+                    self._flat = self._new_flats(4, need + need // 4)
+                    self._roles = [3, 0, 1, 2]
+                st, sp, a, b = self._roles
+                both = mc is not mesh and mr is not mc
+                out_c = self._flat[a][:5 * mc.K * mesh.Np].view(5, mc.K, mesh.Np) if both else None
+                out_r = self._flat[sp][:5 * mr.K * mesh.Np].view(5, mr.K, mesh.Np)
+                if mr is mc:  # only the coarsen pass changed: its output is the new state
+                    out_c, out_r = out_r, None
+                mr2, qn = project_cycle(mesh, mc, mr, q, self.stream, self.phys, out_c, out_r)
                 mr2.prev = None
                 self.mesh, self.q = mr2, qn
+                self._roles = [sp, st, a, b]
                 self._reserve(mr2.K)
-                self._bufs(qn)
+                self._views(mr2.K)
                 ev = self._stages(mr2, qn, qn, events)
         if ev is not None:
             events.append(ev)
