@@ -53,10 +53,10 @@ BUBBLE = dict(N=7, nroot=(8, 8, 8), L=2, lo=(0.0, 0.0, 0.0), hi=(1000.0, 1000.0,
 # for the kernel and forest sources they were taken on (SHA-256 below); otherwise
 # traffic is reported as null.  Not measured by the run that prints the line.
 TRAFFIC = {
-    "sources_sha256": "4d4b2b55d3d9984df242428652782397fa1b15fb27c30bf6b094a015fa401fc6",
-    "fetch_scale": 1048576.0 / 524300.5,  # 1 GiB copy: FETCH_SIZE reads 524300.5 KiB
+    "sources_sha256": "a992e2f8746d593c2077687dadefb5f8294b1351ed84eb3e36473cabf9954e2a",
+    "fetch_scale": 1048576.0 / 524299.5,  # 1 GiB copy: FETCH_SIZE reads 524299.5 KiB
     "write_scale": 1048576.0 / 1048576.0,  # 1 GiB copy: WRITE_SIZE reads 1048576.0 KiB
-    "density_current": {"fetch_kib": 130905.5, "write_kib": 128961.0},
+    "density_current": {"fetch_kib": 131088.9, "write_kib": 128956.6},
     "source": "profiles/k_stage_density_current_N4_traffic.md",
 }
 CSRC = os.path.join(ROOT, "paper_2404_16648_amd", "csrc")

@@ -131,45 +131,6 @@ void set_device_pointers(dg_mesh* m, char* base, const DevLayout& L) {
 
 // every face of every leaf has a type and in-range neighbours (the kernels index
 // field arrays with them); checked on the host before anything is uploaded
-bool tables_consistent(const HostMesh& h) {
-    const int64_t K = (int64_t)h.leaves.size();
-    if ((int64_t)h.ftype.size() != 6 * K || (int64_t)h.fnb.size() != 24 * K) return false;
-    for (int64_t i = 0; i < 6 * K; ++i) {
-        const int type = h.ftype[i] & 0xff;
-        const int nnb = type == FT_WALL ? 0 : type == FT_COARSE ? 4 : 1;
-        if (type > FT_COARSE || h.ftype[i] < 0) return false;
-        for (int q = 0; q < nnb; ++q)
-            if (h.fnb[i * 4 + q] < 0 || h.fnb[i * 4 + q] >= K) return false;
-    }
-    return true;
-}
-
-// the transfer plan indexes fields of K_from source leaves: a kept or refined
-// source in range; a refined leaf's eight children consecutive, ids 0..7, with
-// one source; a merged parent's eight source leaves in range (the transfer
-// kernels read and write whole families from these indices)
-bool plan_consistent(const HostMesh& h, int64_t K_from) {
-    const int64_t K = (int64_t)h.leaves.size();
-    if ((int64_t)h.xfer_src.size() != K || (int64_t)h.xfer_kind.size() != K) return false;
-    for (int64_t e = 0; e < K; ++e) {
-        const int64_t src = h.xfer_src[e];
-        const int kind = h.xfer_kind[e];
-        if (kind == DG_KIND_COPY) {
-            if (src < 0 || src >= K_from) return false;
-        } else if (kind == DG_KIND_FAMILY) {
-            if (src < 0 || src + 7 >= K_from) return false;
-        } else if (kind >= 0 && kind < 8) {
-            const int64_t e0 = e - kind;
-            if (src < 0 || src >= K_from || e0 < 0 || e0 + 7 >= K) return false;
-            for (int c = 0; c < 8; ++c)
-                if (h.xfer_kind[e0 + c] != c || h.xfer_src[e0 + c] != src) return false;
-        } else {
-            return false;
-        }
-    }
-    return true;
-}
-
 // A pass that changed no leaf leaves every table as it was: the device block is
 // cloned from the previous mesh's (and its background, when computed), and only
 // the identity transfer plan is uploaded.

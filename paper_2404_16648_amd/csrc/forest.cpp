@@ -632,6 +632,46 @@ void forest_tables(HostMesh& m) {
     face_lists(m);
 }
 
+bool tables_consistent(const HostMesh& h) {
+    const int64_t K = (int64_t)h.leaves.size();
+    if ((int64_t)h.ftype.size() != 6 * K || (int64_t)h.fnb.size() != 24 * K) return false;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad) if (K > 4096)
+    for (int64_t i = 0; i < 6 * K; ++i) {
+        const int type = h.ftype[i] & 0xff;
+        const int nnb = type == FT_WALL ? 0 : type == FT_COARSE ? 4 : 1;
+        bad |= type > FT_COARSE || h.ftype[i] < 0;
+        for (int q = 0; q < nnb; ++q) bad |= h.fnb[i * 4 + q] < 0 || h.fnb[i * 4 + q] >= K;
+    }
+    return !bad;
+}
+
+bool plan_consistent(const HostMesh& h, int64_t K_from) {
+    const int64_t K = (int64_t)h.leaves.size();
+    if ((int64_t)h.xfer_src.size() != K || (int64_t)h.xfer_kind.size() != K) return false;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad) if (K > 4096)
+    for (int64_t e = 0; e < K; ++e) {
+        const int64_t src = h.xfer_src[e];
+        const int kind = h.xfer_kind[e];
+        if (kind == DG_KIND_COPY) {
+            bad |= src < 0 || src >= K_from;
+        } else if (kind == DG_KIND_FAMILY) {
+            bad |= src < 0 || src + 7 >= K_from;
+        } else if (kind >= 0 && kind < 8) {
+            const int64_t e0 = e - kind;
+            if (src < 0 || src >= K_from || e0 < 0 || e0 + 7 >= K) {
+                bad = 1;
+            } else {
+                for (int c = 0; c < 8; ++c) bad |= h.xfer_kind[e0 + c] != c || h.xfer_src[e0 + c] != src;
+            }
+        } else {
+            bad = 1;
+        }
+    }
+    return !bad;
+}
+
 void box_leaf_arrays(const HostMesh& h, const std::vector<double>& xi, double* geo, double* c1d, int32_t* level) {
     const int64_t K = (int64_t)h.leaves.size();
     const int N1 = h.desc.N + 1;

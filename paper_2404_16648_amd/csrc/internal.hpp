@@ -73,6 +73,12 @@ std::string forest_coarsen(const HostMesh& prev, const int8_t* flags, HostMesh& 
 void forest_tables(HostMesh& m);
 // whether forest_refine (refine) or forest_coarsen (!refine) would change a leaf
 bool pass_changes(const HostMesh& prev, const int8_t* flags, bool refine);
+// host checks of a new mesh (in parallel): every face has a type and in-range
+// neighbours; the transfer plan indexes fields of K_from source leaves (a kept or
+// refined source in range, a refined leaf's eight children consecutive with ids
+// 0..7 and one source, a merged parent's eight sources in range)
+bool tables_consistent(const HostMesh& h);
+bool plan_consistent(const HostMesh& h, int64_t K_from);
 // per-leaf device arrays of a brick mesh, in parallel: geo [K][4] (2/h per axis,
 // volume / 8), c1d [3][K][N+1] node coordinates per axis, level [K]
 void box_leaf_arrays(const HostMesh& h, const std::vector<double>& xi, double* geo, double* c1d, int32_t* level);
