@@ -383,7 +383,6 @@ __global__ void __launch_bounds__(MortSz<N>::NT) k_mortar_sphere(const SphereMor
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
             double acc = 0.0;
-            #pragma unroll 1
             for (int a = 0; a < N1; ++a) {
                 double tb = 0.0;
                 for (int b = 0; b < N1; ++b) tb = fma(Ib[b2 * N1 + b], sTc[v * NF + a + N1 * b], tb);
@@ -425,7 +424,6 @@ __global__ void __launch_bounds__(MortSz<N>::NT) k_mortar_sphere(const SphereMor
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 double acc = 0.0;
-                #pragma unroll 1
                 for (int a2 = 0; a2 < N1; ++a2) {
                     double tb = 0.0;
                     for (int b2 = 0; b2 < N1; ++b2) tb = fma(Rb[b * N1 + b2], sG[(quad * 5 + v) * NF + a2 + N1 * b2], tb);
