@@ -228,17 +228,49 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_tracer_stage(const TracerArgs A) 
         for (int v = 0; v < 5; ++v) sQ[v * NP + t] = A.qs[v * KNP + e * NP + t];
         sC[t] = A.cs[e * NP + t];
     }
-    __syncthreads();
-    const double liftc = 0.5 * N * (N + 1);
-    for (int it = t; it < 6 * NF; it += NT) {
-        const int f = it / NF, m = it % NF;
+    // face items grouped by axis, each axis padded to whole waves (a wave never mixes
+    // the three axis variants); this thread's items' neighbour states, tracer and
+    // mortar terms are loaded with the tile, before the first barrier
+    constexpr int PAD = ((2 * NF + 63) / 64) * 64;
+    constexpr int ITEMS = (3 * PAD + NT - 1) / NT;
+    double qR_[ITEMS][5], CR_[ITEMS], bR_[ITEMS][3];
+#pragma unroll
+    for (int u = 0; u < ITEMS; ++u) {
+        const int it = t + u * NT;
+        CR_[u] = 0.0;
+        if (it >= 3 * PAD) continue;
+        const int ax = it / PAD, r = it % PAD;
+        if (r >= 2 * NF) continue;
+        const int f = 2 * ax + r / NF, m = r % NF;
         const int tf = rec[f], type = tf & 0xff;
         if (type == FT_FINE || type == FT_COARSE) {
             const int64_t row = (int64_t)rec[12 + f] * 5 + (type == FT_COARSE ? 0 : 1 + ((tf >> 8) & 0xff));
-            sS[it] = A.mortC[row * NF + m];
-            continue;
+            sS[f * NF + m] = A.mortC[row * NF + m];
+        } else if (type != FT_WALL) {
+            const int64_t nb = rec[6 + f];
+            const int nn = face_node<N>(f ^ 1, m);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qR_[u][v] = A.qs[v * KNP + nb * NP + nn];
+            CR_[u] = A.cs[nb * NP + nn];
+            if (tf & FT_BG_NB) {
+                const int kn = face_k<N>(f ^ 1, m);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) bR_[u][c] = A.bg[c * KN1 + nb * N1 + kn];
+            }
         }
-        const int d = f >> 1;
+    }
+    __syncthreads();
+    const double liftc = 0.5 * N * (N + 1);
+#pragma unroll
+    for (int u = 0; u < ITEMS; ++u) {
+        const int it = t + u * NT;
+        if (it >= 3 * PAD) continue;
+        const int ax = it / PAD, r = it % PAD;
+        if (r >= 2 * NF) continue;
+        const int f = 2 * ax + r / NF, m = r % NF;
+        const int tf = rec[f], type = tf & 0xff;
+        if (type == FT_FINE || type == FT_COARSE) continue;
+        const int d = ax;
         const double sgn = (f & 1) ? 1.0 : -1.0;
         const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
         double qL[5], qR[5];
@@ -253,21 +285,16 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_tracer_stage(const TracerArgs A) 
             for (int v = 0; v < 5; ++v) qR[v] = qL[v];
             qR[1 + d] = -qL[1 + d];  // mirror state
         } else {
-            const int64_t nb = rec[6 + f];
-            const int nn = face_node<N>(f ^ 1, m);
 #pragma unroll
-            for (int v = 0; v < 5; ++v) qR[v] = A.qs[v * KNP + nb * NP + nn];
-            CR = A.cs[nb * NP + nn];
-            if (tf & FT_BG_NB) {
-                const int kn = face_k<N>(f ^ 1, m);
-                bR = bg_make(A.bg[nb * N1 + kn], A.bg[KN1 + nb * N1 + kn], A.bg[2 * KN1 + nb * N1 + kn]);
-            }
+            for (int v = 0; v < 5; ++v) qR[v] = qR_[u][v];
+            CR = CR_[u];
+            if (tf & FT_BG_NB) bR = bg_make(bR_[u][0], bR_[u][1], bR_[u][2]);
         }
         const double PpL = pprime(qL[4], bL.rTh, bL.P, gamma, A.binom);
         const double PpR = pprime(qR[4], bR.rTh, bR.P, gamma, A.binom);
         const double lift = sGeo[d] * liftc;
         with_axis(d, [&](auto dc) {
-            sS[it] = tracer_lifted<decltype(dc)::value>(qL, CL, bL, PpL, qR, CR, bR, PpR, sgn, gamma, lift);
+            sS[f * NF + m] = tracer_lifted<decltype(dc)::value>(qL, CL, bL, PpL, qR, CR, bR, PpR, sgn, gamma, lift);
         });
     }
     // volume: R = -sum_d (2/h_d) D_d (C u_d), one direction at a time
