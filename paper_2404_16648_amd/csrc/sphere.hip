@@ -418,7 +418,7 @@ __global__ void __launch_bounds__(MortSz<N>::NT) k_mortar_sphere(const SphereMor
     if (t < NF) {
         const int a = t % N1, b = t / N1;
         double proj[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int quad = 0; quad < 4; ++quad) {
+        auto add_quadrant = [&](int quad) {
             const double* Ra = sR + (quad & 1) * NF;
             const double* Rb = sR + (quad >> 1) * NF;
 #pragma unroll
@@ -431,6 +431,14 @@ __global__ void __launch_bounds__(MortSz<N>::NT) k_mortar_sphere(const SphereMor
                 }
                 proj[v] = proj[v] + acc;
             }
+        };
+        // left to the compiler (unrolled) except at N = 3, where the unrolled form
+        // spills to scratch memory
+        if constexpr (N == 3) {
+#pragma unroll 1
+            for (int quad = 0; quad < 4; ++quad) add_quadrant(quad);
+        } else {
+            for (int quad = 0; quad < 4; ++quad) add_quadrant(quad);
         }
         const int nc = face_node<N>(fc, t), kc = face_k<N>(fc, t);
         double qc[5], Fc[5];

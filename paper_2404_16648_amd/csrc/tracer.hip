@@ -26,37 +26,47 @@ namespace {
 
 using namespace dev;
 
-// wave speed |u_D| + c of a full state q (perturbation about bg) and u_D
-template <int D>
-__device__ __forceinline__ void speed_u(const double q[5], const Bg& bg, double Pp, double gamma, double& lam,
+// The tracer flux along e_D needs three of the five Euler variables: rho', the
+// momentum U_D and Theta' (through P').  They are passed as scalars, the momentum
+// picked by a select on the axis, so no state array is ever indexed by a run-time
+// axis (such an index puts the array in scratch memory).
+struct TrState {
+    double rho, m, Thp;  // rho', U_D, Theta'
+};
+
+// the state's entries for axis d
+__device__ __forceinline__ TrState tr_state(double rho, double mx, double my, double mz, double Thp, int d) {
+    return TrState{rho, d == 0 ? mx : d == 1 ? my : mz, Thp};
+}
+
+// wave speed |u_D| + c of a full state (perturbation about bg) and u_D
+__device__ __forceinline__ void speed_u(const TrState& q, const Bg& bg, double Pp, double gamma, double& lam,
                                         double& ud) {
-    const double rinv = rcp_pos(bg.rho + q[0]);
-    ud = q[1 + D] * rinv;
+    const double rinv = rcp_pos(bg.rho + q.rho);
+    ud = q.m * rinv;
     lam = fabs(ud) + sqrt_pos(gamma * (bg.P + Pp) * rinv);
 }
 
 // lifted tracer surface term of the leaf on the L side of a face with outward
 // normal sgn e_D: lift (1/2 sgn (C_R u_R - C_L u_L) + 1/2 lambda (C_L - C_R)),
 // i.e. lift (F*_C - F_C(L)).n for the Rusanov flux
-template <int D>
-__device__ __forceinline__ double tracer_lifted(const double qL[5], double CL, const Bg& bL, double PpL,
-                                                const double qR[5], double CR, const Bg& bR, double PpR, double sgn,
+__device__ __forceinline__ double tracer_lifted(const TrState& qL, double CL, const Bg& bL, double PpL,
+                                                const TrState& qR, double CR, const Bg& bR, double PpR, double sgn,
                                                 double gamma, double lift) {
     double lL, lR, uL, uR;
-    speed_u<D>(qL, bL, PpL, gamma, lL, uL);
-    speed_u<D>(qR, bR, PpR, gamma, lR, uR);
+    speed_u(qL, bL, PpL, gamma, lL, uL);
+    speed_u(qR, bR, PpR, gamma, lR, uR);
     const double c1 = 0.5 * sgn * lift, c2 = 0.5 * fmax(lL, lR) * lift;
     return fma(c1, CR * uR - CL * uL, c2 * (CL - CR));
 }
 
 // F*_C . n for n = sgn e_D (the flux itself, for the mortars) and the L side's own C u.n
-template <int D>
-__device__ __forceinline__ void tracer_rusanov(const double qL[5], double CL, const Bg& bL, double PpL,
-                                               const double qR[5], double CR, const Bg& bR, double PpR, double sgn,
+__device__ __forceinline__ void tracer_rusanov(const TrState& qL, double CL, const Bg& bL, double PpL,
+                                               const TrState& qR, double CR, const Bg& bR, double PpR, double sgn,
                                                double gamma, double& Fs, double& FL) {
     double lL, lR, uL, uR;
-    speed_u<D>(qL, bL, PpL, gamma, lL, uL);
-    speed_u<D>(qR, bR, PpR, gamma, lR, uR);
+    speed_u(qL, bL, PpL, gamma, lL, uL);
+    speed_u(qR, bR, PpR, gamma, lR, uR);
     FL = sgn * (CL * uL);
     const double FR = sgn * (CR * uR);
     Fs = 0.5 * (FL + FR) + 0.5 * fmax(lL, lR) * (CL - CR);
@@ -127,9 +137,9 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_tracer_mortar(const TracerMortArg
         const double PpF = pprime(qF[4], bF.rTh, bF.P, gamma, A.binom);
         const double PpM = pprime(qM[4], bF.rTh, bF.P, gamma, A.binom);
         double Fs = 0.0, Fo = 0.0;
-        with_axis(f >> 1, [&](auto dc) {
-            tracer_rusanov<decltype(dc)::value>(qF, cF, bF, PpF, qM, cM, bF, PpM, -sgn, gamma, Fs, Fo);
-        });
+        const int d = f >> 1;
+        tracer_rusanov(tr_state(qF[0], qF[1], qF[2], qF[3], qF[4], d), cF, bF, PpF,
+                       tr_state(qM[0], qM[1], qM[2], qM[3], qM[4], d), cM, bF, PpM, -sgn, gamma, Fs, Fo);
         A.mortC[(h * 5 + 1 + quad) * NF + m] = (Fs - Fo) * lift_f;
         if (PW) {
 #pragma unroll
@@ -178,6 +188,8 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_tracer_mortar(const TracerMortArg
         for (int v = 0; v < 5; ++v) qL[v] = sT[v * NF + m];
         const double cL = sT[5 * NF + m];
         const double PpL = pprime(qL[4], b.rTh, b.P, gamma, A.binom);
+        const int d = f >> 1;
+        const TrState sL = tr_state(qL[0], qL[1], qL[2], qL[3], qL[4], d);
         double Fc = 0.0, Fo = 0.0;
         if constexpr (PW) {
             double qR[5];
@@ -185,12 +197,11 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_tracer_mortar(const TracerMortArg
             for (int v = 0; v < 5; ++v) qR[v] = sU[v * NF + m];
             const double cR = sU[5 * NF + m];
             const double PpR = pprime(qR[4], b.rTh, b.P, gamma, A.binom);
-            with_axis(f >> 1, [&](auto dc) {
-                tracer_rusanov<decltype(dc)::value>(qL, cL, b, PpL, qR, cR, b, PpR, sgn, gamma, Fc, Fo);
-            });
+            tracer_rusanov(sL, cL, b, PpL, tr_state(qR[0], qR[1], qR[2], qR[3], qR[4], d), cR, b, PpR, sgn, gamma,
+                           Fc, Fo);
         } else {
             double lam, ud;
-            with_axis(f >> 1, [&](auto dc) { speed_u<decltype(dc)::value>(qL, b, PpL, gamma, lam, ud); });
+            speed_u(sL, b, PpL, gamma, lam, ud);
             Fo = sgn * (cL * ud);
             Fc = sU[m];
         }
@@ -233,7 +244,9 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_tracer_stage(const TracerArgs A) 
     // mortar terms are loaded with the tile, before the first barrier
     constexpr int PAD = ((2 * NF + 63) / 64) * 64;
     constexpr int ITEMS = (3 * PAD + NT - 1) / NT;
-    double qR_[ITEMS][5], CR_[ITEMS], bR_[ITEMS][3];
+    // (of the neighbour's Euler state only rho', the momentum along the face's axis
+    // and Theta' enter the tracer flux)
+    double qR_[ITEMS][3], CR_[ITEMS], bR_[ITEMS][3];
 #pragma unroll
     for (int u = 0; u < ITEMS; ++u) {
         const int it = t + u * NT;
@@ -249,9 +262,11 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_tracer_stage(const TracerArgs A) 
         } else if (type != FT_WALL) {
             const int64_t nb = rec[6 + f];
             const int nn = face_node<N>(f ^ 1, m);
-#pragma unroll
-            for (int v = 0; v < 5; ++v) qR_[u][v] = A.qs[v * KNP + nb * NP + nn];
-            CR_[u] = A.cs[nb * NP + nn];
+            const int64_t at = nb * NP + nn;
+            qR_[u][0] = A.qs[at];
+            qR_[u][1] = A.qs[(1 + ax) * KNP + at];
+            qR_[u][2] = A.qs[4 * KNP + at];
+            CR_[u] = A.cs[at];
             if (tf & FT_BG_NB) {
                 const int kn = face_k<N>(f ^ 1, m);
 #pragma unroll
@@ -273,29 +288,21 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_tracer_stage(const TracerArgs A) 
         const int d = ax;
         const double sgn = (f & 1) ? 1.0 : -1.0;
         const int n = face_node<N>(f, m), kk = face_k<N>(f, m);
-        double qL[5], qR[5];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) qL[v] = sQ[v * NP + n];
+        const TrState qL{sQ[n], sQ[(1 + d) * NP + n], sQ[4 * NP + n]};
+        TrState qR{qL.rho, -qL.m, qL.Thp};  // a wall's mirror state: the normal momentum reversed
         const double CL = sC[n];
         double CR = CL;
         const Bg bL{sBg[kk], sBg[N1 + kk], sBg[2 * N1 + kk], sBg[3 * N1 + kk]};
         Bg bR = bL;
-        if (type == FT_WALL) {
-#pragma unroll
-            for (int v = 0; v < 5; ++v) qR[v] = qL[v];
-            qR[1 + d] = -qL[1 + d];  // mirror state
-        } else {
-#pragma unroll
-            for (int v = 0; v < 5; ++v) qR[v] = qR_[u][v];
+        if (type != FT_WALL) {
+            qR = TrState{qR_[u][0], qR_[u][1], qR_[u][2]};
             CR = CR_[u];
             if (tf & FT_BG_NB) bR = bg_make(bR_[u][0], bR_[u][1], bR_[u][2]);
         }
-        const double PpL = pprime(qL[4], bL.rTh, bL.P, gamma, A.binom);
-        const double PpR = pprime(qR[4], bR.rTh, bR.P, gamma, A.binom);
+        const double PpL = pprime(qL.Thp, bL.rTh, bL.P, gamma, A.binom);
+        const double PpR = pprime(qR.Thp, bR.rTh, bR.P, gamma, A.binom);
         const double lift = sGeo[d] * liftc;
-        with_axis(d, [&](auto dc) {
-            sS[f * NF + m] = tracer_lifted<decltype(dc)::value>(qL, CL, bL, PpL, qR, CR, bR, PpR, sgn, gamma, lift);
-        });
+        sS[f * NF + m] = tracer_lifted(qL, CL, bL, PpL, qR, CR, bR, PpR, sgn, gamma, lift);
     }
     // volume: R = -sum_d (2/h_d) D_d (C u_d), one direction at a time
     double R = 0.0, rinv = 0.0, C = 0.0;
