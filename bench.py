@@ -626,8 +626,8 @@ def sphere_vortex(dg, torch, N=4, n=24, nz=8, thr=0.1, dt=0.1, steps=20):
     atmosphere under gravity and a Gaussian theta vortex (1 K, 500 km, at latitude 0,
     longitude 0, at unperturbed density), refined once where theta' > thr: the
     float64 and precision-split stage durations and the split's error against the
-    float64 stage (the library's float64 stage is held to the oracle by the parity
-    tests; the oracle is too slow at this size), the transposed right-hand side
+    float64 stage (the library's float64 stage is held to the oracle at this size
+    by the parity tests), the transposed right-hand side
     against the right-hand side, and the gradient of a final-time functional over
     `steps` checkpointed SSP-RK3 steps against the forward integration."""
     from paper_2404_16648_amd import adjoint as adj
