@@ -753,7 +753,19 @@ def extras(dg, torch, mesh, q, ph, args):
         "stage_us": tr_us, "bytes_per_node": 64.0, "kernels": "k_tracer_mortar<4, false> + k_tracer_stage<4, 1>",
         "note": "reads the Euler stage input (40 B/node) and c0, cs, writes the tracer (8 B each)",
         "frac_hbm": nodes * 64.0 / (tr_us * 1e-6) / 1e9 / HBM_PEAK_GBS}
-    del lam, g, Ra, Rb, q1, c0, cs, c1
+    # a whole SSP-RK3 step of the Euler state and the tracer: the tracer stages on the
+    # same stream as the Euler stages, or on a side stream beside them
+    qq, cc = q.clone(), c0.clone()
+    qa, qb, ca, cb = torch.empty_like(q), torch.empty_like(q), torch.empty_like(c0), torch.empty_like(c0)
+    euler_us = _time_launches(torch, lambda: dg.ssp_rk3_step(mesh, ph, dt, qq, qa, qb), 10)
+    one_us = _time_launches(torch, lambda: dg.ssp_rk3_step_tracer(mesh, ph, dt, qq, qa, qb, cc, ca, cb), 10)
+    side = torch.cuda.Stream()
+    two_us = _time_launches(torch, lambda: dg.ssp_rk3_step_tracer(mesh, ph, dt, qq, qa, qb, cc, ca, cb, side=side), 10)
+    out["density_current_tracer_step"] = {
+        "euler_step_us": euler_us, "euler_and_tracer_one_stream_us": one_us,
+        "euler_and_tracer_side_stream_us": two_us, "side_stream_speedup": one_us / two_us,
+        "tracer_cost_over_euler_step": (two_us - euler_us) / euler_us}
+    del lam, g, Ra, Rb, q1, c0, cs, c1, qq, cc, qa, qb, ca, cb
     _progress("extras: density current forced adaptation cycle")
     out["density_current_forced_cycle"] = forced_cycle(dg, torch, mesh, q)
     # ---- AMR warm bubble (N = 7): the adaptive run as for the headline

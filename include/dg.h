@@ -439,8 +439,12 @@ dg_status dg_rk_stage_adjoint(const dg_mesh* mesh, const dg_phys* phys, double a
  * speed (the same local maximum |u.n| + c as the Euler flux; the tracer jump is
  * C- - C+).  Walls carry no tracer flux; hanging faces use phys->nonconforming
  * (mortars: the tracer's integral is conserved to round-off; pointwise: not),
- * through a pre-pass into the mesh's tracer workspace (calls on one mesh must be
- * ordered, as for dg_rhs).  dg_tracer_rhs: rhs := R_C(q, c).  dg_tracer_stage:
+ * through a pre-pass into the mesh's tracer workspace (tracer calls on one mesh
+ * must be ordered among themselves; the workspace is not the one of the Euler
+ * calls, and both only read the mesh's tables, so tracer calls may run on another
+ * stream beside Euler calls on the same mesh once a call has made its device
+ * tables and its background for phys, and has completed or is waited for).
+ * dg_tracer_rhs: rhs := R_C(q, c).  dg_tracer_stage:
  * cout := a c0 + b (cs + dt R_C(qs, cs)), the tracer part of the Shu-Osher
  * stage whose Euler part is dg_rk_stage(a, b, dt, q0, qs, ...) (call it before
  * that stage overwrites qs, or with a distinct output); cout may alias c0 but

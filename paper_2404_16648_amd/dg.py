@@ -465,16 +465,45 @@ def dg_project_fields(src: Mesh, dst: Mesh, q_from, q_to, stream=None):
     _check(lib().dg_project_fields(src.handle, dst.handle, nv, _ptr(q_from), _ptr(q_to), _stream(stream)))
 
 
-def ssp_rk3_step_tracer(mesh: Mesh, phys: PhysParams, dt, q, q1, q2, c, c1, c2, stream=None):
+def ssp_rk3_step_tracer(mesh: Mesh, phys: PhysParams, dt, q, q1, q2, c, c1, c2, stream=None, side=None):
     """One SSP-RK3 step of the Euler state and a passive tracer, in place on q and
-    c (stage buffers q1, q2, c1, c2): each tracer stage runs before the Euler stage
-    that could overwrite its input."""
-    dg_tracer_stage(mesh, phys, *SSP_RK3[0], dt, q, c, c, c1, stream)
-    dg_rk_stage(mesh, phys, *SSP_RK3[0], dt, q, q, q1, stream)
-    dg_tracer_stage(mesh, phys, *SSP_RK3[1], dt, q1, c, c1, c2, stream)
-    dg_rk_stage(mesh, phys, *SSP_RK3[1], dt, q, q1, q2, stream)
-    dg_tracer_stage(mesh, phys, *SSP_RK3[2], dt, q2, c, c2, c, stream)
-    dg_rk_stage(mesh, phys, *SSP_RK3[2], dt, q, q2, q, stream)
+    c (stage buffers q1, q2, c1, c2).
+
+    Tracer stage k needs the Euler stage input of stage k (for the velocity and
+    the wave speed).  On one stream each tracer stage runs before the Euler stage
+    that could overwrite its input.  With `side` (another stream) the tracer
+    stages run there, beside the Euler stages on `stream` (the two use separate
+    mortar workspaces of the mesh and only read its tables): after the first Euler
+    stage (which also makes the mesh's device tables and background if this is
+    the first call on it), side runs the first two tracer stages while the second
+    Euler stage runs, and the third beside the third, which waits for the first
+    tracer stage (it overwrites q, which that stage reads).  `stream` waits for
+    side at the end, so later work on it is ordered after the whole step.  The
+    results are bitwise those of the one-stream order."""
+    if side is None:
+        dg_tracer_stage(mesh, phys, *SSP_RK3[0], dt, q, c, c, c1, stream)
+        dg_rk_stage(mesh, phys, *SSP_RK3[0], dt, q, q, q1, stream)
+        dg_tracer_stage(mesh, phys, *SSP_RK3[1], dt, q1, c, c1, c2, stream)
+        dg_rk_stage(mesh, phys, *SSP_RK3[1], dt, q, q1, q2, stream)
+        dg_tracer_stage(mesh, phys, *SSP_RK3[2], dt, q2, c, c2, c, stream)
+        dg_rk_stage(mesh, phys, *SSP_RK3[2], dt, q, q2, q, stream)
+        return
+    import torch
+    main = stream if stream is not None else torch.cuda.current_stream()
+    dg_rk_stage(mesh, phys, *SSP_RK3[0], dt, q, q, q1, main)
+    side.wait_stream(main)                       # q, c ready and q1 written
+    dg_tracer_stage(mesh, phys, *SSP_RK3[0], dt, q, c, c, c1, side)
+    t1 = torch.cuda.Event()
+    t1.record(side)
+    dg_tracer_stage(mesh, phys, *SSP_RK3[1], dt, q1, c, c1, c2, side)
+    dg_rk_stage(mesh, phys, *SSP_RK3[1], dt, q, q1, q2, main)
+    e2 = torch.cuda.Event()
+    e2.record(main)
+    side.wait_event(e2)                          # q2 written
+    dg_tracer_stage(mesh, phys, *SSP_RK3[2], dt, q2, c, c2, c, side)
+    main.wait_event(t1)                          # the first tracer stage has read q
+    dg_rk_stage(mesh, phys, *SSP_RK3[2], dt, q, q2, q, main)
+    main.wait_stream(side)
 
 
 def dg_rhs_adjoint(mesh: Mesh, phys: PhysParams, q, lam, qbar, stream=None):

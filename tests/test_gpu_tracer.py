@@ -104,6 +104,33 @@ def test_tracer_budget_mortar_against_pointwise():
     assert gaps[dg.DG_NC_POINTWISE] > 1e3 * max(gaps[dg.DG_NC_MORTAR], 1e-16)
 
 
+def test_tracer_steps_beside_the_euler_stages_are_bitwise_the_same():
+    """ssp_rk3_step_tracer with the tracer stages on a side stream (beside the Euler
+    stages) against the one-stream order: bitwise the same state and tracer after
+    5 steps, the side-stream run starting on a mesh with no device tables yet"""
+    import torch
+    N = 4
+    od = oracle_desc(N, (4, 4, 4), 2, *BOX, (0, 0, 0))
+    seq = random_refinements(od, 1, 93, p=0.3)
+    runs = []
+    for use_side in (False, True):
+        lm, om = both_meshes(N, (4, 4, 4), 2, flag_seq=seq)
+        ph = dg.PhysParams()
+        q = lm.field()
+        dg.dg_init_bell(lm, ph, q, 2.0, (500.0, 500.0, 350.0), (250.0, 250.0, 250.0))
+        q += 0.05 * gpu(torch.as_tensor(random_state(om.K, N, 94)))
+        c = 0.5 + 0.5 * gpu(_tracer_field(om.K, N, 95))
+        q1, q2, c1, c2 = lm.field(), lm.field(), torch.empty_like(c), torch.empty_like(c)
+        side = torch.cuda.Stream() if use_side else None
+        for _ in range(5):
+            dg.ssp_rk3_step_tracer(lm, ph, 0.01, q, q1, q2, c, c1, c2, side=side)
+        torch.cuda.synchronize()
+        runs.append((q.cpu(), c.cpu()))
+    print("side-stream tracer steps: K", om.K, "hanging", len(om.hang), flush=True)
+    assert len(om.hang) > 0
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+
+
 def test_project_fields_against_oracle():
     N = 3
     od = oracle_desc(N, (2, 2, 2), 2, *BOX, (0, 0, 0))
