@@ -174,7 +174,7 @@ def adaptive_run(dg, torch, cfg, steps, warmup, every):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only (no multi-GPU path); use --gpus 1"}))
+        print(json.dumps({"error": "the library runs on one GPU only (no multi-GPU path); use --gpus 1"}))
         sys.exit(2)
     import torch
 
