@@ -56,7 +56,7 @@ TRAFFIC = {
     "sources_sha256": "a992e2f8746d593c2077687dadefb5f8294b1351ed84eb3e36473cabf9954e2a",
     "fetch_scale": 1048576.0 / 524299.5,  # 1 GiB copy: FETCH_SIZE reads 524299.5 KiB
     "write_scale": 1048576.0 / 1048576.0,  # 1 GiB copy: WRITE_SIZE reads 1048576.0 KiB
-    "density_current": {"fetch_kib": 131055.6, "write_kib": 128946.7},
+    "density_current": {"fetch_kib": 131085.2, "write_kib": 128877.3},
     "source": "profiles/k_stage_density_current_N4_traffic.md",
 }
 CSRC = os.path.join(ROOT, "paper_2404_16648_amd", "csrc")

@@ -49,12 +49,12 @@ __device__ __forceinline__ void speed_u(const TrState& q, const Bg& bg, double P
 
 // lifted tracer surface term of the leaf on the L side of a face with outward
 // normal sgn e_D: lift (1/2 sgn (C_R u_R - C_L u_L) + 1/2 lambda (C_L - C_R)),
-// i.e. lift (F*_C - F_C(L)).n for the Rusanov flux
-__device__ __forceinline__ double tracer_lifted(const TrState& qL, double CL, const Bg& bL, double PpL,
-                                                const TrState& qR, double CR, const Bg& bR, double PpR, double sgn,
-                                                double gamma, double lift) {
-    double lL, lR, uL, uR;
-    speed_u(qL, bL, PpL, gamma, lL, uL);
+// i.e. lift (F*_C - F_C(L)).n for the Rusanov flux, with the L side's u_D and wave
+// speed lL already formed (the stage kernel forms them once per node, with the
+// expressions of speed_u)
+__device__ __forceinline__ double tracer_lifted(double uL, double lL, double CL, const TrState& qR, double CR,
+                                                const Bg& bR, double PpR, double sgn, double gamma, double lift) {
+    double lR, uR;
     speed_u(qR, bR, PpR, gamma, lR, uR);
     const double c1 = 0.5 * sgn * lift, c2 = 0.5 * fmax(lL, lR) * lift;
     return fma(c1, CR * uR - CL * uL, c2 * (CL - CR));
@@ -217,6 +217,8 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_tracer_stage(const TracerArgs A) 
     __shared__ double sC[NP];       // the leaf's tracer
     __shared__ double sF[NP];       // the flux plane of one direction
     __shared__ double sS[6 * NF];   // lifted face contributions [f][m]
+    __shared__ double sRinv[NP];    // 1/rho at each node
+    __shared__ double sCs[NP];      // the sound speed at each node
     __shared__ double sD[N1 * N1];
     __shared__ double sBg[4 * N1];  // rho, Theta, P, 1/Theta
     __shared__ double sGeo[4];
@@ -275,6 +277,16 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_tracer_stage(const TracerArgs A) 
         }
     }
     __syncthreads();
+    // 1/rho and the sound speed once per node (the face items read their own side's
+    // here instead of forming them again: the same expressions, the same values)
+    double rinv = 0.0;
+    if (t < NP) {
+        rinv = rcp_pos(sBg[k] + sQ[t]);
+        const double Pp = pprime(sQ[4 * NP + t], sBg[3 * N1 + k], sBg[2 * N1 + k], gamma, A.binom);
+        sRinv[t] = rinv;
+        sCs[t] = sqrt_pos(gamma * (sBg[2 * N1 + k] + Pp) * rinv);
+    }
+    __syncthreads();
     const double liftc = 0.5 * N * (N + 1);
 #pragma unroll
     for (int u = 0; u < ITEMS; ++u) {
@@ -299,17 +311,14 @@ __global__ void __launch_bounds__(Sz<N>::NT) k_tracer_stage(const TracerArgs A) 
             CR = CR_[u];
             if (tf & FT_BG_NB) bR = bg_make(bR_[u][0], bR_[u][1], bR_[u][2]);
         }
-        const double PpL = pprime(qL.Thp, bL.rTh, bL.P, gamma, A.binom);
         const double PpR = pprime(qR.Thp, bR.rTh, bR.P, gamma, A.binom);
         const double lift = sGeo[d] * liftc;
-        sS[f * NF + m] = tracer_lifted(qL, CL, bL, PpL, qR, CR, bR, PpR, sgn, gamma, lift);
+        const double uL = qL.m * sRinv[n];
+        sS[f * NF + m] = tracer_lifted(uL, fabs(uL) + sCs[n], CL, qR, CR, bR, PpR, sgn, gamma, lift);
     }
     // volume: R = -sum_d (2/h_d) D_d (C u_d), one direction at a time
-    double R = 0.0, rinv = 0.0, C = 0.0;
-    if (t < NP) {
-        rinv = rcp_pos(sBg[k] + sQ[t]);
-        C = sC[t];
-    }
+    double R = 0.0, C = 0.0;
+    if (t < NP) C = sC[t];
 #pragma unroll 1
     for (int d = 0; d < 3; ++d) {
         __syncthreads();
