@@ -269,6 +269,37 @@ def test_shell_adjoint_against_central_differences():
     assert abs(ad - fd) <= 1e-7 * abs(ad), (ad, fd)
 
 
+def test_shell_adjoint_at_rest_richardson():
+    """At a state at rest (the vortex: u = 0 at every node) the Rusanov wave speed's
+    |u.n| sits on its kink at every face node: the reverse mode differentiates it
+    as 0 there and central differences see it symmetric, but where the kink meets a
+    jump (a wall's mirror state, whose normal momentum jumps by 2 U.n under the
+    perturbation) the central difference is off by a term linear in eps.  The gap
+    halves with eps, and Richardson extrapolation 2 D(eps/2) - D(eps) agrees with
+    the reverse mode far below the plain difference's gap."""
+    N = 2
+    m = sp.SphereMesh(sp.SphereDesc(N=N, n=1, nz=1, max_level=1))
+    m = sp.refine_pass(m, (np.arange(m.K) % 3 == 0).astype(np.int8))
+    op = sp.SphereOperator(m, eu.Phys(), sp.BG_ISOTHERMAL)
+    shape = (5, m.K, N + 1, N + 1, N + 1)
+    q = sp.vortex_state(op, width=2.0e6)
+    assert float(q[1:4].abs().max()) == 0.0
+    lam = torch.as_tensor(random_state(m.K, N, 34)).reshape(shape)
+    v = torch.as_tensor(random_state(m.K, N, 35)).reshape(shape)
+    ad = float((eu.rhs_adjoint(op, q, lam) * v).sum())
+
+    def central(eps):
+        return float((lam * (op.rhs(q + eps * v) - op.rhs(q - eps * v))).sum()) / (2 * eps)
+
+    d1, d2 = central(1e-3), central(5e-4)
+    g1, g2 = abs(d1 - ad), abs(d2 - ad)
+    rich = abs(2 * d2 - d1 - ad)
+    print("rest-state dot-product gaps: eps 1e-3", g1 / abs(ad), "eps 5e-4", g2 / abs(ad), "Richardson",
+          rich / abs(ad), flush=True)
+    assert 1.8 < g1 / g2 < 2.2
+    assert rich <= 1e-3 * g2 and rich <= 1e-9 * abs(ad)
+
+
 def test_vortex_state():
     """theta' = Theta'/rhobar is 1 K times exp(-(d / w)^2) in the great-circle distance
     d from the centre, rho' and the momentum vanish"""
