@@ -6,7 +6,6 @@ equation, the tracer's budget through SSP-RK3 steps (mortars conserve it,
 pointwise matching does not), and the conservative transfer of a tracer field
 and of several fields at once (dg_project_fields) against the oracle's."""
 import dataclasses
-import math
 
 import numpy as np
 import pytest
