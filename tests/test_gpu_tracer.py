@@ -107,7 +107,6 @@ def test_tracer_steps_beside_the_euler_stages_are_bitwise_the_same():
     """ssp_rk3_step_tracer with the tracer stages on a side stream (beside the Euler
     stages) against the one-stream order: bitwise the same state and tracer after
     5 steps, the side-stream run starting on a mesh with no device tables yet"""
-    import torch
     N = 4
     od = oracle_desc(N, (4, 4, 4), 2, *BOX, (0, 0, 0))
     seq = random_refinements(od, 1, 93, p=0.3)
